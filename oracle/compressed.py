@@ -1,0 +1,147 @@
+"""Compressed expansions and translations (Secs. 3.3, 3.4, 4.1, 4.1.1).
+
+  P2M   beta = M^T alpha                                  (eq. define_beta_multipole)
+  M2L   theta_i = sum_{q in j} G^(i+q)(c2 - c1) beta_q,  i in j   (eq. m2l_toeplitz,
+        kept in derivative form: the 1/i! of the local coefficient is applied at
+        evaluation, as the stored local of eq. stored_local_coeffs carries none)
+  L2P   phi(x) = sum_i [M theta]_i / i! (x - c)^i         (eq. compressed-local-form)
+
+Scaled form (Sec. 4.1.1) with parameter t:
+  beta~_q = beta_q t^|q|,  table~_m = G^(m) / t^|m|,  theta~_i = theta_i / t^|i|,
+  theta~ = sum_q table~_{i+q} beta~_q.
+
+FFT form (eq. convolution_m2l): the sum over q is a 3-D correlation of the
+derivative grid g[m] = G^(m), m in [0, 2M], M = (max_j nu_x, max_j nu_y, max_j nu_z),
+with the kept coefficients; embedding in a circulant of size 2M + 1 per axis turns it
+into one FFT product.
+
+Coefficient vectors are in the order of the kept positions j of Sec. 3.1 (which,
+for the graded order used here, is the graded order restricted to m_z < c).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .compression import decompression_matrix, kept_indices, position_map
+from .kernels import deriv_table_mp, deriv_table_rec, pde_order, slab_indices
+from .multiindex import graded_order, madd, mfact, morder, mpow
+from .taylor import l2p_full, p2m_full
+
+
+def kept(kernel: str, param: float, p: int) -> list:
+    return kept_indices(kernel, param, p)
+
+
+def p2m(kernel: str, param: float, p: int, center, src, w) -> np.ndarray:
+    M, _, _ = decompression_matrix(kernel, param, p)
+    return M.T @ p2m_full(p, center, src, w)
+
+
+def slab_table(kernel: str, param: float, p: int, d, mp: bool = False) -> dict:
+    """{m: G^(m)(d)} for |m| <= 2p, m_z <= 2(c-1): all the compressed M2L reads."""
+    idx = slab_indices(2 * p, 2 * (pde_order(kernel) - 1))
+    vals = (deriv_table_mp if mp else deriv_table_rec)(kernel, param, d, idx)
+    return dict(zip(idx, vals))
+
+
+def m2l_matrix(kernel: str, param: float, p: int, d, table: dict | None = None) -> np.ndarray:
+    """T[i, q] = G^(i+q)(d) for i, q in j."""
+    if table is None:
+        table = slab_table(kernel, param, p, d)
+    J = kept(kernel, param, p)
+    return np.array([[table[madd(i, q)] for q in J] for i in J])
+
+
+def m2l(kernel: str, param: float, p: int, d, beta, table: dict | None = None) -> np.ndarray:
+    return m2l_matrix(kernel, param, p, d, table) @ np.asarray(beta)
+
+
+def local_full(kernel: str, param: float, p: int, theta) -> np.ndarray:
+    """M theta: the full derivative-form local vector in graded order of M(p)."""
+    M, _, _ = decompression_matrix(kernel, param, p)
+    return M @ np.asarray(theta)
+
+
+def l2p(kernel: str, param: float, p: int, center, theta, tgt) -> np.ndarray:
+    return l2p_full(p, center, local_full(kernel, param, p, theta), tgt)
+
+
+# ----------------------------------------------------------------------------- scaled form
+
+def scale_multipole(kernel, param, p, beta, t):
+    J = kept(kernel, param, p)
+    return np.asarray(beta) * np.array([float(t) ** morder(q) for q in J])
+
+
+def unscale_multipole(kernel, param, p, beta_s, t):
+    J = kept(kernel, param, p)
+    return np.asarray(beta_s) / np.array([float(t) ** morder(q) for q in J])
+
+
+def scale_local(kernel, param, p, theta, t):
+    J = kept(kernel, param, p)
+    return np.asarray(theta) / np.array([float(t) ** morder(i) for i in J])
+
+
+def unscale_local(kernel, param, p, theta_s, t):
+    J = kept(kernel, param, p)
+    return np.asarray(theta_s) * np.array([float(t) ** morder(i) for i in J])
+
+
+def m2l_scaled(kernel, param, p, d, beta_s, t, table: dict | None = None):
+    """theta~ = sum_q (G^(i+q)/t^|i+q|) beta~_q  (Sec. 4.1.1)."""
+    if table is None:
+        table = slab_table(kernel, param, p, d)
+    tt = {m: v / float(t) ** morder(m) for m, v in table.items()}
+    return m2l(kernel, param, p, d, beta_s, tt)
+
+
+# ----------------------------------------------------------------------------- FFT form
+
+def m2l_fft(kernel: str, param: float, p: int, d, beta, table: dict | None = None) -> np.ndarray:
+    """eq. convolution_m2l evaluated by a circulant embedding and numpy FFTs."""
+    if table is None:
+        table = slab_table(kernel, param, p, d)
+    J = kept(kernel, param, p)
+    Mx = max(m[0] for m in J)
+    My = max(m[1] for m in J)
+    Mz = max(m[2] for m in J)
+    L = (2 * Mx + 1, 2 * My + 1, 2 * Mz + 1)
+    cplx = np.iscomplexobj(beta) or any(np.iscomplexobj(v) for v in table.values())
+    g = np.zeros(L, dtype=np.complex128)
+    for m, v in table.items():
+        if m[0] <= 2 * Mx and m[1] <= 2 * My and m[2] <= 2 * Mz:
+            g[m] = v
+    b = np.zeros(L, dtype=np.complex128)
+    for q, v in zip(J, beta):
+        b[(-q[0]) % L[0], (-q[1]) % L[1], (-q[2]) % L[2]] = v
+    conv = np.fft.ifftn(np.fft.fftn(g) * np.fft.fftn(b))
+    out = np.array([conv[i] for i in J])
+    return out if cplx else out.real
+
+
+# ----------------------------------------------------------------------------- batched helpers
+
+def p2m_boxes(kernel, param, p, centers, pt_range, src, w, boxes, t=None):
+    """beta (scaled by t^|q| per box when t is given) for the listed boxes."""
+    out = []
+    for k, b in enumerate(boxes):
+        lo, hi = pt_range[b]
+        beta = p2m(kernel, param, p, centers[b], src[lo:hi], w[lo:hi])
+        if t is not None:
+            beta = scale_multipole(kernel, param, p, beta, t[k])
+        out.append(beta)
+    return np.array(out)
+
+
+def l2p_boxes(kernel, param, p, centers, pt_range, tgt, theta, boxes, n_tgt, t=None):
+    """phi at every target of the listed boxes (theta scaled by 1/t^|i| when t given)."""
+    dtype = np.complex128 if np.iscomplexobj(theta) else np.float64
+    phi = np.zeros(n_tgt, dtype=dtype)
+    for k, b in enumerate(boxes):
+        lo, hi = pt_range[b]
+        th = theta[k]
+        if t is not None:
+            th = unscale_local(kernel, param, p, th, t[k])
+        phi[lo:hi] += l2p(kernel, param, p, centers[b], th, tgt[lo:hi])
+    return phi

@@ -1,0 +1,295 @@
+"""Seeded synthetic workloads: point clouds, weights, octrees and interaction lists.
+
+This module is shared by the CPU oracle and the GPU path.  It holds no arithmetic
+of the expansion method itself (no derivatives, moments, translations or
+compression): only the geometry that every FMM pass needs as input --
+
+* point distributions (uniform cube, Plummer sphere, Gaussian mixture) drawn from
+  NumPy's PCG64 with an explicit seed;
+* octrees over the unit cube, uniform or adaptive, with points sorted in Morton
+  order so that the points of every box (at every level) are one contiguous range;
+* "List 2" (interaction list) pairs: boxes of the same level whose parents are
+  adjacent or equal but which are not adjacent themselves (the well-separated
+  pairs an FMM translates by multipole-to-local).
+
+Box ids are global across levels.  For every box: ``level``, integer grid
+coordinates ``ijk`` at its level, ``center`` (float64), ``pt_range`` (int64
+(begin, end) into the Morton-sorted points).  A box at level l has side 2**-l.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MAX_DEPTH = 20  # Morton keys use 3 * MAX_DEPTH = 60 bits of a uint64
+
+
+# --------------------------------------------------------------------------- points
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_points(n: int, seed: int, low=0.0, high=1.0) -> np.ndarray:
+    """n points uniform in [low, high)^3 (per-axis bounds allowed), float64 [n, 3]."""
+    g = rng(seed)
+    low = np.broadcast_to(np.asarray(low, dtype=np.float64), (3,))
+    high = np.broadcast_to(np.asarray(high, dtype=np.float64), (3,))
+    return low + (high - low) * g.random((n, 3))
+
+
+def normal_weights(n: int, seed: int, complex_: bool = False) -> np.ndarray:
+    """Weights with N(0,1) entries; complex weights have N(0,1) real and imaginary parts."""
+    g = rng(seed)
+    if complex_:
+        w = g.standard_normal((n, 2))
+        return w[:, 0] + 1j * w[:, 1]
+    return g.standard_normal(n)
+
+
+def plummer_points(n: int, seed: int, scale: float = 0.1, center=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """Plummer-sphere radii r = a (u^(-2/3) - 1)^(-1/2), isotropic directions,
+    points outside the unit cube rejected and redrawn."""
+    g = rng(seed)
+    center = np.asarray(center, dtype=np.float64)
+    out = np.empty((0, 3))
+    while out.shape[0] < n:
+        m = max(1024, int((n - out.shape[0]) * 1.3))
+        u = g.random(m)
+        u = np.clip(u, 1e-300, 1.0)
+        r = scale / np.sqrt(u ** (-2.0 / 3.0) - 1.0)
+        v = g.standard_normal((m, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        x = center + r[:, None] * v
+        ok = np.all((x >= 0.0) & (x < 1.0), axis=1)
+        out = np.concatenate([out, x[ok]], axis=0)
+    return out[:n]
+
+
+def gaussian_mixture_points(n: int, seed: int, k: int = 4, sigma: float = 0.05,
+                            mean_low: float = 0.2, mean_high: float = 0.8) -> np.ndarray:
+    """k equal-weight isotropic Gaussians (std sigma), means uniform in
+    [mean_low, mean_high]^3; points outside the unit cube rejected and redrawn."""
+    g = rng(seed)
+    means = mean_low + (mean_high - mean_low) * g.random((k, 3))
+    out = np.empty((0, 3))
+    while out.shape[0] < n:
+        m = max(1024, int((n - out.shape[0]) * 1.2))
+        comp = g.integers(0, k, m)
+        x = means[comp] + sigma * g.standard_normal((m, 3))
+        ok = np.all((x >= 0.0) & (x < 1.0), axis=1)
+        out = np.concatenate([out, x[ok]], axis=0)
+    return out[:n]
+
+
+# --------------------------------------------------------------------------- morton
+
+def _spread_bits(v: np.ndarray) -> np.ndarray:
+    """Insert two zero bits between each of the low 20 bits of v (uint64)."""
+    v = v.astype(np.uint64) & np.uint64(0xFFFFF)
+    out = np.zeros_like(v)
+    for b in range(MAX_DEPTH):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
+    return out
+
+
+def morton_keys(ijk: np.ndarray) -> np.ndarray:
+    """Interleaved key (x bit highest within each triple) for integer coords [n, 3]."""
+    ijk = np.asarray(ijk)
+    return (_spread_bits(ijk[:, 0]) << np.uint64(2)) | (_spread_bits(ijk[:, 1]) << np.uint64(1)) \
+        | _spread_bits(ijk[:, 2])
+
+
+def _compact_bits(k: np.ndarray) -> np.ndarray:
+    out = np.zeros_like(k)
+    for b in range(MAX_DEPTH):
+        out |= ((k >> np.uint64(3 * b)) & np.uint64(1)) << np.uint64(b)
+    return out
+
+
+def morton_decode(keys: np.ndarray) -> np.ndarray:
+    keys = np.asarray(keys, dtype=np.uint64)
+    return np.stack([_compact_bits(keys >> np.uint64(2)), _compact_bits(keys >> np.uint64(1)),
+                     _compact_bits(keys)], axis=1).astype(np.int64)
+
+
+# --------------------------------------------------------------------------- trees
+
+@dataclass
+class Tree:
+    """Octree over [0,1)^3 with Morton-sorted points.
+
+    perm:      original index of each sorted point
+    points:    sorted points [n, 3]
+    level, ijk, center, pt_range: per box (global ids, level-major order);
+               pt_range[b] = (begin, end) into the sorted points
+    level_start: first box id of each level (len n_levels + 1)
+    is_leaf:   per box
+    """
+    points: np.ndarray
+    perm: np.ndarray
+    level: np.ndarray
+    ijk: np.ndarray
+    center: np.ndarray
+    pt_range: np.ndarray
+    level_start: np.ndarray
+    is_leaf: np.ndarray
+    kind: str = "uniform"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_box(self) -> int:
+        return int(self.level.shape[0])
+
+    @property
+    def n_levels(self) -> int:
+        return int(self.level_start.shape[0] - 1)
+
+    def boxes_at(self, lev: int) -> np.ndarray:
+        return np.arange(self.level_start[lev], self.level_start[lev + 1])
+
+    def box_size(self, lev: int) -> float:
+        return 2.0 ** (-lev)
+
+    def counts(self) -> np.ndarray:
+        return self.pt_range[:, 1] - self.pt_range[:, 0]
+
+
+def _point_keys(points: np.ndarray) -> np.ndarray:
+    scale = float(1 << MAX_DEPTH)
+    ijk = np.floor(points * scale).astype(np.int64)
+    ijk = np.clip(ijk, 0, (1 << MAX_DEPTH) - 1)
+    return morton_keys(ijk)
+
+
+def _assemble(points, perm, keys_sorted, level_keys, is_leaf_lists, kind, meta) -> Tree:
+    """level_keys[l] = sorted unique Morton prefixes (level-l keys) of existing boxes."""
+    levels, ijks, centers, ranges, leaves, level_start = [], [], [], [], [], [0]
+    for lev, lk in enumerate(level_keys):
+        shift = np.uint64(3 * (MAX_DEPTH - lev))
+        lo = np.searchsorted(keys_sorted, lk << shift, side="left")
+        hi = np.searchsorted(keys_sorted, (lk + np.uint64(1)) << shift, side="left") if lev > 0 \
+            else np.array([keys_sorted.shape[0]])
+        ijk = morton_decode(lk)
+        h = 2.0 ** (-lev)
+        levels.append(np.full(lk.shape[0], lev, dtype=np.int32))
+        ijks.append(ijk.astype(np.int32))
+        centers.append((ijk + 0.5) * h)
+        ranges.append(np.stack([lo, hi], axis=1).astype(np.int64))
+        leaves.append(is_leaf_lists[lev])
+        level_start.append(level_start[-1] + lk.shape[0])
+    return Tree(points=points, perm=perm, level=np.concatenate(levels), ijk=np.concatenate(ijks),
+                center=np.concatenate(centers), pt_range=np.concatenate(ranges),
+                level_start=np.asarray(level_start, dtype=np.int64),
+                is_leaf=np.concatenate(leaves), kind=kind, meta=meta)
+
+
+def uniform_tree(points: np.ndarray, depth: int) -> Tree:
+    """All 8**l boxes at every level l <= depth (empty boxes included)."""
+    keys = _point_keys(points)
+    perm = np.argsort(keys, kind="stable")
+    ks = keys[perm]
+    level_keys, leaf = [], []
+    for lev in range(depth + 1):
+        lk = np.arange(8 ** lev, dtype=np.uint64)
+        level_keys.append(lk)
+        leaf.append(np.full(lk.shape[0], lev == depth))
+    return _assemble(points[perm], perm, ks, level_keys, leaf, "uniform", {"depth": depth})
+
+
+def adaptive_tree(points: np.ndarray, max_leaf: int, max_depth: int = 16) -> Tree:
+    """Refine every box holding more than max_leaf points; empty children are dropped."""
+    keys = _point_keys(points)
+    perm = np.argsort(keys, kind="stable")
+    ks = keys[perm]
+    level_keys, leaf = [np.zeros(1, dtype=np.uint64)], []
+    active = ks  # keys of points inside boxes that get refined
+    lev = 0
+    while True:
+        lk = level_keys[-1]
+        shift = np.uint64(3 * (MAX_DEPTH - lev))
+        counts = (np.searchsorted(ks, (lk + np.uint64(1)) << shift) - np.searchsorted(ks, lk << shift)) \
+            if lev > 0 else np.array([ks.shape[0]])
+        refine = (counts > max_leaf) & (lev < max_depth)
+        leaf.append(~refine)
+        if not np.any(refine):
+            break
+        # points of refined boxes -> unique child keys
+        box_of_pt = ks >> shift
+        sel = np.isin(box_of_pt, lk[refine])
+        active = ks[sel]
+        child = np.unique(active >> np.uint64(3 * (MAX_DEPTH - lev - 1)))
+        level_keys.append(child)
+        lev += 1
+    return _assemble(points[perm], perm, ks, level_keys, leaf, "adaptive", {"max_leaf": max_leaf})
+
+
+# --------------------------------------------------------------------------- interaction lists
+
+def list2_offsets(parity) -> np.ndarray:
+    """Integer offsets o = ijk_t - ijk_s of List 2 for a target with the given child parity
+    (ijk mod 2): sources are children of the parent's neighbours (parent included) that are
+    not adjacent to the target.  189 offsets per parity, 316 distinct over all parities."""
+    per_axis = []
+    for par in parity:
+        # source child coords span [2P-2, 2P+3]; target is at 2P + par
+        lo, hi = -2 - par, 3 - par  # o_src = s - t in [lo, hi]
+        per_axis.append(np.arange(lo, hi + 1))
+    g = np.stack(np.meshgrid(*per_axis, indexing="ij"), axis=-1).reshape(-1, 3)
+    g = g[np.max(np.abs(g), axis=1) >= 2]
+    return -g  # o = t - s
+
+
+def all_list2_offsets() -> np.ndarray:
+    r = np.arange(-3, 4)
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    return g[np.max(np.abs(g), axis=1) >= 2]
+
+
+def interaction_pairs(tree: Tree, levels=None) -> tuple[np.ndarray, np.ndarray]:
+    """All List-2 pairs (target box, source box) at the given levels (default: all levels >= 2).
+    Both boxes must exist in the tree.  Returns int32 arrays, sorted by (target, source)."""
+    if levels is None:
+        levels = range(2, tree.n_levels)
+    tgts, srcs = [], []
+    for lev in levels:
+        ids = tree.boxes_at(lev)
+        if ids.size == 0:
+            continue
+        ijk = tree.ijk[ids].astype(np.int64)
+        n_side = 1 << lev
+        keys = morton_keys(ijk)  # sorted, since boxes are stored in Morton order
+        for par in np.ndindex(2, 2, 2):
+            sel = np.all((ijk & 1) == np.asarray(par), axis=1)
+            if not np.any(sel):
+                continue
+            t_ids = ids[sel]
+            offs = list2_offsets(par)  # o = t - s  =>  s = t - o
+            cand = ijk[sel][:, None, :] - offs[None, :, :]
+            inside = np.all((cand >= 0) & (cand < n_side), axis=2)
+            ti = np.broadcast_to(t_ids[:, None], inside.shape)[inside]
+            cs = cand[inside]
+            ck = morton_keys(cs)
+            pos = np.searchsorted(keys, ck)
+            pos_c = np.minimum(pos, keys.shape[0] - 1)
+            found = keys[pos_c] == ck
+            tgts.append(ti[found])
+            srcs.append(ids[pos_c[found]])
+    if not tgts:
+        return np.zeros(0, np.int32), np.zeros(0, np.int32)
+    t = np.concatenate(tgts).astype(np.int32)
+    s = np.concatenate(srcs).astype(np.int32)
+    order = np.lexsort((s, t))
+    return t[order], s[order]
+
+
+# --------------------------------------------------------------------------- configs
+
+def small_two_box(seed: int = 0):
+    """64 sources uniform in [-0.5,0.5]^3 (expansion centre 0) and 64 targets uniform in a
+    unit box centred at (3,0,0), weights N(0,1)."""
+    src = uniform_points(64, seed, -0.5, 0.5)
+    tgt = uniform_points(64, seed + 1, (2.5, -0.5, -0.5), (3.5, 0.5, 0.5))
+    w = normal_weights(64, seed + 2)
+    return src, tgt, w, np.zeros(3), np.array([3.0, 0.0, 0.0])
