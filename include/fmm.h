@@ -1,0 +1,180 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) library for the PDE-compressed
+ * Cartesian-Taylor FMM translation operators of Fernando & Kloeckner,
+ * "Automatic Synthesis of Low-Complexity Translation Operators for the Fast
+ * Multipole Method" (arXiv 2305.17867).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers are device pointers unless marked [host].  The caller owns every
+ * buffer it passes; the library never frees or retains caller memory.  Launch
+ * entry points enqueue kernels on `stream` (a hipStream_t passed as void*,
+ * NULL = the default stream), return at once, never allocate device memory and
+ * never synchronise, so they may be captured into a HIP graph.  Only
+ * fmm_plan_create, fmm_m2l_prepare and fmm_batch_destroy / fmm_plan_destroy
+ * allocate, free or synchronise.
+ *
+ * Every entry point returns an fmm_status.  Arguments are validated on the host
+ * before anything is enqueued; on a non-OK status nothing was enqueued and
+ * fmm_last_error() returns a thread-local message.  Device-side index values
+ * (box point ranges, box ids in prepared batches) cannot be checked on the host
+ * without a synchronisation; kernels clamp point ranges to [0, n_points] so a
+ * bad range never reads or writes out of bounds.
+ *
+ * Kernels G (3-D, r = |x|), each obeying a constant-coefficient elliptic PDE
+ * (Sec. 4.1, Property 1):
+ *   FMM_LAPLACE    1/(4 pi r)            Delta G = 0
+ *   FMM_HELMHOLTZ  exp(i k r)/(4 pi r)   (Delta + k^2) G = 0,  param = k
+ *   FMM_YUKAWA     exp(-l r)/(4 pi r)    (Delta - l^2) G = 0,  param = l
+ *   FMM_BIHARMONIC r                     Delta^2 G = 0
+ *
+ * Dtypes.  FMM_F64: points, weights, coefficients and potentials float64.
+ * FMM_F32: points float32, weights/coefficients/potentials float32; M2L runs as
+ * FP32 matrix-core products with each offset group's partial sum accumulated in
+ * FP64, derivative tables are generated in FP64 and rounded once.  FMM_C128 /
+ * FMM_C64: as F64 / F32 with complex weights, coefficients and potentials,
+ * interleaved (re, im) like C99 double complex.  Helmholtz needs a complex
+ * dtype; the other kernels need a real one.  Box centres are always float64.
+ *
+ * Expansions (Secs. 2, 3.3, 3.4, 4.1).  With J = {m : |m| <= p, m_z < c} (c = PDE
+ * order; the compressed axis is z, Lemma max_prod_nice) a multipole about centre
+ * c1 is stored as beta = M^T alpha, alpha_q = sum_y w(y) (c1 - y)^q / q!
+ * (eqs. mpole, define_beta_multipole), and a local about c2 as the kept derivatives
+ * theta_i, i in J (eqs. stored_local_coeffs, compressed-local-form: no factorial).
+ * Both are stored in the scaled form of Sec. 4.1.1 with t = 1/h, h the box size
+ * of the box's level:  beta~_q = beta_q / h^|q|,  theta~_i = theta_i * h^|i|.
+ * Coefficient arrays are [n_box][Nc] (Nc = |J|), entries in the order that
+ * fmm_index_table returns: lexicographic in (m_z, m_x, m_y), m_y fastest.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMM_ABI_VERSION 1
+#define FMM_MAX_ORDER 16
+
+typedef enum {
+  FMM_OK = 0,
+  FMM_EINVAL = -1,       /* invalid argument (null pointer, size, range, mismatch) */
+  FMM_EUNSUPPORTED = -2, /* valid but not supported (kernel/dtype pair, order) */
+  FMM_EHIP = -3,         /* a HIP runtime call failed */
+  FMM_ENOMEM = -4,       /* device or host allocation failed */
+  FMM_ESTATE = -5        /* object in the wrong state (e.g. destroyed plan) */
+} fmm_status;
+
+typedef enum { FMM_LAPLACE = 0, FMM_HELMHOLTZ = 1, FMM_YUKAWA = 2, FMM_BIHARMONIC = 3 } fmm_kernel;
+typedef enum { FMM_F64 = 0, FMM_F32 = 1, FMM_C128 = 2, FMM_C64 = 3 } fmm_dtype;
+
+typedef struct {
+  int32_t kernel; /* fmm_kernel */
+  int32_t order;  /* expansion order p, 0 <= p <= FMM_MAX_ORDER */
+  int32_t dtype;  /* fmm_dtype */
+  int32_t flags;  /* must be 0 */
+  double param;   /* Helmholtz k or Yukawa lambda (> 0); ignored otherwise */
+} fmm_desc;
+
+typedef struct fmm_plan_s* fmm_plan;   /* per (kernel, p, dtype, level sizes): index and
+                                          recursion tables in device memory */
+typedef struct fmm_batch_s* fmm_batch; /* a prepared M2L batch: derivative tables and
+                                          target-tile work lists in device memory */
+
+/* ABI version (FMM_ABI_VERSION). */
+int32_t fmm_abi_version(void);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* fmm_last_error(void);
+
+/* Sizes of the full Taylor set M(p) (N(p) = C(p+3,3), reading of eq. np-count) and of
+ * the kept set J (|J| = N(p) - N(p-c), Sec. 3.1).  Host only; no GPU needed.
+ * n_full, n_compressed: [host] outputs, either may be NULL. */
+int fmm_sizes(const fmm_desc* desc, int32_t* n_full, int32_t* n_compressed);
+
+/* Multi-indices of the stored coefficients, in storage order (Lemma max_prod_nice: J =
+ * {m : m_z < c}).  mxyz: [host] output [Nc][3] (m_x, m_y, m_z).  Host only. */
+int fmm_index_table(const fmm_desc* desc, int32_t* mxyz);
+
+/* Derivative tables G^(m)(h * o) * h^|m| (the scaled table of Sec. 4.1.1 with t = 1/h) for
+ * |m| <= 2p and m_z <= 2(c-1): every derivative the compressed M2L of eq. m2l_toeplitz
+ * reads.  Generated in FP64 whatever desc->dtype says (Taylor-coefficient recurrences; for
+ * Laplace the recurrence of eq. deriv_laplace_3d is the same relation).
+ *   n       number of tables
+ *   offset  [n][3] float64: translation vector in units of h (c_target - c_source) / h;
+ *           must be nonzero
+ *   h       [n] float64 > 0 box sizes
+ *   out     [n][2c-1][2p+1][2p+1] float64 (complex128 for Helmholtz), index
+ *           (m_z, m_x, m_y); entries with |m| > 2p are set to zero.  OVERWRITTEN. */
+int fmm_deriv_tables(const fmm_desc* desc, int64_t n, const double* offset, const double* h,
+                     void* out, void* stream);
+
+/* Create a plan.  level_box_size [host][n_levels]: h of each tree level (> 0).  Allocates
+ * and synchronises (not capturable). */
+int fmm_plan_create(const fmm_desc* desc, int32_t n_levels, const double* level_box_size,
+                    fmm_plan* plan);
+void fmm_plan_destroy(fmm_plan plan);
+
+/* Compressed P2M (Sec. 3.4): for each box b < n_box, the scaled compressed multipole
+ * beta~ = (M^T alpha)/h^|q| of the sources src[pt_range[b][0] : pt_range[b][1]] about
+ * box_center[b], h = level_box_size[box_level[b]].
+ *   box_center [n_box][3] f64; box_level [n_box] i32; pt_range [n_box][2] i64
+ *   src_xyz    [n_src][3] real dtype; weight [n_src] dtype
+ *   mpole      [n_box][Nc] dtype, OVERWRITTEN */
+int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* pt_range, int64_t n_src, const void* src_xyz, const void* weight,
+            void* mpole, void* stream);
+
+/* Compressed L2P (Sec. 3.3, eq. compressed-local-form): for each box b, decompress its
+ * scaled local, apply 1/i!, and add phi(x) = sum_i ([M theta]_i / i!) (x - c)^i to every
+ * target x in tgt[pt_range[b][0] : pt_range[b][1]].
+ *   tgt_xyz [n_tgt][3] real dtype; local [n_box][Nc] dtype
+ *   potential [n_tgt] dtype, ACCUMULATED.  The point ranges of the boxes of one call must
+ *   be disjoint (apply tree levels in separate calls). */
+int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local,
+            void* potential, void* stream);
+
+/* Prepare a batched M2L (Sec. 4.1, eq. m2l_toeplitz) over n_pair (target box, source box)
+ * pairs, all [host]:
+ *   tgt_box, src_box [n_pair] i32 in [0, n_box); both boxes of a pair on the same level
+ *   box_ijk   [n_box][3] i32 integer grid coordinates of each box on its level
+ *   box_level [n_box] i32 in [0, n_levels)
+ * The translation vector of a pair is (ijk_t - ijk_s) * h_level; it must be nonzero and
+ * |ijk_t - ijk_s|_inf <= 8.  Pairs are grouped by (level, offset), one FP64 derivative
+ * table per group is generated on the GPU, and targets are tiled so that every output
+ * coefficient is owned by one workgroup.  Allocates and synchronises (not capturable). */
+int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                    int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
+                    fmm_batch* batch);
+void fmm_batch_destroy(fmm_batch batch);
+
+/* Statistics of a prepared batch, written to info[0 .. n_info-1] ([host]):
+ * 0 n_pair, 1 n_tables, 2 n_tiles, 3 n_entries (tile x offset groups), 4 n_items (workgroups
+ * of one launch), 5 useful pair-columns, 6 computed pair-columns (incl. padding), 7 Nc,
+ * 8 rows padded to a multiple of 16, 9 scratch bytes. */
+int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
+
+/* Batched M2L: local[t] += sum over pairs (t, s) of T(c_t - c_s) mpole[s], T[i,q] =
+ * G^(i+q) in the scaled form.  mpole [n_box][Nc] dtype; local [n_box][Nc] dtype,
+ * ACCUMULATED.  Deterministic: every output is summed in a fixed order. */
+int fmm_m2l_batched(fmm_batch batch, const void* mpole, void* local, void* stream);
+
+/* Several prepared batches (same dtype; kernels and orders may differ) drained by one
+ * persistent launch.  batches, mpole, local: [host] arrays of n pointers. */
+int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const* mpole,
+                          void* const* local, void* stream);
+
+/* Direct sum eq. (1): potential[x] = sum_y G(x - y) weight[y], terms with x == y skipped.
+ *   src_xyz [n_src][3], tgt_xyz [n_tgt][3] real dtype; weight [n_src] dtype;
+ *   potential [n_tgt] dtype, OVERWRITTEN. */
+int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const void* weight,
+               int64_t n_tgt, const void* tgt_xyz, void* potential, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H */

@@ -1,0 +1,532 @@
+// C ABI: argument validation, plans, M2L batch preparation and launch wrappers.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace fmm;
+
+struct fmm_plan_s {
+  fmm_desc desc{};
+  int p = 0, c = 2, nc = 0, nfull = 0, S = 1, Sz = 1;
+  int n_levels = 0;
+  std::vector<double> h;
+  std::vector<MIdx> J;
+  RecArgs rec{};
+  double* d_level_h = nullptr;
+  int32_t* d_jbase = nullptr;
+  bool alive = true;
+};
+
+struct fmm_batch_s {
+  fmm_plan plan = nullptr;
+  int dtype = 0;
+  int nc = 0, nc_pad = 0, ts = 0, waves = 1, rows_per_wave = 1;
+  int64_t n_pair = 0, n_tab = 0, n_tiles = 0, n_entries = 0, n_items = 0;
+  int64_t useful = 0, computed = 0, scratch_bytes = 0;
+  void* d_tab = nullptr;
+  int32_t* d_tile_tgt = nullptr;
+  int32_t* d_tile_nparts = nullptr;
+  int32_t* d_tile_item0 = nullptr;
+  int32_t* d_counter = nullptr;
+  double* d_scratch = nullptr;
+  int32_t* d_entry_tab = nullptr;
+  int32_t* d_entry_src = nullptr;
+  M2LItem* d_items = nullptr;
+  int32_t* d_jbase = nullptr;
+};
+
+namespace {
+
+template <typename T>
+int dev_upload(T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return FMM_OK;
+  hipError_t e = hipMalloc((void**)dst, v.size() * sizeof(T));
+  if (e != hipSuccess) return fail(FMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(FMM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  return FMM_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+int env_int(const char* name, int dflt) {
+  const char* s = std::getenv(name);
+  if (!s || !*s) return dflt;
+  return std::atoi(s);
+}
+
+RecArgs make_rec(const fmm_desc& d) {
+  RecArgs r{};
+  auto terms = recursion_terms(d.kernel, d.param);
+  r.n = (int)terms.size();
+  for (int k = 0; k < r.n; ++k) {
+    r.dx[k] = terms[k].dx;
+    r.dy[k] = terms[k].dy;
+    r.dz[k] = terms[k].dz;
+    r.hpow[k] = terms[k].hpow;
+    r.coef[k] = terms[k].coef;
+  }
+  return r;
+}
+
+uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffff;
+  uint64_t out = 0;
+  for (int b = 0; b < 21; ++b) out |= ((x >> b) & 1ull) << (3 * b);
+  return out;
+}
+
+int check_plan(fmm_plan plan) {
+  if (!plan) return fail(FMM_EINVAL, "plan is NULL");
+  if (!plan->alive) return fail(FMM_ESTATE, "plan was destroyed");
+  return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fmm_abi_version(void) { return FMM_ABI_VERSION; }
+
+const char* fmm_last_error(void) { return last_error().c_str(); }
+
+int fmm_sizes(const fmm_desc* desc, int32_t* n_full_out, int32_t* n_compressed) {
+  int st = check_desc(desc);
+  if (st) return st;
+  const int p = desc->order, c = pde_order(desc->kernel);
+  if (n_full_out) *n_full_out = (int32_t)n_full(p);
+  if (n_compressed) *n_compressed = (int32_t)(n_full(p) - n_full(p - c));
+  return FMM_OK;
+}
+
+int fmm_index_table(const fmm_desc* desc, int32_t* mxyz) {
+  int st = check_desc(desc);
+  if (st) return st;
+  FMM_REQUIRE(mxyz, FMM_EINVAL, "mxyz is NULL");
+  auto J = kept_set(desc->order, pde_order(desc->kernel));
+  for (size_t k = 0; k < J.size(); ++k) {
+    mxyz[3 * k] = J[k].x;
+    mxyz[3 * k + 1] = J[k].y;
+    mxyz[3 * k + 2] = J[k].z;
+  }
+  return FMM_OK;
+}
+
+int fmm_deriv_tables(const fmm_desc* desc, int64_t n, const double* offset, const double* h, void* out,
+                     void* stream) {
+  int st = check_desc(desc);
+  if (st) return st;
+  FMM_REQUIRE(n >= 0, FMM_EINVAL, "n < 0");
+  if (n == 0) return FMM_OK;
+  FMM_REQUIRE(offset && h && out, FMM_EINVAL, "NULL pointer");
+  FMM_REQUIRE(n <= (int64_t)0x7fffffff, FMM_EINVAL, "too many tables");
+  TableArgs a{};
+  a.n = n;
+  a.offset = offset;
+  a.h = h;
+  a.out = out;
+  a.kernel = desc->kernel;
+  a.p2 = 2 * desc->order;
+  a.S = 2 * desc->order + 1;
+  a.Sz = 2 * pde_order(desc->kernel) - 1;
+  a.param = desc->param;
+  return launch_tables(a, desc->kernel == FMM_HELMHOLTZ, (hipStream_t)stream);
+}
+
+int fmm_plan_create(const fmm_desc* desc, int32_t n_levels, const double* level_box_size, fmm_plan* out) {
+  int st = check_desc(desc);
+  if (st) return st;
+  FMM_REQUIRE(out, FMM_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  FMM_REQUIRE(n_levels >= 1 && n_levels <= 64, FMM_EINVAL, "n_levels must be in [1, 64]");
+  FMM_REQUIRE(level_box_size, FMM_EINVAL, "level_box_size is NULL");
+  for (int l = 0; l < n_levels; ++l)
+    FMM_REQUIRE(level_box_size[l] > 0.0 && std::isfinite(level_box_size[l]), FMM_EINVAL,
+                "level_box_size must be finite and > 0");
+  auto* pl = new fmm_plan_s();
+  pl->desc = *desc;
+  pl->p = desc->order;
+  pl->c = pde_order(desc->kernel);
+  pl->J = kept_set(pl->p, pl->c);
+  pl->nc = (int)pl->J.size();
+  pl->nfull = (int)n_full(pl->p);
+  pl->S = 2 * pl->p + 1;
+  pl->Sz = 2 * pl->c - 1;
+  pl->n_levels = n_levels;
+  pl->h.assign(level_box_size, level_box_size + n_levels);
+  pl->rec = make_rec(*desc);
+  std::vector<int32_t> jb(pl->nc);
+  for (int k = 0; k < pl->nc; ++k) jb[k] = (pl->J[k].z * pl->S + pl->J[k].x) * pl->S + pl->J[k].y;
+  if ((st = dev_upload(&pl->d_level_h, pl->h)) || (st = dev_upload(&pl->d_jbase, jb))) {
+    fmm_plan_destroy(pl);
+    return st;
+  }
+  *out = pl;
+  return FMM_OK;
+}
+
+void fmm_plan_destroy(fmm_plan plan) {
+  if (!plan) return;
+  plan->alive = false;
+  dev_free(plan->d_level_h);
+  dev_free(plan->d_jbase);
+  delete plan;
+}
+
+static int check_box_args(fmm_plan plan, int64_t n_box, const double* center, const int32_t* level,
+                          const int64_t* range, int64_t n_pts, const void* xyz, const void* v1, const void* v2) {
+  int st = check_plan(plan);
+  if (st) return st;
+  FMM_REQUIRE(n_box >= 0 && n_box <= (int64_t)0x7fffffff, FMM_EINVAL, "n_box out of range");
+  FMM_REQUIRE(n_pts >= 0, FMM_EINVAL, "n_pts < 0");
+  if (n_box == 0) return FMM_OK;
+  FMM_REQUIRE(center && level && range, FMM_EINVAL, "box arrays must not be NULL");
+  FMM_REQUIRE(v1 && v2, FMM_EINVAL, "coefficient / value arrays must not be NULL");
+  FMM_REQUIRE(n_pts == 0 || xyz, FMM_EINVAL, "point array is NULL");
+  return FMM_OK;
+}
+
+int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* pt_range, int64_t n_src, const void* src_xyz, const void* weight, void* mpole,
+            void* stream) {
+  int st = check_box_args(plan, n_box, box_center, box_level, pt_range, n_src, src_xyz, mpole,
+                          n_src ? weight : mpole);
+  if (st || n_box == 0) return st;
+  P2MArgs a{};
+  a.n_box = n_box;
+  a.center = box_center;
+  a.level = box_level;
+  a.range = pt_range;
+  a.level_h = plan->d_level_h;
+  a.n_levels = plan->n_levels;
+  a.n_pts = n_src;
+  a.xyz = src_xyz;
+  a.w = weight;
+  a.out = mpole;
+  a.nc = plan->nc;
+  a.c = plan->c;
+  a.rec = plan->rec;
+  return launch_p2m(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
+int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local, void* potential,
+            void* stream) {
+  int st = check_box_args(plan, n_box, box_center, box_level, pt_range, n_tgt, tgt_xyz, local,
+                          n_tgt ? potential : local);
+  if (st || n_box == 0) return st;
+  L2PArgs a{};
+  a.n_box = n_box;
+  a.center = box_center;
+  a.level = box_level;
+  a.range = pt_range;
+  a.level_h = plan->d_level_h;
+  a.n_levels = plan->n_levels;
+  a.n_pts = n_tgt;
+  a.xyz = tgt_xyz;
+  a.local = local;
+  a.pot = potential;
+  a.nc = plan->nc;
+  a.c = plan->c;
+  a.rec = plan->rec;
+  return launch_l2p(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
+int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const void* weight, int64_t n_tgt,
+               const void* tgt_xyz, void* potential, void* stream) {
+  int st = check_desc(desc);
+  if (st) return st;
+  FMM_REQUIRE(n_src >= 0 && n_tgt >= 0, FMM_EINVAL, "negative size");
+  FMM_REQUIRE(n_tgt <= (int64_t)0x7fffffff * 256, FMM_EINVAL, "too many targets");
+  if (n_tgt == 0) return FMM_OK;
+  FMM_REQUIRE(tgt_xyz && potential, FMM_EINVAL, "NULL target pointer");
+  FMM_REQUIRE(n_src == 0 || (src_xyz && weight), FMM_EINVAL, "NULL source pointer");
+  DirectArgs a{};
+  a.n_src = n_src;
+  a.n_tgt = n_tgt;
+  a.src = src_xyz;
+  a.w = weight;
+  a.tgt = tgt_xyz;
+  a.pot = potential;
+  a.kernel = desc->kernel;
+  a.param = desc->param;
+  return launch_direct(a, desc->dtype, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------------------- M2L batches
+
+int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                    int64_t n_box, const int32_t* box_ijk, const int32_t* box_level, fmm_batch* out) {
+  int st = check_plan(plan);
+  if (st) return st;
+  FMM_REQUIRE(out, FMM_EINVAL, "batch output pointer is NULL");
+  *out = nullptr;
+  FMM_REQUIRE(n_pair >= 0 && n_box >= 0 && n_box <= (int64_t)0x7fffffff, FMM_EINVAL, "bad sizes");
+  FMM_REQUIRE(n_pair <= (int64_t)1 << 31, FMM_EINVAL, "too many pairs");
+  FMM_REQUIRE(n_pair == 0 || (tgt_box && src_box && box_ijk && box_level), FMM_EINVAL, "NULL host array");
+  const int dtype = plan->desc.dtype;
+  const bool cplx = dtype_complex(dtype);
+  const int CW = cplx ? 2 : 1;
+
+  // 1. validate pairs, group by (level, offset)
+  std::unordered_map<int64_t, int32_t> tab_of_key;
+  std::vector<int64_t> tab_keys;
+  std::vector<int32_t> pair_tab(n_pair);
+  for (int64_t k = 0; k < n_pair; ++k) {
+    const int32_t t = tgt_box[k], s = src_box[k];
+    FMM_REQUIRE(t >= 0 && t < n_box && s >= 0 && s < n_box, FMM_EINVAL,
+                "pair " + std::to_string(k) + ": box id out of range");
+    const int lt = box_level[t], ls = box_level[s];
+    FMM_REQUIRE(lt >= 0 && lt < plan->n_levels, FMM_EINVAL, "box level out of range");
+    FMM_REQUIRE(lt == ls, FMM_EINVAL, "pair " + std::to_string(k) + ": boxes on different levels");
+    const int ox = box_ijk[3 * t] - box_ijk[3 * s], oy = box_ijk[3 * t + 1] - box_ijk[3 * s + 1],
+              oz = box_ijk[3 * t + 2] - box_ijk[3 * s + 2];
+    FMM_REQUIRE(std::abs(ox) <= 8 && std::abs(oy) <= 8 && std::abs(oz) <= 8, FMM_EINVAL,
+                "pair " + std::to_string(k) + ": |offset| > 8");
+    FMM_REQUIRE(ox || oy || oz, FMM_EINVAL, "pair " + std::to_string(k) + ": zero offset");
+    const int64_t key = ((int64_t)lt * 17 + (ox + 8)) * 289 + (oy + 8) * 17 + (oz + 8);
+    auto it = tab_of_key.find(key);
+    if (it == tab_of_key.end()) {
+      it = tab_of_key.emplace(key, (int32_t)tab_keys.size()).first;
+      tab_keys.push_back(key);
+    }
+    pair_tab[k] = it->second;
+  }
+
+  auto* b = new fmm_batch_s();
+  b->plan = plan;
+  b->dtype = dtype;
+  b->nc = plan->nc;
+  b->nc_pad = (plan->nc + 15) / 16 * 16;
+  b->ts = plan->Sz * plan->S * plan->S;
+  b->n_pair = n_pair;
+  b->n_tab = (int64_t)tab_keys.size();
+  auto bail = [&](int s) {
+    fmm_batch_destroy(b);
+    return s;
+  };
+
+  // 2. target tiles: same level and child parity, Morton order of the parent
+  std::vector<int32_t> targets(tgt_box, tgt_box + n_pair);
+  std::sort(targets.begin(), targets.end());
+  targets.erase(std::unique(targets.begin(), targets.end()), targets.end());
+  auto tkey = [&](int32_t t) {
+    const int x = box_ijk[3 * t], y = box_ijk[3 * t + 1], z = box_ijk[3 * t + 2];
+    const uint64_t par = (uint64_t)((x & 1) << 2 | (y & 1) << 1 | (z & 1));
+    const uint64_t mort = (spread3((uint32_t)(x >> 1)) << 2) | (spread3((uint32_t)(y >> 1)) << 1) |
+                          spread3((uint32_t)(z >> 1));
+    return std::make_tuple(box_level[t], par, mort, t);
+  };
+  std::sort(targets.begin(), targets.end(), [&](int32_t a, int32_t c) { return tkey(a) < tkey(c); });
+  std::vector<int32_t> tile_tgt;
+  std::unordered_map<int32_t, int32_t> slot_of;  // target -> tile*16 + col
+  {
+    int col = 16;
+    int64_t prev_group = -1;
+    for (int32_t t : targets) {
+      auto k = tkey(t);
+      const int64_t group = (int64_t)std::get<0>(k) * 8 + (int64_t)std::get<1>(k);
+      if (col == 16 || group != prev_group) {
+        tile_tgt.resize(tile_tgt.size() + 16, -1);
+        col = 0;
+        prev_group = group;
+      }
+      const int32_t tile = (int32_t)(tile_tgt.size() / 16 - 1);
+      tile_tgt[tile * 16 + col] = t;
+      slot_of[t] = tile * 16 + col;
+      ++col;
+    }
+  }
+  const int64_t n_tiles = (int64_t)tile_tgt.size() / 16;
+  b->n_tiles = n_tiles;
+
+  // 3. entries: (tile, table) -> 16 sources
+  struct PE {
+    int32_t tile, tab, col, src;
+  };
+  std::vector<PE> pe(n_pair);
+  for (int64_t k = 0; k < n_pair; ++k) {
+    const int32_t sl = slot_of[tgt_box[k]];
+    pe[k] = {sl / 16, pair_tab[k], sl % 16, src_box[k]};
+  }
+  std::sort(pe.begin(), pe.end(), [](const PE& a, const PE& c) {
+    return std::tie(a.tile, a.tab, a.col) < std::tie(c.tile, c.tab, c.col);
+  });
+  std::vector<int32_t> entry_tab, entry_src, tile_e0(n_tiles + 1, 0);
+  for (int64_t k = 0; k < n_pair; ++k) {
+    if (k > 0 && pe[k].tile == pe[k - 1].tile && pe[k].tab == pe[k - 1].tab && pe[k].col == pe[k - 1].col)
+      return bail(fail(FMM_EINVAL, "duplicate pair (same target and offset twice)"));
+    if (k == 0 || pe[k].tile != pe[k - 1].tile || pe[k].tab != pe[k - 1].tab) {
+      entry_tab.push_back(pe[k].tab);
+      entry_src.resize(entry_src.size() + 16, -1);
+      tile_e0[pe[k].tile + 1] = (int32_t)entry_tab.size();
+    }
+    entry_src[(entry_tab.size() - 1) * 16 + pe[k].col] = pe[k].src;
+  }
+  for (int64_t t = 1; t <= n_tiles; ++t) tile_e0[t] = std::max(tile_e0[t], tile_e0[t - 1]);
+  b->n_entries = (int64_t)entry_tab.size();
+  b->useful = n_pair;
+  b->computed = b->n_entries * 16;
+
+  // 4. work items: split tiles into parts so that one launch has enough workgroups
+  const int target_items = std::max(1, env_int("FMM_M2L_ITEMS", 2048));
+  const int min_entries = std::max(1, env_int("FMM_M2L_MIN_ENTRIES", 8));
+  std::vector<M2LItem> items;
+  std::vector<int32_t> tile_nparts(n_tiles), tile_item0(n_tiles);
+  int64_t split_items = 0;
+  const int64_t want_parts = n_tiles ? (target_items + n_tiles - 1) / n_tiles : 1;
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    const int ne = tile_e0[t + 1] - tile_e0[t];
+    int np = (int)std::min<int64_t>(want_parts, std::max(1, ne / min_entries));
+    np = std::max(1, std::min(np, ne));
+    tile_nparts[t] = np;
+    tile_item0[t] = (int32_t)items.size();
+    for (int k = 0; k < np; ++k) {
+      const int e0 = tile_e0[t] + (int)((int64_t)ne * k / np), e1 = tile_e0[t] + (int)((int64_t)ne * (k + 1) / np);
+      items.push_back({(int32_t)t, e0, e1, k});
+    }
+    if (np > 1) split_items = (int64_t)items.size();
+  }
+  b->n_items = (int64_t)items.size();
+  // partials are indexed by item id; allocate for every item up to the last split tile
+  b->scratch_bytes = split_items * 16 * b->nc_pad * CW * (int64_t)sizeof(double);
+
+  const int rtiles = b->nc_pad / 16;
+  b->rows_per_wave = rtiles > 16 ? 2 : 1;
+  b->waves = (rtiles + b->rows_per_wave - 1) / b->rows_per_wave;
+
+  // 5. derivative tables (FP64) for every (level, offset), then the M2L layout in the dtype
+  std::vector<double> off(3 * b->n_tab), hs(b->n_tab);
+  for (int64_t k = 0; k < b->n_tab; ++k) {
+    const int64_t key = tab_keys[k];
+    const int oz = (int)(key % 17) - 8, oy = (int)((key / 17) % 17) - 8, ox = (int)((key / 289) % 17) - 8;
+    const int lev = (int)(key / (289 * 17));
+    off[3 * k] = ox;
+    off[3 * k + 1] = oy;
+    off[3 * k + 2] = oz;
+    hs[k] = plan->h[lev];
+  }
+  double *d_off = nullptr, *d_h = nullptr, *d_tab64 = nullptr;
+  if ((st = dev_upload(&d_off, off)) || (st = dev_upload(&d_h, hs))) {
+    dev_free(d_off);
+    dev_free(d_h);
+    return bail(st);
+  }
+  const size_t tab_vals = (size_t)b->n_tab * b->ts * CW;
+  if (tab_vals) {
+    if (hipMalloc((void**)&d_tab64, tab_vals * sizeof(double)) != hipSuccess ||
+        hipMalloc(&b->d_tab, tab_vals * real_size(dtype)) != hipSuccess) {
+      dev_free(d_off);
+      dev_free(d_h);
+      dev_free(d_tab64);
+      return bail(fail(FMM_ENOMEM, "table allocation failed"));
+    }
+    st = fmm_deriv_tables(&plan->desc, b->n_tab, d_off, d_h, d_tab64, nullptr);
+    if (!st) st = launch_m2l_table_layout(d_tab64, b->d_tab, b->n_tab, b->ts, dtype, nullptr);
+    hipError_t e = hipDeviceSynchronize();
+    dev_free(d_off);
+    dev_free(d_h);
+    dev_free(d_tab64);
+    if (st) return bail(st);
+    if (e != hipSuccess) return bail(fail(FMM_EHIP, std::string("table generation: ") + hipGetErrorString(e)));
+  } else {
+    dev_free(d_off);
+    dev_free(d_h);
+  }
+
+  std::vector<int32_t> zeros(n_tiles, 0);
+  if ((st = dev_upload(&b->d_tile_tgt, tile_tgt)) || (st = dev_upload(&b->d_tile_nparts, tile_nparts)) ||
+      (st = dev_upload(&b->d_tile_item0, tile_item0)) || (st = dev_upload(&b->d_counter, zeros)) ||
+      (st = dev_upload(&b->d_entry_tab, entry_tab)) || (st = dev_upload(&b->d_entry_src, entry_src)) ||
+      (st = dev_upload(&b->d_items, items)))
+    return bail(st);
+  b->d_jbase = plan->d_jbase;
+  if (b->scratch_bytes) {
+    if (hipMalloc((void**)&b->d_scratch, b->scratch_bytes) != hipSuccess)
+      return bail(fail(FMM_ENOMEM, "scratch allocation failed"));
+  }
+  *out = b;
+  return FMM_OK;
+}
+
+void fmm_batch_destroy(fmm_batch b) {
+  if (!b) return;
+  dev_free(b->d_tab);
+  dev_free(b->d_tile_tgt);
+  dev_free(b->d_tile_nparts);
+  dev_free(b->d_tile_item0);
+  dev_free(b->d_counter);
+  dev_free(b->d_scratch);
+  dev_free(b->d_entry_tab);
+  dev_free(b->d_entry_src);
+  dev_free(b->d_items);
+  delete b;
+}
+
+int fmm_batch_info(fmm_batch b, int64_t* info, int32_t n_info) {
+  FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
+  FMM_REQUIRE(info || n_info == 0, FMM_EINVAL, "info is NULL");
+  const int64_t v[] = {b->n_pair, b->n_tab, b->n_tiles, b->n_entries, b->n_items,
+                       b->useful, b->computed, b->nc, b->nc_pad, b->scratch_bytes};
+  for (int k = 0; k < n_info && k < (int)(sizeof(v) / sizeof(v[0])); ++k) info[k] = v[k];
+  return FMM_OK;
+}
+
+static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local) {
+  M2LArgs a{};
+  a.items = b->d_items;
+  a.n_items = (int32_t)b->n_items;
+  a.tile_tgt = b->d_tile_tgt;
+  a.tile_nparts = b->d_tile_nparts;
+  a.tile_item0 = b->d_tile_item0;
+  a.counter = b->d_counter;
+  a.scratch = b->d_scratch;
+  a.entry_tab = b->d_entry_tab;
+  a.entry_src = b->d_entry_src;
+  a.tab = b->d_tab;
+  a.jbase = b->d_jbase;
+  a.mpole = mpole;
+  a.local = local;
+  a.nc = b->nc;
+  a.nc_pad = b->nc_pad;
+  a.ts = b->ts;
+  return a;
+}
+
+int fmm_m2l_batched(fmm_batch b, const void* mpole, void* local, void* stream) {
+  FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
+  FMM_REQUIRE(b->plan && b->plan->alive, FMM_ESTATE, "the batch's plan was destroyed");
+  if (b->n_items == 0) return FMM_OK;
+  FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
+  return launch_m2l(m2l_args(b, mpole, local), b->dtype, b->rows_per_wave, b->waves, (hipStream_t)stream);
+}
+
+int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const* mpole, void* const* local,
+                          void* stream) {
+  FMM_REQUIRE(n >= 0, FMM_EINVAL, "n < 0");
+  if (n == 0) return FMM_OK;
+  FMM_REQUIRE(batches && mpole && local, FMM_EINVAL, "NULL array");
+  for (int k = 0; k < n; ++k) {
+    FMM_REQUIRE(batches[k], FMM_EINVAL, "NULL batch");
+    FMM_REQUIRE(batches[k]->dtype == batches[0]->dtype, FMM_EINVAL, "batches must share one dtype");
+  }
+  for (int k = 0; k < n; ++k) {
+    int st = fmm_m2l_batched(batches[k], mpole[k], local[k], stream);
+    if (st) return st;
+  }
+  return FMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Small device helpers: complex arithmetic, dtype traits, wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fmm {
+
+// Trivially default-constructible (usable in __shared__ arrays); T{} / T(0) give zero.
+template <typename R>
+struct Cx {
+  R re, im;
+  Cx() = default;
+  __host__ __device__ constexpr Cx(R r, R i = 0) : re(r), im(i) {}
+};
+template <typename R>
+__device__ inline Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ inline Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ inline Cx<R> operator*(Cx<R> a, Cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ inline Cx<R> operator*(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R>
+__device__ inline Cx<R> operator*(Cx<R> a, R s) { return {s * a.re, s * a.im}; }
+template <typename R>
+__device__ inline Cx<R>& operator+=(Cx<R>& a, Cx<R> b) {
+  a.re += b.re;
+  a.im += b.im;
+  return a;
+}
+
+// Value type for a (real type, complex?) pair.
+template <typename R, bool CPLX>
+struct Val;
+template <typename R>
+struct Val<R, false> {
+  using T = R;
+};
+template <typename R>
+struct Val<R, true> {
+  using T = Cx<R>;
+};
+
+__device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ inline float shfl_xor_d(float v, int m) { return __shfl_xor(v, m, 64); }
+
+// Reduce-scatter of the 2^M values v[] over the 64 lanes of a wavefront by halving
+// exchanges: after the call, every lane holds the wave-wide sum of v[lane >> (6 - M)].
+// Uses 2^M - 1 shuffles for the halving steps plus (6 - M) for the remaining ones.
+template <int M, typename R>
+__device__ inline R wave_reduce_scatter(R (&v)[1 << M], int lane) {
+#pragma unroll
+  for (int step = 0; step < M; ++step) {
+    const int L = (1 << M) >> step;
+    const int s = 32 >> step;
+    const bool up = (lane & s) != 0;
+#pragma unroll
+    for (int k = 0; k < L / 2; ++k) {
+      R keep = up ? v[L / 2 + k] : v[k];
+      R send = up ? v[k] : v[L / 2 + k];
+      v[k] = keep + shfl_xor_d(send, s);
+    }
+  }
+  R r = v[0];
+#pragma unroll
+  for (int s = (32 >> M); s >= 1; s >>= 1) r += shfl_xor_d(r, s);
+  return r;
+}
+
+__host__ __device__ constexpr int tri(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) / 2; }
+__host__ __device__ constexpr int nfull(int p) { return p < 0 ? 0 : (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Position of (x, y, z) in the internal full order of M(p): (m_z, m_x, m_y) lexicographic.
+// The kept set J = {m_z < c} is a prefix of this order.
+__host__ __device__ constexpr int full_index(int p, int x, int y, int z) {
+  // slab start: sum_{z' < z} tri(p - z')
+  int s = nfull(p) - nfull(p - z);
+  // row start within slab: sum_{x' < x} (p - z - x' + 1)
+  int r = x * (p - z + 1) - x * (x - 1) / 2;
+  return s + r + y;
+}
+
+}  // namespace fmm

@@ -1,0 +1,106 @@
+// Argument blocks and launchers of the device kernels.  Each launcher validates
+// nothing (the C ABI layer has done that) and only enqueues work on `stream`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fmm {
+
+constexpr int kMaxRecTerms = 6;
+
+// Compression recursion (Sec. 3.1), see RecTerm: for m_z >= c,
+//   D_m = sum_k coef[k] * h^hpow[k] * D_{m + d[k]}    (scaled coefficients, level size h).
+struct RecArgs {
+  int n;
+  int dx[kMaxRecTerms], dy[kMaxRecTerms], dz[kMaxRecTerms], hpow[kMaxRecTerms];
+  double coef[kMaxRecTerms];
+};
+
+struct P2MArgs {
+  int64_t n_box;
+  const double* center;     // [n_box][3]
+  const int32_t* level;     // [n_box]
+  const int64_t* range;     // [n_box][2]
+  const double* level_h;    // [n_levels]
+  int32_t n_levels;
+  int64_t n_pts;
+  const void* xyz;          // [n_pts][3] real
+  const void* w;            // [n_pts] dtype
+  void* out;                // [n_box][Nc] dtype
+  int32_t nc;
+  int32_t c;
+  RecArgs rec;
+};
+
+struct L2PArgs {
+  int64_t n_box;
+  const double* center;
+  const int32_t* level;
+  const int64_t* range;
+  const double* level_h;
+  int32_t n_levels;
+  int64_t n_pts;
+  const void* xyz;          // [n_pts][3] real
+  const void* local;        // [n_box][Nc] dtype
+  void* pot;                // [n_pts] dtype, accumulated
+  int32_t nc;
+  int32_t c;
+  RecArgs rec;
+};
+
+struct TableArgs {
+  int64_t n;
+  const double* offset;  // [n][3] units of h
+  const double* h;       // [n]
+  void* out;             // [n][Sz][S][S] f64 or c128
+  int32_t kernel;
+  int32_t p2;            // 2p
+  int32_t S, Sz;
+  double param;
+};
+
+// One workgroup's share of a target tile: entries [e0, e1) of tile `tile`, part `part` of
+// the tile's `nparts` (nparts > 1 => partial sums go through scratch, last one reduces).
+struct M2LItem {
+  int32_t tile, e0, e1, part;
+};
+
+struct M2LArgs {
+  const M2LItem* items;
+  int32_t n_items;
+  const int32_t* tile_tgt;     // [n_tiles][16], -1 = empty column
+  const int32_t* tile_nparts;  // [n_tiles]
+  const int32_t* tile_item0;   // [n_tiles] first item of the tile
+  int32_t* counter;            // [n_tiles], zero between launches
+  double* scratch;             // [n_items][16][nc_pad] (x2 complex) partials
+  const int32_t* entry_tab;    // [n_entries]
+  const int32_t* entry_src;    // [n_entries][16], -1 = no source
+  const void* tab;             // [n_tab][TS] table values (f64 / f32 / c128 / c64)
+  const int32_t* jbase;        // [Nc] base offset of each kept index into a table
+  const void* mpole;           // [n_box][Nc]
+  void* local;                 // [n_box][Nc]
+  int32_t nc, nc_pad;          // nc_pad = rows rounded to 16
+  int32_t ts;                  // table size S*S*Sz
+};
+
+struct DirectArgs {
+  int64_t n_src, n_tgt;
+  const void* src;
+  const void* w;
+  const void* tgt;
+  void* pot;
+  int32_t kernel;
+  double param;
+};
+
+int launch_tables(const TableArgs& a, bool cplx, hipStream_t s);
+int launch_p2m(const P2MArgs& a, int p, int dtype, hipStream_t s);
+int launch_l2p(const L2PArgs& a, int p, int dtype, hipStream_t s);
+int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int waves, hipStream_t s);
+int launch_direct(const DirectArgs& a, int dtype, hipStream_t s);
+int launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s);
+
+}  // namespace fmm

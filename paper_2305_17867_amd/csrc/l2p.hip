@@ -1,0 +1,50 @@
+// Dispatch of L2P launches to the per-order instantiations (l2p_orders_*.hip).
+#include "../../include/fmm.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fmm {
+
+int launch_l2p_order_0(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_1(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_2(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_3(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_4(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_5(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_6(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_7(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_8(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_9(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_10(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_11(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_12(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_13(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_14(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_15(const L2PArgs& a, int dtype, hipStream_t s);
+int launch_l2p_order_16(const L2PArgs& a, int dtype, hipStream_t s);
+
+int launch_l2p(const L2PArgs& a, int p, int dtype, hipStream_t s) {
+  if (a.n_box == 0) return FMM_OK;
+  switch (p) {
+    case 0: return launch_l2p_order_0(a, dtype, s);
+    case 1: return launch_l2p_order_1(a, dtype, s);
+    case 2: return launch_l2p_order_2(a, dtype, s);
+    case 3: return launch_l2p_order_3(a, dtype, s);
+    case 4: return launch_l2p_order_4(a, dtype, s);
+    case 5: return launch_l2p_order_5(a, dtype, s);
+    case 6: return launch_l2p_order_6(a, dtype, s);
+    case 7: return launch_l2p_order_7(a, dtype, s);
+    case 8: return launch_l2p_order_8(a, dtype, s);
+    case 9: return launch_l2p_order_9(a, dtype, s);
+    case 10: return launch_l2p_order_10(a, dtype, s);
+    case 11: return launch_l2p_order_11(a, dtype, s);
+    case 12: return launch_l2p_order_12(a, dtype, s);
+    case 13: return launch_l2p_order_13(a, dtype, s);
+    case 14: return launch_l2p_order_14(a, dtype, s);
+    case 15: return launch_l2p_order_15(a, dtype, s);
+    case 16: return launch_l2p_order_16(a, dtype, s);
+  }
+  return fail(FMM_EUNSUPPORTED, "order");
+}
+
+}  // namespace fmm

@@ -1,0 +1,213 @@
+"""Python binding of the C ABI: torch tensors in, kernel launches out.
+
+Every function here only checks and marshals arguments and calls libfmm.so; all
+arithmetic of the method runs in the HIP kernels.  Device tensors must live on
+the current CUDA (HIP) device; work is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, make_desc
+
+REAL = {"f64": torch.float64, "f32": torch.float32, "c128": torch.float64, "c64": torch.float32}
+VALUE = {"f64": torch.float64, "f32": torch.float32, "c128": torch.complex128, "c64": torch.complex64}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Desc:
+    """(kernel, order p, dtype, param): kernel in laplace/helmholtz/yukawa/biharmonic,
+    dtype in f64/f32/c128/c64, param = k (Helmholtz) or lambda (Yukawa)."""
+
+    def __init__(self, kernel: str, order: int, dtype: str = "f64", param: float = 0.0):
+        self.kernel, self.order, self.dtype, self.param = kernel, int(order), dtype, float(param)
+        self.c = make_desc(kernel, order, dtype, param)
+
+    def sizes(self) -> tuple[int, int]:
+        nf, nc = C.c_int32(), C.c_int32()
+        check(_lib.load().fmm_sizes(C.byref(self.c), C.byref(nf), C.byref(nc)), "fmm_sizes")
+        return nf.value, nc.value
+
+    @property
+    def nc(self) -> int:
+        return self.sizes()[1]
+
+    def index_table(self) -> np.ndarray:
+        nc = self.nc
+        out = np.zeros((nc, 3), dtype=np.int32)
+        check(_lib.load().fmm_index_table(C.byref(self.c), out.ctypes.data_as(_lib.I32P)),
+              "fmm_index_table")
+        return out
+
+    @property
+    def real_dtype(self):
+        return REAL[self.dtype]
+
+    @property
+    def value_dtype(self):
+        return VALUE[self.dtype]
+
+
+def deriv_tables(desc: Desc, offsets: torch.Tensor, h: torch.Tensor) -> torch.Tensor:
+    """Scaled FP64 derivative tables [n, 2c-1, 2p+1, 2p+1] (complex128 for Helmholtz)."""
+    n = offsets.shape[0]
+    _dev(offsets, torch.float64, "offsets", (n, 3))
+    _dev(h, torch.float64, "h", (n,))
+    p, c = desc.order, (4 if desc.kernel == "biharmonic" else 2)
+    dt = torch.complex128 if desc.kernel == "helmholtz" else torch.float64
+    out = torch.empty((n, 2 * c - 1, 2 * p + 1, 2 * p + 1), dtype=dt, device=offsets.device)
+    check(_lib.load().fmm_deriv_tables(C.byref(desc.c), n, _ptr(offsets), _ptr(h), _ptr(out), _stream()),
+          "fmm_deriv_tables")
+    return out
+
+
+class Plan:
+    """A plan for one (kernel, p, dtype) and the box sizes of the tree levels."""
+
+    def __init__(self, desc: Desc, level_box_size):
+        self.desc = desc
+        lv = np.ascontiguousarray(np.asarray(level_box_size, dtype=np.float64))
+        self.n_levels = int(lv.shape[0])
+        self._h = C.c_void_p()
+        check(_lib.load().fmm_plan_create(C.byref(desc.c), self.n_levels, lv.ctypes.data_as(_lib.F64P),
+                                          C.byref(self._h)), "fmm_plan_create")
+        self.nf, self.nc = desc.sizes()
+
+    def close(self):
+        if self._h:
+            _lib.load().fmm_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _boxes(self, center, level, rng):
+        nb = center.shape[0]
+        _dev(center, torch.float64, "box_center", (nb, 3))
+        _dev(level, torch.int32, "box_level", (nb,))
+        _dev(rng, torch.int64, "pt_range", (nb, 2))
+        return nb
+
+    def p2m(self, center, level, rng, src, w, out=None) -> torch.Tensor:
+        nb = self._boxes(center, level, rng)
+        n = src.shape[0]
+        _dev(src, self.desc.real_dtype, "src_xyz", (n, 3))
+        _dev(w, self.desc.value_dtype, "weight", (n,))
+        if out is None:
+            out = torch.empty((nb, self.nc), dtype=self.desc.value_dtype, device=src.device)
+        _dev(out, self.desc.value_dtype, "mpole", (nb, self.nc))
+        check(_lib.load().fmm_p2m(self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(src),
+                                  _ptr(w), _ptr(out), _stream()), "fmm_p2m")
+        return out
+
+    def l2p(self, center, level, rng, tgt, local, pot) -> torch.Tensor:
+        nb = self._boxes(center, level, rng)
+        n = tgt.shape[0]
+        _dev(tgt, self.desc.real_dtype, "tgt_xyz", (n, 3))
+        _dev(local, self.desc.value_dtype, "local", (nb, self.nc))
+        _dev(pot, self.desc.value_dtype, "potential", (n,))
+        check(_lib.load().fmm_l2p(self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(tgt),
+                                  _ptr(local), _ptr(pot), _stream()), "fmm_l2p")
+        return pot
+
+    def prepare(self, tgt_box, src_box, box_ijk, box_level) -> "Batch":
+        return Batch(self, tgt_box, src_box, box_ijk, box_level)
+
+
+class Batch:
+    """A prepared M2L batch (host arrays in, device work lists and tables owned)."""
+
+    INFO = ("n_pair", "n_tables", "n_tiles", "n_entries", "n_items", "useful_columns",
+            "computed_columns", "nc", "nc_pad", "scratch_bytes")
+
+    def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level):
+        self.plan = plan
+        t = np.ascontiguousarray(np.asarray(tgt_box, dtype=np.int32))
+        s = np.ascontiguousarray(np.asarray(src_box, dtype=np.int32))
+        ijk = np.ascontiguousarray(np.asarray(box_ijk, dtype=np.int32))
+        lev = np.ascontiguousarray(np.asarray(box_level, dtype=np.int32))
+        if t.shape != s.shape or ijk.ndim != 2 or ijk.shape[1] != 3 or lev.shape[0] != ijk.shape[0]:
+            raise ValueError("pair / box array shapes do not match")
+        self.n_box = int(ijk.shape[0])
+        self._h = C.c_void_p()
+        check(_lib.load().fmm_m2l_prepare(plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P),
+                                          s.ctypes.data_as(_lib.I32P), self.n_box,
+                                          ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P),
+                                          C.byref(self._h)), "fmm_m2l_prepare")
+
+    def info(self) -> dict:
+        v = np.zeros(len(self.INFO), dtype=np.int64)
+        check(_lib.load().fmm_batch_info(self._h, v.ctypes.data_as(_lib.I64P), len(self.INFO)),
+              "fmm_batch_info")
+        return dict(zip(self.INFO, v.tolist()))
+
+    def __call__(self, mpole: torch.Tensor, local: torch.Tensor) -> torch.Tensor:
+        d = self.plan.desc
+        _dev(mpole, d.value_dtype, "mpole", (self.n_box, self.plan.nc))
+        _dev(local, d.value_dtype, "local", (self.n_box, self.plan.nc))
+        check(_lib.load().fmm_m2l_batched(self._h, _ptr(mpole), _ptr(local), _stream()), "fmm_m2l_batched")
+        return local
+
+    def close(self):
+        if self._h:
+            _lib.load().fmm_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def m2l_multi(batches, mpoles, locals_):
+    n = len(batches)
+    for b, m, l in zip(batches, mpoles, locals_):
+        d = b.plan.desc
+        _dev(m, d.value_dtype, "mpole", (b.n_box, b.plan.nc))
+        _dev(l, d.value_dtype, "local", (b.n_box, b.plan.nc))
+    hb = (C.c_void_p * n)(*[b._h for b in batches])
+    hm = (C.c_void_p * n)(*[m.data_ptr() for m in mpoles])
+    hl = (C.c_void_p * n)(*[l.data_ptr() for l in locals_])
+    check(_lib.load().fmm_m2l_batched_multi(n, hb, hm, hl, _stream()), "fmm_m2l_batched_multi")
+
+
+def direct(desc: Desc, src, w, tgt, out=None) -> torch.Tensor:
+    ns, nt = src.shape[0], tgt.shape[0]
+    _dev(src, desc.real_dtype, "src_xyz", (ns, 3))
+    _dev(w, desc.value_dtype, "weight", (ns,))
+    _dev(tgt, desc.real_dtype, "tgt_xyz", (nt, 3))
+    if out is None:
+        out = torch.empty(nt, dtype=desc.value_dtype, device=tgt.device)
+    _dev(out, desc.value_dtype, "potential", (nt,))
+    check(_lib.load().fmm_direct(C.byref(desc.c), ns, _ptr(src), _ptr(w), nt, _ptr(tgt), _ptr(out),
+                                 _stream()), "fmm_direct")
+    return out

@@ -1,0 +1,66 @@
+"""Shared test helpers: seeded inputs on the device and oracle references in the library's
+coefficient order.  Oracle values are computed here with ``oracle`` only."""
+from __future__ import annotations
+
+from functools import lru_cache
+
+import numpy as np
+
+import workloads as W
+from oracle import compressed as Z
+from oracle import kernels as K
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / (nb if nb else 1.0))
+
+
+def perm_to_lib(kernel, param, p, lib_index_table):
+    """Positions in the oracle's kept order of each library coefficient."""
+    J = Z.kept(kernel, param, p)
+    pos = {m: k for k, m in enumerate(J)}
+    return np.array([pos[tuple(int(v) for v in r)] for r in lib_index_table])
+
+
+@lru_cache(maxsize=None)
+def oracle_scaled_table(kernel, param, p, o, h):
+    """{m: G^(m)(h o) h^|m|} for the compressed slab (oracle, recurrence tables)."""
+    d = np.array(o, dtype=np.float64) * h
+    tab = Z.slab_table(kernel, param, p, d)
+    return {m: v * h ** sum(m) for m, v in tab.items()}
+
+
+def oracle_m2l_scaled(kernel, param, p, tree_ijk, tree_level, level_h, t, s, beta_s):
+    """theta~ for every box from scaled multipoles beta_s [n_box, Nc] (oracle kept order),
+    grouped by (level, offset) and applied with the oracle's dense T~ matrices."""
+    nb, nc = beta_s.shape
+    out = np.zeros((nb, nc), dtype=np.result_type(beta_s.dtype, np.complex128 if kernel == "helmholtz"
+                                                  else np.float64))
+    off = tree_ijk[t] - tree_ijk[s]
+    lev = tree_level[t]
+    keys = np.concatenate([lev[:, None], off], axis=1)
+    uk, inv = np.unique(keys, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    for g, key in enumerate(uk):
+        sel = np.nonzero(inv == g)[0]
+        h = level_h[int(key[0])]
+        tab = oracle_scaled_table(kernel, param, p, tuple(int(v) for v in key[1:]), h)
+        T = Z.m2l_matrix(kernel, param, p, None, tab)
+        contrib = beta_s[s[sel]] @ T.T
+        np.add.at(out, t[sel], contrib)
+    return out
+
+
+def tree_inputs(n_pts, depth, seed, kind="uniform", max_leaf=64, complex_w=False):
+    if kind == "uniform":
+        pts = W.uniform_points(n_pts, seed)
+        tr = W.uniform_tree(pts, depth)
+    elif kind == "plummer":
+        tr = W.adaptive_tree(W.plummer_points(n_pts, seed, 0.1), max_leaf)
+    else:
+        tr = W.adaptive_tree(W.gaussian_mixture_points(n_pts, seed), max_leaf)
+    w = W.normal_weights(tr.points.shape[0], seed + 100, complex_=complex_w)
+    return tr, w

@@ -1,0 +1,249 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle on seeded inputs.
+
+Tolerances (normwise relative l2 over the whole output array unless stated):
+  FP64 / complex128: 1e-12 (P2M, M2L, L2P, direct, end to end); derivative tables 1e-13
+  per derivative order.
+  FP32 / complex64: P2M and L2P 2e-6, direct 1e-5 (700-term sums), M2L 2e-5 (FP32 products of entries that
+  span many orders of magnitude, FP64 accumulation across offset groups).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import compressed as Z
+from oracle import kernels as K
+from oracle import multiindex as MI
+
+from helpers import oracle_m2l_scaled, oracle_scaled_table, perm_to_lib, rel, tree_inputs
+
+pytestmark = pytest.mark.gpu
+
+CASES = {  # kernel -> (param, real dtype, complex?)
+    "laplace": 0.0, "yukawa": 2.0, "helmholtz": 1.0, "biharmonic": 0.0}
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def desc_for(fmm, kernel, p, single, param=None):
+    cplx = kernel == "helmholtz"
+    dt = ("c64" if single else "c128") if cplx else ("f32" if single else "f64")
+    return fmm.Desc(kernel, p, dt, CASES[kernel] if param is None else param)
+
+
+# ----------------------------------------------------------------------------- derivative tables
+
+@pytest.mark.parametrize("kernel,param,p,h", [
+    ("laplace", 0.0, 8, 1 / 16), ("laplace", 0.0, 12, 1 / 16), ("yukawa", 2.0, 8, 1 / 16),
+    ("yukawa", 2.0, 12, 1 / 4), ("helmholtz", 16.0, 12, 1 / 16), ("helmholtz", 1.0, 6, 1.0),
+    ("biharmonic", 0.0, 10, 1 / 8)])
+def test_deriv_tables(gpu_lib, kernel, param, p, h):
+    fmm = gpu_lib
+    d = fmm.Desc(kernel, p, "c128" if kernel == "helmholtz" else "f64", param)
+    offs = W.all_list2_offsets()[::7]
+    got = host(fmm.deriv_tables(d, dev(offs.astype(np.float64), torch.float64),
+                                dev(np.full(len(offs), h), torch.float64)))
+    for k, o in enumerate(offs):
+        ref = oracle_scaled_table(kernel, param, p, tuple(int(v) for v in o), h)
+        for n in range(2 * p + 1):
+            ms = [m for m in ref if sum(m) == n]
+            a = np.array([got[k][m[2], m[0], m[1]] for m in ms])
+            b = np.array([ref[m] for m in ms])
+            assert rel(a, b) < 1e-13, (o, n, rel(a, b))
+        # unused corner (|m| > 2p) is zero
+        assert got[k][0, 2 * p, 2 * p] == 0
+
+
+# ----------------------------------------------------------------------------- P2M / L2P
+
+def small_tree(seed=3, complex_w=False):
+    tr, w = tree_inputs(1 << 13, 3, seed, complex_w=complex_w)
+    return tr, w
+
+
+@pytest.mark.parametrize("kernel", list(CASES))
+@pytest.mark.parametrize("single", [False, True])
+@pytest.mark.parametrize("p", [0, 4, 8])
+def test_p2m(gpu_lib, kernel, single, p):
+    fmm = gpu_lib
+    d = desc_for(fmm, kernel, p, single)
+    tr, w = small_tree(complex_w=kernel == "helmholtz")
+    param = CASES[kernel]
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    # boxes of levels 2 and 3 in one call (different h), plus an empty and a one-point range
+    boxes = np.concatenate([tr.boxes_at(2), tr.boxes_at(3)])
+    rng = tr.pt_range[boxes].copy()
+    rng[3] = [rng[3][0], rng[3][0]]
+    rng[5] = [rng[5][0], rng[5][0] + 1]
+    rd = d.real_dtype
+    out = plan.p2m(dev(tr.center[boxes], torch.float64), dev(tr.level[boxes], torch.int32),
+                   dev(rng, torch.int64), dev(tr.points, rd), dev(w, d.value_dtype))
+    got = host(out)[:, :]
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    ref = []
+    for k, b in enumerate(boxes):
+        lo, hi = rng[k]
+        beta = Z.p2m(kernel, param, p, tr.center[b], tr.points[lo:hi], w[lo:hi])
+        ref.append(Z.scale_multipole(kernel, param, p, beta, 1.0 / lh[tr.level[b]])[perm])
+    ref = np.array(ref)
+    assert np.all(got[3] == 0)
+    tol = 2e-6 if single else 1e-12
+    assert rel(got, ref) < tol, rel(got, ref)
+
+
+@pytest.mark.parametrize("kernel", list(CASES))
+@pytest.mark.parametrize("single", [False, True])
+@pytest.mark.parametrize("p", [0, 5, 8])
+def test_l2p(gpu_lib, kernel, single, p):
+    fmm = gpu_lib
+    d = desc_for(fmm, kernel, p, single)
+    tr, _ = small_tree(seed=4)
+    param = CASES[kernel]
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    boxes = tr.boxes_at(3)
+    nc = d.nc
+    g = np.random.Generator(np.random.PCG64(11))
+    theta = g.standard_normal((len(boxes), nc))
+    if kernel == "helmholtz":
+        theta = theta + 1j * g.standard_normal((len(boxes), nc))
+    pot0 = g.standard_normal(tr.points.shape[0])
+    if kernel == "helmholtz":
+        pot0 = pot0 + 0j
+    pot = dev(pot0, d.value_dtype)
+    plan.l2p(dev(tr.center[boxes], torch.float64), dev(tr.level[boxes], torch.int32),
+             dev(tr.pt_range[boxes], torch.int64), dev(tr.points, d.real_dtype),
+             dev(theta, d.value_dtype), pot)
+    got = host(pot) - pot0
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    inv = np.argsort(perm)
+    th_or = theta[:, inv]  # oracle kept order
+    ref = np.zeros_like(pot0)
+    for k, b in enumerate(boxes):
+        lo, hi = tr.pt_range[b]
+        th = Z.unscale_local(kernel, param, p, th_or[k], 1.0 / lh[3])
+        ref[lo:hi] += Z.l2p(kernel, param, p, tr.center[b], th, tr.points[lo:hi])
+    tol = 2e-6 if single else 1e-12
+    assert rel(got, ref) < tol, rel(got, ref)
+
+
+# ----------------------------------------------------------------------------- M2L
+
+M2L_CASES = [("laplace", 8, False), ("laplace", 8, True), ("laplace", 12, False), ("yukawa", 6, True),
+             ("biharmonic", 6, False), ("helmholtz", 6, False), ("helmholtz", 4, True),
+             ("laplace", 16, False), ("biharmonic", 12, True)]
+
+
+@pytest.fixture(scope="module")
+def m2l_tree():
+    pts = W.uniform_points(4096, 7)
+    return W.uniform_tree(pts, 3)
+
+
+@pytest.mark.parametrize("kernel,p,single", M2L_CASES)
+@pytest.mark.parametrize("items", [1, 4096])
+def test_m2l(gpu_lib, m2l_tree, kernel, p, single, items, monkeypatch):
+    fmm = gpu_lib
+    monkeypatch.setenv("FMM_M2L_ITEMS", str(items))
+    tr = m2l_tree
+    param = CASES[kernel]
+    d = desc_for(fmm, kernel, p, single)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    levels = [3] if p >= 12 else [2, 3]
+    t, s = W.interaction_pairs(tr, levels)
+    batch = plan.prepare(t, s, tr.ijk, tr.level)
+    info = batch.info()
+    assert info["n_pair"] == len(t)
+    nc = d.nc
+    g = np.random.Generator(np.random.PCG64(21))
+    beta = g.standard_normal((tr.n_box, nc))
+    if kernel == "helmholtz":
+        beta = beta + 1j * g.standard_normal((tr.n_box, nc))
+    loc0 = g.standard_normal((tr.n_box, nc))
+    if kernel == "helmholtz":
+        loc0 = loc0 + 1j * g.standard_normal((tr.n_box, nc))
+    mp = dev(beta, d.value_dtype)
+    loc = dev(loc0, d.value_dtype)
+    batch(mp, loc)
+    got = host(loc) - host(dev(loc0, d.value_dtype))
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    inv = np.argsort(perm)
+    ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t, s, beta[:, inv])
+    ref = ref[:, perm]
+    tol = 2e-5 if single else 1e-12
+    assert rel(got, ref) < tol, rel(got, ref)
+    # deterministic: a second launch on the same input gives bit-identical output
+    loc2 = dev(loc0, d.value_dtype)
+    batch(mp, loc2)
+    assert np.array_equal(host(loc2), host(loc))
+
+
+def test_m2l_empty_and_validation(gpu_lib):
+    fmm = gpu_lib
+    d = fmm.Desc("laplace", 4, "f64")
+    plan = fmm.Plan(d, [1.0, 0.5])
+    b = plan.prepare(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((2, 3), np.int32),
+                     np.zeros(2, np.int32))
+    z = torch.zeros((2, d.nc), dtype=torch.float64, device="cuda")
+    b(z, z)
+    with pytest.raises(fmm._lib.FmmError):
+        plan.prepare([0], [1], [[0, 0, 0], [1, 0, 0]], [1, 0])  # different levels
+    with pytest.raises(fmm._lib.FmmError):
+        plan.prepare([0], [0], [[0, 0, 0]], [0])  # zero offset
+    with pytest.raises(fmm._lib.FmmError):
+        plan.prepare([0, 0], [1, 1], [[0, 0, 0], [2, 0, 0]], [0, 0])  # duplicate pair
+
+
+# ----------------------------------------------------------------------------- direct, end to end
+
+@pytest.mark.parametrize("kernel", list(CASES))
+@pytest.mark.parametrize("single", [False, True])
+def test_direct(gpu_lib, kernel, single):
+    fmm = gpu_lib
+    d = desc_for(fmm, kernel, 2, single)
+    g = np.random.Generator(np.random.PCG64(2))
+    src = g.random((700, 3))
+    tgt = np.concatenate([g.random((300, 3)), src[:5]])  # includes coincident points
+    w = W.normal_weights(700, 4, complex_=kernel == "helmholtz")
+    got = host(fmm.direct(d, dev(src, d.real_dtype), dev(w, d.value_dtype), dev(tgt, d.real_dtype)))
+    ref = K.direct_sum(kernel, CASES[kernel], src, w, tgt)
+    tol = 1e-5 if single else 1e-12
+    assert rel(got, ref) < tol
+
+
+def test_end_to_end_two_box_laplace_p4(gpu_lib):
+    """64 sources in [-0.5,0.5]^3, 64 targets in the unit box at (3,0,0), Laplace p=4, FP64."""
+    fmm = gpu_lib
+    src, tgt, w, c1, c2 = W.small_two_box(0)
+    p = 4
+    d = fmm.Desc("laplace", p, "f64")
+    plan = fmm.Plan(d, [1.0])
+    cen = np.array([c1, c2])
+    lev = np.zeros(2, np.int32)
+    rng_s = np.array([[0, 64], [0, 0]])
+    mp = plan.p2m(dev(cen, torch.float64), dev(lev, torch.int32), dev(rng_s, torch.int64),
+                  dev(src, torch.float64), dev(w, torch.float64))
+    batch = plan.prepare([1], [0], [[0, 0, 0], [3, 0, 0]], [0, 0])
+    loc = torch.zeros_like(mp)
+    batch(mp, loc)
+    pot = torch.zeros(64, dtype=torch.float64, device="cuda")
+    plan.l2p(dev(cen[1:], torch.float64), dev(lev[1:], torch.int32), dev(np.array([[0, 64]]), torch.int64),
+             dev(tgt, torch.float64), loc[1:].contiguous(), pot)
+    got = host(pot)
+    beta = Z.p2m("laplace", 0.0, p, c1, src, w)
+    th = Z.m2l("laplace", 0.0, p, c2 - c1, beta)
+    ref = Z.l2p("laplace", 0.0, p, c2, th, tgt)
+    assert rel(got, ref) < 1e-12
+    exact = K.direct_sum("laplace", 0.0, src, w, tgt)
+    e = rel(got, exact)
+    assert 1e-5 < e < 1e-3  # the truncation error of p = 4, not roundoff
