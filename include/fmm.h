@@ -151,10 +151,32 @@ int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const
                     fmm_batch* batch);
 void fmm_batch_destroy(fmm_batch batch);
 
+/* Launch shape of a prepared M2L batch.  A workgroup owns a tile of 16 * col_groups *
+ * col_tiles_per_wave target boxes; each of its wavefronts computes rows_per_wave x
+ * col_tiles_per_wave output tiles of 16 x 16 coefficients on the matrix cores, and there are
+ * ceil(ceil(Nc / 16) / rows_per_wave) * col_groups wavefronts (at most 8).  Tiles are split
+ * into parts (partials summed in a fixed order) so that one launch has about target_items
+ * workgroups.  Zero fields are chosen automatically. */
+typedef struct {
+  int32_t rows_per_wave;      /* 1..5 */
+  int32_t col_tiles_per_wave; /* 1..2 */
+  int32_t col_groups;         /* 1, 2 or 4 */
+  int32_t target_items;       /* >= 1 */
+  int32_t lds_buffers;        /* 1: stage one offset group at a time; 2: double buffered */
+} fmm_m2l_tuning;
+
+/* fmm_m2l_prepare with an explicit launch shape (tuning may be NULL: automatic).  An
+ * unsupported or unfitting shape returns FMM_EUNSUPPORTED. */
+int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                       int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
+                       const fmm_m2l_tuning* tuning, fmm_batch* batch);
+
 /* Statistics of a prepared batch, written to info[0 .. n_info-1] ([host]):
  * 0 n_pair, 1 n_tables, 2 n_tiles, 3 n_entries (tile x offset groups), 4 n_items (workgroups
  * of one launch), 5 useful pair-columns, 6 computed pair-columns (incl. padding), 7 Nc,
- * 8 rows padded to a multiple of 16, 9 scratch bytes. */
+ * 8 rows padded to a multiple of 16, 9 scratch bytes, 10 row tiles per wavefront,
+ * 11 column tiles per wavefront, 12 wavefronts per workgroup, 13 column groups,
+ * 14 LDS bytes per workgroup, 15 LDS buffers. */
 int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
 
 /* Batched M2L: local[t] += sum over pairs (t, s) of T(c_t - c_s) mpole[s], T[i,q] =

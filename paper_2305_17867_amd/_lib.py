@@ -23,6 +23,11 @@ class FmmDesc(C.Structure):
                 ("flags", C.c_int32), ("param", C.c_double)]
 
 
+class FmmM2LTuning(C.Structure):
+    _fields_ = [("rows_per_wave", C.c_int32), ("col_tiles_per_wave", C.c_int32),
+                ("col_groups", C.c_int32), ("target_items", C.c_int32), ("lds_buffers", C.c_int32)]
+
+
 class FmmError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
@@ -46,6 +51,8 @@ SIGNATURES = {
     "fmm_p2m": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
     "fmm_l2p": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
     "fmm_m2l_prepare": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P, C.POINTER(P)]),
+    "fmm_m2l_prepare_ex": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P,
+                                     C.POINTER(FmmM2LTuning), C.POINTER(P)]),
     "fmm_batch_destroy": (None, [P]),
     "fmm_batch_info": (C.c_int, [P, I64P, C.c_int32]),
     "fmm_m2l_batched": (C.c_int, [P, P, P, P]),

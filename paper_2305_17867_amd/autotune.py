@@ -1,0 +1,107 @@
+"""Autotuner for the batched M2L launch shape.
+
+For one (kernel, order, dtype) and one set of interaction pairs it prepares the batch with
+every candidate launch shape (rows per wavefront, column tiles per wavefront, column
+groups, workgroups per launch; see fmm_m2l_tuning in include/fmm.h), times the launches
+with HIP events on the current stream, and keeps the fastest.  Results are cached in a JSON
+file keyed by device, kernel, order, dtype and problem size, so later runs reuse them.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import fmm
+
+SHAPES = [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (5, 1)]  # (rows, col tiles) per wave
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fmm_m2l_autotune.json")
+
+
+def candidates(nc: int, n_cu: int, max_waves: int = 8):
+    rtiles = (nc + 15) // 16
+    out = []
+    for rt, ctw in SHAPES:
+        nrg = -(-rtiles // rt)
+        for ncg in (1, 2, 4):
+            waves = nrg * ncg
+            if waves > max_waves or ncg * ctw > 4:
+                continue
+            for items in (n_cu, 2 * n_cu):
+                for nbuf in (1, 2):
+                    out.append({"rows_per_wave": rt, "col_tiles_per_wave": ctw, "col_groups": ncg,
+                                "target_items": items, "lds_buffers": nbuf})
+    return out
+
+
+def _key(desc, n_pair: int) -> str:
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return f"{name}|hip{torch.version.hip}|{desc.kernel}|p{desc.order}|{desc.dtype}|pairs{n_pair}"
+
+
+def time_batch(batch, mpole, local, reps: int = 5) -> float:
+    batch(mpole, local)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        batch(mpole, local)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def tune(plan: "fmm.Plan", tgt_box, src_box, box_ijk, box_level, reps: int = 5,
+         cache: str | None = DEFAULT_CACHE, max_candidates: int | None = None, log=None) -> dict:
+    """Returns {"tuning": best tuning dict, "ms": its time, "results": [(tuning, ms | error)]}."""
+    desc = plan.desc
+    key = _key(desc, len(tgt_box))
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                db = json.load(f)
+            if key in db:
+                return db[key]
+        except (OSError, ValueError):
+            pass
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n_box = int(np.asarray(box_level).shape[0])
+    mpole = torch.randn((n_box, plan.nc), dtype=desc.value_dtype, device="cuda")
+    local = torch.zeros_like(mpole)
+    cands = candidates(plan.nc, n_cu)
+    if max_candidates:
+        cands = cands[:max_candidates]
+    results = []
+    best = None
+    t0 = time.time()
+    for tun in cands:
+        try:
+            b = plan.prepare(tgt_box, src_box, box_ijk, box_level, tuning=tun)
+        except fmm._lib.FmmError as e:
+            results.append((tun, str(e).split(":")[1].strip()))
+            continue
+        ms = time_batch(b, mpole, local, reps)
+        b.close()
+        results.append((tun, ms))
+        if log:
+            log(f"  {tun} -> {ms:.3f} ms")
+        if best is None or ms < best[1]:
+            best = (tun, ms)
+    out = {"tuning": best[0] if best else None, "ms": best[1] if best else None, "results": results,
+           "seconds": time.time() - t0}
+    if cache and best:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        db = {}
+        if os.path.exists(cache):
+            try:
+                with open(cache) as f:
+                    db = json.load(f)
+            except (OSError, ValueError):
+                db = {}
+        db[key] = out
+        with open(cache, "w") as f:
+            json.dump(db, f, indent=1)
+    return out

@@ -29,7 +29,10 @@ struct fmm_plan_s {
 struct fmm_batch_s {
   fmm_plan plan = nullptr;
   int dtype = 0;
-  int nc = 0, nc_pad = 0, ts = 0, waves = 1, rows_per_wave = 1;
+  int nc = 0, nc_pad = 0, ts = 0, waves = 1, rows_per_wave = 1, col_tiles = 1, col_groups = 1;
+  int pf_class = 0, nbuf = 2;
+  int64_t lds_bytes = 0;
+  M2LArgs shape{};  // ldb, k4p, tab_off, buf_elems, nt, nrg
   int64_t n_pair = 0, n_tab = 0, n_tiles = 0, n_entries = 0, n_items = 0;
   int64_t useful = 0, computed = 0, scratch_bytes = 0;
   void* d_tab = nullptr;
@@ -269,6 +272,12 @@ int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const v
 
 int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
                     int64_t n_box, const int32_t* box_ijk, const int32_t* box_level, fmm_batch* out) {
+  return fmm_m2l_prepare_ex(plan, n_pair, tgt_box, src_box, n_box, box_ijk, box_level, nullptr, out);
+}
+
+int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                       int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
+                       const fmm_m2l_tuning* tuning, fmm_batch* out) {
   int st = check_plan(plan);
   if (st) return st;
   FMM_REQUIRE(out, FMM_EINVAL, "batch output pointer is NULL");
@@ -313,53 +322,162 @@ int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const
   b->ts = plan->Sz * plan->S * plan->S;
   b->n_pair = n_pair;
   b->n_tab = (int64_t)tab_keys.size();
-  auto bail = [&](int s) {
-    fmm_batch_destroy(b);
-    return s;
-  };
 
-  // 2. target tiles: same level and child parity, Morton order of the parent
+  // 2. launch shape (see fmm_m2l_tuning): the automatic choice scores every instantiated shape
+  //    by row padding, LDS reads per matrix-core product, column fill and occupancy.
+  int dev = 0, lds_max = 65536, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      lds_max = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+  }
+  (void)hipGetLastError();
+  {
+    const int rtiles = b->nc_pad / 16;
+    const size_t rb = real_size(dtype);
+    const size_t cap = (size_t)lds_max - 64;  // room for the kernel's static LDS
+    struct Cand {
+      int rt, ctw, ncg, nrg, waves, pf, nbuf;
+      M2LArgs sh;
+      size_t lds;
+    };
+    auto make = [&](int rt, int ctw, int ncg, int nbuf, Cand& c) {
+      if (rt < 1 || ctw < 1 || ncg < 1 || !m2l_shape_instantiated(rt, ctw)) return false;
+      const int nrg = (rtiles + rt - 1) / rt;
+      const int waves = nrg * ncg;
+      if (waves > kM2LMaxThreads / 64 || ncg * ctw > 4) return false;
+      c.rt = rt;
+      c.ctw = ctw;
+      c.ncg = ncg;
+      c.nrg = nrg;
+      c.waves = waves;
+      c.sh = M2LArgs{};
+      c.sh.ts = b->ts;
+      c.sh.nc = b->nc;
+      m2l_shape(c.sh, rb, cplx, ncg * ctw);
+      c.sh.nrg = nrg;
+      c.pf = m2l_prefetch_class(c.sh, cplx, ncg * ctw, waves);
+      c.nbuf = nbuf;
+      c.lds = m2l_lds_bytes(c.sh, rb, nbuf);
+      return c.pf >= 0 && c.lds <= cap;
+    };
+    Cand best{};
+    bool found = false;
+    if (tuning && tuning->rows_per_wave > 0) {
+      found = make(tuning->rows_per_wave, std::max(1, tuning->col_tiles_per_wave), std::max(1, tuning->col_groups),
+                   tuning->lds_buffers == 1 ? 1 : 2, best);
+      if (!found) {
+        delete b;
+        return fail(FMM_EUNSUPPORTED, "requested M2L launch shape is not instantiated or does not fit");
+      }
+    } else {
+      // score: row padding x LDS reads per product x column fill x occupancy (waves per SIMD
+      // from LDS and an estimate of the register need)
+      double best_score = 1e30;
+      for (int rt = 1; rt <= 5; ++rt)
+        for (int ctw = 1; ctw <= 2; ++ctw)
+          for (int ncg : {1, 2, 4})
+            for (int nb : {1, 2}) {
+              Cand c{};
+              if (!make(rt, ctw, ncg, nb, c)) continue;
+              const double pad = (double)(c.nrg * rt) / rtiles;
+              const double reads = (double)(rt + ctw) / (rt * ctw);
+              const int nt = 16 * ncg * ctw;
+              const double fill = nt <= 16 ? 1.0 : (nt <= 32 ? 1.04 : 1.10);
+              const int wg_lds = (int)std::max<size_t>(1, (size_t)lds_max / std::max<size_t>(c.lds, 1));
+              const int vgpr = 40 + rt * ctw * (cplx ? 2 : 1) * (int)(rb == 8 ? 8 : 4) * (rb == 4 ? 2 : 1) +
+                               (c.pf == 0 ? 24 : c.pf == 1 ? 48 : 88) * (int)(rb / 4);
+              const int waves_simd_reg = std::max(1, 512 / std::max(64, vgpr));
+              const int wgs = std::max(1, std::min(wg_lds, (4 * waves_simd_reg) / c.waves));
+              const double per_simd = (double)(wgs * c.waves) / 4.0;
+              const double occ = per_simd >= 2.0 ? 1.0 : (per_simd >= 1.0 ? 1.5 : 2.0);
+              const double sync = nb == 1 ? 1.0 : 1.08;
+              const double score = pad * (0.5 + 0.5 * reads) * fill * occ * sync;
+              if (score < best_score) {
+                best_score = score;
+                best = c;
+                found = true;
+              }
+            }
+      if (!found) {
+        delete b;
+        return fail(FMM_EUNSUPPORTED, "M2L tile does not fit in LDS / registers for this order and dtype");
+      }
+    }
+    b->rows_per_wave = best.rt;
+    b->col_tiles = best.ctw;
+    b->col_groups = best.ncg;
+    b->waves = best.waves;
+    b->pf_class = best.pf;
+    b->nbuf = best.nbuf;
+    b->shape = best.sh;
+    b->lds_bytes = (int64_t)best.lds;
+  }
+  const int NT = 16 * b->col_tiles * b->col_groups;
+
+
+  // 3. target tiles: same level and child parity, then the same set of offsets (signature) where
+  //    possible, then Morton order of the parent; NT targets per tile
   std::vector<int32_t> targets(tgt_box, tgt_box + n_pair);
   std::sort(targets.begin(), targets.end());
   targets.erase(std::unique(targets.begin(), targets.end()), targets.end());
-  auto tkey = [&](int32_t t) {
+  std::unordered_map<int32_t, int32_t> tpos;
+  for (size_t k = 0; k < targets.size(); ++k) tpos[targets[k]] = (int32_t)k;
+  std::vector<std::vector<int32_t>> sig(targets.size());
+  for (int64_t k = 0; k < n_pair; ++k) sig[tpos[tgt_box[k]]].push_back(pair_tab[k]);
+  auto geo = [&](int32_t t) {
     const int x = box_ijk[3 * t], y = box_ijk[3 * t + 1], z = box_ijk[3 * t + 2];
     const uint64_t par = (uint64_t)((x & 1) << 2 | (y & 1) << 1 | (z & 1));
     const uint64_t mort = (spread3((uint32_t)(x >> 1)) << 2) | (spread3((uint32_t)(y >> 1)) << 1) |
                           spread3((uint32_t)(z >> 1));
     return std::make_tuple(box_level[t], par, mort, t);
   };
-  std::sort(targets.begin(), targets.end(), [&](int32_t a, int32_t c) { return tkey(a) < tkey(c); });
+  std::sort(targets.begin(), targets.end(), [&](int32_t a, int32_t c) { return geo(a) < geo(c); });
+  std::map<std::vector<int32_t>, int32_t> sig_id;
+  std::vector<int32_t> tsig(targets.size());
+  for (int32_t t : targets) {
+    auto& v = sig[tpos[t]];
+    std::sort(v.begin(), v.end());
+    auto it2 = sig_id.emplace(v, (int32_t)sig_id.size()).first;
+    tsig[tpos[t]] = it2->second;
+  }
+  std::stable_sort(targets.begin(), targets.end(), [&](int32_t a, int32_t c) {
+    auto ga = geo(a), gc = geo(c);
+    if (std::get<0>(ga) != std::get<0>(gc)) return std::get<0>(ga) < std::get<0>(gc);
+    if (std::get<1>(ga) != std::get<1>(gc)) return std::get<1>(ga) < std::get<1>(gc);
+    return tsig[tpos[a]] < tsig[tpos[c]];
+  });
   std::vector<int32_t> tile_tgt;
-  std::unordered_map<int32_t, int32_t> slot_of;  // target -> tile*16 + col
+  std::unordered_map<int32_t, int32_t> slot_of;  // target -> tile * NT + col
   {
-    int col = 16;
+    int col = NT;
     int64_t prev_group = -1;
     for (int32_t t : targets) {
-      auto k = tkey(t);
+      auto k = geo(t);
       const int64_t group = (int64_t)std::get<0>(k) * 8 + (int64_t)std::get<1>(k);
-      if (col == 16 || group != prev_group) {
-        tile_tgt.resize(tile_tgt.size() + 16, -1);
+      if (col == NT || group != prev_group) {
+        tile_tgt.resize(tile_tgt.size() + NT, -1);
         col = 0;
         prev_group = group;
       }
-      const int32_t tile = (int32_t)(tile_tgt.size() / 16 - 1);
-      tile_tgt[tile * 16 + col] = t;
-      slot_of[t] = tile * 16 + col;
+      const int32_t tile = (int32_t)(tile_tgt.size() / NT - 1);
+      tile_tgt[tile * NT + col] = t;
+      slot_of[t] = tile * NT + col;
       ++col;
     }
   }
-  const int64_t n_tiles = (int64_t)tile_tgt.size() / 16;
+  const int64_t n_tiles = (int64_t)tile_tgt.size() / NT;
   b->n_tiles = n_tiles;
 
-  // 3. entries: (tile, table) -> 16 sources
+  // 4. entries: (tile, table) -> NT sources
   struct PE {
     int32_t tile, tab, col, src;
   };
   std::vector<PE> pe(n_pair);
   for (int64_t k = 0; k < n_pair; ++k) {
     const int32_t sl = slot_of[tgt_box[k]];
-    pe[k] = {sl / 16, pair_tab[k], sl % 16, src_box[k]};
+    pe[k] = {sl / NT, pair_tab[k], sl % NT, src_box[k]};
   }
   std::sort(pe.begin(), pe.end(), [](const PE& a, const PE& c) {
     return std::tie(a.tile, a.tab, a.col) < std::tie(c.tile, c.tab, c.col);
@@ -367,21 +485,29 @@ int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const
   std::vector<int32_t> entry_tab, entry_src, tile_e0(n_tiles + 1, 0);
   for (int64_t k = 0; k < n_pair; ++k) {
     if (k > 0 && pe[k].tile == pe[k - 1].tile && pe[k].tab == pe[k - 1].tab && pe[k].col == pe[k - 1].col)
-      return bail(fail(FMM_EINVAL, "duplicate pair (same target and offset twice)"));
+    {
+      delete b;
+      return fail(FMM_EINVAL, "duplicate pair (same target and offset twice)");
+    }
     if (k == 0 || pe[k].tile != pe[k - 1].tile || pe[k].tab != pe[k - 1].tab) {
       entry_tab.push_back(pe[k].tab);
-      entry_src.resize(entry_src.size() + 16, -1);
+      entry_src.resize(entry_src.size() + NT, -1);
       tile_e0[pe[k].tile + 1] = (int32_t)entry_tab.size();
     }
-    entry_src[(entry_tab.size() - 1) * 16 + pe[k].col] = pe[k].src;
+    entry_src[(entry_tab.size() - 1) * NT + pe[k].col] = pe[k].src;
   }
   for (int64_t t = 1; t <= n_tiles; ++t) tile_e0[t] = std::max(tile_e0[t], tile_e0[t - 1]);
   b->n_entries = (int64_t)entry_tab.size();
+  auto bail = [&](int s) {
+    fmm_batch_destroy(b);
+    return s;
+  };
   b->useful = n_pair;
-  b->computed = b->n_entries * 16;
+  b->computed = b->n_entries * NT;
 
-  // 4. work items: split tiles into parts so that one launch has enough workgroups
-  const int target_items = std::max(1, env_int("FMM_M2L_ITEMS", 2048));
+  // 5. work items: split tiles into parts so that one launch has enough workgroups
+  int target_items = (tuning && tuning->target_items > 0) ? tuning->target_items : 2 * n_cu;
+  target_items = std::max(1, env_int("FMM_M2L_ITEMS", target_items));
   const int min_entries = std::max(1, env_int("FMM_M2L_MIN_ENTRIES", 8));
   std::vector<M2LItem> items;
   std::vector<int32_t> tile_nparts(n_tiles), tile_item0(n_tiles);
@@ -401,13 +527,9 @@ int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const
   }
   b->n_items = (int64_t)items.size();
   // partials are indexed by item id; allocate for every item up to the last split tile
-  b->scratch_bytes = split_items * 16 * b->nc_pad * CW * (int64_t)sizeof(double);
+  b->scratch_bytes = split_items * NT * b->nc_pad * CW * (int64_t)sizeof(double);
 
-  const int rtiles = b->nc_pad / 16;
-  b->rows_per_wave = rtiles > 16 ? 2 : 1;
-  b->waves = (rtiles + b->rows_per_wave - 1) / b->rows_per_wave;
-
-  // 5. derivative tables (FP64) for every (level, offset), then the M2L layout in the dtype
+  // 6. derivative tables (FP64) for every (level, offset), then the M2L layout in the dtype
   std::vector<double> off(3 * b->n_tab), hs(b->n_tab);
   for (int64_t k = 0; k < b->n_tab; ++k) {
     const int64_t key = tab_keys[k];
@@ -478,8 +600,10 @@ void fmm_batch_destroy(fmm_batch b) {
 int fmm_batch_info(fmm_batch b, int64_t* info, int32_t n_info) {
   FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
   FMM_REQUIRE(info || n_info == 0, FMM_EINVAL, "info is NULL");
-  const int64_t v[] = {b->n_pair, b->n_tab, b->n_tiles, b->n_entries, b->n_items,
-                       b->useful, b->computed, b->nc, b->nc_pad, b->scratch_bytes};
+  const int64_t v[] = {b->n_pair,        b->n_tab,     b->n_tiles, b->n_entries,  b->n_items,
+                       b->useful,        b->computed,  b->nc,      b->nc_pad,     b->scratch_bytes,
+                       b->rows_per_wave, b->col_tiles, b->waves,   b->col_groups, b->lds_bytes,
+                       b->nbuf};
   for (int k = 0; k < n_info && k < (int)(sizeof(v) / sizeof(v[0])); ++k) info[k] = v[k];
   return FMM_OK;
 }
@@ -502,6 +626,12 @@ static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local) {
   a.nc = b->nc;
   a.nc_pad = b->nc_pad;
   a.ts = b->ts;
+  a.ldb = b->shape.ldb;
+  a.k4p = b->shape.k4p;
+  a.tab_off = b->shape.tab_off;
+  a.buf_elems = b->shape.buf_elems;
+  a.nt = b->shape.nt;
+  a.nrg = b->shape.nrg;
   return a;
 }
 
@@ -510,7 +640,8 @@ int fmm_m2l_batched(fmm_batch b, const void* mpole, void* local, void* stream) {
   FMM_REQUIRE(b->plan && b->plan->alive, FMM_ESTATE, "the batch's plan was destroyed");
   if (b->n_items == 0) return FMM_OK;
   FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
-  return launch_m2l(m2l_args(b, mpole, local), b->dtype, b->rows_per_wave, b->waves, (hipStream_t)stream);
+  return launch_m2l(m2l_args(b, mpole, local), b->dtype, b->rows_per_wave, b->col_tiles, b->pf_class, b->nbuf,
+                    b->waves, (hipStream_t)stream);
 }
 
 int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const* mpole, void* const* local,

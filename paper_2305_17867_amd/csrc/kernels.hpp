@@ -67,22 +67,35 @@ struct M2LItem {
   int32_t tile, e0, e1, part;
 };
 
+// M2L launch limits: at most 8 wavefronts per workgroup; per-thread register prefetch of one
+// entry in two size classes (table values, source-tile values).
+constexpr int kM2LMaxThreads = 512;
+constexpr int kPrefT0 = 4, kPrefB0 = 8;
+constexpr int kPrefT1 = 8, kPrefB1 = 16;
+constexpr int kPrefT2 = 20, kPrefB2 = 24;
+
 struct M2LArgs {
   const M2LItem* items;
   int32_t n_items;
-  const int32_t* tile_tgt;     // [n_tiles][16], -1 = empty column
+  const int32_t* tile_tgt;     // [n_tiles][16 CT], -1 = empty column
   const int32_t* tile_nparts;  // [n_tiles]
   const int32_t* tile_item0;   // [n_tiles] first item of the tile
   int32_t* counter;            // [n_tiles], zero between launches
-  double* scratch;             // [n_items][16][nc_pad] (x2 complex) partials
+  double* scratch;             // [n_items][16 CT][nc_pad] (x2 complex) partials
   const int32_t* entry_tab;    // [n_entries]
-  const int32_t* entry_src;    // [n_entries][16], -1 = no source
+  const int32_t* entry_src;    // [n_entries][16 CT], -1 = no source
   const void* tab;             // [n_tab][TS] table values (f64 / f32 / c128 / c64)
   const int32_t* jbase;        // [Nc] base offset of each kept index into a table
   const void* mpole;           // [n_box][Nc]
   void* local;                 // [n_box][Nc]
   int32_t nc, nc_pad;          // nc_pad = rows rounded to 16
   int32_t ts;                  // table size S*S*Sz
+  int32_t ldb;                 // LDS row stride of the staged source tile (>= 4 k4p)
+  int32_t k4p;                 // K steps per lane group (ceil(nc/4) rounded to the vector width)
+  int32_t tab_off;             // offset of the source tile in an LDS buffer (elements)
+  int32_t buf_elems;           // elements of one LDS buffer (two buffers)
+  int32_t nt;                  // targets per tile (16 x column tiles of the workgroup)
+  int32_t nrg;                 // row groups: wavefront w owns row group w % nrg, column group w / nrg
 };
 
 struct DirectArgs {
@@ -98,7 +111,12 @@ struct DirectArgs {
 int launch_tables(const TableArgs& a, bool cplx, hipStream_t s);
 int launch_p2m(const P2MArgs& a, int p, int dtype, hipStream_t s);
 int launch_l2p(const L2PArgs& a, int p, int dtype, hipStream_t s);
-int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int waves, hipStream_t s);
+int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int col_tiles, int pf_class, int nbuf, int waves,
+               hipStream_t s);
+void m2l_shape(M2LArgs& a, size_t real_bytes, bool cplx, int ct_total);
+size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf);
+int m2l_prefetch_class(const M2LArgs& a, bool cplx, int ct_total, int waves);
+bool m2l_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
 int launch_direct(const DirectArgs& a, int dtype, hipStream_t s);
 int launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s);

@@ -55,125 +55,244 @@ struct MF<float> {
   static __device__ inline int row(int kq, int v) { return 4 * kq + v; }
 };
 
-// RT: row tiles per wavefront (1 or 2).
-template <typename R, bool CPLX, int RT>
-__global__ __launch_bounds__(1024) void m2l_kernel(M2LArgs a) {
+// One workgroup owns a tile of NT targets and a contiguous range of its entries (offset
+// groups).  Wavefront w owns the RT x CT output tiles (16 x 16 each) of row group w % nrg and
+// column group w / nrg.  For every entry the derivative grid (planar re/im, [CW][ts]) and the NT source
+// multipoles ([CW][NT][ldb]) are staged in LDS, double buffered: the global loads of entry e+1
+// are issued into registers before the products of entry e and written to the other buffer
+// after them, one barrier per entry.
+//
+// K ordering: lane group kq (lanes 16 kq .. 16 kq + 15) takes the contiguous range
+// q = kq K4p + ks, ks < K4p (K4p = ceil(Nc/4) rounded up to the vector width), so its B values
+// are read from LDS as 128-bit vectors and the table base of q advances incrementally along
+// the kept order (m_z, m_x, m_y).  B rows are zero beyond Nc, which makes the padded K steps
+// add nothing; padded rows (i >= Nc) read a valid table entry and are never stored.
+template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
+__global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
   using V = typename MF<R>::V;
   constexpr int CW = CPLX ? 2 : 1;
+  const int NT = a.nt;  // 16 x column tiles of the workgroup
+  constexpr int VW = 16 / sizeof(R);  // K steps per 128-bit B read
+  constexpr bool ACC64 = sizeof(R) == 4;
+  typedef R RV __attribute__((ext_vector_type(VW)));
   extern __shared__ __align__(16) char smem_raw[];
-  R* tre = reinterpret_cast<R*>(smem_raw);
-  R* tim = tre + a.ts;  // used when CPLX
-  int* sb = reinterpret_cast<int*>(tre + (int64_t)a.ts * CW);
+  const int ts = a.ts, nc = a.nc, ncp = a.nc_pad, ldb = a.ldb, k4p = a.k4p;
+  const int n_tv = CW * ts;
+  const int buf_elems = a.buf_elems;  // CW ts rounded up to 4, + CW NT ldb
+  R* buf0 = reinterpret_cast<R*>(smem_raw);
+  int* sbq = reinterpret_cast<int*>(buf0 + (DB ? 2 : 1) * buf_elems);  // [4 k4p] table base of q
   __shared__ int s_last;
 
   const M2LItem it = a.items[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
-  const int nc = a.nc, ncp = a.nc_pad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nthr = blockDim.x;
   const int rtiles = ncp >> 4;
-  const int col = lane & 15;  // B column / C column / A row within the tile
-  const int kq = lane >> 4;   // k within the 4-deep MFMA step
-  for (int k = tid; k < nc; k += blockDim.x) sb[k] = a.jbase[k];
+  // wavefront -> (row group, column group): row tiles rg RT + r, column tiles cg CT + c
+  const int rg = wave % a.nrg, cg = wave / a.nrg;
+  const int col = lane & 15;
+  const int kq = lane >> 4;
+  const int tab_off = a.tab_off;  // start of the source tile within a buffer
+  const int ncw = nc * CW;
 
-  double acc[RT][CW][4];
-#pragma unroll
-  for (int r = 0; r < RT; ++r)
-#pragma unroll
-    for (int u = 0; u < CW; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[r][u][v] = 0.0;
+  // zero both buffers' source tiles once: rows are written only for q < Nc afterwards
+  for (int k = tid; k < CW * NT * ldb; k += nthr) {
+    buf0[tab_off + k] = R(0);
+    if constexpr (DB) buf0[buf_elems + tab_off + k] = R(0);
+  }
+  for (int k = tid; k < 4 * k4p; k += nthr) sbq[k] = k < nc ? a.jbase[k] : 0;
 
   const R* mp = reinterpret_cast<const R*>(a.mpole);
   const R* tabg = reinterpret_cast<const R*>(a.tab);
-  const int k4 = (nc + 3) >> 2;
+
+  // register prefetch: table elements tid + k nthr; source column js, values rs + k tps
+  R pft[PT], pfb[PB];
+  const int tps = nthr / NT;
+  const int js = tid / tps, rs = tid - js * tps;
+  const int us = CPLX ? (rs & 1) : 0;
+  const int qs = CPLX ? (rs >> 1) : rs;
+  const int qstep = CPLX ? (tps >> 1) : tps;
+  const int bdst_off = tab_off + (us * NT + js) * ldb + qs;
+  auto issue = [&](int e) {
+    const R* gt = tabg + (int64_t)a.entry_tab[e] * n_tv;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int f = tid + k * nthr;
+      if (f < n_tv) pft[k] = gt[f];
+    }
+    const int src = a.entry_src[(int64_t)e * NT + js];
+    const R* gb = mp + (int64_t)(src < 0 ? 0 : src) * ncw + rs;
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      if (rs + k * tps < ncw) pfb[k] = src >= 0 ? gb[k * tps] : R(0);
+    }
+  };
+  auto commit = [&](R* bufp) {
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int f = tid + k * nthr;
+      if (f < n_tv) bufp[f] = pft[k];
+    }
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      if (rs + k * tps < ncw) bufp[bdst_off + k * qstep] = pfb[k];
+    }
+  };
+
+  V part[RT][CT][CW];
+  double acc[RT][CT][CW][4];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int u = 0; u < CW; ++u) {
+        part[r][c][u] = V{};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[r][c][u][v] = 0.0;
+      }
+  // table base of this lane's A rows (padded rows use row 0, results discarded)
+  int ib[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int i = (rg * RT + r) * 16 + col;
+    ib[r] = (i < nc) ? a.jbase[i] : 0;
+  }
+  const int q0 = kq * k4p;
+
+  if (it.e0 < it.e1) issue(it.e0);
+  __syncthreads();  // zero fill done
+  if (it.e0 < it.e1) commit(buf0);
+  __syncthreads();
 
   for (int e = it.e0; e < it.e1; ++e) {
-    __syncthreads();
-    const int tabid = a.entry_tab[e];
-    const R* src_tab = tabg + (int64_t)tabid * a.ts * CW;
-    for (int k = tid; k < a.ts * CW; k += blockDim.x) tre[k] = src_tab[k];
-    __syncthreads();
-    const int src = a.entry_src[e * 16 + col];
-    const R* bsrc = mp + (int64_t)(src < 0 ? 0 : src) * nc * CW;
-    int ib[RT];
+    R* cur = DB ? buf0 + ((e - it.e0) & 1) * buf_elems : buf0;
+    R* nxt = DB ? buf0 + (((e - it.e0) & 1) ^ 1) * buf_elems : buf0;
+    if (e + 1 < it.e1) issue(e + 1);
+    const R* brow[CT][CW];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      const int i = (wave + r * W) * 16 + col;
-      ib[r] = (i < nc) ? sb[i] : -1;
-    }
-    V part[RT][CW];
+    for (int c = 0; c < CT; ++c)
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
+      for (int u = 0; u < CW; ++u) brow[c][u] = cur + tab_off + (u * NT + (cg * CT + c) * 16 + col) * ldb + q0;
+    // software pipeline: the B vectors and table offsets of step ks + VW load while the
+    // products of step ks run
+    typedef int IV __attribute__((ext_vector_type(VW)));
+    const int* qrow = sbq + q0;
+    RV bc[CT][CW], bn[CT][CW];
+    IV qc = *reinterpret_cast<const IV*>(qrow), qn;
 #pragma unroll
-      for (int u = 0; u < CW; ++u) part[r][u] = V{};
-    for (int ks = 0; ks < k4; ++ks) {
-      const int q = ks * 4 + kq;
-      const bool qok = q < nc;
-      const int qb = qok ? sb[q] : 0;
-      R br = R(0), bi = R(0);
-      if (qok && src >= 0) {
-        br = bsrc[q * CW];
-        if constexpr (CPLX) bi = bsrc[q * CW + 1];
-      }
+    for (int c = 0; c < CT; ++c)
 #pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        if (wave + r * W >= rtiles) continue;
-        const bool ok = qok && ib[r] >= 0;
-        const R ar = ok ? tre[ib[r] + qb] : R(0);
-        if constexpr (CPLX) {
-          const R ai = ok ? tim[ib[r] + qb] : R(0);
-          part[r][0] = MF<R>::mma(ar, br, part[r][0]);
-          part[r][0] = MF<R>::mma(-ai, bi, part[r][0]);
-          part[r][1] = MF<R>::mma(ar, bi, part[r][1]);
-          part[r][1] = MF<R>::mma(ai, br, part[r][1]);
-        } else {
-          part[r][0] = MF<R>::mma(ar, br, part[r][0]);
+      for (int u = 0; u < CW; ++u) bc[c][u] = *reinterpret_cast<const RV*>(brow[c][u]);
+    for (int ks = 0; ks < k4p; ks += VW) {
+      R ar[VW][RT], ai[VW][RT];
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          ar[v][r] = cur[ib[r] + qc[v]];
+          if constexpr (CPLX) ai[v][r] = cur[ts + ib[r] + qc[v]];
         }
+      const bool more = ks + VW < k4p;
+      if (more) {
+        qn = *reinterpret_cast<const IV*>(qrow + ks + VW);
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) bn[c][u] = *reinterpret_cast<const RV*>(brow[c][u] + ks + VW);
+      }
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          if (RT > 1 && rg * RT + r >= rtiles) continue;
+          if constexpr (CPLX) {
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+              part[r][c][0] = MF<R>::mma(ar[v][r], bc[c][0][v], part[r][c][0]);
+              part[r][c][0] = MF<R>::mma(-ai[v][r], bc[c][1][v], part[r][c][0]);
+              part[r][c][1] = MF<R>::mma(ar[v][r], bc[c][1][v], part[r][c][1]);
+              part[r][c][1] = MF<R>::mma(ai[v][r], bc[c][0][v], part[r][c][1]);
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < CT; ++c) part[r][c][0] = MF<R>::mma(ar[v][r], bc[c][0][v], part[r][c][0]);
+          }
+        }
+      if (more) {
+        qc = qn;
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) bc[c][u] = bn[c][u];
       }
     }
+    if constexpr (ACC64) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[r][c][u][v] += (double)part[r][c][u][v];
+            part[r][c][u] = V{};
+          }
+    }
+    if constexpr (!DB) __syncthreads();  // single buffer: everyone is done reading it
+    if (e + 1 < it.e1) commit(nxt);
+    __syncthreads();
+  }
+  if constexpr (!ACC64) {
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
-      for (int u = 0; u < CW; ++u)
+      for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[r][u][v] += (double)part[r][u][v];
+        for (int u = 0; u < CW; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[r][c][u][v] = (double)part[r][c][u][v];
   }
 
-  // result rows of this lane: MF<R>::row(kq, v), column col
+  // result rows of this lane: MF<R>::row(kq, v), column (cg CT + c) 16 + col
   const int nparts = a.tile_nparts[it.tile];
-  const int* tg = a.tile_tgt + it.tile * 16;
+  const int* tg = a.tile_tgt + (int64_t)it.tile * NT;
   if (nparts == 1) {
-    const int t = tg[col];
-    if (t >= 0) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int t = tg[(cg * CT + c) * 16 + col];
+      if (t < 0) continue;
       R* out = reinterpret_cast<R*>(a.local) + (int64_t)t * nc * CW;
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        const int rt = wave + r * W;
+        const int rt = rg * RT + r;
         if (rt >= rtiles) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = rt * 16 + MF<R>::row(kq, v);
           if (i < nc) {
 #pragma unroll
-            for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((double)out[i * CW + u] + acc[r][u][v]);
+            for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((double)out[i * CW + u] + acc[r][c][u][v]);
           }
         }
       }
     }
     return;
   }
-  // split tile: FP64 partial to scratch, last workgroup reduces in part order
-  double* mine = a.scratch + (int64_t)blockIdx.x * 16 * ncp * CW;
+  // split tile: FP64 partial to scratch, the last workgroup of the tile adds all parts in order
+  double* mine = a.scratch + (int64_t)blockIdx.x * NT * ncp * CW;
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const int rt = wave + r * W;
-    if (rt >= rtiles) continue;
+  for (int c = 0; c < CT; ++c)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = rt * 16 + MF<R>::row(kq, v);
+    for (int r = 0; r < RT; ++r) {
+      const int rt = rg * RT + r;
+      if (rt >= rtiles) continue;
 #pragma unroll
-      for (int u = 0; u < CW; ++u) mine[(col * ncp + i) * CW + u] = acc[r][u][v];
+      for (int v = 0; v < 4; ++v) {
+        const int i = rt * 16 + MF<R>::row(kq, v);
+#pragma unroll
+        for (int u = 0; u < CW; ++u) mine[(((cg * CT + c) * 16 + col) * ncp + i) * CW + u] = acc[r][c][u][v];
+      }
     }
-  }
   __threadfence();
   __syncthreads();
   if (tid == 0) {
@@ -184,13 +303,13 @@ __global__ __launch_bounds__(1024) void m2l_kernel(M2LArgs a) {
   if (!s_last) return;
   __threadfence();
   const int item0 = a.tile_item0[it.tile];
-  for (int k = tid; k < 16 * nc; k += blockDim.x) {
-    const int c = k / nc, i = k % nc;
+  for (int k = tid; k < NT * nc; k += nthr) {
+    const int c = k / nc, i = k - c * nc;
     const int t = tg[c];
     if (t < 0) continue;
     double sr = 0.0, si = 0.0;
     for (int pt = 0; pt < nparts; ++pt) {
-      const double* ps = a.scratch + (int64_t)(item0 + pt) * 16 * ncp * CW;
+      const double* ps = a.scratch + (int64_t)(item0 + pt) * NT * ncp * CW;
       sr += ps[(c * ncp + i) * CW];
       if constexpr (CPLX) si += ps[(c * ncp + i) * CW + 1];
     }
@@ -201,19 +320,49 @@ __global__ __launch_bounds__(1024) void m2l_kernel(M2LArgs a) {
   if (tid == 0) atomicExch(a.counter + it.tile, 0);
 }
 
-template <typename R, bool CPLX>
-int launch_typed(const M2LArgs& a, int rt, int waves, hipStream_t s) {
-  const size_t lds = (size_t)a.ts * sizeof(R) * (CPLX ? 2 : 1) + (size_t)a.nc * sizeof(int);
-  dim3 g((unsigned)a.n_items), t((unsigned)(waves * 64));
-  if (rt == 1)
-    hipLaunchKernelGGL((m2l_kernel<R, CPLX, 1>), g, t, lds, s, a);
-  else if (rt == 2)
-    hipLaunchKernelGGL((m2l_kernel<R, CPLX, 2>), g, t, lds, s, a);
-  else
-    return fail(FMM_EUNSUPPORTED, "rows per wave must be 1 or 2");
+template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
+int launch_cfg(const M2LArgs& a, int waves, hipStream_t s) {
+  const size_t lds = m2l_lds_bytes(a, sizeof(R), DB ? 2 : 1);
+  auto kern = m2l_kernel<R, CPLX, RT, CT, PT, PB, DB>;
+  if (lds > 65536) {
+    static size_t granted = 0;  // per instantiation
+    if (lds > granted) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FMM_EUNSUPPORTED, "M2L needs " + std::to_string(lds) +
+                                          " bytes of LDS per workgroup: " + hipGetErrorString(e));
+      }
+      granted = lds;
+    }
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.n_items), dim3((unsigned)(waves * 64)), lds, s, a);
   FMM_HIP_CHECK(hipGetLastError());
   return FMM_OK;
 }
+
+template <typename R, bool CPLX, int RT, int CT, bool DB>
+int launch_pf(const M2LArgs& a, int pf_class, int waves, hipStream_t s) {
+  if (pf_class == 0) return launch_cfg<R, CPLX, RT, CT, kPrefT0, kPrefB0, DB>(a, waves, s);
+  if (pf_class == 1) return launch_cfg<R, CPLX, RT, CT, kPrefT1, kPrefB1, DB>(a, waves, s);
+  return launch_cfg<R, CPLX, RT, CT, kPrefT2, kPrefB2, DB>(a, waves, s);
+}
+
+// Instantiated per-wavefront tile shapes (row tiles RT x column tiles CT).
+#define FMM_M2L_SHAPES(X) X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1) X(5, 1)
+
+template <typename R, bool CPLX>
+int launch_typed(const M2LArgs& a, int rt, int ct, int pf, int nbuf, int waves, hipStream_t s) {
+#define FMM_M2L_CASE(RT_, CT_)                                                        \
+  if (rt == RT_ && ct == CT_)                                                         \
+    return nbuf == 2 ? launch_pf<R, CPLX, RT_, CT_, true>(a, pf, waves, s)            \
+                     : launch_pf<R, CPLX, RT_, CT_, false>(a, pf, waves, s);
+  FMM_M2L_SHAPES(FMM_M2L_CASE)
+#undef FMM_M2L_CASE
+  return fail(FMM_EUNSUPPORTED, "M2L tile shape (rows per wave, column tiles) not instantiated");
+}
+
 
 __global__ void convert_f32_kernel(const double* src, float* dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -236,13 +385,54 @@ __global__ void m2l_table_layout_kernel(const double* src, R* dst, int64_t n, in
 
 }  // namespace
 
-int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int waves, hipStream_t s) {
+bool m2l_shape_instantiated(int rt, int ct) {
+#define FMM_M2L_CASE(RT_, CT_) \
+  if (rt == RT_ && ct == CT_) return true;
+  FMM_M2L_SHAPES(FMM_M2L_CASE)
+#undef FMM_M2L_CASE
+  return false;
+}
+
+void m2l_shape(M2LArgs& a, size_t real_bytes, bool cplx, int ct_total) {
+  const int cw = cplx ? 2 : 1;
+  const int vw = (int)(16 / real_bytes);
+  const int k4 = (a.nc + 3) / 4;
+  a.k4p = (k4 + vw - 1) / vw * vw;
+  // row stride: >= 4 k4p, and an odd number of 16-byte units so that the 16 columns of a
+  // 128-bit read fall in distinct bank groups
+  const int per16 = vw;  // elements per 16 bytes
+  int units = (4 * a.k4p + per16 - 1) / per16;
+  if ((units & 1) == 0) ++units;
+  a.ldb = units * per16;
+  a.tab_off = (cw * a.ts + 3) / 4 * 4;
+  a.buf_elems = a.tab_off + cw * 16 * ct_total * a.ldb;
+  a.nt = 16 * ct_total;
+}
+
+size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf) {
+  return (size_t)nbuf * a.buf_elems * real_bytes + 4 * (size_t)a.k4p * sizeof(int);
+}
+
+int m2l_prefetch_class(const M2LArgs& a, bool cplx, int ct_total, int waves) {
+  const int cw = cplx ? 2 : 1, nthr = waves * 64, nt = 16 * ct_total;
+  if (nthr % nt) return -1;
+  const int tps = nthr / nt;
+  if (cplx && (tps & 1)) return -1;
+  const int kt = (cw * a.ts + nthr - 1) / nthr, kb = (a.nc * cw + tps - 1) / tps;
+  if (kt <= kPrefT0 && kb <= kPrefB0) return 0;
+  if (kt <= kPrefT1 && kb <= kPrefB1) return 1;
+  if (kt <= kPrefT2 && kb <= kPrefB2) return 2;
+  return -1;
+}
+
+int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int col_tiles, int pf_class, int nbuf, int waves,
+               hipStream_t s) {
   if (a.n_items == 0) return FMM_OK;
   switch (dtype) {
-    case FMM_F64: return launch_typed<double, false>(a, rows_per_wave, waves, s);
-    case FMM_F32: return launch_typed<float, false>(a, rows_per_wave, waves, s);
-    case FMM_C128: return launch_typed<double, true>(a, rows_per_wave, waves, s);
-    case FMM_C64: return launch_typed<float, true>(a, rows_per_wave, waves, s);
+    case FMM_F64: return launch_typed<double, false>(a, rows_per_wave, col_tiles, pf_class, nbuf, waves, s);
+    case FMM_F32: return launch_typed<float, false>(a, rows_per_wave, col_tiles, pf_class, nbuf, waves, s);
+    case FMM_C128: return launch_typed<double, true>(a, rows_per_wave, col_tiles, pf_class, nbuf, waves, s);
+    case FMM_C64: return launch_typed<float, true>(a, rows_per_wave, col_tiles, pf_class, nbuf, waves, s);
   }
   return fail(FMM_EINVAL, "dtype");
 }

@@ -7,12 +7,31 @@ the current CUDA (HIP) device; work is enqueued on torch's current stream.
 from __future__ import annotations
 
 import ctypes as C
+import json
+import os
 
 import numpy as np
 import torch
 
 from . import _lib
 from ._lib import check, make_desc
+
+_TUNED = None
+
+
+def tuned_m2l_shape(kernel: str, order: int, dtype: str):
+    """Launch shape chosen by the autotuner for (kernel, p, dtype) on MI355X, or None.
+    The table (m2l_tuned.json) is written by paper_2305_17867_amd.autotune."""
+    global _TUNED
+    if _TUNED is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "m2l_tuned.json")
+        try:
+            with open(path) as fh:
+                _TUNED = json.load(fh)
+        except (OSError, ValueError):
+            _TUNED = {}
+    ent = _TUNED.get(f"{kernel}|p{order}|{dtype}")
+    return dict(ent["tuning"]) if ent else None
 
 REAL = {"f64": torch.float64, "f32": torch.float32, "c128": torch.float64, "c64": torch.float32}
 VALUE = {"f64": torch.float64, "f32": torch.float32, "c128": torch.complex128, "c64": torch.complex64}
@@ -138,17 +157,26 @@ class Plan:
                                   _ptr(local), _ptr(pot), _stream()), "fmm_l2p")
         return pot
 
-    def prepare(self, tgt_box, src_box, box_ijk, box_level) -> "Batch":
-        return Batch(self, tgt_box, src_box, box_ijk, box_level)
+    def prepare(self, tgt_box, src_box, box_ijk, box_level, tuning=None) -> "Batch":
+        """tuning: None (the autotuned shape for this kernel, order and dtype if there is one,
+        else the library's own choice), "library" (the library's choice), or a dict with
+        rows_per_wave, col_tiles_per_wave, col_groups, target_items, lds_buffers
+        (see fmm_m2l_tuning)."""
+        if tuning is None:
+            tuning = tuned_m2l_shape(self.desc.kernel, self.desc.order, self.desc.dtype)
+        elif tuning == "library":
+            tuning = None
+        return Batch(self, tgt_box, src_box, box_ijk, box_level, tuning)
 
 
 class Batch:
     """A prepared M2L batch (host arrays in, device work lists and tables owned)."""
 
     INFO = ("n_pair", "n_tables", "n_tiles", "n_entries", "n_items", "useful_columns",
-            "computed_columns", "nc", "nc_pad", "scratch_bytes")
+            "computed_columns", "nc", "nc_pad", "scratch_bytes", "rows_per_wave", "col_tiles_per_wave",
+            "waves", "col_groups", "lds_bytes", "lds_buffers")
 
-    def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level):
+    def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None):
         self.plan = plan
         t = np.ascontiguousarray(np.asarray(tgt_box, dtype=np.int32))
         s = np.ascontiguousarray(np.asarray(src_box, dtype=np.int32))
@@ -158,10 +186,16 @@ class Batch:
             raise ValueError("pair / box array shapes do not match")
         self.n_box = int(ijk.shape[0])
         self._h = C.c_void_p()
-        check(_lib.load().fmm_m2l_prepare(plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P),
-                                          s.ctypes.data_as(_lib.I32P), self.n_box,
-                                          ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P),
-                                          C.byref(self._h)), "fmm_m2l_prepare")
+        tun = None
+        if tuning is not None:
+            tun = _lib.FmmM2LTuning(int(tuning.get("rows_per_wave", 0)), int(tuning.get("col_tiles_per_wave", 0)),
+                                    int(tuning.get("col_groups", 0)), int(tuning.get("target_items", 0)),
+                                    int(tuning.get("lds_buffers", 0)))
+        check(_lib.load().fmm_m2l_prepare_ex(plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P),
+                                             s.ctypes.data_as(_lib.I32P), self.n_box,
+                                             ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P),
+                                             None if tun is None else C.byref(tun), C.byref(self._h)),
+              "fmm_m2l_prepare_ex")
 
     def info(self) -> dict:
         v = np.zeros(len(self.INFO), dtype=np.int64)
