@@ -189,6 +189,38 @@ int fmm_m2l_batched(fmm_batch batch, const void* mpole, void* local, void* strea
 int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const* mpole,
                           void* const* local, void* stream);
 
+/* ---- Adjoints (real dtypes).  For a loss L with d L / d phi = potential_grad at the targets,
+ * these apply the transposes of L2P, M2L and P2M in the scaled coefficient convention above,
+ * so that a backward pass  L2P^T -> M2L^T -> P2M^T  gives d L / d (weights, source positions,
+ * target positions) of the discrete FMM map.  Complex dtypes return FMM_EUNSUPPORTED. ---- */
+
+/* Transpose of fmm_l2p.  local_grad[b] = M~^T (sum_x g(x) X^i / i!), X = (x - c)/h, over the
+ * targets of box b ([n_box][Nc], OVERWRITTEN); if tgt_xyz_grad is not NULL, also
+ * tgt_xyz_grad[x] += g(x) * grad phi(x) ([n_tgt][3], ACCUMULATED; needs `local`, the forward
+ * local expansions).  g = potential_grad [n_tgt]. */
+int fmm_l2p_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+                    const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local,
+                    const void* potential_grad, void* local_grad, void* tgt_xyz_grad, void* stream);
+
+/* Prepare the transpose of a batched M2L over the same pairs (same arguments as
+ * fmm_m2l_prepare_ex).  Because T~[i, q] = G^(i+q) is symmetric, the transpose applies the same
+ * tables with target and source exchanged. */
+int fmm_m2l_prepare_adjoint(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                            int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
+                            const fmm_m2l_tuning* tuning, fmm_batch* batch);
+
+/* mpole_grad[s] += sum over pairs (t, s) of T~(c_t - c_s) local_grad[t]  ([n_box][Nc],
+ * ACCUMULATED).  batch must come from fmm_m2l_prepare_adjoint. */
+int fmm_m2l_batched_adjoint(fmm_batch batch, const void* local_grad, void* mpole_grad, void* stream);
+
+/* Transpose of fmm_p2m.  With g = M~ mpole_grad[b] (decompression), for every source s of box b:
+ * weight_grad[s] += sum_q g_q X_s^q / q!  and  src_xyz_grad[s] += w_s d/dy_s of that sum,
+ * X_s = (c - y_s)/h.  Either output may be NULL (src_xyz_grad needs `weight`).  Point ranges of
+ * one call must be disjoint. */
+int fmm_p2m_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+                    const int64_t* pt_range, int64_t n_src, const void* src_xyz, const void* weight,
+                    const void* mpole_grad, void* weight_grad, void* src_xyz_grad, void* stream);
+
 /* Direct sum eq. (1): potential[x] = sum_y G(x - y) weight[y], terms with x == y skipped.
  *   src_xyz [n_src][3], tgt_xyz [n_tgt][3] real dtype; weight [n_src] dtype;
  *   potential [n_tgt] dtype, OVERWRITTEN. */

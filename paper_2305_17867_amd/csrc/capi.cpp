@@ -29,6 +29,7 @@ struct fmm_plan_s {
 struct fmm_batch_s {
   fmm_plan plan = nullptr;
   int dtype = 0;
+  bool adjoint = false;  // prepared by fmm_m2l_prepare_adjoint: pairs reversed, original tables
   int nc = 0, nc_pad = 0, ts = 0, waves = 1, rows_per_wave = 1, col_tiles = 1, col_groups = 1;
   int pf_class = 0, nbuf = 2;
   int64_t lds_bytes = 0;
@@ -221,6 +222,7 @@ int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
   a.nc = plan->nc;
   a.c = plan->c;
   a.rec = plan->rec;
+  a.xsign = 1.0;
   return launch_p2m(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
 }
 
@@ -244,7 +246,87 @@ int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
   a.nc = plan->nc;
   a.c = plan->c;
   a.rec = plan->rec;
+  a.xsign = 1.0;
+  a.grad = nullptr;
+  a.gscale = nullptr;
   return launch_l2p(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
+int fmm_l2p_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+                    const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local,
+                    const void* potential_grad, void* local_grad, void* tgt_xyz_grad, void* stream) {
+  int st = check_box_args(plan, n_box, box_center, box_level, pt_range, n_tgt, tgt_xyz, local_grad,
+                          n_tgt ? potential_grad : local_grad);
+  if (st || n_box == 0) return st;
+  FMM_REQUIRE(!dtype_complex(plan->desc.dtype), FMM_EUNSUPPORTED, "adjoints are implemented for real dtypes");
+  FMM_REQUIRE(!tgt_xyz_grad || local, FMM_EINVAL, "target gradients need the local expansions");
+  // d L / d theta~ = M~^T (sum_x g(x) X^i / i!), X = (x - c) / h: target moments, then compression
+  P2MArgs m{};
+  m.n_box = n_box;
+  m.center = box_center;
+  m.level = box_level;
+  m.range = pt_range;
+  m.level_h = plan->d_level_h;
+  m.n_levels = plan->n_levels;
+  m.n_pts = n_tgt;
+  m.xyz = tgt_xyz;
+  m.w = potential_grad;
+  m.out = local_grad;
+  m.nc = plan->nc;
+  m.c = plan->c;
+  m.rec = plan->rec;
+  m.xsign = -1.0;
+  st = launch_p2m(m, plan->p, plan->desc.dtype, (hipStream_t)stream);
+  if (st || !tgt_xyz_grad) return st;
+  // d L / d x = g(x) grad phi(x)
+  L2PArgs e{};
+  e.n_box = n_box;
+  e.center = box_center;
+  e.level = box_level;
+  e.range = pt_range;
+  e.level_h = plan->d_level_h;
+  e.n_levels = plan->n_levels;
+  e.n_pts = n_tgt;
+  e.xyz = tgt_xyz;
+  e.local = local;
+  e.pot = nullptr;
+  e.nc = plan->nc;
+  e.c = plan->c;
+  e.rec = plan->rec;
+  e.xsign = 1.0;
+  e.grad = tgt_xyz_grad;
+  e.gscale = potential_grad;
+  return launch_l2p(e, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
+int fmm_p2m_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+                    const int64_t* pt_range, int64_t n_src, const void* src_xyz, const void* weight,
+                    const void* mpole_grad, void* weight_grad, void* src_xyz_grad, void* stream) {
+  int st = check_box_args(plan, n_box, box_center, box_level, pt_range, n_src, src_xyz, mpole_grad, mpole_grad);
+  if (st || n_box == 0) return st;
+  FMM_REQUIRE(!dtype_complex(plan->desc.dtype), FMM_EUNSUPPORTED, "adjoints are implemented for real dtypes");
+  FMM_REQUIRE(weight_grad || src_xyz_grad, FMM_EINVAL, "nothing to compute: both gradients are NULL");
+  FMM_REQUIRE(!src_xyz_grad || weight, FMM_EINVAL, "source position gradients need the weights");
+  // g = M~ (d L / d beta~); d L / d w_s = sum_q g_q X_s^q / q!, X_s = (c - y_s) / h; d L / d y_s =
+  // w_s d/dy of the same polynomial: a decompress-and-evaluate at the sources
+  L2PArgs e{};
+  e.n_box = n_box;
+  e.center = box_center;
+  e.level = box_level;
+  e.range = pt_range;
+  e.level_h = plan->d_level_h;
+  e.n_levels = plan->n_levels;
+  e.n_pts = n_src;
+  e.xyz = src_xyz;
+  e.local = mpole_grad;
+  e.pot = weight_grad;
+  e.nc = plan->nc;
+  e.c = plan->c;
+  e.rec = plan->rec;
+  e.xsign = -1.0;
+  e.grad = src_xyz_grad;
+  e.gscale = weight;
+  return launch_l2p(e, plan->p, plan->desc.dtype, (hipStream_t)stream);
 }
 
 int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const void* weight, int64_t n_tgt,
@@ -275,9 +357,28 @@ int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const
   return fmm_m2l_prepare_ex(plan, n_pair, tgt_box, src_box, n_box, box_ijk, box_level, nullptr, out);
 }
 
+static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                        int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
+                        const fmm_m2l_tuning* tuning, bool adjoint, fmm_batch* out);
+
 int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
                        int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
                        const fmm_m2l_tuning* tuning, fmm_batch* out) {
+  return prepare_impl(plan, n_pair, tgt_box, src_box, n_box, box_ijk, box_level, tuning, false, out);
+}
+
+int fmm_m2l_prepare_adjoint(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                            int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
+                            const fmm_m2l_tuning* tuning, fmm_batch* out) {
+  FMM_REQUIRE(plan && !dtype_complex(plan->desc.dtype), FMM_EUNSUPPORTED,
+              "adjoints are implemented for real dtypes");
+  // the transpose runs the same translations with the roles of the boxes swapped
+  return prepare_impl(plan, n_pair, src_box, tgt_box, n_box, box_ijk, box_level, tuning, true, out);
+}
+
+static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                        int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
+                        const fmm_m2l_tuning* tuning, bool adjoint, fmm_batch* out) {
   int st = check_plan(plan);
   if (st) return st;
   FMM_REQUIRE(out, FMM_EINVAL, "batch output pointer is NULL");
@@ -300,8 +401,11 @@ int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, co
     const int lt = box_level[t], ls = box_level[s];
     FMM_REQUIRE(lt >= 0 && lt < plan->n_levels, FMM_EINVAL, "box level out of range");
     FMM_REQUIRE(lt == ls, FMM_EINVAL, "pair " + std::to_string(k) + ": boxes on different levels");
-    const int ox = box_ijk[3 * t] - box_ijk[3 * s], oy = box_ijk[3 * t + 1] - box_ijk[3 * s + 1],
-              oz = box_ijk[3 * t + 2] - box_ijk[3 * s + 2];
+    // translation offset of the original pair (target - source); for the adjoint the arrays
+    // hold the pair reversed, and T~ of the original offset is applied (T~ is symmetric)
+    const int sg = adjoint ? -1 : 1;
+    const int ox = sg * (box_ijk[3 * t] - box_ijk[3 * s]), oy = sg * (box_ijk[3 * t + 1] - box_ijk[3 * s + 1]),
+              oz = sg * (box_ijk[3 * t + 2] - box_ijk[3 * s + 2]);
     FMM_REQUIRE(std::abs(ox) <= 8 && std::abs(oy) <= 8 && std::abs(oz) <= 8, FMM_EINVAL,
                 "pair " + std::to_string(k) + ": |offset| > 8");
     FMM_REQUIRE(ox || oy || oz, FMM_EINVAL, "pair " + std::to_string(k) + ": zero offset");
@@ -317,6 +421,7 @@ int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, co
   auto* b = new fmm_batch_s();
   b->plan = plan;
   b->dtype = dtype;
+  b->adjoint = adjoint;
   b->nc = plan->nc;
   b->nc_pad = (plan->nc + 15) / 16 * 16;
   b->ts = plan->Sz * plan->S * plan->S;
@@ -635,8 +740,21 @@ static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local) {
   return a;
 }
 
+static int m2l_launch(fmm_batch b, const void* in, void* out, void* stream);
+
 int fmm_m2l_batched(fmm_batch b, const void* mpole, void* local, void* stream) {
   FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
+  FMM_REQUIRE(!b->adjoint, FMM_ESTATE, "batch was prepared for the adjoint; use fmm_m2l_batched_adjoint");
+  return m2l_launch(b, mpole, local, stream);
+}
+
+int fmm_m2l_batched_adjoint(fmm_batch b, const void* local_grad, void* mpole_grad, void* stream) {
+  FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
+  FMM_REQUIRE(b->adjoint, FMM_ESTATE, "batch was not prepared with fmm_m2l_prepare_adjoint");
+  return m2l_launch(b, local_grad, mpole_grad, stream);
+}
+
+static int m2l_launch(fmm_batch b, const void* mpole, void* local, void* stream) {
   FMM_REQUIRE(b->plan && b->plan->alive, FMM_ESTATE, "the batch's plan was destroyed");
   if (b->n_items == 0) return FMM_OK;
   FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
@@ -652,6 +770,7 @@ int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const
   for (int k = 0; k < n; ++k) {
     FMM_REQUIRE(batches[k], FMM_EINVAL, "NULL batch");
     FMM_REQUIRE(batches[k]->dtype == batches[0]->dtype, FMM_EINVAL, "batches must share one dtype");
+    FMM_REQUIRE(!batches[k]->adjoint, FMM_ESTATE, "adjoint batch passed to fmm_m2l_batched_multi");
   }
   for (int k = 0; k < n; ++k) {
     int st = fmm_m2l_batched(batches[k], mpole[k], local[k], stream);

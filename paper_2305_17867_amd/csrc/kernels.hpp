@@ -32,6 +32,7 @@ struct P2MArgs {
   int32_t nc;
   int32_t c;
   RecArgs rec;
+  double xsign;             // X = xsign (c - y) / h  (+1: multipole moments; -1: target moments)
 };
 
 struct L2PArgs {
@@ -44,10 +45,13 @@ struct L2PArgs {
   int64_t n_pts;
   const void* xyz;          // [n_pts][3] real
   const void* local;        // [n_box][Nc] dtype
-  void* pot;                // [n_pts] dtype, accumulated
+  void* pot;                // [n_pts] dtype, accumulated (may be null when grad is set)
   int32_t nc;
   int32_t c;
   RecArgs rec;
+  double xsign;             // X = xsign (x - c) / h  (+1: local evaluation; -1: at sources)
+  void* grad;               // [n_pts][3] real, accumulated: gscale(x) * d phi / d x (optional)
+  const void* gscale;       // [n_pts] real per-point factor of grad (null = 1)
 };
 
 struct TableArgs {

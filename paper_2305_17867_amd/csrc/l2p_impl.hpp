@@ -68,12 +68,33 @@ __device__ inline void decompress_lds(double* L, const RecArgs& rec, int c, doub
   }
 }
 
-template <int P, typename R, bool CPLX>
+// Nested Horner evaluation of sum_{|m| <= Q} C[full_index(Q, m)] X^m.
+template <int Q, typename R>
+__device__ inline R horner(const R* C, int W, int u, R X, R Y, R Z) {
+  R pz = R(0);
+#pragma unroll
+  for (int z = Q; z >= 0; --z) {
+    R qx = R(0);
+#pragma unroll
+    for (int x = Q - z; x >= 0; --x) {
+      R ry = R(0);
+#pragma unroll
+      for (int y = Q - z - x; y >= 0; --y) ry = ry * Y + C[full_index(Q, x, y, z) * W + u];
+      qx = qx * X + ry;
+    }
+    pz = pz * Z + qx;
+  }
+  return pz;
+}
+
+template <int P, typename R, bool CPLX, bool GRAD>
 __global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
   constexpr int NP = nfull(P);
+  constexpr int NG = GRAD ? nfull(P - 1) : 0;
   constexpr int W = CPLX ? 2 : 1;
   __shared__ double Ld[NP * W];
   __shared__ R Lc[NP * W];
+  __shared__ R Lg[3][(NG > 0 ? NG : 1) * W];
   const int64_t b = blockIdx.x;
   int lev = a.level[b];
   lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
@@ -83,6 +104,7 @@ __global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
   for (int k = threadIdx.x; k < nc * W; k += blockDim.x) Ld[k] = (double)loc[k];
   __syncthreads();
   decompress_lds<P, CPLX>(Ld, a.rec, a.c, h);
+  constexpr InvFact IF{};
   for (int k = threadIdx.x; k < NP; k += blockDim.x) {
     // recover (x, y, z) of full index k
     int z = 0;
@@ -94,9 +116,20 @@ __global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
       ++x;
     }
     const int y = rem;
-    constexpr InvFact IF{};
     const double f = IF.v[x] * IF.v[y] * IF.v[z];
     for (int u = 0; u < W; ++u) Lc[k * W + u] = (R)(Ld[k * W + u] * f);
+    if constexpr (GRAD) {
+      // d/dX_k of L_m X^m / m!: coefficient of X^(m - e_k) is L_m / (m - e_k)!
+      const int mm[3] = {x, y, z};
+      for (int ax = 0; ax < 3; ++ax) {
+        if (mm[ax] == 0) continue;
+        int d[3] = {x, y, z};
+        d[ax] -= 1;
+        const int g = full_index(P - 1, d[0], d[1], d[2]);
+        const double fg = IF.v[d[0]] * IF.v[d[1]] * IF.v[d[2]];
+        for (int u = 0; u < W; ++u) Lg[ax][g * W + u] = (R)(Ld[k * W + u] * fg);
+      }
+    }
   }
   __syncthreads();
   const double cen[3] = {a.center[3 * b], a.center[3 * b + 1], a.center[3 * b + 2]};
@@ -104,36 +137,22 @@ __global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
   lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
   hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
   const R* xyz = reinterpret_cast<const R*>(a.xyz);
-  const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)(1.0 / h);
+  const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)(a.xsign / h);
   for (int64_t s = lo + threadIdx.x; s < hi; s += blockDim.x) {
     const R X = (xyz[3 * s + 0] - cx) * ih;
     const R Y = (xyz[3 * s + 1] - cy) * ih;
     const R Z = (xyz[3 * s + 2] - cz) * ih;
-    R pr = R(0), pi = R(0);
-#pragma unroll
-    for (int z = P; z >= 0; --z) {
-      R qr = R(0), qi = R(0);
-#pragma unroll
-      for (int x = P - z; x >= 0; --x) {
-        R rr = R(0), ri = R(0);
-#pragma unroll
-        for (int y = P - z - x; y >= 0; --y) {
-          const int k = full_index(P, x, y, z);
-          rr = rr * Y + Lc[k * W];
-          if constexpr (CPLX) ri = ri * Y + Lc[k * W + 1];
-        }
-        qr = qr * X + rr;
-        if constexpr (CPLX) qi = qi * X + ri;
-      }
-      pr = pr * Z + qr;
-      if constexpr (CPLX) pi = pi * Z + qi;
+    if (a.pot) {
+      R* pot = reinterpret_cast<R*>(a.pot);
+      pot[s * W] += horner<P, R>(Lc, W, 0, X, Y, Z);
+      if constexpr (CPLX) pot[2 * s + 1] += horner<P, R>(Lc, W, 1, X, Y, Z);
     }
-    R* pot = reinterpret_cast<R*>(a.pot);
-    if constexpr (CPLX) {
-      pot[2 * s] += pr;
-      pot[2 * s + 1] += pi;
-    } else {
-      pot[s] += pr;
+    if constexpr (GRAD && P > 0 && !CPLX) {
+      const R sc = a.gscale ? reinterpret_cast<const R*>(a.gscale)[s] : R(1);
+      R* g = reinterpret_cast<R*>(a.grad);
+      g[3 * s + 0] += sc * ih * horner<P - 1, R>(Lg[0], 1, 0, X, Y, Z);
+      g[3 * s + 1] += sc * ih * horner<P - 1, R>(Lg[1], 1, 0, X, Y, Z);
+      g[3 * s + 2] += sc * ih * horner<P - 1, R>(Lg[2], 1, 0, X, Y, Z);
     }
   }
 }
@@ -141,11 +160,18 @@ __global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
 template <int P>
 int launch_l2p_p(const L2PArgs& a, int dtype, hipStream_t s) {
   dim3 g((unsigned)a.n_box), t(kThreads);
+  const bool grad = a.grad != nullptr;
   switch (dtype) {
-    case FMM_F64: hipLaunchKernelGGL((l2p_kernel<P, double, false>), g, t, 0, s, a); break;
-    case FMM_F32: hipLaunchKernelGGL((l2p_kernel<P, float, false>), g, t, 0, s, a); break;
-    case FMM_C128: hipLaunchKernelGGL((l2p_kernel<P, double, true>), g, t, 0, s, a); break;
-    case FMM_C64: hipLaunchKernelGGL((l2p_kernel<P, float, true>), g, t, 0, s, a); break;
+    case FMM_F64:
+      if (grad) hipLaunchKernelGGL((l2p_kernel<P, double, false, true>), g, t, 0, s, a);
+      else hipLaunchKernelGGL((l2p_kernel<P, double, false, false>), g, t, 0, s, a);
+      break;
+    case FMM_F32:
+      if (grad) hipLaunchKernelGGL((l2p_kernel<P, float, false, true>), g, t, 0, s, a);
+      else hipLaunchKernelGGL((l2p_kernel<P, float, false, false>), g, t, 0, s, a);
+      break;
+    case FMM_C128: hipLaunchKernelGGL((l2p_kernel<P, double, true, false>), g, t, 0, s, a); break;
+    case FMM_C64: hipLaunchKernelGGL((l2p_kernel<P, float, true, false>), g, t, 0, s, a); break;
     default: return fail(FMM_EINVAL, "dtype");
   }
   FMM_HIP_CHECK(hipGetLastError());

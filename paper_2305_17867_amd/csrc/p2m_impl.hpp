@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
   hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
   constexpr int QMAX = CPLX ? 16 : 32;
   constexpr int NCH = Chunks<P, R, CPLX, QMAX>::N;
-  run_chunks<P, R, CPLX, 0, NCH>(a, lo, hi, cen, 1.0 / h, wave, lane, alpha);
+  run_chunks<P, R, CPLX, 0, NCH>(a, lo, hi, cen, a.xsign / h, wave, lane, alpha);
   __syncthreads();
   compress_lds<P, CPLX>(alpha, a.rec, a.c, h);
   // the kept set is the prefix [0, nc) of the full order

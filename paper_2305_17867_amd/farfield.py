@@ -1,0 +1,107 @@
+"""The far field of a tree pass built from the hot-path operators, with a hand-written adjoint.
+
+For a uniform octree the far field of every target box is the sum over its List-2 source
+boxes at every level >= 2; each box's multipole is formed by P2M straight from its points
+(every box's points are one Morton range at every level) and each level's local expansion is
+evaluated by L2P at that level's boxes.  ``FarField`` sets this up once (plans, prepared M2L
+batches and their transposes) and ``apply`` runs it as a torch.autograd.Function:
+
+    phi = FarField(...).apply(w, src_xyz, tgt_xyz)
+
+whose backward calls only the HIP adjoints (L2P^T, M2L^T, P2M^T) and returns
+d L / d w, d L / d src_xyz and d L / d tgt_xyz for the frozen tree (box membership of the
+points is fixed when FarField is built).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import workloads as W
+
+from . import fmm
+
+
+class FarField:
+    def __init__(self, kernel: str, order: int, dtype: str, src_tree: "W.Tree", tgt_tree: "W.Tree",
+                 param: float = 0.0, levels=None, device="cuda"):
+        assert src_tree.n_levels == tgt_tree.n_levels and np.array_equal(src_tree.ijk, tgt_tree.ijk), \
+            "source and target trees must share the box grid (uniform trees of one depth)"
+        self.desc = fmm.Desc(kernel, order, dtype, param)
+        n_lev = src_tree.n_levels
+        self.levels = list(range(2, n_lev)) if levels is None else list(levels)
+        self.plan = fmm.Plan(self.desc, [src_tree.box_size(l) for l in range(n_lev)])
+        t, s = W.interaction_pairs(src_tree, self.levels)
+        self.n_pair = len(t)
+        self.batch = self.plan.prepare(t, s, src_tree.ijk, src_tree.level)
+        self.batch_t = self.plan.prepare_adjoint(t, s, src_tree.ijk, src_tree.level)
+        self.n_box = src_tree.n_box
+        dev = torch.device(device)
+        i64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int64, device=dev)
+        self.center = torch.as_tensor(src_tree.center, dtype=torch.float64, device=dev)
+        self.level = torch.as_tensor(src_tree.level, dtype=torch.int32, device=dev)
+        self.src_rng = i64(src_tree.pt_range)
+        self.tgt_rng = i64(tgt_tree.pt_range)
+        self.level_boxes = {l: (int(src_tree.level_start[l]), int(src_tree.level_start[l + 1])) for l in self.levels}
+        lo, hi = self.level_boxes[self.levels[0]][0], self.level_boxes[self.levels[-1]][1]
+        self.box_lo, self.box_hi = lo, hi  # boxes with multipoles / locals
+
+    def _sl(self, a):
+        return a[self.box_lo:self.box_hi]
+
+    def forward_raw(self, w, src, tgt):
+        d = self.desc
+        nc = self.plan.nc
+        mpole = torch.zeros((self.n_box, nc), dtype=d.value_dtype, device=w.device)
+        lo, hi = self.box_lo, self.box_hi
+        self.plan.p2m(self._sl(self.center), self._sl(self.level), self._sl(self.src_rng), src, w,
+                      out=mpole[lo:hi])
+        local = torch.zeros_like(mpole)
+        self.batch(mpole, local)
+        pot = torch.zeros(tgt.shape[0], dtype=d.value_dtype, device=w.device)
+        for l in self.levels:
+            a, b = self.level_boxes[l]
+            self.plan.l2p(self.center[a:b], self.level[a:b], self.tgt_rng[a:b], tgt, local[a:b], pot)
+        return pot, mpole, local
+
+    def backward_raw(self, g, w, src, tgt, local, need_w=True, need_src=True, need_tgt=True):
+        local_grad = torch.zeros_like(local)
+        tgt_grad = torch.zeros_like(tgt) if need_tgt else None
+        # L2P^T level by level (point ranges of one call are disjoint): local gradients of the
+        # level's boxes and, when asked, the target-position gradients
+        for l in self.levels:
+            a, b = self.level_boxes[l]
+            self.plan.l2p_adjoint(self.center[a:b], self.level[a:b], self.tgt_rng[a:b], tgt, g,
+                                  local_grad=local_grad[a:b], local=local[a:b] if need_tgt else None,
+                                  tgt_grad=tgt_grad)
+        mpole_grad = torch.zeros_like(local)
+        self.batch_t(local_grad, mpole_grad)
+        w_grad = torch.zeros_like(w) if need_w else None
+        src_grad = torch.zeros_like(src) if need_src else None
+        for l in self.levels:
+            a, b = self.level_boxes[l]
+            self.plan.p2m_adjoint(self.center[a:b], self.level[a:b], self.src_rng[a:b], src, w,
+                                  mpole_grad[a:b], w_grad=w_grad, src_grad=src_grad)
+        return w_grad, src_grad, tgt_grad
+
+    def apply(self, w, src, tgt):
+        return _FarFieldFn.apply(w, src, tgt, self)
+
+
+class _FarFieldFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w, src, tgt, ff: FarField):
+        w, src, tgt = w.detach().contiguous(), src.detach().contiguous(), tgt.detach().contiguous()
+        pot, _, local = ff.forward_raw(w, src, tgt)
+        ctx.ff = ff
+        ctx.save_for_backward(w, src, tgt, local)
+        return pot
+
+    @staticmethod
+    def backward(ctx, g):
+        w, src, tgt, local = ctx.saved_tensors
+        ff = ctx.ff
+        need = ctx.needs_input_grad
+        wg, sg, tg = ff.backward_raw(g.contiguous(), w, src, tgt, local, need_w=need[0], need_src=need[1],
+                                     need_tgt=need[2])
+        return wg, sg, tg, None

@@ -157,6 +157,49 @@ class Plan:
                                   _ptr(local), _ptr(pot), _stream()), "fmm_l2p")
         return pot
 
+    def l2p_adjoint(self, center, level, rng, tgt, pot_grad, local_grad=None, local=None, tgt_grad=None):
+        """local_grad (overwritten) = L2P^T(pot_grad); tgt_grad (accumulated) += pot_grad * grad phi
+        when given (needs the forward local expansions `local`)."""
+        nb = self._boxes(center, level, rng)
+        n = tgt.shape[0]
+        d = self.desc
+        _dev(tgt, d.real_dtype, "tgt_xyz", (n, 3))
+        _dev(pot_grad, d.value_dtype, "potential_grad", (n,))
+        if local_grad is None:
+            local_grad = torch.empty((nb, self.nc), dtype=d.value_dtype, device=tgt.device)
+        _dev(local_grad, d.value_dtype, "local_grad", (nb, self.nc))
+        if tgt_grad is not None:
+            _dev(tgt_grad, d.real_dtype, "tgt_xyz_grad", (n, 3))
+            _dev(local, d.value_dtype, "local", (nb, self.nc))
+        check(_lib.load().fmm_l2p_adjoint(self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(tgt),
+                                          _ptr(local), _ptr(pot_grad), _ptr(local_grad), _ptr(tgt_grad),
+                                          _stream()), "fmm_l2p_adjoint")
+        return local_grad
+
+    def p2m_adjoint(self, center, level, rng, src, w, mpole_grad, w_grad=None, src_grad=None):
+        """w_grad += P2M^T(mpole_grad); src_grad += w * d/dy of it (both accumulated, optional)."""
+        nb = self._boxes(center, level, rng)
+        n = src.shape[0]
+        d = self.desc
+        _dev(src, d.real_dtype, "src_xyz", (n, 3))
+        _dev(w, d.value_dtype, "weight", (n,))
+        _dev(mpole_grad, d.value_dtype, "mpole_grad", (nb, self.nc))
+        if w_grad is not None:
+            _dev(w_grad, d.value_dtype, "weight_grad", (n,))
+        if src_grad is not None:
+            _dev(src_grad, d.real_dtype, "src_xyz_grad", (n, 3))
+        check(_lib.load().fmm_p2m_adjoint(self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(src),
+                                          _ptr(w), _ptr(mpole_grad), _ptr(w_grad), _ptr(src_grad), _stream()),
+              "fmm_p2m_adjoint")
+
+    def prepare_adjoint(self, tgt_box, src_box, box_ijk, box_level, tuning=None) -> "Batch":
+        """Transpose of the M2L over the same pairs (see fmm_m2l_prepare_adjoint)."""
+        if tuning is None:
+            tuning = tuned_m2l_shape(self.desc.kernel, self.desc.order, self.desc.dtype)
+        elif tuning == "library":
+            tuning = None
+        return Batch(self, tgt_box, src_box, box_ijk, box_level, tuning, adjoint=True)
+
     def prepare(self, tgt_box, src_box, box_ijk, box_level, tuning=None) -> "Batch":
         """tuning: None (the autotuned shape for this kernel, order and dtype if there is one,
         else the library's own choice), "library" (the library's choice), or a dict with
@@ -176,8 +219,9 @@ class Batch:
             "computed_columns", "nc", "nc_pad", "scratch_bytes", "rows_per_wave", "col_tiles_per_wave",
             "waves", "col_groups", "lds_bytes", "lds_buffers")
 
-    def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None):
+    def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None, adjoint=False):
         self.plan = plan
+        self.adjoint = adjoint
         t = np.ascontiguousarray(np.asarray(tgt_box, dtype=np.int32))
         s = np.ascontiguousarray(np.asarray(src_box, dtype=np.int32))
         ijk = np.ascontiguousarray(np.asarray(box_ijk, dtype=np.int32))
@@ -191,11 +235,11 @@ class Batch:
             tun = _lib.FmmM2LTuning(int(tuning.get("rows_per_wave", 0)), int(tuning.get("col_tiles_per_wave", 0)),
                                     int(tuning.get("col_groups", 0)), int(tuning.get("target_items", 0)),
                                     int(tuning.get("lds_buffers", 0)))
-        check(_lib.load().fmm_m2l_prepare_ex(plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P),
-                                             s.ctypes.data_as(_lib.I32P), self.n_box,
-                                             ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P),
-                                             None if tun is None else C.byref(tun), C.byref(self._h)),
-              "fmm_m2l_prepare_ex")
+        fn = _lib.load().fmm_m2l_prepare_adjoint if adjoint else _lib.load().fmm_m2l_prepare_ex
+        check(fn(plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P), s.ctypes.data_as(_lib.I32P), self.n_box,
+                 ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P),
+                 None if tun is None else C.byref(tun), C.byref(self._h)),
+              "fmm_m2l_prepare_adjoint" if adjoint else "fmm_m2l_prepare_ex")
 
     def info(self) -> dict:
         v = np.zeros(len(self.INFO), dtype=np.int64)
@@ -204,10 +248,15 @@ class Batch:
         return dict(zip(self.INFO, v.tolist()))
 
     def __call__(self, mpole: torch.Tensor, local: torch.Tensor) -> torch.Tensor:
+        """Forward batch: local += M2L(mpole).  Adjoint batch: mpole_grad (2nd) += M2L^T(local_grad)."""
         d = self.plan.desc
-        _dev(mpole, d.value_dtype, "mpole", (self.n_box, self.plan.nc))
-        _dev(local, d.value_dtype, "local", (self.n_box, self.plan.nc))
-        check(_lib.load().fmm_m2l_batched(self._h, _ptr(mpole), _ptr(local), _stream()), "fmm_m2l_batched")
+        _dev(mpole, d.value_dtype, "input", (self.n_box, self.plan.nc))
+        _dev(local, d.value_dtype, "output", (self.n_box, self.plan.nc))
+        if self.adjoint:
+            check(_lib.load().fmm_m2l_batched_adjoint(self._h, _ptr(mpole), _ptr(local), _stream()),
+                  "fmm_m2l_batched_adjoint")
+        else:
+            check(_lib.load().fmm_m2l_batched(self._h, _ptr(mpole), _ptr(local), _stream()), "fmm_m2l_batched")
         return local
 
     def close(self):

@@ -33,13 +33,20 @@ def oracle_scaled_table(kernel, param, p, o, h):
     return {m: v * h ** sum(m) for m, v in tab.items()}
 
 
-def oracle_m2l_scaled(kernel, param, p, tree_ijk, tree_level, level_h, t, s, beta_s):
+def oracle_m2l_scaled(kernel, param, p, tree_ijk, tree_level, level_h, t, s, beta_s, transpose_of=None):
     """theta~ for every box from scaled multipoles beta_s [n_box, Nc] (oracle kept order),
-    grouped by (level, offset) and applied with the oracle's dense T~ matrices."""
+    grouped by (level, offset) and applied with the oracle's dense T~ matrices.
+
+    transpose_of=(t0, s0): apply T~(ijk_t0 - ijk_s0)^T for each pair instead (t, s given reversed),
+    i.e. the transpose of the M2L over the pairs (t0, s0)."""
     nb, nc = beta_s.shape
     out = np.zeros((nb, nc), dtype=np.result_type(beta_s.dtype, np.complex128 if kernel == "helmholtz"
                                                   else np.float64))
-    off = tree_ijk[t] - tree_ijk[s]
+    if transpose_of is not None:
+        t0, s0 = transpose_of
+        off = tree_ijk[t0] - tree_ijk[s0]
+    else:
+        off = tree_ijk[t] - tree_ijk[s]
     lev = tree_level[t]
     keys = np.concatenate([lev[:, None], off], axis=1)
     uk, inv = np.unique(keys, axis=0, return_inverse=True)
@@ -49,6 +56,8 @@ def oracle_m2l_scaled(kernel, param, p, tree_ijk, tree_level, level_h, t, s, bet
         h = level_h[int(key[0])]
         tab = oracle_scaled_table(kernel, param, p, tuple(int(v) for v in key[1:]), h)
         T = Z.m2l_matrix(kernel, param, p, None, tab)
+        if transpose_of is not None:
+            T = T.T
         contrib = beta_s[s[sel]] @ T.T
         np.add.at(out, t[sel], contrib)
     return out

@@ -1,0 +1,225 @@
+"""GPU adjoints (L2P^T, M2L^T, P2M^T, position gradients, autograd far field) against brute-force
+transposes of the oracle, dot-product identities and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint as A
+from oracle import compressed as Z
+
+from helpers import oracle_m2l_scaled, perm_to_lib, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def tree3():
+    pts = W.uniform_points(2048, 12)
+    return W.uniform_tree(pts, 3)
+
+
+KP = [("laplace", 0.0), ("yukawa", 2.0), ("biharmonic", 0.0)]
+
+
+@pytest.mark.parametrize("kernel,param", KP)
+def test_l2p_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param):
+    fmm = gpu_lib
+    p = 5
+    tr = tree3
+    d = fmm.Desc(kernel, p, "f64", param)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    boxes = tr.boxes_at(3)[:40]
+    n = tr.points.shape[0]
+    g = np.random.Generator(np.random.PCG64(1)).standard_normal(n)
+    theta = np.random.Generator(np.random.PCG64(2)).standard_normal((len(boxes), d.nc))
+    tgt_grad = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    lg = plan.l2p_adjoint(dev(tr.center[boxes], torch.float64), dev(tr.level[boxes], torch.int32),
+                          dev(tr.pt_range[boxes], torch.int64), dev(tr.points, torch.float64),
+                          dev(g, torch.float64), local=dev(theta, torch.float64), tgt_grad=tgt_grad)
+    lg = host(lg)
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    inv = np.argsort(perm)
+    h = lh[3]
+    ref = np.zeros_like(lg)
+    ref_tg = np.zeros((n, 3))
+    eye = np.eye(d.nc)
+    for k, b in enumerate(boxes):
+        lo, hi = tr.pt_range[b]
+        x = tr.points[lo:hi]
+        for j in range(d.nc):  # column j of the Jacobian of phi w.r.t. theta~ (library order)
+            th = Z.unscale_local(kernel, param, p, eye[j][inv], 1.0 / h)
+            ref[k, j] = g[lo:hi] @ Z.l2p(kernel, param, p, tr.center[b], th, x)
+        th = Z.unscale_local(kernel, param, p, theta[k][inv], 1.0 / h)
+        eps = 1e-6
+        for ax in range(3):
+            dx = np.zeros(3)
+            dx[ax] = eps
+            fd = (Z.l2p(kernel, param, p, tr.center[b], th, x + dx) - Z.l2p(kernel, param, p, tr.center[b], th, x - dx)) / (2 * eps)
+            ref_tg[lo:hi, ax] = g[lo:hi] * fd
+    assert rel(lg, ref) < 1e-12
+    sel = np.concatenate([np.arange(*tr.pt_range[b]) for b in boxes])
+    assert rel(host(tgt_grad)[sel], ref_tg[sel]) < 1e-7
+
+
+@pytest.mark.parametrize("kernel,param", KP)
+def test_p2m_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param):
+    fmm = gpu_lib
+    p = 5
+    tr = tree3
+    d = fmm.Desc(kernel, p, "f64", param)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    boxes = tr.boxes_at(3)[:30]
+    n = tr.points.shape[0]
+    w = W.normal_weights(n, 4)
+    mg = np.random.Generator(np.random.PCG64(3)).standard_normal((len(boxes), d.nc))
+    wg = torch.zeros(n, dtype=torch.float64, device="cuda")
+    sg = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    plan.p2m_adjoint(dev(tr.center[boxes], torch.float64), dev(tr.level[boxes], torch.int32),
+                     dev(tr.pt_range[boxes], torch.int64), dev(tr.points, torch.float64), dev(w, torch.float64),
+                     dev(mg, torch.float64), w_grad=wg, src_grad=sg)
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    h = lh[3]
+    ref_w = np.zeros(n)
+    ref_s = np.zeros((n, 3))
+    beta_of = lambda c, y, wy: Z.scale_multipole(kernel, param, p, Z.p2m(kernel, param, p, c, y, wy), 1 / h)[perm]
+    for k, b in enumerate(boxes):
+        lo, hi = tr.pt_range[b]
+        for s_ in range(lo, hi):
+            y = tr.points[s_:s_ + 1]
+            ref_w[s_] = beta_of(tr.center[b], y, np.ones(1)) @ mg[k]
+            eps = 1e-6
+            for ax in range(3):
+                dy = np.zeros((1, 3))
+                dy[0, ax] = eps
+                ref_s[s_, ax] = w[s_] * (beta_of(tr.center[b], y + dy, np.ones(1)) -
+                                         beta_of(tr.center[b], y - dy, np.ones(1))) @ mg[k] / (2 * eps)
+    sel = np.concatenate([np.arange(*tr.pt_range[b]) for b in boxes])
+    assert rel(host(wg)[sel], ref_w[sel]) < 1e-12
+    assert rel(host(sg)[sel], ref_s[sel]) < 1e-7
+
+
+@pytest.mark.parametrize("kernel,param,p", [("laplace", 0.0, 8), ("yukawa", 2.0, 6), ("biharmonic", 0.0, 6)])
+def test_m2l_adjoint_is_the_transpose(gpu_lib, tree3, kernel, param, p):
+    fmm = gpu_lib
+    tr = tree3
+    d = fmm.Desc(kernel, p, "f64", param)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    t, s = W.interaction_pairs(tr, [2, 3])
+    fwd = plan.prepare(t, s, tr.ijk, tr.level)
+    adj = plan.prepare_adjoint(t, s, tr.ijk, tr.level)
+    g = np.random.Generator(np.random.PCG64(5))
+    beta = g.standard_normal((tr.n_box, d.nc))
+    lgrad = g.standard_normal((tr.n_box, d.nc))
+    out = dev(np.zeros((tr.n_box, d.nc)), torch.float64)
+    adj(dev(lgrad, torch.float64), out)
+    loc = dev(np.zeros((tr.n_box, d.nc)), torch.float64)
+    fwd(dev(beta, torch.float64), loc)
+    # dot-product identity <M2L beta, u> = <beta, M2L^T u>
+    lhs = np.sum(host(loc) * lgrad)
+    rhs = np.sum(beta * host(out))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0) * 10
+    # against the oracle's transposed matrices
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    inv = np.argsort(perm)
+    ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, s, t, lgrad[:, inv],
+                            transpose_of=(t, s))
+    assert rel(host(out), ref[:, perm]) < 1e-12
+    # a forward batch is refused by the adjoint launch (and the other way round)
+    with pytest.raises(fmm._lib.FmmError):
+        fmm._lib.check(fmm._lib.load().fmm_m2l_batched_adjoint(fwd._h, None, None, None), "adjoint")
+    with pytest.raises(fmm._lib.FmmError):
+        fmm._lib.check(fmm._lib.load().fmm_m2l_batched(adj._h, None, None, None), "forward")
+
+
+def build_farfield(fmm_mod, p, dtype, seed=0, n=3000, depth=3):
+    from paper_2305_17867_amd.farfield import FarField
+    src = W.uniform_points(n, seed)
+    tgt = W.uniform_points(n, seed + 1)
+    ts = W.uniform_tree(src, depth)
+    tt = W.uniform_tree(tgt, depth)
+    ff = FarField("laplace", p, dtype, ts, tt)
+    w = W.normal_weights(n, seed + 2)
+    c = W.normal_weights(n, seed + 3)
+    return ff, ts, tt, w, c
+
+
+def test_farfield_forward_matches_oracle(gpu_lib):
+    ff, ts, tt, w, c = build_farfield(gpu_lib, 6, "f64", n=1200, depth=3)
+    phi = host(ff.apply(dev(w, torch.float64), dev(ts.points, torch.float64), dev(tt.points, torch.float64)))
+    pairs = W.interaction_pairs(ts, [2, 3])
+    ref = A.far_field("laplace", 0.0, 6, ts, tt, pairs, w, ts.points, tt.points)
+    assert rel(phi, ref) < 1e-12
+    direct = A.far_field_direct("laplace", 0.0, ts, tt, pairs, w, ts.points, tt.points)
+    assert rel(phi, direct) < 1e-3  # truncation error of p = 6
+
+
+def test_farfield_gradients_vs_finite_differences_fp64(gpu_lib):
+    ff, ts, tt, w, c = build_farfield(gpu_lib, 8, "f64")
+    W_ = dev(w, torch.float64).requires_grad_(True)
+    S_ = dev(ts.points, torch.float64).requires_grad_(True)
+    T_ = dev(tt.points, torch.float64).requires_grad_(True)
+    C_ = dev(c, torch.float64)
+    L = (ff.apply(W_, S_, T_) * C_).sum()
+    L.backward()
+    gw, gs, gt = W_.grad.clone(), S_.grad.clone(), T_.grad.clone()
+    g = np.random.Generator(np.random.PCG64(9))
+
+    def loss(w_, s_, t_):
+        with torch.no_grad():
+            return float((ff.apply(w_, s_, t_) * C_).sum())
+
+    # fourth-order central differences, step h = 1e-4: the expansions are polynomials of degree
+    # p in (x - c)/box size, so the second-order stencil's error ~ h^2 (p / box)^2 would exceed 1e-6
+    eps = 1e-4
+    for grad, which in ((gw, 0), (gs, 1), (gt, 2)):
+        for _ in range(2):
+            base = [W_.detach(), S_.detach(), T_.detach()]
+            dirn = torch.as_tensor(g.standard_normal(tuple(base[which].shape)), dtype=torch.float64, device="cuda")
+
+            def at(k):
+                args = list(base)
+                args[which] = (base[which] + k * eps * dirn).contiguous()
+                return loss(*args)
+
+            fd = (-at(2) + 8 * at(1) - 8 * at(-1) + at(-2)) / (12 * eps)
+            an = float((grad * dirn).sum())
+            assert abs(fd - an) <= 1e-6 * abs(an), (which, fd, an)
+    # dot-product identity in the weights (the map is linear in w)
+    v = torch.as_tensor(g.standard_normal(len(w)), dtype=torch.float64, device="cuda")
+    lhs = float((ff.apply(v, S_.detach(), T_.detach()) * C_).sum())
+    assert abs(lhs - float((gw * v).sum())) <= 1e-12 * abs(lhs) * 10
+
+
+def test_farfield_fp32_gradients_agree_with_fp64(gpu_lib):
+    out = {}
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        ff, ts, tt, w, c = build_farfield(gpu_lib, 8, dt)
+        W_ = dev(w, tdt).requires_grad_(True)
+        S_ = dev(ts.points, tdt).requires_grad_(True)
+        T_ = dev(tt.points, tdt).requires_grad_(True)
+        (ff.apply(W_, S_, T_) * dev(c, tdt)).sum().backward()
+        out[dt] = [host(x.grad).astype(np.float64) for x in (W_, S_, T_)]
+    for a, b in zip(out["f32"], out["f64"]):
+        assert rel(a, b) < 2e-5
+
+
+def test_farfield_weight_gradient_vs_direct_sum_gradient(gpu_lib):
+    ff, ts, tt, w, c = build_farfield(gpu_lib, 10, "f64", n=1500, depth=3)
+    W_ = dev(w, torch.float64).requires_grad_(True)
+    (ff.apply(W_, dev(ts.points, torch.float64), dev(tt.points, torch.float64)) * dev(c, torch.float64)).sum().backward()
+    pairs = W.interaction_pairs(ts, [2, 3])
+    # d L / d w_s of the direct far field = far field with the roles of sources and targets swapped
+    ref = A.far_field_direct("laplace", 0.0, tt, ts, pairs[::-1], c, tt.points, ts.points)
+    assert rel(host(W_.grad), ref) < 1e-5
