@@ -171,6 +171,16 @@ int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, co
                        int64_t n_box, const int32_t* box_ijk, const int32_t* box_level,
                        const fmm_m2l_tuning* tuning, fmm_batch* batch);
 
+/* Prepare the FFT form of the batched M2L (eq. convolution_m2l): per table and per source box a
+ * real 3-D DFT of size (2c-1) x (2p+1) x (2p+1) (Hermitian half kept), per target box the sum of
+ * spectral products over its pairs and one inverse DFT; the inputs are rescaled by
+ * tau = max(1, p/4) (Sec. 4.1.1) for accuracy.  fmm_m2l_batched then computes the same result
+ * as the matrix-core path (to the FFT's rounding error, which grows with p).  Real dtypes only
+ * (FMM_EUNSUPPORTED otherwise); same pair arguments as fmm_m2l_prepare.  Allocates the spectra
+ * of all n_box boxes. */
+int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                        int64_t n_box, const int32_t* box_ijk, const int32_t* box_level, fmm_batch* batch);
+
 /* Statistics of a prepared batch, written to info[0 .. n_info-1] ([host]):
  * 0 n_pair, 1 n_tables, 2 n_tiles, 3 n_entries (tile x offset groups), 4 n_items (workgroups
  * of one launch), 5 useful pair-columns, 6 computed pair-columns (incl. padding), 7 Nc,

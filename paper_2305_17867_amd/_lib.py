@@ -63,6 +63,7 @@ SIGNATURES = {
     "fmm_m2l_prepare_adjoint": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P,
                                           C.POINTER(FmmM2LTuning), C.POINTER(P)]),
     "fmm_m2l_batched_adjoint": (C.c_int, [P, P, P, P]),
+    "fmm_m2l_prepare_fft": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P, C.POINTER(P)]),
 }
 
 _LIB = None

@@ -7,6 +7,7 @@
 #include <numeric>
 #include <string>
 #include <unordered_map>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -23,6 +24,7 @@ struct fmm_plan_s {
   RecArgs rec{};
   double* d_level_h = nullptr;
   int32_t* d_jbase = nullptr;
+  int32_t* d_jxyz = nullptr;
   bool alive = true;
 };
 
@@ -30,6 +32,8 @@ struct fmm_batch_s {
   fmm_plan plan = nullptr;
   int dtype = 0;
   bool adjoint = false;  // prepared by fmm_m2l_prepare_adjoint: pairs reversed, original tables
+  bool fft = false;      // prepared by fmm_m2l_prepare_fft
+  FftArgs fa{};          // FFT path: device lists and spectra (owned)
   int nc = 0, nc_pad = 0, ts = 0, waves = 1, rows_per_wave = 1, col_tiles = 1, col_groups = 1;
   int pf_class = 0, nbuf = 2;
   int64_t lds_bytes = 0;
@@ -171,9 +175,13 @@ int fmm_plan_create(const fmm_desc* desc, int32_t n_levels, const double* level_
   pl->n_levels = n_levels;
   pl->h.assign(level_box_size, level_box_size + n_levels);
   pl->rec = make_rec(*desc);
-  std::vector<int32_t> jb(pl->nc);
-  for (int k = 0; k < pl->nc; ++k) jb[k] = (pl->J[k].z * pl->S + pl->J[k].x) * pl->S + pl->J[k].y;
-  if ((st = dev_upload(&pl->d_level_h, pl->h)) || (st = dev_upload(&pl->d_jbase, jb))) {
+  std::vector<int32_t> jb(pl->nc), jx(pl->nc);
+  for (int k = 0; k < pl->nc; ++k) {
+    jb[k] = (pl->J[k].z * pl->S + pl->J[k].x) * pl->S + pl->J[k].y;
+    jx[k] = pl->J[k].x | (pl->J[k].y << 8) | (pl->J[k].z << 16);
+  }
+  if ((st = dev_upload(&pl->d_level_h, pl->h)) || (st = dev_upload(&pl->d_jbase, jb)) ||
+      (st = dev_upload(&pl->d_jxyz, jx))) {
     fmm_plan_destroy(pl);
     return st;
   }
@@ -186,6 +194,7 @@ void fmm_plan_destroy(fmm_plan plan) {
   plan->alive = false;
   dev_free(plan->d_level_h);
   dev_free(plan->d_jbase);
+  dev_free(plan->d_jxyz);
   delete plan;
 }
 
@@ -688,8 +697,151 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   return FMM_OK;
 }
 
+int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
+                        int64_t n_box, const int32_t* box_ijk, const int32_t* box_level, fmm_batch* out) {
+  int st = check_plan(plan);
+  if (st) return st;
+  FMM_REQUIRE(out, FMM_EINVAL, "batch output pointer is NULL");
+  *out = nullptr;
+  const int dtype = plan->desc.dtype;
+  FMM_REQUIRE(!dtype_complex(dtype), FMM_EUNSUPPORTED, "the FFT M2L path is implemented for real dtypes");
+  FMM_REQUIRE(n_pair >= 0 && n_box >= 0 && n_box <= (int64_t)0x7fffffff && n_pair <= (int64_t)0x7fffffff,
+              FMM_EINVAL, "bad sizes");
+  FMM_REQUIRE(n_pair == 0 || (tgt_box && src_box && box_ijk && box_level), FMM_EINVAL, "NULL host array");
+  const int S = plan->S, Sz = plan->Sz, Hy = (S + 1) / 2, nh = Sz * S * Hy;
+  FMM_REQUIRE((nh + 255) / 256 <= kFftMaxPerThread, FMM_EUNSUPPORTED, "order too high for the FFT M2L path");
+  int dev = 0, lds_max = 65536;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) lds_max = v;
+  }
+  (void)hipGetLastError();
+  FMM_REQUIRE(fft_lds_bytes(S, Sz, real_size(dtype)) <= (size_t)lds_max, FMM_EUNSUPPORTED,
+              "FFT M2L working set exceeds LDS for this order");
+  // (level, offset) tables and per-target pair lists
+  std::unordered_map<int64_t, int32_t> tab_of_key;
+  std::vector<int64_t> tab_keys;
+  std::vector<std::tuple<int32_t, int32_t, int32_t>> pe(n_pair);  // target, table, source
+  for (int64_t k = 0; k < n_pair; ++k) {
+    const int32_t t = tgt_box[k], s = src_box[k];
+    FMM_REQUIRE(t >= 0 && t < n_box && s >= 0 && s < n_box, FMM_EINVAL, "box id out of range");
+    const int lt = box_level[t];
+    FMM_REQUIRE(lt >= 0 && lt < plan->n_levels && lt == box_level[s], FMM_EINVAL, "bad box levels");
+    const int ox = box_ijk[3 * t] - box_ijk[3 * s], oy = box_ijk[3 * t + 1] - box_ijk[3 * s + 1],
+              oz = box_ijk[3 * t + 2] - box_ijk[3 * s + 2];
+    FMM_REQUIRE(std::abs(ox) <= 8 && std::abs(oy) <= 8 && std::abs(oz) <= 8 && (ox || oy || oz), FMM_EINVAL,
+                "offset zero or larger than 8");
+    const int64_t key = ((int64_t)lt * 17 + (ox + 8)) * 289 + (oy + 8) * 17 + (oz + 8);
+    auto it = tab_of_key.find(key);
+    if (it == tab_of_key.end()) {
+      it = tab_of_key.emplace(key, (int32_t)tab_keys.size()).first;
+      tab_keys.push_back(key);
+    }
+    pe[k] = {t, it->second, s};
+  }
+  std::sort(pe.begin(), pe.end());
+  std::vector<int32_t> tgt_list, tgt_ptr{0}, ent_tab, ent_src, src_list(src_box, src_box + n_pair);
+  for (int64_t k = 0; k < n_pair; ++k) {
+    if (k == 0 || std::get<0>(pe[k]) != std::get<0>(pe[k - 1])) {
+      if (k > 0) tgt_ptr.push_back((int32_t)k);
+      tgt_list.push_back(std::get<0>(pe[k]));
+    }
+    ent_tab.push_back(std::get<1>(pe[k]));
+    ent_src.push_back(std::get<2>(pe[k]));
+  }
+  if (n_pair) tgt_ptr.push_back((int32_t)n_pair);
+  std::sort(src_list.begin(), src_list.end());
+  src_list.erase(std::unique(src_list.begin(), src_list.end()), src_list.end());
+
+  auto* b = new fmm_batch_s();
+  b->plan = plan;
+  b->dtype = dtype;
+  b->fft = true;
+  b->nc = plan->nc;
+  b->n_pair = n_pair;
+  b->n_tab = (int64_t)tab_keys.size();
+  b->n_tiles = (int64_t)tgt_list.size();
+  b->n_entries = n_pair;
+  b->n_items = (int64_t)tgt_list.size();
+  b->useful = b->computed = n_pair;
+  FftArgs& a = b->fa;
+  a.S = S;
+  a.Sz = Sz;
+  a.nc = plan->nc;
+  a.n_tab = b->n_tab;
+  a.n_src = (int64_t)src_list.size();
+  a.n_tgt = (int64_t)tgt_list.size();
+  a.jxyz = plan->d_jxyz;
+  a.tau = std::max(1.0, plan->p / 4.0);
+  std::vector<double> tp(2 * plan->p + 1);
+  for (int k = 0; k <= 2 * plan->p; ++k) tp[k] = std::pow(a.tau, k);
+  std::vector<double> off(3 * b->n_tab), hs(b->n_tab);
+  for (int64_t k = 0; k < b->n_tab; ++k) {
+    const int64_t key = tab_keys[k];
+    off[3 * k] = (int)((key / 289) % 17) - 8;
+    off[3 * k + 1] = (int)((key / 17) % 17) - 8;
+    off[3 * k + 2] = (int)(key % 17) - 8;
+    hs[k] = plan->h[(int)(key / (289 * 17))];
+  }
+  auto bail = [&](int s) {
+    fmm_batch_destroy(b);
+    return s;
+  };
+  double *d_off = nullptr, *d_h = nullptr, *d_tp = nullptr;
+  int32_t *d_sl = nullptr, *d_tl = nullptr, *d_tp2 = nullptr, *d_et = nullptr, *d_es = nullptr;
+  if ((st = dev_upload(&d_tp, tp)) || (st = dev_upload(&d_sl, src_list)) || (st = dev_upload(&d_tl, tgt_list)) ||
+      (st = dev_upload(&d_tp2, tgt_ptr)) || (st = dev_upload(&d_et, ent_tab)) || (st = dev_upload(&d_es, ent_src)))
+    return bail(st);
+  a.taupow = d_tp;
+  a.src_list = d_sl;
+  a.tgt_list = d_tl;
+  a.tgt_ptr = d_tp2;
+  a.ent_tab = d_et;
+  a.ent_src = d_es;
+  const size_t cb = 2 * real_size(dtype);
+  double* d_tab64 = nullptr;
+  if (b->n_tab) {
+    if ((st = dev_upload(&d_off, off)) || (st = dev_upload(&d_h, hs))) {
+      dev_free(d_off);
+      dev_free(d_h);
+      return bail(st);
+    }
+    if (hipMalloc((void**)&d_tab64, (size_t)b->n_tab * Sz * S * S * sizeof(double)) != hipSuccess ||
+        hipMalloc(&a.spec_tab, (size_t)b->n_tab * nh * cb) != hipSuccess) {
+      dev_free(d_off);
+      dev_free(d_h);
+      dev_free(d_tab64);
+      return bail(fail(FMM_ENOMEM, "FFT table allocation failed"));
+    }
+    a.tab64 = d_tab64;
+    st = fmm_deriv_tables(&plan->desc, b->n_tab, d_off, d_h, d_tab64, nullptr);
+    if (!st) st = launch_fft(a, dtype, 0, nullptr);
+    hipError_t e = hipDeviceSynchronize();
+    dev_free(d_off);
+    dev_free(d_h);
+    if (st) return bail(st);
+    if (e != hipSuccess) return bail(fail(FMM_EHIP, std::string("FFT table spectra: ") + hipGetErrorString(e)));
+  }
+  if (n_box && hipMalloc(&a.spec_src, (size_t)n_box * nh * cb) != hipSuccess)
+    return bail(fail(FMM_ENOMEM, "FFT spectra allocation failed"));
+  b->scratch_bytes = (int64_t)n_box * nh * cb;
+  *out = b;
+  return FMM_OK;
+}
+
 void fmm_batch_destroy(fmm_batch b) {
   if (!b) return;
+  if (b->fft) {
+    dev_free((void*)b->fa.tab64);
+    dev_free(b->fa.spec_tab);
+    dev_free(b->fa.spec_src);
+    dev_free((void*)b->fa.src_list);
+    dev_free((void*)b->fa.tgt_list);
+    dev_free((void*)b->fa.tgt_ptr);
+    dev_free((void*)b->fa.ent_tab);
+    dev_free((void*)b->fa.ent_src);
+    dev_free((void*)b->fa.taupow);
+  }
   dev_free(b->d_tab);
   dev_free(b->d_tile_tgt);
   dev_free(b->d_tile_nparts);
@@ -756,6 +908,16 @@ int fmm_m2l_batched_adjoint(fmm_batch b, const void* local_grad, void* mpole_gra
 
 static int m2l_launch(fmm_batch b, const void* mpole, void* local, void* stream) {
   FMM_REQUIRE(b->plan && b->plan->alive, FMM_ESTATE, "the batch's plan was destroyed");
+  if (b->fft) {
+    if (b->n_pair == 0) return FMM_OK;
+    FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
+    FftArgs a = b->fa;
+    a.mpole = mpole;
+    a.local = local;
+    int st = launch_fft(a, b->dtype, 1, (hipStream_t)stream);
+    if (st) return st;
+    return launch_fft(a, b->dtype, 2, (hipStream_t)stream);
+  }
   if (b->n_items == 0) return FMM_OK;
   FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
   return launch_m2l(m2l_args(b, mpole, local), b->dtype, b->rows_per_wave, b->col_tiles, b->pf_class, b->nbuf,
@@ -771,6 +933,7 @@ int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const
     FMM_REQUIRE(batches[k], FMM_EINVAL, "NULL batch");
     FMM_REQUIRE(batches[k]->dtype == batches[0]->dtype, FMM_EINVAL, "batches must share one dtype");
     FMM_REQUIRE(!batches[k]->adjoint, FMM_ESTATE, "adjoint batch passed to fmm_m2l_batched_multi");
+    FMM_REQUIRE(!batches[k]->fft, FMM_EINVAL, "FFT batch passed to fmm_m2l_batched_multi");
   }
   for (int k = 0; k < n; ++k) {
     int st = fmm_m2l_batched(batches[k], mpole[k], local[k], stream);

@@ -102,6 +102,27 @@ struct M2LArgs {
   int32_t nrg;                 // row groups: wavefront w owns row group w % nrg, column group w / nrg
 };
 
+// FFT form of the M2L (eq. convolution_m2l): spectra are Hermitian halves [Sz][S][(S+1)/2].
+constexpr int kFftMaxPerThread = 16;  // frequencies per thread in the accumulation (256 threads)
+
+struct FftArgs {
+  int32_t S, Sz, nc;
+  int64_t n_tab, n_src, n_tgt;
+  const double* tab64;      // [n_tab][Sz][S][S] FP64 scaled derivative grids
+  void* spec_tab;           // [n_tab][nh] complex R
+  void* spec_src;           // [n_box][nh] complex R (rows of listed sources written)
+  const int32_t* src_list;  // [n_src] source boxes
+  const int32_t* tgt_list;  // [n_tgt] target boxes
+  const int32_t* tgt_ptr;   // [n_tgt + 1] CSR into ent_*
+  const int32_t* ent_tab;   // table of each (target, source) pair
+  const int32_t* ent_src;   // source box of each pair
+  const int32_t* jxyz;      // [nc] packed (m_x | m_y << 8 | m_z << 16)
+  const double* taupow;     // [2p + 1] tau^k
+  double tau;
+  const void* mpole;        // [n_box][nc] R
+  void* local;              // [n_box][nc] R, accumulated
+};
+
 struct DirectArgs {
   int64_t n_src, n_tgt;
   const void* src;
@@ -122,6 +143,8 @@ size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf);
 int m2l_prefetch_class(const M2LArgs& a, bool cplx, int ct_total, int waves);
 bool m2l_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
 int launch_direct(const DirectArgs& a, int dtype, hipStream_t s);
+int launch_fft(const FftArgs& a, int dtype, int which, hipStream_t s);  // 0 tables, 1 sources, 2 targets
+size_t fft_lds_bytes(int S, int Sz, size_t real_bytes);
 int launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s);
 

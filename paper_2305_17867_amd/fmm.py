@@ -200,6 +200,10 @@ class Plan:
             tuning = None
         return Batch(self, tgt_box, src_box, box_ijk, box_level, tuning, adjoint=True)
 
+    def prepare_fft(self, tgt_box, src_box, box_ijk, box_level) -> "Batch":
+        """The FFT form of the batched M2L over the same pairs (fmm_m2l_prepare_fft)."""
+        return Batch(self, tgt_box, src_box, box_ijk, box_level, None, fft=True)
+
     def prepare(self, tgt_box, src_box, box_ijk, box_level, tuning=None) -> "Batch":
         """tuning: None (the autotuned shape for this kernel, order and dtype if there is one,
         else the library's own choice), "library" (the library's choice), or a dict with
@@ -219,9 +223,11 @@ class Batch:
             "computed_columns", "nc", "nc_pad", "scratch_bytes", "rows_per_wave", "col_tiles_per_wave",
             "waves", "col_groups", "lds_bytes", "lds_buffers")
 
-    def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None, adjoint=False):
+    def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None, adjoint=False,
+                 fft=False):
         self.plan = plan
         self.adjoint = adjoint
+        self.fft = fft
         t = np.ascontiguousarray(np.asarray(tgt_box, dtype=np.int32))
         s = np.ascontiguousarray(np.asarray(src_box, dtype=np.int32))
         ijk = np.ascontiguousarray(np.asarray(box_ijk, dtype=np.int32))
@@ -235,11 +241,14 @@ class Batch:
             tun = _lib.FmmM2LTuning(int(tuning.get("rows_per_wave", 0)), int(tuning.get("col_tiles_per_wave", 0)),
                                     int(tuning.get("col_groups", 0)), int(tuning.get("target_items", 0)),
                                     int(tuning.get("lds_buffers", 0)))
-        fn = _lib.load().fmm_m2l_prepare_adjoint if adjoint else _lib.load().fmm_m2l_prepare_ex
-        check(fn(plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P), s.ctypes.data_as(_lib.I32P), self.n_box,
-                 ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P),
-                 None if tun is None else C.byref(tun), C.byref(self._h)),
-              "fmm_m2l_prepare_adjoint" if adjoint else "fmm_m2l_prepare_ex")
+        args = (plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P), s.ctypes.data_as(_lib.I32P), self.n_box,
+                ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P))
+        if fft:
+            check(_lib.load().fmm_m2l_prepare_fft(*args, C.byref(self._h)), "fmm_m2l_prepare_fft")
+        else:
+            fn = _lib.load().fmm_m2l_prepare_adjoint if adjoint else _lib.load().fmm_m2l_prepare_ex
+            check(fn(*args, None if tun is None else C.byref(tun), C.byref(self._h)),
+                  "fmm_m2l_prepare_adjoint" if adjoint else "fmm_m2l_prepare_ex")
 
     def info(self) -> dict:
         v = np.zeros(len(self.INFO), dtype=np.int64)
