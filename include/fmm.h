@@ -82,6 +82,7 @@ typedef struct fmm_plan_s* fmm_plan;   /* per (kernel, p, dtype, level sizes): i
                                           recursion tables in device memory */
 typedef struct fmm_batch_s* fmm_batch; /* a prepared M2L batch: derivative tables and
                                           target-tile work lists in device memory */
+typedef struct fmm_multi_s* fmm_multi; /* several batches drained by one persistent launch */
 
 /* ABI version (FMM_ABI_VERSION). */
 int32_t fmm_abi_version(void);
@@ -194,10 +195,22 @@ int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
  * ACCUMULATED.  Deterministic: every output is summed in a fixed order. */
 int fmm_m2l_batched(fmm_batch batch, const void* mpole, void* local, void* stream);
 
-/* Several prepared batches (same dtype; kernels and orders may differ) drained by one
- * persistent launch.  batches, mpole, local: [host] arrays of n pointers. */
+/* Several prepared batches launched one after another on `stream` (same dtype).  batches,
+ * mpole, local: [host] arrays of n pointers.  For a single persistent launch see below. */
 int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const* mpole,
                           void* const* local, void* stream);
+
+/* One persistent launch that drains the work of up to 32 prepared batches (kernels, orders,
+ * levels and interaction lists may differ; the batches must share the dtype and the launch
+ * shape, i.e. be prepared with one fmm_m2l_tuning; each batch at most once).  Work items of all batches are ordered by
+ * decreasing cost and taken round-robin by a grid of at most twice the compute units; the
+ * workgroup has the largest wavefront count of the batches.  Allocates (not capturable). */
+int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* multi);
+
+/* Enqueue the persistent launch: local[k] += M2L_k(mpole[k]) for every batch k.  mpole, local:
+ * [host] arrays of the batches' device coefficient arrays.  Allocates nothing; capturable. */
+int fmm_m2l_multi_launch(fmm_multi multi, const void* const* mpole, void* const* local, void* stream);
+void fmm_m2l_multi_destroy(fmm_multi multi);
 
 /* ---- Adjoints (real dtypes).  For a loss L with d L / d phi = potential_grad at the targets,
  * these apply the transposes of L2P, M2L and P2M in the scaled coefficient convention above,

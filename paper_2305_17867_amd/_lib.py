@@ -64,6 +64,9 @@ SIGNATURES = {
                                           C.POINTER(FmmM2LTuning), C.POINTER(P)]),
     "fmm_m2l_batched_adjoint": (C.c_int, [P, P, P, P]),
     "fmm_m2l_prepare_fft": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P, C.POINTER(P)]),
+    "fmm_m2l_multi_prepare": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),
+    "fmm_m2l_multi_launch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), P]),
+    "fmm_m2l_multi_destroy": (None, [P]),
 }
 
 _LIB = None

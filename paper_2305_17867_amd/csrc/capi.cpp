@@ -28,6 +28,15 @@ struct fmm_plan_s {
   bool alive = true;
 };
 
+struct fmm_multi_s {
+  std::vector<fmm_batch> batches;
+  int dtype = 0, rt = 1, ctw = 1, pf = 0, nbuf = 1, waves = 1, grid = 1;
+  size_t lds = 0;
+  M2LArgs* d_args = nullptr;
+  int2* d_work = nullptr;
+  int32_t n_work = 0;
+};
+
 struct fmm_batch_s {
   fmm_plan plan = nullptr;
   int dtype = 0;
@@ -50,6 +59,7 @@ struct fmm_batch_s {
   int32_t* d_entry_src = nullptr;
   M2LItem* d_items = nullptr;
   int32_t* d_jbase = nullptr;
+  std::vector<M2LItem> h_items;  // host copy (work ordering of persistent launches)
 };
 
 namespace {
@@ -688,6 +698,7 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
       (st = dev_upload(&b->d_entry_tab, entry_tab)) || (st = dev_upload(&b->d_entry_src, entry_src)) ||
       (st = dev_upload(&b->d_items, items)))
     return bail(st);
+  b->h_items = items;
   b->d_jbase = plan->d_jbase;
   if (b->scratch_bytes) {
     if (hipMalloc((void**)&b->d_scratch, b->scratch_bytes) != hipSuccess)
@@ -922,6 +933,106 @@ static int m2l_launch(fmm_batch b, const void* mpole, void* local, void* stream)
   FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
   return launch_m2l(m2l_args(b, mpole, local), b->dtype, b->rows_per_wave, b->col_tiles, b->pf_class, b->nbuf,
                     b->waves, (hipStream_t)stream);
+}
+
+static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local);
+
+int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* out) {
+  FMM_REQUIRE(out, FMM_EINVAL, "output pointer is NULL");
+  *out = nullptr;
+  FMM_REQUIRE(n >= 1 && n <= kM2LMultiMax, FMM_EINVAL, "number of batches must be in [1, 32]");
+  FMM_REQUIRE(batches, FMM_EINVAL, "batches is NULL");
+  const fmm_batch b0 = batches[0];
+  FMM_REQUIRE(b0, FMM_EINVAL, "NULL batch");
+  for (int k = 0; k < n; ++k) {
+    const fmm_batch b = batches[k];
+    FMM_REQUIRE(b && b->plan && b->plan->alive, FMM_EINVAL, "NULL or stale batch");
+    FMM_REQUIRE(!b->fft && !b->adjoint, FMM_EINVAL, "FFT and adjoint batches cannot join a multi launch");
+    FMM_REQUIRE(b->dtype == b0->dtype, FMM_EINVAL, "batches must share one dtype");
+    for (int j = 0; j < k; ++j)  // split tiles keep their partials in the batch's own scratch
+      FMM_REQUIRE(batches[j] != b, FMM_EINVAL, "a batch may appear only once in a multi launch");
+    FMM_REQUIRE(b->rows_per_wave == b0->rows_per_wave && b->col_tiles == b0->col_tiles && b->nbuf == b0->nbuf,
+                FMM_EINVAL, "batches must share rows_per_wave, col_tiles_per_wave and lds_buffers (prepare "
+                            "them with one fmm_m2l_tuning)");
+  }
+  FMM_REQUIRE(m2l_multi_shape_instantiated(b0->rows_per_wave, b0->col_tiles), FMM_EUNSUPPORTED,
+              "launch shape not instantiated for multi-batch launches");
+  auto* m = new fmm_multi_s();
+  m->batches.assign(batches, batches + n);
+  m->dtype = b0->dtype;
+  m->rt = b0->rows_per_wave;
+  m->ctw = b0->col_tiles;
+  m->nbuf = b0->nbuf;
+  std::vector<M2LArgs> args(n);
+  struct W {
+    double cost;
+    int2 w;
+  };
+  std::vector<W> work;
+  for (int k = 0; k < n; ++k) {
+    const fmm_batch b = batches[k];
+    m->waves = std::max(m->waves, b->waves);
+    m->pf = std::max(m->pf, b->pf_class);
+    m->lds = std::max(m->lds, (size_t)b->lds_bytes);
+    args[k] = m2l_args(b, nullptr, nullptr);
+    for (size_t i = 0; i < b->h_items.size(); ++i) {
+      const M2LItem& it = b->h_items[i];
+      const double cost = (double)(it.e1 - it.e0) * b->nc_pad * b->shape.k4p * b->shape.nt;
+      work.push_back({cost, int2{k, (int)i}});
+    }
+  }
+  // the shared workgroup has the largest wave count; every batch's staging must divide evenly
+  for (int k = 0; k < n; ++k) {
+    const fmm_batch b = batches[k];
+    const int nthr = m->waves * 64;
+    if (nthr % b->shape.nt || (dtype_complex(m->dtype) && ((nthr / b->shape.nt) & 1))) {
+      delete m;
+      return fail(FMM_EUNSUPPORTED, "batch tile size does not divide the shared workgroup");
+    }
+  }
+  std::stable_sort(work.begin(), work.end(), [](const W& a, const W& c) { return a.cost > c.cost; });
+  std::vector<int2> wl(work.size());
+  for (size_t i = 0; i < work.size(); ++i) wl[i] = work[i].w;
+  m->n_work = (int32_t)wl.size();
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+  }
+  (void)hipGetLastError();
+  m->grid = std::max(1, std::min<int>(m->n_work, 2 * n_cu));
+  int st;
+  if ((st = dev_upload(&m->d_args, args)) || (st = dev_upload(&m->d_work, wl))) {
+    fmm_m2l_multi_destroy(m);
+    return st;
+  }
+  *out = m;
+  return FMM_OK;
+}
+
+int fmm_m2l_multi_launch(fmm_multi m, const void* const* mpole, void* const* local, void* stream) {
+  FMM_REQUIRE(m, FMM_EINVAL, "multi is NULL");
+  FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL pointer arrays");
+  if (m->n_work == 0) return FMM_OK;
+  M2LMulti a{};
+  a.args = m->d_args;
+  a.work = m->d_work;
+  a.n_work = m->n_work;
+  for (size_t k = 0; k < m->batches.size(); ++k) {
+    FMM_REQUIRE(m->batches[k]->plan && m->batches[k]->plan->alive, FMM_ESTATE, "a batch's plan was destroyed");
+    FMM_REQUIRE(mpole[k] && local[k], FMM_EINVAL, "NULL coefficient array");
+    a.mpole[k] = mpole[k];
+    a.local[k] = local[k];
+  }
+  return launch_m2l_multi(a, m->dtype, m->rt, m->ctw, m->pf, m->nbuf, m->lds, m->waves, m->grid,
+                          (hipStream_t)stream);
+}
+
+void fmm_m2l_multi_destroy(fmm_multi m) {
+  if (!m) return;
+  dev_free(m->d_args);
+  dev_free(m->d_work);
+  delete m;
 }
 
 int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const* mpole, void* const* local,

@@ -123,6 +123,16 @@ struct FftArgs {
   void* local;              // [n_box][nc] R, accumulated
 };
 
+// Persistent launch over several prepared batches (same dtype and launch shape).
+constexpr int kM2LMultiMax = 32;
+struct M2LMulti {
+  const M2LArgs* args;  // [n_batches] device copies (mpole / local pointers replaced below)
+  const int2* work;     // [n_work] (batch, item of the batch)
+  int32_t n_work;
+  const void* mpole[kM2LMultiMax];
+  void* local[kM2LMultiMax];
+};
+
 struct DirectArgs {
   int64_t n_src, n_tgt;
   const void* src;
@@ -145,6 +155,9 @@ bool m2l_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
 int launch_direct(const DirectArgs& a, int dtype, hipStream_t s);
 int launch_fft(const FftArgs& a, int dtype, int which, hipStream_t s);  // 0 tables, 1 sources, 2 targets
 size_t fft_lds_bytes(int S, int Sz, size_t real_bytes);
+int launch_m2l_multi(const M2LMulti& m, int dtype, int rows_per_wave, int col_tiles, int pf_class, int nbuf,
+                     size_t lds, int waves, int grid, hipStream_t s);
+bool m2l_multi_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
 int launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s);
 

@@ -55,6 +55,9 @@ struct MF<float> {
   static __device__ inline int row(int kq, int v) { return 4 * kq + v; }
 };
 
+// Shapes instantiated for the persistent multi-batch launch.
+#define FMM_M2L_MSHAPES(X) X(2, 2) X(3, 2) X(2, 1) X(3, 1)
+
 // One workgroup owns a tile of NT targets and a contiguous range of its entries (offset
 // groups).  Wavefront w owns the RT x CT output tiles (16 x 16 each) of row group w % nrg and
 // column group w / nrg.  For every entry the derivative grid (planar re/im, [CW][ts]) and the NT source
@@ -68,7 +71,7 @@ struct MF<float> {
 // the kept order (m_z, m_x, m_y).  B rows are zero beyond Nc, which makes the padded K steps
 // add nothing; padded rows (i >= Nc) read a valid table entry and are never stored.
 template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
-__global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
+__device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, const int item_id) {
   using V = typename MF<R>::V;
   constexpr int CW = CPLX ? 2 : 1;
   const int NT = a.nt;  // 16 x column tiles of the workgroup
@@ -83,12 +86,14 @@ __global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
   int* sbq = reinterpret_cast<int*>(buf0 + (DB ? 2 : 1) * buf_elems);  // [4 k4p] table base of q
   __shared__ int s_last;
 
-  const M2LItem it = a.items[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nthr = blockDim.x;
   const int rtiles = ncp >> 4;
-  // wavefront -> (row group, column group): row tiles rg RT + r, column tiles cg CT + c
+  // wavefront -> (row group, column group): row tiles rg RT + r, column tiles cg CT + c.
+  // In a launch shared by several batches a workgroup may have more wavefronts than this
+  // batch needs; those only help with the staging.
   const int rg = wave % a.nrg, cg = wave / a.nrg;
+  const bool active = cg * CT * 16 < NT;
   const int col = lane & 15;
   const int kq = lane >> 4;
   const int tab_off = a.tab_off;  // start of the source tile within a buffer
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
       for (int v = 0; v < VW; ++v)
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-          if (RT > 1 && rg * RT + r >= rtiles) continue;
+          if ((RT > 1 && rg * RT + r >= rtiles) || !active) continue;
           if constexpr (CPLX) {
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
@@ -257,6 +262,7 @@ __global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
   const int nparts = a.tile_nparts[it.tile];
   const int* tg = a.tile_tgt + (int64_t)it.tile * NT;
   if (nparts == 1) {
+    if (!active) return;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const int t = tg[(cg * CT + c) * 16 + col];
@@ -279,13 +285,13 @@ __global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
     return;
   }
   // split tile: FP64 partial to scratch, the last workgroup of the tile adds all parts in order
-  double* mine = a.scratch + (int64_t)blockIdx.x * NT * ncp * CW;
+  double* mine = a.scratch + (int64_t)item_id * NT * ncp * CW;
 #pragma unroll
   for (int c = 0; c < CT; ++c)
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
       const int rt = rg * RT + r;
-      if (rt >= rtiles) continue;
+      if (rt >= rtiles || !active) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = rt * 16 + MF<R>::row(kq, v);
@@ -318,6 +324,65 @@ __global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
     if constexpr (CPLX) out[i * CW + 1] = (R)((double)out[i * CW + 1] + si);
   }
   if (tid == 0) atomicExch(a.counter + it.tile, 0);
+}
+
+template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
+__global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
+  m2l_item<R, CPLX, RT, CT, PT, PB, DB>(a, a.items[blockIdx.x], blockIdx.x);
+}
+
+// Persistent launch over the work items of several batches: workgroup g takes items
+// g, g + gridDim.x, ... of the combined list (sorted by decreasing cost on the host); every
+// wavefront reaches the end of the list, so the grid drains.
+template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
+__global__ __launch_bounds__(kM2LMaxThreads) void m2l_multi_kernel(M2LMulti m) {
+  for (int w = blockIdx.x; w < m.n_work; w += gridDim.x) {
+    __syncthreads();
+    const int2 wk = m.work[w];
+    M2LArgs a = m.args[wk.x];
+    a.mpole = m.mpole[wk.x];
+    a.local = m.local[wk.x];
+    m2l_item<R, CPLX, RT, CT, PT, PB, DB>(a, a.items[wk.y], wk.y);
+  }
+}
+
+template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
+int launch_multi_cfg(const M2LMulti& m, size_t lds, int waves, int grid, hipStream_t s) {
+  auto kern = m2l_multi_kernel<R, CPLX, RT, CT, PT, PB, DB>;
+  if (lds > 65536) {
+    static size_t granted = 0;
+    if (lds > granted) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FMM_EUNSUPPORTED, "multi-batch M2L needs too much LDS per workgroup");
+      }
+      granted = lds;
+    }
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((unsigned)(waves * 64)), lds, s, m);
+  FMM_HIP_CHECK(hipGetLastError());
+  return FMM_OK;
+}
+
+template <typename R, bool CPLX, int RT, int CT, bool DB>
+int launch_multi_pf(const M2LMulti& m, int pf, size_t lds, int waves, int grid, hipStream_t s) {
+  if (pf == 0) return launch_multi_cfg<R, CPLX, RT, CT, kPrefT0, kPrefB0, DB>(m, lds, waves, grid, s);
+  if (pf == 1) return launch_multi_cfg<R, CPLX, RT, CT, kPrefT1, kPrefB1, DB>(m, lds, waves, grid, s);
+  return launch_multi_cfg<R, CPLX, RT, CT, kPrefT2, kPrefB2, DB>(m, lds, waves, grid, s);
+}
+
+template <typename R, bool CPLX>
+int launch_multi_typed(const M2LMulti& m, int rt, int ct, int pf, int nbuf, size_t lds, int waves, int grid,
+                       hipStream_t s) {
+#define FMM_M2L_MCASE(RT_, CT_)                                                                   \
+  if (rt == RT_ && ct == CT_)                                                                     \
+    return nbuf == 2 ? launch_multi_pf<R, CPLX, RT_, CT_, true>(m, pf, lds, waves, grid, s)      \
+                     : launch_multi_pf<R, CPLX, RT_, CT_, false>(m, pf, lds, waves, grid, s);
+  FMM_M2L_MSHAPES(FMM_M2L_MCASE)
+#undef FMM_M2L_MCASE
+  return fail(FMM_EUNSUPPORTED, "multi-batch M2L shape not instantiated");
 }
 
 template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
@@ -435,6 +500,26 @@ int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int col_tiles, in
     case FMM_C64: return launch_typed<float, true>(a, rows_per_wave, col_tiles, pf_class, nbuf, waves, s);
   }
   return fail(FMM_EINVAL, "dtype");
+}
+
+int launch_m2l_multi(const M2LMulti& m, int dtype, int rows_per_wave, int col_tiles, int pf_class, int nbuf,
+                     size_t lds, int waves, int grid, hipStream_t s) {
+  if (m.n_work == 0) return FMM_OK;
+  switch (dtype) {
+    case FMM_F64: return launch_multi_typed<double, false>(m, rows_per_wave, col_tiles, pf_class, nbuf, lds, waves, grid, s);
+    case FMM_F32: return launch_multi_typed<float, false>(m, rows_per_wave, col_tiles, pf_class, nbuf, lds, waves, grid, s);
+    case FMM_C128: return launch_multi_typed<double, true>(m, rows_per_wave, col_tiles, pf_class, nbuf, lds, waves, grid, s);
+    case FMM_C64: return launch_multi_typed<float, true>(m, rows_per_wave, col_tiles, pf_class, nbuf, lds, waves, grid, s);
+  }
+  return fail(FMM_EINVAL, "dtype");
+}
+
+bool m2l_multi_shape_instantiated(int rt, int ct) {
+#define FMM_M2L_MCASE(RT_, CT_) \
+  if (rt == RT_ && ct == CT_) return true;
+  FMM_M2L_MSHAPES(FMM_M2L_MCASE)
+#undef FMM_M2L_MCASE
+  return false;
 }
 
 int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s) {

@@ -303,3 +303,36 @@ def direct(desc: Desc, src, w, tgt, out=None) -> torch.Tensor:
     check(_lib.load().fmm_direct(C.byref(desc.c), ns, _ptr(src), _ptr(w), nt, _ptr(tgt), _ptr(out),
                                  _stream()), "fmm_direct")
     return out
+
+
+class Multi:
+    """Several prepared forward batches drained by one persistent launch (fmm_m2l_multi_*).
+    The batches must share the dtype and the launch shape (prepare them with one tuning)."""
+
+    def __init__(self, batches):
+        self.batches = list(batches)
+        n = len(self.batches)
+        hb = (C.c_void_p * n)(*[b._h for b in self.batches])
+        self._h = C.c_void_p()
+        check(_lib.load().fmm_m2l_multi_prepare(n, hb, C.byref(self._h)), "fmm_m2l_multi_prepare")
+
+    def __call__(self, mpoles, locals_):
+        n = len(self.batches)
+        for b, m, l in zip(self.batches, mpoles, locals_):
+            d = b.plan.desc
+            _dev(m, d.value_dtype, "mpole", (b.n_box, b.plan.nc))
+            _dev(l, d.value_dtype, "local", (b.n_box, b.plan.nc))
+        hm = (C.c_void_p * n)(*[m.data_ptr() for m in mpoles])
+        hl = (C.c_void_p * n)(*[l.data_ptr() for l in locals_])
+        check(_lib.load().fmm_m2l_multi_launch(self._h, hm, hl, _stream()), "fmm_m2l_multi_launch")
+
+    def close(self):
+        if self._h:
+            _lib.load().fmm_m2l_multi_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

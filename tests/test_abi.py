@@ -85,6 +85,12 @@ def test_null_arguments_are_rejected_before_any_launch(lib):
     assert L.fmm_batch_info(None, None, 0) == -1
     assert L.fmm_direct(C.byref(d), -1, None, None, 0, None, None, None) == -1
     assert L.fmm_m2l_batched_multi(-1, None, None, None, None) == -1
+    h = C.c_void_p()
+    assert L.fmm_m2l_multi_prepare(0, None, C.byref(h)) == -1 and not h.value
+    assert L.fmm_m2l_multi_prepare(33, None, C.byref(h)) == -1
+    assert L.fmm_m2l_multi_prepare(1, None, None) == -1
+    assert L.fmm_m2l_multi_launch(None, None, None, None) == -1
+    L.fmm_m2l_multi_destroy(None)
     # zero-size work is a no-op that needs no GPU
     assert L.fmm_direct(C.byref(d), 0, None, None, 0, None, None, None) == 0
     assert L.fmm_deriv_tables(C.byref(d), 0, None, None, None, None) == 0
