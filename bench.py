@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6e12, "f32": 157.3e12}  # dense matrix-core peaks, FLOP/s
 DEPTH, NPTS, SEED = 4, 1 << 20, 1
+COPY_BYTES = 256 << 20  # plain copy used to calibrate the FETCH_SIZE / WRITE_SIZE counters
 
 
 def log(*a):
@@ -178,6 +179,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default=None, help="run one variant, e.g. f64:8 (for profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy three times, to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a "
@@ -235,6 +238,13 @@ def main():
                      "algorithmic": f"2*Nc^2 FLOP per pair, Nc={head['nc']}, {len(t)} pairs per launch"},
         "variants": results,
     }
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = COPY_BYTES
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(tr, w, t, s)

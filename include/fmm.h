@@ -155,15 +155,19 @@ void fmm_batch_destroy(fmm_batch batch);
 /* Launch shape of a prepared M2L batch.  A workgroup owns a tile of 16 * col_groups *
  * col_tiles_per_wave target boxes; each of its wavefronts computes rows_per_wave x
  * col_tiles_per_wave output tiles of 16 x 16 coefficients on the matrix cores, and there are
- * ceil(ceil(Nc / 16) / rows_per_wave) * col_groups wavefronts (at most 8).  Tiles are split
- * into parts (partials summed in a fixed order) so that one launch has about target_items
- * workgroups.  Zero fields are chosen automatically. */
+ * ceil(ceil(Nc / 16) / rows_per_wave) * col_groups * k_splits wavefronts (at most 8): with
+ * k_splits > 1 the contraction index of every product is cut into k_splits ranges taken by
+ * different wavefronts, whose FP64 partial sums are added in a fixed order at the end of the
+ * workgroup's work (more wavefronts share one staged offset group).  Tiles are split into parts
+ * (partials summed in a fixed order) so that one launch has about target_items workgroups.
+ * Zero fields are chosen automatically (k_splits 0 means 1 when rows_per_wave is given). */
 typedef struct {
   int32_t rows_per_wave;      /* 1..5 */
   int32_t col_tiles_per_wave; /* 1..2 */
   int32_t col_groups;         /* 1, 2 or 4 */
   int32_t target_items;       /* >= 1 */
   int32_t lds_buffers;        /* 1: stage one offset group at a time; 2: double buffered */
+  int32_t k_splits;           /* 1..4 */
 } fmm_m2l_tuning;
 
 /* fmm_m2l_prepare with an explicit launch shape (tuning may be NULL: automatic).  An
@@ -187,7 +191,7 @@ int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
  * of one launch), 5 useful pair-columns, 6 computed pair-columns (incl. padding), 7 Nc,
  * 8 rows padded to a multiple of 16, 9 scratch bytes, 10 row tiles per wavefront,
  * 11 column tiles per wavefront, 12 wavefronts per workgroup, 13 column groups,
- * 14 LDS bytes per workgroup, 15 LDS buffers. */
+ * 14 LDS bytes per workgroup, 15 LDS buffers, 16 K splits. */
 int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
 
 /* Batched M2L: local[t] += sum over pairs (t, s) of T(c_t - c_s) mpole[s], T[i,q] =

@@ -25,7 +25,8 @@ class FmmDesc(C.Structure):
 
 class FmmM2LTuning(C.Structure):
     _fields_ = [("rows_per_wave", C.c_int32), ("col_tiles_per_wave", C.c_int32),
-                ("col_groups", C.c_int32), ("target_items", C.c_int32), ("lds_buffers", C.c_int32)]
+                ("col_groups", C.c_int32), ("target_items", C.c_int32), ("lds_buffers", C.c_int32),
+                ("k_splits", C.c_int32)]
 
 
 class FmmError(RuntimeError):

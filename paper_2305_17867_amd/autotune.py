@@ -2,7 +2,7 @@
 
 For one (kernel, order, dtype) and one set of interaction pairs it prepares the batch with
 every candidate launch shape (rows per wavefront, column tiles per wavefront, column
-groups, workgroups per launch; see fmm_m2l_tuning in include/fmm.h), times the launches
+groups, K splits, LDS buffers, workgroups per launch; see fmm_m2l_tuning in include/fmm.h), times the launches
 with HIP events on the current stream, and keeps the fastest.  Results are cached in a JSON
 file keyed by device, kernel, order, dtype and problem size, so later runs reuse them.
 """
@@ -19,6 +19,7 @@ from . import fmm
 
 SHAPES = [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (5, 1)]  # (rows, col tiles) per wave
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fmm_m2l_autotune.json")
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "m2l_tuned.json")
 
 
 def candidates(nc: int, n_cu: int, max_waves: int = 8):
@@ -27,13 +28,14 @@ def candidates(nc: int, n_cu: int, max_waves: int = 8):
     for rt, ctw in SHAPES:
         nrg = -(-rtiles // rt)
         for ncg in (1, 2, 4):
-            waves = nrg * ncg
-            if waves > max_waves or ncg * ctw > 4:
-                continue
-            for items in (n_cu, 2 * n_cu):
-                for nbuf in (1, 2):
-                    out.append({"rows_per_wave": rt, "col_tiles_per_wave": ctw, "col_groups": ncg,
-                                "target_items": items, "lds_buffers": nbuf})
+            for nks in (1, 2, 3, 4):
+                waves = nrg * ncg * nks
+                if waves > max_waves or ncg * ctw > 4:
+                    continue
+                for items in (2 * n_cu, 3 * n_cu, 4 * n_cu):
+                    for nbuf in (1, 2):
+                        out.append({"rows_per_wave": rt, "col_tiles_per_wave": ctw, "col_groups": ncg,
+                                    "target_items": items, "lds_buffers": nbuf, "k_splits": nks})
     return out
 
 
@@ -105,3 +107,32 @@ def tune(plan: "fmm.Plan", tgt_box, src_box, box_ijk, box_level, reps: int = 5,
         with open(cache, "w") as f:
             json.dump(db, f, indent=1)
     return out
+
+
+def write_table(path: str = TABLE, cases=((8, "f64"), (8, "f32"), (12, "f64"), (12, "f32")), reps: int = 5,
+                log=print) -> dict:
+    """Tune the Laplace M2L of the uniform workload (2^20 random points in the unit cube,
+    octree depth 4, all List-2 pairs of level 4) for each (order, dtype) and write the launch
+    shape table read by fmm.tuned_m2l_shape()."""
+    import workloads as W
+    pts = W.uniform_points(1 << 20, 1)
+    tr = W.uniform_tree(pts, 4)
+    t, s = W.interaction_pairs(tr, [4])
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    table = {}
+    for p, dt in cases:
+        plan = fmm.Plan(fmm.Desc("laplace", p, dt), lh)
+        r = tune(plan, t, s, tr.ijk, tr.level, reps=reps, cache=None)
+        log(f"laplace p={p} {dt}: {r['ms']:.4f} ms {r['tuning']} ({len(r['results'])} candidates, "
+            f"{r['seconds']:.0f} s)")
+        table[f"laplace|p{p}|{dt}"] = {"tuning": r["tuning"], "ms": round(r["ms"], 4), "pairs": int(len(t)),
+                                       "device": torch.cuda.get_device_name(0), "hip": torch.version.hip,
+                                       "workload": "uniform 2^20 points, depth 4, level-4 List-2 pairs"}
+        plan.close()
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return table
+
+
+if __name__ == "__main__":
+    write_table()

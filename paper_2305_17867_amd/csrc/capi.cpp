@@ -43,10 +43,10 @@ struct fmm_batch_s {
   bool adjoint = false;  // prepared by fmm_m2l_prepare_adjoint: pairs reversed, original tables
   bool fft = false;      // prepared by fmm_m2l_prepare_fft
   FftArgs fa{};          // FFT path: device lists and spectra (owned)
-  int nc = 0, nc_pad = 0, ts = 0, waves = 1, rows_per_wave = 1, col_tiles = 1, col_groups = 1;
+  int nc = 0, nc_pad = 0, ts = 0, waves = 1, rows_per_wave = 1, col_tiles = 1, col_groups = 1, k_splits = 1;
   int pf_class = 0, nbuf = 2;
   int64_t lds_bytes = 0;
-  M2LArgs shape{};  // ldb, k4p, tab_off, buf_elems, nt, nrg
+  M2LArgs shape{};  // ldb, k4p, tab_off, buf_elems, nt, nrg, nks
   int64_t n_pair = 0, n_tab = 0, n_tiles = 0, n_entries = 0, n_items = 0;
   int64_t useful = 0, computed = 0, scratch_bytes = 0;
   void* d_tab = nullptr;
@@ -462,14 +462,14 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     const size_t rb = real_size(dtype);
     const size_t cap = (size_t)lds_max - 64;  // room for the kernel's static LDS
     struct Cand {
-      int rt, ctw, ncg, nrg, waves, pf, nbuf;
+      int rt, ctw, ncg, nrg, waves, pf, nbuf, nks;
       M2LArgs sh;
       size_t lds;
     };
-    auto make = [&](int rt, int ctw, int ncg, int nbuf, Cand& c) {
-      if (rt < 1 || ctw < 1 || ncg < 1 || !m2l_shape_instantiated(rt, ctw)) return false;
+    auto make = [&](int rt, int ctw, int ncg, int nbuf, int nks, Cand& c) {
+      if (rt < 1 || ctw < 1 || ncg < 1 || nks < 1 || nks > 4 || !m2l_shape_instantiated(rt, ctw)) return false;
       const int nrg = (rtiles + rt - 1) / rt;
-      const int waves = nrg * ncg;
+      const int waves = nrg * ncg * nks;
       if (waves > kM2LMaxThreads / 64 || ncg * ctw > 4) return false;
       c.rt = rt;
       c.ctw = ctw;
@@ -481,16 +481,19 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
       c.sh.nc = b->nc;
       m2l_shape(c.sh, rb, cplx, ncg * ctw);
       c.sh.nrg = nrg;
+      c.sh.nks = nks;
+      c.nks = nks;
+      if (nks > c.sh.k4p / (int)(16 / rb)) return false;  // every K range non-empty
       c.pf = m2l_prefetch_class(c.sh, cplx, ncg * ctw, waves);
       c.nbuf = nbuf;
-      c.lds = m2l_lds_bytes(c.sh, rb, nbuf);
+      c.lds = m2l_lds_bytes(c.sh, rb, nbuf, rt, cplx);
       return c.pf >= 0 && c.lds <= cap;
     };
     Cand best{};
     bool found = false;
     if (tuning && tuning->rows_per_wave > 0) {
       found = make(tuning->rows_per_wave, std::max(1, tuning->col_tiles_per_wave), std::max(1, tuning->col_groups),
-                   tuning->lds_buffers == 1 ? 1 : 2, best);
+                   tuning->lds_buffers == 1 ? 1 : 2, std::max(1, tuning->k_splits), best);
       if (!found) {
         delete b;
         return fail(FMM_EUNSUPPORTED, "requested M2L launch shape is not instantiated or does not fit");
@@ -502,9 +505,10 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
       for (int rt = 1; rt <= 5; ++rt)
         for (int ctw = 1; ctw <= 2; ++ctw)
           for (int ncg : {1, 2, 4})
-            for (int nb : {1, 2}) {
+            for (int nb : {1, 2})
+              for (int nks : {1, 2}) {
               Cand c{};
-              if (!make(rt, ctw, ncg, nb, c)) continue;
+              if (!make(rt, ctw, ncg, nb, nks, c)) continue;
               const double pad = (double)(c.nrg * rt) / rtiles;
               const double reads = (double)(rt + ctw) / (rt * ctw);
               const int nt = 16 * ncg * ctw;
@@ -515,8 +519,8 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
               const int waves_simd_reg = std::max(1, 512 / std::max(64, vgpr));
               const int wgs = std::max(1, std::min(wg_lds, (4 * waves_simd_reg) / c.waves));
               const double per_simd = (double)(wgs * c.waves) / 4.0;
-              const double occ = per_simd >= 2.0 ? 1.0 : (per_simd >= 1.0 ? 1.5 : 2.0);
-              const double sync = nb == 1 ? 1.0 : 1.08;
+              const double occ = per_simd >= 3.0 ? 1.0 : per_simd >= 2.0 ? 1.1 : (per_simd >= 1.0 ? 1.5 : 2.0);
+              const double sync = (nb == 1 ? 1.0 : 1.08) * (1.0 + 0.02 * (nks - 1));
               const double score = pad * (0.5 + 0.5 * reads) * fill * occ * sync;
               if (score < best_score) {
                 best_score = score;
@@ -532,6 +536,7 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     b->rows_per_wave = best.rt;
     b->col_tiles = best.ctw;
     b->col_groups = best.ncg;
+    b->k_splits = best.nks;
     b->waves = best.waves;
     b->pf_class = best.pf;
     b->nbuf = best.nbuf;
@@ -630,16 +635,18 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   b->computed = b->n_entries * NT;
 
   // 5. work items: split tiles into parts so that one launch has enough workgroups
-  int target_items = (tuning && tuning->target_items > 0) ? tuning->target_items : 2 * n_cu;
+  int target_items = (tuning && tuning->target_items > 0) ? tuning->target_items : 4 * n_cu;
   target_items = std::max(1, env_int("FMM_M2L_ITEMS", target_items));
   const int min_entries = std::max(1, env_int("FMM_M2L_MIN_ENTRIES", 8));
   std::vector<M2LItem> items;
   std::vector<int32_t> tile_nparts(n_tiles), tile_item0(n_tiles);
   int64_t split_items = 0;
-  const int64_t want_parts = n_tiles ? (target_items + n_tiles - 1) / n_tiles : 1;
+  // parts of about equal cost: every item gets about n_entries / target_items entries (at
+  // least min_entries), so that the workgroups of one launch finish together
+  const double per_item = std::max<double>(min_entries, (double)b->n_entries / target_items);
   for (int64_t t = 0; t < n_tiles; ++t) {
     const int ne = tile_e0[t + 1] - tile_e0[t];
-    int np = (int)std::min<int64_t>(want_parts, std::max(1, ne / min_entries));
+    int np = (int)std::lround(ne / per_item);
     np = std::max(1, std::min(np, ne));
     tile_nparts[t] = np;
     tile_item0[t] = (int32_t)items.size();
@@ -650,6 +657,11 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     if (np > 1) split_items = (int64_t)items.size();
   }
   b->n_items = (int64_t)items.size();
+  // launch order: part-major, so that consecutive workgroups (which the hardware deals out
+  // round-robin over the XCDs) take the same part of different tiles; partial sums keep
+  // their slot tile_item0[tile] + part
+  std::stable_sort(items.begin(), items.end(),
+                   [](const M2LItem& x, const M2LItem& y) { return x.part < y.part; });
   // partials are indexed by item id; allocate for every item up to the last split tile
   b->scratch_bytes = split_items * NT * b->nc_pad * CW * (int64_t)sizeof(double);
 
@@ -871,7 +883,7 @@ int fmm_batch_info(fmm_batch b, int64_t* info, int32_t n_info) {
   const int64_t v[] = {b->n_pair,        b->n_tab,     b->n_tiles, b->n_entries,  b->n_items,
                        b->useful,        b->computed,  b->nc,      b->nc_pad,     b->scratch_bytes,
                        b->rows_per_wave, b->col_tiles, b->waves,   b->col_groups, b->lds_bytes,
-                       b->nbuf};
+                       b->nbuf,          b->k_splits};
   for (int k = 0; k < n_info && k < (int)(sizeof(v) / sizeof(v[0])); ++k) info[k] = v[k];
   return FMM_OK;
 }
@@ -900,6 +912,7 @@ static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local) {
   a.buf_elems = b->shape.buf_elems;
   a.nt = b->shape.nt;
   a.nrg = b->shape.nrg;
+  a.nks = b->shape.nks;
   return a;
 }
 

@@ -48,6 +48,20 @@ struct Val<R, true> {
 __device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 __device__ inline float shfl_xor_d(float v, int m) { return __shfl_xor(v, m, 64); }
 
+// c ? a : b by bit masks.  A plain select of two elements of a register array can be turned
+// by the compiler into one load with a lane-dependent index, which moves the whole array to
+// scratch memory; the masks keep it in registers.
+template <typename R>
+__device__ inline R pick_bits(bool c, R a, R b) {
+  if constexpr (sizeof(R) == 8) {
+    const uint64_t m = 0ull - (uint64_t)c;
+    return __builtin_bit_cast(R, (__builtin_bit_cast(uint64_t, a) & m) | (__builtin_bit_cast(uint64_t, b) & ~m));
+  } else {
+    const uint32_t m = 0u - (uint32_t)c;
+    return __builtin_bit_cast(R, (__builtin_bit_cast(uint32_t, a) & m) | (__builtin_bit_cast(uint32_t, b) & ~m));
+  }
+}
+
 // Reduce-scatter of the 2^M values v[] over the 64 lanes of a wavefront by halving
 // exchanges: after the call, every lane holds the wave-wide sum of v[lane >> (6 - M)].
 // Uses 2^M - 1 shuffles for the halving steps plus (6 - M) for the remaining ones.
@@ -60,9 +74,8 @@ __device__ inline R wave_reduce_scatter(R (&v)[1 << M], int lane) {
     const bool up = (lane & s) != 0;
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) {
-      R keep = up ? v[L / 2 + k] : v[k];
-      R send = up ? v[k] : v[L / 2 + k];
-      v[k] = keep + shfl_xor_d(send, s);
+      const R lo = v[k], hi = v[L / 2 + k];
+      v[k] = pick_bits(up, hi, lo) + shfl_xor_d(pick_bits(up, lo, hi), s);
     }
   }
   R r = v[0];

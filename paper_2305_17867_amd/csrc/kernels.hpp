@@ -74,7 +74,7 @@ struct M2LItem {
 // M2L launch limits: at most 8 wavefronts per workgroup; per-thread register prefetch of one
 // entry in two size classes (table values, source-tile values).
 constexpr int kM2LMaxThreads = 512;
-constexpr int kPrefT0 = 4, kPrefB0 = 8;
+constexpr int kPrefT0 = 4, kPrefB0 = 12;
 constexpr int kPrefT1 = 8, kPrefB1 = 16;
 constexpr int kPrefT2 = 20, kPrefB2 = 24;
 
@@ -99,7 +99,8 @@ struct M2LArgs {
   int32_t tab_off;             // offset of the source tile in an LDS buffer (elements)
   int32_t buf_elems;           // elements of one LDS buffer (two buffers)
   int32_t nt;                  // targets per tile (16 x column tiles of the workgroup)
-  int32_t nrg;                 // row groups: wavefront w owns row group w % nrg, column group w / nrg
+  int32_t nrg;                 // row groups: wavefront w owns row group w % nrg
+  int32_t nks;                 // K splits: wavefront w takes K range (w / nrg) / (nt / (16 CT))
 };
 
 // FFT form of the M2L (eq. convolution_m2l): spectra are Hermitian halves [Sz][S][(S+1)/2].
@@ -149,7 +150,7 @@ int launch_l2p(const L2PArgs& a, int p, int dtype, hipStream_t s);
 int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int col_tiles, int pf_class, int nbuf, int waves,
                hipStream_t s);
 void m2l_shape(M2LArgs& a, size_t real_bytes, bool cplx, int ct_total);
-size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf);
+size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf, int rt, bool cplx);
 int m2l_prefetch_class(const M2LArgs& a, bool cplx, int ct_total, int waves);
 bool m2l_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
 int launch_direct(const DirectArgs& a, int dtype, hipStream_t s);

@@ -2,8 +2,14 @@
 // local theta~ (forward substitution over the PDE recursion, Thm. mult_decompression,
 // levels of m_z ascending), multiply by 1/i!, and add
 //   phi(x) = sum_{i in M(p)} L~_i / i! X^i,    X = (x - c) / h,
-// to every target of the box.  One workgroup per box; the coefficients live in LDS and are
-// read as wave-wide broadcasts; each thread evaluates a nested Horner scheme.
+// to every target of the box.
+//
+// One wavefront per box (a workgroup of 64 lanes, so its barriers cost next to nothing).  The
+// decompressed coefficients live in LDS and are read as wave-wide broadcasts; every lane
+// evaluates kU targets at once with a nested Horner scheme, so that each coefficient read
+// feeds kU fused multiply-adds.  The index decode (full index -> (x, y, z)) comes from
+// compile-time tables, and the recursion terms are unrolled so that no per-lane array is
+// indexed dynamically.
 #pragma once
 
 #include "../../include/fmm.h"
@@ -15,7 +21,9 @@ namespace fmm {
 
 namespace detail_l2p {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 64;  // one wavefront per box
+constexpr int kU = 4;         // targets per lane and pass
+constexpr int kWavesPerEU = 4;  // register budget: at most 128 per lane
 
 struct InvFact {
   double v[FMM_MAX_ORDER + 1];
@@ -28,27 +36,50 @@ struct InvFact {
   }
 };
 
+// (x, y, z) of every full index of M(P), and 1 / (x! y! z!)
+template <int P>
+struct FullDecode {
+  unsigned char x[nfull(P)], y[nfull(P)], z[nfull(P)];
+  double inv_fact[nfull(P)];
+  constexpr FullDecode() : x(), y(), z(), inv_fact() {
+    constexpr InvFact IF{};
+    int k = 0;
+    for (int mz = 0; mz <= P; ++mz)
+      for (int mx = 0; mx <= P - mz; ++mx)
+        for (int my = 0; my <= P - mz - mx; ++my) {
+          x[k] = (unsigned char)mx;
+          y[k] = (unsigned char)my;
+          z[k] = (unsigned char)mz;
+          inv_fact[k] = IF.v[mx] * IF.v[my] * IF.v[mz];
+          ++k;
+        }
+  }
+};
+
+template <int P>
+__device__ constexpr FullDecode<P> kDecode{};
+
+// Forward substitution L = M theta in LDS, levels m_z = c .. P (values in double, complex
+// interleaved).  Entry k of level z is full index slab(z) + k.
 template <int P, bool CPLX>
 __device__ inline void decompress_lds(double* L, const RecArgs& rec, int c, double h) {
   double cf[kMaxRecTerms];
-  for (int t = 0; t < rec.n; ++t) {
+#pragma unroll
+  for (int t = 0; t < kMaxRecTerms; ++t) {
     double f = rec.coef[t];
     for (int e = 0; e < rec.hpow[t]; ++e) f *= h;
     cf[t] = f;
   }
   for (int z = c; z <= P; ++z) {
-    const int cnt = tri(P - z);
+    const int s0 = nfull(P) - nfull(P - z), cnt = tri(P - z);
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-      int x = 0, rem = k;
-      while (rem > P - z - x) {
-        rem -= P - z - x + 1;
-        ++x;
-      }
-      const int y = rem;
+      const int m = s0 + k;
+      const int x = kDecode<P>.x[m], y = kDecode<P>.y[m];
       double sr = 0.0, si = 0.0;
-      for (int t = 0; t < rec.n; ++t) {
-        const int nx = x + rec.dx[t], ny = y + rec.dy[t], nz = z + rec.dz[t];
-        const int n = full_index(P, nx, ny, nz);
+#pragma unroll
+      for (int t = 0; t < kMaxRecTerms; ++t) {
+        if (t >= rec.n) break;
+        const int n = full_index(P, x + rec.dx[t], y + rec.dy[t], z + rec.dz[t]);
         if constexpr (CPLX) {
           sr += cf[t] * L[2 * n];
           si += cf[t] * L[2 * n + 1];
@@ -56,7 +87,6 @@ __device__ inline void decompress_lds(double* L, const RecArgs& rec, int c, doub
           sr += cf[t] * L[n];
         }
       }
-      const int m = full_index(P, x, y, z);
       if constexpr (CPLX) {
         L[2 * m] = sr;
         L[2 * m + 1] = si;
@@ -68,27 +98,76 @@ __device__ inline void decompress_lds(double* L, const RecArgs& rec, int c, doub
   }
 }
 
-// Nested Horner evaluation of sum_{|m| <= Q} C[full_index(Q, m)] X^m.
-template <int Q, typename R>
-__device__ inline R horner(const R* C, int W, int u, R X, R Y, R Z) {
-  R pz = R(0);
-#pragma unroll
-  for (int z = Q; z >= 0; --z) {
-    R qx = R(0);
-#pragma unroll
-    for (int x = Q - z; x >= 0; --x) {
-      R ry = R(0);
-#pragma unroll
-      for (int y = Q - z - x; y >= 0; --y) ry = ry * Y + C[full_index(Q, x, y, z) * W + u];
-      qx = qx * X + ry;
-    }
-    pz = pz * Z + qx;
+// Position of every full index of M(Q) in the order in which the nested Horner scheme below
+// consumes the coefficients (z from Q down, then x down, then y down).
+template <int Q>
+struct HornerOrder {
+  int pos[nfull(Q) > 0 ? nfull(Q) : 1];
+  constexpr HornerOrder() : pos() {
+    int k = 0;
+    for (int z = Q; z >= 0; --z)
+      for (int x = Q - z; x >= 0; --x)
+        for (int y = Q - z - x; y >= 0; --y) pos[full_index(Q, x, y, z)] = k++;
   }
-  return pz;
+};
+
+template <int Q>
+__device__ constexpr HornerOrder<Q> kHorner{};
+
+// out[j][u] = sum_{|m| <= Q} c_m,u X_j^m for kU points j at once (nested Horner: y innermost,
+// then x, then z), the coefficients C[W * k + u] stored in Horner order.  The row loops are
+// kept as loops so that the coefficients are read from LDS as they are consumed.
+template <int Q, int W, typename R>
+__device__ inline void horner_u(const R* C, const R (&X)[kU], const R (&Y)[kU], const R (&Z)[kU],
+                                R (&out)[kU][W]) {
+  R pz[kU][W];
+#pragma unroll
+  for (int j = 0; j < kU; ++j)
+#pragma unroll
+    for (int u = 0; u < W; ++u) pz[j][u] = R(0);
+  int idx = 0;
+#pragma unroll 1
+  for (int z = Q; z >= 0; --z) {
+    R qx[kU][W];
+#pragma unroll
+    for (int j = 0; j < kU; ++j)
+#pragma unroll
+      for (int u = 0; u < W; ++u) qx[j][u] = R(0);
+#pragma unroll 1
+    for (int x = Q - z; x >= 0; --x) {
+      R ry[kU][W];
+#pragma unroll
+      for (int j = 0; j < kU; ++j)
+#pragma unroll
+        for (int u = 0; u < W; ++u) ry[j][u] = R(0);
+      const int n = Q - z - x + 1;
+#pragma unroll 2
+      for (int y = 0; y < n; ++y, ++idx) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          const R cv = C[idx * W + u];
+#pragma unroll
+          for (int j = 0; j < kU; ++j) ry[j][u] = ry[j][u] * Y[j] + cv;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kU; ++j)
+#pragma unroll
+        for (int u = 0; u < W; ++u) qx[j][u] = qx[j][u] * X[j] + ry[j][u];
+    }
+#pragma unroll
+    for (int j = 0; j < kU; ++j)
+#pragma unroll
+      for (int u = 0; u < W; ++u) pz[j][u] = pz[j][u] * Z[j] + qx[j][u];
+  }
+#pragma unroll
+  for (int j = 0; j < kU; ++j)
+#pragma unroll
+    for (int u = 0; u < W; ++u) out[j][u] = pz[j][u];
 }
 
 template <int P, typename R, bool CPLX, bool GRAD>
-__global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void l2p_kernel(L2PArgs a) {
   constexpr int NP = nfull(P);
   constexpr int NG = GRAD ? nfull(P - 1) : 0;
   constexpr int W = CPLX ? 2 : 1;
@@ -101,32 +180,24 @@ __global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
   const double h = a.level_h[lev];
   const int nc = a.nc;
   const R* loc = reinterpret_cast<const R*>(a.local) + b * (int64_t)nc * W;
-  for (int k = threadIdx.x; k < nc * W; k += blockDim.x) Ld[k] = (double)loc[k];
+  for (int k = threadIdx.x; k < nc * W; k += kThreads) Ld[k] = (double)loc[k];
   __syncthreads();
   decompress_lds<P, CPLX>(Ld, a.rec, a.c, h);
-  constexpr InvFact IF{};
-  for (int k = threadIdx.x; k < NP; k += blockDim.x) {
-    // recover (x, y, z) of full index k
-    int z = 0;
-    while (nfull(P) - nfull(P - z - 1) <= k) ++z;
-    int rem = k - (nfull(P) - nfull(P - z));
-    int x = 0;
-    while (rem > P - z - x) {
-      rem -= P - z - x + 1;
-      ++x;
-    }
-    const int y = rem;
-    const double f = IF.v[x] * IF.v[y] * IF.v[z];
-    for (int u = 0; u < W; ++u) Lc[k * W + u] = (R)(Ld[k * W + u] * f);
+  for (int k = threadIdx.x; k < NP; k += kThreads) {
+    const double f = kDecode<P>.inv_fact[k];
+    const int hk = kHorner<P>.pos[k];
+#pragma unroll
+    for (int u = 0; u < W; ++u) Lc[hk * W + u] = (R)(Ld[k * W + u] * f);
     if constexpr (GRAD) {
-      // d/dX_k of L_m X^m / m!: coefficient of X^(m - e_k) is L_m / (m - e_k)!
-      const int mm[3] = {x, y, z};
+      // d/dX_ax of L_m X^m / m!: the coefficient of X^(m - e_ax) is L_m / (m - e_ax)!
+      const int mm[3] = {kDecode<P>.x[k], kDecode<P>.y[k], kDecode<P>.z[k]};
+#pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         if (mm[ax] == 0) continue;
-        int d[3] = {x, y, z};
-        d[ax] -= 1;
-        const int g = full_index(P - 1, d[0], d[1], d[2]);
-        const double fg = IF.v[d[0]] * IF.v[d[1]] * IF.v[d[2]];
+        const int d0 = mm[0] - (ax == 0), d1 = mm[1] - (ax == 1), d2 = mm[2] - (ax == 2);
+        const int g = kHorner<P - 1>.pos[full_index(P - 1, d0, d1, d2)];
+        const double fg = f * mm[ax];
+#pragma unroll
         for (int u = 0; u < W; ++u) Lg[ax][g * W + u] = (R)(Ld[k * W + u] * fg);
       }
     }
@@ -138,21 +209,44 @@ __global__ __launch_bounds__(kThreads) void l2p_kernel(L2PArgs a) {
   hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
   const R* xyz = reinterpret_cast<const R*>(a.xyz);
   const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)(a.xsign / h);
-  for (int64_t s = lo + threadIdx.x; s < hi; s += blockDim.x) {
-    const R X = (xyz[3 * s + 0] - cx) * ih;
-    const R Y = (xyz[3 * s + 1] - cy) * ih;
-    const R Z = (xyz[3 * s + 2] - cz) * ih;
+  for (int64_t s0 = lo + threadIdx.x; s0 < hi; s0 += kThreads * kU) {
+    R X[kU], Y[kU], Z[kU];
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      const int64_t s = s0 + (int64_t)j * kThreads;
+      const bool ok = s < hi;
+      X[j] = ok ? (xyz[3 * s + 0] - cx) * ih : R(0);
+      Y[j] = ok ? (xyz[3 * s + 1] - cy) * ih : R(0);
+      Z[j] = ok ? (xyz[3 * s + 2] - cz) * ih : R(0);
+    }
     if (a.pot) {
+      R v[kU][W];
+      horner_u<P, W, R>(Lc, X, Y, Z, v);
       R* pot = reinterpret_cast<R*>(a.pot);
-      pot[s * W] += horner<P, R>(Lc, W, 0, X, Y, Z);
-      if constexpr (CPLX) pot[2 * s + 1] += horner<P, R>(Lc, W, 1, X, Y, Z);
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        const int64_t s = s0 + (int64_t)j * kThreads;
+        if (s < hi) {
+#pragma unroll
+          for (int u = 0; u < W; ++u) pot[s * W + u] += v[j][u];
+        }
+      }
     }
     if constexpr (GRAD && P > 0 && !CPLX) {
-      const R sc = a.gscale ? reinterpret_cast<const R*>(a.gscale)[s] : R(1);
-      R* g = reinterpret_cast<R*>(a.grad);
-      g[3 * s + 0] += sc * ih * horner<P - 1, R>(Lg[0], 1, 0, X, Y, Z);
-      g[3 * s + 1] += sc * ih * horner<P - 1, R>(Lg[1], 1, 0, X, Y, Z);
-      g[3 * s + 2] += sc * ih * horner<P - 1, R>(Lg[2], 1, 0, X, Y, Z);
+      R g[3][kU][1];
+      horner_u<P - 1, 1, R>(Lg[0], X, Y, Z, g[0]);
+      horner_u<P - 1, 1, R>(Lg[1], X, Y, Z, g[1]);
+      horner_u<P - 1, 1, R>(Lg[2], X, Y, Z, g[2]);
+      R* gout = reinterpret_cast<R*>(a.grad);
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        const int64_t s = s0 + (int64_t)j * kThreads;
+        if (s < hi) {
+          const R sc = a.gscale ? reinterpret_cast<const R*>(a.gscale)[s] : R(1);
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) gout[3 * s + ax] += sc * ih * g[ax][j][0];
+        }
+      }
     }
   }
 }

@@ -71,7 +71,7 @@ struct MF<float> {
 // the kept order (m_z, m_x, m_y).  B rows are zero beyond Nc, which makes the padded K steps
 // add nothing; padded rows (i >= Nc) read a valid table entry and are never stored.
 template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
-__device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, const int item_id) {
+__device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
   using V = typename MF<R>::V;
   constexpr int CW = CPLX ? 2 : 1;
   const int NT = a.nt;  // 16 x column tiles of the workgroup
@@ -86,14 +86,19 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, con
   int* sbq = reinterpret_cast<int*>(buf0 + (DB ? 2 : 1) * buf_elems);  // [4 k4p] table base of q
   __shared__ int s_last;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wavefront index is uniform: keep it (and everything derived from it) in scalar
+  // registers, so that the row-group / K-range conditions of the inner loop are scalar branches
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nthr = blockDim.x;
   const int rtiles = ncp >> 4;
-  // wavefront -> (row group, column group): row tiles rg RT + r, column tiles cg CT + c.
-  // In a launch shared by several batches a workgroup may have more wavefronts than this
-  // batch needs; those only help with the staging.
-  const int rg = wave % a.nrg, cg = wave / a.nrg;
-  const bool active = cg * CT * 16 < NT;
+  // wavefront -> (row group, column group, K range): row tiles rg RT + r, column tiles
+  // cg CT + c, K steps [s0, s1) of every lane group.  In a launch shared by several batches a
+  // workgroup may have more wavefronts than this batch needs; those only help with the staging.
+  const int nrg = a.nrg, ncg = NT / (16 * CT), nks = a.nks;
+  const int rg = wave % nrg, cg = (wave / nrg) % ncg, kh = wave / (nrg * ncg);
+  const bool active = kh < nks;
+  const int nsteps = k4p / VW;
+  const int s0 = active ? (kh * nsteps) / nks * VW : 0, s1 = active ? ((kh + 1) * nsteps) / nks * VW : 0;
   const int col = lane & 15;
   const int kq = lane >> 4;
   const int tab_off = a.tab_off;  // start of the source tile within a buffer
@@ -117,14 +122,21 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, con
   const int qs = CPLX ? (rs >> 1) : rs;
   const int qstep = CPLX ? (tps >> 1) : tps;
   const int bdst_off = tab_off + (us * NT + js) * ldb + qs;
-  auto issue = [&](int e) {
-    const R* gt = tabg + (int64_t)a.entry_tab[e] * n_tv;
+  // table and source indices of the next entry to issue, read one entry ahead so that the
+  // operand loads of issue() do not wait on them
+  int idx_tab = 0, idx_src = -1;
+  auto load_idx = [&](int e) {
+    idx_tab = a.entry_tab[e];
+    idx_src = a.entry_src[(int64_t)e * NT + js];
+  };
+  auto issue = [&]() {
+    const R* gt = tabg + (int64_t)idx_tab * n_tv;
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
       const int f = tid + k * nthr;
       if (f < n_tv) pft[k] = gt[f];
     }
-    const int src = a.entry_src[(int64_t)e * NT + js];
+    const int src = idx_src;
     const R* gb = mp + (int64_t)(src < 0 ? 0 : src) * ncw + rs;
 #pragma unroll
     for (int k = 0; k < PB; ++k) {
@@ -164,7 +176,11 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, con
   }
   const int q0 = kq * k4p;
 
-  if (it.e0 < it.e1) issue(it.e0);
+  if (it.e0 < it.e1) {
+    load_idx(it.e0);
+    issue();
+    if (it.e0 + 1 < it.e1) load_idx(it.e0 + 1);
+  }
   __syncthreads();  // zero fill done
   if (it.e0 < it.e1) commit(buf0);
   __syncthreads();
@@ -172,63 +188,55 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, con
   for (int e = it.e0; e < it.e1; ++e) {
     R* cur = DB ? buf0 + ((e - it.e0) & 1) * buf_elems : buf0;
     R* nxt = DB ? buf0 + (((e - it.e0) & 1) ^ 1) * buf_elems : buf0;
-    if (e + 1 < it.e1) issue(e + 1);
+    if (e + 1 < it.e1) {
+      issue();
+      if (e + 2 < it.e1) load_idx(e + 2);
+    }
     const R* brow[CT][CW];
 #pragma unroll
     for (int c = 0; c < CT; ++c)
 #pragma unroll
       for (int u = 0; u < CW; ++u) brow[c][u] = cur + tab_off + (u * NT + (cg * CT + c) * 16 + col) * ldb + q0;
-    // software pipeline: the B vectors and table offsets of step ks + VW load while the
-    // products of step ks run
+    // K steps of this wavefront.  The operands of a step are read from LDS right before its
+    // products: the other wavefronts of the SIMD cover the latency, and single-buffered
+    // operands keep the register count low enough for four wavefronts per SIMD.
     typedef int IV __attribute__((ext_vector_type(VW)));
     const int* qrow = sbq + q0;
-    RV bc[CT][CW], bn[CT][CW];
-    IV qc = *reinterpret_cast<const IV*>(qrow), qn;
-#pragma unroll
-    for (int c = 0; c < CT; ++c)
-#pragma unroll
-      for (int u = 0; u < CW; ++u) bc[c][u] = *reinterpret_cast<const RV*>(brow[c][u]);
-    for (int ks = 0; ks < k4p; ks += VW) {
-      R ar[VW][RT], ai[VW][RT];
-#pragma unroll
-      for (int v = 0; v < VW; ++v)
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          ar[v][r] = cur[ib[r] + qc[v]];
-          if constexpr (CPLX) ai[v][r] = cur[ts + ib[r] + qc[v]];
-        }
-      const bool more = ks + VW < k4p;
-      if (more) {
-        qn = *reinterpret_cast<const IV*>(qrow + ks + VW);
+    const int nr = rtiles - rg * RT;  // row tiles of this wavefront that exist (uniform)
+    if (active) {
+      for (int ks = s0; ks < s1; ks += VW) {
+        const IV qc = *reinterpret_cast<const IV*>(qrow + ks);
+        RV bc[CT][CW];
 #pragma unroll
         for (int c = 0; c < CT; ++c)
 #pragma unroll
-          for (int u = 0; u < CW; ++u) bn[c][u] = *reinterpret_cast<const RV*>(brow[c][u] + ks + VW);
-      }
+          for (int u = 0; u < CW; ++u) bc[c][u] = *reinterpret_cast<const RV*>(brow[c][u] + ks);
+        R ac[VW][RT][CW];
 #pragma unroll
-      for (int v = 0; v < VW; ++v)
+        for (int v = 0; v < VW; ++v)
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          if ((RT > 1 && rg * RT + r >= rtiles) || !active) continue;
-          if constexpr (CPLX) {
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-              part[r][c][0] = MF<R>::mma(ar[v][r], bc[c][0][v], part[r][c][0]);
-              part[r][c][0] = MF<R>::mma(-ai[v][r], bc[c][1][v], part[r][c][0]);
-              part[r][c][1] = MF<R>::mma(ar[v][r], bc[c][1][v], part[r][c][1]);
-              part[r][c][1] = MF<R>::mma(ai[v][r], bc[c][0][v], part[r][c][1]);
-            }
-          } else {
-#pragma unroll
-            for (int c = 0; c < CT; ++c) part[r][c][0] = MF<R>::mma(ar[v][r], bc[c][0][v], part[r][c][0]);
+          for (int r = 0; r < RT; ++r) {
+            ac[v][r][0] = cur[ib[r] + qc[v]];
+            if constexpr (CPLX) ac[v][r][1] = cur[ts + ib[r] + qc[v]];
           }
-        }
-      if (more) {
-        qc = qn;
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
+        for (int v = 0; v < VW; ++v)
 #pragma unroll
-          for (int u = 0; u < CW; ++u) bc[c][u] = bn[c][u];
+          for (int r = 0; r < RT; ++r) {
+            if (RT > 1 && r >= nr) continue;
+            if constexpr (CPLX) {
+#pragma unroll
+              for (int c = 0; c < CT; ++c) {
+                part[r][c][0] = MF<R>::mma(ac[v][r][0], bc[c][0][v], part[r][c][0]);
+                part[r][c][0] = MF<R>::mma(-ac[v][r][1], bc[c][1][v], part[r][c][0]);
+                part[r][c][1] = MF<R>::mma(ac[v][r][0], bc[c][1][v], part[r][c][1]);
+                part[r][c][1] = MF<R>::mma(ac[v][r][1], bc[c][0][v], part[r][c][1]);
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < CT; ++c) part[r][c][0] = MF<R>::mma(ac[v][r][0], bc[c][0][v], part[r][c][0]);
+            }
+          }
       }
     }
     if constexpr (ACC64) {
@@ -258,11 +266,46 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, con
           for (int v = 0; v < 4; ++v) acc[r][c][u][v] = (double)part[r][c][u][v];
   }
 
+  // K splits: the partial sums of wavefronts kh = 1 .. nks-1 are added to those of kh = 0, in
+  // that order, through LDS (the staging buffers are free now)
+  if (nks > 1) {
+    constexpr int NACC = RT * CT * CW * 4;
+    double* red = reinterpret_cast<double*>(smem_raw);
+    const int slot = wave % (nrg * ncg);
+    for (int k = 1; k < nks; ++k) {
+      __syncthreads();
+      if (kh == k) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int u = 0; u < CW; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                red[(slot * NACC + ((r * CT + c) * CW + u) * 4 + v) * 64 + lane] = acc[r][c][u][v];
+      }
+      __syncthreads();
+      if (kh == 0) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int u = 0; u < CW; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                acc[r][c][u][v] += red[(slot * NACC + ((r * CT + c) * CW + u) * 4 + v) * 64 + lane];
+      }
+    }
+  }
+  const bool writer = active && kh == 0;
+
   // result rows of this lane: MF<R>::row(kq, v), column (cg CT + c) 16 + col
   const int nparts = a.tile_nparts[it.tile];
   const int* tg = a.tile_tgt + (int64_t)it.tile * NT;
   if (nparts == 1) {
-    if (!active) return;
+    if (!writer) return;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const int t = tg[(cg * CT + c) * 16 + col];
@@ -285,13 +328,13 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, con
     return;
   }
   // split tile: FP64 partial to scratch, the last workgroup of the tile adds all parts in order
-  double* mine = a.scratch + (int64_t)item_id * NT * ncp * CW;
+  double* mine = a.scratch + (int64_t)(a.tile_item0[it.tile] + it.part) * NT * ncp * CW;
 #pragma unroll
   for (int c = 0; c < CT; ++c)
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
       const int rt = rg * RT + r;
-      if (rt >= rtiles || !active) continue;
+      if (rt >= rtiles || !writer) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = rt * 16 + MF<R>::row(kq, v);
@@ -308,27 +351,55 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it, con
   __syncthreads();
   if (!s_last) return;
   __threadfence();
+  // four outputs per thread and pass, the loads of all parts issued before the sums
   const int item0 = a.tile_item0[it.tile];
-  for (int k = tid; k < NT * nc; k += nthr) {
-    const int c = k / nc, i = k - c * nc;
-    const int t = tg[c];
-    if (t < 0) continue;
-    double sr = 0.0, si = 0.0;
-    for (int pt = 0; pt < nparts; ++pt) {
-      const double* ps = a.scratch + (int64_t)(item0 + pt) * NT * ncp * CW;
-      sr += ps[(c * ncp + i) * CW];
-      if constexpr (CPLX) si += ps[(c * ncp + i) * CW + 1];
+  const double* __restrict__ parts = a.scratch + (int64_t)item0 * NT * ncp * CW;
+  const int64_t pstride = (int64_t)NT * ncp * CW;
+  constexpr int U = 4;
+  for (int k0 = tid; k0 < NT * nc; k0 += U * nthr) {
+    double sr[U], si[U];
+    int off[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int k = k0 + j * nthr;
+      const int c = k / nc, i = k - c * nc;
+      off[j] = k < NT * nc ? (c * ncp + i) * CW : 0;
+      sr[j] = si[j] = 0.0;
     }
-    R* out = reinterpret_cast<R*>(a.local) + (int64_t)t * nc * CW;
-    out[i * CW] = (R)((double)out[i * CW] + sr);
-    if constexpr (CPLX) out[i * CW + 1] = (R)((double)out[i * CW + 1] + si);
+    for (int pt = 0; pt < nparts; ++pt) {
+      const double* ps = parts + pt * pstride;
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        sr[j] += ps[off[j]];
+        if constexpr (CPLX) si[j] += ps[off[j] + 1];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int k = k0 + j * nthr;
+      if (k >= NT * nc) continue;
+      const int c = k / nc, i = k - c * nc;
+      const int t = tg[c];
+      if (t < 0) continue;
+      R* out = reinterpret_cast<R*>(a.local) + (int64_t)t * nc * CW;
+      out[i * CW] = (R)((double)out[i * CW] + sr[j]);
+      if constexpr (CPLX) out[i * CW + 1] = (R)((double)out[i * CW + 1] + si[j]);
+    }
   }
   if (tid == 0) atomicExch(a.counter + it.tile, 0);
 }
 
+// Register target: the 2x2 and 3x2 real FP64 tiles with the smallest staging class fit in
+// 128 registers, i.e. four wavefronts per SIMD (the compiler would otherwise take a few more).
+template <typename R, bool CPLX, int RT, int CT, int PT>
+constexpr int m2l_waves_hint() {
+  return (sizeof(R) == 8 && !CPLX && PT == kPrefT0 && CT == 2 && (RT == 2 || RT == 3)) ? 4 : 1;
+}
+
 template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
-__global__ __launch_bounds__(kM2LMaxThreads) void m2l_kernel(M2LArgs a) {
-  m2l_item<R, CPLX, RT, CT, PT, PB, DB>(a, a.items[blockIdx.x], blockIdx.x);
+__global__ __launch_bounds__(kM2LMaxThreads)
+__attribute__((amdgpu_waves_per_eu(m2l_waves_hint<R, CPLX, RT, CT, PT>()))) void m2l_kernel(M2LArgs a) {
+  m2l_item<R, CPLX, RT, CT, PT, PB, DB>(a, a.items[blockIdx.x]);
 }
 
 // Persistent launch over the work items of several batches: workgroup g takes items
@@ -342,7 +413,7 @@ __global__ __launch_bounds__(kM2LMaxThreads) void m2l_multi_kernel(M2LMulti m) {
     M2LArgs a = m.args[wk.x];
     a.mpole = m.mpole[wk.x];
     a.local = m.local[wk.x];
-    m2l_item<R, CPLX, RT, CT, PT, PB, DB>(a, a.items[wk.y], wk.y);
+    m2l_item<R, CPLX, RT, CT, PT, PB, DB>(a, a.items[wk.y]);
   }
 }
 
@@ -387,7 +458,7 @@ int launch_multi_typed(const M2LMulti& m, int rt, int ct, int pf, int nbuf, size
 
 template <typename R, bool CPLX, int RT, int CT, int PT, int PB, bool DB>
 int launch_cfg(const M2LArgs& a, int waves, hipStream_t s) {
-  const size_t lds = m2l_lds_bytes(a, sizeof(R), DB ? 2 : 1);
+  const size_t lds = m2l_lds_bytes(a, sizeof(R), DB ? 2 : 1, RT, CPLX);
   auto kern = m2l_kernel<R, CPLX, RT, CT, PT, PB, DB>;
   if (lds > 65536) {
     static size_t granted = 0;  // per instantiation
@@ -474,8 +545,11 @@ void m2l_shape(M2LArgs& a, size_t real_bytes, bool cplx, int ct_total) {
   a.nt = 16 * ct_total;
 }
 
-size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf) {
-  return (size_t)nbuf * a.buf_elems * real_bytes + 4 * (size_t)a.k4p * sizeof(int);
+size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf, int rt, bool cplx) {
+  const size_t stage = (size_t)nbuf * a.buf_elems * real_bytes + 4 * (size_t)a.k4p * sizeof(int);
+  // K-split reduction: one FP64 accumulator set per (row group, column group) wavefront
+  const size_t red = a.nks > 1 ? (size_t)a.nrg * (a.nt / 16) * rt * (cplx ? 2 : 1) * 4 * 64 * sizeof(double) : 0;
+  return stage > red ? stage : red;
 }
 
 int m2l_prefetch_class(const M2LArgs& a, bool cplx, int ct_total, int waves) {

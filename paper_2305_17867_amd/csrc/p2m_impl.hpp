@@ -61,7 +61,10 @@ __device__ inline void accumulate_chunk(R (&acc)[2][QP], const R (&px)[P + 1], c
 template <int P, typename R, bool CPLX, int QMAX>
 struct Chunks {
   static constexpr int NP = nfull(P);
-  static constexpr int N = (NP + QMAX - 1) / QMAX;
+  // number of chunks: a multiple of the wavefront count when there is enough work, so that
+  // the wavefronts of a box get the same number of chunks
+  static constexpr int N0 = (NP + QMAX - 1) / QMAX;
+  static constexpr int N = N0 >= kWaves ? (N0 + kWaves - 1) / kWaves * kWaves : N0;
   static constexpr int Q = (NP + N - 1) / N;  // balanced chunk size <= QMAX
   static constexpr int M = Q <= 1 ? 0 : Q <= 2 ? 1 : Q <= 4 ? 2 : Q <= 8 ? 3 : Q <= 16 ? 4 : Q <= 32 ? 5 : 6;
   static constexpr int QP = 1 << M;
@@ -125,29 +128,31 @@ __device__ inline void run_chunks(const P2MArgs& a, int64_t lo, int64_t hi, cons
   }
 }
 
+template <int P>
+__device__ constexpr FullIdx<P> kFullIdx{};
+
 // In-LDS back substitution beta = M^T alpha over the recursion terms (gather form, levels
-// of m_z from P down to 0).  Values in double (complex interleaved).
+// of m_z from P down to 0).  Values in double (complex interleaved).  Entry k of level z is
+// full index slab(z) + k; the recursion terms are unrolled, so nothing is indexed dynamically
+// in registers.
 template <int P, bool CPLX>
 __device__ inline void compress_lds(double* al, const RecArgs& rec, int c, double h) {
   double cf[kMaxRecTerms];
-  for (int t = 0; t < rec.n; ++t) {
+#pragma unroll
+  for (int t = 0; t < kMaxRecTerms; ++t) {
     double f = rec.coef[t];
     for (int e = 0; e < rec.hpow[t]; ++e) f *= h;
     cf[t] = f;
   }
   for (int z = P; z >= 0; --z) {
-    const int cnt = tri(P - z);
+    const int s0 = nfull(P) - nfull(P - z), cnt = tri(P - z);
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-      // (x, y) with x + y <= P - z, enumerated row by row
-      int x = 0, rem = k;
-      while (rem > P - z - x) {
-        rem -= P - z - x + 1;
-        ++x;
-      }
-      const int y = rem;
-      const int n = full_index(P, x, y, z);
+      const int n = s0 + k;
+      const int x = kFullIdx<P>.x[n], y = kFullIdx<P>.y[n];
       double sr = 0.0, si = 0.0;
-      for (int t = 0; t < rec.n; ++t) {
+#pragma unroll
+      for (int t = 0; t < kMaxRecTerms; ++t) {
+        if (t >= rec.n) break;
         // m = n - d with m_z >= c feeds n
         const int mx = x - rec.dx[t], my = y - rec.dy[t], mz = z - rec.dz[t];
         if (mx < 0 || my < 0 || mz < c || mx + my + mz > P) continue;

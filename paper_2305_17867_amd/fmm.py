@@ -221,7 +221,7 @@ class Batch:
 
     INFO = ("n_pair", "n_tables", "n_tiles", "n_entries", "n_items", "useful_columns",
             "computed_columns", "nc", "nc_pad", "scratch_bytes", "rows_per_wave", "col_tiles_per_wave",
-            "waves", "col_groups", "lds_bytes", "lds_buffers")
+            "waves", "col_groups", "lds_bytes", "lds_buffers", "k_splits")
 
     def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None, adjoint=False,
                  fft=False):
@@ -240,7 +240,7 @@ class Batch:
         if tuning is not None:
             tun = _lib.FmmM2LTuning(int(tuning.get("rows_per_wave", 0)), int(tuning.get("col_tiles_per_wave", 0)),
                                     int(tuning.get("col_groups", 0)), int(tuning.get("target_items", 0)),
-                                    int(tuning.get("lds_buffers", 0)))
+                                    int(tuning.get("lds_buffers", 0)), int(tuning.get("k_splits", 0)))
         args = (plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P), s.ctypes.data_as(_lib.I32P), self.n_box,
                 ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P))
         if fft:

@@ -188,6 +188,47 @@ def test_m2l(gpu_lib, m2l_tree, kernel, p, single, items, monkeypatch):
     assert np.array_equal(host(loc2), host(loc))
 
 
+KSPLIT_CASES = [("laplace", 8, False, (2, 2, 1)), ("laplace", 8, True, (3, 2, 1)), ("helmholtz", 6, False, (2, 1, 2)),
+                ("biharmonic", 12, True, (3, 2, 1)), ("yukawa", 10, True, (2, 1, 1))]
+
+
+@pytest.mark.parametrize("kernel,p,single,shape", KSPLIT_CASES)
+@pytest.mark.parametrize("nks", [2, 3])
+@pytest.mark.parametrize("items", [None, 4096])
+def test_m2l_k_split(gpu_lib, m2l_tree, kernel, p, single, shape, nks, items):
+    """Contraction split over several wavefronts of a workgroup (fmm_m2l_tuning.k_splits),
+    against the oracle at the M2L tolerance, with and without split tiles."""
+    fmm = gpu_lib
+    tr = m2l_tree
+    param = CASES[kernel]
+    d = desc_for(fmm, kernel, p, single)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    t, s = W.interaction_pairs(tr, [3])
+    rt, ct, ncg = shape
+    tun = dict(rows_per_wave=rt, col_tiles_per_wave=ct, col_groups=ncg, lds_buffers=1, k_splits=nks)
+    if items:
+        tun["target_items"] = items
+    try:
+        batch = plan.prepare(t, s, tr.ijk, tr.level, tuning=tun)
+    except fmm._lib.FmmError as e:
+        pytest.skip(f"shape does not fit: {e}")
+    assert batch.info()["k_splits"] == nks
+    nc = d.nc
+    g = np.random.Generator(np.random.PCG64(23))
+    beta = g.standard_normal((tr.n_box, nc))
+    if kernel == "helmholtz":
+        beta = beta + 1j * g.standard_normal((tr.n_box, nc))
+    mp = dev(beta, d.value_dtype)
+    loc = torch.zeros_like(mp)
+    batch(mp, loc)
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    inv = np.argsort(perm)
+    ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t, s, beta[:, inv])[:, perm]
+    tol = 2e-5 if single else 1e-12
+    assert rel(host(loc), ref) < tol, rel(host(loc), ref)
+
+
 def test_m2l_empty_and_validation(gpu_lib):
     fmm = gpu_lib
     d = fmm.Desc("laplace", 4, "f64")
