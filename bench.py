@@ -5,17 +5,23 @@ the unit cube (one set serving as sources and targets), weights N(0,1), uniform 
 depth 4 (4,096 leaves, ~256 points each), M2L over all 584,136 List-2 pairs of level 4
 (316 distinct offsets).  One step = compressed P2M of every leaf -> batched M2L -> L2P at
 every point (plus clearing the local and potential arrays).  Inputs are resident in HBM
-before the timed region.  The headline line is FP64 at p = 8; FP32 and p = 12 are reported
+before the timed region.  The step is captured in a HIP graph and replayed (the eager time,
+with Python launch overhead, is reported beside it).  The headline line is FP64 at p = 8; FP32 and p = 12 are reported
 as variants in the same line.
 
 value = M2L box-pairs per second of the whole step (pairs / step time).
 roofline: the M2L kernel (the dominant one), algorithmic FLOPs 2 Nc^2 per pair over its
-average launch time measured with HIP events on its stream.
+average launch time measured with HIP events on its stream.  traffic: HBM bytes per launch from
+the rocprofv3 FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (scaled by the factors a
+plain copy gives), or null when the kernel sources changed since they were taken.
+Supplementary fields: the FFT form of the same M2L, and the mixed Yukawa + biharmonic workload
+(524,288 points, orders per level) as one graph-captured persistent launch.
 cpu_baseline: the CPU oracle (NumPy) on a bounded sample of the same workload, scaled.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +35,31 @@ sys.path.insert(0, ROOT)
 PEAK = {"f64": 78.6e12, "f32": 157.3e12}  # dense matrix-core peaks, FLOP/s
 DEPTH, NPTS, SEED = 4, 1 << 20, 1
 COPY_BYTES = 256 << 20  # plain copy used to calibrate the FETCH_SIZE / WRITE_SIZE counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_kernel_laplace_p8_f64_traffic.txt")
+# sources that decide the M2L kernel's memory traffic at the headline configuration
+TRAFFIC_SOURCES = ["paper_2305_17867_amd/csrc/m2l.hip", "paper_2305_17867_amd/csrc/kernels.hpp",
+                   "paper_2305_17867_amd/csrc/capi.cpp", "paper_2305_17867_amd/m2l_tuned.json"]
+
+
+def sources_hash() -> str:
+    h = hashlib.sha256()
+    for rel_path in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel_path), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per M2L launch from the recorded counter passes, or None if absent or stale."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_sources_sha256") != sources_hash():
+        return None
+    return float(kv["m2l_traffic_bytes"])
 
 
 def log(*a):
@@ -90,15 +121,34 @@ class Case:
         self.l2p()
 
 
-def time_step(torch, case, steps, warmup):
+def time_step(torch, case, steps, warmup, graph=True):
+    """Seconds per step.  After the warm-up the whole step (fills, P2M, M2L, L2P) is captured
+    once in a HIP graph and replayed, so that the timed region holds the GPU work of the step
+    without the Python launch overhead; graph=False times eager launches."""
     for _ in range(warmup):
         case.step()
     torch.cuda.synchronize()
+    run = case.step
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                case.step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        run = g.replay
+        run()
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        case.step()
+        run()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sec = (time.perf_counter() - t0) / steps
+    if graph:
+        del g
+    return sec
 
 
 def time_kernel(torch, fn, reps=20):
@@ -171,6 +221,50 @@ def cpu_baseline(tr, w, t, s, p=8, budget_s=12.0):
             "l2p_pts_per_s": pts_l2p / t_l2p}
 
 
+def mixed_batch(torch, fmm, reps=10):
+    """Yukawa (lambda = 2) + biharmonic far field of 524,288 Gaussian-mixture points (adaptive
+    octree, <= 64 per leaf), orders 6/8/10 by level, FP32: one batch per (kernel, order), all
+    drained by one persistent launch, captured in a HIP graph and replayed."""
+    import workloads as W
+    tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    tuning = {"rows_per_wave": 2, "col_tiles_per_wave": 2, "col_groups": 1, "lds_buffers": 1}
+    batches, mps, flops, pairs = [], [], 0.0, 0
+    for kernel, param in (("yukawa", 2.0), ("biharmonic", 0.0)):
+        for p in (6, 8, 10):
+            levels = [l for l in range(2, tr.n_levels) if 6 + 2 * ((l - 2) % 3) == p]
+            t, s = W.interaction_pairs(tr, levels)
+            if len(t) == 0:
+                continue
+            d = fmm.Desc(kernel, p, "f32", param)
+            plan = fmm.Plan(d, lh)
+            batches.append(plan.prepare(t, s, tr.ijk, tr.level, tuning=tuning))
+            mps.append(torch.randn((tr.n_box, d.nc), dtype=torch.float32, device="cuda"))
+            flops += 2.0 * d.nc ** 2 * len(t)
+            pairs += len(t)
+    locs = [torch.zeros_like(m) for m in mps]
+    multi = fmm.Multi(batches)
+    seq = time_kernel(torch, lambda: [b(m, l) for b, m, l in zip(batches, mps, locs)], reps)
+    one = time_kernel(torch, lambda: multi(mps, locs), reps)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            multi(mps, locs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    replay = time_kernel(torch, graph.replay, reps)
+    out = {"workload": "mixture 524288 pts, adaptive <=64, yukawa+biharmonic p 6/8/10 by level, f32",
+           "batches": len(batches), "pairs": pairs, "gflop": flops / 1e9,
+           "sequential_ms": seq * 1e3, "persistent_ms": one * 1e3, "graph_replay_ms": replay * 1e3,
+           "pairs_per_s": pairs / replay, "tflops": flops / replay / 1e12,
+           "frac": flops / replay / PEAK["f32"]}
+    del graph
+    multi.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +273,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default=None, help="run one variant, e.g. f64:8 (for profiling)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FFT path and the mixed workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, to calibrate HBM counters")
     args = ap.parse_args()
@@ -204,18 +299,26 @@ def main():
         case = Case(fmm, torch, tr, w, t, s, p, dt)
         log(f"variant {dt} p={p}: time {args.steps} steps")
         sec = time_step(torch, case, args.steps, args.warmup)
+        sec_eager = time_step(torch, case, args.steps, 1, graph=False)
         t_p2m = time_kernel(torch, case.p2m)
         t_m2l = time_kernel(torch, case.m2l)
         t_l2p = time_kernel(torch, case.l2p)
         flops = 2.0 * case.nc ** 2 * case.n_pair
         achieved = flops / t_m2l
+        t_fft = None
+        if not (args.only or args.no_extras) and dt == "f64":
+            fb = case.plan.prepare_fft(t, s, tr.ijk, tr.level)
+            t_fft = time_kernel(torch, lambda: fb(case.mpole, case.local))
+            fb.close()
         results.append({
             "dtype": dt, "order": p, "nc": case.nc, "ms_per_step": sec * 1e3,
+            "ms_per_step_eager": sec_eager * 1e3,
             "pairs_per_s": case.n_pair / sec,
             "p2m_pts_per_s": NPTS / t_p2m, "m2l_pairs_per_s": case.n_pair / t_m2l,
             "l2p_pts_per_s": NPTS / t_l2p,
             "p2m_ms": t_p2m * 1e3, "m2l_ms": t_m2l * 1e3, "l2p_ms": t_l2p * 1e3,
             "m2l_tflops": achieved / 1e12, "m2l_frac": achieved / PEAK[dt],
+            "m2l_fft_ms": None if t_fft is None else t_fft * 1e3,
             "m2l_batch": case.info,
         })
         log(json.dumps(results[-1]))
@@ -234,10 +337,13 @@ def main():
         "l2p_pts_per_s": head["l2p_pts_per_s"],
         "roofline": {"bound": "mfma", "kernel": "m2l_kernel",
                      "achieved": head["m2l_tflops"], "peak": PEAK[head["dtype"]] / 1e12, "unit": "TFLOP/s",
-                     "frac": head["m2l_frac"], "traffic": None,
+                     "frac": head["m2l_frac"], "traffic": recorded_traffic(),
                      "algorithmic": f"2*Nc^2 FLOP per pair, Nc={head['nc']}, {len(t)} pairs per launch"},
         "variants": results,
     }
+    if not (args.only or args.no_extras):
+        log("mixed workload (persistent, graph-captured launch)")
+        out["mixed_batch"] = mixed_batch(torch, fmm)
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
