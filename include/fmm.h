@@ -191,7 +191,8 @@ int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
  * of one launch), 5 useful pair-columns, 6 computed pair-columns (incl. padding), 7 Nc,
  * 8 rows padded to a multiple of 16, 9 scratch bytes, 10 row tiles per wavefront,
  * 11 column tiles per wavefront, 12 wavefronts per workgroup, 13 column groups,
- * 14 LDS bytes per workgroup, 15 LDS buffers, 16 K splits. */
+ * 14 LDS bytes per workgroup, 15 LDS buffers, 16 K splits, 17 rows contracted on the vector
+ * ALU (at most 2 rows past the last full 16-row tile). */
 int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
 
 /* Batched M2L: local[t] += sum over pairs (t, s) of T(c_t - c_s) mpole[s], T[i,q] =

@@ -23,7 +23,8 @@ TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "m2l_tuned.json
 
 
 def candidates(nc: int, n_cu: int, max_waves: int = 8):
-    rtiles = (nc + 15) // 16
+    rem = nc % 16
+    rtiles = nc // 16 if (nc > 16 and 1 <= rem <= 2) else (nc + 15) // 16  # matrix-core row tiles
     out = []
     for rt, ctw in SHAPES:
         nrg = -(-rtiles // rt)

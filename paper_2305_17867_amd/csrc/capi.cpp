@@ -458,7 +458,12 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   }
   (void)hipGetLastError();
   {
-    const int rtiles = b->nc_pad / 16;
+    // rows past the last full 16-row tile: up to kMaxRem of them are contracted on the VALU
+    // instead of a mostly empty matrix-core tile (e.g. 81 = 5 x 16 + 1 at Laplace p = 8)
+    int nrem = b->nc % 16;
+    const bool valu_rows = b->nc > 16 && nrem >= 1 && nrem <= kMaxRem && env_int("FMM_M2L_VALU_ROWS", 1) != 0;
+    const int rtiles = valu_rows ? b->nc / 16 : b->nc_pad / 16;
+    if (!valu_rows) nrem = 0;
     const size_t rb = real_size(dtype);
     const size_t cap = (size_t)lds_max - 64;  // room for the kernel's static LDS
     struct Cand {
@@ -482,6 +487,8 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
       m2l_shape(c.sh, rb, cplx, ncg * ctw);
       c.sh.nrg = nrg;
       c.sh.nks = nks;
+      c.sh.rtiles = rtiles;
+      c.sh.nrem = nrem;
       c.nks = nks;
       if (nks > c.sh.k4p / (int)(16 / rb)) return false;  // every K range non-empty
       c.pf = m2l_prefetch_class(c.sh, cplx, ncg * ctw, waves);
@@ -657,11 +664,24 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     if (np > 1) split_items = (int64_t)items.size();
   }
   b->n_items = (int64_t)items.size();
-  // launch order: part-major, so that consecutive workgroups (which the hardware deals out
-  // round-robin over the XCDs) take the same part of different tiles; partial sums keep
-  // their slot tile_item0[tile] + part
+  // launch order: part-major within each group below; partial sums keep their slot
+  // tile_item0[tile] + part whatever the order
   std::stable_sort(items.begin(), items.end(),
                    [](const M2LItem& x, const M2LItem& y) { return x.part < y.part; });
+  if (n_tiles >= 8) {
+    // XCD-contiguous order: the tiles are cut into 8 contiguous ranges (neighbouring targets,
+    // hence shared sources and tables in one XCD's L2); position i of the launch takes the next
+    // item of range i % 8
+    std::vector<std::vector<M2LItem>> grp(8);
+    for (const M2LItem& it : items) grp[std::min<int64_t>(7, (int64_t)it.tile * 8 / n_tiles)].push_back(it);
+    std::vector<size_t> pos(8, 0);
+    std::vector<M2LItem> out;
+    out.reserve(items.size());
+    while (out.size() < items.size())
+      for (int x = 0; x < 8; ++x)
+        if (pos[x] < grp[x].size()) out.push_back(grp[x][pos[x]++]);
+    items.swap(out);
+  }
   // partials are indexed by item id; allocate for every item up to the last split tile
   b->scratch_bytes = split_items * NT * b->nc_pad * CW * (int64_t)sizeof(double);
 
@@ -883,7 +903,7 @@ int fmm_batch_info(fmm_batch b, int64_t* info, int32_t n_info) {
   const int64_t v[] = {b->n_pair,        b->n_tab,     b->n_tiles, b->n_entries,  b->n_items,
                        b->useful,        b->computed,  b->nc,      b->nc_pad,     b->scratch_bytes,
                        b->rows_per_wave, b->col_tiles, b->waves,   b->col_groups, b->lds_bytes,
-                       b->nbuf,          b->k_splits};
+                       b->nbuf,          b->k_splits,  b->shape.nrem};
   for (int k = 0; k < n_info && k < (int)(sizeof(v) / sizeof(v[0])); ++k) info[k] = v[k];
   return FMM_OK;
 }
@@ -912,6 +932,8 @@ static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local) {
   a.buf_elems = b->shape.buf_elems;
   a.nt = b->shape.nt;
   a.nrg = b->shape.nrg;
+  a.rtiles = b->shape.rtiles;
+  a.nrem = b->shape.nrem;
   a.nks = b->shape.nks;
   return a;
 }

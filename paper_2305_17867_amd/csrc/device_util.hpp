@@ -97,4 +97,38 @@ __host__ __device__ constexpr int full_index(int p, int x, int y, int z) {
   return s + r + y;
 }
 
+// (x, y) of entry k of a slab of M(p) with x + y <= n, rows x ascending, y fastest (the
+// order of full_index within one m_z).  Arithmetic only: no table lookups.
+__device__ inline void slab_decode(int n, int k, int& x, int& y) {
+  x = 0;
+  while (k > n - x) {
+    k -= n - x + 1;
+    ++x;
+  }
+  y = k;
+}
+
+// (x, y, z) of full index k of M(p): the inverse of full_index.
+__device__ inline void full_decode(int p, int k, int& x, int& y, int& z) {
+  z = 0;
+  while (z < p && k >= tri(p - z)) {
+    k -= tri(p - z);
+    ++z;
+  }
+  slab_decode(p - z, k, x, y);
+}
+
+// 1 / n!
+__device__ inline double inv_factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return 1.0 / f;
+}
+
+// Position of (x, y, z), |m| <= p, in the order of a nested Horner scheme that runs z from p
+// down, then x down, then y down: the slabs above z, the rows above x in slab z, then y.
+__host__ __device__ constexpr int horner_pos(int p, int x, int y, int z) {
+  return nfull(p - z - 1) + tri(p - z - x - 1) + (p - z - x - y);
+}
+
 }  // namespace fmm

@@ -74,6 +74,7 @@ struct M2LItem {
 // M2L launch limits: at most 8 wavefronts per workgroup; per-thread register prefetch of one
 // entry in two size classes (table values, source-tile values).
 constexpr int kM2LMaxThreads = 512;
+constexpr int kMaxRem = 2;  // rows past the last full 16-row tile that go to the VALU instead
 constexpr int kPrefT0 = 4, kPrefB0 = 12;
 constexpr int kPrefT1 = 8, kPrefB1 = 16;
 constexpr int kPrefT2 = 20, kPrefB2 = 24;
@@ -99,6 +100,8 @@ struct M2LArgs {
   int32_t tab_off;             // offset of the source tile in an LDS buffer (elements)
   int32_t buf_elems;           // elements of one LDS buffer (two buffers)
   int32_t nt;                  // targets per tile (16 x column tiles of the workgroup)
+  int32_t rtiles;              // matrix-core row tiles (16 rows each)
+  int32_t nrem;                // rows 16 rtiles .. 16 rtiles + nrem - 1 contracted on the VALU
   int32_t nrg;                 // row groups: wavefront w owns row group w % nrg
   int32_t nks;                 // K splits: wavefront w takes K range (w / nrg) / (nt / (16 CT))
 };

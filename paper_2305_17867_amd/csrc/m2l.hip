@@ -90,7 +90,8 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
   // registers, so that the row-group / K-range conditions of the inner loop are scalar branches
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nthr = blockDim.x;
-  const int rtiles = ncp >> 4;
+  const int rtiles = a.rtiles;  // matrix-core row tiles; rows 16 rtiles .. 16 rtiles + nrem - 1 on the VALU
+  const int nrem = a.nrem;
   // wavefront -> (row group, column group, K range): row tiles rg RT + r, column tiles
   // cg CT + c, K steps [s0, s1) of every lane group.  In a launch shared by several batches a
   // workgroup may have more wavefronts than this batch needs; those only help with the staging.
@@ -175,6 +176,22 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
     ib[r] = (i < nc) ? a.jbase[i] : 0;
   }
   const int q0 = kq * k4p;
+  // Rows beyond the last full 16-row tile (at most kMaxRem of them) are contracted on the
+  // vector ALU by the wavefronts of the last row group, in FP64: a mostly empty 16-row
+  // matrix-core tile would cost far more.  Each lane sums its own K steps and columns; the
+  // four lane groups are added at the end of the item.
+  const bool do_rem = active && nrem > 0 && rg == nrg - 1;
+  int ibr[kMaxRem];
+  double racc[kMaxRem][CT][CW];
+#pragma unroll
+  for (int j = 0; j < kMaxRem; ++j) {
+    const int i = rtiles * 16 + j;
+    ibr[j] = (j < nrem && i < nc) ? a.jbase[i] : 0;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int u = 0; u < CW; ++u) racc[j][c][u] = 0.0;
+  }
 
   if (it.e0 < it.e1) {
     load_idx(it.e0);
@@ -237,6 +254,27 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
               for (int c = 0; c < CT; ++c) part[r][c][0] = MF<R>::mma(ac[v][r][0], bc[c][0][v], part[r][c][0]);
             }
           }
+        if (do_rem) {
+#pragma unroll
+          for (int v = 0; v < VW; ++v)
+#pragma unroll
+            for (int j = 0; j < kMaxRem; ++j) {
+              if (j >= nrem) continue;
+              const double tr = (double)cur[ibr[j] + qc[v]];
+              if constexpr (CPLX) {
+                const double ti = (double)cur[ts + ibr[j] + qc[v]];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                  const double br = (double)bc[c][0][v], bi = (double)bc[c][1][v];
+                  racc[j][c][0] += tr * br - ti * bi;
+                  racc[j][c][1] += tr * bi + ti * br;
+                }
+              } else {
+#pragma unroll
+                for (int c = 0; c < CT; ++c) racc[j][c][0] += tr * (double)bc[c][0][v];
+              }
+            }
+        }
       }
     }
     if constexpr (ACC64) {
@@ -266,14 +304,27 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
           for (int v = 0; v < 4; ++v) acc[r][c][u][v] = (double)part[r][c][u][v];
   }
 
+  if (do_rem) {
+    // add the four lane groups (K ranges) of every column
+#pragma unroll
+    for (int j = 0; j < kMaxRem; ++j)
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int u = 0; u < CW; ++u) {
+          racc[j][c][u] += __shfl_xor(racc[j][c][u], 16, 64);
+          racc[j][c][u] += __shfl_xor(racc[j][c][u], 32, 64);
+        }
+  }
   // K splits: the partial sums of wavefronts kh = 1 .. nks-1 are added to those of kh = 0, in
   // that order, through LDS (the staging buffers are free now)
   if (nks > 1) {
-    constexpr int NACC = RT * CT * CW * 4;
+    constexpr int NACC = RT * CT * CW * 4 + kMaxRem * CT * CW;
     double* red = reinterpret_cast<double*>(smem_raw);
     const int slot = wave % (nrg * ncg);
     for (int k = 1; k < nks; ++k) {
       __syncthreads();
+      constexpr int RB = RT * CT * CW * 4;  // start of the remainder-row sums in a slot
       if (kh == k) {
 #pragma unroll
         for (int r = 0; r < RT; ++r)
@@ -284,6 +335,12 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
 #pragma unroll
               for (int v = 0; v < 4; ++v)
                 red[(slot * NACC + ((r * CT + c) * CW + u) * 4 + v) * 64 + lane] = acc[r][c][u][v];
+#pragma unroll
+        for (int j = 0; j < kMaxRem; ++j)
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int u = 0; u < CW; ++u) red[(slot * NACC + RB + (j * CT + c) * CW + u) * 64 + lane] = racc[j][c][u];
       }
       __syncthreads();
       if (kh == 0) {
@@ -296,6 +353,12 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
 #pragma unroll
               for (int v = 0; v < 4; ++v)
                 acc[r][c][u][v] += red[(slot * NACC + ((r * CT + c) * CW + u) * 4 + v) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < kMaxRem; ++j)
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int u = 0; u < CW; ++u) racc[j][c][u] += red[(slot * NACC + RB + (j * CT + c) * CW + u) * 64 + lane];
       }
     }
   }
@@ -311,6 +374,15 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
       const int t = tg[(cg * CT + c) * 16 + col];
       if (t < 0) continue;
       R* out = reinterpret_cast<R*>(a.local) + (int64_t)t * nc * CW;
+      if (do_rem && kq == 0) {
+#pragma unroll
+        for (int j = 0; j < kMaxRem; ++j) {
+          if (j >= nrem) continue;
+          const int i = rtiles * 16 + j;
+#pragma unroll
+          for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((double)out[i * CW + u] + racc[j][c][u]);
+        }
+      }
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
         const int rt = rg * RT + r;
@@ -342,6 +414,17 @@ __device__ __forceinline__ void m2l_item(const M2LArgs& a, const M2LItem it) {
         for (int u = 0; u < CW; ++u) mine[(((cg * CT + c) * 16 + col) * ncp + i) * CW + u] = acc[r][c][u][v];
       }
     }
+  if (writer && do_rem && kq == 0) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int j = 0; j < kMaxRem; ++j) {
+        if (j >= nrem) continue;
+        const int i = rtiles * 16 + j;
+#pragma unroll
+        for (int u = 0; u < CW; ++u) mine[(((cg * CT + c) * 16 + col) * ncp + i) * CW + u] = racc[j][c][u];
+      }
+  }
   __threadfence();
   __syncthreads();
   if (tid == 0) {
@@ -548,7 +631,8 @@ void m2l_shape(M2LArgs& a, size_t real_bytes, bool cplx, int ct_total) {
 size_t m2l_lds_bytes(const M2LArgs& a, size_t real_bytes, int nbuf, int rt, bool cplx) {
   const size_t stage = (size_t)nbuf * a.buf_elems * real_bytes + 4 * (size_t)a.k4p * sizeof(int);
   // K-split reduction: one FP64 accumulator set per (row group, column group) wavefront
-  const size_t red = a.nks > 1 ? (size_t)a.nrg * (a.nt / 16) * rt * (cplx ? 2 : 1) * 4 * 64 * sizeof(double) : 0;
+  const size_t red = a.nks > 1 ? (size_t)a.nrg * (a.nt / 16) * (cplx ? 2 : 1) * (4 * rt + kMaxRem) * 64 * sizeof(double)
+                               : 0;
   return stage > red ? stage : red;
 }
 

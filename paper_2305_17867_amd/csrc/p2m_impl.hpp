@@ -128,13 +128,10 @@ __device__ inline void run_chunks(const P2MArgs& a, int64_t lo, int64_t hi, cons
   }
 }
 
-template <int P>
-__device__ constexpr FullIdx<P> kFullIdx{};
-
 // In-LDS back substitution beta = M^T alpha over the recursion terms (gather form, levels
 // of m_z from P down to 0).  Values in double (complex interleaved).  Entry k of level z is
-// full index slab(z) + k; the recursion terms are unrolled, so nothing is indexed dynamically
-// in registers.
+// full index slab(z) + k, decoded arithmetically; the recursion terms are unrolled, so nothing
+// is indexed dynamically in registers.
 template <int P, bool CPLX>
 __device__ inline void compress_lds(double* al, const RecArgs& rec, int c, double h) {
   double cf[kMaxRecTerms];
@@ -148,7 +145,8 @@ __device__ inline void compress_lds(double* al, const RecArgs& rec, int c, doubl
     const int s0 = nfull(P) - nfull(P - z), cnt = tri(P - z);
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
       const int n = s0 + k;
-      const int x = kFullIdx<P>.x[n], y = kFullIdx<P>.y[n];
+      int x, y;
+      slab_decode(P - z, k, x, y);
       double sr = 0.0, si = 0.0;
 #pragma unroll
       for (int t = 0; t < kMaxRecTerms; ++t) {

@@ -221,7 +221,7 @@ class Batch:
 
     INFO = ("n_pair", "n_tables", "n_tiles", "n_entries", "n_items", "useful_columns",
             "computed_columns", "nc", "nc_pad", "scratch_bytes", "rows_per_wave", "col_tiles_per_wave",
-            "waves", "col_groups", "lds_bytes", "lds_buffers", "k_splits")
+            "waves", "col_groups", "lds_bytes", "lds_buffers", "k_splits", "valu_rows")
 
     def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None, adjoint=False,
                  fft=False):

@@ -145,7 +145,7 @@ def test_multi_validation(gpu_lib, mixed, monkeypatch):
     p64 = fmm.Plan(fmm.Desc(g["kernel"], g["p"], "f64", g["param"]), lh)
     b32 = p32.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=TUNING)
     b64 = p64.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=TUNING)
-    other = dict(TUNING, rows_per_wave=3)
+    other = dict(TUNING, col_tiles_per_wave=1)
     b32o = p32.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=other)
     adj = p32.prepare_adjoint(g["t"], g["s"], tr.ijk, tr.level, tuning=TUNING)
     for bad in ([b32, b64], [b32, b32o], [b32, adj], []):
