@@ -7,9 +7,9 @@
 // One wavefront per box (a workgroup of 64 lanes, so its barriers cost next to nothing).  The
 // decompressed coefficients live in LDS and are read as wave-wide broadcasts; every lane
 // evaluates kU targets at once with a nested Horner scheme, so that each coefficient read
-// feeds kU fused multiply-adds.  Index decoding (full index -> (x, y, z), Horner positions,
-// factorials) is arithmetic, so the prologue waits on no memory but the box's coefficients,
-// and the recursion terms are unrolled so that no per-lane array is indexed dynamically.
+// feeds kU fused multiply-adds.  The index decode (full index -> (x, y, z)) comes from
+// compile-time tables, and the recursion terms are unrolled so that no per-lane array is
+// indexed dynamically.
 #pragma once
 
 #include "../../include/fmm.h"
@@ -24,6 +24,40 @@ namespace detail_l2p {
 constexpr int kThreads = 64;  // one wavefront per box
 constexpr int kU = 4;         // targets per lane and pass
 constexpr int kWavesPerEU = 4;  // register budget: at most 128 per lane
+
+struct InvFact {
+  double v[FMM_MAX_ORDER + 1];
+  constexpr InvFact() : v() {
+    double f = 1.0;
+    for (int i = 0; i <= FMM_MAX_ORDER; ++i) {
+      if (i > 0) f *= i;
+      v[i] = 1.0 / f;
+    }
+  }
+};
+
+// (x, y, z) of every full index of M(P), and 1 / (x! y! z!)
+template <int P>
+struct FullDecode {
+  unsigned char x[nfull(P)], y[nfull(P)], z[nfull(P)];
+  double inv_fact[nfull(P)];
+  constexpr FullDecode() : x(), y(), z(), inv_fact() {
+    constexpr InvFact IF{};
+    int k = 0;
+    for (int mz = 0; mz <= P; ++mz)
+      for (int mx = 0; mx <= P - mz; ++mx)
+        for (int my = 0; my <= P - mz - mx; ++my) {
+          x[k] = (unsigned char)mx;
+          y[k] = (unsigned char)my;
+          z[k] = (unsigned char)mz;
+          inv_fact[k] = IF.v[mx] * IF.v[my] * IF.v[mz];
+          ++k;
+        }
+  }
+};
+
+template <int P>
+__device__ constexpr FullDecode<P> kDecode{};
 
 // Forward substitution L = M theta in LDS, levels m_z = c .. P (values in double, complex
 // interleaved).  Entry k of level z is full index slab(z) + k.
@@ -41,7 +75,7 @@ __device__ inline void decompress_lds(double* L, const RecArgs& rec, int c, doub
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
       const int m = s0 + k;
       int x, y;
-      slab_decode(P - z, k, x, y);
+      slab_decode(P - z, k, x, y);  // arithmetic: no memory wait on the level's critical path
       double sr = 0.0, si = 0.0;
 #pragma unroll
       for (int t = 0; t < kMaxRecTerms; ++t) {
@@ -65,8 +99,24 @@ __device__ inline void decompress_lds(double* L, const RecArgs& rec, int c, doub
   }
 }
 
+// Position of every full index of M(Q) in the order in which the nested Horner scheme below
+// consumes the coefficients (z from Q down, then x down, then y down).
+template <int Q>
+struct HornerOrder {
+  int pos[nfull(Q) > 0 ? nfull(Q) : 1];
+  constexpr HornerOrder() : pos() {
+    int k = 0;
+    for (int z = Q; z >= 0; --z)
+      for (int x = Q - z; x >= 0; --x)
+        for (int y = Q - z - x; y >= 0; --y) pos[full_index(Q, x, y, z)] = k++;
+  }
+};
+
+template <int Q>
+__device__ constexpr HornerOrder<Q> kHorner{};
+
 // out[j][u] = sum_{|m| <= Q} c_m,u X_j^m for kU points j at once (nested Horner: y innermost,
-// then x, then z), the coefficients C[W * k + u] stored in Horner order (horner_pos).  The row loops are
+// then x, then z), the coefficients C[W * k + u] stored in Horner order.  The row loops are
 // kept as loops so that the coefficients are read from LDS as they are consumed.
 template <int Q, int W, typename R>
 __device__ inline void horner_u(const R* C, const R (&X)[kU], const R (&Y)[kU], const R (&Z)[kU],
@@ -76,6 +126,14 @@ __device__ inline void horner_u(const R* C, const R (&X)[kU], const R (&Y)[kU], 
   for (int j = 0; j < kU; ++j)
 #pragma unroll
     for (int u = 0; u < W; ++u) pz[j][u] = R(0);
+  // the coefficients are consumed strictly in storage order, so the reads run two steps ahead
+  // of the products across row and slab boundaries (C holds two zero entries of padding)
+  R c0[W], c1[W];
+#pragma unroll
+  for (int u = 0; u < W; ++u) {
+    c0[u] = C[u];
+    c1[u] = C[W + u];
+  }
   int idx = 0;
 #pragma unroll 1
   for (int z = Q; z >= 0; --z) {
@@ -96,7 +154,9 @@ __device__ inline void horner_u(const R* C, const R (&X)[kU], const R (&Y)[kU], 
       for (int y = 0; y < n; ++y, ++idx) {
 #pragma unroll
         for (int u = 0; u < W; ++u) {
-          const R cv = C[idx * W + u];
+          const R cv = c0[u];
+          c0[u] = c1[u];
+          c1[u] = C[(idx + 2) * W + u];
 #pragma unroll
           for (int j = 0; j < kU; ++j) ry[j][u] = ry[j][u] * Y[j] + cv;
         }
@@ -123,8 +183,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   constexpr int NG = GRAD ? nfull(P - 1) : 0;
   constexpr int W = CPLX ? 2 : 1;
   __shared__ double Ld[NP * W];
-  __shared__ R Lc[NP * W];
-  __shared__ R Lg[3][(NG > 0 ? NG : 1) * W];
+  __shared__ R Lc[(NP + 2) * W];  // + 2 zero entries read ahead by horner_u
+  __shared__ R Lg[3][((NG > 0 ? NG : 1) + 2) * W];
   const int64_t b = blockIdx.x;
   int lev = a.level[b];
   lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
@@ -132,23 +192,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const int nc = a.nc;
   const R* loc = reinterpret_cast<const R*>(a.local) + b * (int64_t)nc * W;
   for (int k = threadIdx.x; k < nc * W; k += kThreads) Ld[k] = (double)loc[k];
+  if (threadIdx.x < 2 * W) {
+    Lc[NP * W + threadIdx.x] = R(0);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) Lg[ax][(NG > 0 ? NG : 1) * W + threadIdx.x] = R(0);
+  }
   __syncthreads();
   decompress_lds<P, CPLX>(Ld, a.rec, a.c, h);
   for (int k = threadIdx.x; k < NP; k += kThreads) {
-    int x, y, z;
-    full_decode(P, k, x, y, z);
-    const double f = inv_factorial(x) * inv_factorial(y) * inv_factorial(z);
-    const int hk = horner_pos(P, x, y, z);
+    const double f = kDecode<P>.inv_fact[k];
+    const int hk = kHorner<P>.pos[k];
 #pragma unroll
     for (int u = 0; u < W; ++u) Lc[hk * W + u] = (R)(Ld[k * W + u] * f);
     if constexpr (GRAD) {
       // d/dX_ax of L_m X^m / m!: the coefficient of X^(m - e_ax) is L_m / (m - e_ax)!
-      const int mm[3] = {x, y, z};
+      const int mm[3] = {kDecode<P>.x[k], kDecode<P>.y[k], kDecode<P>.z[k]};
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         if (mm[ax] == 0) continue;
         const int d0 = mm[0] - (ax == 0), d1 = mm[1] - (ax == 1), d2 = mm[2] - (ax == 2);
-        const int g = horner_pos(P - 1, d0, d1, d2);
+        const int g = kHorner<P - 1>.pos[full_index(P - 1, d0, d1, d2)];
         const double fg = f * mm[ax];
 #pragma unroll
         for (int u = 0; u < W; ++u) Lg[ax][g * W + u] = (R)(Ld[k * W + u] * fg);

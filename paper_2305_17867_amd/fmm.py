@@ -147,6 +147,27 @@ class Plan:
                                   _ptr(w), _ptr(out), _stream()), "fmm_p2m")
         return out
 
+    def bind_p2m(self, center, level, rng, src, w, out):
+        """A zero-argument callable that enqueues this P2M on the current stream.  The tensors
+        are checked and their pointers taken once here; the caller keeps them alive and
+        unmoved.  For loops that launch the same step many times."""
+        self.p2m(center, level, rng, src, w, out=out)  # validates the arguments
+        fn = _lib.load().fmm_p2m
+        args = (self._h, center.shape[0], _ptr(center), _ptr(level), _ptr(rng), src.shape[0], _ptr(src),
+                _ptr(w), _ptr(out))
+        return lambda: check(fn(*args, _stream()), "fmm_p2m")
+
+    def bind_l2p(self, center, level, rng, tgt, local, pot):
+        """Like bind_p2m, for L2P (the potentials keep accumulating on every call)."""
+        nb = self._boxes(center, level, rng)
+        n = tgt.shape[0]
+        _dev(tgt, self.desc.real_dtype, "tgt_xyz", (n, 3))
+        _dev(local, self.desc.value_dtype, "local", (nb, self.nc))
+        _dev(pot, self.desc.value_dtype, "potential", (n,))
+        fn = _lib.load().fmm_l2p
+        args = (self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(tgt), _ptr(local), _ptr(pot))
+        return lambda: check(fn(*args, _stream()), "fmm_l2p")
+
     def l2p(self, center, level, rng, tgt, local, pot) -> torch.Tensor:
         nb = self._boxes(center, level, rng)
         n = tgt.shape[0]
@@ -267,6 +288,18 @@ class Batch:
         else:
             check(_lib.load().fmm_m2l_batched(self._h, _ptr(mpole), _ptr(local), _stream()), "fmm_m2l_batched")
         return local
+
+    def bind(self, mpole: torch.Tensor, local: torch.Tensor):
+        """A zero-argument callable that enqueues this batch on the current stream with the
+        given (checked once) tensors; see Plan.bind_p2m."""
+        d = self.plan.desc
+        _dev(mpole, d.value_dtype, "input", (self.n_box, self.plan.nc))
+        _dev(local, d.value_dtype, "output", (self.n_box, self.plan.nc))
+        lib = _lib.load()
+        fn, name = ((lib.fmm_m2l_batched_adjoint, "fmm_m2l_batched_adjoint") if self.adjoint
+                    else (lib.fmm_m2l_batched, "fmm_m2l_batched"))
+        h, a, b = self._h, _ptr(mpole), _ptr(local)
+        return lambda: check(fn(h, a, b, _stream()), name)
 
     def close(self):
         if self._h:

@@ -288,3 +288,33 @@ def test_end_to_end_two_box_laplace_p4(gpu_lib):
     exact = K.direct_sum("laplace", 0.0, src, w, tgt)
     e = rel(got, exact)
     assert 1e-5 < e < 1e-3  # the truncation error of p = 4, not roundoff
+
+
+def test_bound_launches_match_calls(gpu_lib, m2l_tree):
+    """Plan.bind_p2m / bind_l2p and Batch.bind enqueue the same work as the plain calls."""
+    fmm = gpu_lib
+    tr = m2l_tree
+    d = fmm.Desc("laplace", 6, "f64")
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    boxes = tr.boxes_at(3)
+    cen, lev, rng = dev(tr.center[boxes], torch.float64), dev(tr.level[boxes], torch.int32), dev(tr.pt_range[boxes], torch.int64)
+    pts = dev(tr.points, torch.float64)
+    w = dev(W.normal_weights(tr.points.shape[0], 5), torch.float64)
+    a = plan.p2m(cen, lev, rng, pts, w)
+    b = torch.zeros_like(a)
+    plan.bind_p2m(cen, lev, rng, pts, w, b)()
+    assert torch.equal(a, b)
+    t, s = W.interaction_pairs(tr, [3])
+    batch = plan.prepare(t, s, tr.ijk, tr.level)
+    mp = torch.randn((tr.n_box, d.nc), dtype=torch.float64, device="cuda")
+    l1, l2 = torch.zeros_like(mp), torch.zeros_like(mp)
+    batch(mp, l1)
+    batch.bind(mp, l2)()
+    assert torch.equal(l1, l2)
+    th = torch.randn((len(boxes), d.nc), dtype=torch.float64, device="cuda")
+    p1 = torch.zeros(tr.points.shape[0], dtype=torch.float64, device="cuda")
+    p2 = torch.zeros_like(p1)
+    plan.l2p(cen, lev, rng, pts, th, p1)
+    plan.bind_l2p(cen, lev, rng, pts, th, p2)()
+    assert torch.equal(p1, p2)
