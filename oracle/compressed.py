@@ -98,15 +98,21 @@ def m2l_scaled(kernel, param, p, d, beta_s, t, table: dict | None = None):
 
 # ----------------------------------------------------------------------------- FFT form
 
+def fft_grid(kernel: str, param: float, p: int) -> tuple:
+    """Sizes (2 M_x + 1, 2 M_y + 1, 2 M_z + 1) of the circulant embedding of the convolution
+    (eq. convolution_m2l and the complexity argument after it), M the largest index of J
+    along each axis."""
+    J = kept(kernel, param, p)
+    return tuple(2 * max(m[k] for m in J) + 1 for k in range(3))
+
+
 def m2l_fft(kernel: str, param: float, p: int, d, beta, table: dict | None = None) -> np.ndarray:
     """eq. convolution_m2l evaluated by a circulant embedding and numpy FFTs."""
     if table is None:
         table = slab_table(kernel, param, p, d)
     J = kept(kernel, param, p)
-    Mx = max(m[0] for m in J)
-    My = max(m[1] for m in J)
-    Mz = max(m[2] for m in J)
-    L = (2 * Mx + 1, 2 * My + 1, 2 * Mz + 1)
+    L = fft_grid(kernel, param, p)
+    Mx, My, Mz = [(n - 1) // 2 for n in L]
     cplx = np.iscomplexobj(beta) or any(np.iscomplexobj(v) for v in table.values())
     g = np.zeros(L, dtype=np.complex128)
     for m, v in table.items():
