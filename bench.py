@@ -270,6 +270,51 @@ def mixed_batch(torch, fmm, reps=10):
     return out
 
 
+def plummer_helmholtz(torch, fmm, dt, reps=5):
+    """Helmholtz p = 12 far field of 2^21 Plummer points (adaptive octree <= 64 per leaf,
+    k = 1 / largest leaf side): every level's List-2 pairs in one prepared batch, one launch."""
+    import workloads as W
+    tr = W.adaptive_tree(W.plummer_points(1 << 21, 3, 0.1), 64)
+    leaf_side = max(tr.box_size(int(tr.level[b])) for b in np.nonzero(tr.is_leaf)[0])
+    t, s = W.interaction_pairs(tr, list(range(2, tr.n_levels)))
+    d = fmm.Desc("helmholtz", 12, dt, 1.0 / leaf_side)
+    plan = fmm.Plan(d, [tr.box_size(l) for l in range(tr.n_levels)])
+    batch = plan.prepare(t, s, tr.ijk, tr.level)
+    mp = torch.randn((tr.n_box, d.nc), dtype=d.value_dtype, device="cuda")
+    loc = torch.zeros_like(mp)
+    sec = time_kernel(torch, lambda: batch(mp, loc), reps)
+    flops = 8.0 * d.nc ** 2 * len(t)
+    return {"workload": "plummer 2097152 pts, adaptive <=64, helmholtz p12 k*h_leaf=1, all levels one launch",
+            "dtype": dt, "pairs": int(len(t)), "m2l_ms": sec * 1e3, "pairs_per_s": len(t) / sec,
+            "tflops": flops / sec / 1e12, "frac": flops / sec / PEAK["f64" if dt == "c128" else "f32"]}
+
+
+def gradient_pass(torch, dt, reps=3):
+    """Laplace p = 10 far field of 2^21 sources at 2^21 targets (depth-4 octrees) and its
+    adjoint: forward and forward + backward times."""
+    import workloads as W
+    from paper_2305_17867_amd.farfield import FarField
+    n = 1 << 21
+    ts = W.uniform_tree(W.uniform_points(n, 5), 4)
+    tt = W.uniform_tree(W.uniform_points(n, 6), 4)
+    ff = FarField("laplace", 10, dt, ts, tt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    w = torch.as_tensor(W.normal_weights(n, 7), dtype=tdt, device="cuda").requires_grad_(True)
+    S = torch.as_tensor(ts.points, dtype=tdt, device="cuda").requires_grad_(True)
+    T = torch.as_tensor(tt.points, dtype=tdt, device="cuda").requires_grad_(True)
+    c = torch.as_tensor(W.normal_weights(n, 8), dtype=tdt, device="cuda")
+
+    def fwd():
+        with torch.no_grad():
+            ff.apply(w, S, T)
+
+    def fwd_bwd():
+        (ff.apply(w, S, T) * c).sum().backward()
+
+    return {"workload": "uniform 2^21 sources + 2^21 targets, depth 4, laplace p10, far field", "dtype": dt,
+            "forward_ms": time_kernel(torch, fwd, reps) * 1e3, "forward_backward_ms": time_kernel(torch, fwd_bwd, reps) * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +324,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default=None, help="run one variant, e.g. f64:8 (for profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the FFT path and the mixed workload")
+    ap.add_argument("--extended", action="store_true",
+                    help="also time the Plummer Helmholtz launch and the far-field gradient pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, to calibrate HBM counters")
     args = ap.parse_args()
@@ -349,6 +396,11 @@ def main():
     if not (args.only or args.no_extras):
         log("mixed workload (persistent, graph-captured launch)")
         out["mixed_batch"] = mixed_batch(torch, fmm)
+    if args.extended:
+        log("Plummer Helmholtz, one launch over all levels")
+        out["plummer_helmholtz"] = [plummer_helmholtz(torch, fmm, dt) for dt in ("c128", "c64")]
+        log("far-field gradient pass")
+        out["gradient"] = [gradient_pass(torch, dt) for dt in ("f32", "f64")]
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

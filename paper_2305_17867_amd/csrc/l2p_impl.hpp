@@ -70,12 +70,25 @@ __device__ inline void decompress_lds(double* L, const RecArgs& rec, int c, doub
     for (int e = 0; e < rec.hpow[t]; ++e) f *= h;
     cf[t] = f;
   }
-  for (int z = c; z <= P; ++z) {
-    const int s0 = nfull(P) - nfull(P - z), cnt = tri(P - z);
+  // a level reads only levels at least dmin below it, so dmin consecutive levels are
+  // independent and share one barrier
+  int dmin = P + 1;
+#pragma unroll
+  for (int t = 0; t < kMaxRecTerms; ++t)
+    if (t < rec.n) dmin = min(dmin, -rec.dz[t]);
+  dmin = max(dmin, 1);
+  for (int z0 = c; z0 <= P; z0 += dmin) {
+    const int z1 = min(P, z0 + dmin - 1);
+    const int s0 = nfull(P) - nfull(P - z0), cnt = nfull(P - z0) - nfull(P - z1 - 1);
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
       const int m = s0 + k;
+      int z = z0, kk = k;
+      while (kk >= tri(P - z)) {
+        kk -= tri(P - z);
+        ++z;
+      }
       int x, y;
-      slab_decode(P - z, k, x, y);  // arithmetic: no memory wait on the level's critical path
+      slab_decode(P - z, kk, x, y);  // arithmetic: no memory wait on the level's critical path
       double sr = 0.0, si = 0.0;
 #pragma unroll
       for (int t = 0; t < kMaxRecTerms; ++t) {

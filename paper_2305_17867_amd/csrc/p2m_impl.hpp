@@ -141,12 +141,25 @@ __device__ inline void compress_lds(double* al, const RecArgs& rec, int c, doubl
     for (int e = 0; e < rec.hpow[t]; ++e) f *= h;
     cf[t] = f;
   }
-  for (int z = P; z >= 0; --z) {
-    const int s0 = nfull(P) - nfull(P - z), cnt = tri(P - z);
+  // a level gathers only from levels at least dmin above it, so dmin consecutive levels are
+  // independent and share one barrier
+  int dmin = P + 1;
+#pragma unroll
+  for (int t = 0; t < kMaxRecTerms; ++t)
+    if (t < rec.n) dmin = min(dmin, -rec.dz[t]);
+  dmin = max(dmin, 1);
+  for (int z1 = P; z1 >= 0; z1 -= dmin) {
+    const int z0 = max(0, z1 - dmin + 1);  // levels z0 .. z1
+    const int s0 = nfull(P) - nfull(P - z0), cnt = nfull(P - z0) - nfull(P - z1 - 1);
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
       const int n = s0 + k;
+      int z = z0, kk = k;
+      while (kk >= tri(P - z)) {
+        kk -= tri(P - z);
+        ++z;
+      }
       int x, y;
-      slab_decode(P - z, k, x, y);
+      slab_decode(P - z, kk, x, y);
       double sr = 0.0, si = 0.0;
 #pragma unroll
       for (int t = 0; t < kMaxRecTerms; ++t) {
