@@ -123,7 +123,10 @@ void fmm_plan_destroy(fmm_plan plan);
  * box_center[b], h = level_box_size[box_level[b]].
  *   box_center [n_box][3] f64; box_level [n_box] i32; pt_range [n_box][2] i64
  *   src_xyz    [n_src][3] real dtype; weight [n_src] dtype
- *   mpole      [n_box][Nc] dtype, OVERWRITTEN */
+ *   mpole      [n_box][Nc] dtype, OVERWRITTEN
+ * Boxes with many points are spread over several workgroups whose results go through a
+ * buffer owned by the plan and are added in a fixed order, so P2M calls (and fmm_l2p_adjoint
+ * calls) of one plan must not run at the same time on different streams. */
 int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
             const int64_t* pt_range, int64_t n_src, const void* src_xyz, const void* weight,
             void* mpole, void* stream);

@@ -25,8 +25,14 @@ struct fmm_plan_s {
   double* d_level_h = nullptr;
   int32_t* d_jbase = nullptr;
   int32_t* d_jxyz = nullptr;
+  double* d_p2m_part = nullptr;  // per-chunk P2M results of boxes spread over several workgroups
   bool alive = true;
 };
+
+namespace {
+constexpr size_t kP2MPartBytes = 16u << 20;  // capacity of fmm_plan_s::d_p2m_part
+constexpr int64_t kP2MChunkPoints = 2048;     // points per P2M workgroup for large boxes
+}  // namespace
 
 struct fmm_multi_s {
   std::vector<fmm_batch> batches;
@@ -191,7 +197,9 @@ int fmm_plan_create(const fmm_desc* desc, int32_t n_levels, const double* level_
     jx[k] = pl->J[k].x | (pl->J[k].y << 8) | (pl->J[k].z << 16);
   }
   if ((st = dev_upload(&pl->d_level_h, pl->h)) || (st = dev_upload(&pl->d_jbase, jb)) ||
-      (st = dev_upload(&pl->d_jxyz, jx))) {
+      (st = dev_upload(&pl->d_jxyz, jx)) ||
+      (hipMalloc((void**)&pl->d_p2m_part, kP2MPartBytes) != hipSuccess &&
+       (st = fail(FMM_ENOMEM, "hipMalloc of the P2M chunk buffer failed")))) {
     fmm_plan_destroy(pl);
     return st;
   }
@@ -205,6 +213,7 @@ void fmm_plan_destroy(fmm_plan plan) {
   dev_free(plan->d_level_h);
   dev_free(plan->d_jbase);
   dev_free(plan->d_jxyz);
+  dev_free(plan->d_p2m_part);
   delete plan;
 }
 
@@ -219,6 +228,20 @@ static int check_box_args(fmm_plan plan, int64_t n_box, const double* center, co
   FMM_REQUIRE(v1 && v2, FMM_EINVAL, "coefficient / value arrays must not be NULL");
   FMM_REQUIRE(n_pts == 0 || xyz, FMM_EINVAL, "point array is NULL");
   return FMM_OK;
+}
+
+// Workgroups per box for P2M: boxes with many points (coarse levels) are split into chunks of
+// about kP2MChunkPoints points whose results are added in chunk order, as far as the plan's
+// chunk buffer allows.
+static void set_p2m_chunks(fmm_plan plan, P2MArgs& a) {
+  a.ny = 1;
+  a.part = plan->d_p2m_part;
+  if (a.n_box <= 0 || !plan->d_p2m_part) return;
+  const int64_t per_box = (a.n_pts + a.n_box - 1) / a.n_box;
+  int64_t ny = (per_box + kP2MChunkPoints - 1) / kP2MChunkPoints;
+  const int64_t width = (int64_t)plan->nc * (dtype_complex(plan->desc.dtype) ? 2 : 1);
+  ny = std::min<int64_t>(ny, (int64_t)(kP2MPartBytes / sizeof(double)) / (a.n_box * width));
+  a.ny = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ny, 1024));
 }
 
 int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
@@ -242,6 +265,7 @@ int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
   a.c = plan->c;
   a.rec = plan->rec;
   a.xsign = 1.0;
+  set_p2m_chunks(plan, a);
   return launch_p2m(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
 }
 
@@ -295,6 +319,7 @@ int fmm_l2p_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, cons
   m.c = plan->c;
   m.rec = plan->rec;
   m.xsign = -1.0;
+  set_p2m_chunks(plan, m);
   st = launch_p2m(m, plan->p, plan->desc.dtype, (hipStream_t)stream);
   if (st || !tgt_xyz_grad) return st;
   // d L / d x = g(x) grad phi(x)

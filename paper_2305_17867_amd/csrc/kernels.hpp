@@ -33,6 +33,8 @@ struct P2MArgs {
   int32_t c;
   RecArgs rec;
   double xsign;             // X = xsign (c - y) / h  (+1: multipole moments; -1: target moments)
+  int32_t ny;               // workgroups per box (contiguous point chunks); > 1 needs part
+  double* part;             // [n_box][ny][Nc] (x2 complex) FP64 per-chunk results, summed in chunk order
 };
 
 struct L2PArgs {

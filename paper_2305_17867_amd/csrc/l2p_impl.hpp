@@ -17,6 +17,8 @@
 #include "device_util.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace fmm {
 
 namespace detail_l2p {
@@ -199,6 +201,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   __shared__ R Lc[(NP + 2) * W];  // + 2 zero entries read ahead by horner_u
   __shared__ R Lg[3][((NG > 0 ? NG : 1) + 2) * W];
   const int64_t b = blockIdx.x;
+  // points of the box: workgroup y of the box takes chunks y, y + gridDim.y, ... of kThreads kU
+  // targets, so that large boxes (coarse levels) are spread over several workgroups
+  int64_t lo = a.range[2 * b], hi = a.range[2 * b + 1];
+  lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
+  hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
+  if (lo + (int64_t)blockIdx.y * kThreads * kU >= hi) return;  // uniform: no points for this workgroup
   int lev = a.level[b];
   lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
   const double h = a.level_h[lev];
@@ -233,12 +241,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   }
   __syncthreads();
   const double cen[3] = {a.center[3 * b], a.center[3 * b + 1], a.center[3 * b + 2]};
-  int64_t lo = a.range[2 * b], hi = a.range[2 * b + 1];
-  lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
-  hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
   const R* xyz = reinterpret_cast<const R*>(a.xyz);
   const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)(a.xsign / h);
-  for (int64_t s0 = lo + threadIdx.x; s0 < hi; s0 += kThreads * kU) {
+  for (int64_t s0 = lo + (int64_t)blockIdx.y * kThreads * kU + threadIdx.x; s0 < hi;
+       s0 += (int64_t)gridDim.y * kThreads * kU) {
     R X[kU], Y[kU], Z[kU];
 #pragma unroll
     for (int j = 0; j < kU; ++j) {
@@ -282,7 +288,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
 
 template <int P>
 int launch_l2p_p(const L2PArgs& a, int dtype, hipStream_t s) {
-  dim3 g((unsigned)a.n_box), t(kThreads);
+  // workgroups per box: enough that the average box gets one per kThreads kU targets
+  const int64_t per_box = a.n_box > 0 ? (a.n_pts + a.n_box - 1) / a.n_box : 1;
+  const int64_t ny = std::max<int64_t>(1, std::min<int64_t>(1024, (per_box + kThreads * kU - 1) / (kThreads * kU)));
+  dim3 g((unsigned)a.n_box, (unsigned)ny), t(kThreads);
   const bool grad = a.grad != nullptr;
   switch (dtype) {
     case FMM_F64:

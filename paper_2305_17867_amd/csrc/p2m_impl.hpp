@@ -199,6 +199,12 @@ __global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
   int64_t lo = a.range[2 * b], hi = a.range[2 * b + 1];
   lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
   hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
+  if (gridDim.y > 1) {  // chunk blockIdx.y of the box's points (compression is linear)
+    const int64_t len = (hi - lo + gridDim.y - 1) / gridDim.y;
+    const int64_t c0 = lo + (int64_t)blockIdx.y * len;
+    hi = c0 + len < hi ? c0 + len : hi;
+    lo = c0 < hi ? c0 : hi;
+  }
   constexpr int QMAX = CPLX ? 16 : 32;
   constexpr int NCH = Chunks<P, R, CPLX, QMAX>::N;
   run_chunks<P, R, CPLX, 0, NCH>(a, lo, hi, cen, a.xsign / h, wave, lane, alpha);
@@ -206,6 +212,12 @@ __global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
   compress_lds<P, CPLX>(alpha, a.rec, a.c, h);
   // the kept set is the prefix [0, nc) of the full order
   const int nc = a.nc;
+  if (gridDim.y > 1) {
+    constexpr int W = CPLX ? 2 : 1;
+    double* part = a.part + (b * gridDim.y + blockIdx.y) * (int64_t)nc * W;
+    for (int k = threadIdx.x; k < W * nc; k += blockDim.x) part[k] = alpha[k];
+    return;
+  }
   if constexpr (CPLX) {
     R* out = reinterpret_cast<R*>(a.out) + b * (int64_t)nc * 2;
     for (int k = threadIdx.x; k < 2 * nc; k += blockDim.x) out[k] = (R)alpha[k];
@@ -217,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
 
 template <int P>
 int launch_p2m_p(const P2MArgs& a, int dtype, hipStream_t s) {
-  dim3 g((unsigned)a.n_box), t(kThreads);
+  dim3 g((unsigned)a.n_box, (unsigned)(a.ny > 1 ? a.ny : 1)), t(kThreads);
   switch (dtype) {
     case FMM_F64: hipLaunchKernelGGL((p2m_kernel<P, double, false>), g, t, 0, s, a); break;
     case FMM_F32: hipLaunchKernelGGL((p2m_kernel<P, float, false>), g, t, 0, s, a); break;

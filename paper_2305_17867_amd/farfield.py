@@ -53,9 +53,11 @@ class FarField:
         d = self.desc
         nc = self.plan.nc
         mpole = torch.zeros((self.n_box, nc), dtype=d.value_dtype, device=w.device)
-        lo, hi = self.box_lo, self.box_hi
-        self.plan.p2m(self._sl(self.center), self._sl(self.level), self._sl(self.src_rng), src, w,
-                      out=mpole[lo:hi])
+        # one call per level: the boxes of a level have similar point counts, so the large boxes
+        # of coarse levels are spread over several workgroups
+        for l in self.levels:
+            a, b = self.level_boxes[l]
+            self.plan.p2m(self.center[a:b], self.level[a:b], self.src_rng[a:b], src, w, out=mpole[a:b])
         local = torch.zeros_like(mpole)
         self.batch(mpole, local)
         pot = torch.zeros(tgt.shape[0], dtype=d.value_dtype, device=w.device)

@@ -318,3 +318,29 @@ def test_bound_launches_match_calls(gpu_lib, m2l_tree):
     plan.l2p(cen, lev, rng, pts, th, p1)
     plan.bind_l2p(cen, lev, rng, pts, th, p2)()
     assert torch.equal(p1, p2)
+
+
+@pytest.mark.parametrize("kernel,single", [("laplace", False), ("helmholtz", False), ("yukawa", True)])
+def test_p2m_large_boxes_split_over_workgroups(gpu_lib, kernel, single):
+    """Boxes with tens of thousands of points are spread over several workgroups whose results
+    are added in chunk order; the multipoles still match the oracle."""
+    fmm = gpu_lib
+    pts = W.uniform_points(200_000, 12)
+    tr = W.uniform_tree(pts, 2)
+    p = 8
+    d = desc_for(fmm, kernel, p, single)
+    param = CASES[kernel]
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    boxes = tr.boxes_at(1)  # 8 boxes of ~25,000 points
+    w = W.normal_weights(tr.points.shape[0], 13, complex_=kernel == "helmholtz")
+    got = host(plan.p2m(dev(tr.center[boxes], torch.float64), dev(tr.level[boxes], torch.int32),
+                        dev(tr.pt_range[boxes], torch.int64), dev(tr.points, d.real_dtype), dev(w, d.value_dtype)))
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    ref = []
+    for b in boxes[:3]:
+        lo, hi = tr.pt_range[b]
+        beta = Z.p2m(kernel, param, p, tr.center[b], tr.points[lo:hi], w[lo:hi])
+        ref.append(Z.scale_multipole(kernel, param, p, beta, 1.0 / lh[1])[perm])
+    tol = 2e-6 if single else 1e-12
+    assert rel(got[:3], np.array(ref)) < tol, rel(got[:3], np.array(ref))
