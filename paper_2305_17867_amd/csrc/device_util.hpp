@@ -62,26 +62,80 @@ __device__ inline R pick_bits(bool c, R a, R b) {
   }
 }
 
-// Reduce-scatter of the 2^M values v[] over the 64 lanes of a wavefront by halving
-// exchanges: after the call, every lane holds the wave-wide sum of v[lane >> (6 - M)].
-// Uses 2^M - 1 shuffles for the halving steps plus (6 - M) for the remaining ones.
-template <int M, typename R>
-__device__ inline R wave_reduce_scatter(R (&v)[1 << M], int lane) {
+// Wavefront exchanges used by the reduce-scatter below: the value of the lane l ^ mask for
+// mask = 15, 7, 2, 1 (lane moves within rows of 16 lanes: row mirror, half-row mirror, quad
+// permutations), 16 (swizzle within 32 lanes) and 32 (LDS permute).
+constexpr int kRsMasks[6] = {15, 7, 2, 1, 16, 32};
+constexpr int kRsUpBit[6] = {3, 2, 1, 0, 4, 5};  // the lane bit that tells the two partners apart
+
+template <int MASK>
+__device__ inline int xchg32(int v) {
+  if constexpr (MASK == 15) return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);      // row_mirror
+  else if constexpr (MASK == 7) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  else if constexpr (MASK == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  else if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  else if constexpr (MASK == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);             // xor 16 in 32 lanes
+  else return __shfl_xor(v, 32, 64);
+}
+
+template <int MASK, typename R>
+__device__ inline R xchg(R v) {
+  if constexpr (sizeof(R) == 8) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)xchg32<MASK>((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)xchg32<MASK>((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(R, ((uint64_t)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(R, xchg32<MASK>(__builtin_bit_cast(int, v)));
+  }
+}
+
+// Reduce-scatter of the 2^M values v[] over the 64 lanes of a wavefront by halving exchanges,
+// the stages with the most values first on the cheapest exchanges (lane moves within rows).
+// Stage i pairs lane l with l ^ kRsMasks[i]; the masks are independent over GF(2), so after
+// all six stages every lane holds a sum over all 64 lanes.  The lane keeps the upper half when
+// its bit kRsUpBit[i] is set.  Afterwards lane l holds the wave-wide sum of v[rs_index<M>(l)],
+// and rs_owner<M>(l) marks one lane per index.
+template <int M>
+__device__ inline int rs_index(int lane) {
+  int k = 0;
 #pragma unroll
-  for (int step = 0; step < M; ++step) {
-    const int L = (1 << M) >> step;
-    const int s = 32 >> step;
-    const bool up = (lane & s) != 0;
+  for (int i = 0; i < M; ++i) k |= ((lane >> kRsUpBit[i]) & 1) << (M - 1 - i);
+  return k;
+}
+template <int M>
+__device__ inline bool rs_owner(int lane) {
+  int used = 0;
+#pragma unroll
+  for (int i = 0; i < M; ++i) used |= 1 << kRsUpBit[i];
+  return (lane & (63 & ~used)) == 0;
+}
+
+template <int M, int I, typename R>
+__device__ inline void rs_stage(R (&v)[1 << M], int lane) {
+  if constexpr (I < M) {
+    constexpr int L = (1 << M) >> I;
+    const bool up = ((lane >> kRsUpBit[I]) & 1) != 0;
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) {
       const R lo = v[k], hi = v[L / 2 + k];
-      v[k] = pick_bits(up, hi, lo) + shfl_xor_d(pick_bits(up, lo, hi), s);
+      v[k] = pick_bits(up, hi, lo) + xchg<kRsMasks[I]>(pick_bits(up, lo, hi));
     }
+    rs_stage<M, I + 1, R>(v, lane);
   }
-  R r = v[0];
-#pragma unroll
-  for (int s = (32 >> M); s >= 1; s >>= 1) r += shfl_xor_d(r, s);
-  return r;
+}
+
+template <int I, typename R>
+__device__ inline R rs_allreduce(R r) {
+  if constexpr (I < 6) return rs_allreduce<I + 1, R>(r + xchg<kRsMasks[I]>(r));
+  else return r;
+}
+
+template <int M, typename R>
+__device__ inline R wave_reduce_scatter(R (&v)[1 << M], int lane) {
+  static_assert(M >= 0 && M <= 5, "at most 32 values per lane");
+  rs_stage<M, 0, R>(v, lane);
+  return rs_allreduce<M, R>(v[0]);
 }
 
 __host__ __device__ constexpr int tri(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) / 2; }

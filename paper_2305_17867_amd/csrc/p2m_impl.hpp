@@ -104,12 +104,11 @@ __device__ inline void run_chunk(const P2MArgs& a, int64_t lo, int64_t hi, const
     }
     accumulate_chunk<P, Q0, QN, C::QP, R, CPLX>(acc, px, py, pz, wr, wi);
   }
-  constexpr int SHIFT = 6 - C::M;
   R re = wave_reduce_scatter<C::M, R>(acc[0], lane);
   R im = R(0);
   if constexpr (CPLX) im = wave_reduce_scatter<C::M, R>(acc[1], lane);
-  const int k = lane >> SHIFT;
-  if ((lane & ((1 << SHIFT) - 1)) == 0 && k < QN) {
+  const int k = rs_index<C::M>(lane);
+  if (rs_owner<C::M>(lane) && k < QN) {
     if constexpr (CPLX) {
       alpha[2 * (Q0 + k)] = (double)re;
       alpha[2 * (Q0 + k) + 1] = (double)im;
