@@ -212,6 +212,9 @@ def test_m2l_k_split(gpu_lib, m2l_tree, kernel, p, single, shape, nks, items):
     try:
         batch = plan.prepare(t, s, tr.ijk, tr.level, tuning=tun)
     except fmm._lib.FmmError as e:
+        # only a shape that is not instantiated (prefetch classes) or exceeds the LDS is skipped
+        if e.status != fmm._lib.FMM_EUNSUPPORTED:
+            raise
         pytest.skip(f"shape does not fit: {e}")
     assert batch.info()["k_splits"] == nks
     nc = d.nc
