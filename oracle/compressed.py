@@ -5,6 +5,10 @@
         kept in derivative form: the 1/i! of the local coefficient is applied at
         evaluation, as the stored local of eq. stored_local_coeffs carries none)
   L2P   phi(x) = sum_i [M theta]_i / i! (x - c)^i         (eq. compressed-local-form)
+  M2M   psi = M^T T E beta                                (eq. define_psi: embed with
+        zeros at the indices not kept, translate uncompressed, compress again)
+  L2L   theta' = [T_L M theta]_j                          (Sec. 4.2: decompress, translate
+        with eq. l2l-expr, keep the entries of j)
 
 Scaled form (Sec. 4.1.1) with parameter t:
   beta~_q = beta_q t^|q|,  table~_m = G^(m) / t^|m|,  theta~_i = theta_i / t^|i|,
@@ -25,7 +29,7 @@ import numpy as np
 from .compression import decompression_matrix, kept_indices, position_map
 from .kernels import deriv_table_mp, deriv_table_rec, pde_order, slab_indices
 from .multiindex import graded_order, madd, mfact, morder, mpow
-from .taylor import l2p_full, p2m_full
+from .taylor import l2l_full, l2p_full, m2m_full, p2m_full
 
 
 def kept(kernel: str, param: float, p: int) -> list:
@@ -66,6 +70,29 @@ def l2p(kernel: str, param: float, p: int, center, theta, tgt) -> np.ndarray:
     return l2p_full(p, center, local_full(kernel, param, p, theta), tgt)
 
 
+def embed(kernel: str, param: float, p: int, beta) -> np.ndarray:
+    """E beta: the kept coefficients placed in the graded order of M(p), zero elsewhere
+    (the embedding operator E of Sec. 4.3)."""
+    beta = np.asarray(beta)
+    out = np.zeros(len(graded_order(p)), dtype=beta.dtype)
+    out[position_map(p, kept(kernel, param, p))] = beta
+    return out
+
+
+def m2m(kernel: str, param: float, p: int, h, beta) -> np.ndarray:
+    """Compressed multipole translation by h = c_new - c_old: psi = M^T T E beta
+    (eq. define_psi)."""
+    M, _, _ = decompression_matrix(kernel, param, p)
+    return M.T @ m2m_full(p, h, embed(kernel, param, p, beta))
+
+
+def l2l(kernel: str, param: float, p: int, h, theta) -> np.ndarray:
+    """Compressed local translation by h = c_new - c_old: decompress, translate
+    (eq. l2l-expr), keep the entries of j (Sec. 4.2)."""
+    full = l2l_full(p, h, local_full(kernel, param, p, theta))
+    return full[position_map(p, kept(kernel, param, p))]
+
+
 # ----------------------------------------------------------------------------- scaled form
 
 def scale_multipole(kernel, param, p, beta, t):
@@ -94,6 +121,18 @@ def m2l_scaled(kernel, param, p, d, beta_s, t, table: dict | None = None):
         table = slab_table(kernel, param, p, d)
     tt = {m: v / float(t) ** morder(m) for m, v in table.items()}
     return m2l(kernel, param, p, d, beta_s, tt)
+
+
+def m2m_scaled(kernel, param, p, h, beta_s, t_old, t_new):
+    """m2m on scaled coefficients: beta~ at parameter t_old in, psi~ at t_new out."""
+    beta = unscale_multipole(kernel, param, p, beta_s, t_old)
+    return scale_multipole(kernel, param, p, m2m(kernel, param, p, h, beta), t_new)
+
+
+def l2l_scaled(kernel, param, p, h, theta_s, t_old, t_new):
+    """l2l on scaled coefficients: theta~ at parameter t_old in, at t_new out."""
+    theta = unscale_local(kernel, param, p, theta_s, t_old)
+    return scale_local(kernel, param, p, l2l(kernel, param, p, h, theta), t_new)
 
 
 # ----------------------------------------------------------------------------- FFT form

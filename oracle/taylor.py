@@ -6,6 +6,10 @@ Conventions (the paper's, with the density w restored in every source sum):
   M2L         L[i] = sum_{q in M(p)} G^(i+q)(c2 - c1) alpha_q      (O(p^6) naive M2L)
               (derivative form: L[i] is d^i of the potential at c2)
   L2P         phi(x) = sum_{i in M(p)} L[i] (x - c2)^i / i!        (eq. local)
+  M2M         rho_q = sum_{i <= q} h^(q-i) / (q-i)! alpha_i,  h = c_new - c_old
+                                                     (eq. mpole_translated_full_coeffs)
+  L2L         L'[i] = sum_{q >= i, q in M(p)} L[q] h^(q-i) / (q-i)!,  h = c_new - c_old
+              (eq. l2l-expr, written for the derivative form: L'[i] = i! mu_i)
 All coefficient vectors are in the graded order of M(p).
 """
 from __future__ import annotations
@@ -13,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 from .kernels import deriv_table_mp, deriv_table_rec
-from .multiindex import graded_order, madd, mfact, mpow
+from .multiindex import graded_order, madd, mfact, mge, mpow, msub
 
 
 def p2m_full(p: int, center, src, w) -> np.ndarray:
@@ -56,4 +60,36 @@ def p2l_full(kernel: str, param: float, p: int, center, src, w) -> np.ndarray:
                    else np.float64)
     for y, wy in zip(np.asarray(src), np.asarray(w)):
         out = out + wy * deriv_table_rec(kernel, param, np.asarray(center) - y, order)
+    return out
+
+
+def _shift_factor(h, m) -> float:
+    """h^m / m! for one translation vector h."""
+    return float(mpow(np.asarray(h, np.float64)[None, :], m)[0]) / mfact(m)
+
+
+def m2m_full(p: int, h, alpha) -> np.ndarray:
+    """Multipole translation by h = c_new - c_old (eq. mpole_translated_full_coeffs):
+    rho_q = sum_{i <= q} h^(q-i)/(q-i)! alpha_i, from the binomial expansion of
+    (c_new - y)^q = ((c_new - c_old) + (c_old - y))^q."""
+    order = graded_order(p)
+    alpha = np.asarray(alpha)
+    out = np.zeros(len(order), dtype=alpha.dtype)
+    for a, q in enumerate(order):
+        for b, i in enumerate(order):
+            if mge(q, i):
+                out[a] += _shift_factor(h, msub(q, i)) * alpha[b]
+    return out
+
+
+def l2l_full(p: int, h, L) -> np.ndarray:
+    """Local translation by h = c_new - c_old (eq. l2l-expr), derivative form: the
+    derivatives at c_new of the degree-p polynomial sum_q L[q] (x - c_old)^q / q!."""
+    order = graded_order(p)
+    L = np.asarray(L)
+    out = np.zeros(len(order), dtype=L.dtype)
+    for a, i in enumerate(order):
+        for b, q in enumerate(order):
+            if mge(q, i):
+                out[a] += _shift_factor(h, msub(q, i)) * L[b]
     return out
