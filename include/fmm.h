@@ -141,6 +141,33 @@ int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
             const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local,
             void* potential, void* stream);
 
+/* Compressed M2M (Sec. 4.3, eq. define_psi): for each k < n_parent, the scaled compressed
+ * multipole of box parent[k] becomes psi~ = M^T T E beta~ summed over its children: each
+ * child's kept coefficients are embedded with zeros elsewhere (E), translated to the parent
+ * centre with the binomial formula of eq. mpole_translated_full_coeffs (T) and compressed
+ * at the parent's box size (M^T).  Exact for Laplace and biharmonic; for Helmholtz and
+ * Yukawa the translated expansion differs from the parent's own P2M at truncation level.
+ *   parent     [n_parent] i32 box indices; entries outside [0, n_box) are skipped
+ *   child      [n_parent][8] i32 box indices; entries outside [0, n_box) mean "no child"
+ *   box_center [n_box][3] f64; box_level [n_box] i32 (scaled by the level's box size)
+ *   mpole      [n_box][Nc] dtype: read at the children, OVERWRITTEN at the parents (zero
+ *              for a parent without children).
+ * A box must not be both a parent and a child in one call (apply levels in separate calls,
+ * children first). */
+int fmm_m2m(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+            const double* box_center, const int32_t* box_level, void* mpole, void* stream);
+
+/* Compressed L2L (Sec. 4.2, eq. l2l-expr in derivative form): for each k < n_parent the
+ * scaled compressed local of box parent[k] is decompressed (M), translated to the centre of
+ * each of its children and the kept entries are added to the child's local.  Exact for
+ * Laplace and biharmonic (the local polynomial satisfies the PDE); truncation-level
+ * differences for Helmholtz and Yukawa.
+ *   parent, child, box_center, box_level as for fmm_m2m
+ *   local      [n_box][Nc] dtype: read at the parents, ACCUMULATED at the children.
+ * A box must appear at most once as a child and not also as a parent in one call. */
+int fmm_l2l(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+            const double* box_center, const int32_t* box_level, void* local, void* stream);
+
 /* Prepare a batched M2L (Sec. 4.1, eq. m2l_toeplitz) over n_pair (target box, source box)
  * pairs, all [host]:
  *   tgt_box, src_box [n_pair] i32 in [0, n_box); both boxes of a pair on the same level

@@ -51,6 +51,8 @@ SIGNATURES = {
     "fmm_plan_destroy": (None, [P]),
     "fmm_p2m": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
     "fmm_l2p": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
+    "fmm_m2m": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, P, P, P]),
+    "fmm_l2l": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, P, P, P]),
     "fmm_m2l_prepare": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P, C.POINTER(P)]),
     "fmm_m2l_prepare_ex": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P,
                                      C.POINTER(FmmM2LTuning), C.POINTER(P)]),

@@ -269,6 +269,47 @@ int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
   return launch_p2m(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
 }
 
+static int trans_args(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+                      const double* box_center, const int32_t* box_level, void* coef, TransArgs& a) {
+  int st = check_plan(plan);
+  if (st) return st;
+  FMM_REQUIRE(n_parent >= 0 && n_parent <= (int64_t)0x7fffffff, FMM_EINVAL, "n_parent out of range");
+  FMM_REQUIRE(n_box >= 0 && n_box <= (int64_t)0x7fffffff, FMM_EINVAL, "n_box out of range");
+  if (n_parent == 0) return FMM_OK;
+  FMM_REQUIRE(parent && child, FMM_EINVAL, "parent / child arrays must not be NULL");
+  FMM_REQUIRE(box_center && box_level && coef, FMM_EINVAL, "box arrays must not be NULL");
+  a = TransArgs{};
+  a.n_parent = n_parent;
+  a.parent = parent;
+  a.child = child;
+  a.n_box = n_box;
+  a.center = box_center;
+  a.level = box_level;
+  a.level_h = plan->d_level_h;
+  a.n_levels = plan->n_levels;
+  a.coef = coef;
+  a.nc = plan->nc;
+  a.c = plan->c;
+  a.rec = plan->rec;
+  return FMM_OK;
+}
+
+int fmm_m2m(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+            const double* box_center, const int32_t* box_level, void* mpole, void* stream) {
+  TransArgs a{};
+  const int st = trans_args(plan, n_parent, parent, child, n_box, box_center, box_level, mpole, a);
+  if (st || n_parent == 0) return st;
+  return launch_m2m(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
+int fmm_l2l(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+            const double* box_center, const int32_t* box_level, void* local, void* stream) {
+  TransArgs a{};
+  const int st = trans_args(plan, n_parent, parent, child, n_box, box_center, box_level, local, a);
+  if (st || n_parent == 0) return st;
+  return launch_l2l(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
 int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
             const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local, void* potential,
             void* stream) {

@@ -37,6 +37,23 @@ struct P2MArgs {
   double* part;             // [n_box][ny][Nc] (x2 complex) FP64 per-chunk results, summed in chunk order
 };
 
+// Multipole-to-multipole and local-to-local translation between a parent box and its (up
+// to eight) children.  Boxes are indices into the box arrays; child[8 k + i] < 0 means none.
+struct TransArgs {
+  int64_t n_parent;
+  const int32_t* parent;    // [n_parent] box index
+  const int32_t* child;     // [n_parent][8] box index, < 0: no child
+  int64_t n_box;
+  const double* center;     // [n_box][3]
+  const int32_t* level;     // [n_box]
+  const double* level_h;    // [n_levels]
+  int32_t n_levels;
+  void* coef;               // [n_box][Nc] dtype: multipoles (M2M) or locals (L2L)
+  int32_t nc;
+  int32_t c;
+  RecArgs rec;
+};
+
 struct L2PArgs {
   int64_t n_box;
   const double* center;
@@ -151,6 +168,8 @@ struct DirectArgs {
 
 int launch_tables(const TableArgs& a, bool cplx, hipStream_t s);
 int launch_p2m(const P2MArgs& a, int p, int dtype, hipStream_t s);
+int launch_m2m(const TransArgs& a, int p, int dtype, hipStream_t s);
+int launch_l2l(const TransArgs& a, int p, int dtype, hipStream_t s);
 int launch_l2p(const L2PArgs& a, int p, int dtype, hipStream_t s);
 int launch_m2l(const M2LArgs& a, int dtype, int rows_per_wave, int col_tiles, int pf_class, int nbuf, int waves,
                hipStream_t s);

@@ -178,6 +178,32 @@ class Plan:
                                   _ptr(local), _ptr(pot), _stream()), "fmm_l2p")
         return pot
 
+    def _tree(self, parent, child, center, level, coef, name):
+        npar = parent.shape[0]
+        nb = center.shape[0]
+        _dev(parent, torch.int32, "parent", (npar,))
+        _dev(child, torch.int32, "child", (npar, 8))
+        _dev(center, torch.float64, "box_center", (nb, 3))
+        _dev(level, torch.int32, "box_level", (nb,))
+        _dev(coef, self.desc.value_dtype, name, (nb, self.nc))
+        return npar, nb
+
+    def m2m(self, parent, child, center, level, mpole) -> torch.Tensor:
+        """mpole[parent[k]] (overwritten) = compressed M2M of its children mpole[child[k, :]]
+        (child < 0: none).  One tree level per call."""
+        npar, nb = self._tree(parent, child, center, level, mpole, "mpole")
+        check(_lib.load().fmm_m2m(self._h, npar, _ptr(parent), _ptr(child), nb, _ptr(center), _ptr(level),
+                                  _ptr(mpole), _stream()), "fmm_m2m")
+        return mpole
+
+    def l2l(self, parent, child, center, level, local) -> torch.Tensor:
+        """local[child[k, :]] += compressed L2L of local[parent[k]] (child < 0: none).  One tree
+        level per call."""
+        npar, nb = self._tree(parent, child, center, level, local, "local")
+        check(_lib.load().fmm_l2l(self._h, npar, _ptr(parent), _ptr(child), nb, _ptr(center), _ptr(level),
+                                  _ptr(local), _stream()), "fmm_l2l")
+        return local
+
     def l2p_adjoint(self, center, level, rng, tgt, pot_grad, local_grad=None, local=None, tgt_grad=None):
         """local_grad (overwritten) = L2P^T(pot_grad); tgt_grad (accumulated) += pot_grad * grad phi
         when given (needs the forward local expansions `local`)."""

@@ -1,0 +1,194 @@
+"""GPU parity of the compressed M2M and L2L (fmm_m2m, fmm_l2l) against the CPU oracle.
+
+Inputs are seeded: random scaled coefficients on the boxes of uniform and adaptive
+(Plummer) octrees, so that every parent has eight, some or no children.  Tolerances,
+normwise relative l2 over all outputs: FP64 / complex128 1e-12; FP32 / complex64 2e-6
+(inputs and outputs rounded to single precision, arithmetic in double).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import compressed as Z
+
+from helpers import perm_to_lib, rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("laplace", 0.0), ("yukawa", 2.0), ("helmholtz", 1.0), ("biharmonic", 0.0)]
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make(fmm, kernel, param, p, single, tree):
+    cplx = kernel == "helmholtz"
+    dt = ("c64" if single else "c128") if cplx else ("f32" if single else "f64")
+    d = fmm.Desc(kernel, p, dt, param)
+    plan = fmm.Plan(d, [tree.box_size(l) for l in range(tree.n_levels)])
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    return d, plan, perm
+
+
+def random_coefs(tree, nc, cplx, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    v = g.standard_normal((tree.n_box, nc))
+    return v + 1j * g.standard_normal((tree.n_box, nc)) if cplx else v
+
+
+def oracle_m2m(kernel, param, p, tree, parents, child, coef_lib, perm):
+    """Scaled psi~ of each parent (library order) from the children's scaled beta~."""
+    out = {}
+    for k, pb in enumerate(parents):
+        tp = 1.0 / tree.box_size(int(tree.level[pb]))
+        acc = 0
+        for cb in child[k]:
+            if cb < 0:
+                continue
+            tc = 1.0 / tree.box_size(int(tree.level[cb]))
+            beta = np.empty_like(coef_lib[cb])
+            beta[perm] = coef_lib[cb]
+            acc = acc + Z.m2m_scaled(kernel, param, p, tree.center[pb] - tree.center[cb], beta, tc, tp)
+        psi = np.zeros(coef_lib.shape[1], dtype=coef_lib.dtype) if np.isscalar(acc) else acc
+        out[int(pb)] = np.asarray(psi)[perm]
+    return out
+
+
+def oracle_l2l(kernel, param, p, tree, parents, child, coef_lib, perm):
+    """Scaled theta~ added to each child (library order) from its parent's scaled theta~."""
+    out = {}
+    for k, pb in enumerate(parents):
+        tp = 1.0 / tree.box_size(int(tree.level[pb]))
+        theta = np.empty_like(coef_lib[pb])
+        theta[perm] = coef_lib[pb]
+        for cb in child[k]:
+            if cb < 0:
+                continue
+            tc = 1.0 / tree.box_size(int(tree.level[cb]))
+            out[int(cb)] = np.asarray(
+                Z.l2l_scaled(kernel, param, p, tree.center[cb] - tree.center[pb], theta, tp, tc))[perm]
+    return out
+
+
+@pytest.fixture(scope="module")
+def uniform3():
+    return W.uniform_tree(W.uniform_points(4096, 31), 3)
+
+
+@pytest.fixture(scope="module")
+def plummer():
+    return W.adaptive_tree(W.plummer_points(20000, 32, 0.1), 64)
+
+
+def run_m2m(fmm, kernel, param, p, single, tree, lev, seed, sample=None):
+    d, plan, perm = make(fmm, kernel, param, p, single, tree)
+    parents, child = W.children(tree, lev)
+    if sample is not None:
+        parents, child = parents[sample], child[sample]
+    coef = random_coefs(tree, plan.nc, d.value_dtype.is_complex, seed)
+    mp = dev(coef, d.value_dtype)
+    plan.m2m(dev(parents, torch.int32), dev(child, torch.int32), dev(tree.center, torch.float64),
+             dev(tree.level, torch.int32), mp)
+    got = host(mp)
+    ref = oracle_m2m(kernel, param, p, tree, parents, child, host(dev(coef, d.value_dtype)).astype(coef.dtype), perm)
+    a = np.array([got[b] for b in ref])
+    b = np.array([ref[b] for b in ref])
+    # boxes that are not parents keep their values
+    others = np.setdiff1d(np.arange(tree.n_box), parents)
+    assert np.array_equal(got[others], host(dev(coef, d.value_dtype))[others])
+    return rel(a, b)
+
+
+def run_l2l(fmm, kernel, param, p, single, tree, lev, seed, sample=None):
+    d, plan, perm = make(fmm, kernel, param, p, single, tree)
+    parents, child = W.children(tree, lev)
+    if sample is not None:
+        parents, child = parents[sample], child[sample]
+    coef = random_coefs(tree, plan.nc, d.value_dtype.is_complex, seed)
+    start = host(dev(coef, d.value_dtype))
+    loc = dev(coef, d.value_dtype)
+    plan.l2l(dev(parents, torch.int32), dev(child, torch.int32), dev(tree.center, torch.float64),
+             dev(tree.level, torch.int32), loc)
+    got = host(loc)
+    ref = oracle_l2l(kernel, param, p, tree, parents, child, start.astype(coef.dtype), perm)
+    a = np.array([got[b] - start[b] for b in ref])
+    b = np.array([ref[b] for b in ref])
+    touched = np.array(sorted(ref))
+    others = np.setdiff1d(np.arange(tree.n_box), touched)
+    assert np.array_equal(got[others], start[others])
+    return rel(a, b)
+
+
+@pytest.mark.parametrize("kernel,param", CASES)
+@pytest.mark.parametrize("single", [False, True])
+def test_m2m_uniform(gpu_lib, uniform3, kernel, param, single):
+    err = run_m2m(gpu_lib, kernel, param, 4, single, uniform3, 2, 41)
+    assert err < (2e-6 if single else 1e-12), err
+
+
+@pytest.mark.parametrize("kernel,param", CASES)
+@pytest.mark.parametrize("single", [False, True])
+def test_l2l_uniform(gpu_lib, uniform3, kernel, param, single):
+    err = run_l2l(gpu_lib, kernel, param, 4, single, uniform3, 2, 42)
+    assert err < (2e-6 if single else 1e-12), err
+
+
+@pytest.mark.parametrize("kernel,param,p", [("laplace", 0.0, 8), ("helmholtz", 1.0, 8), ("yukawa", 2.0, 12),
+                                            ("biharmonic", 0.0, 10)])
+def test_m2m_l2l_high_order_sampled(gpu_lib, uniform3, kernel, param, p):
+    sample = np.array([0, 21, 42, 63])
+    assert run_m2m(gpu_lib, kernel, param, p, False, uniform3, 2, 43, sample) < 1e-12
+    assert run_l2l(gpu_lib, kernel, param, p, False, uniform3, 2, 44, sample) < 1e-12
+
+
+@pytest.mark.parametrize("kernel,param", [("laplace", 0.0), ("helmholtz", 1.0)])
+def test_ragged_children_adaptive_tree(gpu_lib, plummer, kernel, param):
+    """Parents with fewer than eight children (and parents without any: M2M writes zeros)."""
+    parents, child = W.children(plummer, 3)
+    assert (child < 0).any()
+    assert run_m2m(gpu_lib, kernel, param, 6, False, plummer, 3, 45) < 1e-12
+    assert run_l2l(gpu_lib, kernel, param, 6, False, plummer, 3, 46) < 1e-12
+
+
+def test_parent_without_children_gets_zero_and_bad_indices_are_skipped(gpu_lib, uniform3):
+    fmm = gpu_lib
+    d, plan, _ = make(fmm, "laplace", 0.0, 4, False, uniform3)
+    coef = random_coefs(uniform3, plan.nc, False, 47)
+    mp = dev(coef, torch.float64)
+    parents = np.array([0, 1, uniform3.n_box + 5, -3], dtype=np.int32)
+    child = np.full((4, 8), -1, dtype=np.int32)
+    child[1, 0] = uniform3.n_box + 100  # out of range: no child
+    plan.m2m(dev(parents, torch.int32), dev(child, torch.int32), dev(uniform3.center, torch.float64),
+             dev(uniform3.level, torch.int32), mp)
+    got = host(mp)
+    assert np.all(got[0] == 0) and np.all(got[1] == 0)
+    assert np.array_equal(got[2:], coef[2:])
+    # zero parents: nothing happens
+    plan.m2m(dev(np.zeros(0, np.int32), torch.int32), dev(np.zeros((0, 8), np.int32), torch.int32),
+             dev(uniform3.center, torch.float64), dev(uniform3.level, torch.int32), mp)
+    assert np.array_equal(host(mp), got)
+
+
+@pytest.mark.parametrize("kernel,param", [("laplace", 0.0), ("biharmonic", 0.0)])
+def test_m2m_of_leaf_moments_equals_parent_moments(gpu_lib, uniform3, kernel, param):
+    """For PDEs whose terms have one order the compressed M2M is exact (Sec. 4.3): P2M at
+    the leaves then M2M equals P2M at the parents, on the GPU end to end."""
+    fmm = gpu_lib
+    tr = uniform3
+    d, plan, _ = make(fmm, kernel, param, 8, False, tr)
+    w = W.normal_weights(tr.points.shape[0], 48)
+    pts, wd = dev(tr.points, torch.float64), dev(w, torch.float64)
+    cen, lev, rng = dev(tr.center, torch.float64), dev(tr.level, torch.int32), dev(tr.pt_range, torch.int64)
+    direct = plan.p2m(cen, lev, rng, pts, wd)
+    moved = torch.zeros_like(direct)
+    leaves = tr.boxes_at(3)
+    moved[leaves] = direct[leaves]
+    parents, child = W.children(tr, 2)
+    plan.m2m(dev(parents, torch.int32), dev(child, torch.int32), cen, lev, moved)
+    assert rel(host(moved[parents]), host(direct[parents])) < 1e-12

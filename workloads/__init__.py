@@ -156,6 +156,22 @@ class Tree:
         return self.pt_range[:, 1] - self.pt_range[:, 0]
 
 
+def children(tree: Tree, lev: int) -> tuple[np.ndarray, np.ndarray]:
+    """Boxes of level lev and their children on level lev + 1: (parent [n] int32,
+    child [n][8] int32, -1 where a child box does not exist).  Octant o of a parent with
+    integer coordinates ijk is the box 2 ijk + (o & 1, (o >> 1) & 1, (o >> 2) & 1)."""
+    parents = tree.boxes_at(lev)
+    nxt = tree.boxes_at(lev + 1)
+    index = {tuple(int(v) for v in tree.ijk[b]): int(b) for b in nxt}
+    child = np.full((parents.shape[0], 8), -1, dtype=np.int32)
+    for k, b in enumerate(parents):
+        base = 2 * tree.ijk[b]
+        for o in range(8):
+            key = (int(base[0]) + (o & 1), int(base[1]) + ((o >> 1) & 1), int(base[2]) + ((o >> 2) & 1))
+            child[k, o] = index.get(key, -1)
+    return parents.astype(np.int32), child
+
+
 def _point_keys(points: np.ndarray) -> np.ndarray:
     scale = float(1 << MAX_DEPTH)
     ijk = np.floor(points * scale).astype(np.int64)
