@@ -226,6 +226,55 @@ def cpu_baseline(tr, w, t, s, p=8, budget_s=12.0):
             "l2p_pts_per_s": pts_l2p / t_l2p}
 
 
+def translation_flops(p, c, rec_terms):
+    """Algorithmic FLOPs (2 per multiply-add) of the separable M2M per child, of the compression
+    (or, for L2L, the decompression) per parent, and of the L2L per child."""
+    full = [(x, y, z) for z in range(p + 1) for x in range(p + 1 - z) for y in range(p + 1 - z - x)]
+    kept = [m for m in full if m[2] < c]
+    m2m_child = 2 * (sum(x + 1 for x, y, z in kept) + sum(y + 1 for x, y, z in kept)
+                     + sum(min(z, c - 1) + 1 for x, y, z in full))
+    l2l_child = 2 * 3 * sum(p - x - y - z + 1 for x, y, z in kept)  # three passes, p - |m| + 1 terms
+    recompress = 2 * rec_terms * (len(full) - len(kept))
+    return m2m_child, recompress, l2l_child
+
+
+def translations(torch, fmm, tr, reps=20):
+    """Compressed M2M (levels 4 -> 3 -> 2) and L2L (2 -> 3 -> 4) on the headline octree,
+    Laplace p = 8, FP64 and FP32: launch times and child translations per second."""
+    import workloads as W
+    out = []
+    dev = "cuda"
+    cen = torch.as_tensor(tr.center, dtype=torch.float64, device=dev)
+    lev = torch.as_tensor(tr.level, dtype=torch.int32, device=dev)
+    fam = {}
+    for l in (3, 2):
+        par, ch = W.children(tr, l)
+        fam[l] = (torch.as_tensor(par, device=dev), torch.as_tensor(ch, device=dev), int((ch >= 0).sum()))
+    m2m_child, recompress, l2l_child = translation_flops(8, 2, 2)
+    for dt in ("f64", "f32"):
+        desc = fmm.Desc("laplace", 8, dt)
+        plan = fmm.Plan(desc, [tr.box_size(l) for l in range(tr.n_levels)])
+        coef = torch.randn((tr.n_box, plan.nc), dtype=desc.value_dtype, device=dev)
+        row = {"dtype": dt}
+        for l in (3, 2):
+            par, ch, nch = fam[l]
+            t = time_kernel(torch, lambda: plan.m2m(par, ch, cen, lev, coef), reps)
+            row[f"m2m_l{l + 1}_to_l{l}_us"] = t * 1e6
+            row[f"m2m_l{l + 1}_to_l{l}_children_per_s"] = nch / t
+            row[f"m2m_l{l + 1}_to_l{l}_gflops"] = (nch * m2m_child + par.shape[0] * recompress) / t / 1e9
+        for l in (2, 3):
+            par, ch, nch = fam[l]
+            t = time_kernel(torch, lambda: plan.l2l(par, ch, cen, lev, coef), reps)
+            row[f"l2l_l{l}_to_l{l + 1}_us"] = t * 1e6
+            row[f"l2l_l{l}_to_l{l + 1}_children_per_s"] = nch / t
+            row[f"l2l_l{l}_to_l{l + 1}_gflops"] = (nch * l2l_child + par.shape[0] * recompress) / t / 1e9
+        out.append(row)
+    return {"workload": "uniform octree depth 4 (2^20 points), laplace p8: M2M 4->3->2, L2L 2->3->4",
+            "flops_per_child_m2m": m2m_child, "flops_per_child_l2l": l2l_child,
+            "flops_per_parent_compression": recompress,
+            "variants": out}
+
+
 def mixed_batch(torch, fmm, reps=10):
     """Yukawa (lambda = 2) + biharmonic far field of 524,288 Gaussian-mixture points (adaptive
     octree, <= 64 per leaf), orders 6/8/10 by level, FP32: one batch per (kernel, order), all
@@ -328,6 +377,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default=None, help="run one variant, e.g. f64:8 (for profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the FFT path and the mixed workload")
+    ap.add_argument("--translations", action="store_true",
+                    help="also time M2M / L2L when --only or --no-extras is given")
     ap.add_argument("--extended", action="store_true",
                     help="also time the Plummer Helmholtz launch and the far-field gradient pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -397,6 +448,9 @@ def main():
                      "algorithmic": f"2*Nc^2 FLOP per pair, Nc={head['nc']}, {len(t)} pairs per launch"},
         "variants": results,
     }
+    if args.translations or not (args.only or args.no_extras):
+        log("M2M / L2L")
+        out["translations"] = translations(torch, fmm, tr)
     if not (args.only or args.no_extras):
         log("mixed workload (persistent, graph-captured launch)")
         out["mixed_batch"] = mixed_batch(torch, fmm)

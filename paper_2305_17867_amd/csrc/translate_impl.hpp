@@ -20,7 +20,8 @@
 //   L2L  theta~_i = r^|i| sum_{q >= i} delta^(q - i) / (q - i)!  L~_q,
 // and the compression / decompression use the parent's box size.
 //
-// One wavefront per parent box; the coefficients are kept in double in LDS.
+// One workgroup per parent box, one wavefront per child (up to eight at once); the
+// coefficients are kept in double in LDS.
 #pragma once
 
 #include "../../include/fmm.h"
@@ -33,8 +34,6 @@
 namespace fmm {
 
 namespace detail_trans {
-
-constexpr int kThreads = 64;
 
 // (x, y, z) of every full index of M(P) in the internal order (m_z, m_x, m_y).
 template <int P>
@@ -61,18 +60,18 @@ __device__ inline int clamp_level(const TransArgs& a, int64_t box) {
   return l < 0 ? 0 : (l >= a.n_levels ? a.n_levels - 1 : l);
 }
 
-// sh[ax][k] = delta_ax^k / k! for k = 0..P, rp[k] = r^k (one thread per axis).
+// sh[ax][k] = delta_ax^k / k! for k = 0..P, rp[k] = r^k (lanes 0..3 of the wavefront).
 template <int P>
-__device__ inline void shift_factors(const double (&delta)[3], double r, double (&sh)[3][P + 1], double (&rp)[P + 1]) {
-  const int t = threadIdx.x;
-  if (t < 3) {
+__device__ inline void shift_factors(int lane, const double (&delta)[3], double r, double (&sh)[3][P + 1],
+                                     double (&rp)[P + 1]) {
+  if (lane < 3) {
     double v = 1.0;
-    sh[t][0] = 1.0;
+    sh[lane][0] = 1.0;
     for (int k = 1; k <= P; ++k) {
-      v *= delta[t] / k;
-      sh[t][k] = v;
+      v *= delta[lane] / k;
+      sh[lane][k] = v;
     }
-  } else if (t == 3) {
+  } else if (lane == 3) {
     double v = 1.0;
     rp[0] = 1.0;
     for (int k = 1; k <= P; ++k) {
@@ -82,168 +81,211 @@ __device__ inline void shift_factors(const double (&delta)[3], double r, double 
   }
 }
 
+// Children translated at once, one wavefront each: as many as the per-child LDS buffers
+// (two full coefficient sets in double) allow beside the parent's own set within 60 KB.
+__host__ __device__ constexpr int kids_at_once(int p, bool cplx) {
+  const int set = nfull(p) * (cplx ? 2 : 1) * 8;
+  const int budget = 60 * 1024 - set;
+  return 16 * set <= budget ? 8 : 8 * set <= budget ? 4 : 4 * set <= budget ? 2 : 1;
+}
+
 template <int P, typename R, bool CPLX>
-__global__ __launch_bounds__(kThreads) void m2m_kernel(TransArgs a) {
+__global__ __launch_bounds__(64 * kids_at_once(P, CPLX)) void m2m_kernel(TransArgs a) {
   constexpr int NP = nfull(P);
   constexpr int W = CPLX ? 2 : 1;
+  constexpr int NK = kids_at_once(P, CPLX);
+  constexpr int NT = 64 * NK;
   __shared__ double sig[NP * W];  // translated moments summed over the children (full set)
-  __shared__ double b0[NP * W], b1[NP * W];
-  __shared__ double sh[3][P + 1], rp[P + 1];
+  __shared__ double buf[NK][2][NP * W];
+  __shared__ double sh[NK][3][P + 1], rp[NK][P + 1];
+  __shared__ int ok[NK];
   const int pb = a.parent[blockIdx.x];
   if (pb < 0 || pb >= a.n_box) return;  // uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const double hp = a.level_h[clamp_level(a, pb)];
   const int nc = a.nc, c = a.c;
-  for (int k = threadIdx.x; k < NP * W; k += kThreads) sig[k] = 0.0;
+  for (int k = threadIdx.x; k < NP * W; k += NT) sig[k] = 0.0;
   const R* in = reinterpret_cast<const R*>(a.coef);
-  for (int ch = 0; ch < 8; ++ch) {
-    const int cb = a.child[8 * (int64_t)blockIdx.x + ch];
-    if (cb < 0 || cb >= a.n_box) continue;  // uniform
-    const double hc = a.level_h[clamp_level(a, cb)];
-    const double delta[3] = {(a.center[3 * pb] - a.center[3 * cb]) / hp, (a.center[3 * pb + 1] - a.center[3 * cb + 1]) / hp,
-                             (a.center[3 * pb + 2] - a.center[3 * cb + 2]) / hp};
-    __syncthreads();  // the previous child's passes are done with b0, b1, sh
-    shift_factors<P>(delta, hc / hp, sh, rp);
-    __syncthreads();
-    // E and the child-to-parent scaling r^|i|: the kept set is the prefix [0, nc)
-    for (int k = threadIdx.x; k < nc; k += kThreads) {
-      const double f = rp[kXyz<P>.x[k] + kXyz<P>.y[k] + kXyz<P>.z[k]];
-#pragma unroll
-      for (int u = 0; u < W; ++u) b0[k * W + u] = f * (double)in[(int64_t)cb * nc * W + k * W + u];
+  for (int g = 0; g < 8; g += NK) {
+    // wavefront `wave` translates child g + wave (uniform within the wavefront)
+    const int cb = a.child[8 * (int64_t)blockIdx.x + g + wave];
+    const bool have = cb >= 0 && cb < a.n_box;
+    double* b0 = buf[wave][0];
+    double* b1 = buf[wave][1];
+    __syncthreads();  // the previous group is done with buf, sh and ok
+    if (lane == 0) ok[wave] = have;
+    if (have) {
+      const double hc = a.level_h[clamp_level(a, cb)];
+      const double delta[3] = {(a.center[3 * pb] - a.center[3 * cb]) / hp,
+                               (a.center[3 * pb + 1] - a.center[3 * cb + 1]) / hp,
+                               (a.center[3 * pb + 2] - a.center[3 * cb + 2]) / hp};
+      shift_factors<P>(lane, delta, hc / hp, sh[wave], rp[wave]);
     }
     __syncthreads();
-    // along x: b1(e1, y, z) = sum_{s <= e1} delta_x^(e1 - s) / (e1 - s)! b0(s, y, z), z < c
-    for (int k = threadIdx.x; k < nc; k += kThreads) {
-      const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
-      double acc[W] = {};
-      for (int s = 0; s <= x; ++s) {
-        const int n = full_index(P, s, y, z);
+    if (have) {  // E and the child-to-parent scaling r^|i|: the kept set is the prefix [0, nc)
+      for (int k = lane; k < nc; k += 64) {
+        const double f = rp[wave][kXyz<P>.x[k] + kXyz<P>.y[k] + kXyz<P>.z[k]];
 #pragma unroll
-        for (int u = 0; u < W; ++u) acc[u] += sh[0][x - s] * b0[n * W + u];
+        for (int u = 0; u < W; ++u) b0[k * W + u] = f * (double)in[(int64_t)cb * nc * W + k * W + u];
       }
-#pragma unroll
-      for (int u = 0; u < W; ++u) b1[k * W + u] = acc[u];
     }
     __syncthreads();
-    // along y
-    for (int k = threadIdx.x; k < nc; k += kThreads) {
-      const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
-      double acc[W] = {};
-      for (int s = 0; s <= y; ++s) {
-        const int n = full_index(P, x, s, z);
+    if (have) {  // along x: b1(e1, y, z) = sum_{s <= e1} delta_x^(e1 - s) / (e1 - s)! b0(s, y, z), z < c
+      for (int k = lane; k < nc; k += 64) {
+        const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
+        double acc[W] = {};
+        for (int s = 0; s <= x; ++s) {
+          const int n = full_index(P, s, y, z);
 #pragma unroll
-        for (int u = 0; u < W; ++u) acc[u] += sh[1][y - s] * b1[n * W + u];
+          for (int u = 0; u < W; ++u) acc[u] += sh[wave][0][x - s] * b0[n * W + u];
+        }
+#pragma unroll
+        for (int u = 0; u < W; ++u) b1[k * W + u] = acc[u];
       }
-#pragma unroll
-      for (int u = 0; u < W; ++u) b0[k * W + u] = acc[u];
     }
     __syncthreads();
-    // along z, into every entry of the full set (sources only at z < c)
-    for (int k = threadIdx.x; k < NP; k += kThreads) {
-      const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
-      const int smax = z < c - 1 ? z : c - 1;
-      double acc[W] = {};
-      for (int s = 0; s <= smax; ++s) {
-        const int n = full_index(P, x, y, s);
+    if (have) {  // along y
+      for (int k = lane; k < nc; k += 64) {
+        const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
+        double acc[W] = {};
+        for (int s = 0; s <= y; ++s) {
+          const int n = full_index(P, x, s, z);
 #pragma unroll
-        for (int u = 0; u < W; ++u) acc[u] += sh[2][z - s] * b0[n * W + u];
+          for (int u = 0; u < W; ++u) acc[u] += sh[wave][1][y - s] * b1[n * W + u];
+        }
+#pragma unroll
+        for (int u = 0; u < W; ++u) b0[k * W + u] = acc[u];
       }
+    }
+    __syncthreads();
+    if (have) {  // along z, into every entry of the full set (sources only at z < c)
+      for (int k = lane; k < NP; k += 64) {
+        const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
+        const int smax = z < c - 1 ? z : c - 1;
+        double acc[W] = {};
+        for (int s = 0; s <= smax; ++s) {
+          const int n = full_index(P, x, y, s);
 #pragma unroll
-      for (int u = 0; u < W; ++u) sig[k * W + u] += acc[u];
+          for (int u = 0; u < W; ++u) acc[u] += sh[wave][2][z - s] * b0[n * W + u];
+        }
+#pragma unroll
+        for (int u = 0; u < W; ++u) b1[k * W + u] = acc[u];
+      }
+    }
+    __syncthreads();
+    // the children's contributions are added in child order
+    for (int k = threadIdx.x; k < NP * W; k += NT) {
+      double v = sig[k];
+#pragma unroll
+      for (int w = 0; w < NK; ++w)
+        if (ok[w]) v += buf[w][1][k];
+      sig[k] = v;
     }
   }
   __syncthreads();
   detail_p2m::compress_lds<P, CPLX>(sig, a.rec, c, hp);
   R* out = reinterpret_cast<R*>(a.coef) + (int64_t)pb * nc * W;
-  for (int k = threadIdx.x; k < nc * W; k += kThreads) out[k] = (R)sig[k];
+  for (int k = threadIdx.x; k < nc * W; k += NT) out[k] = (R)sig[k];
 }
 
 template <int P, typename R, bool CPLX>
-__global__ __launch_bounds__(kThreads) void l2l_kernel(TransArgs a) {
+__global__ __launch_bounds__(64 * kids_at_once(P, CPLX)) void l2l_kernel(TransArgs a) {
   constexpr int NP = nfull(P);
   constexpr int W = CPLX ? 2 : 1;
+  constexpr int NK = kids_at_once(P, CPLX);
+  constexpr int NT = 64 * NK;
   __shared__ double L[NP * W];  // the parent's decompressed local (full set)
-  __shared__ double b0[NP * W], b1[NP * W];
-  __shared__ double sh[3][P + 1], rp[P + 1];
+  __shared__ double buf[NK][2][NP * W];
+  __shared__ double sh[NK][3][P + 1], rp[NK][P + 1];
   const int pb = a.parent[blockIdx.x];
   if (pb < 0 || pb >= a.n_box) return;  // uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const double hp = a.level_h[clamp_level(a, pb)];
   const int nc = a.nc, c = a.c;
   R* coef = reinterpret_cast<R*>(a.coef);
-  for (int k = threadIdx.x; k < nc * W; k += kThreads) L[k] = (double)coef[(int64_t)pb * nc * W + k];
+  for (int k = threadIdx.x; k < nc * W; k += NT) L[k] = (double)coef[(int64_t)pb * nc * W + k];
   __syncthreads();
   detail_l2p::decompress_lds<P, CPLX>(L, a.rec, c, hp);
-  for (int ch = 0; ch < 8; ++ch) {
-    const int cb = a.child[8 * (int64_t)blockIdx.x + ch];
-    if (cb < 0 || cb >= a.n_box) continue;  // uniform
-    const double hc = a.level_h[clamp_level(a, cb)];
-    const double delta[3] = {(a.center[3 * cb] - a.center[3 * pb]) / hp, (a.center[3 * cb + 1] - a.center[3 * pb + 1]) / hp,
-                             (a.center[3 * cb + 2] - a.center[3 * pb + 2]) / hp};
-    __syncthreads();  // the previous child's passes are done with b0, b1, sh
-    shift_factors<P>(delta, hc / hp, sh, rp);
-    __syncthreads();
-    // along z, only the outputs with z < c (the kept prefix):
-    //   b0(x, y, e3) = sum_{s >= e3} delta_z^(s - e3) / (s - e3)! L(x, y, s)
-    for (int k = threadIdx.x; k < nc; k += kThreads) {
-      const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
-      double acc[W] = {};
-      for (int s = z; s <= P - x - y; ++s) {
-        const int n = full_index(P, x, y, s);
-#pragma unroll
-        for (int u = 0; u < W; ++u) acc[u] += sh[2][s - z] * L[n * W + u];
-      }
-#pragma unroll
-      for (int u = 0; u < W; ++u) b0[k * W + u] = acc[u];
+  for (int g = 0; g < 8; g += NK) {
+    const int cb = a.child[8 * (int64_t)blockIdx.x + g + wave];
+    const bool have = cb >= 0 && cb < a.n_box;
+    double* b0 = buf[wave][0];
+    double* b1 = buf[wave][1];
+    __syncthreads();  // the previous group is done with buf and sh
+    if (have) {
+      const double hc = a.level_h[clamp_level(a, cb)];
+      const double delta[3] = {(a.center[3 * cb] - a.center[3 * pb]) / hp,
+                               (a.center[3 * cb + 1] - a.center[3 * pb + 1]) / hp,
+                               (a.center[3 * cb + 2] - a.center[3 * pb + 2]) / hp};
+      shift_factors<P>(lane, delta, hc / hp, sh[wave], rp[wave]);
     }
     __syncthreads();
-    // along y
-    for (int k = threadIdx.x; k < nc; k += kThreads) {
-      const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
-      double acc[W] = {};
-      for (int s = y; s <= P - x - z; ++s) {
-        const int n = full_index(P, x, s, z);
+    if (have) {  // along z, only the outputs with z < c (the kept prefix):
+                 //   b0(x, y, e3) = sum_{s >= e3} delta_z^(s - e3) / (s - e3)! L(x, y, s)
+      for (int k = lane; k < nc; k += 64) {
+        const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
+        double acc[W] = {};
+        for (int s = z; s <= P - x - y; ++s) {
+          const int n = full_index(P, x, y, s);
 #pragma unroll
-        for (int u = 0; u < W; ++u) acc[u] += sh[1][s - y] * b0[n * W + u];
+          for (int u = 0; u < W; ++u) acc[u] += sh[wave][2][s - z] * L[n * W + u];
+        }
+#pragma unroll
+        for (int u = 0; u < W; ++u) b0[k * W + u] = acc[u];
       }
-#pragma unroll
-      for (int u = 0; u < W; ++u) b1[k * W + u] = acc[u];
     }
     __syncthreads();
-    // along x, then the parent-to-child scaling r^|i|, added to the child's local
-    R* out = coef + (int64_t)cb * nc * W;
-    for (int k = threadIdx.x; k < nc; k += kThreads) {
-      const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
-      double acc[W] = {};
-      for (int s = x; s <= P - y - z; ++s) {
-        const int n = full_index(P, s, y, z);
+    if (have) {  // along y
+      for (int k = lane; k < nc; k += 64) {
+        const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
+        double acc[W] = {};
+        for (int s = y; s <= P - x - z; ++s) {
+          const int n = full_index(P, x, s, z);
 #pragma unroll
-        for (int u = 0; u < W; ++u) acc[u] += sh[0][s - x] * b1[n * W + u];
+          for (int u = 0; u < W; ++u) acc[u] += sh[wave][1][s - y] * b0[n * W + u];
+        }
+#pragma unroll
+        for (int u = 0; u < W; ++u) b1[k * W + u] = acc[u];
       }
-      const double f = rp[x + y + z];
+    }
+    __syncthreads();
+    if (have) {  // along x, then the parent-to-child scaling r^|i|, added to the child's local
+      R* out = coef + (int64_t)cb * nc * W;
+      for (int k = lane; k < nc; k += 64) {
+        const int x = kXyz<P>.x[k], y = kXyz<P>.y[k], z = kXyz<P>.z[k];
+        double acc[W] = {};
+        for (int s = x; s <= P - y - z; ++s) {
+          const int n = full_index(P, s, y, z);
 #pragma unroll
-      for (int u = 0; u < W; ++u) out[k * W + u] += (R)(f * acc[u]);
+          for (int u = 0; u < W; ++u) acc[u] += sh[wave][0][s - x] * b1[n * W + u];
+        }
+        const double f = rp[wave][x + y + z];
+#pragma unroll
+        for (int u = 0; u < W; ++u) out[k * W + u] += (R)(f * acc[u]);
+      }
     }
   }
 }
 
 template <int P>
 int launch_trans_p(const TransArgs& a, int dtype, bool l2l, hipStream_t s) {
-  const dim3 g((unsigned)a.n_parent), t(kThreads);
+  const dim3 g((unsigned)a.n_parent);
   switch (dtype) {
     case FMM_F64:
-      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, double, false>), g, t, 0, s, a);
-      else hipLaunchKernelGGL((m2m_kernel<P, double, false>), g, t, 0, s, a);
+      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, double, false>), g, dim3(64 * kids_at_once(P, false)), 0, s, a);
+      else hipLaunchKernelGGL((m2m_kernel<P, double, false>), g, dim3(64 * kids_at_once(P, false)), 0, s, a);
       break;
     case FMM_F32:
-      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, float, false>), g, t, 0, s, a);
-      else hipLaunchKernelGGL((m2m_kernel<P, float, false>), g, t, 0, s, a);
+      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, float, false>), g, dim3(64 * kids_at_once(P, false)), 0, s, a);
+      else hipLaunchKernelGGL((m2m_kernel<P, float, false>), g, dim3(64 * kids_at_once(P, false)), 0, s, a);
       break;
     case FMM_C128:
-      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, double, true>), g, t, 0, s, a);
-      else hipLaunchKernelGGL((m2m_kernel<P, double, true>), g, t, 0, s, a);
+      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, double, true>), g, dim3(64 * kids_at_once(P, true)), 0, s, a);
+      else hipLaunchKernelGGL((m2m_kernel<P, double, true>), g, dim3(64 * kids_at_once(P, true)), 0, s, a);
       break;
     case FMM_C64:
-      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, float, true>), g, t, 0, s, a);
-      else hipLaunchKernelGGL((m2m_kernel<P, float, true>), g, t, 0, s, a);
+      if (l2l) hipLaunchKernelGGL((l2l_kernel<P, float, true>), g, dim3(64 * kids_at_once(P, true)), 0, s, a);
+      else hipLaunchKernelGGL((m2m_kernel<P, float, true>), g, dim3(64 * kids_at_once(P, true)), 0, s, a);
       break;
     default: return fail(FMM_EINVAL, "dtype");
   }
