@@ -168,6 +168,17 @@ int fmm_m2m(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_
 int fmm_l2l(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
             const double* box_center, const int32_t* box_level, void* local, void* stream);
 
+/* Transposes of fmm_m2m and fmm_l2l for gradients (derived from the same passages).
+ * fmm_m2m_adjoint: mpole_grad read at the parents, ACCUMULATED at the children:
+ *   grad beta~_child += (M^T T E)^T grad psi~_parent.
+ * fmm_l2l_adjoint: local_grad read at the children, ACCUMULATED at the parents:
+ *   grad theta~_parent += sum over children of (L2L)^T grad theta~_child.
+ * Arguments and restrictions as for fmm_m2m / fmm_l2l. */
+int fmm_m2m_adjoint(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+                    const double* box_center, const int32_t* box_level, void* mpole_grad, void* stream);
+int fmm_l2l_adjoint(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+                    const double* box_center, const int32_t* box_level, void* local_grad, void* stream);
+
 /* Prepare a batched M2L (Sec. 4.1, eq. m2l_toeplitz) over n_pair (target box, source box)
  * pairs, all [host]:
  *   tgt_box, src_box [n_pair] i32 in [0, n_box); both boxes of a pair on the same level

@@ -53,6 +53,8 @@ SIGNATURES = {
     "fmm_l2p": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
     "fmm_m2m": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, P, P, P]),
     "fmm_l2l": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, P, P, P]),
+    "fmm_m2m_adjoint": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, P, P, P]),
+    "fmm_l2l_adjoint": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, P, P, P]),
     "fmm_m2l_prepare": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P, C.POINTER(P)]),
     "fmm_m2l_prepare_ex": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P,
                                      C.POINTER(FmmM2LTuning), C.POINTER(P)]),

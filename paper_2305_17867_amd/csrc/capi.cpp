@@ -310,6 +310,24 @@ int fmm_l2l(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_
   return launch_l2l(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
 }
 
+int fmm_m2m_adjoint(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+                    const double* box_center, const int32_t* box_level, void* mpole_grad, void* stream) {
+  TransArgs a{};
+  const int st = trans_args(plan, n_parent, parent, child, n_box, box_center, box_level, mpole_grad, a);
+  if (st || n_parent == 0) return st;
+  a.transpose = 1;
+  return launch_l2l(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
+int fmm_l2l_adjoint(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+                    const double* box_center, const int32_t* box_level, void* local_grad, void* stream) {
+  TransArgs a{};
+  const int st = trans_args(plan, n_parent, parent, child, n_box, box_center, box_level, local_grad, a);
+  if (st || n_parent == 0) return st;
+  a.transpose = 1;
+  return launch_m2m(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
+}
+
 int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
             const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local, void* potential,
             void* stream) {

@@ -52,6 +52,9 @@ struct TransArgs {
   int32_t nc;
   int32_t c;
   RecArgs rec;
+  // transposes: the M2M kernel with the translation reversed and the parent accumulated is
+  // the transpose of L2L, the L2L kernel with the translation reversed that of M2M
+  int32_t transpose;
 };
 
 struct L2PArgs {

@@ -9,6 +9,11 @@
 // L2L (eq. l2l-expr, derivative form): the parent's local is decompressed (M), translated
 // by h = c_child - c_parent and the kept entries are added to the child's local.
 //
+// Transposes (for gradients): in the scaled form below, M2M^T is the L2L computation with the
+// translation vector reversed (read at the parent, added at the child), and L2L^T is the M2M
+// computation with the translation vector reversed, added to the parent instead of
+// overwriting it (TransArgs::transpose).
+//
 // Both translations are separable, one axis at a time (the nested partial sums of the proof
 // of the O(p^d) translation theorems): since the compressed coefficients have m_z < c, every
 // pass except the one along z touches only the kept prefix of the full order, and the z pass
@@ -116,9 +121,10 @@ __global__ __launch_bounds__(64 * kids_at_once(P, CPLX)) void m2m_kernel(TransAr
     if (lane == 0) ok[wave] = have;
     if (have) {
       const double hc = a.level_h[clamp_level(a, cb)];
-      const double delta[3] = {(a.center[3 * pb] - a.center[3 * cb]) / hp,
-                               (a.center[3 * pb + 1] - a.center[3 * cb + 1]) / hp,
-                               (a.center[3 * pb + 2] - a.center[3 * cb + 2]) / hp};
+      const double sg = a.transpose ? -1.0 : 1.0;  // c_parent - c_child, or reversed
+      const double delta[3] = {sg * (a.center[3 * pb] - a.center[3 * cb]) / hp,
+                               sg * (a.center[3 * pb + 1] - a.center[3 * cb + 1]) / hp,
+                               sg * (a.center[3 * pb + 2] - a.center[3 * cb + 2]) / hp};
       shift_factors<P>(lane, delta, hc / hp, sh[wave], rp[wave]);
     }
     __syncthreads();
@@ -185,7 +191,11 @@ __global__ __launch_bounds__(64 * kids_at_once(P, CPLX)) void m2m_kernel(TransAr
   __syncthreads();
   detail_p2m::compress_lds<P, CPLX>(sig, a.rec, c, hp);
   R* out = reinterpret_cast<R*>(a.coef) + (int64_t)pb * nc * W;
-  for (int k = threadIdx.x; k < nc * W; k += NT) out[k] = (R)sig[k];
+  if (a.transpose) {
+    for (int k = threadIdx.x; k < nc * W; k += NT) out[k] += (R)sig[k];
+  } else {
+    for (int k = threadIdx.x; k < nc * W; k += NT) out[k] = (R)sig[k];
+  }
 }
 
 template <int P, typename R, bool CPLX>
@@ -214,9 +224,10 @@ __global__ __launch_bounds__(64 * kids_at_once(P, CPLX)) void l2l_kernel(TransAr
     __syncthreads();  // the previous group is done with buf and sh
     if (have) {
       const double hc = a.level_h[clamp_level(a, cb)];
-      const double delta[3] = {(a.center[3 * cb] - a.center[3 * pb]) / hp,
-                               (a.center[3 * cb + 1] - a.center[3 * pb + 1]) / hp,
-                               (a.center[3 * cb + 2] - a.center[3 * pb + 2]) / hp};
+      const double sg = a.transpose ? -1.0 : 1.0;  // c_child - c_parent, or reversed
+      const double delta[3] = {sg * (a.center[3 * cb] - a.center[3 * pb]) / hp,
+                               sg * (a.center[3 * cb + 1] - a.center[3 * pb + 1]) / hp,
+                               sg * (a.center[3 * cb + 2] - a.center[3 * pb + 2]) / hp};
       shift_factors<P>(lane, delta, hc / hp, sh[wave], rp[wave]);
     }
     __syncthreads();

@@ -1,14 +1,20 @@
 """The far field of a tree pass built from the hot-path operators, with a hand-written adjoint.
 
 For a uniform octree the far field of every target box is the sum over its List-2 source
-boxes at every level >= 2; each box's multipole is formed by P2M straight from its points
-(every box's points are one Morton range at every level) and each level's local expansion is
-evaluated by L2P at that level's boxes.  ``FarField`` sets this up once (plans, prepared M2L
-batches and their transposes) and ``apply`` runs it as a torch.autograd.Function:
+boxes at every level >= 2.  Two ways to form it:
+  - per level (default): each box's multipole is formed by P2M straight from its points (every
+    box's points are one Morton range at every level) and each level's local expansion is
+    evaluated by L2P at that level's boxes;
+  - tree pass (tree_pass=True): P2M at the leaves, compressed M2M up the tree (Sec. 4.3),
+    M2L at every level, compressed L2L down the tree (Sec. 4.2) and L2P at the leaves.  For
+    Laplace and biharmonic the two agree to roundoff; for Helmholtz and Yukawa they differ at
+    the truncation level.
+``FarField`` sets this up once (plans, prepared M2L batches and their transposes) and
+``apply`` runs it as a torch.autograd.Function:
 
     phi = FarField(...).apply(w, src_xyz, tgt_xyz)
 
-whose backward calls only the HIP adjoints (L2P^T, M2L^T, P2M^T) and returns
+whose backward calls only the HIP adjoints (L2P^T, L2L^T, M2L^T, M2M^T, P2M^T) and returns
 d L / d w, d L / d src_xyz and d L / d tgt_xyz for the frozen tree (box membership of the
 points is fixed when FarField is built).
 """
@@ -24,7 +30,7 @@ from . import fmm
 
 class FarField:
     def __init__(self, kernel: str, order: int, dtype: str, src_tree: "W.Tree", tgt_tree: "W.Tree",
-                 param: float = 0.0, levels=None, device="cuda"):
+                 param: float = 0.0, levels=None, device="cuda", tree_pass: bool = False):
         assert src_tree.n_levels == tgt_tree.n_levels and np.array_equal(src_tree.ijk, tgt_tree.ijk), \
             "source and target trees must share the box grid (uniform trees of one depth)"
         self.desc = fmm.Desc(kernel, order, dtype, param)
@@ -45,11 +51,28 @@ class FarField:
         self.level_boxes = {l: (int(src_tree.level_start[l]), int(src_tree.level_start[l + 1])) for l in self.levels}
         lo, hi = self.level_boxes[self.levels[0]][0], self.level_boxes[self.levels[-1]][1]
         self.box_lo, self.box_hi = lo, hi  # boxes with multipoles / locals
+        self.tree_pass = tree_pass
+        if tree_pass:
+            self.leaf = n_lev - 1
+            assert self.levels == list(range(self.levels[0], n_lev)), \
+                "the tree pass needs every level from the first M2L level to the leaves"
+            self.level_boxes[self.leaf] = (int(src_tree.level_start[self.leaf]), int(src_tree.level_start[self.leaf + 1]))
+            # parents on level l and their children on level l + 1
+            self.family = {}
+            for l in range(self.levels[0], self.leaf):
+                par, ch = W.children(src_tree, l)
+                self.family[l] = (torch.as_tensor(par, device=dev), torch.as_tensor(ch, device=dev))
 
     def _sl(self, a):
         return a[self.box_lo:self.box_hi]
 
+    def _leaf_call(self, fn, rng, *args, **kw):
+        a, b = self.level_boxes[self.leaf]
+        return fn(self.center[a:b], self.level[a:b], rng[a:b], *args, **kw)
+
     def forward_raw(self, w, src, tgt):
+        if self.tree_pass:
+            return self._forward_tree(w, src, tgt)
         d = self.desc
         nc = self.plan.nc
         mpole = torch.zeros((self.n_box, nc), dtype=d.value_dtype, device=w.device)
@@ -66,7 +89,42 @@ class FarField:
             self.plan.l2p(self.center[a:b], self.level[a:b], self.tgt_rng[a:b], tgt, local[a:b], pot)
         return pot, mpole, local
 
+    def _forward_tree(self, w, src, tgt):
+        d = self.desc
+        mpole = torch.zeros((self.n_box, self.plan.nc), dtype=d.value_dtype, device=w.device)
+        a, b = self.level_boxes[self.leaf]
+        self._leaf_call(self.plan.p2m, self.src_rng, src, w, out=mpole[a:b])
+        for l in reversed(range(self.levels[0], self.leaf)):  # children before parents
+            self.plan.m2m(*self.family[l], self.center, self.level, mpole)
+        local = torch.zeros_like(mpole)
+        self.batch(mpole, local)
+        for l in range(self.levels[0], self.leaf):  # parents before children
+            self.plan.l2l(*self.family[l], self.center, self.level, local)
+        pot = torch.zeros(tgt.shape[0], dtype=d.value_dtype, device=w.device)
+        self._leaf_call(self.plan.l2p, self.tgt_rng, tgt, local[a:b], pot)
+        return pot, mpole, local
+
+    def _backward_tree(self, g, w, src, tgt, local, need_w, need_src, need_tgt):
+        a, b = self.level_boxes[self.leaf]
+        local_grad = torch.zeros_like(local)
+        tgt_grad = torch.zeros_like(tgt) if need_tgt else None
+        self._leaf_call(self.plan.l2p_adjoint, self.tgt_rng, tgt, g, local_grad=local_grad[a:b],
+                        local=local[a:b] if need_tgt else None, tgt_grad=tgt_grad)
+        for l in reversed(range(self.levels[0], self.leaf)):  # L2L^T: children before parents
+            self.plan.l2l_adjoint(*self.family[l], self.center, self.level, local_grad)
+        mpole_grad = torch.zeros_like(local)
+        self.batch_t(local_grad, mpole_grad)
+        for l in range(self.levels[0], self.leaf):  # M2M^T: parents before children
+            self.plan.m2m_adjoint(*self.family[l], self.center, self.level, mpole_grad)
+        w_grad = torch.zeros_like(w) if need_w else None
+        src_grad = torch.zeros_like(src) if need_src else None
+        self._leaf_call(self.plan.p2m_adjoint, self.src_rng, src, w, mpole_grad[a:b], w_grad=w_grad,
+                        src_grad=src_grad)
+        return w_grad, src_grad, tgt_grad
+
     def backward_raw(self, g, w, src, tgt, local, need_w=True, need_src=True, need_tgt=True):
+        if self.tree_pass:
+            return self._backward_tree(g, w, src, tgt, local, need_w, need_src, need_tgt)
         local_grad = torch.zeros_like(local)
         tgt_grad = torch.zeros_like(tgt) if need_tgt else None
         # L2P^T level by level (point ranges of one call are disjoint): local gradients of the

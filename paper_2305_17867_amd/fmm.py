@@ -204,6 +204,20 @@ class Plan:
                                   _ptr(local), _stream()), "fmm_l2l")
         return local
 
+    def m2m_adjoint(self, parent, child, center, level, mpole_grad) -> torch.Tensor:
+        """mpole_grad[child[k, :]] += M2M^T of mpole_grad[parent[k]]."""
+        npar, nb = self._tree(parent, child, center, level, mpole_grad, "mpole_grad")
+        check(_lib.load().fmm_m2m_adjoint(self._h, npar, _ptr(parent), _ptr(child), nb, _ptr(center),
+                                          _ptr(level), _ptr(mpole_grad), _stream()), "fmm_m2m_adjoint")
+        return mpole_grad
+
+    def l2l_adjoint(self, parent, child, center, level, local_grad) -> torch.Tensor:
+        """local_grad[parent[k]] += L2L^T of local_grad[child[k, :]]."""
+        npar, nb = self._tree(parent, child, center, level, local_grad, "local_grad")
+        check(_lib.load().fmm_l2l_adjoint(self._h, npar, _ptr(parent), _ptr(child), nb, _ptr(center),
+                                          _ptr(level), _ptr(local_grad), _stream()), "fmm_l2l_adjoint")
+        return local_grad
+
     def l2p_adjoint(self, center, level, rng, tgt, pot_grad, local_grad=None, local=None, tgt_grad=None):
         """local_grad (overwritten) = L2P^T(pot_grad); tgt_grad (accumulated) += pot_grad * grad phi
         when given (needs the forward local expansions `local`)."""

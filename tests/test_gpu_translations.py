@@ -192,3 +192,65 @@ def test_m2m_of_leaf_moments_equals_parent_moments(gpu_lib, uniform3, kernel, pa
     parents, child = W.children(tr, 2)
     plan.m2m(dev(parents, torch.int32), dev(child, torch.int32), cen, lev, moved)
     assert rel(host(moved[parents]), host(direct[parents])) < 1e-12
+
+
+@pytest.mark.parametrize("kernel,param", CASES)
+def test_adjoints_are_the_transposes(gpu_lib, uniform3, kernel, param):
+    """<M2M b, g> = <b, M2M^T g> and <L2L t, g> = <t, L2L^T g> (bilinear, no conjugation), with
+    M2M / L2L and their transposes all run on the GPU."""
+    fmm = gpu_lib
+    tr = uniform3
+    d, plan, _ = make(fmm, kernel, param, 6, False, tr)
+    cplx = d.value_dtype.is_complex
+    parents, child = W.children(tr, 2)
+    par, ch = dev(parents, torch.int32), dev(child, torch.int32)
+    cen, lev = dev(tr.center, torch.float64), dev(tr.level, torch.int32)
+    kids = child.ravel()
+    for seed, fwd, adj, out_boxes, in_boxes in (
+            (51, plan.m2m, plan.m2m_adjoint, parents, kids),
+            (52, plan.l2l, plan.l2l_adjoint, kids, parents)):
+        x = random_coefs(tr, plan.nc, cplx, seed)
+        g = random_coefs(tr, plan.nc, cplx, seed + 10)
+        # forward applied to x on the input boxes only
+        xin = np.zeros_like(x)
+        xin[in_boxes] = x[in_boxes]
+        y = dev(xin, d.value_dtype)
+        fwd(par, ch, cen, lev, y)
+        y = host(y)
+        if fwd == plan.l2l:
+            y[in_boxes] = 0  # L2L accumulates into the children: keep only what it added
+        lhs = np.sum(y[out_boxes] * g[out_boxes])
+        gin = np.zeros_like(g)
+        gin[out_boxes] = g[out_boxes]
+        z = dev(gin, d.value_dtype)
+        adj(par, ch, cen, lev, z)
+        z = host(z)
+        rhs = np.sum(x[in_boxes] * (z[in_boxes] - gin[in_boxes]))
+        assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0), (kernel, fwd, lhs, rhs)
+
+
+def _tree_far_field(dtype, tree_pass, kernel="laplace", param=0.0, p=8, n=3000, depth=4):
+    from paper_2305_17867_amd.farfield import FarField
+    ts = W.uniform_tree(W.uniform_points(n, 61), depth)
+    tt = W.uniform_tree(W.uniform_points(n, 62), depth)
+    ff = FarField(kernel, p, dtype, ts, tt, param=param, tree_pass=tree_pass)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    w = dev(W.normal_weights(n, 63), tdt).requires_grad_(True)
+    s = dev(ts.points, tdt).requires_grad_(True)
+    t = dev(tt.points, tdt).requires_grad_(True)
+    c = dev(W.normal_weights(n, 64), tdt)
+    phi = ff.apply(w, s, t)
+    (phi * c).sum().backward()
+    return [host(v) for v in (phi.detach(), w.grad, s.grad, t.grad)]
+
+
+@pytest.mark.parametrize("kernel,param,tol", [("laplace", 0.0, 1e-12), ("biharmonic", 0.0, 1e-12),
+                                              ("yukawa", 2.0, 1e-4)])
+def test_tree_pass_far_field_matches_per_level(gpu_lib, kernel, param, tol):
+    """P2M + M2M up + M2L + L2L down + L2P at the leaves, forward and backward, against P2M and
+    L2P at every level: equal to roundoff for Laplace and biharmonic (M2M and L2L exact), at
+    truncation level for Yukawa."""
+    tree = _tree_far_field("f64", True, kernel, param)
+    per_level = _tree_far_field("f64", False, kernel, param)
+    for a, b in zip(tree, per_level):
+        assert rel(a, b) < tol
