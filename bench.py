@@ -338,15 +338,16 @@ def plummer_helmholtz(torch, fmm, dt, reps=5):
             "tflops": flops / sec / 1e12, "frac": flops / sec / PEAK["f64" if dt == "c128" else "f32"]}
 
 
-def gradient_pass(torch, dt, reps=10):
+def gradient_pass(torch, dt, reps=10, tree_pass=False):
     """Laplace p = 10 far field of 2^21 sources at 2^21 targets (depth-4 octrees) and its
-    adjoint: forward and forward + backward times."""
+    adjoint: forward and forward + backward times (per level, or as a tree pass with M2M and
+    L2L)."""
     import workloads as W
     from paper_2305_17867_amd.farfield import FarField
     n = 1 << 21
     ts = W.uniform_tree(W.uniform_points(n, 5), 4)
     tt = W.uniform_tree(W.uniform_points(n, 6), 4)
-    ff = FarField("laplace", 10, dt, ts, tt)
+    ff = FarField("laplace", 10, dt, ts, tt, tree_pass=tree_pass)
     tdt = torch.float64 if dt == "f64" else torch.float32
     w = torch.as_tensor(W.normal_weights(n, 7), dtype=tdt, device="cuda").requires_grad_(True)
     S = torch.as_tensor(ts.points, dtype=tdt, device="cuda").requires_grad_(True)
@@ -364,7 +365,8 @@ def gradient_pass(torch, dt, reps=10):
     # existing gradients); keep them out of the timed passes
     for _ in range(2):
         fwd_bwd()
-    return {"workload": "uniform 2^21 sources + 2^21 targets, depth 4, laplace p10, far field", "dtype": dt,
+    return {"workload": "uniform 2^21 sources + 2^21 targets, depth 4, laplace p10, far field",
+            "form": "tree pass (M2M / L2L)" if tree_pass else "per level (P2M / L2P at every level)", "dtype": dt,
             "forward_ms": time_kernel(torch, fwd, reps) * 1e3, "forward_backward_ms": time_kernel(torch, fwd_bwd, reps) * 1e3}
 
 
@@ -458,7 +460,7 @@ def main():
         log("Plummer Helmholtz, one launch over all levels")
         out["plummer_helmholtz"] = [plummer_helmholtz(torch, fmm, dt) for dt in ("c128", "c64")]
         log("far-field gradient pass")
-        out["gradient"] = [gradient_pass(torch, dt) for dt in ("f32", "f64")]
+        out["gradient"] = [gradient_pass(torch, dt, tree_pass=tp) for tp in (False, True) for dt in ("f32", "f64")]
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
