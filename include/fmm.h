@@ -218,12 +218,13 @@ int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, co
                        const fmm_m2l_tuning* tuning, fmm_batch* batch);
 
 /* Prepare the FFT form of the batched M2L (eq. convolution_m2l): per table and per source box a
- * real 3-D DFT of size (2c-1) x (2p+1) x (2p+1) (Hermitian half kept), per target box the sum of
- * spectral products over its pairs and one inverse DFT; the inputs are rescaled by
- * tau = max(1, p/4) (Sec. 4.1.1) for accuracy.  fmm_m2l_batched then computes the same result
- * as the matrix-core path (to the FFT's rounding error, which grows with p).  Real dtypes only
- * (FMM_EUNSUPPORTED otherwise); same pair arguments as fmm_m2l_prepare.  Allocates the spectra
- * of all n_box boxes. */
+ * 3-D DFT of size (2c-1) x (2p+1) x (2p+1) (real dtypes: Hermitian half kept; complex dtypes:
+ * full spectrum), per target box the sum of spectral products over its pairs and one inverse
+ * DFT; the inputs are rescaled by tau = max(1, p/4) (Sec. 4.1.1) for accuracy.
+ * fmm_m2l_batched then computes the same result as the matrix-core path (to the FFT's rounding
+ * error, which grows with p).  FMM_EUNSUPPORTED when the working set exceeds the LDS of a
+ * workgroup (high orders); same pair arguments as fmm_m2l_prepare.  Allocates the spectra of
+ * all n_box boxes. */
 int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
                         int64_t n_box, const int32_t* box_ijk, const int32_t* box_level, fmm_batch* batch);
 

@@ -831,11 +831,11 @@ int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   FMM_REQUIRE(out, FMM_EINVAL, "batch output pointer is NULL");
   *out = nullptr;
   const int dtype = plan->desc.dtype;
-  FMM_REQUIRE(!dtype_complex(dtype), FMM_EUNSUPPORTED, "the FFT M2L path is implemented for real dtypes");
+  const bool cplx = dtype_complex(dtype);
   FMM_REQUIRE(n_pair >= 0 && n_box >= 0 && n_box <= (int64_t)0x7fffffff && n_pair <= (int64_t)0x7fffffff,
               FMM_EINVAL, "bad sizes");
   FMM_REQUIRE(n_pair == 0 || (tgt_box && src_box && box_ijk && box_level), FMM_EINVAL, "NULL host array");
-  const int S = plan->S, Sz = plan->Sz, Hy = (S + 1) / 2, nh = Sz * S * Hy;
+  const int S = plan->S, Sz = plan->Sz, Hy = fft_half_y(S, cplx), nh = Sz * S * Hy;
   FMM_REQUIRE((nh + 255) / 256 <= kFftMaxPerThread, FMM_EUNSUPPORTED, "order too high for the FFT M2L path");
   int dev = 0, lds_max = 65536;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -843,7 +843,7 @@ int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) lds_max = v;
   }
   (void)hipGetLastError();
-  FMM_REQUIRE(fft_lds_bytes(S, Sz, real_size(dtype)) <= (size_t)lds_max, FMM_EUNSUPPORTED,
+  FMM_REQUIRE(fft_lds_bytes(S, Sz, real_size(dtype), cplx) <= (size_t)lds_max, FMM_EUNSUPPORTED,
               "FFT M2L working set exceeds LDS for this order");
   // (level, offset) tables and per-target pair lists
   std::unordered_map<int64_t, int32_t> tab_of_key;
@@ -933,7 +933,7 @@ int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
       dev_free(d_h);
       return bail(st);
     }
-    if (hipMalloc((void**)&d_tab64, (size_t)b->n_tab * Sz * S * S * sizeof(double)) != hipSuccess ||
+    if (hipMalloc((void**)&d_tab64, (size_t)b->n_tab * Sz * S * S * sizeof(double) * (cplx ? 2 : 1)) != hipSuccess ||
         hipMalloc(&a.spec_tab, (size_t)b->n_tab * nh * cb) != hipSuccess) {
       dev_free(d_off);
       dev_free(d_h);

@@ -4,8 +4,9 @@
 // derivative grid g[m] = T~[m], m in [0, 2M] (M = (p, p, c - 1), grid (2c-1) x (2p+1) x (2p+1),
 // index (m_z, m_x, m_y)), with the kept coefficients.  Embedding b[(-q) mod L] = beta~_q in the
 // same grid turns it into a circular convolution: theta~ = IDFT(DFT(g) . DFT(b)) restricted to J.
-// Both inputs are real (real dtypes), so every spectrum is kept as its Hermitian half along y
-// ((2p+1+1)/2 of the 2p+1 y frequencies).  To keep the transforms accurate the inputs are
+// For real dtypes both inputs are real, so every spectrum is kept as its Hermitian half along y
+// ((2p+1+1)/2 of the 2p+1 y frequencies); for complex dtypes (Helmholtz) the tables and the
+// coefficients are complex and the full spectrum is kept.  To keep the transforms accurate the inputs are
 // rescaled as in Sec. 4.1.1 with an extra parameter tau: g[m] tau^-|m|, beta~_q tau^|q|, and the
 // outputs multiplied by tau^|i|.
 //
@@ -30,24 +31,39 @@ struct C2 {
   R re, im;
 };
 
-// Forward real 3-D DFT of the grid held in LDS (real, [Sz][S][S]) into the half spectrum
+// y frequencies kept: the Hermitian half for real grids, all of them for complex grids
+__host__ __device__ inline int half_y(int S, bool cplx) { return cplx ? S : (S + 1) / 2; }
+
+// Forward 3-D DFT of the grid held in LDS ([Sz][S][S], real or complex) into the spectrum
 // out[kz][kx][ky] (ky < Hy), using ping-pong complex LDS buffers.
-template <typename R>
-__device__ void dft_forward(const R* grid, C2<R>* b1, C2<R>* b2, const C2<R>* wS, const C2<R>* wZ,
+template <typename R, bool CPLX>
+__device__ void dft_forward(const void* gridv, C2<R>* b1, C2<R>* b2, const C2<R>* wS, const C2<R>* wZ,
                             int S, int Sz, int Hy, C2<R>* out_global) {
   const int nh = Sz * S * Hy;
-  // y (real -> half complex)
+  // y (real -> half complex, or complex -> complex)
   for (int f = threadIdx.x; f < nh; f += blockDim.x) {
     const int z = f / (S * Hy), r = f % (S * Hy), x = r / Hy, ky = r % Hy;
-    const R* line = grid + (z * S + x) * S;
     R sr = 0, si = 0;
     int idx = 0;
-    for (int y = 0; y < S; ++y) {
-      const R v = line[y];
-      sr += v * wS[idx].re;
-      si += v * wS[idx].im;
-      idx += ky;
-      if (idx >= S) idx -= S;
+    if constexpr (CPLX) {
+      const C2<R>* line = reinterpret_cast<const C2<R>*>(gridv) + (z * S + x) * S;
+      for (int y = 0; y < S; ++y) {
+        const C2<R> v = line[y];
+        const C2<R> w = wS[idx];
+        sr += v.re * w.re - v.im * w.im;
+        si += v.re * w.im + v.im * w.re;
+        idx += ky;
+        if (idx >= S) idx -= S;
+      }
+    } else {
+      const R* line = reinterpret_cast<const R*>(gridv) + (z * S + x) * S;
+      for (int y = 0; y < S; ++y) {
+        const R v = line[y];
+        sr += v * wS[idx].re;
+        si += v * wS[idx].im;
+        idx += ky;
+        if (idx >= S) idx -= S;
+      }
     }
     b1[f] = {sr, si};
   }
@@ -97,58 +113,72 @@ __device__ void load_twiddles(C2<R>* wS, C2<R>* wZ, int S, int Sz) {
   }
 }
 
-// tables: grid = T~[m] tau^-|m| (double input, layout of the derivative tables)
-template <typename R>
+// LDS layout of the transform kernels: [grid: ng values, real or complex][b1, b2: nh complex each]
+// [twiddles S + Sz complex]
+template <typename R, bool CPLX>
+__device__ inline C2<R>* after_grid(char* smem, int ng) {
+  return CPLX ? reinterpret_cast<C2<R>*>(smem) + ng : reinterpret_cast<C2<R>*>(reinterpret_cast<R*>(smem) + ((ng + 1) & ~1));
+}
+
+// tables: grid = T~[m] tau^-|m| (double input, layout of the derivative tables; complex tables
+// interleaved)
+template <typename R, bool CPLX>
 __global__ __launch_bounds__(kFftThreads) void fft_tables_kernel(FftArgs a) {
   extern __shared__ __align__(16) char smem[];
-  const int S = a.S, Sz = a.Sz, Hy = (a.S + 1) / 2, ng = Sz * S * S, nh = Sz * S * Hy;
+  constexpr int W = CPLX ? 2 : 1;
+  const int S = a.S, Sz = a.Sz, Hy = half_y(a.S, CPLX), ng = Sz * S * S, nh = Sz * S * Hy;
   R* grid = reinterpret_cast<R*>(smem);
-  C2<R>* b1 = reinterpret_cast<C2<R>*>(grid + ((ng + 1) & ~1));
+  C2<R>* b1 = after_grid<R, CPLX>(smem, ng);
   C2<R>* b2 = b1 + nh;
   C2<R>* wS = b2 + nh;
   C2<R>* wZ = wS + S;
   load_twiddles(wS, wZ, S, Sz);
-  const double* src = a.tab64 + (int64_t)blockIdx.x * ng;
+  const double* src = a.tab64 + (int64_t)blockIdx.x * ng * W;
   for (int k = threadIdx.x; k < ng; k += blockDim.x) {
     const int z = k / (S * S), r = k % (S * S), x = r / S, y = r % S;
-    grid[k] = (R)(src[k] * pow(a.tau, -(double)(x + y + z)));
+    const double sc = pow(a.tau, -(double)(x + y + z));
+#pragma unroll
+    for (int u = 0; u < W; ++u) grid[k * W + u] = (R)(src[k * W + u] * sc);
   }
   __syncthreads();
-  dft_forward<R>(grid, b1, b2, wS, wZ, S, Sz, Hy,
-                 reinterpret_cast<C2<R>*>(a.spec_tab) + (int64_t)blockIdx.x * nh);
+  dft_forward<R, CPLX>(grid, b1, b2, wS, wZ, S, Sz, Hy,
+                       reinterpret_cast<C2<R>*>(a.spec_tab) + (int64_t)blockIdx.x * nh);
 }
 
 // sources: grid = beta~ embedded at (-q) mod L, times tau^|q|
-template <typename R>
+template <typename R, bool CPLX>
 __global__ __launch_bounds__(kFftThreads) void fft_sources_kernel(FftArgs a) {
   extern __shared__ __align__(16) char smem[];
-  const int S = a.S, Sz = a.Sz, Hy = (a.S + 1) / 2, ng = Sz * S * S, nh = Sz * S * Hy;
+  constexpr int W = CPLX ? 2 : 1;
+  const int S = a.S, Sz = a.Sz, Hy = half_y(a.S, CPLX), ng = Sz * S * S, nh = Sz * S * Hy;
   R* grid = reinterpret_cast<R*>(smem);
-  C2<R>* b1 = reinterpret_cast<C2<R>*>(grid + ((ng + 1) & ~1));
+  C2<R>* b1 = after_grid<R, CPLX>(smem, ng);
   C2<R>* b2 = b1 + nh;
   C2<R>* wS = b2 + nh;
   C2<R>* wZ = wS + S;
   load_twiddles(wS, wZ, S, Sz);
   const int box = a.src_list[blockIdx.x];
-  for (int k = threadIdx.x; k < ng; k += blockDim.x) grid[k] = R(0);
+  for (int k = threadIdx.x; k < ng * W; k += blockDim.x) grid[k] = R(0);
   __syncthreads();
-  const R* beta = reinterpret_cast<const R*>(a.mpole) + (int64_t)box * a.nc;
+  const R* beta = reinterpret_cast<const R*>(a.mpole) + (int64_t)box * a.nc * W;
   for (int k = threadIdx.x; k < a.nc; k += blockDim.x) {
     const int pk = a.jxyz[k];
     const int qx = pk & 255, qy = (pk >> 8) & 255, qz = pk >> 16;
     const int z = (Sz - qz) % Sz, x = (S - qx) % S, y = (S - qy) % S;
-    grid[(z * S + x) * S + y] = beta[k] * (R)a.taupow[qx + qy + qz];
+    const R t = (R)a.taupow[qx + qy + qz];
+#pragma unroll
+    for (int u = 0; u < W; ++u) grid[((z * S + x) * S + y) * W + u] = beta[k * W + u] * t;
   }
   __syncthreads();
-  dft_forward<R>(grid, b1, b2, wS, wZ, S, Sz, Hy,
-                 reinterpret_cast<C2<R>*>(a.spec_src) + (int64_t)box * nh);
+  dft_forward<R, CPLX>(grid, b1, b2, wS, wZ, S, Sz, Hy,
+                       reinterpret_cast<C2<R>*>(a.spec_src) + (int64_t)box * nh);
 }
 
 // per target: sum of spectral products over the interaction list, inverse transform, extract J
-template <typename R>
+template <typename R, bool CPLX>
 __global__ __launch_bounds__(kFftThreads) void fft_targets_kernel(FftArgs a) {
   extern __shared__ __align__(16) char smem[];
-  const int S = a.S, Sz = a.Sz, Hy = (a.S + 1) / 2, nh = Sz * S * Hy;
+  const int S = a.S, Sz = a.Sz, Hy = half_y(a.S, CPLX), nh = Sz * S * Hy;
   C2<R>* b1 = reinterpret_cast<C2<R>*>(smem);
   C2<R>* b2 = b1 + nh;
   C2<R>* wS = b2 + nh;
@@ -213,34 +243,52 @@ __global__ __launch_bounds__(kFftThreads) void fft_targets_kernel(FftArgs a) {
     b1[f] = {sr, si};
   }
   __syncthreads();
-  // inverse y (half complex -> real) at the kept indices only, scaled and accumulated
+  // inverse y at the kept indices only (half complex -> real, or complex -> complex), scaled
+  // and accumulated
   const double norm = 1.0 / ((double)Sz * S * S);
-  R* out = reinterpret_cast<R*>(a.local) + (int64_t)tgt * a.nc;
+  constexpr int W = CPLX ? 2 : 1;
+  R* out = reinterpret_cast<R*>(a.local) + (int64_t)tgt * a.nc * W;
   for (int k = threadIdx.x; k < a.nc; k += blockDim.x) {
     const int pk = a.jxyz[k];
     const int ix = pk & 255, iy = (pk >> 8) & 255, iz = pk >> 16;
     const C2<R>* line = b1 + (iz * S + ix) * Hy;
-    R s = line[0].re;
-    int idx = iy;
-    for (int ky = 1; ky < Hy; ++ky) {
-      const C2<R> v = line[ky], w = wS[idx];
-      s += R(2) * (v.re * w.re + v.im * w.im);
-      idx += iy;
-      if (idx >= S) idx -= S;
+    const double sc = norm * a.taupow[ix + iy + iz];
+    if constexpr (CPLX) {
+      R sr = 0, si = 0;
+      int idx = 0;
+      for (int ky = 0; ky < S; ++ky) {
+        const C2<R> v = line[ky], w = wS[idx];
+        sr += v.re * w.re + v.im * w.im;
+        si += v.im * w.re - v.re * w.im;
+        idx += iy;
+        if (idx >= S) idx -= S;
+      }
+      out[2 * k] = (R)((double)out[2 * k] + (double)sr * sc);
+      out[2 * k + 1] = (R)((double)out[2 * k + 1] + (double)si * sc);
+    } else {
+      R s = line[0].re;
+      int idx = iy;
+      for (int ky = 1; ky < Hy; ++ky) {
+        const C2<R> v = line[ky], w = wS[idx];
+        s += R(2) * (v.re * w.re + v.im * w.im);
+        idx += iy;
+        if (idx >= S) idx -= S;
+      }
+      out[k] = (R)((double)out[k] + (double)s * sc);
     }
-    out[k] = (R)((double)out[k] + (double)s * norm * a.taupow[ix + iy + iz]);
   }
 }
 
-size_t fft_lds(int S, int Sz, size_t rb, bool with_grid) {
-  const int Hy = (S + 1) / 2, ng = Sz * S * S, nh = Sz * S * Hy;
-  return (with_grid ? (size_t)((ng + 1) & ~1) * rb : 0) + (2 * (size_t)nh + S + Sz) * 2 * rb;
+size_t fft_lds(int S, int Sz, size_t rb, bool cplx, bool with_grid) {
+  const int ng = Sz * S * S, nh = Sz * S * half_y(S, cplx);
+  const size_t grid = cplx ? (size_t)ng * 2 * rb : (size_t)((ng + 1) & ~1) * rb;
+  return (with_grid ? grid : 0) + (2 * (size_t)nh + S + Sz) * 2 * rb;
 }
 
-template <typename R>
+template <typename R, bool CPLX>
 int launch_fft_t(const FftArgs& a, int which, hipStream_t s) {
   const bool grid = which != 2;
-  const size_t lds = fft_lds(a.S, a.Sz, sizeof(R), grid);
+  const size_t lds = fft_lds(a.S, a.Sz, sizeof(R), CPLX, grid);
   auto set_lds = [&](const void* k) -> int {
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -253,16 +301,16 @@ int launch_fft_t(const FftArgs& a, int which, hipStream_t s) {
   };
   if (which == 0) {
     if (a.n_tab == 0) return FMM_OK;
-    if (int st = set_lds(reinterpret_cast<const void*>(fft_tables_kernel<R>))) return st;
-    hipLaunchKernelGGL(fft_tables_kernel<R>, dim3((unsigned)a.n_tab), dim3(kFftThreads), lds, s, a);
+    if (int st = set_lds(reinterpret_cast<const void*>(fft_tables_kernel<R, CPLX>))) return st;
+    hipLaunchKernelGGL((fft_tables_kernel<R, CPLX>), dim3((unsigned)a.n_tab), dim3(kFftThreads), lds, s, a);
   } else if (which == 1) {
     if (a.n_src == 0) return FMM_OK;
-    if (int st = set_lds(reinterpret_cast<const void*>(fft_sources_kernel<R>))) return st;
-    hipLaunchKernelGGL(fft_sources_kernel<R>, dim3((unsigned)a.n_src), dim3(kFftThreads), lds, s, a);
+    if (int st = set_lds(reinterpret_cast<const void*>(fft_sources_kernel<R, CPLX>))) return st;
+    hipLaunchKernelGGL((fft_sources_kernel<R, CPLX>), dim3((unsigned)a.n_src), dim3(kFftThreads), lds, s, a);
   } else {
     if (a.n_tgt == 0) return FMM_OK;
-    if (int st = set_lds(reinterpret_cast<const void*>(fft_targets_kernel<R>))) return st;
-    hipLaunchKernelGGL(fft_targets_kernel<R>, dim3((unsigned)a.n_tgt), dim3(kFftThreads), lds, s, a);
+    if (int st = set_lds(reinterpret_cast<const void*>(fft_targets_kernel<R, CPLX>))) return st;
+    hipLaunchKernelGGL((fft_targets_kernel<R, CPLX>), dim3((unsigned)a.n_tgt), dim3(kFftThreads), lds, s, a);
   }
   FMM_HIP_CHECK(hipGetLastError());
   return FMM_OK;
@@ -270,12 +318,18 @@ int launch_fft_t(const FftArgs& a, int which, hipStream_t s) {
 
 }  // namespace
 
-size_t fft_lds_bytes(int S, int Sz, size_t real_bytes) { return fft_lds(S, Sz, real_bytes, true); }
+size_t fft_lds_bytes(int S, int Sz, size_t real_bytes, bool cplx) { return fft_lds(S, Sz, real_bytes, cplx, true); }
+
+int fft_half_y(int S, bool cplx) { return half_y(S, cplx); }
 
 int launch_fft(const FftArgs& a, int dtype, int which, hipStream_t s) {
-  if (dtype == FMM_F64) return launch_fft_t<double>(a, which, s);
-  if (dtype == FMM_F32) return launch_fft_t<float>(a, which, s);
-  return fail(FMM_EUNSUPPORTED, "the FFT M2L path is implemented for real dtypes");
+  switch (dtype) {
+    case FMM_F64: return launch_fft_t<double, false>(a, which, s);
+    case FMM_F32: return launch_fft_t<float, false>(a, which, s);
+    case FMM_C128: return launch_fft_t<double, true>(a, which, s);
+    case FMM_C64: return launch_fft_t<float, true>(a, which, s);
+    default: return fail(FMM_EINVAL, "dtype");
+  }
 }
 
 }  // namespace fmm

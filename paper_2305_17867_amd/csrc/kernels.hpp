@@ -182,7 +182,8 @@ int m2l_prefetch_class(const M2LArgs& a, bool cplx, int ct_total, int waves);
 bool m2l_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
 int launch_direct(const DirectArgs& a, int dtype, hipStream_t s);
 int launch_fft(const FftArgs& a, int dtype, int which, hipStream_t s);  // 0 tables, 1 sources, 2 targets
-size_t fft_lds_bytes(int S, int Sz, size_t real_bytes);
+size_t fft_lds_bytes(int S, int Sz, size_t real_bytes, bool cplx);
+int fft_half_y(int S, bool cplx);  // y frequencies kept per spectrum line
 int launch_m2l_multi(const M2LMulti& m, int dtype, int rows_per_wave, int col_tiles, int pf_class, int nbuf,
                      size_t lds, int waves, int grid, hipStream_t s);
 bool m2l_multi_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
