@@ -168,6 +168,21 @@ int fmm_m2m(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_
 int fmm_l2l(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
             const double* box_center, const int32_t* box_level, void* local, void* stream);
 
+/* Near field (P2P): eq. (1) restricted to neighbour boxes.  For each k < n_tbox and every
+ * target x of box tbox[k], phi(x) += sum_y G(x - y) w(y) over the sources y of the boxes
+ * nbr[nbr_ptr[k] : nbr_ptr[k+1]] (terms with x == y skipped).  With the far field of the
+ * interaction lists this completes the FMM potential.
+ *   tbox [n_tbox] i32 box ids; nbr_ptr [n_tbox + 1] i32 CSR pointers into nbr [n_nbr] i32
+ *   box ids (ranges are clamped to [0, n_nbr]; ids outside [0, n_box) are skipped)
+ *   tgt_range, src_range [n_box][2] i64 point ranges of every box into tgt / src
+ *   src_xyz [n_src][3] real dtype; weight [n_src] dtype; tgt_xyz [n_tgt][3] real dtype
+ *   potential [n_tgt] dtype, ACCUMULATED.  The target boxes of one call must have disjoint
+ *   point ranges. */
+int fmm_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* nbr_ptr, int64_t n_nbr,
+            const int32_t* nbr, int64_t n_box, const int64_t* tgt_range, const int64_t* src_range, int64_t n_src,
+            const void* src_xyz, const void* weight, int64_t n_tgt, const void* tgt_xyz, void* potential,
+            void* stream);
+
 /* Transposes of fmm_m2m and fmm_l2l for gradients (derived from the same passages).
  * fmm_m2m_adjoint: mpole_grad read at the parents, ACCUMULATED at the children:
  *   grad beta~_child += (M^T T E)^T grad psi~_parent.

@@ -63,6 +63,8 @@ SIGNATURES = {
     "fmm_m2l_batched": (C.c_int, [P, P, P, P]),
     "fmm_m2l_batched_multi": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P), C.POINTER(P), P]),
     "fmm_direct": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P]),
+    "fmm_p2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, C.c_int64, P, P,
+                          C.c_int64, P, P, P]),
     "fmm_l2p_adjoint": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]),
     "fmm_p2m_adjoint": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]),
     "fmm_m2l_prepare_adjoint": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P,

@@ -453,6 +453,39 @@ int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const v
   return launch_direct(a, desc->dtype, (hipStream_t)stream);
 }
 
+int fmm_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* nbr_ptr, int64_t n_nbr,
+            const int32_t* nbr, int64_t n_box, const int64_t* tgt_range, const int64_t* src_range, int64_t n_src,
+            const void* src_xyz, const void* weight, int64_t n_tgt, const void* tgt_xyz, void* potential,
+            void* stream) {
+  int st = check_desc(desc);
+  if (st) return st;
+  FMM_REQUIRE(n_tbox >= 0 && n_tbox <= (int64_t)0x7fffffff, FMM_EINVAL, "n_tbox out of range");
+  FMM_REQUIRE(n_nbr >= 0 && n_box >= 0 && n_src >= 0 && n_tgt >= 0, FMM_EINVAL, "negative size");
+  if (n_tbox == 0) return FMM_OK;
+  FMM_REQUIRE(tbox && nbr_ptr && (n_nbr == 0 || nbr), FMM_EINVAL, "NULL box list");
+  FMM_REQUIRE(tgt_range && src_range, FMM_EINVAL, "NULL point ranges");
+  FMM_REQUIRE(n_tgt == 0 || (tgt_xyz && potential), FMM_EINVAL, "NULL target pointer");
+  FMM_REQUIRE(n_src == 0 || (src_xyz && weight), FMM_EINVAL, "NULL source pointer");
+  P2PArgs a{};
+  a.n_tbox = n_tbox;
+  a.tbox = tbox;
+  a.nbr_ptr = nbr_ptr;
+  a.nbr = nbr;
+  a.n_nbr = n_nbr;
+  a.n_box = n_box;
+  a.tgt_range = tgt_range;
+  a.src_range = src_range;
+  a.n_src = n_src;
+  a.n_tgt = n_tgt;
+  a.src = src_xyz;
+  a.w = weight;
+  a.tgt = tgt_xyz;
+  a.pot = potential;
+  a.kernel = desc->kernel;
+  a.param = desc->param;
+  return launch_p2p(a, desc->dtype, (hipStream_t)stream);
+}
+
 // ------------------------------------------------------------------------------- M2L batches
 
 int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,

@@ -1,5 +1,7 @@
 // Direct sum eq. (1): phi(x) = sum_y G(x - y) w(y), terms with x == y skipped.
 // One thread per target; sources are staged through LDS in tiles of the block size.
+// The near field (P2P) is the same sum restricted, per target box, to the sources of its
+// neighbour boxes: one workgroup per (target box, chunk of 256 targets).
 #include <cmath>
 
 #include "../../include/fmm.h"
@@ -17,6 +19,30 @@ template <typename R>
 __device__ inline R r_sqrt(R v) { return sqrt(v); }
 __device__ inline float r_sqrt(float v) { return sqrtf(v); }
 
+// acc += G(d) w for one source at offset d = x - y (d != 0)
+template <typename R, bool CPLX, typename T>
+__device__ inline void add_green(T& acc, int kernel, R prm, R dx, R dy, R dz, const T& w) {
+  const R inv4pi = R(1.0 / (4.0 * M_PI));
+  const R r2 = dx * dx + dy * dy + dz * dz;
+  if (r2 == R(0)) return;
+  const R r = r_sqrt(r2);
+  if constexpr (CPLX) {
+    // Helmholtz exp(i k r) / (4 pi r)
+    R sn, cs;
+    if constexpr (sizeof(R) == 8) sincos(prm * r, &sn, &cs);
+    else sincosf(prm * r, &sn, &cs);
+    const R g = inv4pi / r;
+    const T G(g * cs, g * sn);
+    acc += G * w;
+  } else {
+    R G;
+    if (kernel == FMM_LAPLACE) G = inv4pi / r;
+    else if (kernel == FMM_YUKAWA) G = exp(-prm * r) * inv4pi / r;
+    else G = r;
+    acc += G * w;
+  }
+}
+
 template <typename R, bool CPLX>
 __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
   using T = typename Val<R, CPLX>::T;
@@ -33,7 +59,6 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
     z = tg[3 * t + 2];
   }
   T acc{};
-  const R inv4pi = R(1.0 / (4.0 * M_PI));
   const R prm = (R)a.param;
   for (int64_t base = 0; base < a.n_src; base += kThreads) {
     __syncthreads();
@@ -46,32 +71,87 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
     }
     __syncthreads();
     const int cnt = (int)((a.n_src - base) < kThreads ? (a.n_src - base) : kThreads);
-    for (int k = 0; k < cnt; ++k) {
-      const R dx = x - sx[k], dy = y - sy[k], dz = z - sz[k];
-      const R r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 == R(0)) continue;
-      const R r = r_sqrt(r2);
-      if constexpr (CPLX) {
-        // Helmholtz exp(i k r) / (4 pi r)
-        R sn, cs;
-        if constexpr (sizeof(R) == 8) sincos(prm * r, &sn, &cs);
-        else sincosf(prm * r, &sn, &cs);
-        const R g = inv4pi / r;
-        const T G(g * cs, g * sn);
-        acc += G * sw[k];
-      } else {
-        R G;
-        if (a.kernel == FMM_LAPLACE) G = inv4pi / r;
-        else if (a.kernel == FMM_YUKAWA) G = exp(-prm * r) * inv4pi / r;
-        else G = r;
-        acc += G * sw[k];
-      }
-    }
+    for (int k = 0; k < cnt; ++k) add_green<R, CPLX>(acc, a.kernel, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
   }
   if (t < a.n_tgt) reinterpret_cast<T*>(a.pot)[t] = acc;
 }
 
+__device__ inline void clamp_range(const int64_t* rng, int64_t b, int64_t n, int64_t& lo, int64_t& hi) {
+  lo = rng[2 * b];
+  hi = rng[2 * b + 1];
+  lo = lo < 0 ? 0 : (lo > n ? n : lo);
+  hi = hi < lo ? lo : (hi > n ? n : hi);
+}
+
+template <typename R, bool CPLX>
+__global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
+  using T = typename Val<R, CPLX>::T;
+  __shared__ R sx[kThreads], sy[kThreads], sz[kThreads];
+  __shared__ T sw[kThreads];
+  const int tb = a.tbox[blockIdx.x];
+  if (tb < 0 || tb >= a.n_box) return;  // uniform
+  int64_t tlo, thi;
+  clamp_range(a.tgt_range, tb, a.n_tgt, tlo, thi);
+  const R* tg = reinterpret_cast<const R*>(a.tgt);
+  const R* sr = reinterpret_cast<const R*>(a.src);
+  const T* w = reinterpret_cast<const T*>(a.w);
+  const R prm = (R)a.param;
+  // the list range, clamped to the list (the CSR pointers are device data)
+  int64_t e0 = a.nbr_ptr[blockIdx.x], e1 = a.nbr_ptr[blockIdx.x + 1];
+  e0 = e0 < 0 ? 0 : (e0 > a.n_nbr ? a.n_nbr : e0);
+  e1 = e1 < e0 ? e0 : (e1 > a.n_nbr ? a.n_nbr : e1);
+  // workgroup y takes the targets tlo + (y + m gridDim.y) kThreads + threadIdx.x
+  for (int64_t t0 = tlo + (int64_t)blockIdx.y * kThreads; t0 < thi; t0 += (int64_t)gridDim.y * kThreads) {
+    const int64_t t = t0 + threadIdx.x;
+    const bool have = t < thi;
+    R x = 0, y = 0, z = 0;
+    if (have) {
+      x = tg[3 * t];
+      y = tg[3 * t + 1];
+      z = tg[3 * t + 2];
+    }
+    T acc{};
+    for (int64_t e = e0; e < e1; ++e) {
+      const int sb = a.nbr[e];
+      if (sb < 0 || sb >= a.n_box) continue;  // uniform
+      int64_t slo, shi;
+      clamp_range(a.src_range, sb, a.n_src, slo, shi);
+      for (int64_t base = slo; base < shi; base += kThreads) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < shi) {
+          sx[threadIdx.x] = sr[3 * j];
+          sy[threadIdx.x] = sr[3 * j + 1];
+          sz[threadIdx.x] = sr[3 * j + 2];
+          sw[threadIdx.x] = w[j];
+        }
+        __syncthreads();
+        const int cnt = (int)((shi - base) < kThreads ? (shi - base) : kThreads);
+        for (int k = 0; k < cnt; ++k) add_green<R, CPLX>(acc, a.kernel, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
+      }
+    }
+    if (have) reinterpret_cast<T*>(a.pot)[t] += acc;
+  }
+}
+
 }  // namespace
+
+int launch_p2p(const P2PArgs& a, int dtype, hipStream_t s) {
+  if (a.n_tbox == 0) return FMM_OK;
+  // workgroups per target box: enough that the average box gets one per kThreads targets
+  const int64_t per_box = (a.n_tgt + a.n_tbox - 1) / a.n_tbox;
+  const int64_t ny = per_box < kThreads ? 1 : (per_box + kThreads - 1) / kThreads < 1024 ? (per_box + kThreads - 1) / kThreads : 1024;
+  dim3 g((unsigned)a.n_tbox, (unsigned)ny), t(kThreads);
+  switch (dtype) {
+    case FMM_F64: hipLaunchKernelGGL((p2p_kernel<double, false>), g, t, 0, s, a); break;
+    case FMM_F32: hipLaunchKernelGGL((p2p_kernel<float, false>), g, t, 0, s, a); break;
+    case FMM_C128: hipLaunchKernelGGL((p2p_kernel<double, true>), g, t, 0, s, a); break;
+    case FMM_C64: hipLaunchKernelGGL((p2p_kernel<float, true>), g, t, 0, s, a); break;
+    default: return fail(FMM_EINVAL, "dtype");
+  }
+  FMM_HIP_CHECK(hipGetLastError());
+  return FMM_OK;
+}
 
 int launch_direct(const DirectArgs& a, int dtype, hipStream_t s) {
   if (a.n_tgt == 0) return FMM_OK;

@@ -169,7 +169,28 @@ struct DirectArgs {
   double param;
 };
 
+// Near field: for each listed target box, the direct sum over the sources of its neighbour
+// boxes (CSR lists), added to the targets' potentials.
+struct P2PArgs {
+  int64_t n_tbox;
+  const int32_t* tbox;       // [n_tbox] target box ids
+  const int32_t* nbr_ptr;    // [n_tbox + 1]
+  const int32_t* nbr;        // [n_nbr] source box ids
+  int64_t n_nbr;
+  int64_t n_box;
+  const int64_t* tgt_range;  // [n_box][2]
+  const int64_t* src_range;  // [n_box][2]
+  int64_t n_src, n_tgt;
+  const void* src;
+  const void* w;
+  const void* tgt;
+  void* pot;                 // accumulated
+  int32_t kernel;
+  double param;
+};
+
 int launch_tables(const TableArgs& a, bool cplx, hipStream_t s);
+int launch_p2p(const P2PArgs& a, int dtype, hipStream_t s);
 int launch_p2m(const P2MArgs& a, int p, int dtype, hipStream_t s);
 int launch_m2m(const TransArgs& a, int p, int dtype, hipStream_t s);
 int launch_l2l(const TransArgs& a, int p, int dtype, hipStream_t s);

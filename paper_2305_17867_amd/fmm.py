@@ -378,6 +378,26 @@ def direct(desc: Desc, src, w, tgt, out=None) -> torch.Tensor:
     return out
 
 
+def p2p(desc: Desc, tbox, nbr_ptr, nbr, tgt_range, src_range, src, w, tgt, pot) -> torch.Tensor:
+    """Near field: pot[targets of tbox[k]] += direct sum over the sources of the boxes
+    nbr[nbr_ptr[k] : nbr_ptr[k + 1]] (fmm_p2p).  Point ranges are per box id."""
+    nt_box, nb = tbox.shape[0], tgt_range.shape[0]
+    ns, nt = src.shape[0], tgt.shape[0]
+    _dev(tbox, torch.int32, "tbox", (nt_box,))
+    _dev(nbr_ptr, torch.int32, "nbr_ptr", (nt_box + 1,))
+    _dev(nbr, torch.int32, "nbr", (nbr.shape[0],))
+    _dev(tgt_range, torch.int64, "tgt_range", (nb, 2))
+    _dev(src_range, torch.int64, "src_range", (nb, 2))
+    _dev(src, desc.real_dtype, "src_xyz", (ns, 3))
+    _dev(w, desc.value_dtype, "weight", (ns,))
+    _dev(tgt, desc.real_dtype, "tgt_xyz", (nt, 3))
+    _dev(pot, desc.value_dtype, "potential", (nt,))
+    check(_lib.load().fmm_p2p(C.byref(desc.c), nt_box, _ptr(tbox), _ptr(nbr_ptr), nbr.shape[0], _ptr(nbr), nb,
+                              _ptr(tgt_range), _ptr(src_range), ns, _ptr(src), _ptr(w), nt, _ptr(tgt), _ptr(pot),
+                              _stream()), "fmm_p2p")
+    return pot
+
+
 class Multi:
     """Several prepared forward batches drained by one persistent launch (fmm_m2l_multi_*).
     The batches must share the dtype and the launch shape (prepare them with one tuning)."""

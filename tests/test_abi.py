@@ -85,6 +85,8 @@ def test_null_arguments_are_rejected_before_any_launch(lib):
     assert L.fmm_m2m(None, 1, None, None, 0, None, None, None, None) == -1
     assert L.fmm_l2l(None, 1, None, None, 0, None, None, None, None) == -1
     assert L.fmm_m2m_adjoint(None, 1, None, None, 0, None, None, None, None) == -1
+    assert L.fmm_p2p(C.byref(d), 1, None, None, 0, None, 0, None, None, 0, None, None, 0, None, None, None) == -1
+    assert L.fmm_p2p(C.byref(d), 0, None, None, 0, None, 0, None, None, 0, None, None, 0, None, None, None) == 0
     assert L.fmm_l2l_adjoint(None, 1, None, None, 0, None, None, None, None) == -1
     assert L.fmm_batch_info(None, None, 0) == -1
     assert L.fmm_direct(C.byref(d), -1, None, None, 0, None, None, None) == -1

@@ -1,0 +1,125 @@
+"""GPU parity of the near field (fmm_p2p) against the oracle's direct sum over the same
+neighbour boxes, and the complete FMM potential (tree-pass far field + near field) against
+the direct sum of eq. (1).
+
+Tolerances: P2P FP64 / complex128 1e-12, FP32 / complex64 1e-5 (as the direct sum).  The
+complete FMM differs from the direct sum by the truncation error of the expansions: bounded
+here per order from the oracle's own convergence (Laplace, p = 4 and 8) and required to fall
+with p.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import kernels as K
+
+from helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("laplace", 0.0, "f64"), ("yukawa", 2.0, "f64"), ("helmholtz", 1.0, "c128"), ("biharmonic", 0.0, "f64"),
+         ("laplace", 0.0, "f32"), ("helmholtz", 1.0, "c64")]
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def two_sets():
+    src = W.uniform_tree(W.uniform_points(3000, 71), 3)
+    tgt = W.uniform_tree(W.uniform_points(2500, 72), 3)
+    return src, tgt
+
+
+def oracle_near(kernel, param, src_tree, tgt_tree, boxes, ptr, nbr, w, n_tgt):
+    dtype = np.complex128 if kernel == "helmholtz" else np.float64
+    out = np.zeros(n_tgt, dtype=dtype)
+    for k, b in enumerate(boxes):
+        lo, hi = tgt_tree.pt_range[b]
+        if hi == lo:
+            continue
+        idx = np.concatenate([np.arange(*src_tree.pt_range[s]) for s in nbr[ptr[k]:ptr[k + 1]]] + [np.zeros(0, int)])
+        if len(idx):
+            out[lo:hi] = K.direct_sum(kernel, param, src_tree.points[idx], w[idx], tgt_tree.points[lo:hi])
+    return out
+
+
+def run_p2p(fmm, kernel, param, dt, src_tree, tgt_tree, boxes, ptr, nbr, w, start):
+    d = fmm.Desc(kernel, 4, dt, param)
+    pot = dev(start, d.value_dtype)
+    fmm.p2p(d, dev(boxes, torch.int32), dev(ptr, torch.int32), dev(nbr, torch.int32),
+            dev(tgt_tree.pt_range, torch.int64), dev(src_tree.pt_range, torch.int64),
+            dev(src_tree.points, d.real_dtype), dev(w, d.value_dtype), dev(tgt_tree.points, d.real_dtype), pot)
+    return host(pot).astype(start.dtype) - host(dev(start, d.value_dtype)).astype(start.dtype)
+
+
+@pytest.mark.parametrize("kernel,param,dt", CASES)
+def test_p2p_matches_oracle(gpu_lib, two_sets, kernel, param, dt):
+    src_tree, tgt_tree = two_sets
+    boxes, ptr, nbr = W.neighbours(tgt_tree, 3)
+    cplx = kernel == "helmholtz"
+    w = W.normal_weights(src_tree.points.shape[0], 73, complex_=cplx)
+    g = np.random.Generator(np.random.PCG64(74))
+    start = g.standard_normal(tgt_tree.points.shape[0]) * (1 + 1j if cplx else 1)
+    got = run_p2p(gpu_lib, kernel, param, dt, src_tree, tgt_tree, boxes, ptr, nbr, w, start)
+    ref = oracle_near(kernel, param, src_tree, tgt_tree, boxes, ptr, nbr, w, tgt_tree.points.shape[0])
+    single = dt in ("f32", "c64")
+    assert rel(got, ref) < (1e-5 if single else 1e-12), rel(got, ref)
+
+
+def test_p2p_one_point_set_skips_self_terms(gpu_lib):
+    tr = W.uniform_tree(W.uniform_points(2000, 75), 3)
+    boxes, ptr, nbr = W.neighbours(tr, 3)
+    w = W.normal_weights(2000, 76)
+    got = run_p2p(gpu_lib, "laplace", 0.0, "f64", tr, tr, boxes, ptr, nbr, w, np.zeros(2000))
+    ref = oracle_near("laplace", 0.0, tr, tr, boxes, ptr, nbr, w, 2000)
+    assert np.all(np.isfinite(got)) and rel(got, ref) < 1e-12
+
+
+def test_p2p_clamps_lists_and_skips_bad_ids(gpu_lib, two_sets):
+    """CSR pointers past the list are clamped to it; box ids outside [0, n_box) are skipped."""
+    src_tree, tgt_tree = two_sets
+    boxes, ptr, nbr = W.neighbours(tgt_tree, 3)
+    boxes, ptr = boxes[:3].copy(), ptr[:4].copy()
+    nbr = nbr[:ptr[-1]].copy()
+    nbr[0] = src_tree.n_box + 7  # skipped
+    ptr_bad = ptr.copy()
+    ptr_bad[-1] = len(nbr) + 1000  # clamped to len(nbr)
+    w = W.normal_weights(src_tree.points.shape[0], 77)
+    n = tgt_tree.points.shape[0]
+    got = run_p2p(gpu_lib, "laplace", 0.0, "f64", src_tree, tgt_tree, boxes, ptr_bad, nbr, w, np.zeros(n))
+    nbr_ref = np.where(nbr < src_tree.n_box, nbr, -1)
+    keep = [[s for s in nbr_ref[ptr[k]:ptr[k + 1]] if s >= 0] for k in range(3)]
+    ptr_ref = np.concatenate([[0], np.cumsum([len(x) for x in keep])])
+    ref = oracle_near("laplace", 0.0, src_tree, tgt_tree, boxes, ptr_ref, np.concatenate(keep), w, n)
+    assert rel(got, ref) < 1e-12
+
+
+def full_fmm(fmm, p, n=4096, seed=78, sample=96):
+    from paper_2305_17867_amd.farfield import FarField
+    tr = W.uniform_tree(W.uniform_points(n, seed), 3)
+    w = W.normal_weights(n, seed + 1)
+    ff = FarField("laplace", p, "f64", tr, tr, tree_pass=True)
+    pts, wd = dev(tr.points, torch.float64), dev(w, torch.float64)
+    with torch.no_grad():
+        pot, _, _ = ff.forward_raw(wd, pts, pts)
+    boxes, ptr, nbr = W.neighbours(tr, 3)
+    d = fmm.Desc("laplace", p, "f64")
+    fmm.p2p(d, dev(boxes, torch.int32), dev(ptr, torch.int32), dev(nbr, torch.int32),
+            dev(tr.pt_range, torch.int64), dev(tr.pt_range, torch.int64), pts, wd, pts, pot)
+    idx = np.random.Generator(np.random.PCG64(seed + 2)).choice(n, sample, replace=False)
+    ref = K.direct_sum("laplace", 0.0, tr.points, w, tr.points[idx])
+    return rel(host(pot)[idx], ref)
+
+
+def test_full_fmm_matches_direct_sum(gpu_lib):
+    """Far field of every level's interaction list (tree pass) + near field of the leaves =
+    eq. (1) up to the truncation error, which falls with the order."""
+    e4, e8 = full_fmm(gpu_lib, 4), full_fmm(gpu_lib, 8)
+    assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)

@@ -172,6 +172,26 @@ def children(tree: Tree, lev: int) -> tuple[np.ndarray, np.ndarray]:
     return parents.astype(np.int32), child
 
 
+def neighbours(tree: Tree, lev: int) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Near-field lists of the boxes of level lev: every existing box of the same level whose
+    integer coordinates differ by at most one in each axis, the box itself included (the
+    U list of a uniform tree at its leaf level).  Returns (box [n] int32, ptr [n + 1] int32,
+    nbr int32) in CSR form."""
+    boxes = tree.boxes_at(lev)
+    index = {tuple(int(v) for v in tree.ijk[b]): int(b) for b in boxes}
+    ptr, nbr = [0], []
+    for b in boxes:
+        i, j, k = (int(v) for v in tree.ijk[b])
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for dk in (-1, 0, 1):
+                    n = index.get((i + di, j + dj, k + dk))
+                    if n is not None:
+                        nbr.append(n)
+        ptr.append(len(nbr))
+    return boxes.astype(np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(nbr, dtype=np.int32)
+
+
 def _point_keys(points: np.ndarray) -> np.ndarray:
     scale = float(1 << MAX_DEPTH)
     ijk = np.floor(points * scale).astype(np.int64)
