@@ -275,6 +275,51 @@ def translations(torch, fmm, tr, reps=20):
             "variants": out}
 
 
+def full_fmm(torch, fmm, tr, w, reps=5, sample=512):
+    """The complete FMM potential of the headline point set (Laplace p = 8, FP64): far field as
+    a tree pass (P2M at the leaves, M2M up, M2L on levels 2-4, L2L down, L2P at the leaves) plus
+    the near field of the leaves (P2P over the 27 neighbour boxes); its error against the GPU
+    direct sum at sampled targets."""
+    import workloads as W
+    from paper_2305_17867_amd.farfield import FarField
+    dev = "cuda"
+    ff = FarField("laplace", 8, "f64", tr, tr, tree_pass=True)
+    pts = torch.as_tensor(tr.points, dtype=torch.float64, device=dev)
+    wd = torch.as_tensor(w, dtype=torch.float64, device=dev)
+    boxes, ptr, nbr = W.neighbours(tr, DEPTH)
+    d = fmm.Desc("laplace", 8, "f64")
+    lists = [torch.as_tensor(a, device=dev) for a in (boxes, ptr, nbr)]
+    rng = torch.as_tensor(tr.pt_range, dtype=torch.int64, device=dev)
+    out = {}
+
+    def far():
+        with torch.no_grad():
+            out["pot"] = ff.forward_raw(wd, pts, pts)[0]
+
+    def near():
+        fmm.p2p(d, *lists, rng, rng, pts, wd, pts, out["pot"])
+
+    t_far = time_kernel(torch, far, reps)
+    t_near = time_kernel(torch, near, reps)
+    far()
+    near()
+    idx = np.sort(np.random.Generator(np.random.PCG64(SEED + 7)).choice(len(w), sample, replace=False))
+    ref = fmm.direct(d, pts, wd, pts[torch.as_tensor(idx, device=dev)].contiguous())
+    # the direct sum of eq. (1) itself: 4,096 targets against all 2^20 sources
+    sub = pts[torch.as_tensor(np.sort(np.random.Generator(np.random.PCG64(SEED + 8)).choice(len(w), 4096, replace=False)),
+                              device=dev)].contiguous()
+    phi_sub = torch.empty(4096, dtype=torch.float64, device=dev)
+    t_direct = time_kernel(torch, lambda: fmm.direct(d, pts, wd, sub, out=phi_sub), reps)
+    got = out["pot"][torch.as_tensor(idx, device=dev)]
+    err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+    counts = tr.pt_range[:, 1] - tr.pt_range[:, 0]
+    inter = int(sum(int(counts[b]) * int(counts[nbr[ptr[k]:ptr[k + 1]]].sum()) for k, b in enumerate(boxes)))
+    return {"workload": "uniform 2^20 points, depth 4, laplace p8 f64: far field (tree pass) + near field",
+            "far_ms": t_far * 1e3, "near_ms": t_near * 1e3, "near_interactions": inter,
+            "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample,
+            "direct_4096_targets_ms": t_direct * 1e3, "direct_interactions_per_s": 4096 * len(w) / t_direct}
+
+
 def mixed_batch(torch, fmm, reps=10):
     """Yukawa (lambda = 2) + biharmonic far field of 524,288 Gaussian-mixture points (adaptive
     octree, <= 64 per leaf), orders 6/8/10 by level, FP32: one batch per (kernel, order), all
@@ -389,6 +434,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default=None, help="run one variant, e.g. f64:8 (for profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the FFT path and the mixed workload")
+    ap.add_argument("--full-fmm", action="store_true",
+                    help="also time the complete FMM potential when --only or --no-extras is given")
     ap.add_argument("--translations", action="store_true",
                     help="also time M2M / L2L when --only or --no-extras is given")
     ap.add_argument("--extended", action="store_true",
@@ -463,6 +510,9 @@ def main():
     if args.translations or not (args.only or args.no_extras):
         log("M2M / L2L")
         out["translations"] = translations(torch, fmm, tr)
+    if args.full_fmm or not (args.only or args.no_extras):
+        log("complete FMM (far field + near field)")
+        out["full_fmm"] = full_fmm(torch, fmm, tr, w)
     if not (args.only or args.no_extras):
         log("mixed workload (persistent, graph-captured launch)")
         out["mixed_batch"] = mixed_batch(torch, fmm)

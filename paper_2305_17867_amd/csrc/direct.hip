@@ -1,5 +1,8 @@
 // Direct sum eq. (1): phi(x) = sum_y G(x - y) w(y), terms with x == y skipped.
-// One thread per target; sources are staged through LDS in tiles of the block size.
+// Sources are staged through LDS in tiles of the block size.  Each target is taken by `split`
+// adjacent lanes (one when there are many targets; up to a wavefront when there are few, so
+// that the launch still fills the chip), each summing every split-th source of a tile; the
+// lanes' sums are added by a butterfly of lane exchanges in a fixed order.
 // The near field (P2P) is the same sum restricted, per target box, to the sources of its
 // neighbour boxes: one workgroup per (target box, chunk of 256 targets).
 #include <cmath>
@@ -15,9 +18,18 @@ namespace {
 
 constexpr int kThreads = 256;
 
-template <typename R>
-__device__ inline R r_sqrt(R v) { return sqrt(v); }
-__device__ inline float r_sqrt(float v) { return sqrtf(v); }
+// 1 / sqrt(v), v > 0: the hardware estimate refined by Newton steps y <- y (3 - v y^2) / 2,
+// two in double precision (each roughly squares the relative error) and one in single
+__device__ inline double inv_sqrt(double v) {
+  double y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-v * y, y, 1.0), y);
+  return y;
+}
+__device__ inline float inv_sqrt(float v) {
+  const float y = __builtin_amdgcn_rsqf(v);
+  return fmaf(0.5f * y, fmaf(-v * y, y, 1.0f), y);
+}
 
 // acc += G(d) w for one source at offset d = x - y (d != 0)
 template <typename R, bool CPLX, typename T>
@@ -25,30 +37,38 @@ __device__ inline void add_green(T& acc, int kernel, R prm, R dx, R dy, R dz, co
   const R inv4pi = R(1.0 / (4.0 * M_PI));
   const R r2 = dx * dx + dy * dy + dz * dz;
   if (r2 == R(0)) return;
-  const R r = r_sqrt(r2);
+  const R ir = inv_sqrt(r2);
+  const R r = r2 * ir;
   if constexpr (CPLX) {
     // Helmholtz exp(i k r) / (4 pi r)
     R sn, cs;
     if constexpr (sizeof(R) == 8) sincos(prm * r, &sn, &cs);
     else sincosf(prm * r, &sn, &cs);
-    const R g = inv4pi / r;
+    const R g = inv4pi * ir;
     const T G(g * cs, g * sn);
     acc += G * w;
   } else {
     R G;
-    if (kernel == FMM_LAPLACE) G = inv4pi / r;
-    else if (kernel == FMM_YUKAWA) G = exp(-prm * r) * inv4pi / r;
+    if (kernel == FMM_LAPLACE) G = inv4pi * ir;
+    else if (kernel == FMM_YUKAWA) G = exp(-prm * r) * inv4pi * ir;
     else G = r;
     acc += G * w;
   }
 }
+
+template <typename R>
+__device__ inline R lane_xor(R v, int m) { return shfl_xor_d(v, m); }
+template <typename R>
+__device__ inline Cx<R> lane_xor(Cx<R> v, int m) { return {shfl_xor_d(v.re, m), shfl_xor_d(v.im, m)}; }
 
 template <typename R, bool CPLX>
 __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
   using T = typename Val<R, CPLX>::T;
   __shared__ R sx[kThreads], sy[kThreads], sz[kThreads];
   __shared__ T sw[kThreads];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int split = a.split;
+  const int ls = threadIdx.x & (split - 1);  // lane within the target's group
+  const int64_t t = (int64_t)blockIdx.x * (kThreads / split) + threadIdx.x / split;
   const R* tg = reinterpret_cast<const R*>(a.tgt);
   const R* sr = reinterpret_cast<const R*>(a.src);
   const T* w = reinterpret_cast<const T*>(a.w);
@@ -71,9 +91,10 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
     }
     __syncthreads();
     const int cnt = (int)((a.n_src - base) < kThreads ? (a.n_src - base) : kThreads);
-    for (int k = 0; k < cnt; ++k) add_green<R, CPLX>(acc, a.kernel, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
+    for (int k = ls; k < cnt; k += split) add_green<R, CPLX>(acc, a.kernel, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
   }
-  if (t < a.n_tgt) reinterpret_cast<T*>(a.pot)[t] = acc;
+  for (int m = 1; m < split; m <<= 1) acc += lane_xor(acc, m);  // all lanes active here
+  if (ls == 0 && t < a.n_tgt) reinterpret_cast<T*>(a.pot)[t] = acc;
 }
 
 __device__ inline void clamp_range(const int64_t* rng, int64_t b, int64_t n, int64_t& lo, int64_t& hi) {
@@ -153,9 +174,15 @@ int launch_p2p(const P2PArgs& a, int dtype, hipStream_t s) {
   return FMM_OK;
 }
 
-int launch_direct(const DirectArgs& a, int dtype, hipStream_t s) {
-  if (a.n_tgt == 0) return FMM_OK;
-  dim3 g((unsigned)((a.n_tgt + kThreads - 1) / kThreads)), t(kThreads);
+int launch_direct(const DirectArgs& a_in, int dtype, hipStream_t s) {
+  if (a_in.n_tgt == 0) return FMM_OK;
+  // lanes per target: double until the launch has about 1,024 workgroups (or one wavefront
+  // per target)
+  DirectArgs a = a_in;
+  a.split = 1;
+  while (a.split < 64 && (a.n_tgt * a.split + kThreads - 1) / kThreads < 1024) a.split *= 2;
+  const int64_t per_block = kThreads / a.split;
+  dim3 g((unsigned)((a.n_tgt + per_block - 1) / per_block)), t(kThreads);
   switch (dtype) {
     case FMM_F64: hipLaunchKernelGGL((direct_kernel<double, false>), g, t, 0, s, a); break;
     case FMM_F32: hipLaunchKernelGGL((direct_kernel<float, false>), g, t, 0, s, a); break;

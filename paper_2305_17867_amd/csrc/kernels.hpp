@@ -167,6 +167,7 @@ struct DirectArgs {
   void* pot;
   int32_t kernel;
   double param;
+  int32_t split;  // lanes sharing one target (a power of two <= 64), each taking every split-th source
 };
 
 // Near field: for each listed target box, the direct sum over the sources of its neighbour
