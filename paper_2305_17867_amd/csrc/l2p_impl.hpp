@@ -6,8 +6,10 @@
 //
 // One wavefront per box (a workgroup of 64 lanes, so its barriers cost next to nothing).  The
 // decompressed coefficients live in LDS and are read as wave-wide broadcasts; every lane
-// evaluates kU targets at once with a nested Horner scheme, so that each coefficient read
-// feeds kU fused multiply-adds.  The index decode (full index -> (x, y, z)) comes from
+// evaluates KU targets at once with a nested Horner scheme, so that each coefficient read
+// feeds KU fused multiply-adds.  KU is chosen per pass from the points left (1, 2, 4 or 8),
+// so that a pass is not mostly empty: small leaves of adaptive trees take KU = 1, and boxes
+// of a few more than 256 points one pass of KU = 8 instead of two.  The index decode (full index -> (x, y, z)) comes from
 // compile-time tables, and the recursion terms are unrolled so that no per-lane array is
 // indexed dynamically.
 #pragma once
@@ -24,7 +26,11 @@ namespace fmm {
 namespace detail_l2p {
 
 constexpr int kThreads = 64;  // one wavefront per box
-constexpr int kU = 4;         // targets per lane and pass
+// most targets per lane and pass: 8 for real potentials, 4 where complex values or gradients
+// leave fewer registers
+template <bool CPLX, bool GRAD>
+constexpr int kMaxU = (CPLX || GRAD) ? 4 : 8;
+constexpr int kChunk = kThreads * 8;  // points of a box per workgroup of the 2-D grid
 constexpr int kWavesPerEU = 4;  // register budget: at most 128 per lane
 
 struct InvFact {
@@ -130,15 +136,15 @@ struct HornerOrder {
 template <int Q>
 __device__ constexpr HornerOrder<Q> kHorner{};
 
-// out[j][u] = sum_{|m| <= Q} c_m,u X_j^m for kU points j at once (nested Horner: y innermost,
+// out[j][u] = sum_{|m| <= Q} c_m,u X_j^m for KU points j at once (nested Horner: y innermost,
 // then x, then z), the coefficients C[W * k + u] stored in Horner order.  The row loops are
 // kept as loops so that the coefficients are read from LDS as they are consumed.
-template <int Q, int W, typename R>
-__device__ inline void horner_u(const R* C, const R (&X)[kU], const R (&Y)[kU], const R (&Z)[kU],
-                                R (&out)[kU][W]) {
-  R pz[kU][W];
+template <int KU, int Q, int W, typename R>
+__device__ inline void horner_u(const R* C, const R (&X)[KU], const R (&Y)[KU], const R (&Z)[KU],
+                                R (&out)[KU][W]) {
+  R pz[KU][W];
 #pragma unroll
-  for (int j = 0; j < kU; ++j)
+  for (int j = 0; j < KU; ++j)
 #pragma unroll
     for (int u = 0; u < W; ++u) pz[j][u] = R(0);
   // the coefficients are consumed strictly in storage order, so the reads run two steps ahead
@@ -152,16 +158,16 @@ __device__ inline void horner_u(const R* C, const R (&X)[kU], const R (&Y)[kU], 
   int idx = 0;
 #pragma unroll 1
   for (int z = Q; z >= 0; --z) {
-    R qx[kU][W];
+    R qx[KU][W];
 #pragma unroll
-    for (int j = 0; j < kU; ++j)
+    for (int j = 0; j < KU; ++j)
 #pragma unroll
       for (int u = 0; u < W; ++u) qx[j][u] = R(0);
 #pragma unroll 1
     for (int x = Q - z; x >= 0; --x) {
-      R ry[kU][W];
+      R ry[KU][W];
 #pragma unroll
-      for (int j = 0; j < kU; ++j)
+      for (int j = 0; j < KU; ++j)
 #pragma unroll
         for (int u = 0; u < W; ++u) ry[j][u] = R(0);
       const int n = Q - z - x + 1;
@@ -173,23 +179,71 @@ __device__ inline void horner_u(const R* C, const R (&X)[kU], const R (&Y)[kU], 
           c0[u] = c1[u];
           c1[u] = C[(idx + 2) * W + u];
 #pragma unroll
-          for (int j = 0; j < kU; ++j) ry[j][u] = ry[j][u] * Y[j] + cv;
+          for (int j = 0; j < KU; ++j) ry[j][u] = ry[j][u] * Y[j] + cv;
         }
       }
 #pragma unroll
-      for (int j = 0; j < kU; ++j)
+      for (int j = 0; j < KU; ++j)
 #pragma unroll
         for (int u = 0; u < W; ++u) qx[j][u] = qx[j][u] * X[j] + ry[j][u];
     }
 #pragma unroll
-    for (int j = 0; j < kU; ++j)
+    for (int j = 0; j < KU; ++j)
 #pragma unroll
       for (int u = 0; u < W; ++u) pz[j][u] = pz[j][u] * Z[j] + qx[j][u];
   }
 #pragma unroll
-  for (int j = 0; j < kU; ++j)
+  for (int j = 0; j < KU; ++j)
 #pragma unroll
     for (int u = 0; u < W; ++u) out[j][u] = pz[j][u];
+}
+
+// One pass over the next KU * 64 targets of the box from s0 (each lane takes KU of them, 64
+// apart): potentials and, for GRAD, gradients.  Returns the number of targets covered.
+template <int P, typename R, bool CPLX, bool GRAD, int KU, typename LG>
+__device__ inline int pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R* xyz, int64_t s0, int64_t hi, R cx,
+                           R cy, R cz, R ih) {
+  constexpr int W = CPLX ? 2 : 1;
+  const int64_t t0 = s0 + threadIdx.x;
+  R X[KU], Y[KU], Z[KU];
+#pragma unroll
+  for (int j = 0; j < KU; ++j) {
+    const int64_t s = t0 + (int64_t)j * kThreads;
+    const bool ok = s < hi;
+    X[j] = ok ? (xyz[3 * s + 0] - cx) * ih : R(0);
+    Y[j] = ok ? (xyz[3 * s + 1] - cy) * ih : R(0);
+    Z[j] = ok ? (xyz[3 * s + 2] - cz) * ih : R(0);
+  }
+  if (a.pot) {
+    R v[KU][W];
+    horner_u<KU, P, W, R>(Lc, X, Y, Z, v);
+    R* pot = reinterpret_cast<R*>(a.pot);
+#pragma unroll
+    for (int j = 0; j < KU; ++j) {
+      const int64_t s = t0 + (int64_t)j * kThreads;
+      if (s < hi) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) pot[s * W + u] += v[j][u];
+      }
+    }
+  }
+  if constexpr (GRAD && P > 0 && !CPLX) {
+    R g[3][KU][1];
+    horner_u<KU, P - 1, 1, R>(Lg[0], X, Y, Z, g[0]);
+    horner_u<KU, P - 1, 1, R>(Lg[1], X, Y, Z, g[1]);
+    horner_u<KU, P - 1, 1, R>(Lg[2], X, Y, Z, g[2]);
+    R* gout = reinterpret_cast<R*>(a.grad);
+#pragma unroll
+    for (int j = 0; j < KU; ++j) {
+      const int64_t s = t0 + (int64_t)j * kThreads;
+      if (s < hi) {
+        const R sc = a.gscale ? reinterpret_cast<const R*>(a.gscale)[s] : R(1);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) gout[3 * s + ax] += sc * ih * g[ax][j][0];
+      }
+    }
+  }
+  return KU * kThreads;
 }
 
 template <int P, typename R, bool CPLX, bool GRAD>
@@ -201,12 +255,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   __shared__ R Lc[(NP + 2) * W];  // + 2 zero entries read ahead by horner_u
   __shared__ R Lg[3][((NG > 0 ? NG : 1) + 2) * W];
   const int64_t b = blockIdx.x;
-  // points of the box: workgroup y of the box takes chunks y, y + gridDim.y, ... of kThreads kU
-  // targets, so that large boxes (coarse levels) are spread over several workgroups
+  // points of the box: workgroup y of the box takes the chunks y, y + gridDim.y, ... of kChunk
+  // points (large boxes of coarse levels are spread over several workgroups)
   int64_t lo = a.range[2 * b], hi = a.range[2 * b + 1];
   lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
   hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
-  if (lo + (int64_t)blockIdx.y * kThreads * kU >= hi) return;  // uniform: no points for this workgroup
+  if (lo + (int64_t)blockIdx.y * kChunk >= hi) return;  // uniform: no points for this workgroup
   int lev = a.level[b];
   lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
   const double h = a.level_h[lev];
@@ -243,54 +297,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const double cen[3] = {a.center[3 * b], a.center[3 * b + 1], a.center[3 * b + 2]};
   const R* xyz = reinterpret_cast<const R*>(a.xyz);
   const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)(a.xsign / h);
-  for (int64_t s0 = lo + (int64_t)blockIdx.y * kThreads * kU + threadIdx.x; s0 < hi;
-       s0 += (int64_t)gridDim.y * kThreads * kU) {
-    R X[kU], Y[kU], Z[kU];
-#pragma unroll
-    for (int j = 0; j < kU; ++j) {
-      const int64_t s = s0 + (int64_t)j * kThreads;
-      const bool ok = s < hi;
-      X[j] = ok ? (xyz[3 * s + 0] - cx) * ih : R(0);
-      Y[j] = ok ? (xyz[3 * s + 1] - cy) * ih : R(0);
-      Z[j] = ok ? (xyz[3 * s + 2] - cz) * ih : R(0);
-    }
-    if (a.pot) {
-      R v[kU][W];
-      horner_u<P, W, R>(Lc, X, Y, Z, v);
-      R* pot = reinterpret_cast<R*>(a.pot);
-#pragma unroll
-      for (int j = 0; j < kU; ++j) {
-        const int64_t s = s0 + (int64_t)j * kThreads;
-        if (s < hi) {
-#pragma unroll
-          for (int u = 0; u < W; ++u) pot[s * W + u] += v[j][u];
-        }
-      }
-    }
-    if constexpr (GRAD && P > 0 && !CPLX) {
-      R g[3][kU][1];
-      horner_u<P - 1, 1, R>(Lg[0], X, Y, Z, g[0]);
-      horner_u<P - 1, 1, R>(Lg[1], X, Y, Z, g[1]);
-      horner_u<P - 1, 1, R>(Lg[2], X, Y, Z, g[2]);
-      R* gout = reinterpret_cast<R*>(a.grad);
-#pragma unroll
-      for (int j = 0; j < kU; ++j) {
-        const int64_t s = s0 + (int64_t)j * kThreads;
-        if (s < hi) {
-          const R sc = a.gscale ? reinterpret_cast<const R*>(a.gscale)[s] : R(1);
-#pragma unroll
-          for (int ax = 0; ax < 3; ++ax) gout[3 * s + ax] += sc * ih * g[ax][j][0];
-        }
-      }
+  constexpr int KM = kMaxU<CPLX, GRAD>;
+  for (int64_t c0 = lo + (int64_t)blockIdx.y * kChunk; c0 < hi; c0 += (int64_t)gridDim.y * kChunk) {  // uniform
+    const int64_t c1 = c0 + kChunk < hi ? c0 + kChunk : hi;
+    for (int64_t s0 = c0; s0 < c1;) {  // passes sized to the points left in the chunk
+      const int64_t left = c1 - s0;
+      int step;
+      if (left <= kThreads) step = pass<P, R, CPLX, GRAD, 1>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      else if (left <= 2 * kThreads) step = pass<P, R, CPLX, GRAD, 2>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      else if (KM == 4 || left <= 4 * kThreads) step = pass<P, R, CPLX, GRAD, 4>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      else step = pass<P, R, CPLX, GRAD, KM>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      s0 += step;
     }
   }
 }
 
 template <int P>
 int launch_l2p_p(const L2PArgs& a, int dtype, hipStream_t s) {
-  // workgroups per box: enough that the average box gets one per kThreads kU targets
+  // workgroups per box: enough that the average box gets one per kChunk targets
   const int64_t per_box = a.n_box > 0 ? (a.n_pts + a.n_box - 1) / a.n_box : 1;
-  const int64_t ny = std::max<int64_t>(1, std::min<int64_t>(1024, (per_box + kThreads * kU - 1) / (kThreads * kU)));
+  const int64_t ny = std::max<int64_t>(1, std::min<int64_t>(1024, (per_box + kChunk - 1) / kChunk));
   dim3 g((unsigned)a.n_box, (unsigned)ny), t(kThreads);
   const bool grad = a.grad != nullptr;
   switch (dtype) {
