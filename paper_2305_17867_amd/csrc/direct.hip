@@ -4,7 +4,7 @@
 // that the launch still fills the chip), each summing every split-th source of a tile; the
 // lanes' sums are added by a butterfly of lane exchanges in a fixed order.
 // The near field (P2P) is the same sum restricted, per target box, to the sources of its
-// neighbour boxes: one workgroup per (target box, chunk of 256 targets).
+// neighbour boxes: one workgroup per (target box, chunk of up to 512 targets).
 #include <cmath>
 
 #include "../../include/fmm.h"
@@ -104,6 +104,58 @@ __device__ inline void clamp_range(const int64_t* rng, int64_t b, int64_t n, int
   hi = hi < lo ? lo : (hi > n ? n : hi);
 }
 
+// Targets [t0, t1) of one box against the sources of its neighbour boxes, KT targets per
+// thread (kThreads apart), so that each staged source tile feeds KT sums.
+template <typename R, bool CPLX, int KT>
+__device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64_t e0, int64_t e1, R* sx, R* sy, R* sz,
+                                 typename Val<R, CPLX>::T* sw) {
+  using T = typename Val<R, CPLX>::T;
+  const R* tg = reinterpret_cast<const R*>(a.tgt);
+  const R* sr = reinterpret_cast<const R*>(a.src);
+  const T* w = reinterpret_cast<const T*>(a.w);
+  const R prm = (R)a.param;
+  R x[KT], y[KT], z[KT];
+  T acc[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    const int64_t t = t0 + threadIdx.x + (int64_t)j * kThreads;
+    x[j] = y[j] = z[j] = R(0);
+    if (t < t1) {
+      x[j] = tg[3 * t];
+      y[j] = tg[3 * t + 1];
+      z[j] = tg[3 * t + 2];
+    }
+    acc[j] = T{};
+  }
+  for (int64_t e = e0; e < e1; ++e) {
+    const int sb = a.nbr[e];
+    if (sb < 0 || sb >= a.n_box) continue;  // uniform
+    int64_t slo, shi;
+    clamp_range(a.src_range, sb, a.n_src, slo, shi);
+    for (int64_t base = slo; base < shi; base += kThreads) {
+      __syncthreads();
+      const int64_t jsrc = base + threadIdx.x;
+      if (jsrc < shi) {
+        sx[threadIdx.x] = sr[3 * jsrc];
+        sy[threadIdx.x] = sr[3 * jsrc + 1];
+        sz[threadIdx.x] = sr[3 * jsrc + 2];
+        sw[threadIdx.x] = w[jsrc];
+      }
+      __syncthreads();
+      const int cnt = (int)((shi - base) < kThreads ? (shi - base) : kThreads);
+      for (int k = 0; k < cnt; ++k) {
+#pragma unroll
+        for (int j = 0; j < KT; ++j) add_green<R, CPLX>(acc[j], a.kernel, prm, x[j] - sx[k], y[j] - sy[k], z[j] - sz[k], sw[k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    const int64_t t = t0 + threadIdx.x + (int64_t)j * kThreads;
+    if (t < t1) reinterpret_cast<T*>(a.pot)[t] += acc[j];
+  }
+}
+
 template <typename R, bool CPLX>
 __global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
   using T = typename Val<R, CPLX>::T;
@@ -113,45 +165,16 @@ __global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
   if (tb < 0 || tb >= a.n_box) return;  // uniform
   int64_t tlo, thi;
   clamp_range(a.tgt_range, tb, a.n_tgt, tlo, thi);
-  const R* tg = reinterpret_cast<const R*>(a.tgt);
-  const R* sr = reinterpret_cast<const R*>(a.src);
-  const T* w = reinterpret_cast<const T*>(a.w);
-  const R prm = (R)a.param;
   // the list range, clamped to the list (the CSR pointers are device data)
   int64_t e0 = a.nbr_ptr[blockIdx.x], e1 = a.nbr_ptr[blockIdx.x + 1];
   e0 = e0 < 0 ? 0 : (e0 > a.n_nbr ? a.n_nbr : e0);
   e1 = e1 < e0 ? e0 : (e1 > a.n_nbr ? a.n_nbr : e1);
-  // workgroup y takes the targets tlo + (y + m gridDim.y) kThreads + threadIdx.x
-  for (int64_t t0 = tlo + (int64_t)blockIdx.y * kThreads; t0 < thi; t0 += (int64_t)gridDim.y * kThreads) {
-    const int64_t t = t0 + threadIdx.x;
-    const bool have = t < thi;
-    R x = 0, y = 0, z = 0;
-    if (have) {
-      x = tg[3 * t];
-      y = tg[3 * t + 1];
-      z = tg[3 * t + 2];
-    }
-    T acc{};
-    for (int64_t e = e0; e < e1; ++e) {
-      const int sb = a.nbr[e];
-      if (sb < 0 || sb >= a.n_box) continue;  // uniform
-      int64_t slo, shi;
-      clamp_range(a.src_range, sb, a.n_src, slo, shi);
-      for (int64_t base = slo; base < shi; base += kThreads) {
-        __syncthreads();
-        const int64_t j = base + threadIdx.x;
-        if (j < shi) {
-          sx[threadIdx.x] = sr[3 * j];
-          sy[threadIdx.x] = sr[3 * j + 1];
-          sz[threadIdx.x] = sr[3 * j + 2];
-          sw[threadIdx.x] = w[j];
-        }
-        __syncthreads();
-        const int cnt = (int)((shi - base) < kThreads ? (shi - base) : kThreads);
-        for (int k = 0; k < cnt; ++k) add_green<R, CPLX>(acc, a.kernel, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
-      }
-    }
-    if (have) reinterpret_cast<T*>(a.pot)[t] += acc;
+  // workgroup y takes the chunks y, y + gridDim.y, ... of 2 kThreads targets; a chunk of at
+  // most kThreads targets is taken one per thread, a larger one two per thread
+  for (int64_t t0 = tlo + (int64_t)blockIdx.y * 2 * kThreads; t0 < thi; t0 += (int64_t)gridDim.y * 2 * kThreads) {
+    const int64_t t1 = t0 + 2 * kThreads < thi ? t0 + 2 * kThreads : thi;
+    if (t1 - t0 <= kThreads) p2p_chunk<R, CPLX, 1>(a, t0, t1, e0, e1, sx, sy, sz, sw);
+    else p2p_chunk<R, CPLX, 2>(a, t0, t1, e0, e1, sx, sy, sz, sw);
   }
 }
 
@@ -159,9 +182,10 @@ __global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
 
 int launch_p2p(const P2PArgs& a, int dtype, hipStream_t s) {
   if (a.n_tbox == 0) return FMM_OK;
-  // workgroups per target box: enough that the average box gets one per kThreads targets
+  // workgroups per target box: enough that the average box gets one per 2 kThreads targets
   const int64_t per_box = (a.n_tgt + a.n_tbox - 1) / a.n_tbox;
-  const int64_t ny = per_box < kThreads ? 1 : (per_box + kThreads - 1) / kThreads < 1024 ? (per_box + kThreads - 1) / kThreads : 1024;
+  const int64_t chunks = (per_box + 2 * kThreads - 1) / (2 * kThreads);
+  const int64_t ny = chunks < 1 ? 1 : (chunks < 1024 ? chunks : 1024);
   dim3 g((unsigned)a.n_tbox, (unsigned)ny), t(kThreads);
   switch (dtype) {
     case FMM_F64: hipLaunchKernelGGL((p2p_kernel<double, false>), g, t, 0, s, a); break;
