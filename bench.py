@@ -32,7 +32,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6e12, "f32": 157.3e12}  # dense matrix-core peaks, FLOP/s
+PEAK = {"f64": 78.6e12, "f32": 157.3e12}  # dense matrix-core peaks, FLOP/s (equal to the vector peaks)
+HBM_PEAK = 8.0e12  # bytes/s
+# FLOP per point of the Laplace moments (uncompressed P2M), from the paper's operation counts
+# (Fig. "Laplace P2M 3D" of the operation-count section); L2P has very similar counts
+POINT_FLOPS = {8: 276, 12: 788}
 DEPTH, NPTS, SEED = 4, 1 << 20, 1
 COPY_BYTES = 256 << 20  # plain copy used to calibrate the FETCH_SIZE / WRITE_SIZE counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_kernel_laplace_p8_f64_traffic.txt")
@@ -125,6 +129,27 @@ class Case:
         self.run_p2m()
         self.run_m2l()
         self.run_l2p()
+
+
+def point_rooflines(case, dt, p, t_p2m, t_l2p):
+    """P2M and L2P against both ceilings: algorithmic HBM bytes per launch (P2M: x, y, z, w in
+    and the box coefficients out; L2P: x, y, z and the potential in, the potential out, and
+    the box coefficients in) over HBM bandwidth, and the paper's FLOP count per point over
+    the vector peak.  frac is taken against the lower ceiling (the larger of the two)."""
+    rb = 8 if dt == "f64" else 4
+    coef = case.n_leaf * case.nc * rb
+    b_p2m = NPTS * 4 * rb + coef
+    b_l2p = NPTS * 5 * rb + coef
+    fl = POINT_FLOPS.get(p)
+    out = {}
+    for name, b, t in (("p2m", b_p2m, t_p2m), ("l2p", b_l2p, t_l2p)):
+        hbm = b / t / HBM_PEAK
+        valu = NPTS * fl / t / PEAK[dt] if fl else None
+        out[f"{name}_hbm_gbps"] = b / t / 1e9
+        out[f"{name}_hbm_frac"] = hbm
+        out[f"{name}_valu_frac"] = valu
+        out[f"{name}_frac"] = max(hbm, valu or 0.0)
+    return out
 
 
 def time_step(torch, case, steps, warmup, graph=False):
@@ -482,6 +507,7 @@ def main():
             "pairs_per_s": case.n_pair / sec,
             "p2m_pts_per_s": NPTS / t_p2m, "m2l_pairs_per_s": case.n_pair / t_m2l,
             "l2p_pts_per_s": NPTS / t_l2p,
+            **point_rooflines(case, dt, p, t_p2m, t_l2p),
             "p2m_ms": t_p2m * 1e3, "m2l_ms": t_m2l * 1e3, "l2p_ms": t_l2p * 1e3,
             "m2l_tflops": achieved / 1e12, "m2l_frac": achieved / PEAK[dt],
             "m2l_fft_ms": None if t_fft is None else t_fft * 1e3,
