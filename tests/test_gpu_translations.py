@@ -254,3 +254,12 @@ def test_tree_pass_far_field_matches_per_level(gpu_lib, kernel, param, tol):
     per_level = _tree_far_field("f64", False, kernel, param)
     for a, b in zip(tree, per_level):
         assert rel(a, b) < tol
+
+
+def test_tree_pass_fp32_gradients_agree_with_fp64(gpu_lib):
+    """The tree pass in FP32 (M2M / L2L and their transposes in single precision) against the
+    same pass in FP64, at the FP32 adjoint tolerance."""
+    f32 = _tree_far_field("f32", True)
+    f64 = _tree_far_field("f64", True)
+    for a, b in zip(f32, f64):
+        assert rel(a.astype(np.float64), b) < 2e-5
