@@ -49,12 +49,14 @@ template <int P, int Q0, int QN, int QP, typename R, bool CPLX>
 __device__ inline void accumulate_chunk(R (&acc)[2][QP], const R (&px)[P + 1], const R (&py)[P + 1],
                                         const R (&pz)[P + 1], R wr, R wi) {
   constexpr FullIdx<P> I{};
+  // the weight times the (z, x) factor is shared by a row of the chunk (the compiler computes
+  // it once per row), so each coefficient costs one fused multiply-add per component
 #pragma unroll
   for (int k = 0; k < QN; ++k) {
     const int q = Q0 + k;
-    const R mono = (pz[I.z[q]] * px[I.x[q]]) * py[I.y[q]];
-    acc[0][k] += wr * mono;
-    if constexpr (CPLX) acc[1][k] += wi * mono;
+    const R zx = pz[I.z[q]] * px[I.x[q]];
+    acc[0][k] += (wr * zx) * py[I.y[q]];
+    if constexpr (CPLX) acc[1][k] += (wi * zx) * py[I.y[q]];
   }
 }
 
@@ -185,8 +187,16 @@ __device__ inline void compress_lds(double* al, const RecArgs& rec, int c, doubl
   }
 }
 
+// occupancy hint: real FP64 at p = 8 fits 80 VGPRs (6 wavefronts per SIMD) without spills
+// (the chunk layouts of the other orders spill under it); the other forms keep the compiler's
+// own budget
 template <int P, typename R, bool CPLX>
-__global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
+constexpr int p2m_waves_hint() {
+  return (P == 8 && sizeof(R) == 8 && !CPLX) ? 6 : 1;
+}
+
+template <int P, typename R, bool CPLX>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(p2m_waves_hint<P, R, CPLX>()))) void p2m_kernel(P2MArgs a) {
   constexpr int NP = nfull(P);
   __shared__ double alpha[NP * (CPLX ? 2 : 1)];
   const int64_t b = blockIdx.x;
