@@ -32,7 +32,7 @@ class FarField:
     def __init__(self, kernel: str, order: int, dtype: str, src_tree: "W.Tree", tgt_tree: "W.Tree",
                  param: float = 0.0, levels=None, device="cuda", tree_pass: bool = False):
         assert src_tree.n_levels == tgt_tree.n_levels and np.array_equal(src_tree.ijk, tgt_tree.ijk), \
-            "source and target trees must share the box grid (uniform trees of one depth)"
+            "source and target trees must share the box grid (one tree, or uniform trees of one depth)"
         self.desc = fmm.Desc(kernel, order, dtype, param)
         n_lev = src_tree.n_levels
         self.levels = list(range(2, n_lev)) if levels is None else list(levels)
@@ -40,7 +40,9 @@ class FarField:
         t, s = W.interaction_pairs(src_tree, self.levels)
         self.n_pair = len(t)
         self.batch = self.plan.prepare(t, s, src_tree.ijk, src_tree.level)
-        self.batch_t = self.plan.prepare_adjoint(t, s, src_tree.ijk, src_tree.level)
+        # the adjoints are implemented for real dtypes; a complex far field runs forward only
+        self.batch_t = None if dtype in ("c128", "c64") else \
+            self.plan.prepare_adjoint(t, s, src_tree.ijk, src_tree.level)
         self.n_box = src_tree.n_box
         dev = torch.device(device)
         i64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int64, device=dev)
@@ -123,6 +125,8 @@ class FarField:
         return w_grad, src_grad, tgt_grad
 
     def backward_raw(self, g, w, src, tgt, local, need_w=True, need_src=True, need_tgt=True):
+        if self.batch_t is None:
+            raise NotImplementedError("the far-field adjoint is implemented for real dtypes (f64, f32)")
         if self.tree_pass:
             return self._backward_tree(g, w, src, tgt, local, need_w, need_src, need_tgt)
         local_grad = torch.zeros_like(local)

@@ -1,6 +1,6 @@
 """GPU parity of the near field (fmm_p2p) against the oracle's direct sum over the same
 neighbour boxes, and the complete FMM potential (tree-pass far field + near field) against
-the direct sum of eq. (1).
+the direct sum of eq. (1), on uniform and on adaptive octrees.
 
 Tolerances: P2P FP64 / complex128 1e-12, FP32 / complex64 1e-5 (as the direct sum).  The
 complete FMM differs from the direct sum by the truncation error of the expansions: bounded
@@ -123,3 +123,40 @@ def test_full_fmm_matches_direct_sum(gpu_lib):
     eq. (1) up to the truncation error, which falls with the order."""
     e4, e8 = full_fmm(gpu_lib, 4), full_fmm(gpu_lib, 8)
     assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)
+
+
+def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128):
+    """Far field (per-level form: P2M of every box, M2L over the List-2 pairs of every level,
+    L2P of every level's local expansion at its boxes' points) + near field over the adaptive
+    near lists, against the direct sum of eq. (1) at sampled targets."""
+    from paper_2305_17867_amd.farfield import FarField
+    tr = W.adaptive_tree(pts, max_leaf)
+    n = pts.shape[0]
+    cplx = kernel == "helmholtz"
+    w = W.normal_weights(n, seed, complex_=cplx)
+    ff = FarField(kernel, p, dt, tr, tr, param=param)
+    d = ff.desc
+    P, wd = dev(tr.points, d.real_dtype), dev(w, d.value_dtype)
+    with torch.no_grad():
+        pot, _, _ = ff.forward_raw(wd, P, P)
+    leaves, ptr, nbr = W.near_lists(tr)
+    rng = dev(tr.pt_range, torch.int64)
+    fmm.p2p(d, dev(leaves, torch.int32), dev(ptr, torch.int32), dev(nbr, torch.int32), rng, rng, P, wd, P, pot)
+    idx = np.random.Generator(np.random.PCG64(seed + 1)).choice(n, sample, replace=False)
+    ref = K.direct_sum(kernel, param, tr.points, w, tr.points[idx])
+    return rel(host(pot)[idx], ref), tr
+
+
+@pytest.mark.parametrize("kernel,param,dt,dist", [("laplace", 0.0, "f64", "plummer"), ("helmholtz", 2.0, "c128", "plummer"),
+                                                  ("yukawa", 2.0, "f64", "mixture"), ("laplace", 0.0, "f32", "mixture")])
+def test_adaptive_fmm_matches_direct_sum(gpu_lib, kernel, param, dt, dist):
+    """Complete FMM on an adaptive octree (leaves on several levels): the error against the
+    direct sum falls with the order and is small at p = 8 (FP32: down to its rounding)."""
+    pts = W.plummer_points(6000, 81) if dist == "plummer" else W.gaussian_mixture_points(6000, 82)
+    e4, tr = adaptive_fmm(gpu_lib, kernel, param, 4, dt, pts, 32, 83)
+    e8, _ = adaptive_fmm(gpu_lib, kernel, param, 8, dt, pts, 32, 83)
+    assert len(set(tr.level[tr.is_leaf].tolist())) >= 3
+    if dt == "f32":
+        assert e4 < 2e-2 and e8 < 5e-5, (e4, e8)
+    else:
+        assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)

@@ -80,3 +80,62 @@ def test_generators_are_seeded():
     assert np.array_equal(a, b)
     g = W.gaussian_mixture_points(2000, 4)
     assert np.all((g >= 0) & (g < 1))
+
+
+@pytest.mark.parametrize("points,max_leaf", [("plummer", 16), ("mixture", 24), ("uniform", 40)])
+def test_near_lists_and_list2_partition_every_leaf_pair(points, max_leaf):
+    """Every (target leaf, source leaf) pair of an adaptive tree is counted exactly once: by
+    the near list of the target leaf (one list box containing the source leaf), or by exactly
+    one List-2 pair of their ancestors on a level >= 2.  Checked by brute force over all leaf
+    pairs against the definition: near iff the ancestors on the level min(l_t, l_s) are
+    adjacent or equal."""
+    pts = {"plummer": lambda: W.plummer_points(3000, 11),
+           "mixture": lambda: W.gaussian_mixture_points(3000, 12),
+           "uniform": lambda: W.uniform_points(3000, 13)}[points]()
+    tr = W.adaptive_tree(pts, max_leaf)
+    assert len(set(tr.level[tr.is_leaf].tolist())) > 1 or points == "uniform"
+    leaves, ptr, src = W.near_lists(tr)
+    assert np.array_equal(leaves, np.flatnonzero(tr.is_leaf))
+    t, s = W.interaction_pairs(tr)
+    pair_keys = np.sort(t.astype(np.int64) * tr.n_box + s)
+    lv = tr.level.astype(np.int64)
+    ijk = tr.ijk.astype(np.int64)
+    # box id from (level, coords): boxes sorted by a key of level and Morton code
+    box_key = (lv << 58) + W.morton_keys(ijk).astype(np.int64)
+    order = np.argsort(box_key)
+
+    def box_at(level, coords):
+        pos = np.searchsorted(box_key[order], (level << 58) + W.morton_keys(coords).astype(np.int64))
+        return order[np.minimum(pos, len(order) - 1)]  # entries off the tree are masked by the caller
+
+    S = leaves.astype(np.int64)
+    for k, b in enumerate(leaves):
+        lst = src[ptr[k]:ptr[k + 1]].astype(np.int64)
+        assert len(np.unique(lst)) == len(lst)
+        lstar = np.minimum(lv[b], lv[S])
+        anc_b = ijk[b][None, :] >> (lv[b] - lstar)[:, None]
+        anc_s = ijk[S] >> (lv[S] - lstar)[:, None]
+        near = np.max(np.abs(anc_b - anc_s), axis=1) <= 1
+        n_in = np.zeros(len(S), dtype=np.int64)
+        for n in lst:
+            inside = lv[n] <= lv[S]
+            shift = np.where(inside, lv[S] - lv[n], 0)
+            n_in += inside & np.all((ijk[S] >> shift[:, None]) == ijk[n], axis=1)
+        n_far = np.zeros(len(S), dtype=np.int64)
+        for l in range(2, int(lv[b]) + 1):
+            ok = lstar >= l
+            a_b = box_at(np.int64(l), (ijk[b] >> (lv[b] - l))[None, :])[0]
+            a_s = box_at(np.int64(l), ijk[S] >> np.where(ok, lv[S] - l, 0)[:, None])
+            key = a_b * tr.n_box + a_s
+            pos = np.minimum(np.searchsorted(pair_keys, key), len(pair_keys) - 1)
+            n_far += ok & (pair_keys[pos] == key)
+        assert np.array_equal(n_in, near.astype(np.int64)), b
+        assert np.array_equal(n_far, (~near).astype(np.int64)), b
+
+
+def test_near_lists_of_a_uniform_tree_are_the_neighbour_lists():
+    tr = W.uniform_tree(W.uniform_points(500, 14), 2)
+    a = W.near_lists(tr)
+    b = W.neighbours(tr, 2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

@@ -192,6 +192,37 @@ def neighbours(tree: Tree, lev: int) -> tuple[np.ndarray, np.ndarray, np.ndarray
     return boxes.astype(np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(nbr, dtype=np.int32)
 
 
+def near_lists(tree: Tree) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Near-field lists of the leaves of any octree (uniform or adaptive), in CSR form
+    (leaf [n] int32, ptr [n + 1] int32, src int32).
+
+    A source leaf s is near a target leaf b when their ancestors on the level min(level b,
+    level s) are adjacent or equal; every other pair is well separated on some level >= 2 at
+    which both ancestors exist, and is then in exactly one List-2 pair of those ancestors
+    (``interaction_pairs``).  The list of b holds
+      - the existing boxes of b's level adjacent to b, b included, whose point ranges cover
+        all their descendant leaves, and
+      - on every coarser level, the leaves adjacent to b's ancestor there.
+    No box appears twice, and together with the List-2 pairs of all levels every (target,
+    source) leaf pair is counted exactly once."""
+    index = [{tuple(int(v) for v in tree.ijk[b]): int(b) for b in tree.boxes_at(l)} for l in range(tree.n_levels)]
+    leaves = np.flatnonzero(tree.is_leaf)
+    ptr, src = [0], []
+    for b in leaves:
+        lb = int(tree.level[b])
+        ijk = tree.ijk[b].astype(np.int64)
+        for lev in range(lb + 1):
+            a = ijk >> (lb - lev)
+            for di in (-1, 0, 1):
+                for dj in (-1, 0, 1):
+                    for dk in (-1, 0, 1):
+                        n = index[lev].get((int(a[0]) + di, int(a[1]) + dj, int(a[2]) + dk))
+                        if n is not None and (lev == lb or tree.is_leaf[n]):
+                            src.append(n)
+        ptr.append(len(src))
+    return leaves.astype(np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(src, dtype=np.int32)
+
+
 def _point_keys(points: np.ndarray) -> np.ndarray:
     scale = float(1 << MAX_DEPTH)
     ijk = np.floor(points * scale).astype(np.int64)
