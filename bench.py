@@ -345,6 +345,51 @@ def full_fmm(torch, fmm, tr, w, reps=5, sample=512):
             "direct_4096_targets_ms": t_direct * 1e3, "direct_interactions_per_s": 4096 * len(w) / t_direct}
 
 
+def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
+    """The complete FMM potential on an adaptive octree (524,288 Gaussian-mixture points, <= 64
+    per leaf, leaves on several levels), Laplace p = 8, FP64: far field in the per-level form
+    (P2M of every box, M2L over the List-2 pairs of every level, L2P of every level's local at
+    its boxes' points) plus the near field over the adaptive near lists; error against the GPU
+    direct sum at sampled targets."""
+    import workloads as W
+    from paper_2305_17867_amd.farfield import FarField
+    dev = "cuda"
+    tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
+    w = W.normal_weights(tr.points.shape[0], SEED + 9)
+    ff = FarField("laplace", 8, "f64", tr, tr)
+    pts = torch.as_tensor(tr.points, dtype=torch.float64, device=dev)
+    wd = torch.as_tensor(w, dtype=torch.float64, device=dev)
+    leaves, ptr, nbr = W.near_lists(tr, max_src=2048)  # long lists split into parallel entries
+    d = fmm.Desc("laplace", 8, "f64")
+    lists = [torch.as_tensor(a, device=dev) for a in (leaves, ptr, nbr)]
+    rng = torch.as_tensor(tr.pt_range, dtype=torch.int64, device=dev)
+    out = {}
+
+    def far():
+        with torch.no_grad():
+            out["pot"] = ff.forward_raw(wd, pts, pts)[0]
+
+    def near():
+        fmm.p2p(d, *lists, rng, rng, pts, wd, pts, out["pot"])
+
+    t_far = time_kernel(torch, far, reps)
+    t_near = time_kernel(torch, near, reps)
+    far()
+    near()
+    idx = np.sort(np.random.Generator(np.random.PCG64(SEED + 10)).choice(len(w), sample, replace=False))
+    ref = fmm.direct(d, pts, wd, pts[torch.as_tensor(idx, device=dev)].contiguous())
+    got = out["pot"][torch.as_tensor(idx, device=dev)]
+    err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+    counts = tr.pt_range[:, 1] - tr.pt_range[:, 0]
+    inter = int(sum(int(counts[b]) * int(counts[nbr[ptr[k]:ptr[k + 1]]].sum()) for k, b in enumerate(leaves)))
+    leaf_levels = np.bincount(tr.level[tr.is_leaf])
+    return {"workload": "adaptive octree, 524288 Gaussian-mixture points, <= 64 per leaf, laplace p8 f64: "
+                        "far field (per level) + near field",
+            "leaves": int(tr.is_leaf.sum()), "near_entries": int(len(leaves)), "leaf_levels": {int(l): int(c) for l, c in enumerate(leaf_levels) if c},
+            "m2l_pairs": ff.n_pair, "far_ms": t_far * 1e3, "near_ms": t_near * 1e3, "near_interactions": inter,
+            "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample}
+
+
 def mixed_batch(torch, fmm, reps=10):
     """Yukawa (lambda = 2) + biharmonic far field of 524,288 Gaussian-mixture points (adaptive
     octree, <= 64 per leaf), orders 6/8/10 by level, FP32: one batch per (kernel, order), all
@@ -539,6 +584,8 @@ def main():
     if args.full_fmm or not (args.only or args.no_extras):
         log("complete FMM (far field + near field)")
         out["full_fmm"] = full_fmm(torch, fmm, tr, w)
+        log("complete FMM on an adaptive tree (far field + near field)")
+        out["full_fmm_adaptive"] = full_fmm_adaptive(torch, fmm)
     if not (args.only or args.no_extras):
         log("mixed workload (persistent, graph-captured launch)")
         out["mixed_batch"] = mixed_batch(torch, fmm)

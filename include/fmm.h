@@ -176,8 +176,10 @@ int fmm_l2l(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_
  *   box ids (ranges are clamped to [0, n_nbr]; ids outside [0, n_box) are skipped)
  *   tgt_range, src_range [n_box][2] i64 point ranges of every box into tgt / src
  *   src_xyz [n_src][3] real dtype; weight [n_src] dtype; tgt_xyz [n_tgt][3] real dtype
- *   potential [n_tgt] dtype, ACCUMULATED.  The target boxes of one call must have disjoint
- *   point ranges. */
+ *   potential [n_tgt] dtype, ACCUMULATED with atomic adds.  A target box may appear several
+ *   times, each with its own source list (a long list split so that its parts run in
+ *   parallel); the order in which the parts are added is then not fixed, so such results can
+ *   differ in the last bits from run to run.  A box listed once is added by one workgroup. */
 int fmm_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* nbr_ptr, int64_t n_nbr,
             const int32_t* nbr, int64_t n_box, const int64_t* tgt_range, const int64_t* src_range, int64_t n_src,
             const void* src_xyz, const void* weight, int64_t n_tgt, const void* tgt_xyz, void* potential,

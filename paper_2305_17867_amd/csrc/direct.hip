@@ -149,10 +149,20 @@ __device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64
       }
     }
   }
+  // a target box may be listed several times with different source lists, and those entries
+  // run in parallel: the sums are added atomically
+  R* pot = reinterpret_cast<R*>(a.pot);
 #pragma unroll
   for (int j = 0; j < KT; ++j) {
     const int64_t t = t0 + threadIdx.x + (int64_t)j * kThreads;
-    if (t < t1) reinterpret_cast<T*>(a.pot)[t] += acc[j];
+    if (t < t1) {
+      if constexpr (CPLX) {
+        atomicAdd(pot + 2 * t, acc[j].re);
+        atomicAdd(pot + 2 * t + 1, acc[j].im);
+      } else {
+        atomicAdd(pot + t, acc[j]);
+      }
+    }
   }
 }
 

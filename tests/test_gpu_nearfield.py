@@ -125,7 +125,7 @@ def test_full_fmm_matches_direct_sum(gpu_lib):
     assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)
 
 
-def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128):
+def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128, max_src=None):
     """Far field (per-level form: P2M of every box, M2L over the List-2 pairs of every level,
     L2P of every level's local expansion at its boxes' points) + near field over the adaptive
     near lists, against the direct sum of eq. (1) at sampled targets."""
@@ -139,7 +139,7 @@ def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128):
     P, wd = dev(tr.points, d.real_dtype), dev(w, d.value_dtype)
     with torch.no_grad():
         pot, _, _ = ff.forward_raw(wd, P, P)
-    leaves, ptr, nbr = W.near_lists(tr)
+    leaves, ptr, nbr = W.near_lists(tr, max_src)
     rng = dev(tr.pt_range, torch.int64)
     fmm.p2p(d, dev(leaves, torch.int32), dev(ptr, torch.int32), dev(nbr, torch.int32), rng, rng, P, wd, P, pot)
     idx = np.random.Generator(np.random.PCG64(seed + 1)).choice(n, sample, replace=False)
@@ -154,9 +154,24 @@ def test_adaptive_fmm_matches_direct_sum(gpu_lib, kernel, param, dt, dist):
     direct sum falls with the order and is small at p = 8 (FP32: down to its rounding)."""
     pts = W.plummer_points(6000, 81) if dist == "plummer" else W.gaussian_mixture_points(6000, 82)
     e4, tr = adaptive_fmm(gpu_lib, kernel, param, 4, dt, pts, 32, 83)
-    e8, _ = adaptive_fmm(gpu_lib, kernel, param, 8, dt, pts, 32, 83)
+    e8, _ = adaptive_fmm(gpu_lib, kernel, param, 8, dt, pts, 32, 83, max_src=256)
     assert len(set(tr.level[tr.is_leaf].tolist())) >= 3
     if dt == "f32":
         assert e4 < 2e-2 and e8 < 5e-5, (e4, e8)
     else:
         assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)
+
+
+@pytest.mark.parametrize("dt", ["f64", "c128", "f32"])
+def test_p2p_split_lists_match_whole_lists(gpu_lib, dt):
+    """Near lists split into entries of at most 64 source points (a target box listed several
+    times, its parts added atomically) give the near field of the whole lists."""
+    tr = W.adaptive_tree(W.plummer_points(5000, 84), 24)
+    kernel, param = ("helmholtz", 1.5) if dt == "c128" else ("laplace", 0.0)
+    w = W.normal_weights(5000, 85, complex_=dt == "c128")
+    n = tr.points.shape[0]
+    whole = run_p2p(gpu_lib, kernel, param, dt, tr, tr, *W.near_lists(tr), w, np.zeros(n, dtype=w.dtype))
+    owner, ptr, nbr = W.near_lists(tr, 64)
+    assert len(owner) > len(np.unique(owner))
+    split = run_p2p(gpu_lib, kernel, param, dt, tr, tr, owner, ptr, nbr, w, np.zeros(n, dtype=w.dtype))
+    assert rel(split, whole) < (1e-6 if dt == "f32" else 1e-13), rel(split, whole)

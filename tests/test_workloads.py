@@ -82,8 +82,9 @@ def test_generators_are_seeded():
     assert np.all((g >= 0) & (g < 1))
 
 
-@pytest.mark.parametrize("points,max_leaf", [("plummer", 16), ("mixture", 24), ("uniform", 40)])
-def test_near_lists_and_list2_partition_every_leaf_pair(points, max_leaf):
+@pytest.mark.parametrize("points,max_leaf,max_src", [("plummer", 16, None), ("mixture", 24, None), ("uniform", 40, None),
+                                                     ("plummer", 16, 100), ("mixture", 24, 60)])
+def test_near_lists_and_list2_partition_every_leaf_pair(points, max_leaf, max_src):
     """Every (target leaf, source leaf) pair of an adaptive tree is counted exactly once: by
     the near list of the target leaf (one list box containing the source leaf), or by exactly
     one List-2 pair of their ancestors on a level >= 2.  Checked by brute force over all leaf
@@ -94,8 +95,21 @@ def test_near_lists_and_list2_partition_every_leaf_pair(points, max_leaf):
            "uniform": lambda: W.uniform_points(3000, 13)}[points]()
     tr = W.adaptive_tree(pts, max_leaf)
     assert len(set(tr.level[tr.is_leaf].tolist())) > 1 or points == "uniform"
-    leaves, ptr, src = W.near_lists(tr)
-    assert np.array_equal(leaves, np.flatnonzero(tr.is_leaf))
+    owner, ptr, src = W.near_lists(tr, max_src)
+    leaves = np.flatnonzero(tr.is_leaf)
+    assert np.array_equal(np.unique(owner), leaves)
+    counts = tr.counts()
+    if max_src is None:
+        assert np.array_equal(owner, leaves)
+    else:
+        assert len(owner) > len(leaves)  # some lists were split
+        for k in range(len(owner)):  # each entry within the cap, or a single box that is a leaf
+            part = src[ptr[k]:ptr[k + 1]]
+            assert counts[part].sum() <= max_src or (len(part) == 1 and tr.is_leaf[part[0]])
+    # the entries of one leaf, concatenated
+    per_leaf = {int(b): [] for b in leaves}
+    for k, b in enumerate(owner):
+        per_leaf[int(b)].append(src[ptr[k]:ptr[k + 1]])
     t, s = W.interaction_pairs(tr)
     pair_keys = np.sort(t.astype(np.int64) * tr.n_box + s)
     lv = tr.level.astype(np.int64)
@@ -109,8 +123,8 @@ def test_near_lists_and_list2_partition_every_leaf_pair(points, max_leaf):
         return order[np.minimum(pos, len(order) - 1)]  # entries off the tree are masked by the caller
 
     S = leaves.astype(np.int64)
-    for k, b in enumerate(leaves):
-        lst = src[ptr[k]:ptr[k + 1]].astype(np.int64)
+    for b in leaves:
+        lst = np.concatenate(per_leaf[int(b)]).astype(np.int64)
         assert len(np.unique(lst)) == len(lst)
         lstar = np.minimum(lv[b], lv[S])
         anc_b = ijk[b][None, :] >> (lv[b] - lstar)[:, None]

@@ -192,7 +192,7 @@ def neighbours(tree: Tree, lev: int) -> tuple[np.ndarray, np.ndarray, np.ndarray
     return boxes.astype(np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(nbr, dtype=np.int32)
 
 
-def near_lists(tree: Tree) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+def near_lists(tree: Tree, max_src: int | None = None) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Near-field lists of the leaves of any octree (uniform or adaptive), in CSR form
     (leaf [n] int32, ptr [n + 1] int32, src int32).
 
@@ -204,13 +204,33 @@ def near_lists(tree: Tree) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
         all their descendant leaves, and
       - on every coarser level, the leaves adjacent to b's ancestor there.
     No box appears twice, and together with the List-2 pairs of all levels every (target,
-    source) leaf pair is counted exactly once."""
+    source) leaf pair is counted exactly once.
+
+    With max_src, a list whose boxes hold more than max_src points in all is split into
+    several entries of the same leaf: boxes above max_src points are replaced by their
+    children (down to leaves), and the boxes are packed in order into entries of at most
+    max_src points (a single leaf above the cap is an entry of its own).  A coarse leaf next
+    to a densely refined region would otherwise leave one workgroup with most of the work."""
     index = [{tuple(int(v) for v in tree.ijk[b]): int(b) for b in tree.boxes_at(l)} for l in range(tree.n_levels)]
+    count = tree.pt_range[:, 1] - tree.pt_range[:, 0]
+
+    def split(n):
+        if count[n] <= max_src or tree.is_leaf[n]:
+            return [n]
+        lev, base = int(tree.level[n]) + 1, 2 * tree.ijk[n].astype(np.int64)
+        out = []
+        for o in range(8):
+            c = index[lev].get((int(base[0]) + (o & 1), int(base[1]) + ((o >> 1) & 1), int(base[2]) + ((o >> 2) & 1)))
+            if c is not None:
+                out += split(c)
+        return out
+
     leaves = np.flatnonzero(tree.is_leaf)
-    ptr, src = [0], []
+    owner, ptr, src = [], [0], []
     for b in leaves:
         lb = int(tree.level[b])
         ijk = tree.ijk[b].astype(np.int64)
+        lst = []
         for lev in range(lb + 1):
             a = ijk >> (lb - lev)
             for di in (-1, 0, 1):
@@ -218,9 +238,23 @@ def near_lists(tree: Tree) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
                     for dk in (-1, 0, 1):
                         n = index[lev].get((int(a[0]) + di, int(a[1]) + dj, int(a[2]) + dk))
                         if n is not None and (lev == lb or tree.is_leaf[n]):
-                            src.append(n)
+                            lst.append(n)
+        if max_src is None or count[lst].sum() <= max_src:
+            owner.append(b)
+            src += lst
+            ptr.append(len(src))
+            continue
+        total = 0
+        for n in [m for x in lst for m in split(x)]:
+            if total and total + count[n] > max_src:
+                owner.append(b)
+                ptr.append(len(src))
+                total = 0
+            src.append(n)
+            total += count[n]
+        owner.append(b)
         ptr.append(len(src))
-    return leaves.astype(np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(src, dtype=np.int32)
+    return np.asarray(owner, dtype=np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(src, dtype=np.int32)
 
 
 def _point_keys(points: np.ndarray) -> np.ndarray:
