@@ -104,21 +104,27 @@ __device__ inline void clamp_range(const int64_t* rng, int64_t b, int64_t n, int
   hi = hi < lo ? lo : (hi > n ? n : hi);
 }
 
-// Targets [t0, t1) of one box against the sources of its neighbour boxes, KT targets per
-// thread (kThreads apart), so that each staged source tile feeds KT sums.
+// Targets [t0, t1) of one box against the sources of its neighbour boxes.  The sources of the
+// list are one stream: a scan of the boxes' point counts (a segment of up to kThreads list
+// entries at a time) maps a stream position to its box, so every staged tile holds kThreads
+// sources however small the boxes are.  Thread layout: `split` consecutive lanes share a target
+// and take every split-th source of a tile (their sums are combined by butterfly shuffles at
+// the end); KT targets per thread, kThreads / split apart.
 template <typename R, bool CPLX, int KT>
-__device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64_t e0, int64_t e1, R* sx, R* sy, R* sz,
-                                 typename Val<R, CPLX>::T* sw) {
+__device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64_t e0, int64_t e1, int split, R* sx,
+                                 R* sy, R* sz, typename Val<R, CPLX>::T* sw, int64_t* s_lo, int64_t* s_cum) {
   using T = typename Val<R, CPLX>::T;
   const R* tg = reinterpret_cast<const R*>(a.tgt);
   const R* sr = reinterpret_cast<const R*>(a.src);
   const T* w = reinterpret_cast<const T*>(a.w);
   const R prm = (R)a.param;
+  const int tid = threadIdx.x;
+  const int tl = tid / split, sp = tid % split, per = kThreads / split;
   R x[KT], y[KT], z[KT];
   T acc[KT];
 #pragma unroll
   for (int j = 0; j < KT; ++j) {
-    const int64_t t = t0 + threadIdx.x + (int64_t)j * kThreads;
+    const int64_t t = t0 + tl + (int64_t)j * per;
     x[j] = y[j] = z[j] = R(0);
     if (t < t1) {
       x[j] = tg[3 * t];
@@ -127,35 +133,70 @@ __device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64
     }
     acc[j] = T{};
   }
-  for (int64_t e = e0; e < e1; ++e) {
-    const int sb = a.nbr[e];
-    if (sb < 0 || sb >= a.n_box) continue;  // uniform
-    int64_t slo, shi;
-    clamp_range(a.src_range, sb, a.n_src, slo, shi);
-    for (int64_t base = slo; base < shi; base += kThreads) {
+  for (int64_t seg = e0; seg < e1; seg += kThreads) {
+    const int ns = (int)((e1 - seg) < kThreads ? (e1 - seg) : kThreads);
+    int64_t lo = 0, cnt = 0;
+    if (tid < ns) {
+      const int sb = a.nbr[seg + tid];
+      if (sb >= 0 && sb < a.n_box) {
+        int64_t hi;
+        clamp_range(a.src_range, sb, a.n_src, lo, hi);
+        cnt = hi - lo;
+      }
+    }
+    __syncthreads();  // the previous segment's tables are no longer read
+    s_lo[tid] = lo;
+    s_cum[tid] = cnt;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {  // inclusive scan of the counts
+      const int64_t v = tid >= off ? s_cum[tid - off] : 0;
       __syncthreads();
-      const int64_t jsrc = base + threadIdx.x;
-      if (jsrc < shi) {
-        sx[threadIdx.x] = sr[3 * jsrc];
-        sy[threadIdx.x] = sr[3 * jsrc + 1];
-        sz[threadIdx.x] = sr[3 * jsrc + 2];
-        sw[threadIdx.x] = w[jsrc];
+      s_cum[tid] += v;
+      __syncthreads();
+    }
+    const int64_t total = s_cum[kThreads - 1];
+    for (int64_t base = 0; base < total; base += kThreads) {
+      __syncthreads();  // the previous tile has been used
+      const int64_t f = base + tid;
+      if (f < total) {
+        int l = 0, h = ns - 1;  // first entry whose inclusive count exceeds f
+        while (l < h) {
+          const int m = (l + h) >> 1;
+          if (s_cum[m] > f) h = m;
+          else l = m + 1;
+        }
+        const int64_t j = s_lo[l] + (f - (l > 0 ? s_cum[l - 1] : 0));
+        sx[tid] = sr[3 * j];
+        sy[tid] = sr[3 * j + 1];
+        sz[tid] = sr[3 * j + 2];
+        sw[tid] = w[j];
       }
       __syncthreads();
-      const int cnt = (int)((shi - base) < kThreads ? (shi - base) : kThreads);
-      for (int k = 0; k < cnt; ++k) {
+      const int n = (int)((total - base) < kThreads ? (total - base) : kThreads);
+      for (int k = sp; k < n; k += split) {
 #pragma unroll
         for (int j = 0; j < KT; ++j) add_green<R, CPLX>(acc[j], a.kernel, prm, x[j] - sx[k], y[j] - sy[k], z[j] - sz[k], sw[k]);
       }
     }
   }
-  // a target box may be listed several times with different source lists, and those entries
-  // run in parallel: the sums are added atomically
+  // combine the split lanes of each target; a target box may be listed several times with
+  // different source lists, and those entries run in parallel: the sums are added atomically
+  for (int m = 1; m < split; m <<= 1) {
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+      if constexpr (CPLX) {
+        acc[j].re += shfl_xor_d(acc[j].re, m);
+        acc[j].im += shfl_xor_d(acc[j].im, m);
+      } else {
+        acc[j] += shfl_xor_d(acc[j], m);
+      }
+    }
+  }
   R* pot = reinterpret_cast<R*>(a.pot);
 #pragma unroll
   for (int j = 0; j < KT; ++j) {
-    const int64_t t = t0 + threadIdx.x + (int64_t)j * kThreads;
-    if (t < t1) {
+    const int64_t t = t0 + tl + (int64_t)j * per;
+    if (sp == 0 && t < t1) {
       if constexpr (CPLX) {
         atomicAdd(pot + 2 * t, acc[j].re);
         atomicAdd(pot + 2 * t + 1, acc[j].im);
@@ -171,6 +212,7 @@ __global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
   using T = typename Val<R, CPLX>::T;
   __shared__ R sx[kThreads], sy[kThreads], sz[kThreads];
   __shared__ T sw[kThreads];
+  __shared__ int64_t s_lo[kThreads], s_cum[kThreads];
   const int tb = a.tbox[blockIdx.x];
   if (tb < 0 || tb >= a.n_box) return;  // uniform
   int64_t tlo, thi;
@@ -179,12 +221,19 @@ __global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
   int64_t e0 = a.nbr_ptr[blockIdx.x], e1 = a.nbr_ptr[blockIdx.x + 1];
   e0 = e0 < 0 ? 0 : (e0 > a.n_nbr ? a.n_nbr : e0);
   e1 = e1 < e0 ? e0 : (e1 > a.n_nbr ? a.n_nbr : e1);
-  // workgroup y takes the chunks y, y + gridDim.y, ... of 2 kThreads targets; a chunk of at
-  // most kThreads targets is taken one per thread, a larger one two per thread
+  // workgroup y takes the chunks y, y + gridDim.y, ... of 2 kThreads targets; a chunk of more
+  // than kThreads targets is taken two per thread, a smaller one by as many lanes per target
+  // (a power of two up to 16) as fill the workgroup
   for (int64_t t0 = tlo + (int64_t)blockIdx.y * 2 * kThreads; t0 < thi; t0 += (int64_t)gridDim.y * 2 * kThreads) {
     const int64_t t1 = t0 + 2 * kThreads < thi ? t0 + 2 * kThreads : thi;
-    if (t1 - t0 <= kThreads) p2p_chunk<R, CPLX, 1>(a, t0, t1, e0, e1, sx, sy, sz, sw);
-    else p2p_chunk<R, CPLX, 2>(a, t0, t1, e0, e1, sx, sy, sz, sw);
+    const int64_t n = t1 - t0;
+    if (n > kThreads) {
+      p2p_chunk<R, CPLX, 2>(a, t0, t1, e0, e1, 1, sx, sy, sz, sw, s_lo, s_cum);
+    } else {
+      int split = 1;
+      while (split < 16 && n * split * 2 <= kThreads) split *= 2;
+      p2p_chunk<R, CPLX, 1>(a, t0, t1, e0, e1, split, sx, sy, sz, sw, s_lo, s_cum);
+    }
   }
 }
 
