@@ -32,6 +32,8 @@ struct fmm_plan_s {
 namespace {
 constexpr size_t kP2MPartBytes = 16u << 20;  // capacity of fmm_plan_s::d_p2m_part
 constexpr int64_t kP2MChunkPoints = 2048;     // points per P2M workgroup for large boxes
+constexpr int64_t kP2MMinChunkPoints = 512;   // smallest chunk when boxes are split to fill the GPU
+constexpr int64_t kP2MFillGroups = 2048;      // workgroups a P2M launch over few boxes aims for
 }  // namespace
 
 struct fmm_multi_s {
@@ -239,6 +241,11 @@ static void set_p2m_chunks(fmm_plan plan, P2MArgs& a) {
   if (a.n_box <= 0 || !plan->d_p2m_part) return;
   const int64_t per_box = (a.n_pts + a.n_box - 1) / a.n_box;
   int64_t ny = (per_box + kP2MChunkPoints - 1) / kP2MChunkPoints;
+  // few boxes (coarse levels): more, smaller chunks, so that the launch has about
+  // kP2MFillGroups workgroups, but at least kP2MMinChunkPoints points per chunk
+  const int64_t fill = std::min<int64_t>((kP2MFillGroups + a.n_box - 1) / a.n_box,
+                                         (per_box + kP2MMinChunkPoints - 1) / kP2MMinChunkPoints);
+  ny = std::max<int64_t>(ny, fill);
   const int64_t width = (int64_t)plan->nc * (dtype_complex(plan->desc.dtype) ? 2 : 1);
   ny = std::min<int64_t>(ny, (int64_t)(kP2MPartBytes / sizeof(double)) / (a.n_box * width));
   a.ny = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ny, 1024));
