@@ -74,6 +74,7 @@ struct L2PArgs {
   double xsign;             // X = xsign (x - c) / h  (+1: local evaluation; -1: at sources)
   void* grad;               // [n_pts][3] real, accumulated: gscale(x) * d phi / d x (optional)
   const void* gscale;       // [n_pts] real per-point factor of grad (null = 1)
+  int64_t chunk;            // points of a box per workgroup chunk (set by the launcher)
 };
 
 struct TableArgs {

@@ -255,12 +255,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   __shared__ R Lc[(NP + 2) * W];  // + 2 zero entries read ahead by horner_u
   __shared__ R Lg[3][((NG > 0 ? NG : 1) + 2) * W];
   const int64_t b = blockIdx.x;
-  // points of the box: workgroup y of the box takes the chunks y, y + gridDim.y, ... of kChunk
+  // points of the box: workgroup y of the box takes the chunks y, y + gridDim.y, ... of ch
   // points (large boxes of coarse levels are spread over several workgroups)
+  const int64_t ch = a.chunk > 0 ? a.chunk : kChunk;
   int64_t lo = a.range[2 * b], hi = a.range[2 * b + 1];
   lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
   hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
-  if (lo + (int64_t)blockIdx.y * kChunk >= hi) return;  // uniform: no points for this workgroup
+  if (lo + (int64_t)blockIdx.y * ch >= hi) return;  // uniform: no points for this workgroup
   int lev = a.level[b];
   lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
   const double h = a.level_h[lev];
@@ -298,8 +299,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const R* xyz = reinterpret_cast<const R*>(a.xyz);
   const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)(a.xsign / h);
   constexpr int KM = kMaxU<CPLX, GRAD>;
-  for (int64_t c0 = lo + (int64_t)blockIdx.y * kChunk; c0 < hi; c0 += (int64_t)gridDim.y * kChunk) {  // uniform
-    const int64_t c1 = c0 + kChunk < hi ? c0 + kChunk : hi;
+  for (int64_t c0 = lo + (int64_t)blockIdx.y * ch; c0 < hi; c0 += (int64_t)gridDim.y * ch) {  // uniform
+    const int64_t c1 = c0 + ch < hi ? c0 + ch : hi;
     for (int64_t s0 = c0; s0 < c1;) {  // passes sized to the points left in the chunk
       const int64_t left = c1 - s0;
       int step;
@@ -313,10 +314,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
 }
 
 template <int P>
-int launch_l2p_p(const L2PArgs& a, int dtype, hipStream_t s) {
-  // workgroups per box: enough that the average box gets one per kChunk targets
-  const int64_t per_box = a.n_box > 0 ? (a.n_pts + a.n_box - 1) / a.n_box : 1;
-  const int64_t ny = std::max<int64_t>(1, std::min<int64_t>(1024, (per_box + kChunk - 1) / kChunk));
+int launch_l2p_p(const L2PArgs& a_in, int dtype, hipStream_t s) {
+  // workgroups per box: enough that the average box gets one per kChunk targets; with few
+  // boxes (coarse levels), more and smaller chunks (at least 2 kThreads points, a multiple of
+  // kThreads) so that the launch has about kFillGroups workgroups
+  constexpr int64_t kFillGroups = 4096;
+  const int64_t per_box = a_in.n_box > 0 ? (a_in.n_pts + a_in.n_box - 1) / a_in.n_box : 1;
+  int64_t ny = (per_box + kChunk - 1) / kChunk, ch = kChunk;
+  const int64_t fill = a_in.n_box > 0 ? std::min<int64_t>((kFillGroups + a_in.n_box - 1) / a_in.n_box, per_box / (2 * kThreads)) : 0;
+  if (fill > ny) {
+    ch = ((per_box + fill - 1) / fill + kThreads - 1) / kThreads * kThreads;
+    ny = (per_box + ch - 1) / ch;
+  }
+  ny = std::max<int64_t>(1, std::min<int64_t>(1024, ny));
+  L2PArgs a = a_in;
+  a.chunk = ch;
   dim3 g((unsigned)a.n_box, (unsigned)ny), t(kThreads);
   const bool grad = a.grad != nullptr;
   switch (dtype) {
