@@ -339,10 +339,30 @@ def full_fmm(torch, fmm, tr, w, reps=5, sample=512):
     err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
     counts = tr.pt_range[:, 1] - tr.pt_range[:, 0]
     inter = int(sum(int(counts[b]) * int(counts[nbr[ptr[k]:ptr[k + 1]]].sum()) for k, b in enumerate(boxes)))
+    # the same potential in FP32 (FP64 tables, FP32 products), against the same FP64 reference
+    ff32 = FarField("laplace", 8, "f32", tr, tr, tree_pass=True)
+    d32 = fmm.Desc("laplace", 8, "f32")
+    pts32, w32 = pts.float(), wd.float()
+
+    def far32():
+        with torch.no_grad():
+            out["pot32"] = ff32.forward_raw(w32, pts32, pts32)[0]
+
+    def near32():
+        fmm.p2p(d32, *lists, rng, rng, pts32, w32, pts32, out["pot32"])
+
+    t_far32 = time_kernel(torch, far32, reps)
+    t_near32 = time_kernel(torch, near32, reps)
+    far32()
+    near32()
+    got32 = out["pot32"][torch.as_tensor(idx, device=dev)].double()
+    err32 = float(torch.linalg.norm(got32 - ref) / torch.linalg.norm(ref))
     return {"workload": "uniform 2^20 points, depth 4, laplace p8 f64: far field (tree pass) + near field",
             "far_ms": t_far * 1e3, "near_ms": t_near * 1e3, "near_interactions": inter,
             "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample,
-            "direct_4096_targets_ms": t_direct * 1e3, "direct_interactions_per_s": 4096 * len(w) / t_direct}
+            "direct_4096_targets_ms": t_direct * 1e3, "direct_interactions_per_s": 4096 * len(w) / t_direct,
+            "f32": {"far_ms": t_far32 * 1e3, "near_ms": t_near32 * 1e3, "rel_error_vs_direct": err32,
+                    "speedup_vs_f64": (t_far + t_near) / (t_far32 + t_near32)}}
 
 
 def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
