@@ -31,28 +31,30 @@ __device__ inline float inv_sqrt(float v) {
   return fmaf(0.5f * y, fmaf(-v * y, y, 1.0f), y);
 }
 
-// acc += G(d) w for one source at offset d = x - y (d != 0)
-template <typename R, bool CPLX, typename T>
-__device__ inline void add_green(T& acc, int kernel, R prm, R dx, R dy, R dz, const T& w) {
+// acc += G(d) w for one source at offset d = x - y; d = 0 adds nothing (1/r is taken as 0
+// there, which zeroes every kernel's term without a branch).  K is the kernel (compile time).
+template <typename R, bool CPLX, int K, typename T>
+__device__ inline void add_green(T& acc, R prm, R dx, R dy, R dz, const T& w) {
   const R inv4pi = R(1.0 / (4.0 * M_PI));
   const R r2 = dx * dx + dy * dy + dz * dz;
-  if (r2 == R(0)) return;
-  const R ir = inv_sqrt(r2);
-  const R r = r2 * ir;
+  const R ir0 = inv_sqrt(r2);
+  const R ir = r2 > R(0) ? ir0 : R(0);
   if constexpr (CPLX) {
     // Helmholtz exp(i k r) / (4 pi r)
+    const R r = r2 * ir;
     R sn, cs;
     if constexpr (sizeof(R) == 8) sincos(prm * r, &sn, &cs);
     else sincosf(prm * r, &sn, &cs);
     const R g = inv4pi * ir;
     const T G(g * cs, g * sn);
     acc += G * w;
-  } else {
-    R G;
-    if (kernel == FMM_LAPLACE) G = inv4pi * ir;
-    else if (kernel == FMM_YUKAWA) G = exp(-prm * r) * inv4pi * ir;
-    else G = r;
-    acc += G * w;
+  } else if constexpr (K == FMM_LAPLACE) {
+    acc += (inv4pi * ir) * w;
+  } else if constexpr (K == FMM_YUKAWA) {
+    const R r = r2 * ir;
+    acc += (exp(-prm * r) * inv4pi * ir) * w;
+  } else {  // biharmonic: G = r
+    acc += (r2 * ir) * w;
   }
 }
 
@@ -61,7 +63,7 @@ __device__ inline R lane_xor(R v, int m) { return shfl_xor_d(v, m); }
 template <typename R>
 __device__ inline Cx<R> lane_xor(Cx<R> v, int m) { return {shfl_xor_d(v.re, m), shfl_xor_d(v.im, m)}; }
 
-template <typename R, bool CPLX>
+template <typename R, bool CPLX, int K>
 __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
   using T = typename Val<R, CPLX>::T;
   __shared__ R sx[kThreads], sy[kThreads], sz[kThreads];
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
     }
     __syncthreads();
     const int cnt = (int)((a.n_src - base) < kThreads ? (a.n_src - base) : kThreads);
-    for (int k = ls; k < cnt; k += split) add_green<R, CPLX>(acc, a.kernel, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
+    for (int k = ls; k < cnt; k += split) add_green<R, CPLX, K>(acc, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
   }
   for (int m = 1; m < split; m <<= 1) acc += lane_xor(acc, m);  // all lanes active here
   if (ls == 0 && t < a.n_tgt) reinterpret_cast<T*>(a.pot)[t] = acc;
@@ -110,7 +112,7 @@ __device__ inline void clamp_range(const int64_t* rng, int64_t b, int64_t n, int
 // sources however small the boxes are.  Thread layout: `split` consecutive lanes share a target
 // and take every split-th source of a tile (their sums are combined by butterfly shuffles at
 // the end); KT targets per thread, kThreads / split apart.
-template <typename R, bool CPLX, int KT>
+template <typename R, bool CPLX, int K, int KT>
 __device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64_t e0, int64_t e1, int split, R* sx,
                                  R* sy, R* sz, typename Val<R, CPLX>::T* sw, int64_t* s_lo, int64_t* s_cum) {
   using T = typename Val<R, CPLX>::T;
@@ -175,7 +177,7 @@ __device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64
       const int n = (int)((total - base) < kThreads ? (total - base) : kThreads);
       for (int k = sp; k < n; k += split) {
 #pragma unroll
-        for (int j = 0; j < KT; ++j) add_green<R, CPLX>(acc[j], a.kernel, prm, x[j] - sx[k], y[j] - sy[k], z[j] - sz[k], sw[k]);
+        for (int j = 0; j < KT; ++j) add_green<R, CPLX, K>(acc[j], prm, x[j] - sx[k], y[j] - sy[k], z[j] - sz[k], sw[k]);
       }
     }
   }
@@ -207,7 +209,7 @@ __device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64
   }
 }
 
-template <typename R, bool CPLX>
+template <typename R, bool CPLX, int K>
 __global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
   using T = typename Val<R, CPLX>::T;
   __shared__ R sx[kThreads], sy[kThreads], sz[kThreads];
@@ -228,16 +230,31 @@ __global__ __launch_bounds__(kThreads) void p2p_kernel(P2PArgs a) {
     const int64_t t1 = t0 + 2 * kThreads < thi ? t0 + 2 * kThreads : thi;
     const int64_t n = t1 - t0;
     if (n > kThreads) {
-      p2p_chunk<R, CPLX, 2>(a, t0, t1, e0, e1, 1, sx, sy, sz, sw, s_lo, s_cum);
+      p2p_chunk<R, CPLX, K, 2>(a, t0, t1, e0, e1, 1, sx, sy, sz, sw, s_lo, s_cum);
     } else {
       int split = 1;
       while (split < 16 && n * split * 2 <= kThreads) split *= 2;
-      p2p_chunk<R, CPLX, 1>(a, t0, t1, e0, e1, split, sx, sy, sz, sw, s_lo, s_cum);
+      p2p_chunk<R, CPLX, K, 1>(a, t0, t1, e0, e1, split, sx, sy, sz, sw, s_lo, s_cum);
     }
   }
 }
 
 }  // namespace
+
+// Launch KERNEL<R, CPLX, K> for the dtype and the kernel of the arguments (complex dtypes are
+// Helmholtz); returns from the enclosing function on a bad dtype or kernel.
+#define FMM_GREEN_DISPATCH(KERNEL, G, T, S, A, DTYPE)                                                     \
+  switch ((DTYPE) * 8 + ((DTYPE) == FMM_C128 || (DTYPE) == FMM_C64 ? 0 : (A).kernel)) {                     \
+    case FMM_F64 * 8 + FMM_LAPLACE: hipLaunchKernelGGL((KERNEL<double, false, FMM_LAPLACE>), G, T, 0, S, A); break;       \
+    case FMM_F64 * 8 + FMM_YUKAWA: hipLaunchKernelGGL((KERNEL<double, false, FMM_YUKAWA>), G, T, 0, S, A); break;         \
+    case FMM_F64 * 8 + FMM_BIHARMONIC: hipLaunchKernelGGL((KERNEL<double, false, FMM_BIHARMONIC>), G, T, 0, S, A); break; \
+    case FMM_F32 * 8 + FMM_LAPLACE: hipLaunchKernelGGL((KERNEL<float, false, FMM_LAPLACE>), G, T, 0, S, A); break;        \
+    case FMM_F32 * 8 + FMM_YUKAWA: hipLaunchKernelGGL((KERNEL<float, false, FMM_YUKAWA>), G, T, 0, S, A); break;          \
+    case FMM_F32 * 8 + FMM_BIHARMONIC: hipLaunchKernelGGL((KERNEL<float, false, FMM_BIHARMONIC>), G, T, 0, S, A); break;  \
+    case FMM_C128 * 8: hipLaunchKernelGGL((KERNEL<double, true, FMM_HELMHOLTZ>), G, T, 0, S, A); break;                 \
+    case FMM_C64 * 8: hipLaunchKernelGGL((KERNEL<float, true, FMM_HELMHOLTZ>), G, T, 0, S, A); break;                   \
+    default: return fail(FMM_EINVAL, "dtype and kernel");                                                 \
+  }
 
 int launch_p2p(const P2PArgs& a, int dtype, hipStream_t s) {
   if (a.n_tbox == 0) return FMM_OK;
@@ -246,13 +263,7 @@ int launch_p2p(const P2PArgs& a, int dtype, hipStream_t s) {
   const int64_t chunks = (per_box + 2 * kThreads - 1) / (2 * kThreads);
   const int64_t ny = chunks < 1 ? 1 : (chunks < 1024 ? chunks : 1024);
   dim3 g((unsigned)a.n_tbox, (unsigned)ny), t(kThreads);
-  switch (dtype) {
-    case FMM_F64: hipLaunchKernelGGL((p2p_kernel<double, false>), g, t, 0, s, a); break;
-    case FMM_F32: hipLaunchKernelGGL((p2p_kernel<float, false>), g, t, 0, s, a); break;
-    case FMM_C128: hipLaunchKernelGGL((p2p_kernel<double, true>), g, t, 0, s, a); break;
-    case FMM_C64: hipLaunchKernelGGL((p2p_kernel<float, true>), g, t, 0, s, a); break;
-    default: return fail(FMM_EINVAL, "dtype");
-  }
+  FMM_GREEN_DISPATCH(p2p_kernel, g, t, s, a, dtype);
   FMM_HIP_CHECK(hipGetLastError());
   return FMM_OK;
 }
@@ -266,13 +277,7 @@ int launch_direct(const DirectArgs& a_in, int dtype, hipStream_t s) {
   while (a.split < 64 && (a.n_tgt * a.split + kThreads - 1) / kThreads < 1024) a.split *= 2;
   const int64_t per_block = kThreads / a.split;
   dim3 g((unsigned)((a.n_tgt + per_block - 1) / per_block)), t(kThreads);
-  switch (dtype) {
-    case FMM_F64: hipLaunchKernelGGL((direct_kernel<double, false>), g, t, 0, s, a); break;
-    case FMM_F32: hipLaunchKernelGGL((direct_kernel<float, false>), g, t, 0, s, a); break;
-    case FMM_C128: hipLaunchKernelGGL((direct_kernel<double, true>), g, t, 0, s, a); break;
-    case FMM_C64: hipLaunchKernelGGL((direct_kernel<float, true>), g, t, 0, s, a); break;
-    default: return fail(FMM_EINVAL, "dtype");
-  }
+  FMM_GREEN_DISPATCH(direct_kernel, g, t, s, a, dtype);
   FMM_HIP_CHECK(hipGetLastError());
   return FMM_OK;
 }
