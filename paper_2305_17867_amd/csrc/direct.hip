@@ -175,6 +175,7 @@ __device__ inline void p2p_chunk(const P2PArgs& a, int64_t t0, int64_t t1, int64
       }
       __syncthreads();
       const int n = (int)((total - base) < kThreads ? (total - base) : kThreads);
+#pragma unroll 4
       for (int k = sp; k < n; k += split) {
 #pragma unroll
         for (int j = 0; j < KT; ++j) add_green<R, CPLX, K>(acc[j], prm, x[j] - sx[k], y[j] - sy[k], z[j] - sz[k], sw[k]);
