@@ -367,16 +367,17 @@ def full_fmm(torch, fmm, tr, w, reps=5, sample=512):
 
 def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
     """The complete FMM potential on an adaptive octree (524,288 Gaussian-mixture points, <= 64
-    per leaf, leaves on several levels), Laplace p = 8, FP64: far field in the per-level form
-    (P2M of every box, M2L over the List-2 pairs of every level, L2P of every level's local at
-    its boxes' points) plus the near field over the adaptive near lists; error against the GPU
-    direct sum at sampled targets."""
+    per leaf, leaves on several levels), Laplace p = 8, FP64: far field as a tree pass (P2M at
+    the leaves of every level, M2M up, M2L over the List-2 pairs of every level, L2L down, L2P
+    at the leaves; the per-level form is timed beside it) plus the near field over the adaptive
+    near lists; error against the GPU direct sum at sampled targets."""
     import workloads as W
     from paper_2305_17867_amd.farfield import FarField
     dev = "cuda"
     tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
     w = W.normal_weights(tr.points.shape[0], SEED + 9)
-    ff = FarField("laplace", 8, "f64", tr, tr)
+    ff = FarField("laplace", 8, "f64", tr, tr, tree_pass=True)
+    ff_level = FarField("laplace", 8, "f64", tr, tr)
     pts = torch.as_tensor(tr.points, dtype=torch.float64, device=dev)
     wd = torch.as_tensor(w, dtype=torch.float64, device=dev)
     leaves, ptr, nbr = W.near_lists(tr, max_src=2048)  # long lists split into parallel entries
@@ -392,7 +393,12 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
     def near():
         fmm.p2p(d, *lists, rng, rng, pts, wd, pts, out["pot"])
 
+    def far_level():
+        with torch.no_grad():
+            ff_level.forward_raw(wd, pts, pts)
+
     t_far = time_kernel(torch, far, reps)
+    t_far_level = time_kernel(torch, far_level, reps)
     t_near = time_kernel(torch, near, reps)
     far()
     near()
@@ -404,9 +410,10 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
     inter = int(sum(int(counts[b]) * int(counts[nbr[ptr[k]:ptr[k + 1]]].sum()) for k, b in enumerate(leaves)))
     leaf_levels = np.bincount(tr.level[tr.is_leaf])
     return {"workload": "adaptive octree, 524288 Gaussian-mixture points, <= 64 per leaf, laplace p8 f64: "
-                        "far field (per level) + near field",
+                        "far field (tree pass) + near field",
             "leaves": int(tr.is_leaf.sum()), "near_entries": int(len(leaves)), "leaf_levels": {int(l): int(c) for l, c in enumerate(leaf_levels) if c},
-            "m2l_pairs": ff.n_pair, "far_ms": t_far * 1e3, "near_ms": t_near * 1e3, "near_interactions": inter,
+            "m2l_pairs": ff.n_pair, "far_ms": t_far * 1e3, "far_per_level_ms": t_far_level * 1e3,
+            "near_ms": t_near * 1e3, "near_interactions": inter,
             "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample}
 
 

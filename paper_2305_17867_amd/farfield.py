@@ -57,20 +57,26 @@ class FarField:
         if tree_pass:
             self.leaf = n_lev - 1
             assert self.levels == list(range(self.levels[0], n_lev)), \
-                "the tree pass needs every level from the first M2L level to the leaves"
-            self.level_boxes[self.leaf] = (int(src_tree.level_start[self.leaf]), int(src_tree.level_start[self.leaf + 1]))
-            # parents on level l and their children on level l + 1
+                "the tree pass needs every level from the first M2L level to the deepest level"
+            assert np.array_equal(src_tree.is_leaf, tgt_tree.is_leaf), "source and target trees must share their leaves"
+            # P2M and L2P run on every level that holds leaves (only the deepest one for a uniform
+            # tree), over the level's boxes with the point ranges of non-leaf boxes emptied: their
+            # multipoles come from M2M and their locals go down by L2L
+            leaf = src_tree.is_leaf
+            self.leaf_levels = [l for l in self.levels if leaf[slice(*self.level_boxes[l])].any()]
+            self.src_leaf_rng = i64(np.where(leaf[:, None], src_tree.pt_range, 0))
+            self.tgt_leaf_rng = i64(np.where(leaf[:, None], tgt_tree.pt_range, 0))
+            # parents on level l that have children, and their children on level l + 1
             self.family = {}
             for l in range(self.levels[0], self.leaf):
                 par, ch = W.children(src_tree, l)
-                self.family[l] = (torch.as_tensor(par, device=dev), torch.as_tensor(ch, device=dev))
+                keep = np.any(ch >= 0, axis=1)
+                if np.any(keep):
+                    self.family[l] = (torch.as_tensor(par[keep], device=dev),
+                                      torch.as_tensor(np.ascontiguousarray(ch[keep]), device=dev))
 
     def _sl(self, a):
         return a[self.box_lo:self.box_hi]
-
-    def _leaf_call(self, fn, rng, *args, **kw):
-        a, b = self.level_boxes[self.leaf]
-        return fn(self.center[a:b], self.level[a:b], rng[a:b], *args, **kw)
 
     def forward_raw(self, w, src, tgt):
         if self.tree_pass:
@@ -94,34 +100,45 @@ class FarField:
     def _forward_tree(self, w, src, tgt):
         d = self.desc
         mpole = torch.zeros((self.n_box, self.plan.nc), dtype=d.value_dtype, device=w.device)
-        a, b = self.level_boxes[self.leaf]
-        self._leaf_call(self.plan.p2m, self.src_rng, src, w, out=mpole[a:b])
+        for l in self.leaf_levels:
+            a, b = self.level_boxes[l]
+            self.plan.p2m(self.center[a:b], self.level[a:b], self.src_leaf_rng[a:b], src, w, out=mpole[a:b])
         for l in reversed(range(self.levels[0], self.leaf)):  # children before parents
-            self.plan.m2m(*self.family[l], self.center, self.level, mpole)
+            if l in self.family:
+                self.plan.m2m(*self.family[l], self.center, self.level, mpole)
         local = torch.zeros_like(mpole)
         self.batch(mpole, local)
         for l in range(self.levels[0], self.leaf):  # parents before children
-            self.plan.l2l(*self.family[l], self.center, self.level, local)
+            if l in self.family:
+                self.plan.l2l(*self.family[l], self.center, self.level, local)
         pot = torch.zeros(tgt.shape[0], dtype=d.value_dtype, device=w.device)
-        self._leaf_call(self.plan.l2p, self.tgt_rng, tgt, local[a:b], pot)
+        for l in self.leaf_levels:
+            a, b = self.level_boxes[l]
+            self.plan.l2p(self.center[a:b], self.level[a:b], self.tgt_leaf_rng[a:b], tgt, local[a:b], pot)
         return pot, mpole, local
 
     def _backward_tree(self, g, w, src, tgt, local, need_w, need_src, need_tgt):
-        a, b = self.level_boxes[self.leaf]
         local_grad = torch.zeros_like(local)
         tgt_grad = torch.zeros_like(tgt) if need_tgt else None
-        self._leaf_call(self.plan.l2p_adjoint, self.tgt_rng, tgt, g, local_grad=local_grad[a:b],
-                        local=local[a:b] if need_tgt else None, tgt_grad=tgt_grad)
+        for l in self.leaf_levels:
+            a, b = self.level_boxes[l]
+            self.plan.l2p_adjoint(self.center[a:b], self.level[a:b], self.tgt_leaf_rng[a:b], tgt, g,
+                                  local_grad=local_grad[a:b], local=local[a:b] if need_tgt else None,
+                                  tgt_grad=tgt_grad)
         for l in reversed(range(self.levels[0], self.leaf)):  # L2L^T: children before parents
-            self.plan.l2l_adjoint(*self.family[l], self.center, self.level, local_grad)
+            if l in self.family:
+                self.plan.l2l_adjoint(*self.family[l], self.center, self.level, local_grad)
         mpole_grad = torch.zeros_like(local)
         self.batch_t(local_grad, mpole_grad)
         for l in range(self.levels[0], self.leaf):  # M2M^T: parents before children
-            self.plan.m2m_adjoint(*self.family[l], self.center, self.level, mpole_grad)
+            if l in self.family:
+                self.plan.m2m_adjoint(*self.family[l], self.center, self.level, mpole_grad)
         w_grad = torch.zeros_like(w) if need_w else None
         src_grad = torch.zeros_like(src) if need_src else None
-        self._leaf_call(self.plan.p2m_adjoint, self.src_rng, src, w, mpole_grad[a:b], w_grad=w_grad,
-                        src_grad=src_grad)
+        for l in self.leaf_levels:
+            a, b = self.level_boxes[l]
+            self.plan.p2m_adjoint(self.center[a:b], self.level[a:b], self.src_leaf_rng[a:b], src, w,
+                                  mpole_grad[a:b], w_grad=w_grad, src_grad=src_grad)
         return w_grad, src_grad, tgt_grad
 
     def backward_raw(self, g, w, src, tgt, local, need_w=True, need_src=True, need_tgt=True):

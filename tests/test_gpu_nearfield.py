@@ -125,7 +125,7 @@ def test_full_fmm_matches_direct_sum(gpu_lib):
     assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)
 
 
-def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128, max_src=None):
+def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128, max_src=None, tree_pass=False):
     """Far field (per-level form: P2M of every box, M2L over the List-2 pairs of every level,
     L2P of every level's local expansion at its boxes' points) + near field over the adaptive
     near lists, against the direct sum of eq. (1) at sampled targets."""
@@ -134,7 +134,7 @@ def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128, max
     n = pts.shape[0]
     cplx = kernel == "helmholtz"
     w = W.normal_weights(n, seed, complex_=cplx)
-    ff = FarField(kernel, p, dt, tr, tr, param=param)
+    ff = FarField(kernel, p, dt, tr, tr, param=param, tree_pass=tree_pass)
     d = ff.desc
     P, wd = dev(tr.points, d.real_dtype), dev(w, d.value_dtype)
     with torch.no_grad():
@@ -175,3 +175,13 @@ def test_p2p_split_lists_match_whole_lists(gpu_lib, dt):
     assert len(owner) > len(np.unique(owner))
     split = run_p2p(gpu_lib, kernel, param, dt, tr, tr, owner, ptr, nbr, w, np.zeros(n, dtype=w.dtype))
     assert rel(split, whole) < (1e-6 if dt == "f32" else 1e-13), rel(split, whole)
+
+
+@pytest.mark.parametrize("kernel,param,dt", [("laplace", 0.0, "f64"), ("helmholtz", 2.0, "c128")])
+def test_adaptive_fmm_tree_pass_matches_direct_sum(gpu_lib, kernel, param, dt):
+    """The complete FMM on an adaptive octree with the far field as a tree pass (P2M at the
+    leaves of every level, M2M up, M2L, L2L down, L2P at the leaves)."""
+    pts = W.plummer_points(6000, 86)
+    e4, _ = adaptive_fmm(gpu_lib, kernel, param, 4, dt, pts, 32, 87, tree_pass=True)
+    e8, _ = adaptive_fmm(gpu_lib, kernel, param, 8, dt, pts, 32, 87, max_src=256, tree_pass=True)
+    assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)

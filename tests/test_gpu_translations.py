@@ -263,3 +263,33 @@ def test_tree_pass_fp32_gradients_agree_with_fp64(gpu_lib):
     f64 = _tree_far_field("f64", True)
     for a, b in zip(f32, f64):
         assert rel(a.astype(np.float64), b) < 2e-5
+
+
+def _adaptive_far_field(dtype, tree_pass, kernel="laplace", param=0.0, p=8, n=4000):
+    """Far field of an adaptive octree (Plummer points, leaves on several levels), one point
+    set as sources and targets (separate tensors, so that both position gradients are formed)."""
+    from paper_2305_17867_amd.farfield import FarField
+    tr = W.adaptive_tree(W.plummer_points(n, 65), 24)
+    assert len(set(tr.level[tr.is_leaf].tolist())) >= 3
+    ff = FarField(kernel, p, dtype, tr, tr, param=param, tree_pass=tree_pass)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    w = dev(W.normal_weights(n, 66), tdt).requires_grad_(True)
+    s = dev(tr.points, tdt).requires_grad_(True)
+    t = dev(tr.points, tdt).requires_grad_(True)
+    c = dev(W.normal_weights(n, 67), tdt)
+    phi = ff.apply(w, s, t)
+    (phi * c).sum().backward()
+    return [host(v) for v in (phi.detach(), w.grad, s.grad, t.grad)]
+
+
+@pytest.mark.parametrize("kernel,param,tol", [("laplace", 0.0, 1e-12), ("biharmonic", 0.0, 1e-12),
+                                              ("yukawa", 2.0, 1e-4)])
+def test_tree_pass_on_adaptive_tree_matches_per_level(gpu_lib, kernel, param, tol):
+    """On an adaptive tree the tree pass forms multipoles by P2M at leaves of every level and M2M
+    from the parents that have children, and evaluates locals by L2L down to the leaves and L2P
+    there; against P2M and L2P of every box at every level, forward and backward: equal to
+    roundoff for Laplace and biharmonic, at truncation level for Yukawa."""
+    tree = _adaptive_far_field("f64", True, kernel, param)
+    per_level = _adaptive_far_field("f64", False, kernel, param)
+    for a, b in zip(tree, per_level):
+        assert rel(a, b) < tol, rel(a, b)
