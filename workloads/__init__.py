@@ -10,7 +10,11 @@ compression): only the geometry that every FMM pass needs as input --
   order so that the points of every box (at every level) are one contiguous range;
 * "List 2" (interaction list) pairs: boxes of the same level whose parents are
   adjacent or equal but which are not adjacent themselves (the well-separated
-  pairs an FMM translates by multipole-to-local).
+  pairs an FMM translates by multipole-to-local);
+* near-field lists: the neighbour boxes of the leaves of a uniform tree, and for
+  adaptive trees the boxes whose sources are near a leaf at the coarsest level
+  where they separate, so that near lists and List 2 together count every leaf
+  pair once.
 
 Box ids are global across levels.  For every box: ``level``, integer grid
 coordinates ``ijk`` at its level, ``center`` (float64), ``pt_range`` (int64
