@@ -11,9 +11,9 @@ compression): only the geometry that every FMM pass needs as input --
 * "List 2" (interaction list) pairs: boxes of the same level whose parents are
   adjacent or equal but which are not adjacent themselves (the well-separated
   pairs an FMM translates by multipole-to-local);
-* near-field lists: the neighbour boxes of the leaves of a uniform tree, and for
-  adaptive trees the boxes whose sources are near a leaf at the coarsest level
-  where they separate, so that near lists and List 2 together count every leaf
+* near-field lists: the neighbour boxes of the leaves of a uniform tree and, for
+  adaptive trees, the boxes holding the sources that no List-2 pair of any level
+  separates from a leaf, so that near lists and List 2 together count every leaf
   pair once.
 
 Box ids are global across levels.  For every box: ``level``, integer grid
