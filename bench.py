@@ -490,6 +490,51 @@ def plummer_helmholtz(torch, fmm, dt, reps=5):
             "m2l_fft_ms": fft_ms}
 
 
+def plummer_helmholtz_fmm(torch, fmm, reps=3, sample=256):
+    """The complete Helmholtz potential (complex128, p = 12) of 2^21 Plummer points on their
+    adaptive octree (<= 64 per leaf, k = 1 / largest leaf side): far field as a tree pass plus
+    the near field over the adaptive near lists; error against the GPU direct sum at sampled
+    targets."""
+    import workloads as W
+    from paper_2305_17867_amd.farfield import FarField
+    dev = "cuda"
+    tr = W.adaptive_tree(W.plummer_points(1 << 21, 3, 0.1), 64)
+    leaf_side = max(tr.box_size(int(tr.level[b])) for b in np.nonzero(tr.is_leaf)[0])
+    k = 1.0 / leaf_side
+    w = W.normal_weights(tr.points.shape[0], SEED + 11, complex_=True)
+    ff = FarField("helmholtz", 12, "c128", tr, tr, param=k, tree_pass=True)
+    d = ff.desc
+    pts = torch.as_tensor(tr.points, dtype=torch.float64, device=dev)
+    wd = torch.as_tensor(w, dtype=torch.complex128, device=dev)
+    owner, ptr, nbr = W.near_lists(tr, max_src=2048)
+    lists = [torch.as_tensor(a, device=dev) for a in (owner, ptr, nbr)]
+    rng = torch.as_tensor(tr.pt_range, dtype=torch.int64, device=dev)
+    out = {}
+
+    def far():
+        with torch.no_grad():
+            out["pot"] = ff.forward_raw(wd, pts, pts)[0]
+
+    def near():
+        fmm.p2p(d, *lists, rng, rng, pts, wd, pts, out["pot"])
+
+    t_far = time_kernel(torch, far, reps)
+    t_near = time_kernel(torch, near, reps)
+    far()
+    near()
+    idx = np.sort(np.random.Generator(np.random.PCG64(SEED + 12)).choice(len(w), sample, replace=False))
+    ref = fmm.direct(d, pts, wd, pts[torch.as_tensor(idx, device=dev)].contiguous())
+    got = out["pot"][torch.as_tensor(idx, device=dev)]
+    err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+    counts = tr.pt_range[:, 1] - tr.pt_range[:, 0]
+    inter = int(sum(int(counts[b]) * int(counts[nbr[ptr[j]:ptr[j + 1]]].sum()) for j, b in enumerate(owner)))
+    return {"workload": "plummer 2097152 pts, adaptive <=64, helmholtz p12 c128 k*h_leaf=1: far field (tree pass) "
+                        "+ near field",
+            "k": k, "leaves": int(tr.is_leaf.sum()), "m2l_pairs": ff.n_pair, "far_ms": t_far * 1e3,
+            "near_ms": t_near * 1e3, "near_interactions": inter, "near_interactions_per_s": inter / t_near,
+            "rel_error_vs_direct": err, "error_sample": sample}
+
+
 def gradient_pass(torch, dt, reps=10, tree_pass=False):
     """Laplace p = 10 far field of 2^21 sources at 2^21 targets (depth-4 octrees) and its
     adjoint: forward and forward + backward times (per level, or as a tree pass with M2M and
@@ -619,6 +664,8 @@ def main():
     if args.extended:
         log("Plummer Helmholtz, one launch over all levels")
         out["plummer_helmholtz"] = [plummer_helmholtz(torch, fmm, dt) for dt in ("c128", "c64")]
+        log("Plummer Helmholtz, complete FMM (tree pass + near field)")
+        out["plummer_helmholtz_fmm"] = plummer_helmholtz_fmm(torch, fmm)
         log("far-field gradient pass")
         out["gradient"] = [gradient_pass(torch, dt, tree_pass=tp) for tp in (False, True) for dt in ("f32", "f64")]
     if args.copy_calibration:
