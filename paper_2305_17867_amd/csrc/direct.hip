@@ -63,11 +63,24 @@ __device__ inline R lane_xor(R v, int m) { return shfl_xor_d(v, m); }
 template <typename R>
 __device__ inline Cx<R> lane_xor(Cx<R> v, int m) { return {shfl_xor_d(v.re, m), shfl_xor_d(v.im, m)}; }
 
+// One staged source: position and weight side by side, so that the inner loop reads it with
+// 128-bit LDS loads (two for FP64, one for FP32) instead of one load per component.
+template <typename R, bool CPLX>
+struct alignas(16) Staged;
+template <typename R>
+struct alignas(16) Staged<R, false> {
+  R x, y, z, w;
+};
+template <typename R>
+struct alignas(16) Staged<R, true> {
+  R x, y, z, pad;
+  Cx<R> w;
+};
+
 template <typename R, bool CPLX, int K>
 __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
   using T = typename Val<R, CPLX>::T;
-  __shared__ R sx[kThreads], sy[kThreads], sz[kThreads];
-  __shared__ T sw[kThreads];
+  __shared__ Staged<R, CPLX> st[kThreads];
   const int split = a.split;
   const int ls = threadIdx.x & (split - 1);  // lane within the target's group
   const int64_t t = (int64_t)blockIdx.x * (kThreads / split) + threadIdx.x / split;
@@ -86,14 +99,20 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs a) {
     __syncthreads();
     const int64_t j = base + threadIdx.x;
     if (j < a.n_src) {
-      sx[threadIdx.x] = sr[3 * j];
-      sy[threadIdx.x] = sr[3 * j + 1];
-      sz[threadIdx.x] = sr[3 * j + 2];
-      sw[threadIdx.x] = w[j];
+      Staged<R, CPLX> v;
+      v.x = sr[3 * j];
+      v.y = sr[3 * j + 1];
+      v.z = sr[3 * j + 2];
+      if constexpr (CPLX) v.pad = R(0);
+      v.w = w[j];
+      st[threadIdx.x] = v;
     }
     __syncthreads();
     const int cnt = (int)((a.n_src - base) < kThreads ? (a.n_src - base) : kThreads);
-    for (int k = ls; k < cnt; k += split) add_green<R, CPLX, K>(acc, prm, x - sx[k], y - sy[k], z - sz[k], sw[k]);
+    for (int k = ls; k < cnt; k += split) {
+      const Staged<R, CPLX> v = st[k];
+      add_green<R, CPLX, K>(acc, prm, x - v.x, y - v.y, z - v.z, v.w);
+    }
   }
   for (int m = 1; m < split; m <<= 1) acc += lane_xor(acc, m);  // all lanes active here
   if (ls == 0 && t < a.n_tgt) reinterpret_cast<T*>(a.pot)[t] = acc;
@@ -105,20 +124,6 @@ __device__ inline void clamp_range(const int64_t* rng, int64_t b, int64_t n, int
   lo = lo < 0 ? 0 : (lo > n ? n : lo);
   hi = hi < lo ? lo : (hi > n ? n : hi);
 }
-
-// One staged source: position and weight side by side, so that the inner loop reads it with
-// 128-bit LDS loads (two for FP64, one for FP32) instead of one load per component.
-template <typename R, bool CPLX>
-struct alignas(16) Staged;
-template <typename R>
-struct alignas(16) Staged<R, false> {
-  R x, y, z, w;
-};
-template <typename R>
-struct alignas(16) Staged<R, true> {
-  R x, y, z, pad;
-  Cx<R> w;
-};
 
 // Targets [t0, t1) of one box against the sources of its neighbour boxes.  The sources of the
 // list are one stream: a scan of the boxes' point counts (a segment of up to kThreads list
