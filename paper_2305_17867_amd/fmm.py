@@ -380,7 +380,9 @@ def direct(desc: Desc, src, w, tgt, out=None) -> torch.Tensor:
 
 def p2p(desc: Desc, tbox, nbr_ptr, nbr, tgt_range, src_range, src, w, tgt, pot) -> torch.Tensor:
     """Near field: pot[targets of tbox[k]] += direct sum over the sources of the boxes
-    nbr[nbr_ptr[k] : nbr_ptr[k + 1]] (fmm_p2p).  Point ranges are per box id."""
+    nbr[nbr_ptr[k] : nbr_ptr[k + 1]] (fmm_p2p).  Point ranges are per box id.  A target box may
+    be listed several times (a long list split into parts that run in parallel; the parts are
+    added atomically, in no fixed order)."""
     nt_box, nb = tbox.shape[0], tgt_range.shape[0]
     ns, nt = src.shape[0], tgt.shape[0]
     _dev(tbox, torch.int32, "tbox", (nt_box,))
