@@ -582,6 +582,8 @@ def main():
                     help="also time M2M / L2L when --only or --no-extras is given")
     ap.add_argument("--extended", action="store_true",
                     help="also time the Plummer Helmholtz launch and the far-field gradient pass")
+    ap.add_argument("--gradient", action="store_true",
+                    help="also time the far-field gradient pass (part of --extended)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, to calibrate HBM counters")
     args = ap.parse_args()
@@ -666,6 +668,7 @@ def main():
         out["plummer_helmholtz"] = [plummer_helmholtz(torch, fmm, dt) for dt in ("c128", "c64")]
         log("Plummer Helmholtz, complete FMM (tree pass + near field)")
         out["plummer_helmholtz_fmm"] = plummer_helmholtz_fmm(torch, fmm)
+    if args.extended or args.gradient:
         log("far-field gradient pass")
         out["gradient"] = [gradient_pass(torch, dt, tree_pass=tp) for tp in (False, True) for dt in ("f32", "f64")]
     if args.copy_calibration:
