@@ -90,12 +90,13 @@ def gaussian_mixture_points(n: int, seed: int, k: int = 4, sigma: float = 0.05,
 # --------------------------------------------------------------------------- morton
 
 def _spread_bits(v: np.ndarray) -> np.ndarray:
-    """Insert two zero bits between each of the low 20 bits of v (uint64)."""
+    """Insert two zero bits between each of the low 20 bits of v (uint64), by the usual
+    shift-and-mask steps (each step moves groups of bits to their places at once)."""
     v = v.astype(np.uint64) & np.uint64(0xFFFFF)
-    out = np.zeros_like(v)
-    for b in range(MAX_DEPTH):
-        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
-    return out
+    for shift, mask in ((32, 0x1F00000000FFFF), (16, 0x1F0000FF0000FF), (8, 0x100F00F00F00F00F),
+                        (4, 0x10C30C30C30C30C3), (2, 0x1249249249249249)):
+        v = (v | (v << np.uint64(shift))) & np.uint64(mask)
+    return v
 
 
 def morton_keys(ijk: np.ndarray) -> np.ndarray:
@@ -215,47 +216,69 @@ def near_lists(tree: Tree, max_src: int | None = None) -> tuple[np.ndarray, np.n
     children (down to leaves), and the boxes are packed in order into entries of at most
     max_src points (a single leaf above the cap is an entry of its own).  A coarse leaf next
     to a densely refined region would otherwise leave one workgroup with most of the work."""
-    index = [{tuple(int(v) for v in tree.ijk[b]): int(b) for b in tree.boxes_at(l)} for l in range(tree.n_levels)]
     count = tree.pt_range[:, 1] - tree.pt_range[:, 0]
+    index = {}  # (level, i, j, k) -> box, built on first use by split()
 
     def split(n):
         if count[n] <= max_src or tree.is_leaf[n]:
             return [n]
+        if not index:
+            index.update({(int(tree.level[b]),) + tuple(int(v) for v in tree.ijk[b]): int(b) for b in range(tree.n_box)})
         lev, base = int(tree.level[n]) + 1, 2 * tree.ijk[n].astype(np.int64)
         out = []
         for o in range(8):
-            c = index[lev].get((int(base[0]) + (o & 1), int(base[1]) + ((o >> 1) & 1), int(base[2]) + ((o >> 2) & 1)))
+            c = index.get((lev, int(base[0]) + (o & 1), int(base[1]) + ((o >> 1) & 1), int(base[2]) + ((o >> 2) & 1)))
             if c is not None:
                 out += split(c)
         return out
 
+    # candidates of every leaf, found level by level with sorted Morton keys: (leaf position,
+    # level, offset) -> box, kept in the order leaf, level, offset (di, dj, dk lexicographic)
     leaves = np.flatnonzero(tree.is_leaf)
+    lb = tree.level[leaves].astype(np.int64)
+    ijk = tree.ijk[leaves].astype(np.int64)
+    offs = np.array([(di, dj, dk) for di in (-1, 0, 1) for dj in (-1, 0, 1) for dk in (-1, 0, 1)], dtype=np.int64)
+    parts = []  # (leaf position, level, offset index, box)
+    for lev in range(tree.n_levels):
+        sel = np.flatnonzero(lb >= lev)
+        ids = tree.boxes_at(lev)
+        if sel.size == 0 or ids.size == 0:
+            continue
+        keys = morton_keys(tree.ijk[ids].astype(np.int64))  # sorted: boxes are stored in Morton order
+        anc = ijk[sel] >> (lb[sel] - lev)[:, None]
+        cand = anc[:, None, :] + offs[None, :, :]
+        inside = np.all((cand >= 0) & (cand < (1 << lev)), axis=2)
+        ck = morton_keys(np.where(inside[..., None], cand, 0).reshape(-1, 3)).reshape(cand.shape[:2])
+        pos = np.minimum(np.searchsorted(keys, ck), keys.shape[0] - 1)
+        found = inside & (keys[pos] == ck)
+        box = ids[pos]
+        keep = found & ((lb[sel] == lev)[:, None] | tree.is_leaf[box])
+        li, oi = np.nonzero(keep)
+        parts.append(np.stack([sel[li], np.full(li.shape, lev), oi, box[li, oi]], axis=1))
+    allp = np.concatenate(parts) if parts else np.zeros((0, 4), dtype=np.int64)
+    allp = allp[np.lexsort((allp[:, 2], allp[:, 1], allp[:, 0]))]
+    per_leaf = np.bincount(allp[:, 0], minlength=leaves.shape[0])
+    lst_ptr = np.concatenate([[0], np.cumsum(per_leaf)])
+    src_all = allp[:, 3]
+    if max_src is None:
+        return leaves.astype(np.int32), lst_ptr.astype(np.int32), src_all.astype(np.int32)
+    total = np.add.reduceat(count[src_all], lst_ptr[:-1]) if src_all.size else np.zeros(0, dtype=np.int64)
     owner, ptr, src = [], [0], []
-    for b in leaves:
-        lb = int(tree.level[b])
-        ijk = tree.ijk[b].astype(np.int64)
-        lst = []
-        for lev in range(lb + 1):
-            a = ijk >> (lb - lev)
-            for di in (-1, 0, 1):
-                for dj in (-1, 0, 1):
-                    for dk in (-1, 0, 1):
-                        n = index[lev].get((int(a[0]) + di, int(a[1]) + dj, int(a[2]) + dk))
-                        if n is not None and (lev == lb or tree.is_leaf[n]):
-                            lst.append(n)
-        if max_src is None or count[lst].sum() <= max_src:
+    for k, b in enumerate(leaves):
+        lst = src_all[lst_ptr[k]:lst_ptr[k + 1]]
+        if per_leaf[k] == 0 or total[k] <= max_src:
             owner.append(b)
-            src += lst
+            src += lst.tolist()
             ptr.append(len(src))
             continue
-        total = 0
-        for n in [m for x in lst for m in split(x)]:
-            if total and total + count[n] > max_src:
+        run = 0
+        for n in [m for x in lst for m in split(int(x))]:
+            if run and run + count[n] > max_src:
                 owner.append(b)
                 ptr.append(len(src))
-                total = 0
+                run = 0
             src.append(n)
-            total += count[n]
+            run += count[n]
         owner.append(b)
         ptr.append(len(src))
     return np.asarray(owner, dtype=np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(src, dtype=np.int32)
