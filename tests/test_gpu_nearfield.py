@@ -185,3 +185,28 @@ def test_adaptive_fmm_tree_pass_matches_direct_sum(gpu_lib, kernel, param, dt):
     e4, _ = adaptive_fmm(gpu_lib, kernel, param, 4, dt, pts, 32, 87, tree_pass=True)
     e8, _ = adaptive_fmm(gpu_lib, kernel, param, 8, dt, pts, 32, 87, max_src=256, tree_pass=True)
     assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)
+
+
+@pytest.mark.parametrize("dt", ["f64", "c128"])
+def test_p2p_long_and_empty_lists(gpu_lib, dt):
+    """A list longer than one segment of the kernel's source stream (all 512 boxes of a depth-3
+    tree, plus invalid ids, for one target box), an empty list and a target box without points:
+    against the oracle's eq. (1) over all sources."""
+    src_tree, tgt_tree = W.uniform_tree(W.uniform_points(3000, 88), 3), W.uniform_tree(W.uniform_points(800, 89), 3)
+    kernel, param = ("helmholtz", 1.0) if dt == "c128" else ("laplace", 0.0)
+    w = W.normal_weights(3000, 90, complex_=dt == "c128")
+    level3 = src_tree.boxes_at(3)
+    counts = tgt_tree.counts()
+    full = int(next(b for b in level3 if counts[b] > 0))
+    empty_box = int(next((b for b in level3 if counts[b] == 0), level3[0]))
+    other = int(next(b for b in level3 if counts[b] > 0 and b != full))
+    long_list = np.concatenate([level3, [-1, src_tree.n_box + 5]]).astype(np.int32)
+    boxes = np.array([full, other, empty_box], dtype=np.int32)
+    ptr = np.array([0, len(long_list), len(long_list), len(long_list) + 3], dtype=np.int32)
+    nbr = np.concatenate([long_list, level3[:3].astype(np.int32)])
+    n = tgt_tree.points.shape[0]
+    got = run_p2p(gpu_lib, kernel, param, dt, src_tree, tgt_tree, boxes, ptr, nbr, w, np.zeros(n, dtype=w.dtype))
+    ref = np.zeros(n, dtype=w.dtype)
+    lo, hi = tgt_tree.pt_range[full]
+    ref[lo:hi] = K.direct_sum(kernel, param, src_tree.points, w, tgt_tree.points[lo:hi])
+    assert rel(got, ref) < 1e-12, rel(got, ref)
