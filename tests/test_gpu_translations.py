@@ -293,3 +293,12 @@ def test_tree_pass_on_adaptive_tree_matches_per_level(gpu_lib, kernel, param, to
     per_level = _adaptive_far_field("f64", False, kernel, param)
     for a, b in zip(tree, per_level):
         assert rel(a, b) < tol, rel(a, b)
+
+
+def test_tree_pass_on_adaptive_tree_fp32_agrees_with_fp64(gpu_lib):
+    """The adaptive tree pass in FP32, forward and all gradients, against FP64 at the FP32
+    adjoint tolerance."""
+    f32 = _adaptive_far_field("f32", True)
+    f64 = _adaptive_far_field("f64", True)
+    for a, b in zip(f32, f64):
+        assert rel(a.astype(np.float64), b) < 2e-5, rel(a.astype(np.float64), b)
