@@ -18,8 +18,9 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// 1 / sqrt(v), v > 0: the hardware estimate refined by Newton steps y <- y (3 - v y^2) / 2,
-// two in double precision (each roughly squares the relative error) and one in single
+// 1 / sqrt(v), v > 0: in double precision the hardware estimate refined by two Newton steps
+// y <- y (3 - v y^2) / 2 (each roughly squares the relative error); in single precision the
+// hardware result as it is
 __device__ inline double inv_sqrt(double v) {
   double y = __builtin_amdgcn_rsq(v);
 #pragma unroll
@@ -27,8 +28,7 @@ __device__ inline double inv_sqrt(double v) {
   return y;
 }
 __device__ inline float inv_sqrt(float v) {
-  const float y = __builtin_amdgcn_rsqf(v);
-  return fmaf(0.5f * y, fmaf(-v * y, y, 1.0f), y);
+  return __builtin_amdgcn_rsqf(v);  // the hardware result is within about an ulp in FP32
 }
 
 // acc += G(d) w for one source at offset d = x - y; d = 0 adds nothing (1/r is taken as 0
