@@ -68,6 +68,10 @@ struct fmm_batch_s {
   M2LItem* d_items = nullptr;
   int32_t* d_jbase = nullptr;
   std::vector<M2LItem> h_items;  // host copy (work ordering of persistent launches)
+  // streaming form (m2l_stream.hip): 16-target tiles, one contiguous entry chunk per workgroup
+  bool stream = false;
+  int32_t n_wg = 0, c_pde = 2, p = 0, lds_sbq = 0;
+  int32_t* d_wg_item = nullptr;
 };
 
 namespace {
@@ -581,7 +585,34 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
   }
   (void)hipGetLastError();
-  {
+  // the streaming form serves every automatic launch it is instantiated for; an explicit
+  // fmm_m2l_tuning selects the tiled form
+  const M2LStreamShape ssh = m2l_stream_shape(plan->p, pde_order(plan->desc.kernel), dtype);
+  b->stream = ssh.ok && !(tuning && tuning->rows_per_wave > 0) && env_int("FMM_M2L_STREAM", 1) != 0;
+  b->p = plan->p;
+  b->c_pde = pde_order(plan->desc.kernel);
+  if (b->stream) {
+    const int w = std::max(1, std::min(ssh.max_waves, env_int("FMM_M2LS_WAVES", ssh.max_waves)));
+    b->waves = w;
+    b->rows_per_wave = (b->nc + 15) / 16;
+    b->col_tiles = b->col_groups = b->k_splits = 1;
+    b->nbuf = 1;
+    const size_t rb = real_size(dtype);
+    size_t tabs = (size_t)w * ssh.tsp * rb;
+    const size_t red = (size_t)((w + 1) / 2) * ssh.nacc * 64 * sizeof(double);
+    size_t lds = (std::max(tabs, red) + 15) / 16 * 16;
+    b->lds_sbq = (int32_t)lds;
+    lds += (size_t)8 * ssh.kj * sizeof(int32_t);
+    // one workgroup per compute unit: the chunks are equal, so a second resident workgroup on
+    // some units would only make those units finish later
+    if (env_int("FMM_M2LS_ONE_PER_CU", 1) && lds <= (size_t)lds_max / 2) lds = (size_t)lds_max / 2 + 256;
+    if (lds > (size_t)lds_max - 64) {
+      b->stream = false;
+    } else {
+      b->lds_bytes = (int64_t)lds;
+    }
+  }
+  if (!b->stream) {
     // rows past the last full 16-row tile: up to kMaxRem of them are contracted on the VALU
     // instead of a mostly empty matrix-core tile (e.g. 81 = 5 x 16 + 1 at Laplace p = 8)
     int nrem = b->nc % 16;
@@ -674,7 +705,7 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     b->shape = best.sh;
     b->lds_bytes = (int64_t)best.lds;
   }
-  const int NT = 16 * b->col_tiles * b->col_groups;
+  const int NT = b->stream ? 16 : 16 * b->col_tiles * b->col_groups;
 
 
   // 3. target tiles: same level and child parity, then the same set of offsets (signature) where
@@ -765,17 +796,56 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   b->useful = n_pair;
   b->computed = b->n_entries * NT;
 
-  // 5. work items: split tiles into parts so that one launch has enough workgroups
+  // 5. work items.  Streaming form: the entries (already in tile order) are cut into n_wg
+  //    contiguous chunks of equal length; a chunk's share of each tile it touches is one item.
+  std::vector<int32_t> wg_item;
+  std::vector<M2LItem> items;
+  std::vector<int32_t> tile_nparts(n_tiles), tile_item0(n_tiles);
+  if (b->stream) {
+    const int64_t E = b->n_entries;
+    int n_wg = std::max(1, env_int("FMM_M2LS_WG", n_cu));
+    n_wg = (int)std::max<int64_t>(1, std::min<int64_t>(n_wg, (E + 2 * b->waves - 1) / (2 * b->waves)));
+    std::vector<int64_t> cut(n_wg + 1);
+    for (int g = 0; g <= n_wg; ++g) cut[g] = E * g / n_wg;
+    std::vector<std::vector<M2LItem>> chunk(n_wg);
+    std::vector<int32_t> nparts(n_tiles, 0);
+    int64_t t = 0;
+    for (int g = 0; g < n_wg; ++g) {
+      while (t < n_tiles && tile_e0[t + 1] <= cut[g]) ++t;
+      for (int64_t u = t; u < n_tiles && tile_e0[u] < cut[g + 1]; ++u) {
+        const int32_t e0 = (int32_t)std::max<int64_t>(tile_e0[u], cut[g]);
+        const int32_t e1 = (int32_t)std::min<int64_t>(tile_e0[u + 1], cut[g + 1]);
+        if (e0 >= e1) continue;
+        chunk[g].push_back({(int32_t)u, e0, e1, nparts[u]++});
+      }
+    }
+    int64_t slots = 0;
+    for (int64_t u = 0; u < n_tiles; ++u) {
+      tile_nparts[u] = std::max(1, nparts[u]);
+      tile_item0[u] = nparts[u] > 1 ? (int32_t)slots : 0;
+      if (nparts[u] > 1) slots += nparts[u];
+    }
+    // workgroup g runs on XCD g mod 8: give XCD x the chunks x m .. x m + m - 1 (m = n_wg / 8),
+    // neighbouring tiles sharing their sources and tables in that XCD's L2
+    std::vector<int> chunk_of(n_wg);
+    for (int g = 0; g < n_wg; ++g) chunk_of[g] = (n_wg % 8 == 0) ? (g % 8) * (n_wg / 8) + g / 8 : g;
+    wg_item.push_back(0);
+    for (int g = 0; g < n_wg; ++g) {
+      for (const M2LItem& it : chunk[chunk_of[g]]) items.push_back(it);
+      wg_item.push_back((int32_t)items.size());
+    }
+    b->n_wg = n_wg;
+    b->n_items = (int64_t)items.size();
+    b->scratch_bytes = slots * 16 * b->nc_pad * CW * (int64_t)sizeof(double);
+  }
   int target_items = (tuning && tuning->target_items > 0) ? tuning->target_items : 4 * n_cu;
   target_items = std::max(1, env_int("FMM_M2L_ITEMS", target_items));
   const int min_entries = std::max(1, env_int("FMM_M2L_MIN_ENTRIES", 8));
-  std::vector<M2LItem> items;
-  std::vector<int32_t> tile_nparts(n_tiles), tile_item0(n_tiles);
   int64_t split_items = 0;
   // parts of about equal cost: every item gets about n_entries / target_items entries (at
   // least min_entries), so that the workgroups of one launch finish together
   const double per_item = std::max<double>(min_entries, (double)b->n_entries / target_items);
-  for (int64_t t = 0; t < n_tiles; ++t) {
+  for (int64_t t = 0; t < n_tiles && !b->stream; ++t) {
     const int ne = tile_e0[t + 1] - tile_e0[t];
     int np = (int)std::lround(ne / per_item);
     np = std::max(1, std::min(np, ne));
@@ -787,12 +857,13 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     }
     if (np > 1) split_items = (int64_t)items.size();
   }
-  b->n_items = (int64_t)items.size();
+  if (!b->stream) b->n_items = (int64_t)items.size();
   // launch order: part-major within each group below; partial sums keep their slot
   // tile_item0[tile] + part whatever the order
-  std::stable_sort(items.begin(), items.end(),
-                   [](const M2LItem& x, const M2LItem& y) { return x.part < y.part; });
-  if (n_tiles >= 8) {
+  if (!b->stream)
+    std::stable_sort(items.begin(), items.end(),
+                     [](const M2LItem& x, const M2LItem& y) { return x.part < y.part; });
+  if (n_tiles >= 8 && !b->stream) {
     // XCD-contiguous order: the tiles are cut into 8 contiguous ranges (neighbouring targets,
     // hence shared sources and tables in one XCD's L2); position i of the launch takes the next
     // item of range i % 8
@@ -807,7 +878,7 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     items.swap(out);
   }
   // partials are indexed by item id; allocate for every item up to the last split tile
-  b->scratch_bytes = split_items * NT * b->nc_pad * CW * (int64_t)sizeof(double);
+  if (!b->stream) b->scratch_bytes = split_items * NT * b->nc_pad * CW * (int64_t)sizeof(double);
 
   // 6. derivative tables (FP64) for every (level, offset), then the M2L layout in the dtype
   std::vector<double> off(3 * b->n_tab), hs(b->n_tab);
@@ -827,16 +898,20 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     return bail(st);
   }
   const size_t tab_vals = (size_t)b->n_tab * b->ts * CW;
+  const size_t tab_dev = b->stream ? (size_t)b->n_tab * ssh.tsp : tab_vals;  // padded rows (streaming)
   if (tab_vals) {
     if (hipMalloc((void**)&d_tab64, tab_vals * sizeof(double)) != hipSuccess ||
-        hipMalloc(&b->d_tab, tab_vals * real_size(dtype)) != hipSuccess) {
+        hipMalloc(&b->d_tab, tab_dev * real_size(dtype)) != hipSuccess ||
+        (b->stream && hipMemset(b->d_tab, 0, tab_dev * real_size(dtype)) != hipSuccess)) {
       dev_free(d_off);
       dev_free(d_h);
       dev_free(d_tab64);
       return bail(fail(FMM_ENOMEM, "table allocation failed"));
     }
     st = fmm_deriv_tables(&plan->desc, b->n_tab, d_off, d_h, d_tab64, nullptr);
-    if (!st) st = launch_m2l_table_layout(d_tab64, b->d_tab, b->n_tab, b->ts, dtype, nullptr);
+    if (!st)
+      st = b->stream ? launch_m2l_stream_tables(d_tab64, b->d_tab, b->n_tab, b->ts, ssh.tsp, dtype, nullptr)
+                     : launch_m2l_table_layout(d_tab64, b->d_tab, b->n_tab, b->ts, dtype, nullptr);
     hipError_t e = hipDeviceSynchronize();
     dev_free(d_off);
     dev_free(d_h);
@@ -852,7 +927,7 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   if ((st = dev_upload(&b->d_tile_tgt, tile_tgt)) || (st = dev_upload(&b->d_tile_nparts, tile_nparts)) ||
       (st = dev_upload(&b->d_tile_item0, tile_item0)) || (st = dev_upload(&b->d_counter, zeros)) ||
       (st = dev_upload(&b->d_entry_tab, entry_tab)) || (st = dev_upload(&b->d_entry_src, entry_src)) ||
-      (st = dev_upload(&b->d_items, items)))
+      (st = dev_upload(&b->d_items, items)) || (st = dev_upload(&b->d_wg_item, wg_item)))
     return bail(st);
   b->h_items = items;
   b->d_jbase = plan->d_jbase;
@@ -1018,6 +1093,7 @@ void fmm_batch_destroy(fmm_batch b) {
   dev_free(b->d_entry_tab);
   dev_free(b->d_entry_src);
   dev_free(b->d_items);
+  dev_free(b->d_wg_item);
   delete b;
 }
 
@@ -1027,9 +1103,30 @@ int fmm_batch_info(fmm_batch b, int64_t* info, int32_t n_info) {
   const int64_t v[] = {b->n_pair,        b->n_tab,     b->n_tiles, b->n_entries,  b->n_items,
                        b->useful,        b->computed,  b->nc,      b->nc_pad,     b->scratch_bytes,
                        b->rows_per_wave, b->col_tiles, b->waves,   b->col_groups, b->lds_bytes,
-                       b->nbuf,          b->k_splits,  b->shape.nrem};
+                       b->nbuf,          b->k_splits,  b->shape.nrem, (int64_t)b->stream,
+                       b->n_wg};
   for (int k = 0; k < n_info && k < (int)(sizeof(v) / sizeof(v[0])); ++k) info[k] = v[k];
   return FMM_OK;
+}
+
+static M2LStreamArgs m2l_stream_args(fmm_batch b, const void* mpole, void* local) {
+  M2LStreamArgs a{};
+  a.items = b->d_items;
+  a.wg_item = b->d_wg_item;
+  a.n_wg = b->n_wg;
+  a.tile_tgt = b->d_tile_tgt;
+  a.tile_nparts = b->d_tile_nparts;
+  a.tile_item0 = b->d_tile_item0;
+  a.counter = b->d_counter;
+  a.scratch = b->d_scratch;
+  a.entry_tab = b->d_entry_tab;
+  a.entry_src = b->d_entry_src;
+  a.tab = b->d_tab;
+  a.jbase = b->d_jbase;
+  a.mpole = mpole;
+  a.local = local;
+  a.lds_sbq = b->lds_sbq;
+  return a;
 }
 
 static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local) {
@@ -1063,6 +1160,7 @@ static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local) {
 }
 
 static int m2l_launch(fmm_batch b, const void* in, void* out, void* stream);
+static M2LStreamArgs m2l_stream_args(fmm_batch b, const void* mpole, void* local);
 
 int fmm_m2l_batched(fmm_batch b, const void* mpole, void* local, void* stream) {
   FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
@@ -1090,6 +1188,8 @@ static int m2l_launch(fmm_batch b, const void* mpole, void* local, void* stream)
   }
   if (b->n_items == 0) return FMM_OK;
   FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
+  if (b->stream) return launch_m2l_stream(m2l_stream_args(b, mpole, local), b->p, b->c_pde, b->dtype, b->waves,
+                                          (size_t)b->lds_bytes, (hipStream_t)stream);
   return launch_m2l(m2l_args(b, mpole, local), b->dtype, b->rows_per_wave, b->col_tiles, b->pf_class, b->nbuf,
                     b->waves, (hipStream_t)stream);
 }
@@ -1107,6 +1207,8 @@ int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* out) {
     const fmm_batch b = batches[k];
     FMM_REQUIRE(b && b->plan && b->plan->alive, FMM_EINVAL, "NULL or stale batch");
     FMM_REQUIRE(!b->fft && !b->adjoint, FMM_EINVAL, "FFT and adjoint batches cannot join a multi launch");
+    FMM_REQUIRE(!b->stream, FMM_EINVAL,
+                "multi launches take batches prepared with one explicit fmm_m2l_tuning (tiled form)");
     FMM_REQUIRE(b->dtype == b0->dtype, FMM_EINVAL, "batches must share one dtype");
     for (int j = 0; j < k; ++j)  // split tiles keep their partials in the batch's own scratch
       FMM_REQUIRE(batches[j] != b, FMM_EINVAL, "a batch may appear only once in a multi launch");

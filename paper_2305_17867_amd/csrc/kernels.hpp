@@ -129,6 +129,32 @@ struct M2LArgs {
   int32_t nks;                 // K splits: wavefront w takes K range (w / nrg) / (nt / (16 CT))
 };
 
+// Streaming form of the batched M2L: 16-target tiles, entries cut into one contiguous chunk
+// per workgroup; workgroup g takes items wg_item[g] .. wg_item[g + 1] - 1 (each a tile and an
+// entry range of it).  Split tiles keep FP64 partials in scratch slots tile_item0[tile] + part.
+struct M2LStreamArgs {
+  const M2LItem* items;        // [n_items]
+  const int32_t* wg_item;      // [n_wg + 1]
+  int32_t n_wg;
+  const int32_t* tile_tgt;     // [n_tiles][16], -1 = empty column
+  const int32_t* tile_nparts;  // [n_tiles]
+  const int32_t* tile_item0;   // [n_tiles] first partial slot of a split tile
+  int32_t* counter;            // [n_tiles], zero between launches
+  double* scratch;             // [slots][16][nc rounded to 16] (x2 complex) FP64 partials
+  const int32_t* entry_tab;    // [n_entries]
+  const int32_t* entry_src;    // [n_entries][16], -1 = no source
+  const void* tab;             // [n_tab][tsp] tables in the dtype (complex: re plane, im plane)
+  const int32_t* jbase;        // [Nc] base offset of each kept index into a table
+  const void* mpole;           // [n_box][Nc]
+  void* local;                 // [n_box][Nc]
+  int32_t lds_sbq;             // byte offset of the q-base table in LDS
+};
+
+// Compile-time facts of an instantiated streaming shape (ok = 0: not instantiated).
+struct M2LStreamShape {
+  int32_t ok, tsp, nacc, kj, max_waves;
+};
+
 // FFT form of the M2L (eq. convolution_m2l): spectra are Hermitian halves [Sz][S][(S+1)/2].
 constexpr int kFftMaxPerThread = 16;  // frequencies per thread in the accumulation (256 threads)
 
@@ -211,6 +237,11 @@ int launch_m2l_multi(const M2LMulti& m, int dtype, int rows_per_wave, int col_ti
                      size_t lds, int waves, int grid, hipStream_t s);
 bool m2l_multi_shape_instantiated(int rows_per_wave, int col_tiles_per_wave);
 int launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+M2LStreamShape m2l_stream_shape(int p, int c, int dtype);
+int launch_m2l_stream(const M2LStreamArgs& a, int p, int c, int dtype, int waves, size_t lds, hipStream_t s);
+// FP64 tables [n][ts] (complex interleaved) -> [n][tsp] in the dtype, complex as a re plane then
+// an im plane; the padding past CW ts must already be zero.
+int launch_m2l_stream_tables(const double* src, void* dst, int64_t n, int ts, int tsp, int dtype, hipStream_t s);
 int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s);
 
 }  // namespace fmm

@@ -154,6 +154,7 @@ def m2l_tree():
 def test_m2l(gpu_lib, m2l_tree, kernel, p, single, items, monkeypatch):
     fmm = gpu_lib
     monkeypatch.setenv("FMM_M2L_ITEMS", str(items))
+    monkeypatch.setenv("FMM_M2LS_WG", str(items))  # streaming form: one workgroup, or many with split tiles
     tr = m2l_tree
     param = CASES[kernel]
     d = desc_for(fmm, kernel, p, single)
