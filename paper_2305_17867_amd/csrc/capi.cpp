@@ -70,7 +70,7 @@ struct fmm_batch_s {
   std::vector<M2LItem> h_items;  // host copy (work ordering of persistent launches)
   // streaming form (m2l_stream.hip): 16-target tiles, one contiguous entry chunk per workgroup
   bool stream = false;
-  int32_t n_wg = 0, c_pde = 2, p = 0, lds_sbq = 0;
+  int32_t n_wg = 0, c_pde = 2, p = 0, lds_slot = 0, lds_sbq = 0;
   int32_t* d_wg_item = nullptr;
 };
 
@@ -592,17 +592,19 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   b->p = plan->p;
   b->c_pde = pde_order(plan->desc.kernel);
   if (b->stream) {
-    const int w = std::max(1, std::min(ssh.max_waves, env_int("FMM_M2LS_WAVES", ssh.max_waves)));
+    const int w = std::max(1, std::min(std::min(ssh.max_waves, kM2LStreamMaxWaves),
+                                       env_int("FMM_M2LS_WAVES", ssh.max_waves)));
     b->waves = w;
     b->rows_per_wave = (b->nc + 15) / 16;
     b->col_tiles = b->col_groups = b->k_splits = 1;
     b->nbuf = 1;
     const size_t rb = real_size(dtype);
-    size_t tabs = (size_t)w * ssh.tsp * rb;
-    const size_t red = (size_t)((w + 1) / 2) * ssh.nacc * 64 * sizeof(double);
-    size_t lds = (std::max(tabs, red) + 15) / 16 * 16;
+    // LDS: the wavefronts' tables, their item-sum slots, the q bases and two counters
+    size_t lds = ((size_t)w * ssh.tsp * rb + 15) / 16 * 16;
+    b->lds_slot = (int32_t)lds;
+    lds += (size_t)w * ssh.nacc * 64 * sizeof(double);
     b->lds_sbq = (int32_t)lds;
-    lds += (size_t)8 * ssh.kj * sizeof(int32_t);
+    lds += (size_t)8 * ssh.kj * sizeof(int32_t) + (2 + kM2LStreamMaxWaves) * sizeof(int32_t);
     // one workgroup per compute unit: the chunks are equal, so a second resident workgroup on
     // some units would only make those units finish later
     if (env_int("FMM_M2LS_ONE_PER_CU", 1) && lds <= (size_t)lds_max / 2) lds = (size_t)lds_max / 2 + 256;
@@ -1125,6 +1127,7 @@ static M2LStreamArgs m2l_stream_args(fmm_batch b, const void* mpole, void* local
   a.jbase = b->d_jbase;
   a.mpole = mpole;
   a.local = local;
+  a.lds_slot = b->lds_slot;
   a.lds_sbq = b->lds_sbq;
   return a;
 }

@@ -147,8 +147,11 @@ struct M2LStreamArgs {
   const int32_t* jbase;        // [Nc] base offset of each kept index into a table
   const void* mpole;           // [n_box][Nc]
   void* local;                 // [n_box][Nc]
-  int32_t lds_sbq;             // byte offset of the q-base table in LDS
+  int32_t lds_slot;            // byte offset of the wavefronts' item-sum slots in LDS
+  int32_t lds_sbq;             // byte offset of the q-base table (and two counters) in LDS
 };
+
+constexpr int kM2LStreamMaxWaves = 16;
 
 // Compile-time facts of an instantiated streaming shape (ok = 0: not instantiated).
 struct M2LStreamShape {

@@ -15,8 +15,8 @@
 // entries.  Per entry a wavefront
 //   * writes the entry's compact derivative grid tab[(m_z, m_x, m_y)] (loaded into registers
 //     during the previous entry) to its private LDS buffer,
-//   * gathers the A operand of v_mfma 16x16x4 from that grid: T~[i, q] = grid[base(i) +
-//     base(q)] with base(m) = (m_z S + m_x) S + m_y, so T~ is never expanded,
+//   * gathers the A operand of the matrix-core products from that grid: T~[i, q] =
+//     grid[base(i) + base(q)] with base(m) = (m_z S + m_x) S + m_y, so T~ is never expanded,
 //   * takes the B operand (the 16 source multipoles) straight from global memory into
 //     registers: lane group g (lanes 16 g .. 16 g + 15) holds the pair q = 8 j + 2 g, q + 1
 //     for step j, so the four lane groups read 8 consecutive coefficients of each source;
@@ -25,11 +25,12 @@
 // At the end of a workgroup's share of a tile the wavefronts' accumulators are added in a
 // fixed tree order through LDS.
 //
-// Accumulation: FP64 dtypes accumulate in FP64 matrix-core registers.  FP32 dtypes run each
-// entry (offset group) as an FP32 product with FP32 accumulation and add the entry's partial
-// into FP64 registers, so the sum over the (up to 189 per level) offset groups is FP64.
-// Complex dtypes use four real products per K step.  Rows past the last full 16-row tile (at
-// most two) are contracted on the vector ALU in FP64.
+// Products: v_mfma 16x16x4.  FP64 dtypes accumulate in FP64.  FP32 dtypes run each entry
+// (offset group) as an FP32 product with FP32 accumulation (two accumulator sets, one per
+// coefficient of a B pair, for more independent products in flight), then add the entry's
+// partial into FP64 registers, so the sum over the (up to 189 per level) offset groups is
+// FP64.  At most two rows past the last full 16-row tile are contracted on the vector ALU in
+// FP64.  Complex dtypes use four real products per K step.
 #include "../../include/fmm.h"
 #include "common.hpp"
 #include "device_util.hpp"
@@ -42,24 +43,32 @@ namespace {
 typedef double sd4 __attribute__((ext_vector_type(4)));
 typedef float sf4 __attribute__((ext_vector_type(4)));
 
+// Matrix-core tile of one accumulator set: v_mfma 16x16x4 (FP64 or FP32), a 16-row tile.  Lane
+// l supplies A[l & 15][l >> 4] and B[l >> 4][l & 15] (the 16 columns are the 16 targets of a
+// tile) and holds C[row(l >> 4, v)][l & 15] in register v:  FP64 row = 4 v + (l >> 4),
+// FP32 row = 4 (l >> 4) + v.  (The FP64 4x4x4 product, four independent 4 x 4 x 4 blocks on
+// the lane quads, issues faster, but as a 4-row tile it needs one A gather per product and
+// measured slower here.)
 template <typename R>
-struct SMF;
-// Operand layouts: lane l supplies A[l & 15][l >> 4] and B[l >> 4][l & 15].  Register v of
-// lane l holds C[row(l >> 4, v)][l & 15]:  f64: row = 4 v + (l >> 4);  f32: row = 4 (l >> 4) + v.
+struct STile;
 template <>
-struct SMF<double> {
+struct STile<double> {
   using V = sd4;
+  static constexpr int ROWS = 16, NV = 4;
   static __device__ inline V mma(double a, double b, V c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ inline int arow(int lane) { return lane & 15; }
   static __device__ inline int row(int kq, int v) { return 4 * v + kq; }
 };
 template <>
-struct SMF<float> {
+struct STile<float> {
   using V = sf4;
+  static constexpr int ROWS = 16, NV = 4;
   static __device__ inline V mma(float a, float b, V c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ inline int arow(int lane) { return lane & 15; }
   static __device__ inline int row(int kq, int v) { return 4 * kq + v; }
 };
 
@@ -70,17 +79,22 @@ template <typename R, bool CPLX, int P, int C>
 struct SShape {
   static constexpr int CW = CPLX ? 2 : 1;
   static constexpr int NC = n_full_c(P) - n_full_c(P - C);      // |J|
-  static constexpr int REM = NC % 16;
-  static constexpr bool VALU_ROWS = NC > 16 && REM >= 1 && REM <= kMaxRem;
-  static constexpr int RT = VALU_ROWS ? NC / 16 : (NC + 15) / 16;  // matrix-core row tiles
-  static constexpr int NREM = VALU_ROWS ? REM : 0;                 // rows on the vector ALU
-  static constexpr int KJ = (NC + 7) / 8;                          // B steps of 8 coefficients
+  static constexpr int TR = STile<R>::ROWS, NV = STile<R>::NV;
+  static constexpr int REM = NC % TR;
+  // 16-row tiles: at most two rows past the last full tile go to the vector ALU
+  static constexpr bool VALU_ROWS = TR == 16 && NC > 16 && REM >= 1 && REM <= kMaxRem;
+  static constexpr int RT = VALU_ROWS ? NC / TR : (NC + TR - 1) / TR;  // matrix-core row tiles
+  static constexpr int NREM = VALU_ROWS ? REM : 0;                   // rows on the vector ALU
+  // FP32 keeps separate accumulators for the two coefficients of a B step (twice the
+  // independent product chains); FP64 has one per 4-row tile
+  static constexpr int NSET = sizeof(R) == 4 ? 2 : 1;
+  static constexpr int KJ = (NC + 7) / 8;                            // B steps of 8 coefficients
   static constexpr int S = 2 * P + 1, SZ = 2 * C - 1;
-  static constexpr int TS = SZ * S * S;                            // grid values per plane
-  static constexpr int VEC = 16 / (int)sizeof(R);                  // elements per 128-bit load
+  static constexpr int TS = SZ * S * S;                              // grid values per plane
+  static constexpr int VEC = 16 / (int)sizeof(R);                    // elements per 128-bit load
   static constexpr int TSP = (CW * TS + 64 * VEC - 1) / (64 * VEC) * (64 * VEC);  // padded table
-  static constexpr int NTV = TSP / (64 * VEC);                     // 128-bit table loads per lane
-  static constexpr int NACC = RT * CW * 4 + NREM * CW;             // FP64 sums per lane
+  static constexpr int NTV = TSP / (64 * VEC);                       // 128-bit table loads per lane
+  static constexpr int NACC = RT * CW * NV + NREM * CW;              // FP64 sums per lane
 };
 
 template <typename R, int N>
@@ -95,8 +109,10 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
   using SH = SShape<R, CPLX, P, C>;
   constexpr int CW = SH::CW, NC = SH::NC, RT = SH::RT, NREM = SH::NREM, KJ = SH::KJ;
   constexpr int TS = SH::TS, TSP = SH::TSP, NTV = SH::NTV, VEC = SH::VEC, NACC = SH::NACC;
+  constexpr int TR = SH::TR, NV = SH::NV, NSET = SH::NSET;
   constexpr bool ACC64 = sizeof(R) == 4;
-  using V = typename SMF<R>::V;
+  using TL = STile<R>;
+  using V = typename TL::V;
   using BV = typename RVec<R, 2 * CW>::T;  // the lane's pair (q, q + 1) of one B step
   using TV = typename RVec<R, VEC>::T;     // one 128-bit table load
   extern __shared__ __align__(16) char smem_raw[];
@@ -107,6 +123,10 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
   const int col = lane & 15, kq = lane >> 4;
   R* const tb = reinterpret_cast<R*>(smem_raw) + wave * TSP;
   int* const sbq = reinterpret_cast<int*>(smem_raw + a.lds_sbq);  // [4][2 KJ] base(q), 0 past Nc
+  double* const slots = reinterpret_cast<double*>(smem_raw + a.lds_slot);  // [W][NACC][64] item sums
+  // [0] wavefronts arrived at the current item, [1] items done, [2 + w] entries done by wavefront w
+  int* const ctl = sbq + 8 * KJ;
+  if (tid < 2 + kM2LStreamMaxWaves) ctl[tid] = 0;
 
   for (int k = tid; k < 8 * KJ; k += blockDim.x) {
     const int g = k / (2 * KJ), jj = k - g * (2 * KJ);
@@ -116,12 +136,12 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
   int ib[RT];
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
-    const int i = 16 * r + col;
+    const int i = TR * r + TL::arow(lane);
     ib[r] = i < NC ? a.jbase[i] : 0;  // padded rows read a valid grid value, never stored
   }
   int ibr[NREM > 0 ? NREM : 1];
 #pragma unroll
-  for (int j = 0; j < NREM; ++j) ibr[j] = a.jbase[16 * RT + j];
+  for (int j = 0; j < NREM; ++j) ibr[j] = a.jbase[TR * RT + j];
   __syncthreads();
 
   const R* const mp = reinterpret_cast<const R*>(a.mpole);
@@ -129,27 +149,30 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
   const int* const sbq_l = sbq + kq * (2 * KJ);
   const int w0 = a.wg_item[blockIdx.x], w1 = a.wg_item[blockIdx.x + 1];
   int rot = 0;  // round-robin start: continues across the workgroup's items
+  int done_entries = 0;  // entries this wavefront has started (all items)
 
   for (int ii = w0; ii < w1; ++ii) {
     const M2LItem it = a.items[ii];
     const int nent = it.e1 - it.e0;
-    double acc[RT][CW][4];
+    double acc[RT][CW][NV];
     double racc[NREM > 0 ? NREM : 1][CW];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
       for (int u = 0; u < CW; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[r][u][v] = 0.0;
+        for (int v = 0; v < NV; ++v) acc[r][u][v] = 0.0;
 #pragma unroll
     for (int j = 0; j < (NREM > 0 ? NREM : 1); ++j)
 #pragma unroll
       for (int u = 0; u < CW; ++u) racc[j][u] = 0.0;
-    V vacc[RT][CW];  // FP64: the accumulators; FP32: one entry's partial
+    V vacc[NSET][RT][CW];  // FP64: the accumulators; FP32: one entry's partials
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
+    for (int h = 0; h < NSET; ++h)
 #pragma unroll
-      for (int u = 0; u < CW; ++u) vacc[r][u] = V{};
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int u = 0; u < CW; ++u) vacc[h][r][u] = V{};
 
     int first = wave - rot;
     if (first < 0) first += W;
@@ -180,32 +203,58 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
         bv[j] = x;
       }
     };
+    // table and source indices run two entries ahead of the compute, so that the operand
+    // loads of the next entry never wait on them
+    int tab1 = 0, src1 = -1;  // entry e + W
     if (e < it.e1) {
       const int tab = a.entry_tab[e];
       const int s = a.entry_src[(int64_t)e * 16 + col];
+      if (e + W < it.e1) {
+        tab1 = a.entry_tab[e + W];
+        src1 = a.entry_src[(int64_t)(e + W) * 16 + col];
+      }
       const R* src = mp + (int64_t)(s < 0 ? 0 : s) * NC * CW;
       load_tab(tab);
 #pragma unroll
       for (int j = 0; j < KJ; ++j) load_b(src, s >= 0, j);
     }
     for (; e < it.e1; e += W) {
+      // the two wavefronts that share a SIMD (w and w + W/2) would otherwise run at very
+      // different speeds (the issue arbiter favours the older one) and the younger one would
+      // finish alone; the one that is behind takes the higher priority
+      if (W >= 8) {
+        ++done_entries;
+        if (lane == 0) __hip_atomic_store(ctl + 2 + wave, done_entries, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int partner = __hip_atomic_load(ctl + 2 + (wave + W / 2) % W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__builtin_amdgcn_readfirstlane(partner) < done_entries)
+          __builtin_amdgcn_s_setprio(0);
+        else
+          __builtin_amdgcn_s_setprio(1);
+      }
 #pragma unroll
       for (int k = 0; k < NTV; ++k) *reinterpret_cast<TV*>(tb + (k * 64 + lane) * VEC) = tv[k];
-      const int en = e + W;
+      const int en = e + W, enn = e + 2 * W;
       const bool more = en < it.e1;
-      int sn = -1;
-      if (more) {
-        const int tabn = a.entry_tab[en];
-        sn = a.entry_src[(int64_t)en * 16 + col];
-        load_tab(tabn);
+      int tab2 = 0, src2 = -1;
+      if (enn < it.e1) {
+        tab2 = a.entry_tab[enn];
+        src2 = a.entry_src[(int64_t)enn * 16 + col];
       }
+      if (more) load_tab(tab1);
+      const int sn = src1;
       const R* srcn = mp + (int64_t)(sn < 0 ? 0 : sn) * NC * CW;
+      tab1 = tab2;
+      src1 = src2;
+      int2 qb_next = *reinterpret_cast<const int2*>(sbq_l);
 #pragma unroll
       for (int j = 0; j < KJ; ++j) {
-        const int2 qb = *reinterpret_cast<const int2*>(sbq_l + 2 * j);
+        // the table bases of step j + 1 are read while step j runs
+        const int2 qb = qb_next;
+        if (j + 1 < KJ) qb_next = *reinterpret_cast<const int2*>(sbq_l + 2 * (j + 1));
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           const int qo = v ? qb.y : qb.x;
+          (void)qo;
           R ar[RT], ai[RT];
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
@@ -213,16 +262,17 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
             if constexpr (CPLX) ai[r] = tb[TS + ib[r] + qo];
           }
           const R br = bv[j][v * CW];
+          const int h = NSET > 1 ? v : 0;
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
             if constexpr (CPLX) {
               const R bi = bv[j][v * CW + 1];
-              vacc[r][0] = SMF<R>::mma(ar[r], br, vacc[r][0]);
-              vacc[r][0] = SMF<R>::mma(-ai[r], bi, vacc[r][0]);
-              vacc[r][1] = SMF<R>::mma(ar[r], bi, vacc[r][1]);
-              vacc[r][1] = SMF<R>::mma(ai[r], br, vacc[r][1]);
+              vacc[h][r][0] = TL::mma(ar[r], br, vacc[h][r][0]);
+              vacc[h][r][0] = TL::mma(-ai[r], bi, vacc[h][r][0]);
+              vacc[h][r][1] = TL::mma(ar[r], bi, vacc[h][r][1]);
+              vacc[h][r][1] = TL::mma(ai[r], br, vacc[h][r][1]);
             } else {
-              vacc[r][0] = SMF<R>::mma(ar[r], br, vacc[r][0]);
+              vacc[h][r][0] = TL::mma(ar[r], br, vacc[h][r][0]);
             }
           }
 #pragma unroll
@@ -246,8 +296,14 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
 #pragma unroll
           for (int u = 0; u < CW; ++u) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[r][u][v] += (double)vacc[r][u][v];
-            vacc[r][u] = V{};
+            for (int v = 0; v < NV; ++v) {
+              double x = 0.0;
+#pragma unroll
+              for (int h = 0; h < NSET; ++h) x += (double)vacc[h][r][u][v];
+              acc[r][u][v] += x;
+            }
+#pragma unroll
+            for (int h = 0; h < NSET; ++h) vacc[h][r][u] = V{};
           }
       }
     }
@@ -258,7 +314,7 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
 #pragma unroll
         for (int u = 0; u < CW; ++u)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[r][u][v] = vacc[r][u][v];
+          for (int v = 0; v < NV; ++v) acc[r][u][v] = vacc[0][r][u][v];
     }
     // the VALU rows: add the four lane groups (K ranges) of every column
 #pragma unroll
@@ -269,50 +325,69 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
         racc[jr][u] += __shfl_xor(racc[jr][u], 32, 64);
       }
 
-    // wavefront sums in a fixed tree order through LDS (the table buffers are free after the
-    // barrier): at stride s, wavefront w (w mod 2s == s) hands its sums to wavefront w - s
-    double* red = reinterpret_cast<double*>(smem_raw);
-    for (int s = 1; s < W; s *= 2) {
-      __syncthreads();
-      if (wave % (2 * s) == s) {
-        double* slot = red + (int64_t)(wave / (2 * s)) * NACC * 64 + lane;
+    // Hand-off of the item's sums without a barrier: every wavefront stores its sums in its own
+    // LDS slot and counts itself in; the last one to arrive adds the slots in wavefront order
+    // (a fixed order, so results are bit-reproducible), writes the item out and frees the slots.
+    // A wavefront waits before storing only if the previous item's slots are not read yet.
+    const int item_no = ii - w0;
+    while (__hip_atomic_load(ctl + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < item_no)
+      __builtin_amdgcn_s_sleep(1);
+    {
+      double* slot = slots + (int64_t)wave * NACC * 64 + lane;
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+      for (int r = 0; r < RT; ++r)
 #pragma unroll
-          for (int u = 0; u < CW; ++u)
+        for (int u = 0; u < CW; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) slot[((r * CW + u) * 4 + v) * 64] = acc[r][u][v];
+          for (int v = 0; v < NV; ++v) slot[((r * CW + u) * NV + v) * 64] = acc[r][u][v];
 #pragma unroll
-        for (int jr = 0; jr < NREM; ++jr)
+      for (int jr = 0; jr < NREM; ++jr)
 #pragma unroll
-          for (int u = 0; u < CW; ++u) slot[(RT * CW * 4 + jr * CW + u) * 64] = racc[jr][u];
-      }
-      __syncthreads();
-      if (wave % (2 * s) == 0 && wave + s < W) {
-        const double* slot = red + (int64_t)(wave / (2 * s)) * NACC * 64 + lane;
+        for (int u = 0; u < CW; ++u) slot[(RT * CW * NV + jr * CW + u) * 64] = racc[jr][u];
+    }
+    int arrived = 0;
+    if (lane == 0) arrived = __hip_atomic_fetch_add(ctl, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    arrived = __builtin_amdgcn_readfirstlane(arrived);
+    if (arrived != W - 1) continue;  // another wavefront finishes this item
+
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
-          for (int u = 0; u < CW; ++u)
+      for (int u = 0; u < CW; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[r][u][v] += slot[((r * CW + u) * 4 + v) * 64];
+        for (int v = 0; v < NV; ++v) acc[r][u][v] = 0.0;
 #pragma unroll
-        for (int jr = 0; jr < NREM; ++jr)
+    for (int jr = 0; jr < NREM; ++jr)
 #pragma unroll
-          for (int u = 0; u < CW; ++u) racc[jr][u] += slot[(RT * CW * 4 + jr * CW + u) * 64];
-      }
+      for (int u = 0; u < CW; ++u) racc[jr][u] = 0.0;
+    for (int w = 0; w < W; ++w) {
+      const double* slot = slots + (int64_t)w * NACC * 64 + lane;
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int u = 0; u < CW; ++u)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[r][u][v] += slot[((r * CW + u) * NV + v) * 64];
+#pragma unroll
+      for (int jr = 0; jr < NREM; ++jr)
+#pragma unroll
+        for (int u = 0; u < CW; ++u) racc[jr][u] += slot[(RT * CW * NV + jr * CW + u) * 64];
+    }
+    if (lane == 0) {
+      __hip_atomic_store(ctl, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(ctl + 1, item_no + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     const int nparts = a.tile_nparts[it.tile];
     const int t = a.tile_tgt[(int64_t)it.tile * 16 + col];
     if (nparts == 1) {
-      if (wave == 0 && t >= 0) {
+      if (t >= 0) {
         R* out = reinterpret_cast<R*>(a.local) + (int64_t)t * NC * CW;
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * r + SMF<R>::row(kq, v);
+          for (int v = 0; v < NV; ++v) {
+            const int i = TR * r + TL::row(kq, v);
             if (i < NC) {
 #pragma unroll
               for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((double)out[i * CW + u] + acc[r][u][v]);
@@ -323,62 +398,119 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
           for (int jr = 0; jr < NREM; ++jr)
 #pragma unroll
             for (int u = 0; u < CW; ++u) {
-              const int i = 16 * RT + jr;
+              const int i = TR * RT + jr;
               out[i * CW + u] = (R)((double)out[i * CW + u] + racc[jr][u]);
             }
         }
       }
-      __syncthreads();  // the reduction area is reused by the next item's tables
       continue;
     }
-    // split tile: FP64 partial to scratch; the last workgroup of the tile adds the parts in order
+    // split tile: FP64 partial to scratch; the last part of the tile to finish adds the parts in
+    // part order
     constexpr int NCP = (NC + 15) / 16 * 16;
     const int64_t pstride = (int64_t)16 * NCP * CW;
-    if (wave == 0) {
+    {
       double* mine = a.scratch + (int64_t)(a.tile_item0[it.tile] + it.part) * pstride;
 #pragma unroll
       for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 16 * r + SMF<R>::row(kq, v);
+        for (int v = 0; v < NV; ++v) {
+          const int i = TR * r + TL::row(kq, v);
+          if (i < NC) {
 #pragma unroll
-          for (int u = 0; u < CW; ++u) mine[(col * NCP + i) * CW + u] = acc[r][u][v];
+            for (int u = 0; u < CW; ++u) mine[(col * NCP + i) * CW + u] = acc[r][u][v];
+          }
         }
       if (kq == 0) {
 #pragma unroll
         for (int jr = 0; jr < NREM; ++jr)
 #pragma unroll
-          for (int u = 0; u < CW; ++u) mine[(col * NCP + 16 * RT + jr) * CW + u] = racc[jr][u];
+          for (int u = 0; u < CW; ++u) mine[(col * NCP + TR * RT + jr) * CW + u] = racc[jr][u];
       }
-      __threadfence();
     }
-    __shared__ int s_last;
-    __syncthreads();
-    if (tid == 0) {
-      const int old = atomicAdd(a.counter + it.tile, 1);
-      s_last = (old == nparts - 1);
-    }
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      const double* parts = a.scratch + (int64_t)a.tile_item0[it.tile] * pstride;
-      for (int k = tid; k < 16 * NC; k += blockDim.x) {
-        const int c = k / NC, i = k - c * NC;
-        const int tt = a.tile_tgt[(int64_t)it.tile * 16 + c];
-        if (tt < 0) continue;
-        double sr = 0.0, si = 0.0;
-        for (int pt = 0; pt < nparts; ++pt) {
-          const double* ps = parts + pt * pstride + (c * NCP + i) * CW;
-          sr += ps[0];
-          if constexpr (CPLX) si += ps[1];
+    __threadfence();
+    int old = 0;
+    if (lane == 0) old = atomicAdd(a.counter + it.tile, 1);
+    old = __builtin_amdgcn_readfirstlane(old);
+    if (old != nparts - 1) continue;
+    __threadfence();
+    // the last part: add all parts in part order, its own from registers, the others from
+    // scratch at the same (lane, register) positions (all their loads issued before the sums)
+    {
+      double tot[RT][CW][NV], totr[NREM > 0 ? NREM : 1][CW];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int u = 0; u < CW; ++u)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) tot[r][u][v] = 0.0;
+#pragma unroll
+      for (int jr = 0; jr < (NREM > 0 ? NREM : 1); ++jr)
+#pragma unroll
+        for (int u = 0; u < CW; ++u) totr[jr][u] = 0.0;
+      for (int pt = 0; pt < nparts; ++pt) {
+        if (pt == it.part) {
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int u = 0; u < CW; ++u)
+#pragma unroll
+              for (int v = 0; v < NV; ++v) tot[r][u][v] += acc[r][u][v];
+#pragma unroll
+          for (int jr = 0; jr < NREM; ++jr)
+#pragma unroll
+            for (int u = 0; u < CW; ++u) totr[jr][u] += racc[jr][u];
+          continue;
         }
-        R* out = reinterpret_cast<R*>(a.local) + (int64_t)tt * NC * CW;
-        out[i * CW] = (R)((double)out[i * CW] + sr);
-        if constexpr (CPLX) out[i * CW + 1] = (R)((double)out[i * CW + 1] + si);
+        const double* ps = a.scratch + (int64_t)(a.tile_item0[it.tile] + pt) * pstride;
+        double lr[RT][CW][NV], lrr[NREM > 0 ? NREM : 1][CW];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int i = TR * r + TL::row(kq, v);
+#pragma unroll
+            for (int u = 0; u < CW; ++u) lr[r][u][v] = i < NC ? ps[(col * NCP + i) * CW + u] : 0.0;
+          }
+#pragma unroll
+        for (int jr = 0; jr < NREM; ++jr)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) lrr[jr][u] = ps[(col * NCP + TR * RT + jr) * CW + u];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int u = 0; u < CW; ++u)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) tot[r][u][v] += lr[r][u][v];
+#pragma unroll
+        for (int jr = 0; jr < NREM; ++jr)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) totr[jr][u] += lrr[jr][u];
       }
-      if (tid == 0) atomicExch(a.counter + it.tile, 0);
+      if (t >= 0) {
+        R* out = reinterpret_cast<R*>(a.local) + (int64_t)t * NC * CW;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int i = TR * r + TL::row(kq, v);
+            if (i < NC) {
+#pragma unroll
+              for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((double)out[i * CW + u] + tot[r][u][v]);
+            }
+          }
+        if (kq == 0) {
+#pragma unroll
+          for (int jr = 0; jr < NREM; ++jr)
+#pragma unroll
+            for (int u = 0; u < CW; ++u) {
+              const int i = TR * RT + jr;
+              out[i * CW + u] = (R)((double)out[i * CW + u] + totr[jr][u]);
+            }
+        }
+      }
     }
-    __syncthreads();
+    if (lane == 0) atomicExch(a.counter + it.tile, 0);
   }
 }
 
@@ -387,19 +519,31 @@ __global__ __launch_bounds__(MAXT) void m2l_stream_kernel(M2LStreamArgs a) {
   m2ls_workgroup<R, CPLX, P, C>(a);
 }
 
-// Two wavefronts per SIMD (512 threads) when the estimated register need of a wavefront fits
-// in 256 registers, else one (256 threads, up to 512 registers).
+// Registers a wavefront needs at least: accumulators, the ring of B pairs, the next entry's
+// table, the row bases and the A operands of one step in flight.
 template <typename R, bool CPLX, int P, int C>
-constexpr int stream_max_threads() {
+constexpr int stream_min_regs() {
   using SH = SShape<R, CPLX, P, C>;
   constexpr int rw = (int)sizeof(R) / 4;  // registers per element
-  constexpr int regs = 2 * SH::NACC + (sizeof(R) == 4 ? SH::RT * SH::CW * 4 : 0) + SH::KJ * 2 * SH::CW * rw +
-                       SH::NTV * 4 + 2 * SH::RT * SH::CW * rw + 40;
-  return regs <= 240 ? 512 : 256;
+  return 2 * SH::NACC + (sizeof(R) == 4 ? SH::NSET * SH::RT * SH::CW * 4 : 0) + SH::KJ * 2 * SH::CW * rw +
+         SH::NTV * 4 + SH::RT + (CPLX ? 4 : 2) * (SH::RT < 16 ? SH::RT : 16) * SH::CW * rw + 30;
+}
+// Two wavefronts per SIMD (512 threads) when that need leaves room for scheduling, else one.
+template <typename R, bool CPLX, int P, int C>
+constexpr int stream_max_threads() {
+  return stream_min_regs<R, CPLX, P, C>() <= 200 ? 512 : 256;
+}
+// Instantiations whose need exceeds what one wavefront can hold use the tiled form.
+template <typename R, bool CPLX, int P, int C>
+constexpr bool stream_fits() {
+  return stream_min_regs<R, CPLX, P, C>() <= 400;
 }
 
 template <typename R, bool CPLX, int P, int C>
 int launch_stream_cfg(const M2LStreamArgs& a, int waves, size_t lds, hipStream_t s) {
+  if constexpr (!stream_fits<R, CPLX, P, C>()) {
+    return fail(FMM_EUNSUPPORTED, "streaming M2L: order too high for one wavefront's registers");
+  } else {
   constexpr int MAXT = stream_max_threads<R, CPLX, P, C>();
   if (waves * 64 > MAXT) return fail(FMM_EUNSUPPORTED, "streaming M2L: too many wavefronts per workgroup");
   auto kern = m2l_stream_kernel<R, CPLX, P, C, MAXT>;
@@ -419,6 +563,7 @@ int launch_stream_cfg(const M2LStreamArgs& a, int waves, size_t lds, hipStream_t
   hipLaunchKernelGGL(kern, dim3((unsigned)a.n_wg), dim3((unsigned)(waves * 64)), lds, s, a);
   FMM_HIP_CHECK(hipGetLastError());
   return FMM_OK;
+  }
 }
 
 // Instantiated (order, PDE order) pairs: the orders of the Laplace-type kernels (c = 2) and of
@@ -426,7 +571,7 @@ int launch_stream_cfg(const M2LStreamArgs& a, int waves, size_t lds, hipStream_t
 // the order whose accumulators and operand registers fit one wavefront.
 #define FMM_M2LS_REAL_ORDERS(X) \
   X(2, 2) X(4, 2) X(6, 2) X(8, 2) X(10, 2) X(12, 2) X(6, 4) X(8, 4) X(10, 4)
-#define FMM_M2LS_CPLX_ORDERS(X) X(2, 2) X(4, 2) X(6, 2) X(8, 2)
+#define FMM_M2LS_CPLX_ORDERS(X) X(2, 2) X(4, 2) X(6, 2)
 
 template <typename R, bool CPLX>
 int launch_stream_typed(const M2LStreamArgs& a, int p, int c, int waves, size_t lds, hipStream_t s) {
@@ -446,7 +591,7 @@ void stream_shape_typed(int p, int c, M2LStreamShape& sh) {
 #define FMM_M2LS_SHAPE(P_, C_)                                     \
   if (p == P_ && c == C_) {                                        \
     using SH = SShape<R, CPLX, P_, C_>;                            \
-    sh.ok = 1;                                                     \
+    sh.ok = stream_fits<R, CPLX, P_, C_>() ? 1 : 0;                \
     sh.tsp = SH::TSP;                                              \
     sh.nacc = SH::NACC;                                            \
     sh.kj = SH::KJ;                                                \
