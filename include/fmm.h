@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define FMM_ABI_VERSION 1
+#define FMM_ABI_VERSION 2
 #define FMM_MAX_ORDER 16
 
 typedef enum {
@@ -210,7 +210,17 @@ int fmm_m2l_prepare(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const
                     fmm_batch* batch);
 void fmm_batch_destroy(fmm_batch batch);
 
-/* Launch shape of a prepared M2L batch.  A workgroup owns a tile of 16 * col_groups *
+/* Launch shape of a prepared M2L batch.  Two forms compute the same sums:
+ *
+ * Streaming form (FMM_M2L_FORM_STREAM): targets are tiled in groups of 16; the (tile, offset)
+ * entries of all tiles are cut into `workgroups` contiguous chunks of equal length, one per
+ * workgroup of `waves` wavefronts; every wavefront streams its own entries with its own staged
+ * derivative table and owns all Nc output rows of its 16 targets (no barrier between entries);
+ * a tile cut by a chunk boundary is summed from FP64 partials in part order.  Instantiated for
+ * the Laplace-type kernels at p = 2, 4, ..., 12 (real dtypes; complex up to p = 6) and the
+ * biharmonic kernel at p = 6, 8 (and 10 in FP32).
+ *
+ * Tiled form (FMM_M2L_FORM_TILED): a workgroup owns a tile of 16 * col_groups *
  * col_tiles_per_wave target boxes; each of its wavefronts computes rows_per_wave x
  * col_tiles_per_wave output tiles of 16 x 16 coefficients on the matrix cores, and there are
  * ceil(ceil(Nc / 16) / rows_per_wave) * col_groups * k_splits wavefronts (at most 8): with
@@ -218,14 +228,23 @@ void fmm_batch_destroy(fmm_batch batch);
  * different wavefronts, whose FP64 partial sums are added in a fixed order at the end of the
  * workgroup's work (more wavefronts share one staged offset group).  Tiles are split into parts
  * (partials summed in a fixed order) so that one launch has about target_items workgroups.
- * Zero fields are chosen automatically (k_splits 0 means 1 when rows_per_wave is given). */
+ *
+ * form 0 (automatic): the streaming form where it is instantiated and fits, else the tiled
+ * form; rows_per_wave > 0 with form 0 selects the tiled form.  Zero fields are chosen
+ * automatically (k_splits 0 means 1 when rows_per_wave is given). */
+#define FMM_M2L_FORM_AUTO 0
+#define FMM_M2L_FORM_TILED 1
+#define FMM_M2L_FORM_STREAM 2
 typedef struct {
-  int32_t rows_per_wave;      /* 1..5 */
-  int32_t col_tiles_per_wave; /* 1..2 */
-  int32_t col_groups;         /* 1, 2 or 4 */
-  int32_t target_items;       /* >= 1 */
-  int32_t lds_buffers;        /* 1: stage one offset group at a time; 2: double buffered */
-  int32_t k_splits;           /* 1..4 */
+  int32_t rows_per_wave;      /* 1..5 (tiled) */
+  int32_t col_tiles_per_wave; /* 1..2 (tiled) */
+  int32_t col_groups;         /* 1, 2 or 4 (tiled) */
+  int32_t target_items;       /* >= 1 (tiled) */
+  int32_t lds_buffers;        /* 1: stage one offset group at a time; 2: double buffered (tiled) */
+  int32_t k_splits;           /* 1..4 (tiled) */
+  int32_t form;               /* FMM_M2L_FORM_* */
+  int32_t waves;              /* wavefronts per workgroup, 1..16 (streaming; 0 = the most that fit) */
+  int32_t workgroups;         /* chunks = workgroups of one launch (streaming; 0 = compute units) */
 } fmm_m2l_tuning;
 
 /* fmm_m2l_prepare with an explicit launch shape (tuning may be NULL: automatic).  An
@@ -251,7 +270,8 @@ int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
  * 8 rows padded to a multiple of 16, 9 scratch bytes, 10 row tiles per wavefront,
  * 11 column tiles per wavefront, 12 wavefronts per workgroup, 13 column groups,
  * 14 LDS bytes per workgroup, 15 LDS buffers, 16 K splits, 17 rows contracted on the vector
- * ALU (at most 2 rows past the last full 16-row tile). */
+ * ALU (at most 2 rows past the last full 16-row tile), 18 1 for the streaming form, 19 its
+ * workgroups per launch. */
 int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
 
 /* Batched M2L: local[t] += sum over pairs (t, s) of T(c_t - c_s) mpole[s], T[i,q] =

@@ -26,7 +26,7 @@ class FmmDesc(C.Structure):
 class FmmM2LTuning(C.Structure):
     _fields_ = [("rows_per_wave", C.c_int32), ("col_tiles_per_wave", C.c_int32),
                 ("col_groups", C.c_int32), ("target_items", C.c_int32), ("lds_buffers", C.c_int32),
-                ("k_splits", C.c_int32)]
+                ("k_splits", C.c_int32), ("form", C.c_int32), ("waves", C.c_int32), ("workgroups", C.c_int32)]
 
 
 class FmmError(RuntimeError):

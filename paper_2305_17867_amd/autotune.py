@@ -1,8 +1,9 @@
 """Autotuner for the batched M2L launch shape.
 
 For one (kernel, order, dtype) and one set of interaction pairs it prepares the batch with
-every candidate launch shape (rows per wavefront, column tiles per wavefront, column
-groups, K splits, LDS buffers, workgroups per launch; see fmm_m2l_tuning in include/fmm.h), times the launches
+every candidate launch shape (the streaming form with its wavefronts and workgroups per launch;
+the tiled form with rows per wavefront, column tiles per wavefront, column groups, K splits,
+LDS buffers, workgroups per launch; see fmm_m2l_tuning in include/fmm.h), times the launches
 with HIP events on the current stream, and keeps the fastest.  Results are cached in a JSON
 file keyed by device, kernel, order, dtype and problem size, so later runs reuse them.
 """
@@ -17,26 +18,31 @@ import torch
 
 from . import fmm
 
-SHAPES = [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (5, 1)]  # (rows, col tiles) per wave
+SHAPES = [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (5, 1)]  # tiled (rows, col tiles) per wave
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fmm_m2l_autotune.json")
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "m2l_tuned.json")
 
 
-def candidates(nc: int, n_cu: int, max_waves: int = 8):
+def candidates(nc: int, n_cu: int, max_waves: int = 8, full: bool = False):
+    """Streaming-form candidates (wavefronts per workgroup, workgroups per launch) first, then
+    tiled-form candidates: all of them with full=True, else the shapes that have won on the
+    Laplace workloads (2-3 row tiles of 2 column tiles per wavefront, no column groups)."""
+    out = [{"form": "stream", "waves": w, "workgroups": g}
+           for w in (16, 8, 4, 2) for g in (n_cu, n_cu // 2) if w <= 16]
     rem = nc % 16
     rtiles = nc // 16 if (nc > 16 and 1 <= rem <= 2) else (nc + 15) // 16  # matrix-core row tiles
-    out = []
-    for rt, ctw in SHAPES:
+    for rt, ctw in (SHAPES if full else [(2, 2), (3, 2)]):
         nrg = -(-rtiles // rt)
-        for ncg in (1, 2, 4):
-            for nks in (1, 2, 3, 4):
+        for ncg in ((1, 2, 4) if full else (1,)):
+            for nks in ((1, 2, 3, 4) if full else (1, 2)):
                 waves = nrg * ncg * nks
                 if waves > max_waves or ncg * ctw > 4:
                     continue
-                for items in (2 * n_cu, 3 * n_cu, 4 * n_cu):
-                    for nbuf in (1, 2):
-                        out.append({"rows_per_wave": rt, "col_tiles_per_wave": ctw, "col_groups": ncg,
-                                    "target_items": items, "lds_buffers": nbuf, "k_splits": nks})
+                for items in ((2 * n_cu, 3 * n_cu, 4 * n_cu) if full else (2 * n_cu, 4 * n_cu)):
+                    for nbuf in ((1, 2) if full else (1,)):
+                        out.append({"form": "tiled", "rows_per_wave": rt, "col_tiles_per_wave": ctw,
+                                    "col_groups": ncg, "target_items": items, "lds_buffers": nbuf,
+                                    "k_splits": nks})
     return out
 
 
@@ -58,7 +64,8 @@ def time_batch(batch, mpole, local, reps: int = 5) -> float:
 
 
 def tune(plan: "fmm.Plan", tgt_box, src_box, box_ijk, box_level, reps: int = 5,
-         cache: str | None = DEFAULT_CACHE, max_candidates: int | None = None, log=None) -> dict:
+         cache: str | None = DEFAULT_CACHE, max_candidates: int | None = None, log=None,
+         full: bool = False) -> dict:
     """Returns {"tuning": best tuning dict, "ms": its time, "results": [(tuning, ms | error)]}."""
     desc = plan.desc
     key = _key(desc, len(tgt_box))
@@ -74,7 +81,7 @@ def tune(plan: "fmm.Plan", tgt_box, src_box, box_ijk, box_level, reps: int = 5,
     n_box = int(np.asarray(box_level).shape[0])
     mpole = torch.randn((n_box, plan.nc), dtype=desc.value_dtype, device="cuda")
     local = torch.zeros_like(mpole)
-    cands = candidates(plan.nc, n_cu)
+    cands = candidates(plan.nc, n_cu, full=full)
     if max_candidates:
         cands = cands[:max_candidates]
     results = []

@@ -585,17 +585,34 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
   }
   (void)hipGetLastError();
-  // the streaming form serves every automatic launch it is instantiated for; an explicit
-  // fmm_m2l_tuning selects the tiled form
+  // form: the streaming form serves every automatic launch it is instantiated for; the tiled
+  // form is chosen explicitly or by giving its tile shape
   const M2LStreamShape ssh = m2l_stream_shape(plan->p, pde_order(plan->desc.kernel), dtype);
-  b->stream = ssh.ok && !(tuning && tuning->rows_per_wave > 0) && env_int("FMM_M2L_STREAM", 1) != 0;
+  const int form = tuning ? tuning->form : FMM_M2L_FORM_AUTO;
+  if (form < FMM_M2L_FORM_AUTO || form > FMM_M2L_FORM_STREAM) {
+    delete b;
+    return fail(FMM_EINVAL, "unknown M2L form");
+  }
+  if (form == FMM_M2L_FORM_STREAM && !ssh.ok) {
+    delete b;
+    return fail(FMM_EUNSUPPORTED, "streaming M2L is not instantiated for this kernel, order and dtype");
+  }
+  b->stream = ssh.ok && form != FMM_M2L_FORM_TILED &&
+              !(form == FMM_M2L_FORM_AUTO && tuning && tuning->rows_per_wave > 0) &&
+              env_int("FMM_M2L_STREAM", 1) != 0;
   b->p = plan->p;
   b->c_pde = pde_order(plan->desc.kernel);
   if (b->stream) {
-    const int w = std::max(1, std::min(std::min(ssh.max_waves, kM2LStreamMaxWaves),
-                                       env_int("FMM_M2LS_WAVES", ssh.max_waves)));
+    const int wmax = std::min(ssh.max_waves, kM2LStreamMaxWaves);
+    int w = (tuning && tuning->waves > 0) ? tuning->waves : env_int("FMM_M2LS_WAVES", wmax);
+    if (w > wmax || w < 1) {
+      delete b;
+      return fail(FMM_EUNSUPPORTED, "streaming M2L: " + std::to_string(w) + " wavefronts per workgroup (at most " +
+                                        std::to_string(wmax) + " for this order and dtype)");
+    }
     b->waves = w;
-    b->rows_per_wave = (b->nc + 15) / 16;
+    b->rows_per_wave = (b->nc % 16 >= 1 && b->nc % 16 <= kMaxRem && b->nc > 16) ? b->nc / 16 : (b->nc + 15) / 16;
+    b->shape.nrem = (b->nc % 16 >= 1 && b->nc % 16 <= kMaxRem && b->nc > 16) ? b->nc % 16 : 0;
     b->col_tiles = b->col_groups = b->k_splits = 1;
     b->nbuf = 1;
     const size_t rb = real_size(dtype);
@@ -609,6 +626,10 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     // some units would only make those units finish later
     if (env_int("FMM_M2LS_ONE_PER_CU", 1) && lds <= (size_t)lds_max / 2) lds = (size_t)lds_max / 2 + 256;
     if (lds > (size_t)lds_max - 64) {
+      if (form == FMM_M2L_FORM_STREAM) {
+        delete b;
+        return fail(FMM_EUNSUPPORTED, "streaming M2L needs more LDS than a workgroup has");
+      }
       b->stream = false;
     } else {
       b->lds_bytes = (int64_t)lds;
@@ -805,7 +826,7 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   std::vector<int32_t> tile_nparts(n_tiles), tile_item0(n_tiles);
   if (b->stream) {
     const int64_t E = b->n_entries;
-    int n_wg = std::max(1, env_int("FMM_M2LS_WG", n_cu));
+    int n_wg = (tuning && tuning->workgroups > 0) ? tuning->workgroups : std::max(1, env_int("FMM_M2LS_WG", n_cu));
     n_wg = (int)std::max<int64_t>(1, std::min<int64_t>(n_wg, (E + 2 * b->waves - 1) / (2 * b->waves)));
     std::vector<int64_t> cut(n_wg + 1);
     for (int g = 0; g <= n_wg; ++g) cut[g] = E * g / n_wg;

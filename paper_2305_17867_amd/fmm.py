@@ -282,7 +282,8 @@ class Batch:
 
     INFO = ("n_pair", "n_tables", "n_tiles", "n_entries", "n_items", "useful_columns",
             "computed_columns", "nc", "nc_pad", "scratch_bytes", "rows_per_wave", "col_tiles_per_wave",
-            "waves", "col_groups", "lds_bytes", "lds_buffers", "k_splits", "valu_rows")
+            "waves", "col_groups", "lds_bytes", "lds_buffers", "k_splits", "valu_rows", "stream_form",
+            "workgroups")
 
     def __init__(self, plan: Plan, tgt_box, src_box, box_ijk, box_level, tuning=None, adjoint=False,
                  fft=False):
@@ -299,9 +300,12 @@ class Batch:
         self._h = C.c_void_p()
         tun = None
         if tuning is not None:
+            form = tuning.get("form", 0)
+            form = {"auto": 0, "tiled": 1, "stream": 2}.get(form, form)
             tun = _lib.FmmM2LTuning(int(tuning.get("rows_per_wave", 0)), int(tuning.get("col_tiles_per_wave", 0)),
                                     int(tuning.get("col_groups", 0)), int(tuning.get("target_items", 0)),
-                                    int(tuning.get("lds_buffers", 0)), int(tuning.get("k_splits", 0)))
+                                    int(tuning.get("lds_buffers", 0)), int(tuning.get("k_splits", 0)),
+                                    int(form), int(tuning.get("waves", 0)), int(tuning.get("workgroups", 0)))
         args = (plan._h, int(t.shape[0]), t.ctypes.data_as(_lib.I32P), s.ctypes.data_as(_lib.I32P), self.n_box,
                 ijk.ctypes.data_as(_lib.I32P), lev.ctypes.data_as(_lib.I32P))
         if fft:

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(L, n), n
     # and the binding declares a signature for each
     assert set(names) <= set(lib.SIGNATURES), set(names) - set(lib.SIGNATURES)
-    assert L.fmm_abi_version() == 1
+    assert L.fmm_abi_version() == 2
 
 
 @pytest.mark.parametrize("kernel,c", [("laplace", 2), ("helmholtz", 2), ("yukawa", 2), ("biharmonic", 4)])
