@@ -264,6 +264,18 @@ int fmm_m2l_prepare_ex(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, co
 int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, const int32_t* src_box,
                         int64_t n_box, const int32_t* box_ijk, const int32_t* box_level, fmm_batch* batch);
 
+/* fmm_m2l_batched without any allocation or library scratch, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the FP64 partial sums of tiles split over several workgroups and the per-tile part
+ * counters live in one fixed device array of 16 MiB per device (held until the process ends)
+ * instead of the batch's scratch.  Same arguments and results as fmm_m2l_batched (bit-identical
+ * for the same batch and inputs).  A batch whose partials and counters need more than 16 MiB
+ * gets FMM_EUNSUPPORTED; FFT batches get FMM_EUNSUPPORTED, adjoint batches FMM_ESTATE.  The
+ * counters are cleared by a small kernel on `stream` at every call.  All calls on one device
+ * share the array: calls that can overlap in time on one device (different streams without
+ * ordering) race and give wrong results. */
+int fmm_m2l_batched_static(fmm_batch batch, const void* mpole, void* local, void* stream);
+
 /* Statistics of a prepared batch, written to info[0 .. n_info-1] ([host]):
  * 0 n_pair, 1 n_tables, 2 n_tiles, 3 n_entries (tile x offset groups), 4 n_items (workgroups
  * of one launch), 5 useful pair-columns, 6 computed pair-columns (incl. padding), 7 Nc,

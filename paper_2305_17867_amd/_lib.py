@@ -61,6 +61,7 @@ SIGNATURES = {
     "fmm_batch_destroy": (None, [P]),
     "fmm_batch_info": (C.c_int, [P, I64P, C.c_int32]),
     "fmm_m2l_batched": (C.c_int, [P, P, P, P]),
+    "fmm_m2l_batched_static": (C.c_int, [P, P, P, P]),
     "fmm_m2l_batched_multi": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P), C.POINTER(P), P]),
     "fmm_direct": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P]),
     "fmm_p2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, C.c_int64, P, P,

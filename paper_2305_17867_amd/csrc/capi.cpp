@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <unordered_map>
@@ -1219,6 +1220,67 @@ static int m2l_launch(fmm_batch b, const void* mpole, void* local, void* stream)
 }
 
 static M2LArgs m2l_args(fmm_batch b, const void* mpole, void* local);
+
+// ---- fmm_m2l_batched_static: the split-tile partials and part counters of an M2L launch in a
+// fixed device array instead of the batch's own scratch, for callers that cannot allocate.
+namespace {
+constexpr size_t kStaticScratchBytes = 16u << 20;
+constexpr int kMaxDevices = 64;
+// Host code must not use this name as a device address: its address on a device comes from
+// hipGetSymbolAddress (static_scratch below), once per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = 0;
+  FMM_HIP_CHECK(hipGetDevice(&dev));
+  FMM_REQUIRE(dev >= 0 && dev < kMaxDevices, FMM_EUNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FMM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FMM_OK;
+}
+}  // namespace
+
+int fmm_m2l_batched_static(fmm_batch b, const void* mpole, void* local, void* stream) {
+  FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
+  FMM_REQUIRE(b->plan && b->plan->alive, FMM_ESTATE, "the batch's plan was destroyed");
+  FMM_REQUIRE(!b->adjoint, FMM_ESTATE, "batch was prepared for the adjoint");
+  FMM_REQUIRE(!b->fft, FMM_EUNSUPPORTED, "the FFT form keeps its spectra in the batch; use fmm_m2l_batched");
+  if (b->n_items == 0) return FMM_OK;
+  FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
+  const size_t part_bytes = ((size_t)b->scratch_bytes + 255) / 256 * 256;
+  const size_t need = part_bytes + (size_t)b->n_tiles * sizeof(int32_t);
+  FMM_REQUIRE(need <= kStaticScratchBytes, FMM_EUNSUPPORTED,
+              "this batch needs " + std::to_string(need) + " bytes of scratch; the static array holds " +
+                  std::to_string(kStaticScratchBytes) + " (use fmm_m2l_batched)");
+  void* base = nullptr;
+  int st = static_scratch(&base);
+  if (st) return st;
+  double* part = reinterpret_cast<double*>(base);
+  int32_t* counter = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(base) + part_bytes);
+  // the part counters must start at zero; the array keeps whatever the last call left there
+  st = launch_zero_i32(counter, b->n_tiles, (hipStream_t)stream);
+  if (st) return st;
+  if (b->stream) {
+    M2LStreamArgs a = m2l_stream_args(b, mpole, local);
+    a.scratch = part;
+    a.counter = counter;
+    return launch_m2l_stream(a, b->p, b->c_pde, b->dtype, b->waves, (size_t)b->lds_bytes, (hipStream_t)stream);
+  }
+  M2LArgs a = m2l_args(b, mpole, local);
+  a.scratch = part;
+  a.counter = counter;
+  return launch_m2l(a, b->dtype, b->rows_per_wave, b->col_tiles, b->pf_class, b->nbuf, b->waves,
+                    (hipStream_t)stream);
+}
 
 int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* out) {
   FMM_REQUIRE(out, FMM_EINVAL, "output pointer is NULL");

@@ -245,6 +245,8 @@ int launch_m2l_stream(const M2LStreamArgs& a, int p, int c, int dtype, int waves
 // FP64 tables [n][ts] (complex interleaved) -> [n][tsp] in the dtype, complex as a re plane then
 // an im plane; the padding past CW ts must already be zero.
 int launch_m2l_stream_tables(const double* src, void* dst, int64_t n, int ts, int tsp, int dtype, hipStream_t s);
+// p[0 .. n-1] = 0 with a small kernel (capturable, unlike a memset node)
+int launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
 int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s);
 
 }  // namespace fmm

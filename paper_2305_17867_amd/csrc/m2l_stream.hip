@@ -620,7 +620,19 @@ __global__ void m2ls_table_layout_kernel(const double* src, R* dst, int64_t n, i
   }
 }
 
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace
+
+int launch_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return FMM_OK;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  FMM_HIP_CHECK(hipGetLastError());
+  return FMM_OK;
+}
 
 int launch_m2l_stream_tables(const double* src, void* dst, int64_t n, int ts, int tsp, int dtype, hipStream_t s) {
   const int64_t tot = n * ts;
