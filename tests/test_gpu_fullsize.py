@@ -27,7 +27,7 @@ import torch
 import workloads as W
 from oracle import compressed as Z
 
-from helpers import oracle_m2l_scaled, perm_to_lib, rel
+from helpers import decaying_multipoles, oracle_m2l_scaled, per_order_rel, perm_to_lib, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -99,25 +99,37 @@ def check_l2p(fmm, plan, kernel, param, p, tr, boxes, seed, tol, cplx, n_sample=
 
 
 def check_m2l(plan, kernel, param, p, tr, t, s, batch, seed, tol, cplx, targets):
-    """Batched M2L of seeded multipoles over all pairs; the sampled targets against the oracle."""
+    """Batched M2L of seeded multipoles over all pairs (unit-variance ones, then ones with the
+    decay of physical multipoles); the sampled targets against the oracle, normwise and per
+    derivative order."""
     d = plan.desc
     nc = d.nc
     lh = [tr.box_size(l) for l in range(tr.n_levels)]
-    g = np.random.Generator(np.random.PCG64(seed))
-    beta = g.standard_normal((tr.n_box, nc))
-    if cplx:
-        beta = beta + 1j * g.standard_normal((tr.n_box, nc))
-    mp = dev(beta, d.value_dtype)
-    loc = torch.zeros_like(mp)
-    batch(mp, loc)
-    got = host(loc)[targets]
-    perm = perm_to_lib(kernel, param, p, d.index_table())
+    it = d.index_table()
+    perm = perm_to_lib(kernel, param, p, it)
     inv = np.argsort(perm)
     m = np.isin(t, targets)
-    ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t[m], s[m],
-                            beta[:, inv])[targets][:, perm]
-    err = rel(got, ref)
-    assert err < tol, ("m2l", err)
+    for kind in ("unit", "decaying"):
+        if kind == "unit":
+            g = np.random.Generator(np.random.PCG64(seed))
+            beta = g.standard_normal((tr.n_box, nc))
+            if cplx:
+                beta = beta + 1j * g.standard_normal((tr.n_box, nc))
+        else:
+            beta = decaying_multipoles(it, tr.n_box, seed + 1)
+            if cplx:
+                beta = beta + 1j * decaying_multipoles(it, tr.n_box, seed + 2)
+        mp = dev(beta, d.value_dtype)
+        loc = torch.zeros_like(mp)
+        batch(mp, loc)
+        got = host(loc)[targets]
+        ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t[m], s[m],
+                                beta[:, inv])[targets][:, perm]
+        err = rel(got, ref)
+        assert err < tol, ("m2l", kind, err)
+        errs = per_order_rel(got, ref, it)
+        worst = max(errs, key=errs.get)
+        assert errs[worst] < tol, ("m2l per order", kind, worst, errs[worst])
 
 
 # ----------------------------------------------------------------------------- uniform (benchmark)
@@ -143,6 +155,59 @@ def test_uniform_full_size(gpu_lib, uniform, p, dt):
     check_m2l(plan, "laplace", 0.0, p, tr, t, s, batch, 20 + p, 2e-5 if single else 1e-12, False,
               pick(30 + p, leaves, 3))
     check_l2p(fmm, plan, "laplace", 0.0, p, tr, leaves, 40 + p, tol_pts(single, p), False)
+
+
+_E2E_REF = {}
+
+
+def _oracle_far_potential(p, tr, w, t, s, leaf):
+    """The oracle's far-field potential at the points of target leaf `leaf` from its List-2
+    sources: uncompressed geometry, compressed P2M of each source box, M2L by the translation
+    vector of the pair, L2P (Secs. 3.3, 3.4, 4.1)."""
+    key = (p, int(leaf))
+    if key not in _E2E_REF:
+        theta = 0.0
+        for sb in s[t == leaf]:
+            lo, hi = tr.pt_range[sb]
+            beta = Z.p2m("laplace", 0.0, p, tr.center[sb], tr.points[lo:hi], w[lo:hi])
+            theta = theta + Z.m2l("laplace", 0.0, p, tr.center[leaf] - tr.center[sb], beta)
+        lo, hi = tr.pt_range[leaf]
+        _E2E_REF[key] = Z.l2p("laplace", 0.0, p, tr.center[leaf], theta, tr.points[lo:hi])
+    return _E2E_REF[key]
+
+
+@pytest.mark.parametrize("p,dt", [(8, "f64"), (8, "f32"), (12, "f64"), (12, "f32")])
+def test_uniform_end_to_end_potential(gpu_lib, uniform, p, dt):
+    """P2M of every leaf -> batched M2L of level 4 -> L2P at every point, in the benchmark's
+    launch shapes; the potential at the points of sampled target leaves against the oracle's
+    P2M -> M2L -> L2P over the same List-2 pairs.  FP64 at 1e-12; FP32 (FP32 points, weights,
+    products and potentials) at 2e-5, the FP32 M2L bound."""
+    fmm = gpu_lib
+    tr, w, t, s = uniform
+    single = dt == "f32"
+    d = fmm.Desc("laplace", p, dt)
+    plan = fmm.Plan(d, [tr.box_size(l) for l in range(tr.n_levels)])
+    leaves = tr.boxes_at(4)
+    l0, nl = int(leaves[0]), len(leaves)
+    assert np.array_equal(leaves, np.arange(l0, l0 + nl))  # leaves are one contiguous box range
+    rd, vd = d.real_dtype, d.value_dtype
+    cen = dev(tr.center[leaves], torch.float64)
+    lev = dev(tr.level[leaves], torch.int32)
+    rng = dev(tr.pt_range[leaves], torch.int64)
+    pts = dev(tr.points, rd)
+    mp = torch.zeros((tr.n_box, d.nc), dtype=vd, device="cuda")
+    loc = torch.zeros_like(mp)
+    pot = torch.zeros(tr.points.shape[0], dtype=vd, device="cuda")
+    plan.p2m(cen, lev, rng, pts, dev(w, vd), out=mp[l0:l0 + nl])
+    batch = plan.prepare(t, s, tr.ijk, tr.level)  # the benchmark's (tuned) launch shape
+    batch(mp, loc)
+    plan.l2p(cen, lev, rng, pts, loc[l0:l0 + nl].contiguous(), pot)
+    got_all = host(pot).astype(np.float64)
+    sample = pick(200 + p, leaves, 2 if p <= 8 else 1)
+    got = np.concatenate([got_all[tr.pt_range[b][0]:tr.pt_range[b][1]] for b in sample])
+    ref = np.concatenate([_oracle_far_potential(p, tr, w, t, s, b) for b in sample])
+    err = rel(got, ref)
+    assert err < (2e-5 if single else 1e-12), err
 
 
 # ----------------------------------------------------------------------------- Plummer, Helmholtz

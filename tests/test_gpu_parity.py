@@ -1,10 +1,14 @@
 """GPU parity: every entry point of the C ABI against the CPU oracle on seeded inputs.
 
 Tolerances (normwise relative l2 over the whole output array unless stated):
-  FP64 / complex128: 1e-12 (P2M, M2L, L2P, direct, end to end); derivative tables 1e-13
-  per derivative order.
-  FP32 / complex64: P2M and L2P 2e-6, direct 1e-5 (700-term sums), M2L 2e-5 (FP32 products of entries that
-  span many orders of magnitude, FP64 accumulation across offset groups).
+  FP64 / complex128: 1e-12 (P2M, M2L, L2P, direct, end to end); derivative tables 1e-13.
+  FP32 / complex64: P2M and L2P 2e-6, direct 1e-5 (700-term sums), M2L 2e-5 (FP32 products of
+  entries that span many orders of magnitude, FP64 accumulation across offset groups).
+Derivative tables and M2L outputs are checked per derivative order |i| (the normwise error over
+each order on its own), so that the small low-order coefficients are held to the same relative
+bound as the large high-order ones; M2L is fed both unit-variance multipoles and multipoles
+with the decay of physical ones.  The derivative tables are compared with the mpmath (50-digit)
+radial product formula, which shares no step with the recurrences of the GPU tables.
 """
 import os
 
@@ -17,7 +21,8 @@ from oracle import compressed as Z
 from oracle import kernels as K
 from oracle import multiindex as MI
 
-from helpers import oracle_m2l_scaled, oracle_scaled_table, perm_to_lib, rel, tree_inputs
+from helpers import (decaying_multipoles, oracle_m2l_scaled, oracle_scaled_table, per_order_rel, perm_to_lib, rel,
+                     tree_inputs)
 
 pytestmark = pytest.mark.gpu
 
@@ -41,18 +46,25 @@ def desc_for(fmm, kernel, p, single, param=None):
 
 # ----------------------------------------------------------------------------- derivative tables
 
+# offsets of the interaction list, including ones on and near the coordinate axes, where the
+# radial product formula's terms cancel most
+DERIV_OFFSETS = [(2, 0, 0), (0, 0, 3), (0, -2, 0), (3, 3, 3), (2, -3, 1), (-3, 1, -2), (2, 2, 0), (-1, 3, -3),
+                 (0, 2, -3), (3, -2, 2)]
+
+
 @pytest.mark.parametrize("kernel,param,p,h", [
     ("laplace", 0.0, 8, 1 / 16), ("laplace", 0.0, 12, 1 / 16), ("yukawa", 2.0, 8, 1 / 16),
-    ("yukawa", 2.0, 12, 1 / 4), ("helmholtz", 16.0, 12, 1 / 16), ("helmholtz", 1.0, 6, 1.0),
-    ("biharmonic", 0.0, 10, 1 / 8)])
+    ("yukawa", 2.0, 12, 1 / 4), ("helmholtz", 16.0, 8, 1 / 16), ("helmholtz", 16.0, 12, 1 / 16),
+    ("helmholtz", 1.0, 6, 1.0), ("biharmonic", 0.0, 8, 1 / 8), ("biharmonic", 0.0, 12, 1 / 8)])
 def test_deriv_tables(gpu_lib, kernel, param, p, h):
+    """GPU tables (Taylor-coefficient recurrences in FP64) against the mpmath tables of the
+    radial product formula (Sec. 4.4, eq. tausch-dist-derivatives), per derivative order."""
     fmm = gpu_lib
     d = fmm.Desc(kernel, p, "c128" if kernel == "helmholtz" else "f64", param)
-    offs = W.all_list2_offsets()[::7]
-    got = host(fmm.deriv_tables(d, dev(offs.astype(np.float64), torch.float64),
-                                dev(np.full(len(offs), h), torch.float64)))
-    for k, o in enumerate(offs):
-        ref = oracle_scaled_table(kernel, param, p, tuple(int(v) for v in o), h)
+    offs = np.array(DERIV_OFFSETS, dtype=np.float64)
+    got = host(fmm.deriv_tables(d, dev(offs, torch.float64), dev(np.full(len(offs), h), torch.float64)))
+    for k, o in enumerate(DERIV_OFFSETS):
+        ref = oracle_scaled_table(kernel, param, p, o, h, True)
         for n in range(2 * p + 1):
             ms = [m for m in ref if sum(m) == n]
             a = np.array([got[k][m[2], m[0], m[1]] for m in ms])
@@ -149,6 +161,26 @@ def m2l_tree():
     return W.uniform_tree(pts, 3)
 
 
+def _multipoles(kind, kernel, index_table, n_box, seed):
+    """Unit-variance or physically decaying scaled multipoles (complex for Helmholtz)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    if kind == "unit":
+        beta = g.standard_normal((n_box, len(index_table)))
+        if kernel == "helmholtz":
+            beta = beta + 1j * g.standard_normal((n_box, len(index_table)))
+    else:
+        beta = decaying_multipoles(index_table, n_box, seed)
+        if kernel == "helmholtz":
+            beta = beta + 1j * decaying_multipoles(index_table, n_box, seed + 1)
+    return beta
+
+
+def assert_per_order(got, ref, index_table, tol, what):
+    errs = per_order_rel(got, ref, index_table)
+    worst = max(errs, key=errs.get)
+    assert errs[worst] < tol, (what, "order", worst, errs[worst])
+
+
 @pytest.mark.parametrize("kernel,p,single", M2L_CASES)
 @pytest.mark.parametrize("items", [1, 4096])
 def test_m2l(gpu_lib, m2l_tree, kernel, p, single, items, monkeypatch):
@@ -165,32 +197,78 @@ def test_m2l(gpu_lib, m2l_tree, kernel, p, single, items, monkeypatch):
     batch = plan.prepare(t, s, tr.ijk, tr.level)
     info = batch.info()
     assert info["n_pair"] == len(t)
-    nc = d.nc
-    g = np.random.Generator(np.random.PCG64(21))
-    beta = g.standard_normal((tr.n_box, nc))
-    if kernel == "helmholtz":
-        beta = beta + 1j * g.standard_normal((tr.n_box, nc))
-    loc0 = g.standard_normal((tr.n_box, nc))
-    if kernel == "helmholtz":
-        loc0 = loc0 + 1j * g.standard_normal((tr.n_box, nc))
-    mp = dev(beta, d.value_dtype)
-    loc = dev(loc0, d.value_dtype)
-    batch(mp, loc)
-    got = host(loc) - host(dev(loc0, d.value_dtype))
-    perm = perm_to_lib(kernel, param, p, d.index_table())
+    it = d.index_table()
+    perm = perm_to_lib(kernel, param, p, it)
     inv = np.argsort(perm)
-    ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t, s, beta[:, inv])
-    ref = ref[:, perm]
     tol = 2e-5 if single else 1e-12
-    assert rel(got, ref) < tol, rel(got, ref)
-    # deterministic: a second launch on the same input gives bit-identical output
-    loc2 = dev(loc0, d.value_dtype)
-    batch(mp, loc2)
-    assert np.array_equal(host(loc2), host(loc))
+    for kind, seed in (("unit", 21), ("decaying", 22)):
+        beta = _multipoles(kind, kernel, it, tr.n_box, seed)
+        g = np.random.Generator(np.random.PCG64(seed + 100))
+        loc0 = g.standard_normal(beta.shape) + (1j * g.standard_normal(beta.shape) if kernel == "helmholtz" else 0)
+        mp = dev(beta, d.value_dtype)
+        loc = dev(loc0, d.value_dtype)
+        batch(mp, loc)
+        got = host(loc) - host(dev(loc0, d.value_dtype))
+        ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t, s, beta[:, inv])
+        ref = ref[:, perm]
+        targets = np.unique(t)
+        assert rel(got, ref) < tol, (kind, rel(got, ref))
+        assert_per_order(got[targets], ref[targets], it, tol, kind)
+        # deterministic: a second launch on the same input gives bit-identical output
+        loc2 = dev(loc0, d.value_dtype)
+        batch(mp, loc2)
+        assert np.array_equal(host(loc2), host(loc))
 
 
-KSPLIT_CASES = [("laplace", 8, False, (2, 2, 1)), ("laplace", 8, True, (3, 2, 1)), ("helmholtz", 6, False, (2, 1, 2)),
-                ("biharmonic", 12, True, (3, 2, 1)), ("yukawa", 10, True, (2, 1, 1))]
+# each kernel once with mpmath derivative tables (a few offsets, so that the 50-digit tables stay
+# cheap): the M2L output against the oracle's dense T~ built from the mpmath tables, per order,
+# in the streaming and the tiled form
+MP_CASES = [("laplace", 8, "f64"), ("yukawa", 8, "f64"), ("helmholtz", 6, "c128"), ("biharmonic", 8, "f64"),
+            ("laplace", 12, "f64")]
+
+
+@pytest.mark.parametrize("kernel,p,dt", MP_CASES)
+@pytest.mark.parametrize("form", ["stream", "tiled"])
+def test_m2l_against_mpmath_tables(gpu_lib, m2l_tree, kernel, p, dt, form):
+    fmm = gpu_lib
+    tr = m2l_tree
+    param = CASES[kernel]
+    d = fmm.Desc(kernel, p, dt, param)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    t, s = W.interaction_pairs(tr, [3])
+    off = tr.ijk[t] - tr.ijk[s]
+    keep = np.zeros(len(t), bool)
+    for o in DERIV_OFFSETS[:6]:
+        keep |= np.all(off == np.array(o), axis=1)
+    t, s = t[keep], s[keep]
+    assert len(np.unique(tr.ijk[t] - tr.ijk[s], axis=0)) == 6
+    if form == "stream":
+        tun = {"form": "stream", "workgroups": 4}
+    else:
+        tun = {"form": "tiled"}
+    try:
+        batch = plan.prepare(t, s, tr.ijk, tr.level, tuning=tun)
+    except fmm._lib.FmmError as e:
+        assert form == "stream" and e.status == fmm._lib.FMM_EUNSUPPORTED
+        pytest.skip(f"streaming form not instantiated for {kernel} p={p} {dt}")
+    it = d.index_table()
+    perm = perm_to_lib(kernel, param, p, it)
+    inv = np.argsort(perm)
+    for kind, seed in (("unit", 31), ("decaying", 32)):
+        beta = _multipoles(kind, kernel, it, tr.n_box, seed)
+        loc = torch.zeros((tr.n_box, d.nc), dtype=d.value_dtype, device="cuda")
+        batch(dev(beta, d.value_dtype), loc)
+        ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t, s, beta[:, inv],
+                                mp=True)[:, perm]
+        targets = np.unique(t)
+        assert_per_order(host(loc)[targets], ref[targets], it, 1e-12, kind)
+
+
+# tiled launch shapes (rows per wavefront, column tiles per wavefront, column groups) with at
+# most two row groups, so that three K ranges still fit the eight wavefronts of a workgroup
+KSPLIT_CASES = [("laplace", 8, False, (3, 2, 1)), ("laplace", 8, True, (3, 2, 1)), ("helmholtz", 6, False, (2, 1, 1)),
+                ("biharmonic", 8, True, (4, 1, 1)), ("yukawa", 10, True, (4, 1, 1)), ("laplace", 6, False, (3, 1, 2))]
 
 
 @pytest.mark.parametrize("kernel,p,single,shape", KSPLIT_CASES)
@@ -210,27 +288,21 @@ def test_m2l_k_split(gpu_lib, m2l_tree, kernel, p, single, shape, nks, items):
     tun = dict(rows_per_wave=rt, col_tiles_per_wave=ct, col_groups=ncg, lds_buffers=1, k_splits=nks)
     if items:
         tun["target_items"] = items
-    try:
-        batch = plan.prepare(t, s, tr.ijk, tr.level, tuning=tun)
-    except fmm._lib.FmmError as e:
-        # only a shape that is not instantiated (prefetch classes) or exceeds the LDS is skipped
-        if e.status != fmm._lib.FMM_EUNSUPPORTED:
-            raise
-        pytest.skip(f"shape does not fit: {e}")
-    assert batch.info()["k_splits"] == nks
-    nc = d.nc
-    g = np.random.Generator(np.random.PCG64(23))
-    beta = g.standard_normal((tr.n_box, nc))
-    if kernel == "helmholtz":
-        beta = beta + 1j * g.standard_normal((tr.n_box, nc))
-    mp = dev(beta, d.value_dtype)
-    loc = torch.zeros_like(mp)
-    batch(mp, loc)
-    perm = perm_to_lib(kernel, param, p, d.index_table())
+    batch = plan.prepare(t, s, tr.ijk, tr.level, tuning=tun)
+    assert batch.info()["k_splits"] == nks and batch.info()["stream_form"] == 0
+    it = d.index_table()
+    perm = perm_to_lib(kernel, param, p, it)
     inv = np.argsort(perm)
-    ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t, s, beta[:, inv])[:, perm]
     tol = 2e-5 if single else 1e-12
-    assert rel(host(loc), ref) < tol, rel(host(loc), ref)
+    targets = np.unique(t)
+    for kind, seed in (("unit", 23), ("decaying", 24)):
+        beta = _multipoles(kind, kernel, it, tr.n_box, seed)
+        mp = dev(beta, d.value_dtype)
+        loc = torch.zeros_like(mp)
+        batch(mp, loc)
+        ref = oracle_m2l_scaled(kernel, param, p, tr.ijk.astype(np.int64), tr.level, lh, t, s, beta[:, inv])[:, perm]
+        assert rel(host(loc), ref) < tol, (kind, rel(host(loc), ref))
+        assert_per_order(host(loc)[targets], ref[targets], it, tol, kind)
 
 
 def test_m2l_empty_and_validation(gpu_lib):
