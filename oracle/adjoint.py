@@ -6,7 +6,9 @@
     d L / d x   = c(x) sum_y w_y grad G(x - y)
   the far field built from the compressed operators (every level's List-2 pairs, P2M from the
   points of each source box, L2P at each level's target boxes), evaluated plainly per pair, and
-  its gradients by brute-force transposes (unit vectors) and central differences.
+  its gradients by brute-force transposes (unit vectors) and central differences;
+  the same three gradients of the direct sum restricted to the far field's box pairs (the limit
+  of the far field's gradients as p grows).
 """
 from __future__ import annotations
 
@@ -69,3 +71,27 @@ def far_field_direct(kernel, param, tree_s, tree_t, pairs, w, src, tgt):
         if b > a and d > c:
             out[a:b] += K.direct_sum(kernel, param, src[c:d], w[c:d], tgt[a:b])
     return out
+
+
+def far_field_direct_gradients(kernel, param, tree_s, tree_t, pairs, w, src, tgt, c):
+    """(d L/d w, d L/d src, d L/d tgt) of L = sum_x c(x) phi_far(x), phi_far the direct sum of
+    eq. (1) over the points of each (target box, source box) pair (far_field_direct): for every
+    target box, direct_gradients over the points of all its source boxes at once, accumulated."""
+    t_all, s_all = (np.asarray(a) for a in pairs)
+    src = np.asarray(src, np.float64)
+    tgt = np.asarray(tgt, np.float64)
+    dw = np.zeros(src.shape[0])
+    dy = np.zeros_like(src)
+    dx = np.zeros_like(tgt)
+    for t in np.unique(t_all):
+        a, b = tree_t.pt_range[t]
+        if b <= a:
+            continue
+        idx = np.concatenate([np.arange(*tree_s.pt_range[s]) for s in s_all[t_all == t]])
+        if idx.size == 0:
+            continue
+        gw, gy, gx = direct_gradients(kernel, param, src[idx], w[idx], tgt[a:b], c[a:b])
+        np.add.at(dw, idx, gw)
+        np.add.at(dy, idx, gy)
+        dx[a:b] += gx
+    return dw, dy, dx

@@ -27,18 +27,19 @@ def tree3():
     return W.uniform_tree(pts, 3)
 
 
-KP = [("laplace", 0.0), ("yukawa", 2.0), ("biharmonic", 0.0)]
+# (kernel, param, order, boxes checked): the brute-force transposes cost Nc oracle evaluations
+# per box, so the order of the differentiation workload (p = 10) runs on fewer boxes
+KP = [("laplace", 0.0, 5, 40), ("yukawa", 2.0, 5, 40), ("biharmonic", 0.0, 5, 40), ("laplace", 0.0, 10, 8)]
 
 
-@pytest.mark.parametrize("kernel,param", KP)
-def test_l2p_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param):
+@pytest.mark.parametrize("kernel,param,p,nbox", KP)
+def test_l2p_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param, p, nbox):
     fmm = gpu_lib
-    p = 5
     tr = tree3
     d = fmm.Desc(kernel, p, "f64", param)
     lh = [tr.box_size(l) for l in range(tr.n_levels)]
     plan = fmm.Plan(d, lh)
-    boxes = tr.boxes_at(3)[:40]
+    boxes = tr.boxes_at(3)[:nbox]
     n = tr.points.shape[0]
     g = np.random.Generator(np.random.PCG64(1)).standard_normal(n)
     theta = np.random.Generator(np.random.PCG64(2)).standard_normal((len(boxes), d.nc))
@@ -71,15 +72,14 @@ def test_l2p_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param
     assert rel(host(tgt_grad)[sel], ref_tg[sel]) < 1e-7
 
 
-@pytest.mark.parametrize("kernel,param", KP)
-def test_p2m_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param):
+@pytest.mark.parametrize("kernel,param,p,nbox", KP)
+def test_p2m_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param, p, nbox):
     fmm = gpu_lib
-    p = 5
     tr = tree3
     d = fmm.Desc(kernel, p, "f64", param)
     lh = [tr.box_size(l) for l in range(tr.n_levels)]
     plan = fmm.Plan(d, lh)
-    boxes = tr.boxes_at(3)[:30]
+    boxes = tr.boxes_at(3)[:min(nbox, 30)]
     n = tr.points.shape[0]
     w = W.normal_weights(n, 4)
     mg = np.random.Generator(np.random.PCG64(3)).standard_normal((len(boxes), d.nc))
@@ -109,7 +109,8 @@ def test_p2m_adjoint_matches_brute_force_transpose(gpu_lib, tree3, kernel, param
     assert rel(host(sg)[sel], ref_s[sel]) < 1e-7
 
 
-@pytest.mark.parametrize("kernel,param,p", [("laplace", 0.0, 8), ("yukawa", 2.0, 6), ("biharmonic", 0.0, 6)])
+@pytest.mark.parametrize("kernel,param,p", [("laplace", 0.0, 8), ("yukawa", 2.0, 6), ("biharmonic", 0.0, 6),
+                                            ("laplace", 0.0, 10)])
 def test_m2l_adjoint_is_the_transpose(gpu_lib, tree3, kernel, param, p):
     fmm = gpu_lib
     tr = tree3
@@ -223,3 +224,49 @@ def test_farfield_weight_gradient_vs_direct_sum_gradient(gpu_lib):
     # d L / d w_s of the direct far field = far field with the roles of sources and targets swapped
     ref = A.far_field_direct("laplace", 0.0, tt, ts, pairs[::-1], c, tt.points, ts.points)
     assert rel(host(W_.grad), ref) < 1e-5
+
+
+def _gradients_4096(gpu_lib, p, dt):
+    from paper_2305_17867_amd.farfield import FarField
+    n = 4096
+    ts = W.uniform_tree(W.uniform_points(n, 40), 3)
+    tt = W.uniform_tree(W.uniform_points(n, 41), 3)
+    w = W.normal_weights(n, 42)
+    c = W.normal_weights(n, 43)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    ff = FarField("laplace", p, dt, ts, tt)
+    W_ = dev(w, tdt).requires_grad_(True)
+    S_ = dev(ts.points, tdt).requires_grad_(True)
+    T_ = dev(tt.points, tdt).requires_grad_(True)
+    (ff.apply(W_, S_, T_) * dev(c, tdt)).sum().backward()
+    got = [host(x.grad).astype(np.float64) for x in (W_, S_, T_)]
+    key = "direct"
+    if key not in _DIRECT_4096:
+        pairs = W.interaction_pairs(ts, [2, 3])
+        _DIRECT_4096[key] = A.far_field_direct_gradients("laplace", 0.0, ts, tt, pairs, w, ts.points, tt.points, c)
+    return {name: rel(a, b) for name, a, b in zip(("w", "src", "tgt"), got, _DIRECT_4096[key])}
+
+
+_DIRECT_4096 = {}
+# truncation bounds at p = 10 on this workload: the weight gradient is a far-field potential (an
+# order-p expansion); a position gradient differentiates the expansion once, which converges like
+# one of order p - 1 with a factor of about p (measured 1.3e-4 at p = 10)
+TOL_4096 = {"w": 1e-5, "src": 4e-4, "tgt": 4e-4}
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_farfield_gradients_vs_direct_sum_gradients_4096(gpu_lib, dt):
+    """The differentiation workload on a 4,096-point subset: Laplace p = 10, 4,096 sources and
+    4,096 targets uniform (depth-3 octrees, List-2 pairs of levels 2 and 3), FP64 tables; all three
+    gradients of L = sum_x c(x) phi(x) (weights, source and target positions) against the
+    direct-sum gradients of eq. (1) restricted to the same box pairs.  They agree to the
+    truncation error of p = 10, not to roundoff (bounds above); in FP64 every error must also
+    have fallen by more than 5x from p = 6, as a truncation error does and a wrong term,
+    sign or index would not."""
+    err = _gradients_4096(gpu_lib, 10, dt)
+    for name, e in err.items():
+        assert e < TOL_4096[name], (name, e)
+    if dt == "f64":
+        err6 = _gradients_4096(gpu_lib, 6, dt)
+        for name, e in err.items():
+            assert e < err6[name] / 5, (name, e, err6[name])

@@ -45,3 +45,40 @@ def test_far_field_converges_to_direct_far_field():
     ref = A.far_field_direct("laplace", 0.0, tr, tr, pairs, w, tr.points, tr.points)
     errs = [rel_err(A.far_field("laplace", 0.0, p, tr, tr, pairs, w, tr.points, tr.points), ref) for p in (2, 4, 6)]
     assert errs[1] < 0.3 * errs[0] and errs[2] < 0.3 * errs[1] and errs[2] < 1e-3
+
+
+def test_far_field_direct_gradients_pins():
+    """The restricted direct-sum gradients: equal to the unrestricted ones when the pairs cover
+    every (target box, source box) combination, and to central differences of
+    far_field_direct when they do not."""
+    src = W.uniform_points(80, 21)
+    tgt = W.uniform_points(70, 22)
+    ts = W.uniform_tree(src, 1)
+    tt = W.uniform_tree(tgt, 1)
+    w = W.normal_weights(80, 23)
+    c = W.normal_weights(70, 24)
+    boxes = ts.boxes_at(1)
+    every = (np.repeat(boxes, len(boxes)), np.tile(boxes, len(boxes)))
+    got = A.far_field_direct_gradients("laplace", 0.0, ts, tt, every, w, ts.points, tt.points, c)
+    ref = A.direct_gradients("laplace", 0.0, ts.points, w, tt.points, c)
+    for a, b in zip(got, ref):
+        assert rel_err(a, b) < 1e-13
+    # a restricted set: pairs of non-adjacent level-1 boxes only
+    ijk = ts.ijk
+    keep = [(t, s) for t in boxes for s in boxes if np.abs(ijk[t] - ijk[s]).max() >= 1 and (t + s) % 3]
+    pairs = (np.array([k[0] for k in keep]), np.array([k[1] for k in keep]))
+    dw, dy, dx = A.far_field_direct_gradients("yukawa", 2.0, ts, tt, pairs, w, ts.points, tt.points, c)
+    L = lambda w_, s_, t_: c @ A.far_field_direct("yukawa", 2.0, ts, tt, pairs, w_, s_, t_)
+    eps = 1e-6
+    e = np.zeros(80)
+    e[5] = 1.0
+    assert abs(dw[5] - (L(w + eps * e, ts.points, tt.points) - L(w - eps * e, ts.points, tt.points)) / (2 * eps)) < 1e-7
+    for i, k in ((7, 0), (31, 2)):
+        d = np.zeros_like(ts.points)
+        d[i, k] = eps
+        fd = (L(w, ts.points + d, tt.points) - L(w, ts.points - d, tt.points)) / (2 * eps)
+        assert abs(dy[i, k] - fd) <= 1e-6 * max(1.0, abs(fd))
+        d = np.zeros_like(tt.points)
+        d[i, k] = eps
+        fd = (L(w, ts.points, tt.points + d) - L(w, ts.points, tt.points - d)) / (2 * eps)
+        assert abs(dx[i, k] - fd) <= 1e-6 * max(1.0, abs(fd))
