@@ -6,16 +6,22 @@ depth 4 (4,096 leaves, ~256 points each), M2L over all 584,136 List-2 pairs of l
 (316 distinct offsets).  One step = compressed P2M of every leaf -> batched M2L -> L2P at
 every point (plus clearing the local and potential arrays).  Inputs are resident in HBM
 before the timed region.  The step's launches are issued with their arguments marshalled once
-(bound calls); the same step captured in a HIP graph and replayed is reported beside it.  The headline line is FP64 at p = 8; FP32 and p = 12 are reported
-as variants in the same line.
+(bound calls); the same step captured in a HIP graph and replayed is reported beside it.  The
+headline line is FP64 at p = 8; FP32 and p = 12 are reported as variants in the same line.
 
 value = M2L box-pairs per second of the whole step (pairs / step time).
 roofline: the M2L kernel (the dominant one), algorithmic FLOPs 2 Nc^2 per pair over its
 average launch time measured with HIP events on its stream.  traffic: HBM bytes per launch from
 the rocprofv3 FETCH_SIZE / WRITE_SIZE passes recorded in profiles/ (scaled by the factors a
 plain copy gives), or null when the kernel sources changed since they were taken.
-Supplementary fields: the FFT form of the same M2L, and the mixed Yukawa + biharmonic workload
-(524,288 points, orders per level) as one graph-captured persistent launch.
+Further fields: M2M / L2L; the complete FMM on the uniform and an adaptive tree; the mixed
+Yukawa + biharmonic workload (524,288 points, orders per level) in one persistent launch; the
+Helmholtz p = 12 far field of 2^21 Plummer points in one launch (complex128 and complex64) and
+its complete FMM; the Laplace p = 10 far field of 2^21 + 2^21 points with its gradients.
+Every result carries its error against FP64 references on sampled outputs: the oracle's
+compressed expansions where the result is an expansion, the direct sum of eq. (1) (over the
+far-field box pairs where the result is a far field) otherwise.  The oracle runs only in the
+CPU-baseline leg, after the GPU work; --no-cpu-baseline leaves those error fields null.
 cpu_baseline: the CPU oracle (NumPy) on a bounded sample of the same workload, scaled.
 """
 from __future__ import annotations
@@ -41,8 +47,9 @@ DEPTH, NPTS, SEED = 4, 1 << 20, 1
 COPY_BYTES = 256 << 20  # plain copy used to calibrate the FETCH_SIZE / WRITE_SIZE counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_kernel_laplace_p8_f64_traffic.txt")
 # sources that decide the M2L kernel's memory traffic at the headline configuration
-TRAFFIC_SOURCES = ["paper_2305_17867_amd/csrc/m2l.hip", "paper_2305_17867_amd/csrc/kernels.hpp",
-                   "paper_2305_17867_amd/csrc/capi.cpp", "paper_2305_17867_amd/m2l_tuned.json"]
+TRAFFIC_SOURCES = ["paper_2305_17867_amd/csrc/m2l_stream.hip", "paper_2305_17867_amd/csrc/m2l.hip",
+                   "paper_2305_17867_amd/csrc/kernels.hpp", "paper_2305_17867_amd/csrc/capi.cpp",
+                   "paper_2305_17867_amd/m2l_tuned.json"]
 
 
 def sources_hash() -> str:
@@ -194,61 +201,216 @@ def time_kernel(torch, fn, reps=20):
     return float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
 
 
-def cpu_baseline(tr, w, t, s, p=8, budget_s=12.0):
-    """The FP64 oracle on a bounded sample: P2M and L2P of sampled leaves and the full M2L of
-    sampled target boxes (all their pairs), each rate scaled to the whole workload."""
-    import resource
+class Checks:
+    """Sampled GPU outputs, each waiting for the FP64 reference it is compared with.  The
+    references are computed in the CPU-baseline leg (the only part of this script that runs the
+    oracle), after all GPU work; a reference shared by several results (one leaf's potential for
+    FP64 and FP32) is computed once."""
+
+    def __init__(self):
+        self.items = []
+
+    def add(self, where, key, got, ref_key, ref_fn, sample, orders=None):
+        """where[key] receives {"rel_error", "max_rel_error", "sample"} (and, given the total
+        order of every coefficient, "worst_order_rel_error": the largest normwise error over the
+        coefficients of one derivative order, which the highest orders cannot hide)."""
+        where[key] = None
+        self.items.append((where, key, np.asarray(got), ref_key, ref_fn, sample, orders))
+
+    def resolve(self):
+        cache = {}
+        for where, key, got, ref_key, ref_fn, sample, orders in self.items:
+            if ref_key not in cache:
+                cache[ref_key] = np.asarray(ref_fn())
+            ref = cache[ref_key].reshape(got.shape)
+            nref = float(np.linalg.norm(ref.ravel()))
+            res = {"rel_error": float(np.linalg.norm((got - ref).ravel())) / nref,
+                   "max_rel_error": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))), "sample": sample}
+            if orders is not None:
+                o = np.asarray(orders)
+                res["worst_order_rel_error"] = max(
+                    float(np.linalg.norm((got - ref)[..., o == n]) / np.linalg.norm(ref[..., o == n]))
+                    for n in np.unique(o))
+            where[key] = res
+
+
+def ref_far_potential(kernel, param, p, tr, w, t, s, leaf):
+    """Oracle (FP64): the far-field potential at the points of target box `leaf` from its
+    List-2 sources: compressed P2M of each source box, M2L by the pair's translation vector,
+    L2P at the points (Secs. 3.3, 3.4, 4.1)."""
     from oracle import compressed as Z
+    theta = 0.0
+    for sb in s[t == leaf]:
+        lo, hi = tr.pt_range[sb]
+        beta = Z.p2m(kernel, param, p, tr.center[sb], tr.points[lo:hi], w[lo:hi])
+        theta = theta + Z.m2l(kernel, param, p, tr.center[leaf] - tr.center[sb], beta)
+    lo, hi = tr.pt_range[leaf]
+    return Z.l2p(kernel, param, p, tr.center[leaf], theta, tr.points[lo:hi])
+
+
+def ref_m2l_box(kernel, param, p, tr, t, s, beta_lib, target, index_table):
+    """Oracle (FP64): the scaled local theta~ of box `target` (library coefficient order) from
+    the scaled multipoles beta_lib [n_box][Nc] of its List-2 sources, theta~_i =
+    sum_q G^(i+q)(d) h^|i+q| beta~_q with h the side of the target's level (Sec. 4.1, eq.
+    m2l_toeplitz, scaled as in Sec. 4.1.1)."""
+    from oracle import compressed as Z
+    from oracle import multiindex as MI
+    J = Z.kept(kernel, param, p)
+    pos = {m: k for k, m in enumerate(J)}
+    perm = np.array([pos[tuple(int(v) for v in r)] for r in index_table])
+    keys = [MI.madd(i, q) for i in J for q in J]
+    h = tr.box_size(int(tr.level[target]))
+    hp = np.array([h ** sum(k) for k in keys])
+    nc = len(J)
+    theta = np.zeros(nc, dtype=np.complex128 if kernel == "helmholtz" else np.float64)
+    for sb in s[t == target]:
+        tab = Z.slab_table(kernel, param, p, (tr.ijk[target] - tr.ijk[sb]) * h)
+        T = (np.array([tab[k] for k in keys]) * hp).reshape(nc, nc)
+        beta = np.empty(nc, dtype=theta.dtype)
+        beta[perm] = beta_lib[sb]
+        theta += T @ beta
+    return theta[perm]
+
+
+def ancestors(tr, box):
+    """The box and its ancestors on levels >= 2 of a uniform octree."""
+    lev = int(tr.level[box])
+    out = []
+    for l in range(2, lev + 1):
+        ids = tr.boxes_at(l)
+        want = tr.ijk[box] >> (lev - l)
+        out.append(int(ids[np.nonzero(np.all(tr.ijk[ids] == want, axis=1))[0][0]]))
+    return out
+
+
+def ref_far_direct(kernel, param, src_tree, tgt_tree, t, s, w, c, tgt_leaf, tgt_idx, src_leaf, src_idx):
+    """FP64 references for L = sum_x c(x) phi_far(x), phi_far the direct sum of eq. (1) over the
+    points of the far-field box pairs (t, s) (every level): phi_far and dL/dx at the targets
+    tgt_idx of leaf tgt_leaf, dL/dw and dL/dy at the sources src_idx of leaf src_leaf, by the
+    oracle's direct sum and its gradients (the limit of the far field as p grows).  The
+    source-side gradients use G(x - y) = G(y - x) and grad G(x - y) = -grad G(y - x)."""
+    from oracle import adjoint as A
+    from oracle import kernels as K
+    far_s = np.concatenate([np.arange(*src_tree.pt_range[b]) for b in s[np.isin(t, ancestors(tgt_tree, tgt_leaf))]])
+    far_t = np.concatenate([np.arange(*tgt_tree.pt_range[b]) for b in t[np.isin(s, ancestors(src_tree, src_leaf))]])
+    x = tgt_tree.points[tgt_idx]
+    y = src_tree.points[src_idx]
+    phi = K.direct_sum(kernel, param, src_tree.points[far_s], w[far_s], x)
+    dx = A.direct_gradients(kernel, param, src_tree.points[far_s], w[far_s], x, c[tgt_idx])[2]
+    dw = K.direct_sum(kernel, param, tgt_tree.points[far_t], c[far_t], y)
+    dy = A.direct_gradients(kernel, param, tgt_tree.points[far_t], c[far_t], y, w[src_idx])[2]
+    return {"phi": phi, "dx": dx, "dw": dw, "dy": dy}
+
+
+def cpu_baseline(tr, w, t, s, orders=((8, 64), (12, 24)), n_offsets=24, direct_shape=(4096, 4096), reps=3):
+    """The FP64 oracle's arithmetic on the host cores, Laplace at p = 8 and 12: compressed P2M
+    vectorised over the points of sampled leaves (the monomials (c - y)^q / q! of every point,
+    summed per box, then beta = M^T alpha), M2L as one batched matmul per translation offset over
+    every pair of that offset (tables cached per offset, not timed), L2P vectorised (L = M theta,
+    then the polynomial at every point), the uncompressed Taylor variants of the three, and the
+    direct sum of eq. (1) for a block of targets and sources.  Best of `reps` with
+    time.perf_counter, with the BLAS pool on every core the process may use and on one thread;
+    per-unit rates scaled to the whole workload.  A baseline only."""
+    from threadpoolctl import threadpool_limits
+    from oracle import compressed as Z
+    from oracle import compression as OC
+    from oracle import kernels as K
+    from oracle import multiindex as MI
+    from oracle import taylor as TY
+    cores = len(os.sched_getaffinity(0))
+    g = np.random.Generator(np.random.PCG64(0))
     leaves = tr.boxes_at(DEPTH)
     h = tr.box_size(DEPTH)
-    g = np.random.Generator(np.random.PCG64(0))
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    wall0 = time.perf_counter()
-    # P2M
-    n_p2m, t_p2m, pts_p2m = 0, 0.0, 0
-    betas = {}
-    while t_p2m < budget_s / 3:
-        b = int(g.choice(leaves))
-        lo, hi = tr.pt_range[b]
-        a = time.perf_counter()
-        betas[b] = Z.scale_multipole("laplace", 0.0, p, Z.p2m("laplace", 0.0, p, tr.center[b], tr.points[lo:hi],
-                                                                w[lo:hi]), 1 / h)
-        t_p2m += time.perf_counter() - a
-        n_p2m += 1
-        pts_p2m += hi - lo
-    # M2L: whole target boxes
-    n_pairs_done, t_m2l = 0, 0.0
-    beta_any = next(iter(betas.values()))
-    while t_m2l < budget_s / 3:
-        tb = int(g.choice(leaves))
-        sel = np.nonzero(t == tb)[0]
-        a = time.perf_counter()
-        acc = np.zeros_like(beta_any)
-        for k in sel:
-            d = (tr.center[tb] - tr.center[s[k]])
-            acc = acc + Z.m2l("laplace", 0.0, p, d, beta_any)
-        t_m2l += time.perf_counter() - a
-        n_pairs_done += len(sel)
-    # L2P
-    n_l2p, t_l2p, pts_l2p = 0, 0.0, 0
-    while t_l2p < budget_s / 3:
-        b = int(g.choice(leaves))
-        lo, hi = tr.pt_range[b]
-        a = time.perf_counter()
-        Z.l2p("laplace", 0.0, p, tr.center[b], beta_any, tr.points[lo:hi])
-        t_l2p += time.perf_counter() - a
-        pts_l2p += hi - lo
-    wall = time.perf_counter() - wall0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    full = (t_p2m / pts_p2m) * NPTS + (t_m2l / n_pairs_done) * len(t) + (t_l2p / pts_l2p) * NPTS
-    return {"value": len(t) / full, "unit": "box-pairs/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle",
-            "sample": (f"Laplace p={p} FP64 oracle: P2M of {n_p2m} leaves ({pts_p2m} pts), M2L of "
-                       f"{n_pairs_done} pairs (whole target boxes), L2P of {pts_l2p} pts; per-unit times "
-                       f"scaled to {NPTS} pts and {len(t)} pairs"),
-            "p2m_pts_per_s": pts_p2m / t_p2m, "m2l_pairs_per_s": n_pairs_done / t_m2l,
-            "l2p_pts_per_s": pts_l2p / t_l2p}
+    off = tr.ijk[t] - tr.ijk[s]
+    uo, inv = np.unique(off, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    osel = np.sort(g.choice(len(uo), min(n_offsets, len(uo)), replace=False))
+    tgt_d = tr.points[np.sort(g.choice(NPTS, direct_shape[0], replace=False))]
+    src_i = np.sort(g.choice(NPTS, direct_shape[1], replace=False))
+    src_d, w_d = tr.points[src_i], w[src_i]
+
+    def best(fn, *a):
+        ts_ = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn(*a)
+            ts_.append(time.perf_counter() - t0)
+        return min(ts_)
+
+    def one_order(p, n_leaf_sample):
+        samp = np.sort(g.choice(leaves, n_leaf_sample, replace=False))
+        M = OC.decompression_matrix("laplace", 0.0, p)[0]          # [N(p)][Nc]
+        full = list(MI.graded_order(p))
+        fact = np.array([float(MI.mfact(q)) for q in full])
+        cnt = np.array([tr.pt_range[b][1] - tr.pt_range[b][0] for b in samp])
+        idx = np.concatenate([np.arange(*tr.pt_range[b]) for b in samp])
+        starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        box_of = np.repeat(np.arange(len(samp)), cnt)
+        pts, ws = tr.points[idx], w[idx]
+        groups = []
+        for o in osel:
+            sel = np.nonzero(inv == o)[0]
+            d = uo[o] * h
+            T = Z.m2l_matrix("laplace", 0.0, p, d)                        # compressed, [Nc][Nc]
+            tab = TY.full_table("laplace", 0.0, p, d)                      # every derivative to order 2p
+            Tf = np.array([[tab[MI.madd(i, q)] for q in full] for i in full])  # uncompressed, [N(p)][N(p)]
+            groups.append((t[sel], s[sel], T, Tf))
+        n_pairs_s = sum(len(gr[0]) for gr in groups)
+        beta = g.standard_normal((tr.n_box, M.shape[1]))
+        alpha = g.standard_normal((tr.n_box, M.shape[0]))
+        theta = g.standard_normal((len(samp), M.shape[1]))
+
+        def p2m(compressed):
+            v = tr.center[samp][box_of] - pts
+            a = np.stack([np.add.reduceat(ws * MI.mpow(v, q), starts) for q in full], axis=1) / fact
+            return a @ M if compressed else a
+
+        def m2l(compressed):
+            out = np.zeros((tr.n_box, M.shape[1] if compressed else M.shape[0]))
+            for tt, ss, T, Tf in groups:
+                np.add.at(out, tt, beta[ss] @ T.T if compressed else alpha[ss] @ Tf.T)
+            return out
+
+        def l2p(compressed):
+            L = (theta @ M.T if compressed else alpha[:len(samp)]) / fact
+            v = pts - tr.center[samp][box_of]
+            Lp = L[box_of]
+            phi = np.zeros(len(idx))
+            for k, q in enumerate(full):
+                phi += Lp[:, k] * MI.mpow(v, q)
+            return phi
+
+        res = {}
+        for label, nthreads in (("all_cores", cores), ("one_thread", 1)):
+            with threadpool_limits(limits=nthreads):
+                r = {}
+                for comp in (True, False):
+                    key = "compressed" if comp else "uncompressed"
+                    r[f"p2m_{key}_pts_per_s"] = len(idx) / best(p2m, comp)
+                    r[f"m2l_{key}_pairs_per_s"] = n_pairs_s / best(m2l, comp)
+                    r[f"l2p_{key}_pts_per_s"] = len(idx) / best(l2p, comp)
+                step = NPTS / r["p2m_compressed_pts_per_s"] + len(t) / r["m2l_compressed_pairs_per_s"] + \
+                    NPTS / r["l2p_compressed_pts_per_s"]
+                r["pairs_per_s"] = len(t) / step
+                res[label] = r
+        res["sample"] = (f"P2M and L2P of {len(samp)} random leaves ({len(idx)} points), M2L of {n_pairs_s} pairs "
+                         f"({len(groups)} of the {len(uo)} offsets, every pair of each)")
+        return res
+
+    per_p = {f"p{p}": one_order(p, n) for p, n in orders}
+    direct = {}
+    for label, nthreads in (("all_cores", cores), ("one_thread", 1)):
+        with threadpool_limits(limits=nthreads):
+            direct[label] = direct_shape[0] * direct_shape[1] / best(
+                lambda: K.direct_sum("laplace", 0.0, src_d, w_d, tgt_d))
+    head = per_p[f"p{orders[0][0]}"]
+    return {"value": head["all_cores"]["pairs_per_s"], "unit": "box-pairs/s", "cores": cores, "kind": "oracle",
+            "sample": (f"Laplace FP64, per order: {'; '.join(f'{k}: ' + v['sample'] for k, v in per_p.items())}; "
+                       f"tables cached per offset; direct sum {direct_shape[0]} targets x {direct_shape[1]} "
+                       f"sources; best of {reps}; value = the p = {orders[0][0]} step (P2M + M2L + L2P) with "
+                       f"rates scaled to {NPTS} points and {len(t)} pairs, all cores"),
+            "orders": {k: {kk: vv for kk, vv in v.items() if kk != "sample"} for k, v in per_p.items()},
+            "direct_interactions_per_s": direct}
 
 
 def translation_flops(p, c, rec_terms):
@@ -417,7 +579,7 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
             "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample}
 
 
-def mixed_batch(torch, fmm, reps=10):
+def mixed_batch(torch, fmm, checks, reps=10):
     """Yukawa (lambda = 2) + biharmonic far field of 524,288 Gaussian-mixture points (adaptive
     octree, <= 64 per leaf), orders 6/8/10 by level, FP32: one batch per (kernel, order), all
     drained by one persistent launch, captured in a HIP graph and replayed."""
@@ -425,7 +587,8 @@ def mixed_batch(torch, fmm, reps=10):
     tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
     lh = [tr.box_size(l) for l in range(tr.n_levels)]
     tuning = {"rows_per_wave": 2, "col_tiles_per_wave": 2, "col_groups": 1, "lds_buffers": 1}
-    batches, mps, flops, pairs = [], [], 0.0, 0
+    batches, mps, flops, pairs, meta = [], [], 0.0, 0, []
+    g = np.random.Generator(np.random.PCG64(SEED + 20))
     for kernel, param in (("yukawa", 2.0), ("biharmonic", 0.0)):
         for p in (6, 8, 10):
             levels = [l for l in range(2, tr.n_levels) if 6 + 2 * ((l - 2) % 3) == p]
@@ -435,9 +598,11 @@ def mixed_batch(torch, fmm, reps=10):
             d = fmm.Desc(kernel, p, "f32", param)
             plan = fmm.Plan(d, lh)
             batches.append(plan.prepare(t, s, tr.ijk, tr.level, tuning=tuning))
-            mps.append(torch.randn((tr.n_box, d.nc), dtype=torch.float32, device="cuda"))
+            beta = g.standard_normal((tr.n_box, d.nc)).astype(np.float32)
+            mps.append(torch.as_tensor(beta, device="cuda"))
             flops += 2.0 * d.nc ** 2 * len(t)
             pairs += len(t)
+            meta.append((kernel, param, p, t, s, beta, d.index_table(), int(g.choice(np.unique(t)))))
     locs = [torch.zeros_like(m) for m in mps]
     multi = fmm.Multi(batches)
     seq = time_kernel(torch, lambda: [b(m, l) for b, m, l in zip(batches, mps, locs)], reps)
@@ -455,26 +620,68 @@ def mixed_batch(torch, fmm, reps=10):
            "batches": len(batches), "pairs": pairs, "gflop": flops / 1e9,
            "sequential_ms": seq * 1e3, "persistent_ms": one * 1e3, "graph_replay_ms": replay * 1e3,
            "pairs_per_s": pairs / replay, "tflops": flops / replay / 1e12,
-           "frac": flops / replay / PEAK["f32"]}
+           "frac": flops / replay / PEAK["f32"], "errors": []}
+    # one replay from zero locals: the theta~ of one random target box per batch against the oracle
+    for l in locs:
+        l.zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    for (kernel, param, p, t, s, beta, itab, box), l in zip(meta, locs):
+        row = {"kernel": kernel, "order": p}
+        out["errors"].append(row)
+        checks.add(row, "error_vs_oracle", l[box].cpu().double().numpy(), ("mixed", kernel, p, box),
+                   lambda kernel=kernel, param=param, p=p, t=t, s=s, beta=beta, box=box, itab=itab:
+                   ref_m2l_box(kernel, param, p, tr, t, s, beta.astype(np.float64), box, itab),
+                   f"theta~ of target box {box} (level {int(tr.level[box])}, {int((t == box).sum())} pairs), "
+                   "N(0,1) multipoles", orders=itab.sum(axis=1))
     del graph
     multi.close()
     return out
 
 
-def plummer_helmholtz(torch, fmm, dt, reps=5):
+_PLUMMER = {}
+
+
+def plummer_tree():
+    """2^21 Plummer points (scale 0.1) on their adaptive octree (<= 64 per leaf), built once."""
+    import workloads as W
+    if "tr" not in _PLUMMER:
+        _PLUMMER["tr"] = W.adaptive_tree(W.plummer_points(1 << 21, 3, 0.1), 64)
+    return _PLUMMER["tr"]
+
+
+def plummer_helmholtz(torch, fmm, dt, checks, reps=5):
     """Helmholtz p = 12 far field of 2^21 Plummer points (adaptive octree <= 64 per leaf,
     k = 1 / largest leaf side): every level's List-2 pairs in one prepared batch, one launch."""
     import workloads as W
-    tr = W.adaptive_tree(W.plummer_points(1 << 21, 3, 0.1), 64)
+    tr = plummer_tree()
     leaf_side = max(tr.box_size(int(tr.level[b])) for b in np.nonzero(tr.is_leaf)[0])
+    k = 1.0 / leaf_side
     t, s = W.interaction_pairs(tr, list(range(2, tr.n_levels)))
-    d = fmm.Desc("helmholtz", 12, dt, 1.0 / leaf_side)
+    d = fmm.Desc("helmholtz", 12, dt, k)
     plan = fmm.Plan(d, [tr.box_size(l) for l in range(tr.n_levels)])
     batch = plan.prepare(t, s, tr.ijk, tr.level)
-    mp = torch.randn((tr.n_box, d.nc), dtype=d.value_dtype, device="cuda")
+    g = np.random.Generator(np.random.PCG64(SEED + 21))
+    beta = (g.standard_normal((tr.n_box, d.nc)) + 1j * g.standard_normal((tr.n_box, d.nc))) / np.sqrt(2.0)
+    if dt == "c64":
+        beta = beta.astype(np.complex64)
+    mp = torch.as_tensor(beta, device="cuda")
     loc = torch.zeros_like(mp)
     sec = time_kernel(torch, lambda: batch(mp, loc), reps)
     flops = 8.0 * d.nc ** 2 * len(t)
+    # one launch from zero locals: theta~ of a random target box on the deepest level with pairs
+    loc.zero_()
+    batch(mp, loc)
+    lev_t = tr.level[t]
+    box = int(g.choice(np.unique(t[lev_t == lev_t.max()])))
+    out = {"workload": "plummer 2097152 pts, adaptive <=64, helmholtz p12 k*h_leaf=1, all levels one launch",
+           "dtype": dt, "pairs": int(len(t)), "m2l_ms": sec * 1e3, "pairs_per_s": len(t) / sec,
+           "tflops": flops / sec / 1e12, "frac": flops / sec / PEAK["f64" if dt == "c128" else "f32"]}
+    itab = d.index_table()
+    checks.add(out, "error_vs_oracle", loc[box].cpu().to(torch.complex128).numpy(), ("c3", box),
+               lambda: ref_m2l_box("helmholtz", k, 12, tr, t, s, beta.astype(np.complex128), box, itab),
+               f"theta~ of target box {box} (level {int(tr.level[box])}, {int((t == box).sum())} pairs), "
+               "complex N(0,1) multipoles (one draw, rounded to the variant's type)", orders=itab.sum(axis=1))
     batch.close()
     # the FFT form of the same M2L (None where its working set exceeds a workgroup's LDS)
     try:
@@ -484,10 +691,8 @@ def plummer_helmholtz(torch, fmm, dt, reps=5):
     else:
         fft_ms = time_kernel(torch, lambda: fft(mp, loc), reps) * 1e3
         fft.close()
-    return {"workload": "plummer 2097152 pts, adaptive <=64, helmholtz p12 k*h_leaf=1, all levels one launch",
-            "dtype": dt, "pairs": int(len(t)), "m2l_ms": sec * 1e3, "pairs_per_s": len(t) / sec,
-            "tflops": flops / sec / 1e12, "frac": flops / sec / PEAK["f64" if dt == "c128" else "f32"],
-            "m2l_fft_ms": fft_ms}
+    out["m2l_fft_ms"] = fft_ms
+    return out
 
 
 def plummer_helmholtz_fmm(torch, fmm, reps=3, sample=256):
@@ -498,7 +703,7 @@ def plummer_helmholtz_fmm(torch, fmm, reps=3, sample=256):
     import workloads as W
     from paper_2305_17867_amd.farfield import FarField
     dev = "cuda"
-    tr = W.adaptive_tree(W.plummer_points(1 << 21, 3, 0.1), 64)
+    tr = plummer_tree()
     leaf_side = max(tr.box_size(int(tr.level[b])) for b in np.nonzero(tr.is_leaf)[0])
     k = 1.0 / leaf_side
     w = W.normal_weights(tr.points.shape[0], SEED + 11, complex_=True)
@@ -535,21 +740,30 @@ def plummer_helmholtz_fmm(torch, fmm, reps=3, sample=256):
             "rel_error_vs_direct": err, "error_sample": sample}
 
 
-def gradient_pass(torch, dt, reps=10, tree_pass=False):
+_GRAD = {}
+
+
+def gradient_pass(torch, dt, checks, reps=10, tree_pass=False, n_sample=16):
     """Laplace p = 10 far field of 2^21 sources at 2^21 targets (depth-4 octrees) and its
     adjoint: forward and forward + backward times (per level, or as a tree pass with M2M and
-    L2L)."""
+    L2L); phi and the gradients of L = sum c(x) phi(x) with respect to w, the source positions
+    and the target positions at sampled points, against the FP64 direct sum over the far-field
+    pairs."""
     import workloads as W
     from paper_2305_17867_amd.farfield import FarField
     n = 1 << 21
-    ts = W.uniform_tree(W.uniform_points(n, 5), 4)
-    tt = W.uniform_tree(W.uniform_points(n, 6), 4)
+    if "ts" not in _GRAD:
+        _GRAD["ts"] = W.uniform_tree(W.uniform_points(n, 5), 4)
+        _GRAD["tt"] = W.uniform_tree(W.uniform_points(n, 6), 4)
+        _GRAD["w"] = W.normal_weights(n, 7)
+        _GRAD["c"] = W.normal_weights(n, 8)
+    ts, tt, w_h, c_h = _GRAD["ts"], _GRAD["tt"], _GRAD["w"], _GRAD["c"]
     ff = FarField("laplace", 10, dt, ts, tt, tree_pass=tree_pass)
     tdt = torch.float64 if dt == "f64" else torch.float32
-    w = torch.as_tensor(W.normal_weights(n, 7), dtype=tdt, device="cuda").requires_grad_(True)
+    w = torch.as_tensor(w_h, dtype=tdt, device="cuda").requires_grad_(True)
     S = torch.as_tensor(ts.points, dtype=tdt, device="cuda").requires_grad_(True)
     T = torch.as_tensor(tt.points, dtype=tdt, device="cuda").requires_grad_(True)
-    c = torch.as_tensor(W.normal_weights(n, 8), dtype=tdt, device="cuda")
+    c = torch.as_tensor(c_h, dtype=tdt, device="cuda")
 
     def fwd():
         with torch.no_grad():
@@ -562,9 +776,39 @@ def gradient_pass(torch, dt, reps=10, tree_pass=False):
     # existing gradients); keep them out of the timed passes
     for _ in range(2):
         fwd_bwd()
-    return {"workload": "uniform 2^21 sources + 2^21 targets, depth 4, laplace p10, far field",
-            "form": "tree pass (M2M / L2L)" if tree_pass else "per level (P2M / L2P at every level)", "dtype": dt,
-            "forward_ms": time_kernel(torch, fwd, reps) * 1e3, "forward_backward_ms": time_kernel(torch, fwd_bwd, reps) * 1e3}
+    out = {"workload": "uniform 2^21 sources + 2^21 targets, depth 4, laplace p10, far field",
+           "form": "tree pass (M2M / L2L)" if tree_pass else "per level (P2M / L2P at every level)", "dtype": dt,
+           "forward_ms": time_kernel(torch, fwd, reps) * 1e3, "forward_backward_ms": time_kernel(torch, fwd_bwd, reps) * 1e3}
+    # one clean pass, then the sampled values
+    for v in (w, S, T):
+        v.grad = None
+    phi = ff.apply(w, S, T)
+    (phi * c).sum().backward()
+    g = np.random.Generator(np.random.PCG64(SEED + 22))
+    leaves = ts.boxes_at(4)
+    tl, sl = int(g.choice(leaves)), int(g.choice(leaves))
+    ti = np.sort(g.choice(np.arange(*tt.pt_range[tl]), n_sample, replace=False))
+    si = np.sort(g.choice(np.arange(*ts.pt_range[sl]), n_sample, replace=False))
+    got = {"phi": phi.detach()[ti], "dx": T.grad[ti], "dw": w.grad[si], "dy": S.grad[si]}
+    t_all, s_all = W.interaction_pairs(ts, list(range(2, ts.n_levels)))
+    key = ("c5", tl, sl)
+    ref = lambda: ref_far_direct("laplace", 0.0, ts, tt, t_all, s_all, w_h, c_h, tl, ti, sl, si)
+    sample = (f"{n_sample} targets of leaf {tl} (phi, dL/dx) and {n_sample} sources of leaf {sl} (dL/dw, "
+              "dL/dy); reference: FP64 direct sum over the far-field box pairs of every level")
+    for name, v in got.items():
+        checks.add(out, f"{name}_error_vs_direct", v.detach().cpu().double().numpy(), key + (name,),
+                   lambda name=name: ref_cached(key, ref)[name], sample)
+    return out
+
+
+_REF = {}
+
+
+def ref_cached(key, fn):
+    """One computation of a reference dict shared by several checks."""
+    if key not in _REF:
+        _REF[key] = fn()
+    return _REF[key]
 
 
 def main():
@@ -580,10 +824,10 @@ def main():
                     help="also time the complete FMM potential when --only or --no-extras is given")
     ap.add_argument("--translations", action="store_true",
                     help="also time M2M / L2L when --only or --no-extras is given")
-    ap.add_argument("--extended", action="store_true",
-                    help="also time the Plummer Helmholtz launch and the far-field gradient pass")
+    ap.add_argument("--plummer", action="store_true",
+                    help="also time the Plummer Helmholtz launch and FMM when --only or --no-extras is given")
     ap.add_argument("--gradient", action="store_true",
-                    help="also time the far-field gradient pass (part of --extended)")
+                    help="also time the far-field gradient pass when --only or --no-extras is given")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, to calibrate HBM counters")
     args = ap.parse_args()
@@ -597,6 +841,8 @@ def main():
 
     log("building workload")
     tr, w, t, s = build_workload()
+    checks = Checks()
+    err_leaf = int(np.random.Generator(np.random.PCG64(SEED + 23)).choice(tr.boxes_at(DEPTH)))
     variants = [("f64", 8), ("f32", 8), ("f64", 12), ("f32", 12)]
     if args.only:
         dt, p = args.only.split(":")
@@ -610,6 +856,7 @@ def main():
         log(f"variant {dt} p={p}: time {args.steps} steps")
         sec = time_step(torch, case, args.steps, args.warmup, graph=False)
         sec_graph = time_step(torch, case, args.steps, 1, graph=True)
+        pot_leaf = case.pot[slice(*tr.pt_range[err_leaf])].cpu().double().numpy()
         t_p2m = time_kernel(torch, case.p2m)
         t_m2l = time_kernel(torch, case.m2l)
         t_l2p = time_kernel(torch, case.l2p)
@@ -632,6 +879,10 @@ def main():
             "m2l_fft_ms": None if t_fft is None else t_fft * 1e3,
             "m2l_batch": case.info,
         })
+        checks.add(results[-1], "error_vs_oracle", pot_leaf, ("c2", p),
+                   lambda p=p: ref_far_potential("laplace", 0.0, p, tr, w, t, s, err_leaf),
+                   f"potential at the {len(pot_leaf)} points of leaf {err_leaf} after one step "
+                   f"({int((t == err_leaf).sum())} List-2 sources)")
         log(json.dumps(results[-1]))
         del case
         torch.cuda.empty_cache()
@@ -646,7 +897,7 @@ def main():
                    "m2l_level": DEPTH, "m2l_pairs": len(t), "offsets": 316},
         "p2m_pts_per_s": head["p2m_pts_per_s"], "m2l_pairs_per_s": head["m2l_pairs_per_s"],
         "l2p_pts_per_s": head["l2p_pts_per_s"],
-        "roofline": {"bound": "mfma", "kernel": "m2l_kernel",
+        "roofline": {"bound": "mfma", "kernel": "m2l_stream_kernel" if head["m2l_batch"].get("stream_form") else "m2l_kernel",
                      "achieved": head["m2l_tflops"], "peak": PEAK[head["dtype"]] / 1e12, "unit": "TFLOP/s",
                      "frac": head["m2l_frac"], "traffic": recorded_traffic(),
                      "algorithmic": f"2*Nc^2 FLOP per pair, Nc={head['nc']}, {len(t)} pairs per launch"},
@@ -662,15 +913,18 @@ def main():
         out["full_fmm_adaptive"] = full_fmm_adaptive(torch, fmm)
     if not (args.only or args.no_extras):
         log("mixed workload (persistent, graph-captured launch)")
-        out["mixed_batch"] = mixed_batch(torch, fmm)
-    if args.extended:
+        out["mixed_batch"] = mixed_batch(torch, fmm, checks)
+    if args.plummer or not (args.only or args.no_extras):
         log("Plummer Helmholtz, one launch over all levels")
-        out["plummer_helmholtz"] = [plummer_helmholtz(torch, fmm, dt) for dt in ("c128", "c64")]
+        out["plummer_helmholtz"] = [plummer_helmholtz(torch, fmm, dt, checks) for dt in ("c128", "c64")]
         log("Plummer Helmholtz, complete FMM (tree pass + near field)")
         out["plummer_helmholtz_fmm"] = plummer_helmholtz_fmm(torch, fmm)
-    if args.extended or args.gradient:
+        torch.cuda.empty_cache()
+    if args.gradient or not (args.only or args.no_extras):
         log("far-field gradient pass")
-        out["gradient"] = [gradient_pass(torch, dt, tree_pass=tp) for tp in (False, True) for dt in ("f32", "f64")]
+        out["gradient"] = [gradient_pass(torch, dt, checks, tree_pass=tp) for tp in (False, True)
+                           for dt in ("f32", "f64")]
+        torch.cuda.empty_cache()
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -681,6 +935,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(tr, w, t, s)
+        log(f"FP64 references for {len(checks.items)} sampled results (oracle)")
+        checks.resolve()
     print(json.dumps(out), flush=True)
 
 

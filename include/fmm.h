@@ -10,9 +10,10 @@
  * buffer it passes; the library never frees or retains caller memory.  Launch
  * entry points enqueue kernels on `stream` (a hipStream_t passed as void*,
  * NULL = the default stream), return at once, never allocate device memory and
- * never synchronise, so they may be captured into a HIP graph.  Only
- * fmm_plan_create, fmm_m2l_prepare and fmm_batch_destroy / fmm_plan_destroy
- * allocate, free or synchronise.
+ * never synchronise, so they may be captured into a HIP graph.  The set-up and
+ * tear-down calls allocate, free or synchronise: fmm_plan_create, the
+ * fmm_m2l_prepare* calls (_ex, _fft, _adjoint), fmm_m2l_multi_prepare and the
+ * fmm_*_destroy calls.
  *
  * Every entry point returns an fmm_status.  Arguments are validated on the host
  * before anything is enqueued; on a non-OK status nothing was enqueued and
@@ -286,9 +287,10 @@ int fmm_m2l_batched_static(fmm_batch batch, const void* mpole, void* local, void
  * workgroups per launch. */
 int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
 
-/* Batched M2L: local[t] += sum over pairs (t, s) of T(c_t - c_s) mpole[s], T[i,q] =
- * G^(i+q) in the scaled form.  mpole [n_box][Nc] dtype; local [n_box][Nc] dtype,
- * ACCUMULATED.  Deterministic: every output is summed in a fixed order. */
+/* Batched M2L (Sec. 4.1, eq. m2l_toeplitz, in the scaled form of Sec. 4.1.1): local[t] +=
+ * sum over pairs (t, s) of T(c_t - c_s) mpole[s], T[i,q] = G^(i+q) h^|i+q| for i, q in J.
+ * mpole [n_box][Nc] dtype; local [n_box][Nc] dtype, ACCUMULATED.  Deterministic: every output
+ * is summed in a fixed order. */
 int fmm_m2l_batched(fmm_batch batch, const void* mpole, void* local, void* stream);
 
 /* Several prepared batches launched one after another on `stream` (same dtype).  batches,
