@@ -581,13 +581,15 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
 
 def mixed_batch(torch, fmm, checks, reps=10):
     """Yukawa (lambda = 2) + biharmonic far field of 524,288 Gaussian-mixture points (adaptive
-    octree, <= 64 per leaf), orders 6/8/10 by level, FP32: one batch per (kernel, order), all
-    drained by one persistent launch, captured in a HIP graph and replayed."""
+    octree, <= 64 per leaf), orders 6/8/10 by level, FP32: one batch per (kernel, order), each in
+    the launch shape the autotuner chose for it, enqueued as one multi launch, captured in a HIP
+    graph and replayed.  Per batch: its shape, launch time and pairs/s.  Beside it, the six
+    batches in one shared tiled shape drained by a single persistent launch."""
     import workloads as W
     tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
     lh = [tr.box_size(l) for l in range(tr.n_levels)]
-    tuning = {"rows_per_wave": 2, "col_tiles_per_wave": 2, "col_groups": 1, "lds_buffers": 1}
-    batches, mps, flops, pairs, meta = [], [], 0.0, 0, []
+    shared = {"rows_per_wave": 2, "col_tiles_per_wave": 2, "col_groups": 1, "lds_buffers": 1}
+    batches, tiled, mps, flops, pairs, meta, per = [], [], [], 0.0, 0, [], []
     g = np.random.Generator(np.random.PCG64(SEED + 20))
     for kernel, param in (("yukawa", 2.0), ("biharmonic", 0.0)):
         for p in (6, 8, 10):
@@ -597,15 +599,27 @@ def mixed_batch(torch, fmm, checks, reps=10):
                 continue
             d = fmm.Desc(kernel, p, "f32", param)
             plan = fmm.Plan(d, lh)
-            batches.append(plan.prepare(t, s, tr.ijk, tr.level, tuning=tuning))
+            tuned = fmm.tuned_m2l_shape(kernel, p, "f32")
+            batches.append(plan.prepare(t, s, tr.ijk, tr.level))
+            tiled.append(plan.prepare(t, s, tr.ijk, tr.level, tuning=shared))
             beta = g.standard_normal((tr.n_box, d.nc)).astype(np.float32)
             mps.append(torch.as_tensor(beta, device="cuda"))
             flops += 2.0 * d.nc ** 2 * len(t)
             pairs += len(t)
             meta.append((kernel, param, p, t, s, beta, d.index_table(), int(g.choice(np.unique(t)))))
+            info = batches[-1].info()
+            per.append({"kernel": kernel, "order": p, "levels": levels, "nc": d.nc, "pairs": int(len(t)),
+                        "tuning": tuned or "library",
+                        "shape": {"form": "stream" if info["stream_form"] else "tiled", "waves": info["waves"],
+                                  "workgroups": info["workgroups"] if info["stream_form"] else info["n_items"]}})
     locs = [torch.zeros_like(m) for m in mps]
-    multi = fmm.Multi(batches)
+    for row, b, m, l in zip(per, batches, mps, locs):
+        sec = time_kernel(torch, lambda: b(m, l), reps)
+        row["ms"] = sec * 1e3
+        row["pairs_per_s"] = row["pairs"] / sec
+        row["tflops"] = 2.0 * row["nc"] ** 2 * row["pairs"] / sec / 1e12
     seq = time_kernel(torch, lambda: [b(m, l) for b, m, l in zip(batches, mps, locs)], reps)
+    multi = fmm.Multi(batches)
     one = time_kernel(torch, lambda: multi(mps, locs), reps)
     graph = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
@@ -616,19 +630,23 @@ def mixed_batch(torch, fmm, checks, reps=10):
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     replay = time_kernel(torch, graph.replay, reps)
+    shared_multi = fmm.Multi(tiled)
+    persistent = time_kernel(torch, lambda: shared_multi(mps, locs), reps)
+    shared_multi.close()
+    for b in tiled:
+        b.close()
     out = {"workload": "mixture 524288 pts, adaptive <=64, yukawa+biharmonic p 6/8/10 by level, f32",
            "batches": len(batches), "pairs": pairs, "gflop": flops / 1e9,
-           "sequential_ms": seq * 1e3, "persistent_ms": one * 1e3, "graph_replay_ms": replay * 1e3,
+           "sequential_ms": seq * 1e3, "multi_ms": one * 1e3, "graph_replay_ms": replay * 1e3,
            "pairs_per_s": pairs / replay, "tflops": flops / replay / 1e12,
-           "frac": flops / replay / PEAK["f32"], "errors": []}
+           "frac": flops / replay / PEAK["f32"], "one_shared_shape_persistent_ms": persistent * 1e3,
+           "per_batch": per}
     # one replay from zero locals: the theta~ of one random target box per batch against the oracle
     for l in locs:
         l.zero_()
     graph.replay()
     torch.cuda.synchronize()
-    for (kernel, param, p, t, s, beta, itab, box), l in zip(meta, locs):
-        row = {"kernel": kernel, "order": p}
-        out["errors"].append(row)
+    for (kernel, param, p, t, s, beta, itab, box), l, row in zip(meta, locs, per):
         checks.add(row, "error_vs_oracle", l[box].cpu().double().numpy(), ("mixed", kernel, p, box),
                    lambda kernel=kernel, param=param, p=p, t=t, s=s, beta=beta, box=box, itab=itab:
                    ref_m2l_box(kernel, param, p, tr, t, s, beta.astype(np.float64), box, itab),

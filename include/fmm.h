@@ -298,15 +298,22 @@ int fmm_m2l_batched(fmm_batch batch, const void* mpole, void* local, void* strea
 int fmm_m2l_batched_multi(int32_t n, const fmm_batch* batches, const void* const* mpole,
                           void* const* local, void* stream);
 
-/* One persistent launch that drains the work of up to 32 prepared batches (kernels, orders,
- * levels and interaction lists may differ; the batches must share the dtype and the launch
- * shape, i.e. be prepared with one fmm_m2l_tuning; each batch at most once).  Work items of all batches are ordered by
- * decreasing cost and taken round-robin by a grid of at most twice the compute units; the
- * workgroup has the largest wavefront count of the batches.  Allocates (not capturable). */
+/* Up to 32 prepared forward batches of one dtype (kernels, orders, levels and interaction lists
+ * may differ; each batch at most once) enqueued by one call, each keeping its own launch shape
+ * (the batching of uneven lists and mixed orders of Sec. 5's workloads, as one capturable unit):
+ *   - a streaming-form batch runs its own launch, in the wavefront count and workgroup count it
+ *     was prepared with (its instantiation is specific to its kernel and order);
+ *   - tiled-form batches that share a tile shape (rows and column tiles per wavefront, LDS
+ *     buffers) are drained by one persistent launch: work items of all of them ordered by
+ *     decreasing cost and taken round-robin by a grid of at most twice the compute units, the
+ *     workgroup sized for the largest wavefront count.
+ * Launches are enqueued in the order of the batches' first appearance.  Allocates (not
+ * capturable). */
 int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* multi);
 
-/* Enqueue the persistent launch: local[k] += M2L_k(mpole[k]) for every batch k.  mpole, local:
- * [host] arrays of the batches' device coefficient arrays.  Allocates nothing; capturable. */
+/* Enqueue the launches: local[k] += M2L_k(mpole[k]) for every batch k.  mpole, local: [host]
+ * arrays of the batches' device coefficient arrays.  Results are bit-identical to
+ * fmm_m2l_batched of each batch.  Allocates nothing; capturable. */
 int fmm_m2l_multi_launch(fmm_multi multi, const void* const* mpole, void* const* local, void* stream);
 void fmm_m2l_multi_destroy(fmm_multi multi);
 

@@ -117,30 +117,71 @@ def tune(plan: "fmm.Plan", tgt_box, src_box, box_ijk, box_level, reps: int = 5,
     return out
 
 
-def write_table(path: str = TABLE, cases=((8, "f64"), (8, "f32"), (12, "f64"), (12, "f32")), reps: int = 5,
-                log=print) -> dict:
-    """Tune the Laplace M2L of the uniform workload (2^20 random points in the unit cube,
-    octree depth 4, all List-2 pairs of level 4) for each (order, dtype) and write the launch
-    shape table read by fmm.tuned_m2l_shape()."""
-    import workloads as W
-    pts = W.uniform_points(1 << 20, 1)
-    tr = W.uniform_tree(pts, 4)
-    t, s = W.interaction_pairs(tr, [4])
-    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+def _merge(path: str, entries: dict) -> dict:
     table = {}
-    for p, dt in cases:
-        plan = fmm.Plan(fmm.Desc("laplace", p, dt), lh)
-        r = tune(plan, t, s, tr.ijk, tr.level, reps=reps, cache=None)
-        log(f"laplace p={p} {dt}: {r['ms']:.4f} ms {r['tuning']} ({len(r['results'])} candidates, "
-            f"{r['seconds']:.0f} s)")
-        table[f"laplace|p{p}|{dt}"] = {"tuning": r["tuning"], "ms": round(r["ms"], 4), "pairs": int(len(t)),
-                                       "device": torch.cuda.get_device_name(0), "hip": torch.version.hip,
-                                       "workload": "uniform 2^20 points, depth 4, level-4 List-2 pairs"}
-        plan.close()
+    if os.path.exists(path):
+        try:
+            with open(path) as fh:
+                table = json.load(fh)
+        except (OSError, ValueError):
+            table = {}
+    table.update(entries)
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return table
 
 
+def _entry(r, n_pair, workload):
+    return {"tuning": r["tuning"], "ms": round(r["ms"], 4), "pairs": int(n_pair),
+            "device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "workload": workload}
+
+
+def write_table(path: str = TABLE, cases=((8, "f64"), (8, "f32"), (12, "f64"), (12, "f32")), reps: int = 5,
+                log=print) -> dict:
+    """Tune the Laplace M2L of the uniform workload (2^20 random points in the unit cube,
+    octree depth 4, all List-2 pairs of level 4) for each (order, dtype) and add the launch
+    shapes to the table read by fmm.tuned_m2l_shape()."""
+    import workloads as W
+    pts = W.uniform_points(1 << 20, 1)
+    tr = W.uniform_tree(pts, 4)
+    t, s = W.interaction_pairs(tr, [4])
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    entries = {}
+    for p, dt in cases:
+        plan = fmm.Plan(fmm.Desc("laplace", p, dt), lh)
+        r = tune(plan, t, s, tr.ijk, tr.level, reps=reps, cache=None)
+        log(f"laplace p={p} {dt}: {r['ms']:.4f} ms {r['tuning']} ({len(r['results'])} candidates, "
+            f"{r['seconds']:.0f} s)")
+        entries[f"laplace|p{p}|{dt}"] = _entry(r, len(t), "uniform 2^20 points, depth 4, level-4 List-2 pairs")
+        plan.close()
+    return _merge(path, entries)
+
+
+def write_mixture_table(path: str = TABLE, reps: int = 5, log=print) -> dict:
+    """Tune each (kernel, order) batch of the mixed workload: Yukawa (lambda = 2) and
+    biharmonic far fields of 524,288 Gaussian-mixture points (adaptive octree, <= 64 per leaf),
+    order p(l) = 6 + 2 ((l - 2) mod 3) on M2L level l, FP32; add the shapes to the table."""
+    import workloads as W
+    tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    entries = {}
+    for kernel, param in (("yukawa", 2.0), ("biharmonic", 0.0)):
+        for p in (6, 8, 10):
+            levels = [l for l in range(2, tr.n_levels) if 6 + 2 * ((l - 2) % 3) == p]
+            t, s = W.interaction_pairs(tr, levels)
+            plan = fmm.Plan(fmm.Desc(kernel, p, "f32", param), lh)
+            r = tune(plan, t, s, tr.ijk, tr.level, reps=reps, cache=None)
+            log(f"{kernel} p={p} f32: {r['ms']:.4f} ms {r['tuning']} ({len(r['results'])} candidates, "
+                f"{r['seconds']:.0f} s)")
+            entries[f"{kernel}|p{p}|f32"] = _entry(
+                r, len(t), f"mixture 524288 points, adaptive <= 64 per leaf, levels {levels}")
+            plan.close()
+    return _merge(path, entries)
+
+
 if __name__ == "__main__":
-    write_table()
+    import sys
+    if "--mixture" in sys.argv:
+        write_mixture_table()
+    else:
+        write_table()

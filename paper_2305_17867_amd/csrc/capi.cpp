@@ -37,13 +37,22 @@ constexpr int64_t kP2MMinChunkPoints = 512;   // smallest chunk when boxes are s
 constexpr int64_t kP2MFillGroups = 2048;      // workgroups a P2M launch over few boxes aims for
 }  // namespace
 
-struct fmm_multi_s {
-  std::vector<fmm_batch> batches;
-  int dtype = 0, rt = 1, ctw = 1, pf = 0, nbuf = 1, waves = 1, grid = 1;
+// One launch of a multi: a streaming batch on its own (its own tuned shape), or a group of
+// tiled batches sharing one tile shape drained by one persistent launch.
+struct MultiGroup {
+  std::vector<int> idx;  // positions of the group's batches in fmm_multi_s::batches
+  bool stream = false;
+  int rt = 1, ctw = 1, pf = 0, nbuf = 1, waves = 1, grid = 1;
   size_t lds = 0;
   M2LArgs* d_args = nullptr;
   int2* d_work = nullptr;
   int32_t n_work = 0;
+};
+
+struct fmm_multi_s {
+  std::vector<fmm_batch> batches;
+  int dtype = 0;
+  std::vector<MultiGroup> groups;
 };
 
 struct fmm_batch_s {
@@ -1282,6 +1291,50 @@ int fmm_m2l_batched_static(fmm_batch b, const void* mpole, void* local, void* st
                     (hipStream_t)stream);
 }
 
+// Persistent launch state of a group of tiled batches sharing one tile shape: work items of all
+// its batches ordered by decreasing cost, the workgroup sized for the largest wavefront count.
+static int multi_group_prepare(fmm_multi m, MultiGroup& g, int n_cu) {
+  const fmm_batch b0 = m->batches[g.idx[0]];
+  if (!m2l_multi_shape_instantiated(b0->rows_per_wave, b0->col_tiles))
+    return fail(FMM_EUNSUPPORTED, "tiled launch shape not instantiated for multi-batch launches");
+  g.rt = b0->rows_per_wave;
+  g.ctw = b0->col_tiles;
+  g.nbuf = b0->nbuf;
+  std::vector<M2LArgs> args(g.idx.size());
+  struct Wk {
+    double cost;
+    int2 w;
+  };
+  std::vector<Wk> work;
+  for (size_t k = 0; k < g.idx.size(); ++k) {
+    const fmm_batch b = m->batches[g.idx[k]];
+    g.waves = std::max(g.waves, b->waves);
+    g.pf = std::max(g.pf, b->pf_class);
+    g.lds = std::max(g.lds, (size_t)b->lds_bytes);
+    args[k] = m2l_args(b, nullptr, nullptr);
+    for (size_t i = 0; i < b->h_items.size(); ++i) {
+      const M2LItem& it = b->h_items[i];
+      const double cost = (double)(it.e1 - it.e0) * b->nc_pad * b->shape.k4p * b->shape.nt;
+      work.push_back({cost, int2{(int)k, (int)i}});
+    }
+  }
+  // the shared workgroup has the largest wave count; every batch's staging must divide evenly
+  for (int k : g.idx) {
+    const fmm_batch b = m->batches[k];
+    const int nthr = g.waves * 64;
+    if (nthr % b->shape.nt || (dtype_complex(m->dtype) && ((nthr / b->shape.nt) & 1)))
+      return fail(FMM_EUNSUPPORTED, "batch tile size does not divide the shared workgroup");
+  }
+  std::stable_sort(work.begin(), work.end(), [](const Wk& a, const Wk& c) { return a.cost > c.cost; });
+  std::vector<int2> wl(work.size());
+  for (size_t i = 0; i < work.size(); ++i) wl[i] = work[i].w;
+  g.n_work = (int32_t)wl.size();
+  g.grid = std::max(1, std::min<int>(g.n_work, 2 * n_cu));
+  int st;
+  if ((st = dev_upload(&g.d_args, args)) || (st = dev_upload(&g.d_work, wl))) return st;
+  return FMM_OK;
+}
+
 int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* out) {
   FMM_REQUIRE(out, FMM_EINVAL, "output pointer is NULL");
   *out = nullptr;
@@ -1293,65 +1346,50 @@ int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* out) {
     const fmm_batch b = batches[k];
     FMM_REQUIRE(b && b->plan && b->plan->alive, FMM_EINVAL, "NULL or stale batch");
     FMM_REQUIRE(!b->fft && !b->adjoint, FMM_EINVAL, "FFT and adjoint batches cannot join a multi launch");
-    FMM_REQUIRE(!b->stream, FMM_EINVAL,
-                "multi launches take batches prepared with one explicit fmm_m2l_tuning (tiled form)");
     FMM_REQUIRE(b->dtype == b0->dtype, FMM_EINVAL, "batches must share one dtype");
     for (int j = 0; j < k; ++j)  // split tiles keep their partials in the batch's own scratch
       FMM_REQUIRE(batches[j] != b, FMM_EINVAL, "a batch may appear only once in a multi launch");
-    FMM_REQUIRE(b->rows_per_wave == b0->rows_per_wave && b->col_tiles == b0->col_tiles && b->nbuf == b0->nbuf,
-                FMM_EINVAL, "batches must share rows_per_wave, col_tiles_per_wave and lds_buffers (prepare "
-                            "them with one fmm_m2l_tuning)");
   }
-  FMM_REQUIRE(m2l_multi_shape_instantiated(b0->rows_per_wave, b0->col_tiles), FMM_EUNSUPPORTED,
-              "launch shape not instantiated for multi-batch launches");
   auto* m = new fmm_multi_s();
   m->batches.assign(batches, batches + n);
   m->dtype = b0->dtype;
-  m->rt = b0->rows_per_wave;
-  m->ctw = b0->col_tiles;
-  m->nbuf = b0->nbuf;
-  std::vector<M2LArgs> args(n);
-  struct W {
-    double cost;
-    int2 w;
-  };
-  std::vector<W> work;
+  // streaming batches launch on their own; tiled batches are grouped by tile shape, in order of
+  // first appearance
   for (int k = 0; k < n; ++k) {
     const fmm_batch b = batches[k];
-    m->waves = std::max(m->waves, b->waves);
-    m->pf = std::max(m->pf, b->pf_class);
-    m->lds = std::max(m->lds, (size_t)b->lds_bytes);
-    args[k] = m2l_args(b, nullptr, nullptr);
-    for (size_t i = 0; i < b->h_items.size(); ++i) {
-      const M2LItem& it = b->h_items[i];
-      const double cost = (double)(it.e1 - it.e0) * b->nc_pad * b->shape.k4p * b->shape.nt;
-      work.push_back({cost, int2{k, (int)i}});
+    if (b->stream) {
+      MultiGroup g;
+      g.stream = true;
+      g.idx.push_back(k);
+      m->groups.push_back(g);
+      continue;
+    }
+    MultiGroup* hit = nullptr;
+    for (MultiGroup& g : m->groups) {
+      const fmm_batch f = batches[g.idx[0]];
+      if (!g.stream && f->rows_per_wave == b->rows_per_wave && f->col_tiles == b->col_tiles && f->nbuf == b->nbuf)
+        hit = &g;
+    }
+    if (hit) {
+      hit->idx.push_back(k);
+    } else {
+      MultiGroup g;
+      g.idx.push_back(k);
+      m->groups.push_back(g);
     }
   }
-  // the shared workgroup has the largest wave count; every batch's staging must divide evenly
-  for (int k = 0; k < n; ++k) {
-    const fmm_batch b = batches[k];
-    const int nthr = m->waves * 64;
-    if (nthr % b->shape.nt || (dtype_complex(m->dtype) && ((nthr / b->shape.nt) & 1))) {
-      delete m;
-      return fail(FMM_EUNSUPPORTED, "batch tile size does not divide the shared workgroup");
-    }
-  }
-  std::stable_sort(work.begin(), work.end(), [](const W& a, const W& c) { return a.cost > c.cost; });
-  std::vector<int2> wl(work.size());
-  for (size_t i = 0; i < work.size(); ++i) wl[i] = work[i].w;
-  m->n_work = (int32_t)wl.size();
   int dev = 0, n_cu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
   }
   (void)hipGetLastError();
-  m->grid = std::max(1, std::min<int>(m->n_work, 2 * n_cu));
-  int st;
-  if ((st = dev_upload(&m->d_args, args)) || (st = dev_upload(&m->d_work, wl))) {
-    fmm_m2l_multi_destroy(m);
-    return st;
+  for (MultiGroup& g : m->groups) {
+    if (g.stream) continue;
+    if (int st = multi_group_prepare(m, g, n_cu)) {
+      fmm_m2l_multi_destroy(m);
+      return st;
+    }
   }
   *out = m;
   return FMM_OK;
@@ -1360,25 +1398,38 @@ int fmm_m2l_multi_prepare(int32_t n, const fmm_batch* batches, fmm_multi* out) {
 int fmm_m2l_multi_launch(fmm_multi m, const void* const* mpole, void* const* local, void* stream) {
   FMM_REQUIRE(m, FMM_EINVAL, "multi is NULL");
   FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL pointer arrays");
-  if (m->n_work == 0) return FMM_OK;
-  M2LMulti a{};
-  a.args = m->d_args;
-  a.work = m->d_work;
-  a.n_work = m->n_work;
   for (size_t k = 0; k < m->batches.size(); ++k) {
     FMM_REQUIRE(m->batches[k]->plan && m->batches[k]->plan->alive, FMM_ESTATE, "a batch's plan was destroyed");
     FMM_REQUIRE(mpole[k] && local[k], FMM_EINVAL, "NULL coefficient array");
-    a.mpole[k] = mpole[k];
-    a.local[k] = local[k];
   }
-  return launch_m2l_multi(a, m->dtype, m->rt, m->ctw, m->pf, m->nbuf, m->lds, m->waves, m->grid,
-                          (hipStream_t)stream);
+  for (const MultiGroup& g : m->groups) {
+    if (g.stream) {
+      const int k = g.idx[0];
+      if (int st = m2l_launch(m->batches[k], mpole[k], local[k], stream)) return st;
+      continue;
+    }
+    if (g.n_work == 0) continue;
+    M2LMulti a{};
+    a.args = g.d_args;
+    a.work = g.d_work;
+    a.n_work = g.n_work;
+    for (size_t k = 0; k < g.idx.size(); ++k) {
+      a.mpole[k] = mpole[g.idx[k]];
+      a.local[k] = local[g.idx[k]];
+    }
+    if (int st = launch_m2l_multi(a, m->dtype, g.rt, g.ctw, g.pf, g.nbuf, g.lds, g.waves, g.grid,
+                                  (hipStream_t)stream))
+      return st;
+  }
+  return FMM_OK;
 }
 
 void fmm_m2l_multi_destroy(fmm_multi m) {
   if (!m) return;
-  dev_free(m->d_args);
-  dev_free(m->d_work);
+  for (MultiGroup& g : m->groups) {
+    dev_free(g.d_args);
+    dev_free(g.d_work);
+  }
   delete m;
 }
 

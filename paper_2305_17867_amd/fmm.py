@@ -405,8 +405,9 @@ def p2p(desc: Desc, tbox, nbr_ptr, nbr, tgt_range, src_range, src, w, tgt, pot) 
 
 
 class Multi:
-    """Several prepared forward batches drained by one persistent launch (fmm_m2l_multi_*).
-    The batches must share the dtype and the launch shape (prepare them with one tuning)."""
+    """Several prepared forward batches of one dtype enqueued as one unit (fmm_m2l_multi_*):
+    streaming-form batches each in their own tuned launch, tiled-form batches that share a
+    tile shape drained by one persistent launch."""
 
     def __init__(self, batches):
         self.batches = list(batches)

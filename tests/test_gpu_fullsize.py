@@ -8,8 +8,9 @@ Workloads (recipes in the workloads module, seeds below):
             Helmholtz p = 12 with k = 1 / (largest leaf side), List-2 pairs of every level in one
             prepared batch, complex128 and complex64.
   mixture   2^19 points from 4 Gaussians (sigma 0.05), adaptive <= 64, Yukawa (lambda = 2) and
-            biharmonic with p(l) = 6 + 2 ((l - 2) mod 3), FP32, one persistent launch captured in
-            a HIP graph.
+            biharmonic with p(l) = 6 + 2 ((l - 2) mod 3), FP32, the six batches as one multi
+            launch (tuned per-(kernel, order) shapes, or one shared tiled shape drained by one
+            persistent launch) captured in a HIP graph.
   gradient  2^21 sources and 2^21 targets uniform, depth-4 octrees, Laplace p = 10: the far field
             and its adjoint (d L / d weights, source and target positions).
 
@@ -246,11 +247,17 @@ def order_of_level(l):
     return 6 + 2 * ((l - 2) % 3)
 
 
-def test_mixture_full_size_one_captured_launch(gpu_lib):
+@pytest.mark.parametrize("shapes", ["tuned", "one_tiled_shape"])
+def test_mixture_full_size_one_captured_launch(gpu_lib, shapes):
+    """The mixed workload at full size (524,288 mixture points, Yukawa and biharmonic, p = 6/8/10
+    by level, FP32): the six batches in their tuned per-(kernel, order) shapes, or in one shared
+    tiled shape (one persistent launch), enqueued as one multi launch and captured in a graph;
+    replays bit-identical to the eager launch, sampled targets against the oracle."""
     fmm = gpu_lib
     tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
     lh = [tr.box_size(l) for l in range(tr.n_levels)]
-    tuning = {"rows_per_wave": 2, "col_tiles_per_wave": 2, "col_groups": 1, "lds_buffers": 1}
+    tuning = None if shapes == "tuned" else {"rows_per_wave": 2, "col_tiles_per_wave": 2, "col_groups": 1,
+                                              "lds_buffers": 1}
     groups, batches, mps = [], [], []
     for kernel, param in (("yukawa", 2.0), ("biharmonic", 0.0)):
         for p in (6, 8, 10):

@@ -1,10 +1,12 @@
-"""GPU: one persistent launch over several M2L batches (fmm_m2l_multi_*), and its capture
-into a HIP graph.
+"""GPU: several M2L batches enqueued as one unit (fmm_m2l_multi_*), and its capture into a HIP
+graph.
 
 Workload: a mixed far field on an adaptive Gaussian-mixture tree (8192 points, at most 32
 per leaf, levels 2..6), Yukawa (lambda = 2) and biharmonic, with the order depending on the
 level as p(l) = 6 + 2 ((l - 2) mod 3), FP32.  One batch per (kernel, order), six in all,
-prepared with one launch shape.
+prepared three ways: with one tiled shape (one persistent launch drains all six), with each
+batch's own streaming shape (six launches), and mixed (tiled shapes differing per batch, and
+streaming batches beside them).
 
 Checks: every batch of the multi launch against the oracle (normwise relative 2e-5, the FP32
 M2L tolerance), the multi launch bit-identical to the per-batch launches (same work items,
@@ -55,31 +57,40 @@ def oracle_refs(mixed):
                               g["t"], g["s"], g["beta"]) for g in groups]
 
 
-def build(fmm, mixed, monkeypatch, items):
+# per-batch tunings of the "mixed" preparation: two tiled shapes and streaming batches
+MIXED_TUNINGS = [TUNING, {"form": "stream", "waves": 4}, dict(TUNING, col_tiles_per_wave=1),
+                 {"form": "stream"}, TUNING, dict(TUNING, col_tiles_per_wave=1)]
+
+
+def build(fmm, mixed, monkeypatch, items, how="tiled"):
     if items is not None:
         monkeypatch.setenv("FMM_M2L_ITEMS", str(items))
     tr, lh, groups = mixed
     plans, batches, mp, perms = [], [], [], []
-    for g in groups:
+    for k, g in enumerate(groups):
         d = fmm.Desc(g["kernel"], g["p"], "f32", g["param"])
         plan = fmm.Plan(d, lh)
         perm = perm_to_lib(g["kernel"], g["param"], g["p"], d.index_table())
         inv = np.argsort(perm)
         plans.append(plan)
-        batches.append(plan.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=TUNING))
+        tuning = {"tiled": TUNING, "stream": "library", "mixed": MIXED_TUNINGS[k % len(MIXED_TUNINGS)]}[how]
+        batches.append(plan.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=tuning))
         # library order: coefficient k is the oracle's coefficient perm[k]
         mp.append(torch.as_tensor(np.ascontiguousarray(g["beta"][:, perm]), dtype=torch.float32, device="cuda"))
         perms.append((perm, inv))
     return plans, batches, mp, perms
 
 
-@pytest.mark.parametrize("items", [None, 4096])
-def test_multi_matches_oracle_and_single(gpu_lib, mixed, oracle_refs, items, monkeypatch):
+@pytest.mark.parametrize("items,how", [(None, "tiled"), (4096, "tiled"), (None, "stream"), (None, "mixed"),
+                                       (4096, "mixed")])
+def test_multi_matches_oracle_and_single(gpu_lib, mixed, oracle_refs, items, how, monkeypatch):
     fmm = gpu_lib
     tr, lh, groups = mixed
-    plans, batches, mp, perms = build(fmm, mixed, monkeypatch, items)
+    plans, batches, mp, perms = build(fmm, mixed, monkeypatch, items, how)
+    forms = [b.info()["stream_form"] for b in batches]
+    assert forms == ([0] * 6 if how == "tiled" else [1] * 6 if how == "stream" else [0, 1, 0, 1, 0, 0])
     if items is not None:
-        assert any(b.info()["n_items"] > b.info()["n_tiles"] for b in batches)  # split tiles present
+        assert any(b.info()["n_items"] > b.info()["n_tiles"] for b in batches if not b.info()["stream_form"])
     single = [torch.zeros_like(m) for m in mp]
     for b, m, l in zip(batches, mp, single):
         b(m, l)
@@ -104,9 +115,10 @@ def test_multi_matches_oracle_and_single(gpu_lib, mixed, oracle_refs, items, mon
     multi.close()
 
 
-def test_multi_graph_replay(gpu_lib, mixed, monkeypatch):
+@pytest.mark.parametrize("how", ["tiled", "mixed"])
+def test_multi_graph_replay(gpu_lib, mixed, monkeypatch, how):
     fmm = gpu_lib
-    plans, batches, mp, perms = build(fmm, mixed, monkeypatch, None)
+    plans, batches, mp, perms = build(fmm, mixed, monkeypatch, None, how)
     multi = fmm.Multi(batches)
     eager = [torch.zeros_like(m) for m in mp]
     multi(mp, eager)  # also the warm-up before capture
@@ -145,10 +157,9 @@ def test_multi_validation(gpu_lib, mixed, monkeypatch):
     p64 = fmm.Plan(fmm.Desc(g["kernel"], g["p"], "f64", g["param"]), lh)
     b32 = p32.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=TUNING)
     b64 = p64.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=TUNING)
-    other = dict(TUNING, col_tiles_per_wave=1)
-    b32o = p32.prepare(g["t"], g["s"], tr.ijk, tr.level, tuning=other)
     adj = p32.prepare_adjoint(g["t"], g["s"], tr.ijk, tr.level, tuning=TUNING)
-    for bad in ([b32, b64], [b32, b32o], [b32, adj], []):
+    fft = p32.prepare_fft(g["t"], g["s"], tr.ijk, tr.level)
+    for bad in ([b32, b64], [b32, adj], [b32, fft], []):
         with pytest.raises((FmmError, ValueError)):
             fmm.Multi(bad)
     with pytest.raises(FmmError):
