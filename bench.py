@@ -842,6 +842,8 @@ def main():
                     help="also time the complete FMM potential when --only or --no-extras is given")
     ap.add_argument("--translations", action="store_true",
                     help="also time M2M / L2L when --only or --no-extras is given")
+    ap.add_argument("--mixed", action="store_true",
+                    help="also time the mixed Yukawa + biharmonic workload when --only or --no-extras is given")
     ap.add_argument("--plummer", action="store_true",
                     help="also time the Plummer Helmholtz launch and FMM when --only or --no-extras is given")
     ap.add_argument("--gradient", action="store_true",
@@ -929,8 +931,8 @@ def main():
         out["full_fmm"] = full_fmm(torch, fmm, tr, w)
         log("complete FMM on an adaptive tree (far field + near field)")
         out["full_fmm_adaptive"] = full_fmm_adaptive(torch, fmm)
-    if not (args.only or args.no_extras):
-        log("mixed workload (persistent, graph-captured launch)")
+    if args.mixed or not (args.only or args.no_extras):
+        log("mixed workload (per-batch tuned launches, graph-captured)")
         out["mixed_batch"] = mixed_batch(torch, fmm, checks)
     if args.plummer or not (args.only or args.no_extras):
         log("Plummer Helmholtz, one launch over all levels")

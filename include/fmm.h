@@ -272,7 +272,8 @@ int fmm_m2l_prepare_fft(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
  * instead of the batch's scratch.  Same arguments and results as fmm_m2l_batched (bit-identical
  * for the same batch and inputs).  A batch whose partials and counters need more than 16 MiB
  * gets FMM_EUNSUPPORTED; FFT batches get FMM_EUNSUPPORTED, adjoint batches FMM_ESTATE.  The
- * counters are cleared by a small kernel on `stream` at every call.  All calls on one device
+ * counters (and the partial slots, which the streaming form needs empty) are reset by a small
+ * kernel on `stream` at every call.  All calls on one device
  * share the array: calls that can overlap in time on one device (different streams without
  * ordering) race and give wrong results. */
 int fmm_m2l_batched_static(fmm_batch batch, const void* mpole, void* local, void* stream);

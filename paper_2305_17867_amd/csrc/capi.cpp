@@ -967,6 +967,13 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   if (b->scratch_bytes) {
     if (hipMalloc((void**)&b->d_scratch, b->scratch_bytes) != hipSuccess)
       return bail(fail(FMM_ENOMEM, "scratch allocation failed"));
+    if (b->stream) {  // every partial slot starts empty (the kernel leaves it empty again)
+      st = launch_fill_u32(reinterpret_cast<uint32_t*>(b->d_scratch), b->scratch_bytes / 4, kM2LPartialEmptyWord,
+                           nullptr);
+      hipError_t e = hipDeviceSynchronize();
+      if (st) return bail(st);
+      if (e != hipSuccess) return bail(fail(FMM_EHIP, std::string("scratch fill: ") + hipGetErrorString(e)));
+    }
   }
   *out = b;
   return FMM_OK;
@@ -1275,10 +1282,14 @@ int fmm_m2l_batched_static(fmm_batch b, const void* mpole, void* local, void* st
   if (st) return st;
   double* part = reinterpret_cast<double*>(base);
   int32_t* counter = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(base) + part_bytes);
-  // the part counters must start at zero; the array keeps whatever the last call left there
+  // the part counters must start at zero (and, for the streaming form, the partial slots
+  // empty); the array keeps whatever the last call left there
   st = launch_zero_i32(counter, b->n_tiles, (hipStream_t)stream);
   if (st) return st;
   if (b->stream) {
+    st = launch_fill_u32(reinterpret_cast<uint32_t*>(part), b->scratch_bytes / 4, kM2LPartialEmptyWord,
+                         (hipStream_t)stream);
+    if (st) return st;
     M2LStreamArgs a = m2l_stream_args(b, mpole, local);
     a.scratch = part;
     a.counter = counter;

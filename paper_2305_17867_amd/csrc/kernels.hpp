@@ -245,8 +245,17 @@ int launch_m2l_stream(const M2LStreamArgs& a, int p, int c, int dtype, int waves
 // FP64 tables [n][ts] (complex interleaved) -> [n][tsp] in the dtype, complex as a re plane then
 // an im plane; the padding past CW ts must already be zero.
 int launch_m2l_stream_tables(const double* src, void* dst, int64_t n, int ts, int tsp, int dtype, hipStream_t s);
-// p[0 .. n-1] = 0 with a small kernel (capturable, unlike a memset node)
+// p[0 .. n-1] = 0 (or v) with a small kernel (capturable, unlike a memset node)
 int launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+int launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+// An empty slot of the streaming M2L's split-tile partials: a signalling NaN (quiet bit clear,
+// payload nonzero), which no floating-point operation returns; both 32-bit halves are the word
+// kM2LPartialEmptyWord, so a 32-bit fill writes it.
+constexpr uint32_t kM2LPartialEmptyWord = 0x7FF7F7F7u;
+constexpr uint64_t kM2LPartialEmpty = ((uint64_t)kM2LPartialEmptyWord << 32) | kM2LPartialEmptyWord;
+// Polls of an empty slot before the reader gives up (about 0.2 s): the slot's NaN then reaches
+// the output instead of the launch waiting for ever.
+constexpr int kM2LPartialMaxWaits = 1 << 22;
 int launch_m2l_table_layout(const double* src, void* dst, int64_t n, int ts, int dtype, hipStream_t s);
 
 }  // namespace fmm

@@ -405,8 +405,12 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
       }
       continue;
     }
-    // split tile: FP64 partial to scratch; the last part of the tile to finish adds the parts in
-    // part order
+    // split tile: the last part of the tile to finish adds the parts in part order.  The others
+    // leave their FP64 partials in scratch with device-scope atomic stores; a slot holds the
+    // empty pattern (a signalling NaN, which no arithmetic produces) until its value arrives, and
+    // the last part reads each value with device-scope atomic loads until none is empty, then
+    // empties the slots again.  Coherence of each location is all this needs: no cache
+    // write-back or invalidation, and the wait is only for stores already issued.
     constexpr int NCP = (NC + 15) / 16 * 16;
     const int64_t pstride = (int64_t)16 * NCP * CW;
     {
@@ -418,22 +422,25 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
           const int i = TR * r + TL::row(kq, v);
           if (i < NC) {
 #pragma unroll
-            for (int u = 0; u < CW; ++u) mine[(col * NCP + i) * CW + u] = acc[r][u][v];
+            for (int u = 0; u < CW; ++u)
+              __hip_atomic_store(mine + (col * NCP + i) * CW + u, acc[r][u][v], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
           }
         }
       if (kq == 0) {
 #pragma unroll
         for (int jr = 0; jr < NREM; ++jr)
 #pragma unroll
-          for (int u = 0; u < CW; ++u) mine[(col * NCP + TR * RT + jr) * CW + u] = racc[jr][u];
+          for (int u = 0; u < CW; ++u)
+            __hip_atomic_store(mine + (col * NCP + TR * RT + jr) * CW + u, racc[jr][u], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    __threadfence();
     int old = 0;
-    if (lane == 0) old = atomicAdd(a.counter + it.tile, 1);
+    if (lane == 0)
+      old = __hip_atomic_fetch_add(a.counter + it.tile, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     old = __builtin_amdgcn_readfirstlane(old);
     if (old != nparts - 1) continue;
-    __threadfence();
     // the last part: add all parts in part order, its own from registers, the others from
     // scratch at the same (lane, register) positions (all their loads issued before the sums)
     {
@@ -462,20 +469,57 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
             for (int u = 0; u < CW; ++u) totr[jr][u] += racc[jr][u];
           continue;
         }
-        const double* ps = a.scratch + (int64_t)(a.tile_item0[it.tile] + pt) * pstride;
+        double* ps = a.scratch + (int64_t)(a.tile_item0[it.tile] + pt) * pstride;
         double lr[RT][CW][NV], lrr[NREM > 0 ? NREM : 1][CW];
+        bool empty;
+        int waits = 0;  // bounded: a slot that never fills gives NaN results, not a hang
+        do {
+          empty = false;
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const int i = TR * r + TL::row(kq, v);
+#pragma unroll
+              for (int u = 0; u < CW; ++u) {
+                lr[r][u][v] = i < NC ? __hip_atomic_load(ps + (col * NCP + i) * CW + u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                     : 0.0;
+                empty |= __builtin_bit_cast(uint64_t, lr[r][u][v]) == kM2LPartialEmpty;
+              }
+            }
+#pragma unroll
+          for (int jr = 0; jr < NREM; ++jr)
+#pragma unroll
+            for (int u = 0; u < CW; ++u) {
+              lrr[jr][u] = __hip_atomic_load(ps + (col * NCP + TR * RT + jr) * CW + u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+              empty |= __builtin_bit_cast(uint64_t, lrr[jr][u]) == kM2LPartialEmpty;
+            }
+          empty = __builtin_amdgcn_ballot_w64(empty) != 0;
+          if (empty) __builtin_amdgcn_s_sleep(2);
+        } while (empty && ++waits < kM2LPartialMaxWaits);
+        // empty the slot for the next launch (each value was read above by this lane)
+        const double none = __builtin_bit_cast(double, kM2LPartialEmpty);
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             const int i = TR * r + TL::row(kq, v);
+            if (i < NC) {
 #pragma unroll
-            for (int u = 0; u < CW; ++u) lr[r][u][v] = i < NC ? ps[(col * NCP + i) * CW + u] : 0.0;
+              for (int u = 0; u < CW; ++u)
+                __hip_atomic_store(ps + (col * NCP + i) * CW + u, none, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
           }
+        if (kq == 0) {
 #pragma unroll
-        for (int jr = 0; jr < NREM; ++jr)
+          for (int jr = 0; jr < NREM; ++jr)
 #pragma unroll
-          for (int u = 0; u < CW; ++u) lrr[jr][u] = ps[(col * NCP + TR * RT + jr) * CW + u];
+            for (int u = 0; u < CW; ++u)
+              __hip_atomic_store(ps + (col * NCP + TR * RT + jr) * CW + u, none, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -510,7 +554,7 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
         }
       }
     }
-    if (lane == 0) atomicExch(a.counter + it.tile, 0);
+    if (lane == 0) __hip_atomic_store(a.counter + it.tile, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -620,18 +664,22 @@ __global__ void m2ls_table_layout_kernel(const double* src, R* dst, int64_t n, i
   }
 }
 
-__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
+  if (i < n) p[i] = v;
 }
 
 }  // namespace
 
-int launch_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+int launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
   if (n <= 0) return FMM_OK;
-  hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   FMM_HIP_CHECK(hipGetLastError());
   return FMM_OK;
+}
+
+int launch_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+  return launch_fill_u32(reinterpret_cast<uint32_t*>(p), n, 0u, s);
 }
 
 int launch_m2l_stream_tables(const double* src, void* dst, int64_t n, int ts, int tsp, int dtype, hipStream_t s) {
