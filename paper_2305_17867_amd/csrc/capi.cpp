@@ -27,6 +27,9 @@ struct fmm_plan_s {
   int32_t* d_jbase = nullptr;
   int32_t* d_jxyz = nullptr;
   double* d_p2m_part = nullptr;  // per-chunk P2M results of boxes spread over several workgroups
+  // per level: sparse M~^T (compression, rows j < nc) and M~ (decompression, rows m >= nc)
+  int32_t *d_cmp_ptr = nullptr, *d_cmp_col = nullptr, *d_dec_ptr = nullptr, *d_dec_col = nullptr;
+  double *d_cmp_val = nullptr, *d_dec_val = nullptr;
   bool alive = true;
 };
 
@@ -212,8 +215,44 @@ int fmm_plan_create(const fmm_desc* desc, int32_t n_levels, const double* level_
     jb[k] = (pl->J[k].z * pl->S + pl->J[k].x) * pl->S + pl->J[k].y;
     jx[k] = pl->J[k].x | (pl->J[k].y << 8) | (pl->J[k].z << 16);
   }
+  // the compression and decompression of every level as sparse rows (nonzero entries only)
+  std::vector<int32_t> cmp_ptr, cmp_col, dec_ptr, dec_col;
+  std::vector<double> cmp_val, dec_val;
+  {
+    const auto terms = recursion_terms(desc->kernel, desc->param);
+    const int nf = pl->nfull, nc = pl->nc;
+    for (int l = 0; l < n_levels; ++l) {
+      const std::vector<double> M = decompression_matrix(pl->p, pl->c, terms, pl->h[l]);
+      for (int j = 0; j < nc; ++j) {
+        cmp_ptr.push_back((int32_t)cmp_col.size());
+        for (int m = 0; m < nf; ++m)
+          if (M[(size_t)m * nc + j] != 0.0) {
+            cmp_col.push_back(m);
+            cmp_val.push_back(M[(size_t)m * nc + j]);
+          }
+      }
+      cmp_ptr.push_back((int32_t)cmp_col.size());
+      for (int m = 0; m < nf; ++m) {
+        dec_ptr.push_back((int32_t)dec_col.size());
+        if (m < nc) continue;  // kept rows are the identity
+        for (int j = 0; j < nc; ++j)
+          if (M[(size_t)m * nc + j] != 0.0) {
+            dec_col.push_back(j);
+            dec_val.push_back(M[(size_t)m * nc + j]);
+          }
+      }
+      dec_ptr.push_back((int32_t)dec_col.size());
+    }
+    if (dec_col.empty()) {  // order below the PDE order: nothing is eliminated
+      dec_col.push_back(0);
+      dec_val.push_back(0.0);
+    }
+  }
   if ((st = dev_upload(&pl->d_level_h, pl->h)) || (st = dev_upload(&pl->d_jbase, jb)) ||
-      (st = dev_upload(&pl->d_jxyz, jx)) ||
+      (st = dev_upload(&pl->d_jxyz, jx)) || (st = dev_upload(&pl->d_cmp_ptr, cmp_ptr)) ||
+      (st = dev_upload(&pl->d_cmp_col, cmp_col)) || (st = dev_upload(&pl->d_cmp_val, cmp_val)) ||
+      (st = dev_upload(&pl->d_dec_ptr, dec_ptr)) || (st = dev_upload(&pl->d_dec_col, dec_col)) ||
+      (st = dev_upload(&pl->d_dec_val, dec_val)) ||
       (hipMalloc((void**)&pl->d_p2m_part, kP2MPartBytes) != hipSuccess &&
        (st = fail(FMM_ENOMEM, "hipMalloc of the P2M chunk buffer failed")))) {
     fmm_plan_destroy(pl);
@@ -230,6 +269,12 @@ void fmm_plan_destroy(fmm_plan plan) {
   dev_free(plan->d_jbase);
   dev_free(plan->d_jxyz);
   dev_free(plan->d_p2m_part);
+  dev_free(plan->d_cmp_ptr);
+  dev_free(plan->d_cmp_col);
+  dev_free(plan->d_cmp_val);
+  dev_free(plan->d_dec_ptr);
+  dev_free(plan->d_dec_col);
+  dev_free(plan->d_dec_val);
   delete plan;
 }
 
@@ -285,6 +330,9 @@ int fmm_p2m(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
   a.nc = plan->nc;
   a.c = plan->c;
   a.rec = plan->rec;
+  a.cmp_ptr = plan->d_cmp_ptr;
+  a.cmp_col = plan->d_cmp_col;
+  a.cmp_val = plan->d_cmp_val;
   a.xsign = 1.0;
   set_p2m_chunks(plan, a);
   return launch_p2m(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
@@ -369,6 +417,9 @@ int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
   a.nc = plan->nc;
   a.c = plan->c;
   a.rec = plan->rec;
+  a.dec_ptr = plan->d_dec_ptr;
+  a.dec_col = plan->d_dec_col;
+  a.dec_val = plan->d_dec_val;
   a.xsign = 1.0;
   a.grad = nullptr;
   a.gscale = nullptr;
@@ -398,6 +449,9 @@ int fmm_l2p_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, cons
   m.nc = plan->nc;
   m.c = plan->c;
   m.rec = plan->rec;
+  m.cmp_ptr = plan->d_cmp_ptr;
+  m.cmp_col = plan->d_cmp_col;
+  m.cmp_val = plan->d_cmp_val;
   m.xsign = -1.0;
   set_p2m_chunks(plan, m);
   st = launch_p2m(m, plan->p, plan->desc.dtype, (hipStream_t)stream);
@@ -417,6 +471,9 @@ int fmm_l2p_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, cons
   e.nc = plan->nc;
   e.c = plan->c;
   e.rec = plan->rec;
+  e.dec_ptr = plan->d_dec_ptr;
+  e.dec_col = plan->d_dec_col;
+  e.dec_val = plan->d_dec_val;
   e.xsign = 1.0;
   e.grad = tgt_xyz_grad;
   e.gscale = potential_grad;
@@ -447,6 +504,9 @@ int fmm_p2m_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, cons
   e.nc = plan->nc;
   e.c = plan->c;
   e.rec = plan->rec;
+  e.dec_ptr = plan->d_dec_ptr;
+  e.dec_col = plan->d_dec_col;
+  e.dec_val = plan->d_dec_val;
   e.xsign = -1.0;
   e.grad = src_xyz_grad;
   e.gscale = weight;

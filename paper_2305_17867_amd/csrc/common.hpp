@@ -59,4 +59,7 @@ struct RecTerm {
 };
 std::vector<RecTerm> recursion_terms(int kernel, double param);
 
+// The scaled decompression matrix M~ of one tree level (box size h): [nfull][nc] row-major.
+std::vector<double> decompression_matrix(int p, int c, const std::vector<RecTerm>& terms, double h);
+
 }  // namespace fmm

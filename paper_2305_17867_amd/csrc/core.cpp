@@ -77,4 +77,31 @@ std::vector<RecTerm> recursion_terms(int kernel, double param) {
   return out;
 }
 
+// M~ of one level: L = M~ theta for every full index m and kept index j, by the recursion with
+// its coefficients scaled by h^hpow (the forward substitution of Thm. mult_decompression, levels
+// of m_z ascending) run on the unit vectors of the kept set.  Row-major [nfull][nc].
+std::vector<double> decompression_matrix(int p, int c, const std::vector<RecTerm>& terms, double h) {
+  const int nf = (int)n_full(p);
+  const int nc = (int)kept_set(p, c).size();
+  auto index = [p](int x, int y, int z) {  // position in the full order (m_z, m_x, m_y)
+    const int s = (int)(n_full(p) - n_full(p - z));
+    return s + x * (p - z + 1) - x * (x - 1) / 2 + y;
+  };
+  std::vector<double> M((size_t)nf * nc, 0.0);
+  for (int j = 0; j < nc; ++j) M[(size_t)j * nc + j] = 1.0;
+  std::vector<double> cf(terms.size());
+  for (size_t t = 0; t < terms.size(); ++t) cf[t] = terms[t].coef * std::pow(h, terms[t].hpow);
+  const std::vector<MIdx> full = full_set(p);
+  for (int m = nc; m < nf; ++m) {  // the eliminated indices in full order: m_z ascending
+    const MIdx& q = full[m];
+    double* row = &M[(size_t)m * nc];
+    for (size_t t = 0; t < terms.size(); ++t) {
+      const int n = index(q.x + terms[t].dx, q.y + terms[t].dy, q.z + terms[t].dz);
+      const double* src = &M[(size_t)n * nc];
+      for (int j = 0; j < nc; ++j) row[j] += cf[t] * src[j];
+    }
+  }
+  return M;
+}
+
 }  // namespace fmm

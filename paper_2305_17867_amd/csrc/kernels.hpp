@@ -35,6 +35,11 @@ struct P2MArgs {
   double xsign;             // X = xsign (c - y) / h  (+1: multipole moments; -1: target moments)
   int32_t ny;               // workgroups per box (contiguous point chunks); > 1 needs part
   double* part;             // [n_box][ny][Nc] (x2 complex) FP64 per-chunk results, summed in chunk order
+  // compression beta~ = M~^T alpha~ of each level, sparse rows j < Nc: the entries
+  // cmp_ptr[l (Nc + 1) + j] .. cmp_ptr[l (Nc + 1) + j + 1] of cmp_col (full index) / cmp_val
+  const int32_t* cmp_ptr;
+  const int32_t* cmp_col;
+  const double* cmp_val;
 };
 
 // Multipole-to-multipole and local-to-local translation between a parent box and its (up
@@ -75,6 +80,11 @@ struct L2PArgs {
   void* grad;               // [n_pts][3] real, accumulated: gscale(x) * d phi / d x (optional)
   const void* gscale;       // [n_pts] real per-point factor of grad (null = 1)
   int64_t chunk;            // points of a box per workgroup chunk (set by the launcher)
+  // decompression L~ = M~ theta~ of each level, sparse rows m >= Nc of the full order: entries
+  // dec_ptr[l (Nfull + 1) + m] .. dec_ptr[l (Nfull + 1) + m + 1] of dec_col (kept index) / dec_val
+  const int32_t* dec_ptr;
+  const int32_t* dec_col;
+  const double* dec_val;
 };
 
 struct TableArgs {

@@ -1,6 +1,7 @@
 // Compressed L2P (Sec. 3.3, eq. compressed-local-form): per box, decompress the scaled
-// local theta~ (forward substitution over the PDE recursion, Thm. mult_decompression,
-// levels of m_z ascending), multiply by 1/i!, and add
+// local theta~ (L~ = M~ theta~, Thm. mult_decompression, one sparse row of the level's M~ per
+// full index; the matrix is formed once per level on the host from the PDE recursion),
+// multiply by 1/i!, and add
 //   phi(x) = sum_{i in M(p)} L~_i / i! X^i,    X = (x - c) / h,
 // to every target of the box.
 //
@@ -274,12 +275,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     for (int ax = 0; ax < 3; ++ax) Lg[ax][(NG > 0 ? NG : 1) * W + threadIdx.x] = R(0);
   }
   __syncthreads();
-  decompress_lds<P, CPLX>(Ld, a.rec, a.c, h);
+  // decompression L~_m = sum_j M~[m][j] theta~_j (kept rows are theta~ itself): one sparse row
+  // of the level's M~ per full index, read from the kept prefix only, so no level waits for
+  // another
+  const int32_t* rp = a.dec_ptr + (int64_t)lev * (NP + 1);
   for (int k = threadIdx.x; k < NP; k += kThreads) {
+    double lv[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) lv[u] = k < nc ? Ld[k * W + u] : 0.0;
+    if (k >= nc) {
+      for (int e = rp[k]; e < rp[k + 1]; ++e) {
+        const int j = a.dec_col[e];
+        const double v = a.dec_val[e];
+#pragma unroll
+        for (int u = 0; u < W; ++u) lv[u] += v * Ld[j * W + u];
+      }
+    }
     const double f = kDecode<P>.inv_fact[k];
     const int hk = kHorner<P>.pos[k];
 #pragma unroll
-    for (int u = 0; u < W; ++u) Lc[hk * W + u] = (R)(Ld[k * W + u] * f);
+    for (int u = 0; u < W; ++u) Lc[hk * W + u] = (R)(lv[u] * f);
     if constexpr (GRAD) {
       // d/dX_ax of L_m X^m / m!: the coefficient of X^(m - e_ax) is L_m / (m - e_ax)!
       const int mm[3] = {kDecode<P>.x[k], kDecode<P>.y[k], kDecode<P>.z[k]};
@@ -290,7 +305,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
         const int g = kHorner<P - 1>.pos[full_index(P - 1, d0, d1, d2)];
         const double fg = f * mm[ax];
 #pragma unroll
-        for (int u = 0; u < W; ++u) Lg[ax][g * W + u] = (R)(Ld[k * W + u] * fg);
+        for (int u = 0; u < W; ++u) Lg[ax][g * W + u] = (R)(lv[u] * fg);
       }
     }
   }

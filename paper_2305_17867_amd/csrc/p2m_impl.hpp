@@ -3,12 +3,16 @@
 // followed by the compression beta~ = M~^T alpha~ (eq. define_beta_multipole; Thm.
 // mult_decompression: back substitution over the PDE recursion, O(p^3)).
 //
-// Layout of the work: one workgroup (4 wavefronts) per box.  The q set M(p) is cut into
-// chunks of at most 32 (real) / 16 (complex) coefficients; each wavefront owns every
-// fourth chunk.  Lanes stride over the box's points (coalesced loads), keep the chunk's
-// partial sums in registers, and a reduce-scatter over the wavefront leaves one sum per
-// lane, which is stored to LDS.  The compression then runs in LDS level by level in m_z
-// (descending) and the kept prefix is written out.
+// Layout of the work: one workgroup (4 wavefronts) per box.  The box's points are staged in
+// LDS once as (X, Y, Z, w) (tiles of 256 points).  Each wavefront owns a contiguous quarter of
+// M(p) in the full order (rows (m_z, m_x) of consecutive m_y), cut into pieces of at most 48
+// coefficients (24 complex) that stay in registers: per point, the powers of Y once, the
+// factor w Z^z X^x of each row as a running product, then one fused multiply-add per
+// coefficient.  The monomials carry no factorials; 1/q! is applied to the sums.  A piece's
+// sums over the 64 lanes go through a padded LDS transpose (16 values per pass: 16 rows of 16
+// partial sums per lane group, then two exchanges), and land in the box's alpha~ in LDS.  The
+// compression beta~ = M~^T alpha~ is one sparse row of the level's M~^T per coefficient (the
+// matrix formed once per level on the host from the recursion of Thm. mult_decompression).
 #pragma once
 
 #include "../../include/fmm.h"
@@ -39,93 +43,169 @@ struct FullIdx {
   }
 };
 
-template <typename R>
-__device__ inline R load_real(const void* p, int64_t i) {
-  return reinterpret_cast<const R*>(p)[i];
-}
-
-// Accumulate chunk [Q0, Q0 + QN) of the full order for one point.
-template <int P, int Q0, int QN, int QP, typename R, bool CPLX>
-__device__ inline void accumulate_chunk(R (&acc)[2][QP], const R (&px)[P + 1], const R (&py)[P + 1],
-                                        const R (&pz)[P + 1], R wr, R wi) {
-  constexpr FullIdx<P> I{};
-  // the weight times the (z, x) factor is shared by a row of the chunk (the compiler computes
-  // it once per row), so each coefficient costs one fused multiply-add per component
-#pragma unroll
-  for (int k = 0; k < QN; ++k) {
-    const int q = Q0 + k;
-    const R zx = pz[I.z[q]] * px[I.x[q]];
-    acc[0][k] += (wr * zx) * py[I.y[q]];
-    if constexpr (CPLX) acc[1][k] += (wi * zx) * py[I.y[q]];
+// 1 / (x! y! z!) of every full index of M(P)
+template <int P>
+struct InvFactFull {
+  double v[nfull(P)];
+  constexpr InvFactFull() : v() {
+    double f[P + 1] = {};
+    f[0] = 1.0;
+    for (int i = 1; i <= P; ++i) f[i] = f[i - 1] * i;
+    constexpr FullIdx<P> I{};
+    for (int q = 0; q < nfull(P); ++q) v[q] = 1.0 / (f[I.x[q]] * f[I.y[q]] * f[I.z[q]]);
   }
-}
+};
+template <int P>
+__device__ constexpr InvFactFull<P> kInvFact{};
 
-template <int P, typename R, bool CPLX, int QMAX>
-struct Chunks {
-  static constexpr int NP = nfull(P);
-  // number of chunks: a multiple of the wavefront count when there is enough work, so that
-  // the wavefronts of a box get the same number of chunks
-  static constexpr int N0 = (NP + QMAX - 1) / QMAX;
-  static constexpr int N = N0 >= kWaves ? (N0 + kWaves - 1) / kWaves * kWaves : N0;
-  static constexpr int Q = (NP + N - 1) / N;  // balanced chunk size <= QMAX
-  static constexpr int M = Q <= 1 ? 0 : Q <= 2 ? 1 : Q <= 4 ? 2 : Q <= 8 ? 3 : Q <= 16 ? 4 : Q <= 32 ? 5 : 6;
-  static constexpr int QP = 1 << M;
+constexpr int kTile = kThreads;  // points staged per pass
+constexpr int kRedStride = 17;   // LDS row stride of the reduction transpose (16 values + pad)
+
+template <typename R, bool CPLX>
+struct Stage {
+  R x[kTile], y[kTile], z[kTile], wr[kTile], wi[CPLX ? kTile : 1];
 };
 
-template <int P, typename R, bool CPLX, int CH>
-__device__ inline void run_chunk(const P2MArgs& a, int64_t lo, int64_t hi, const double (&cen)[3],
-                                 double inv_h, int lane, double* alpha) {
-  constexpr int QMAX = CPLX ? 16 : 32;
-  using C = Chunks<P, R, CPLX, QMAX>;
-  constexpr int Q0 = CH * C::Q;
-  constexpr int QN = (Q0 + C::Q <= C::NP) ? C::Q : C::NP - Q0;
-  R acc[2][C::QP];
-#pragma unroll
-  for (int k = 0; k < C::QP; ++k) acc[0][k] = acc[1][k] = R(0);
-  const R* xyz = reinterpret_cast<const R*>(a.xyz);
-  const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)inv_h;
-  for (int64_t s = lo + lane; s < hi; s += 64) {
-    const R X = (cx - xyz[s * 3 + 0]) * ih;
-    const R Y = (cy - xyz[s * 3 + 1]) * ih;
-    const R Z = (cz - xyz[s * 3 + 2]) * ih;
-    R wr, wi = R(0);
-    if constexpr (CPLX) {
-      wr = reinterpret_cast<const R*>(a.w)[2 * s];
-      wi = reinterpret_cast<const R*>(a.w)[2 * s + 1];
-    } else {
-      wr = reinterpret_cast<const R*>(a.w)[s];
-    }
-    R px[P + 1], py[P + 1], pz[P + 1];
-    px[0] = py[0] = pz[0] = R(1);
-#pragma unroll
-    for (int k = 1; k <= P; ++k) {
-      const R inv = R(1) / R(k);
-      px[k] = px[k - 1] * (X * inv);
-      py[k] = py[k - 1] * (Y * inv);
-      pz[k] = pz[k - 1] * (Z * inv);
-    }
-    accumulate_chunk<P, Q0, QN, C::QP, R, CPLX>(acc, px, py, pz, wr, wi);
+// Coefficients of wavefront W_ of a box: the full order cut into kWaves contiguous ranges, each
+// cut into NS pieces (NS the same for every wavefront, so that their barriers match).
+template <int P, bool CPLX>
+struct Pieces {
+  static constexpr int NP = nfull(P);
+  static constexpr int QMAX = CPLX ? 24 : 48;
+  static constexpr int QW = (NP + kWaves - 1) / kWaves;  // largest range
+  static constexpr int NS = (QW + QMAX - 1) / QMAX;
+  template <int W_, int S_>
+  static constexpr int q0() {
+    constexpr int a = NP * W_ / kWaves, b = NP * (W_ + 1) / kWaves;
+    return a + (b - a) * S_ / NS;
   }
-  R re = wave_reduce_scatter<C::M, R>(acc[0], lane);
-  R im = R(0);
-  if constexpr (CPLX) im = wave_reduce_scatter<C::M, R>(acc[1], lane);
-  const int k = rs_index<C::M>(lane);
-  if (rs_owner<C::M>(lane) && k < QN) {
-    if constexpr (CPLX) {
-      alpha[2 * (Q0 + k)] = (double)re;
-      alpha[2 * (Q0 + k) + 1] = (double)im;
-    } else {
-      alpha[Q0 + k] = (double)re;
+  template <int W_, int S_>
+  static constexpr int q1() {
+    constexpr int a = NP * W_ / kWaves, b = NP * (W_ + 1) / kWaves;
+    return a + (b - a) * (S_ + 1) / NS;
+  }
+};
+
+// acc[q - A] += w X^x Y^y Z^z for the coefficients q in [A, B) of the full order, one point.
+template <int P, int A, int B, typename R, bool CPLX>
+__device__ __forceinline__ void accumulate_point(R (&ar)[B - A > 0 ? B - A : 1], R (&ai)[B - A > 0 ? B - A : 1],
+                                                 R X, R Y, R Z, R wr, R wi) {
+  constexpr FullIdx<P> I{};
+  if constexpr (B > A) {
+    R py[P + 1];
+    py[0] = R(1);
+#pragma unroll
+    for (int k = 1; k <= P; ++k) py[k] = py[k - 1] * Y;
+    R zr = wr, zi = wi;  // w Z^z
+#pragma unroll
+    for (int e = 0; e < I.z[A]; ++e) {
+      zr *= Z;
+      if constexpr (CPLX) zi *= Z;
+    }
+    R rr = zr, ri = zi;  // w Z^z X^x
+#pragma unroll
+    for (int e = 0; e < I.x[A]; ++e) {
+      rr *= X;
+      if constexpr (CPLX) ri *= X;
+    }
+#pragma unroll
+    for (int q = A; q < B; ++q) {
+      if (q > A && I.y[q] == 0) {  // next row: x + 1, or the next slab (z + 1, x = 0)
+        if (I.x[q] == 0) {
+          zr *= Z;
+          rr = zr;
+          if constexpr (CPLX) {
+            zi *= Z;
+            ri = zi;
+          }
+        } else {
+          rr *= X;
+          if constexpr (CPLX) ri *= X;
+        }
+      }
+      ar[q - A] += rr * py[I.y[q]];
+      if constexpr (CPLX) ai[q - A] += ri * py[I.y[q]];
     }
   }
 }
 
-template <int P, typename R, bool CPLX, int CH, int NCH>
-__device__ inline void run_chunks(const P2MArgs& a, int64_t lo, int64_t hi, const double (&cen)[3],
-                                  double inv_h, int wave, int lane, double* alpha) {
-  if constexpr (CH < NCH) {
-    if (CH % kWaves == wave) run_chunk<P, R, CPLX, CH>(a, lo, hi, cen, inv_h, lane, alpha);
-    run_chunks<P, R, CPLX, CH + 1, NCH>(a, lo, hi, cen, inv_h, wave, lane, alpha);
+// Sum over the 64 lanes of v[0 .. N-1] (one value per lane each) into dst[k * DS] * scale[k],
+// through the wavefront's LDS transpose buffer buf [64][kRedStride].
+template <int N, int DS, typename R>
+__device__ __forceinline__ void wave_sum(const R (&v)[N > 0 ? N : 1], R* buf, int lane, double* dst,
+                                         const double* scale) {
+  const int k = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < (N + 15) / 16; ++j) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) buf[lane * kRedStride + i] = (16 * j + i < N) ? v[16 * j + i] : R(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // this wavefront's writes are in LDS
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s += (double)buf[(16 * g + r) * kRedStride + k];
+    s += xchg<16>(s);
+    s += xchg<32>(s);
+    if (g == 0 && 16 * j + k < N) dst[(16 * j + k) * DS] = s * scale[16 * j + k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // reads done before the next writes
+  }
+}
+
+// Stage points [lo + t0, lo + t0 + cnt) of the box: X = s (c - y) h^-1 and the weights.
+template <typename R, bool CPLX>
+__device__ __forceinline__ void stage_tile(const P2MArgs& a, Stage<R, CPLX>& st, int64_t first, int cnt,
+                                           const double (&cen)[3], double inv_h) {
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    const R* xyz = reinterpret_cast<const R*>(a.xyz);
+    const int64_t s = first + t;
+    const R ih = (R)inv_h;
+    st.x[t] = ((R)cen[0] - xyz[s * 3 + 0]) * ih;
+    st.y[t] = ((R)cen[1] - xyz[s * 3 + 1]) * ih;
+    st.z[t] = ((R)cen[2] - xyz[s * 3 + 2]) * ih;
+    if constexpr (CPLX) {
+      st.wr[t] = reinterpret_cast<const R*>(a.w)[2 * s];
+      st.wi[t] = reinterpret_cast<const R*>(a.w)[2 * s + 1];
+    } else {
+      st.wr[t] = reinterpret_cast<const R*>(a.w)[s];
+    }
+  }
+}
+
+// Piece S_ of wavefront W_: accumulate over every point of the box, then sum into alpha (LDS).
+template <int P, typename R, bool CPLX, int W_, int S_>
+__device__ __forceinline__ void run_piece(const P2MArgs& a, Stage<R, CPLX>& st, R* buf, int64_t lo, int n,
+                                          const double (&cen)[3], double inv_h, int lane, double* alpha) {
+  using PC = Pieces<P, CPLX>;
+  constexpr int A = PC::template q0<W_, S_>(), B = PC::template q1<W_, S_>(), N = B - A;
+  R ar[N > 0 ? N : 1], ai[N > 0 ? N : 1];
+#pragma unroll
+  for (int k = 0; k < (N > 0 ? N : 1); ++k) ar[k] = ai[k] = R(0);
+  const bool one_tile = n <= kTile;
+  for (int t0 = 0; t0 < n; t0 += kTile) {
+    const int cnt = n - t0 < kTile ? n - t0 : kTile;
+    if (!one_tile) {  // the single tile of a small box was staged once before the pieces
+      __syncthreads();
+      stage_tile<R, CPLX>(a, st, lo + t0, cnt, cen, inv_h);
+      __syncthreads();
+    }
+    for (int j = lane; j < cnt; j += 64)
+      accumulate_point<P, A, B, R, CPLX>(ar, ai, st.x[j], st.y[j], st.z[j], st.wr[j], CPLX ? st.wi[j] : R(0));
+  }
+  const double* scale = kInvFact<P>.v + A;
+  if constexpr (CPLX) {
+    wave_sum<N, 2, R>(ar, buf, lane, alpha + 2 * A, scale);
+    wave_sum<N, 2, R>(ai, buf, lane, alpha + 2 * A + 1, scale);
+  } else {
+    wave_sum<N, 1, R>(ar, buf, lane, alpha + A, scale);
+  }
+}
+
+template <int P, typename R, bool CPLX, int W_, int S_>
+__device__ __forceinline__ void run_pieces(const P2MArgs& a, Stage<R, CPLX>& st, R* buf, int64_t lo, int n,
+                                           const double (&cen)[3], double inv_h, int lane, double* alpha) {
+  if constexpr (S_ < Pieces<P, CPLX>::NS) {
+    run_piece<P, R, CPLX, W_, S_>(a, st, buf, lo, n, cen, inv_h, lane, alpha);
+    run_pieces<P, R, CPLX, W_, S_ + 1>(a, st, buf, lo, n, cen, inv_h, lane, alpha);
   }
 }
 
@@ -187,20 +267,14 @@ __device__ inline void compress_lds(double* al, const RecArgs& rec, int c, doubl
   }
 }
 
-// occupancy hint: real FP64 at p = 8 fits 80 VGPRs (6 wavefronts per SIMD) without spills
-// (the chunk layouts of the other orders spill under it); the other forms keep the compiler's
-// own budget
 template <int P, typename R, bool CPLX>
-constexpr int p2m_waves_hint() {
-  return (P == 8 && sizeof(R) == 8 && !CPLX) ? 6 : 1;
-}
-
-template <int P, typename R, bool CPLX>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(p2m_waves_hint<P, R, CPLX>()))) void p2m_kernel(P2MArgs a) {
+__global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
   constexpr int NP = nfull(P);
   __shared__ double alpha[NP * (CPLX ? 2 : 1)];
+  __shared__ Stage<R, CPLX> st;
+  __shared__ R red[kWaves][64 * kRedStride];
   const int64_t b = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   int lev = a.level[b];
   lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
   const double h = a.level_h[lev];
@@ -214,25 +288,42 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(p2m_wa
     hi = c0 + len < hi ? c0 + len : hi;
     lo = c0 < hi ? c0 : hi;
   }
-  constexpr int QMAX = CPLX ? 16 : 32;
-  constexpr int NCH = Chunks<P, R, CPLX, QMAX>::N;
-  run_chunks<P, R, CPLX, 0, NCH>(a, lo, hi, cen, a.xsign / h, wave, lane, alpha);
-  __syncthreads();
-  compress_lds<P, CPLX>(alpha, a.rec, a.c, h);
-  // the kept set is the prefix [0, nc) of the full order
-  const int nc = a.nc;
-  if (gridDim.y > 1) {
-    constexpr int W = CPLX ? 2 : 1;
-    double* part = a.part + (b * gridDim.y + blockIdx.y) * (int64_t)nc * W;
-    for (int k = threadIdx.x; k < W * nc; k += blockDim.x) part[k] = alpha[k];
-    return;
+  const int n = (int)(hi - lo);
+  const double inv_h = a.xsign / h;
+  if (n <= kTile) {
+    stage_tile<R, CPLX>(a, st, lo, n, cen, inv_h);
+    __syncthreads();
   }
-  if constexpr (CPLX) {
-    R* out = reinterpret_cast<R*>(a.out) + b * (int64_t)nc * 2;
-    for (int k = threadIdx.x; k < 2 * nc; k += blockDim.x) out[k] = (R)alpha[k];
-  } else {
-    R* out = reinterpret_cast<R*>(a.out) + b * (int64_t)nc;
-    for (int k = threadIdx.x; k < nc; k += blockDim.x) out[k] = (R)alpha[k];
+  R* buf = red[wave];
+  switch (wave) {
+    case 0: run_pieces<P, R, CPLX, 0, 0>(a, st, buf, lo, n, cen, inv_h, lane, alpha); break;
+    case 1: run_pieces<P, R, CPLX, 1, 0>(a, st, buf, lo, n, cen, inv_h, lane, alpha); break;
+    case 2: run_pieces<P, R, CPLX, 2, 0>(a, st, buf, lo, n, cen, inv_h, lane, alpha); break;
+    default: run_pieces<P, R, CPLX, 3, 0>(a, st, buf, lo, n, cen, inv_h, lane, alpha); break;
+  }
+  __syncthreads();
+  // compression beta~_j = sum_m M~[m][j] alpha~_m: one sparse row of M~^T per coefficient, the
+  // level's matrix formed once on the host from the recursion
+  const int nc = a.nc;
+  const int32_t* rp = a.cmp_ptr + (int64_t)lev * (nc + 1);
+  constexpr int W = CPLX ? 2 : 1;
+  double* part = gridDim.y > 1 ? a.part + (b * gridDim.y + blockIdx.y) * (int64_t)nc * W : nullptr;
+  R* out = reinterpret_cast<R*>(a.out) + b * (int64_t)nc * W;
+  for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (int e = rp[j]; e < rp[j + 1]; ++e) {
+      const int m = a.cmp_col[e];
+      const double v = a.cmp_val[e];
+      sr += v * alpha[W * m];
+      if constexpr (CPLX) si += v * alpha[W * m + 1];
+    }
+    if (part) {
+      part[W * j] = sr;
+      if constexpr (CPLX) part[W * j + 1] = si;
+    } else {
+      out[W * j] = (R)sr;
+      if constexpr (CPLX) out[W * j + 1] = (R)si;
+    }
   }
 }
 
