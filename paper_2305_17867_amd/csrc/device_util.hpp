@@ -74,6 +74,7 @@ __device__ inline int xchg32(int v) {
   else if constexpr (MASK == 7) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
   else if constexpr (MASK == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
   else if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  else if constexpr (MASK == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);   // row_ror:8 (xor 8)
   else if constexpr (MASK == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);             // xor 16 in 32 lanes
   else return __shfl_xor(v, 32, 64);
 }

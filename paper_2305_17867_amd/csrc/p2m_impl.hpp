@@ -9,8 +9,9 @@
 // coefficients (24 complex) that stay in registers: per point, the powers of Y once, the
 // factor w Z^z X^x of each row as a running product, then one fused multiply-add per
 // coefficient.  The monomials carry no factorials; 1/q! is applied to the sums.  A piece's
-// sums over the 64 lanes go through a padded LDS transpose (16 values per pass: 16 rows of 16
-// partial sums per lane group, then two exchanges), and land in the box's alpha~ in LDS.  The
+// sums over the 64 lanes go through a padded LDS transpose (8 values per pass in FP64, 16 in
+// FP32: each lane adds one value over a group of lanes, then lane exchanges combine the groups),
+// and land in the box's alpha~ in LDS.  The
 // compression beta~ = M~^T alpha~ is one sparse row of the level's M~^T per coefficient (the
 // matrix formed once per level on the host from the recursion of Thm. mult_decompression).
 #pragma once
@@ -59,7 +60,12 @@ template <int P>
 __device__ constexpr InvFactFull<P> kInvFact{};
 
 constexpr int kTile = kThreads;  // points staged per pass
-constexpr int kRedStride = 17;   // LDS row stride of the reduction transpose (16 values + pad)
+// values per pass of the reduction transpose: 8 for FP64, whose buffers would otherwise limit
+// the resident workgroups (44 KB per workgroup instead of 28 KB at p = 8), 16 for FP32
+template <typename R>
+constexpr int kRedW = sizeof(R) == 8 ? 8 : 16;
+template <typename R>
+constexpr int kRedStride = kRedW<R> + 1;  // LDS row stride (one element of padding against bank conflicts)
 
 template <typename R, bool CPLX>
 struct Stage {
@@ -130,22 +136,26 @@ __device__ __forceinline__ void accumulate_point(R (&ar)[B - A > 0 ? B - A : 1],
 }
 
 // Sum over the 64 lanes of v[0 .. N-1] (one value per lane each) into dst[k * DS] * scale[k],
-// through the wavefront's LDS transpose buffer buf [64][kRedStride].
+// through the wavefront's LDS transpose buffer buf [64][kRedStride<R>], kRedW<R> values per pass:
+// lane (g, k) adds value k of the kRedW lanes of group g, then the groups are combined by
+// lane exchanges.
 template <int N, int DS, typename R>
 __device__ __forceinline__ void wave_sum(const R (&v)[N > 0 ? N : 1], R* buf, int lane, double* dst,
                                          const double* scale) {
-  const int k = lane & 15, g = lane >> 4;
+  constexpr int RW = kRedW<R>, RS = kRedStride<R>;
+  const int k = lane & (RW - 1), g = lane / RW;
 #pragma unroll
-  for (int j = 0; j < (N + 15) / 16; ++j) {
+  for (int j = 0; j < (N + RW - 1) / RW; ++j) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) buf[lane * kRedStride + i] = (16 * j + i < N) ? v[16 * j + i] : R(0);
+    for (int i = 0; i < RW; ++i) buf[lane * RS + i] = (RW * j + i < N) ? v[RW * j + i] : R(0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // this wavefront's writes are in LDS
     double s = 0.0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) s += (double)buf[(16 * g + r) * kRedStride + k];
+    for (int r = 0; r < RW; ++r) s += (double)buf[(RW * g + r) * RS + k];
+    if constexpr (RW <= 8) s += xchg<8>(s);
     s += xchg<16>(s);
     s += xchg<32>(s);
-    if (g == 0 && 16 * j + k < N) dst[(16 * j + k) * DS] = s * scale[16 * j + k];
+    if (g == 0 && RW * j + k < N) dst[(RW * j + k) * DS] = s * scale[RW * j + k];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // reads done before the next writes
   }
 }
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
   constexpr int NP = nfull(P);
   __shared__ double alpha[NP * (CPLX ? 2 : 1)];
   __shared__ Stage<R, CPLX> st;
-  __shared__ R red[kWaves][64 * kRedStride];
+  __shared__ R red[kWaves][64 * kRedStride<R>];
   const int64_t b = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   int lev = a.level[b];
