@@ -9,6 +9,8 @@
         zeros at the indices not kept, translate uncompressed, compress again)
   L2L   theta' = [T_L M theta]_j                          (Sec. 4.2: decompress, translate
         with eq. l2l-expr, keep the entries of j)
+  P2L   theta = sum_y w(y) [D^p G(c - y)]_j              (Sec. 3.2, eq. stored_local_coeffs)
+  M2P   phi(x) = [D^p G(x - c)]_j^T beta                  (Sec. 3.5, eq. multipole_eval_beta)
 
 Scaled form (Sec. 4.1.1) with parameter t:
   beta~_q = beta_q t^|q|,  table~_m = G^(m) / t^|m|,  theta~_i = theta_i / t^|i|,
@@ -91,6 +93,32 @@ def l2l(kernel: str, param: float, p: int, h, theta) -> np.ndarray:
     (eq. l2l-expr), keep the entries of j (Sec. 4.2)."""
     full = l2l_full(p, h, local_full(kernel, param, p, theta))
     return full[position_map(p, kept(kernel, param, p))]
+
+
+# ----------------------------------------------------------------------------- from and to points
+
+def p2l(kernel: str, param: float, p: int, center, src, w, mp: bool = False) -> np.ndarray:
+    """Compressed local expansion straight from the sources (Sec. 3.2, eq. stored_local_coeffs,
+    with the density restored): theta = sum_y w(y) [D^p G(c - y)]_j, derivative form like the
+    M2L's output (the 1/i! comes after decompression, eq. compressed-local-form)."""
+    J = kept(kernel, param, p)
+    deriv = deriv_table_mp if mp else deriv_table_rec
+    src = np.asarray(src, np.float64)
+    w = np.asarray(w)
+    out = np.zeros(len(J), dtype=np.complex128 if np.iscomplexobj(w) or kernel == "helmholtz" else np.float64)
+    for y, wy in zip(src, w):
+        out = out + wy * deriv(kernel, param, np.asarray(center, np.float64) - y, J)
+    return out
+
+
+def m2p(kernel: str, param: float, p: int, center, beta, tgt, mp: bool = False) -> np.ndarray:
+    """Compressed multipole evaluation (Sec. 3.5, eq. multipole_eval_beta):
+    phi(x) = [D^p G(x - c)]_j^T beta for every target x."""
+    J = kept(kernel, param, p)
+    deriv = deriv_table_mp if mp else deriv_table_rec
+    beta = np.asarray(beta)
+    return np.array([deriv(kernel, param, np.asarray(x, np.float64) - np.asarray(center, np.float64), J) @ beta
+                     for x in np.asarray(tgt, np.float64)])
 
 
 # ----------------------------------------------------------------------------- scaled form
