@@ -169,6 +169,37 @@ int fmm_m2m(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_
 int fmm_l2l(fmm_plan plan, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
             const double* box_center, const int32_t* box_level, void* local, void* stream);
 
+/* Compressed M2P (Sec. 3.5, eq. multipole_eval_beta): multipoles evaluated directly at targets
+ * (the W list of an adaptive tree).  For each k < n_tbox and every target x of box tbox[k],
+ *   potential[x] += sum over the boxes s of list[list_ptr[k] : list_ptr[k+1]] of
+ *                   sum_{q in J} mpole[s][q] G^(q)(x - c_s) h_s^|q|
+ * (the scaled multipoles of fmm_p2m, h_s the size of s's level).  The derivatives at each
+ * target are computed on the kept set only (m_z < c, |m| <= p) by the FP64 recurrences of
+ * fmm_deriv_tables; the sums are FP64, rounded to the dtype when added.
+ *   tbox [n_tbox] i32 box ids, each at most once (its targets are written by one workgroup);
+ *   list_ptr [n_tbox + 1] i32 CSR pointers into list [n_list] i32 box ids (pointers clamped to
+ *   [0, n_list]; ids outside [0, n_box) skipped)
+ *   box_center [n_box][3] f64, box_level [n_box] i32, tgt_range [n_box][2] i64 target ranges
+ *   tgt_xyz [n_tgt][3] real dtype; mpole [n_box][Nc] dtype; potential [n_tgt] dtype, ACCUMULATED.
+ * Deterministic. */
+int fmm_m2p(fmm_plan plan, int64_t n_tbox, const int32_t* tbox, const int32_t* list_ptr, int64_t n_list,
+            const int32_t* list, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* tgt_range, int64_t n_tgt, const void* tgt_xyz, const void* mpole, void* potential,
+            void* stream);
+
+/* Compressed P2L (Sec. 3.2, eq. stored_local_coeffs, with the density): source points formed
+ * directly into local expansions (the X list of an adaptive tree).  For each k < n_tbox,
+ *   local[t][j] += sum over the boxes s of list[list_ptr[k] : list_ptr[k+1]] and their sources y
+ *                  of w(y) G^(j)(c_t - y) h_t^|j|,   t = tbox[k], j in J
+ * (the scaled derivative-form local of fmm_m2l_batched, h_t the size of t's level; fmm_l2p
+ * evaluates it).  Derivatives as in fmm_m2p.  Arguments as fmm_m2p with src_range [n_box][2] i64
+ * source ranges, src_xyz [n_src][3] real dtype, weight [n_src] dtype, and local [n_box][Nc]
+ * dtype, ACCUMULATED; each target box at most once.  Deterministic. */
+int fmm_p2l(fmm_plan plan, int64_t n_tbox, const int32_t* tbox, const int32_t* list_ptr, int64_t n_list,
+            const int32_t* list, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* src_range, int64_t n_src, const void* src_xyz, const void* weight, void* local,
+            void* stream);
+
 /* Near field (P2P): eq. (1) restricted to neighbour boxes.  For each k < n_tbox and every
  * target x of box tbox[k], phi(x) += sum_y G(x - y) w(y) over the sources y of the boxes
  * nbr[nbr_ptr[k] : nbr_ptr[k+1]] (terms with x == y skipped).  With the far field of the

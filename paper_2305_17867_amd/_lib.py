@@ -66,6 +66,8 @@ SIGNATURES = {
     "fmm_direct": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P]),
     "fmm_p2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, C.c_int64, P, P,
                           C.c_int64, P, P, P]),
+    "fmm_m2p": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
+    "fmm_p2l": (C.c_int, [P, C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
     "fmm_l2p_adjoint": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]),
     "fmm_p2m_adjoint": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]),
     "fmm_m2l_prepare_adjoint": (C.c_int, [P, C.c_int64, I32P, I32P, C.c_int64, I32P, I32P,

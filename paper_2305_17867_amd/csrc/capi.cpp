@@ -534,6 +534,70 @@ int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const v
   return launch_direct(a, desc->dtype, (hipStream_t)stream);
 }
 
+static int point_exp_args(fmm_plan plan, int64_t n_tbox, const int32_t* tbox, const int32_t* list_ptr,
+                          int64_t n_list, const int32_t* list, int64_t n_box, const double* box_center,
+                          const int32_t* box_level, const int64_t* range, int64_t n_pts, const void* xyz,
+                          PointExpArgs& a) {
+  int st = check_plan(plan);
+  if (st) return st;
+  FMM_REQUIRE(n_tbox >= 0 && n_tbox <= (int64_t)0x7fffffff, FMM_EINVAL, "n_tbox out of range");
+  FMM_REQUIRE(n_list >= 0 && n_list <= (int64_t)0x7fffffff && n_box >= 0 && n_box <= (int64_t)0x7fffffff &&
+                  n_pts >= 0,
+              FMM_EINVAL, "negative or too large size");
+  if (n_tbox == 0) return FMM_OK;
+  FMM_REQUIRE(tbox && list_ptr && (n_list == 0 || list), FMM_EINVAL, "NULL box list");
+  FMM_REQUIRE(box_center && box_level && range, FMM_EINVAL, "NULL box arrays");
+  FMM_REQUIRE(n_pts == 0 || xyz, FMM_EINVAL, "NULL point array");
+  a.n_tbox = n_tbox;
+  a.tbox = tbox;
+  a.list_ptr = list_ptr;
+  a.list = list;
+  a.n_list = n_list;
+  a.n_box = n_box;
+  a.center = box_center;
+  a.level = box_level;
+  a.range = range;
+  a.level_h = plan->d_level_h;
+  a.n_levels = plan->n_levels;
+  a.n_pts = n_pts;
+  a.xyz = xyz;
+  a.jxyz = plan->d_jxyz;
+  a.nc = plan->nc;
+  a.p = plan->p;
+  a.c = plan->c;
+  a.kernel = plan->desc.kernel;
+  a.param = plan->desc.param;
+  return FMM_OK;
+}
+
+int fmm_m2p(fmm_plan plan, int64_t n_tbox, const int32_t* tbox, const int32_t* list_ptr, int64_t n_list,
+            const int32_t* list, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* tgt_range, int64_t n_tgt, const void* tgt_xyz, const void* mpole, void* potential,
+            void* stream) {
+  PointExpArgs a{};
+  int st = point_exp_args(plan, n_tbox, tbox, list_ptr, n_list, list, n_box, box_center, box_level, tgt_range,
+                          n_tgt, tgt_xyz, a);
+  if (st || n_tbox == 0) return st;
+  FMM_REQUIRE(mpole && (n_tgt == 0 || potential), FMM_EINVAL, "NULL multipole or potential array");
+  a.mpole = mpole;
+  a.out = potential;
+  return launch_m2p(a, plan->desc.dtype, (hipStream_t)stream);
+}
+
+int fmm_p2l(fmm_plan plan, int64_t n_tbox, const int32_t* tbox, const int32_t* list_ptr, int64_t n_list,
+            const int32_t* list, int64_t n_box, const double* box_center, const int32_t* box_level,
+            const int64_t* src_range, int64_t n_src, const void* src_xyz, const void* weight, void* local,
+            void* stream) {
+  PointExpArgs a{};
+  int st = point_exp_args(plan, n_tbox, tbox, list_ptr, n_list, list, n_box, box_center, box_level, src_range,
+                          n_src, src_xyz, a);
+  if (st || n_tbox == 0) return st;
+  FMM_REQUIRE(local && (n_src == 0 || weight), FMM_EINVAL, "NULL local or weight array");
+  a.w = weight;
+  a.out = local;
+  return launch_p2l(a, plan->desc.dtype, (hipStream_t)stream);
+}
+
 int fmm_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* nbr_ptr, int64_t n_nbr,
             const int32_t* nbr, int64_t n_box, const int64_t* tgt_range, const int64_t* src_range, int64_t n_src,
             const void* src_xyz, const void* weight, int64_t n_tgt, const void* tgt_xyz, void* potential,

@@ -87,6 +87,29 @@ struct L2PArgs {
   const double* dec_val;
 };
 
+// Compressed P2L and M2P over lists of boxes (fmm_p2l, fmm_m2p): for each k < n_tbox, the
+// target box tbox[k] and the boxes list[list_ptr[k] .. list_ptr[k + 1]).
+struct PointExpArgs {
+  int64_t n_tbox;
+  const int32_t* tbox;
+  const int32_t* list_ptr;  // [n_tbox + 1], clamped to [0, n_list]
+  const int32_t* list;      // [n_list] box ids (ids outside [0, n_box) are skipped)
+  int64_t n_list, n_box;
+  const double* center;     // [n_box][3]
+  const int32_t* level;     // [n_box]
+  const int64_t* range;     // [n_box][2] point ranges (targets for M2P, sources for P2L)
+  const double* level_h;    // [n_levels]
+  int32_t n_levels;
+  int64_t n_pts;
+  const void* xyz;          // [n_pts][3] real
+  const void* w;            // P2L: [n_pts] weights
+  const void* mpole;        // M2P: [n_box][Nc]
+  void* out;                // M2P: [n_pts] potential; P2L: [n_box][Nc] local (both accumulated)
+  const int32_t* jxyz;      // [Nc] kept index m packed as m_x | m_y << 8 | m_z << 16
+  int32_t nc, p, c, kernel;
+  double param;
+};
+
 struct TableArgs {
   int64_t n;
   const double* offset;  // [n][3] units of h
@@ -231,6 +254,8 @@ struct P2PArgs {
 };
 
 int launch_tables(const TableArgs& a, bool cplx, hipStream_t s);
+int launch_m2p(const PointExpArgs& a, int dtype, hipStream_t s);
+int launch_p2l(const PointExpArgs& a, int dtype, hipStream_t s);
 int launch_p2p(const P2PArgs& a, int dtype, hipStream_t s);
 int launch_p2m(const P2MArgs& a, int p, int dtype, hipStream_t s);
 int launch_m2m(const TransArgs& a, int p, int dtype, hipStream_t s);

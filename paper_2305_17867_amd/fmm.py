@@ -178,6 +178,39 @@ class Plan:
                                   _ptr(local), _ptr(pot), _stream()), "fmm_l2p")
         return pot
 
+    def _lists(self, tbox, list_ptr, lst, center, level, rng, xyz):
+        nt, nb = tbox.shape[0], center.shape[0]
+        _dev(tbox, torch.int32, "tbox", (nt,))
+        _dev(list_ptr, torch.int32, "list_ptr", (nt + 1,))
+        _dev(lst, torch.int32, "list", (lst.shape[0],))
+        _dev(center, torch.float64, "box_center", (nb, 3))
+        _dev(level, torch.int32, "box_level", (nb,))
+        _dev(rng, torch.int64, "range", (nb, 2))
+        _dev(xyz, self.desc.real_dtype, "xyz", (xyz.shape[0], 3))
+        return nt, nb
+
+    def m2p(self, tbox, list_ptr, lst, center, level, tgt_range, tgt, mpole, pot) -> torch.Tensor:
+        """pot[targets of tbox[k]] += compressed multipoles mpole[s] of the boxes s in
+        lst[list_ptr[k] : list_ptr[k + 1]] evaluated at the targets (fmm_m2p)."""
+        nt, nb = self._lists(tbox, list_ptr, lst, center, level, tgt_range, tgt)
+        _dev(mpole, self.desc.value_dtype, "mpole", (nb, self.nc))
+        _dev(pot, self.desc.value_dtype, "potential", (tgt.shape[0],))
+        check(_lib.load().fmm_m2p(self._h, nt, _ptr(tbox), _ptr(list_ptr), lst.shape[0], _ptr(lst), nb, _ptr(center),
+                                  _ptr(level), _ptr(tgt_range), tgt.shape[0], _ptr(tgt), _ptr(mpole), _ptr(pot),
+                                  _stream()), "fmm_m2p")
+        return pot
+
+    def p2l(self, tbox, list_ptr, lst, center, level, src_range, src, w, local) -> torch.Tensor:
+        """local[tbox[k]] += compressed locals formed straight from the sources of the boxes in
+        lst[list_ptr[k] : list_ptr[k + 1]] (fmm_p2l)."""
+        nt, nb = self._lists(tbox, list_ptr, lst, center, level, src_range, src)
+        _dev(w, self.desc.value_dtype, "weight", (src.shape[0],))
+        _dev(local, self.desc.value_dtype, "local", (nb, self.nc))
+        check(_lib.load().fmm_p2l(self._h, nt, _ptr(tbox), _ptr(list_ptr), lst.shape[0], _ptr(lst), nb, _ptr(center),
+                                  _ptr(level), _ptr(src_range), src.shape[0], _ptr(src), _ptr(w), _ptr(local),
+                                  _stream()), "fmm_p2l")
+        return local
+
     def _tree(self, parent, child, center, level, coef, name):
         npar = parent.shape[0]
         nb = center.shape[0]
