@@ -45,7 +45,7 @@ HBM_PEAK = 8.0e12  # bytes/s
 POINT_FLOPS = {8: 276, 12: 788}
 DEPTH, NPTS, SEED = 4, 1 << 20, 1
 COPY_BYTES = 256 << 20  # plain copy used to calibrate the FETCH_SIZE / WRITE_SIZE counters
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_kernel_laplace_p8_f64_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_stream_kernel_laplace_p8_f64_traffic.txt")
 # sources that decide the M2L kernel's memory traffic at the headline configuration
 TRAFFIC_SOURCES = ["paper_2305_17867_amd/csrc/m2l_stream.hip", "paper_2305_17867_amd/csrc/m2l.hip",
                    "paper_2305_17867_amd/csrc/kernels.hpp", "paper_2305_17867_amd/csrc/capi.cpp",
