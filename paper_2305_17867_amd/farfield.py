@@ -30,7 +30,13 @@ from . import fmm
 
 class FarField:
     def __init__(self, kernel: str, order: int, dtype: str, src_tree: "W.Tree", tgt_tree: "W.Tree",
-                 param: float = 0.0, levels=None, device="cuda", tree_pass: bool = False):
+                 param: float = 0.0, levels=None, device="cuda", tree_pass: bool = False, wx_lists=None):
+        """wx_lists: (W, X) of ``workloads.adaptive_lists`` for one tree (sources and targets the
+        same boxes): the forward then also evaluates the multipoles of each leaf's W boxes at
+        its targets (compressed M2P, Sec. 3.5) and forms the locals of each X box from its X
+        leaves' sources (compressed P2L, Sec. 3.2), the interactions that the near lists of
+        ``near_lists`` would otherwise leave to the direct sum (use the U lists for the near
+        field then).  Forward only."""
         assert src_tree.n_levels == tgt_tree.n_levels and np.array_equal(src_tree.ijk, tgt_tree.ijk), \
             "source and target trees must share the box grid (one tree, or uniform trees of one depth)"
         self.desc = fmm.Desc(kernel, order, dtype, param)
@@ -54,6 +60,11 @@ class FarField:
         lo, hi = self.level_boxes[self.levels[0]][0], self.level_boxes[self.levels[-1]][1]
         self.box_lo, self.box_hi = lo, hi  # boxes with multipoles / locals
         self.tree_pass = tree_pass
+        self.wx = None
+        if wx_lists is not None:
+            i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int32, device=dev)
+            (wb, wp, wl), (xb, xp, xl) = wx_lists
+            self.wx = ((i32(wb), i32(wp), i32(wl)), (i32(xb), i32(xp), i32(xl)))
         if tree_pass:
             self.leaf = n_lev - 1
             assert self.levels == list(range(self.levels[0], n_lev)), \
@@ -91,11 +102,25 @@ class FarField:
             self.plan.p2m(self.center[a:b], self.level[a:b], self.src_rng[a:b], src, w, out=mpole[a:b])
         local = torch.zeros_like(mpole)
         self.batch(mpole, local)
+        self._p2l(w, src, local)
         pot = torch.zeros(tgt.shape[0], dtype=d.value_dtype, device=w.device)
         for l in self.levels:
             a, b = self.level_boxes[l]
             self.plan.l2p(self.center[a:b], self.level[a:b], self.tgt_rng[a:b], tgt, local[a:b], pot)
+        self._m2p(tgt, mpole, pot)
         return pot, mpole, local
+
+    def _p2l(self, w, src, local):
+        """X lists: locals of the X boxes straight from the sources of their X leaves."""
+        if self.wx is not None and self.wx[1][0].shape[0]:
+            xb, xp, xl = self.wx[1]
+            self.plan.p2l(xb, xp, xl, self.center, self.level, self.src_rng, src, w, local)
+
+    def _m2p(self, tgt, mpole, pot):
+        """W lists: multipoles of the W boxes at the targets of their leaves."""
+        if self.wx is not None and self.wx[0][0].shape[0]:
+            wb, wp, wl = self.wx[0]
+            self.plan.m2p(wb, wp, wl, self.center, self.level, self.tgt_rng, tgt, mpole, pot)
 
     def _forward_tree(self, w, src, tgt):
         d = self.desc
@@ -108,6 +133,7 @@ class FarField:
                 self.plan.m2m(*self.family[l], self.center, self.level, mpole)
         local = torch.zeros_like(mpole)
         self.batch(mpole, local)
+        self._p2l(w, src, local)
         for l in range(self.levels[0], self.leaf):  # parents before children
             if l in self.family:
                 self.plan.l2l(*self.family[l], self.center, self.level, local)
@@ -115,6 +141,7 @@ class FarField:
         for l in self.leaf_levels:
             a, b = self.level_boxes[l]
             self.plan.l2p(self.center[a:b], self.level[a:b], self.tgt_leaf_rng[a:b], tgt, local[a:b], pot)
+        self._m2p(tgt, mpole, pot)
         return pot, mpole, local
 
     def _backward_tree(self, g, w, src, tgt, local, need_w, need_src, need_tgt):
@@ -142,6 +169,8 @@ class FarField:
         return w_grad, src_grad, tgt_grad
 
     def backward_raw(self, g, w, src, tgt, local, need_w=True, need_src=True, need_tgt=True):
+        if self.wx is not None:
+            raise NotImplementedError("the adjoint of the W / X interactions (M2P, P2L) is not implemented")
         if self.batch_t is None:
             raise NotImplementedError("the far-field adjoint is implemented for real dtypes (f64, f32)")
         if self.tree_pass:

@@ -125,21 +125,27 @@ def test_full_fmm_matches_direct_sum(gpu_lib):
     assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)
 
 
-def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128, max_src=None, tree_pass=False):
+def adaptive_fmm(fmm, kernel, param, p, dt, pts, max_leaf, seed, sample=128, max_src=None, tree_pass=False,
+                 wx=False):
     """Far field (per-level form: P2M of every box, M2L over the List-2 pairs of every level,
     L2P of every level's local expansion at its boxes' points) + near field over the adaptive
-    near lists, against the direct sum of eq. (1) at sampled targets."""
+    near lists, against the direct sum of eq. (1) at sampled targets.  wx=True: the W and X
+    interactions by compressed M2P and P2L, and the direct sum over the U lists only."""
     from paper_2305_17867_amd.farfield import FarField
     tr = W.adaptive_tree(pts, max_leaf)
     n = pts.shape[0]
     cplx = kernel == "helmholtz"
     w = W.normal_weights(n, seed, complex_=cplx)
-    ff = FarField(kernel, p, dt, tr, tr, param=param, tree_pass=tree_pass)
+    U = Wl = X = None
+    if wx:
+        U, Wl, X = W.adaptive_lists(tr, max_src)
+        assert len(Wl[0]) and len(X[0])
+    ff = FarField(kernel, p, dt, tr, tr, param=param, tree_pass=tree_pass, wx_lists=(Wl, X) if wx else None)
     d = ff.desc
     P, wd = dev(tr.points, d.real_dtype), dev(w, d.value_dtype)
     with torch.no_grad():
         pot, _, _ = ff.forward_raw(wd, P, P)
-    leaves, ptr, nbr = W.near_lists(tr, max_src)
+    leaves, ptr, nbr = U if wx else W.near_lists(tr, max_src)
     rng = dev(tr.pt_range, torch.int64)
     fmm.p2p(d, dev(leaves, torch.int32), dev(ptr, torch.int32), dev(nbr, torch.int32), rng, rng, P, wd, P, pot)
     idx = np.random.Generator(np.random.PCG64(seed + 1)).choice(n, sample, replace=False)
@@ -160,6 +166,29 @@ def test_adaptive_fmm_matches_direct_sum(gpu_lib, kernel, param, dt, dist):
         assert e4 < 2e-2 and e8 < 5e-5, (e4, e8)
     else:
         assert e4 < 2e-2 and e8 < 1e-4 and e8 < 0.1 * e4, (e4, e8)
+
+
+@pytest.mark.parametrize("kernel,param,dt,dist,tree_pass", [("laplace", 0.0, "f64", "plummer", False),
+                                                            ("laplace", 0.0, "f64", "plummer", True),
+                                                            ("helmholtz", 2.0, "c128", "plummer", True),
+                                                            ("yukawa", 2.0, "f64", "mixture", False),
+                                                            ("biharmonic", 0.0, "f64", "mixture", True),
+                                                            ("laplace", 0.0, "f32", "mixture", True)])
+def test_adaptive_fmm_with_w_and_x_lists_matches_direct_sum(gpu_lib, kernel, param, dt, dist, tree_pass):
+    """The complete adaptive FMM with the W interactions as compressed M2P, the X interactions
+    as compressed P2L (Secs. 3.5, 3.2) and the direct sum over the U lists only: the error
+    against the direct sum falls with the order and stays within 3x of the error with W and X
+    left to the direct sum (the added expansions are separated by at least one box of the
+    smaller size)."""
+    pts = W.plummer_points(6000, 81) if dist == "plummer" else W.gaussian_mixture_points(6000, 82)
+    e4, tr = adaptive_fmm(gpu_lib, kernel, param, 4, dt, pts, 32, 83, tree_pass=tree_pass, wx=True)
+    e8, _ = adaptive_fmm(gpu_lib, kernel, param, 8, dt, pts, 32, 83, max_src=256, tree_pass=tree_pass, wx=True)
+    b8, _ = adaptive_fmm(gpu_lib, kernel, param, 8, dt, pts, 32, 83, max_src=256, tree_pass=tree_pass)
+    assert len(set(tr.level[tr.is_leaf].tolist())) >= 3
+    if dt == "f32":
+        assert e4 < 5e-2 and e8 < 2e-4, (e4, e8, b8)
+    else:
+        assert e4 < 5e-2 and e8 < 3e-4 and e8 < 0.1 * e4 and e8 < 3 * b8 + 1e-12, (e4, e8, b8)
 
 
 @pytest.mark.parametrize("dt", ["f64", "c128", "f32"])

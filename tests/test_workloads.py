@@ -153,3 +153,57 @@ def test_near_lists_of_a_uniform_tree_are_the_neighbour_lists():
     b = W.neighbours(tr, 2)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("points,max_leaf", [("plummer", 16), ("mixture", 24), ("uniform", 40)])
+def test_adaptive_lists_partition_every_leaf_pair(points, max_leaf):
+    """U (direct sum), W (multipole at the targets), X (sources into a local) and the List-2
+    pairs of every level count every (target leaf, source leaf) pair exactly once, and W and X
+    boxes are separated from the box they serve: a W box does not touch its leaf but its parent
+    does; an X leaf does not touch its box but touches the box's parent.  Brute force over all
+    leaf pairs."""
+    pts = {"plummer": lambda: W.plummer_points(3000, 11),
+           "mixture": lambda: W.gaussian_mixture_points(3000, 12),
+           "uniform": lambda: W.uniform_points(3000, 13)}[points]()
+    tr = W.adaptive_tree(pts, max_leaf)
+    (ub, up, ul), (wb, wp, wl), (xb, xp, xl) = W.adaptive_lists(tr)
+    leaves = np.flatnonzero(tr.is_leaf).astype(np.int64)
+    lv = tr.level.astype(np.int64)
+    ijk = tr.ijk.astype(np.int64)
+    parent = {}
+    for l in range(tr.n_levels - 1):
+        par, ch = W.children(tr, l)
+        for k, pb in enumerate(par):
+            for c in ch[k]:
+                if c >= 0:
+                    parent[int(c)] = int(pb)
+
+    def anc_or_self(b):
+        out = [int(b)]
+        while out[-1] in parent:
+            out.append(parent[out[-1]])
+        return out
+
+    # separation of W and X
+    for k, b in enumerate(wb):
+        for w_ in wl[wp[k]:wp[k + 1]]:
+            assert not W._touch(tr, int(w_), int(b)) and W._touch(tr, parent[int(w_)], int(b))
+    for k, a in enumerate(xb):
+        for x_ in xl[xp[k]:xp[k + 1]]:
+            assert tr.is_leaf[x_] and lv[x_] < lv[a]
+            assert not W._touch(tr, int(x_), int(a)) and W._touch(tr, int(x_), parent[int(a)])
+    U = {int(b): set(ul[up[k]:up[k + 1]].tolist()) for k, b in enumerate(ub)}
+    Wd = {int(b): set(wl[wp[k]:wp[k + 1]].tolist()) for k, b in enumerate(wb)}
+    Xd = {int(a): set(xl[xp[k]:xp[k + 1]].tolist()) for k, a in enumerate(xb)}
+    t, s = W.interaction_pairs(tr)
+    V = set(zip(t.tolist(), s.tolist()))
+    anc = {int(b): anc_or_self(b) for b in leaves}
+    for b in leaves:
+        b = int(b)
+        for sl in leaves:
+            sl = int(sl)
+            n = int(sl in U.get(b, ()))
+            n += sum((ta, sa) in V for ta in anc[b] for sa in anc[sl] if lv[ta] == lv[sa])
+            n += sum(a in Wd.get(b, ()) for a in anc[sl])
+            n += sum(sl in Xd.get(a, ()) for a in anc[b])
+            assert n == 1, (b, sl, n)

@@ -284,6 +284,108 @@ def near_lists(tree: Tree, max_src: int | None = None) -> tuple[np.ndarray, np.n
     return np.asarray(owner, dtype=np.int32), np.asarray(ptr, dtype=np.int32), np.asarray(src, dtype=np.int32)
 
 
+def _touch(tree: Tree, a: int, b: int) -> bool:
+    """Whether the closed cubes of boxes a and b (any levels) intersect."""
+    la, lb = int(tree.level[a]), int(tree.level[b])
+    L = max(la, lb)
+    lo_a = tree.ijk[a].astype(np.int64) << (L - la)
+    lo_b = tree.ijk[b].astype(np.int64) << (L - lb)
+    hi_a = lo_a + (1 << (L - la))
+    hi_b = lo_b + (1 << (L - lb))
+    return bool(np.all((lo_a <= hi_b) & (lo_b <= hi_a)))
+
+
+def adaptive_lists(tree: Tree, max_src: int | None = None):
+    """The near-field lists of an adaptive octree split by what each interaction needs, in
+    CSR form (box [n] int32, ptr [n + 1] int32, list int32):
+
+      U  per leaf b: the leaves touching b (b included): the direct sum (P2P);
+      W  per leaf b: boxes w whose parent touches b but which do not touch b themselves, the
+         children of b's colleagues (same-level boxes touching b) found by descending while
+         boxes touch b: w's multipole is evaluated at b's targets (M2P);
+      X  per box a (any level): leaves x coarser than a that touch a's parent but not a:
+         x's sources form a's local expansion directly (P2L), which L2L carries to the leaves.
+
+    These are the interactions that ``near_lists`` gives to the direct sum; with the List-2
+    pairs of every level (``interaction_pairs``) every (target leaf, source leaf) pair is
+    counted exactly once.  With max_src, U lists are split as in ``near_lists``."""
+    leaves0, ptr0, src0 = near_lists(tree)
+    kid = {}
+    for b in range(tree.n_box):
+        kid[(int(tree.level[b]),) + tuple(int(v) for v in tree.ijk[b])] = b
+
+    def children(n):
+        lev, base = int(tree.level[n]) + 1, 2 * tree.ijk[n].astype(np.int64)
+        out = []
+        for o in range(8):
+            c = kid.get((lev, int(base[0]) + (o & 1), int(base[1]) + ((o >> 1) & 1), int(base[2]) + ((o >> 2) & 1)))
+            if c is not None:
+                out.append(c)
+        return out
+
+    def ancestor(b, lev):
+        lb = int(tree.level[b])
+        return kid[(lev,) + tuple(int(v) >> (lb - lev) for v in tree.ijk[b])]
+
+    u_lists, w_lists, x_sets = {}, {}, {}
+    for k, b in enumerate(leaves0):
+        b = int(b)
+        lb = int(tree.level[b])
+        u, w = [], []
+        for n in src0[ptr0[k]:ptr0[k + 1]]:
+            n = int(n)
+            if int(tree.level[n]) == lb:  # b itself or a colleague: descend while touching b
+                stack = [n]
+                while stack:
+                    m = stack.pop()
+                    if tree.is_leaf[m]:
+                        u.append(m)
+                        continue
+                    for c in children(m):
+                        (stack if _touch(tree, c, b) else w).append(c)
+            elif _touch(tree, n, b):  # a coarser leaf touching b
+                u.append(n)
+            else:  # a coarser leaf: X of the first ancestor of b it does not touch
+                for lev in range(int(tree.level[n]) + 1, lb + 1):
+                    a = ancestor(b, lev)
+                    if not _touch(tree, n, a):
+                        x_sets.setdefault(a, set()).add(n)
+                        break
+        u_lists[b] = sorted(u)
+        w_lists[b] = sorted(w)
+
+    def csr(d, keys):
+        box, ptr, lst = [], [0], []
+        for key in keys:
+            if not d.get(key):
+                continue
+            box.append(key)
+            lst += list(d[key])
+            ptr.append(len(lst))
+        return np.asarray(box, np.int32), np.asarray(ptr, np.int32), np.asarray(lst, np.int32)
+
+    leaves = [int(b) for b in leaves0]
+    U = csr(u_lists, leaves)
+    if max_src is not None:
+        count = tree.pt_range[:, 1] - tree.pt_range[:, 0]
+        owner, ptr, src = [], [0], []
+        for k, b in enumerate(U[0]):
+            run = 0
+            for n in U[2][U[1][k]:U[1][k + 1]]:
+                if run and run + count[n] > max_src:
+                    owner.append(b)
+                    ptr.append(len(src))
+                    run = 0
+                src.append(int(n))
+                run += count[n]
+            owner.append(b)
+            ptr.append(len(src))
+        U = (np.asarray(owner, np.int32), np.asarray(ptr, np.int32), np.asarray(src, np.int32))
+    Wl = csr(w_lists, leaves)
+    X = csr({a: sorted(v) for a, v in x_sets.items()}, sorted(x_sets))
+    return U, Wl, X
+
+
 def _point_keys(points: np.ndarray) -> np.ndarray:
     scale = float(1 << MAX_DEPTH)
     ijk = np.floor(points * scale).astype(np.int64)
