@@ -571,12 +571,33 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
     counts = tr.pt_range[:, 1] - tr.pt_range[:, 0]
     inter = int(sum(int(counts[b]) * int(counts[nbr[ptr[k]:ptr[k + 1]]].sum()) for k, b in enumerate(leaves)))
     leaf_levels = np.bincount(tr.level[tr.is_leaf])
+    # the same with the W interactions as compressed M2P and the X interactions as compressed P2L
+    # (Secs. 3.5, 3.2), and the direct sum over the touching leaves (U lists) only
+    U, Wl, X = W.adaptive_lists(tr, max_src=2048)
+    ff_wx = FarField("laplace", 8, "f64", tr, tr, tree_pass=True, wx_lists=(Wl, X))
+    ulists = [torch.as_tensor(a, device=dev) for a in U]
+
+    def far_wx():
+        with torch.no_grad():
+            out["pot_wx"] = ff_wx.forward_raw(wd, pts, pts)[0]
+
+    def near_u():
+        fmm.p2p(d, *ulists, rng, rng, pts, wd, pts, out["pot_wx"])
+
+    t_far_wx = time_kernel(torch, far_wx, reps)
+    t_near_u = time_kernel(torch, near_u, reps)
+    far_wx()
+    near_u()
+    err_wx = float(torch.linalg.norm(out["pot_wx"][torch.as_tensor(idx, device=dev)] - ref) / torch.linalg.norm(ref))
     return {"workload": "adaptive octree, 524288 Gaussian-mixture points, <= 64 per leaf, laplace p8 f64: "
                         "far field (tree pass) + near field",
             "leaves": int(tr.is_leaf.sum()), "near_entries": int(len(leaves)), "leaf_levels": {int(l): int(c) for l, c in enumerate(leaf_levels) if c},
             "m2l_pairs": ff.n_pair, "far_ms": t_far * 1e3, "far_per_level_ms": t_far_level * 1e3,
             "near_ms": t_near * 1e3, "near_interactions": inter,
-            "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample}
+            "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample,
+            "w_x_lists": {"w_boxes": int(len(Wl[2])), "x_leaves": int(len(X[2])),
+                          "far_with_m2p_p2l_ms": t_far_wx * 1e3, "near_u_ms": t_near_u * 1e3,
+                          "rel_error_vs_direct": err_wx}}
 
 
 def mixed_batch(torch, fmm, checks, reps=10):
