@@ -12,8 +12,8 @@
  * NULL = the default stream), return at once, never allocate device memory and
  * never synchronise, so they may be captured into a HIP graph.  The set-up and
  * tear-down calls allocate, free or synchronise: fmm_plan_create, the
- * fmm_m2l_prepare* calls (_ex, _fft, _adjoint), fmm_m2l_multi_prepare and the
- * fmm_*_destroy calls.
+ * fmm_m2l_prepare* calls (_ex, _fft, _adjoint), fmm_m2l_multi_prepare, the
+ * fmm_tree_* calls and the fmm_*_destroy calls.
  *
  * Every entry point returns an fmm_status.  Arguments are validated on the host
  * before anything is enqueued; on a non-OK status nothing was enqueued and
@@ -386,6 +386,75 @@ int fmm_p2m_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, cons
  *   potential [n_tgt] dtype, OVERWRITTEN. */
 int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const void* weight,
                int64_t n_tgt, const void* tgt_xyz, void* potential, void* stream);
+
+/* ---- Octree and interaction lists on the device (the box hierarchy of Sec. 1 over which
+ * the operators above run; the adaptive lists of the classical adaptive FMM).  Integer work:
+ * every result is exact and equals what a host builder of the same definitions gives.
+ *
+ * Box order: level by level (level 0 = the unit cube [0,1)^3), within a level by increasing
+ * Morton key of the box's integer coordinates ijk (bits interleaved, x highest within each
+ * triple).  Every box's points are one contiguous range of the sorted points.
+ *
+ * All fmm_tree_* calls allocate and synchronise `stream` (set-up calls; not capturable). ---- */
+
+typedef struct fmm_tree_s* fmm_tree;
+
+#define FMM_TREE_MAX_DEPTH 20         /* key bits per axis */
+#define FMM_TREE_MAX_UNIFORM_DEPTH 10 /* every box of every level is stored */
+
+/* Build a tree over n_points points xyz [n_points][3] float64 (device), coordinates in [0, 1)
+ * (values outside are clamped into the boundary boxes; a non-finite coordinate is FMM_EINVAL).
+ * Each point gets the Morton key of floor(x * 2^20) (per axis, clamped to [0, 2^20 - 1]); points
+ * are sorted by key, ties kept in input order (a stable sort).
+ *   max_leaf == 0: uniform tree, all 8^l boxes of every level l <= depth (empty ones
+ *                  included), leaves = the boxes of level `depth` (<= FMM_TREE_MAX_UNIFORM_DEPTH);
+ *   max_leaf  > 0: adaptive tree: a box is refined when it holds more than max_leaf points and
+ *                  its level is below depth (<= FMM_TREE_MAX_DEPTH); children holding no point
+ *                  are not created; unrefined boxes are leaves. */
+int fmm_tree_build(int64_t n_points, const double* xyz, int32_t max_leaf, int32_t depth, fmm_tree* tree,
+                   void* stream);
+
+/* Sizes: boxes, levels, leaves.  Any output may be NULL; all [host]. */
+int fmm_tree_size(fmm_tree tree, int64_t* n_box, int32_t* n_levels, int64_t* n_leaf);
+
+/* Copy the tree out; every output is optional (NULL skips it).
+ *   perm [n_points] i64: input index of each sorted point;  points [n_points][3] f64: sorted
+ *   level [n_box] i32;  ijk [n_box][3] i32;  center [n_box][3] f64 = (ijk + 1/2) 2^-level
+ *   pt_range [n_box][2] i64: [begin, end) into the sorted points;  is_leaf [n_box] u8
+ *   level_start [host][n_levels + 1] i64: first box of each level. */
+int fmm_tree_export(fmm_tree tree, int64_t* perm, double* points, int32_t* level, int32_t* ijk, double* center,
+                    int64_t* pt_range, uint8_t* is_leaf, int64_t* level_start, void* stream);
+
+/* List-2 (well separated, Sec. 1) pairs of the target boxes on levels [level_lo, level_hi): the
+ * children of the parent's neighbours (parent included) that are not adjacent to the target,
+ * sorted by (target, source).  *n_pair [host] receives the count; tgt_box, src_box [n_pair] i32
+ * are written when not NULL (call once with NULL to size them). */
+int fmm_tree_list2(fmm_tree tree, int32_t level_lo, int32_t level_hi, int64_t* n_pair, int32_t* tgt_box,
+                   int32_t* src_box, void* stream);
+
+enum {
+  FMM_LIST_NEAR = 0, /* per leaf b: existing boxes of b's level adjacent to b (b included), then
+                        on every coarser level the leaves adjacent to b's ancestor there; in the
+                        order (level, offset (di, dj, dk) lexicographic).  With List 2 of every
+                        level each (target leaf, source leaf) pair is counted exactly once. */
+  FMM_LIST_U = 1,    /* per leaf b: the leaves whose closed cube touches b's (b included); sorted */
+  FMM_LIST_W = 2,    /* per leaf b with any: boxes not touching b whose parent touches b, below
+                        b's colleagues (multipoles evaluated at b's targets, M2P); sorted */
+  FMM_LIST_X = 3     /* per box a with any: leaves coarser than a that touch a's parent but not a
+                        (their sources form a's local expansion, P2L); sorted */
+};
+
+/* Rows of the lists of `kind` in CSR form: box [n_row] i32 (the row's box), ptr [n_row + 1] i32,
+ * item [n_item] i32.  U, W and X with the List-2 pairs count every leaf pair exactly once.
+ * max_src > 0 (NEAR and U only): a row whose boxes hold more than max_src points in all is cut
+ * into several rows of the same box: boxes above max_src points are replaced by their children
+ * (depth first, octant order, down to leaves) and the boxes are packed in order into rows of at
+ * most max_src points (a box above the cap alone).  *n_row, *n_item [host] receive the sizes;
+ * box, ptr, item are written when not NULL.  Lists are built on first use and kept by the tree. */
+int fmm_tree_lists(fmm_tree tree, int32_t kind, int64_t max_src, int64_t* n_row, int64_t* n_item, int32_t* box,
+                   int32_t* ptr, int32_t* item, void* stream);
+
+void fmm_tree_destroy(fmm_tree tree);
 
 #ifdef __cplusplus
 }

@@ -77,7 +77,15 @@ SIGNATURES = {
     "fmm_m2l_multi_prepare": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),
     "fmm_m2l_multi_launch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), P]),
     "fmm_m2l_multi_destroy": (None, [P]),
+    "fmm_tree_build": (C.c_int, [C.c_int64, P, C.c_int32, C.c_int32, C.POINTER(P), P]),
+    "fmm_tree_size": (C.c_int, [P, I64P, I32P, I64P]),
+    "fmm_tree_export": (C.c_int, [P, P, P, P, P, P, P, P, I64P, P]),
+    "fmm_tree_list2": (C.c_int, [P, C.c_int32, C.c_int32, I64P, P, P, P]),
+    "fmm_tree_lists": (C.c_int, [P, C.c_int32, C.c_int64, I64P, I64P, P, P, P, P]),
+    "fmm_tree_destroy": (None, [P]),
 }
+LIST_KINDS = {"near": 0, "u": 1, "w": 2, "x": 3}
+TREE_MAX_DEPTH, TREE_MAX_UNIFORM_DEPTH = 20, 10
 
 _LIB = None
 

@@ -30,20 +30,24 @@ from . import fmm
 
 class FarField:
     def __init__(self, kernel: str, order: int, dtype: str, src_tree: "W.Tree", tgt_tree: "W.Tree",
-                 param: float = 0.0, levels=None, device="cuda", tree_pass: bool = False, wx_lists=None):
+                 param: float = 0.0, levels=None, device="cuda", tree_pass: bool = False, wx_lists=None,
+                 pairs=None):
         """wx_lists: (W, X) of ``workloads.adaptive_lists`` for one tree (sources and targets the
         same boxes): the forward then also evaluates the multipoles of each leaf's W boxes at
         its targets (compressed M2P, Sec. 3.5) and forms the locals of each X box from its X
         leaves' sources (compressed P2L, Sec. 3.2), the interactions that the near lists of
         ``near_lists`` would otherwise leave to the direct sum (use the U lists for the near
-        field then).  Forward only."""
+        field then).  Forward only.
+        pairs: (target, source) List-2 pairs of the M2L levels (host int32 arrays, e.g. from the
+        device tree build); default: ``workloads.interaction_pairs`` of src_tree."""
         assert src_tree.n_levels == tgt_tree.n_levels and np.array_equal(src_tree.ijk, tgt_tree.ijk), \
             "source and target trees must share the box grid (one tree, or uniform trees of one depth)"
         self.desc = fmm.Desc(kernel, order, dtype, param)
         n_lev = src_tree.n_levels
         self.levels = list(range(2, n_lev)) if levels is None else list(levels)
         self.plan = fmm.Plan(self.desc, [src_tree.box_size(l) for l in range(n_lev)])
-        t, s = W.interaction_pairs(src_tree, self.levels)
+        t, s = W.interaction_pairs(src_tree, self.levels) if pairs is None else \
+            (np.asarray(pairs[0], dtype=np.int32), np.asarray(pairs[1], dtype=np.int32))
         self.n_pair = len(t)
         self.batch = self.plan.prepare(t, s, src_tree.ijk, src_tree.level)
         # the adjoints are implemented for real dtypes; a complex far field runs forward only

@@ -469,3 +469,96 @@ class Multi:
             self.close()
         except Exception:
             pass
+
+
+class Tree:
+    """Octree and interaction lists built on the device (fmm_tree_*).
+
+    max_leaf == 0: uniform tree of the given depth (every box of every level); max_leaf > 0:
+    adaptive tree, boxes above max_leaf points refined down to level `depth` at most, empty
+    children not created.  Box order: level by level, Morton order within a level; each box's
+    points are one range of the sorted points.  Arrays come back as device tensors."""
+
+    def __init__(self, points: torch.Tensor, max_leaf: int = 0, depth: int = 3):
+        _dev(points, torch.float64, "points")
+        if points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError("points: expected shape (n, 3)")
+        self.n = points.shape[0]
+        self.max_leaf, self.depth = int(max_leaf), int(depth)
+        self.device = points.device
+        self._h = C.c_void_p()
+        L = _lib.load()
+        check(L.fmm_tree_build(self.n, _ptr(points), self.max_leaf, self.depth, C.byref(self._h), _stream()),
+              "fmm_tree_build")
+        nb, nl, nleaf = C.c_int64(), C.c_int32(), C.c_int64()
+        check(L.fmm_tree_size(self._h, C.byref(nb), C.byref(nl), C.byref(nleaf)), "fmm_tree_size")
+        self.n_box, self.n_levels, self.n_leaf = nb.value, nl.value, nleaf.value
+
+    def arrays(self) -> dict:
+        """perm, points (sorted), level, ijk, center, pt_range, is_leaf (device tensors) and
+        level_start (numpy)."""
+        dev, n, nb = self.device, self.n, self.n_box
+        out = {"perm": torch.empty(n, dtype=torch.int64, device=dev),
+               "points": torch.empty((n, 3), dtype=torch.float64, device=dev),
+               "level": torch.empty(nb, dtype=torch.int32, device=dev),
+               "ijk": torch.empty((nb, 3), dtype=torch.int32, device=dev),
+               "center": torch.empty((nb, 3), dtype=torch.float64, device=dev),
+               "pt_range": torch.empty((nb, 2), dtype=torch.int64, device=dev),
+               "is_leaf": torch.empty(nb, dtype=torch.uint8, device=dev)}
+        ls = np.zeros(self.n_levels + 1, dtype=np.int64)
+        o = out
+        check(_lib.load().fmm_tree_export(self._h, _ptr(o["perm"]), _ptr(o["points"]), _ptr(o["level"]),
+                                          _ptr(o["ijk"]), _ptr(o["center"]), _ptr(o["pt_range"]),
+                                          _ptr(o["is_leaf"]), ls.ctypes.data_as(_lib.I64P), _stream()),
+              "fmm_tree_export")
+        out["level_start"] = ls
+        return out
+
+    def to_host(self):
+        """The tree as a workloads.Tree (numpy arrays), for the host-side set-up calls."""
+        import workloads as W
+        a = {k: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for k, v in self.arrays().items()}
+        kind = "uniform" if self.max_leaf == 0 else "adaptive"
+        meta = {"depth": self.depth} if self.max_leaf == 0 else {"max_leaf": self.max_leaf}
+        return W.Tree(points=a["points"], perm=a["perm"], level=a["level"], ijk=a["ijk"], center=a["center"],
+                      pt_range=a["pt_range"], level_start=a["level_start"], is_leaf=a["is_leaf"].astype(bool),
+                      kind=kind, meta=meta)
+
+    def list2(self, level_lo: int = 2, level_hi: int | None = None):
+        """List-2 pairs (target, source) of the target boxes on levels [level_lo, level_hi),
+        sorted by (target, source): two int32 device tensors.  The range is clipped to the
+        tree's levels (levels 0 and 1 have no List-2 pairs)."""
+        hi = self.n_levels if level_hi is None else min(int(level_hi), self.n_levels)
+        level_lo = min(max(int(level_lo), 0), hi)
+        L, n = _lib.load(), C.c_int64()
+        check(L.fmm_tree_list2(self._h, int(level_lo), hi, C.byref(n), None, None, _stream()), "fmm_tree_list2")
+        t = torch.empty(n.value, dtype=torch.int32, device=self.device)
+        s = torch.empty_like(t)
+        check(L.fmm_tree_list2(self._h, int(level_lo), hi, C.byref(n), _ptr(t), _ptr(s), _stream()),
+              "fmm_tree_list2")
+        return t, s
+
+    def lists(self, kind: str, max_src: int | None = None):
+        """Rows (box, ptr, item) of the near, U, W or X lists (int32 device tensors); max_src cuts
+        long near / U rows as fmm_tree_lists describes."""
+        L, nr, ni = _lib.load(), C.c_int64(), C.c_int64()
+        k, ms = _lib.LIST_KINDS[kind], int(max_src or 0)
+        check(L.fmm_tree_lists(self._h, k, ms, C.byref(nr), C.byref(ni), None, None, None, _stream()),
+              "fmm_tree_lists")
+        box = torch.empty(nr.value, dtype=torch.int32, device=self.device)
+        ptr = torch.empty(nr.value + 1, dtype=torch.int32, device=self.device)
+        item = torch.empty(ni.value, dtype=torch.int32, device=self.device)
+        check(L.fmm_tree_lists(self._h, k, ms, C.byref(nr), C.byref(ni), _ptr(box), _ptr(ptr), _ptr(item),
+                               _stream()), "fmm_tree_lists")
+        return box, ptr, item
+
+    def close(self):
+        if self._h:
+            _lib.load().fmm_tree_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -100,6 +100,19 @@ def test_null_arguments_are_rejected_before_any_launch(lib):
     assert L.fmm_m2l_multi_prepare(1, None, None) == -1
     assert L.fmm_m2l_multi_launch(None, None, None, None) == -1
     L.fmm_m2l_multi_destroy(None)
+    t = C.c_void_p()
+    assert L.fmm_tree_build(-1, None, 0, 2, C.byref(t), None) == -1 and not t.value
+    assert L.fmm_tree_build(8, None, 0, 2, C.byref(t), None) == -1
+    assert L.fmm_tree_build(0, None, 0, 11, C.byref(t), None) == -1  # uniform depth above 10
+    assert L.fmm_tree_build(0, None, 4, 21, C.byref(t), None) == -1  # adaptive depth above 20
+    assert L.fmm_tree_build(0, None, -1, 2, C.byref(t), None) == -1
+    assert L.fmm_tree_build(0, None, 0, 2, None, None) == -1
+    n64 = C.c_int64()
+    assert L.fmm_tree_size(None, None, None, None) == -1
+    assert L.fmm_tree_export(None, None, None, None, None, None, None, None, None, None) == -1
+    assert L.fmm_tree_list2(None, 2, 3, C.byref(n64), None, None, None) == -1
+    assert L.fmm_tree_lists(None, 0, 0, C.byref(n64), C.byref(n64), None, None, None, None) == -1
+    L.fmm_tree_destroy(None)
     # zero-size work is a no-op that needs no GPU
     assert L.fmm_direct(C.byref(d), 0, None, None, 0, None, None, None) == 0
     assert L.fmm_deriv_tables(C.byref(d), 0, None, None, None, None) == 0

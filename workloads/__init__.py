@@ -213,8 +213,9 @@ def near_lists(tree: Tree, max_src: int | None = None) -> tuple[np.ndarray, np.n
 
     With max_src, a list whose boxes hold more than max_src points in all is split into
     several entries of the same leaf: boxes above max_src points are replaced by their
-    children (down to leaves), and the boxes are packed in order into entries of at most
-    max_src points (a single leaf above the cap is an entry of its own).  A coarse leaf next
+    children (depth first, children in box order, i.e. by Morton key; down to leaves), and the
+    boxes are packed in order into entries of at most max_src points (a single leaf above the
+    cap is an entry of its own).  A coarse leaf next
     to a densely refined region would otherwise leave one workgroup with most of the work."""
     count = tree.pt_range[:, 1] - tree.pt_range[:, 0]
     index = {}  # (level, i, j, k) -> box, built on first use by split()
@@ -226,8 +227,8 @@ def near_lists(tree: Tree, max_src: int | None = None) -> tuple[np.ndarray, np.n
             index.update({(int(tree.level[b]),) + tuple(int(v) for v in tree.ijk[b]): int(b) for b in range(tree.n_box)})
         lev, base = int(tree.level[n]) + 1, 2 * tree.ijk[n].astype(np.int64)
         out = []
-        for o in range(8):
-            c = index.get((lev, int(base[0]) + (o & 1), int(base[1]) + ((o >> 1) & 1), int(base[2]) + ((o >> 2) & 1)))
+        for o in range(8):  # Morton order of the children: x bit highest
+            c = index.get((lev, int(base[0]) + ((o >> 2) & 1), int(base[1]) + ((o >> 1) & 1), int(base[2]) + (o & 1)))
             if c is not None:
                 out += split(c)
         return out
