@@ -536,13 +536,19 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
     import workloads as W
     from paper_2305_17867_amd.farfield import FarField
     dev = "cuda"
-    tr = W.adaptive_tree(W.gaussian_mixture_points(1 << 19, 4), 64)
+    raw = W.gaussian_mixture_points(1 << 19, 4)
+    host_s = {}
+    t0 = time.perf_counter()
+    tr = W.adaptive_tree(raw, 64)
+    host_s["tree"] = time.perf_counter() - t0
     w = W.normal_weights(tr.points.shape[0], SEED + 9)
     ff = FarField("laplace", 8, "f64", tr, tr, tree_pass=True)
     ff_level = FarField("laplace", 8, "f64", tr, tr)
     pts = torch.as_tensor(tr.points, dtype=torch.float64, device=dev)
     wd = torch.as_tensor(w, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
     leaves, ptr, nbr = W.near_lists(tr, max_src=2048)  # long lists split into parallel entries
+    host_s["near"] = time.perf_counter() - t0
     d = fmm.Desc("laplace", 8, "f64")
     lists = [torch.as_tensor(a, device=dev) for a in (leaves, ptr, nbr)]
     rng = torch.as_tensor(tr.pt_range, dtype=torch.int64, device=dev)
@@ -573,7 +579,9 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
     leaf_levels = np.bincount(tr.level[tr.is_leaf])
     # the same with the W interactions as compressed M2P and the X interactions as compressed P2L
     # (Secs. 3.5, 3.2), and the direct sum over the touching leaves (U lists) only
+    t0 = time.perf_counter()
     U, Wl, X = W.adaptive_lists(tr, max_src=2048)
+    host_s["u_w_x"] = time.perf_counter() - t0
     ff_wx = FarField("laplace", 8, "f64", tr, tr, tree_pass=True, wx_lists=(Wl, X))
     ulists = [torch.as_tensor(a, device=dev) for a in U]
 
@@ -589,6 +597,11 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
     far_wx()
     near_u()
     err_wx = float(torch.linalg.norm(out["pot_wx"][torch.as_tensor(idx, device=dev)] - ref) / torch.linalg.norm(ref))
+    t0 = time.perf_counter()
+    l2_host = W.interaction_pairs(tr)
+    host_s["list2"] = time.perf_counter() - t0
+    dev_build = device_tree_build(torch, fmm, raw, tr, l2_host, (leaves, ptr, nbr), (U, Wl, X))
+    dev_build["host_builder_ms"] = {k: v * 1e3 for k, v in host_s.items()}
     return {"workload": "adaptive octree, 524288 Gaussian-mixture points, <= 64 per leaf, laplace p8 f64: "
                         "far field (tree pass) + near field",
             "leaves": int(tr.is_leaf.sum()), "near_entries": int(len(leaves)), "leaf_levels": {int(l): int(c) for l, c in enumerate(leaf_levels) if c},
@@ -597,7 +610,45 @@ def full_fmm_adaptive(torch, fmm, reps=5, sample=512):
             "near_interactions_per_s": inter / t_near, "rel_error_vs_direct": err, "error_sample": sample,
             "w_x_lists": {"w_boxes": int(len(Wl[2])), "x_leaves": int(len(X[2])),
                           "far_with_m2p_p2l_ms": t_far_wx * 1e3, "near_u_ms": t_near_u * 1e3,
-                          "rel_error_vs_direct": err_wx}}
+                          "rel_error_vs_direct": err_wx},
+            "tree_and_lists_on_device": dev_build}
+
+
+def device_tree_build(torch, fmm, raw, tr, l2, near, uwx, reps=3):
+    """The octree and every list of the adaptive run built on the device (fmm_tree_*: Morton keys,
+    radix sort, boxes level by level, List 2, near lists split at 2048 sources, U / W / X),
+    timed per stage over fresh builds (each stage synchronises), and checked identical to the
+    host builders' arrays."""
+    pts = torch.as_tensor(raw, dtype=torch.float64, device="cuda")
+    stages = ("tree", "list2", "near", "u_w_x")
+    best = {k: float("inf") for k in stages}
+    for _ in range(reps + 1):  # the first build warms the allocator and the sort's code
+        torch.cuda.synchronize()
+        t = [time.perf_counter()]
+        gt = fmm.Tree(pts, 64, 16)
+        t.append(time.perf_counter())
+        got_l2 = gt.list2(2)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        got_near = gt.lists("near", 2048)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        got_uwx = (gt.lists("u", 2048), gt.lists("w"), gt.lists("x"))
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        for k, a, b in zip(stages, t[:-1], t[1:]):
+            best[k] = min(best[k], b - a)
+        arrays = gt.arrays()
+        gt.close()
+    h = lambda x: x.cpu().numpy()
+    same = all(np.array_equal(h(arrays[k]), getattr(tr, k)) for k in ("perm", "level", "ijk", "center", "pt_range"))
+    same &= np.array_equal(arrays["level_start"], tr.level_start)
+    same &= np.array_equal(h(arrays["is_leaf"]).astype(bool), tr.is_leaf)
+    same &= all(np.array_equal(h(g), np.asarray(w)) for g, w in zip(got_l2, l2))
+    same &= all(np.array_equal(h(g), np.asarray(w)) for g, w in zip(got_near, near))
+    same &= all(np.array_equal(h(g), np.asarray(w)) for G, Wt in zip(got_uwx, uwx) for g, w in zip(G, Wt))
+    return {"device_ms": {k: v * 1e3 for k, v in best.items()}, "device_total_ms": sum(best.values()) * 1e3,
+            "boxes": int(tr.n_box), "list2_pairs": int(len(l2[0])), "identical_to_host_builders": bool(same)}
 
 
 def mixed_batch(torch, fmm, checks, reps=10):
