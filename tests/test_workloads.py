@@ -207,3 +207,34 @@ def test_adaptive_lists_partition_every_leaf_pair(points, max_leaf):
             n += sum(a in Wd.get(b, ()) for a in anc[sl])
             n += sum(sl in Xd.get(a, ()) for a in anc[b])
             assert n == 1, (b, sl, n)
+
+
+def test_quadtree_ranges_and_list2_partition_every_leaf_pair():
+    """Uniform quadtree: every box's range holds exactly its points, and the List-2 pairs of
+    all levels with the leaf neighbours count every (target, source) leaf pair exactly once."""
+    import numpy as np
+    import workloads as W
+    pts = W.uniform_points2d(3000, 3)
+    tr = W.uniform_quadtree(pts, 4)
+    for b in range(tr.n_box):
+        lo, hi = tr.pt_range[b]
+        h = tr.box_size(int(tr.level[b]))
+        inside = np.all((tr.points >= tr.ij[b] * h) & (tr.points < (tr.ij[b] + 1) * h), axis=1)
+        assert inside.sum() == hi - lo and inside[lo:hi].all()
+    t, s = W.quad_list2(tr)
+    assert np.all(np.diff(t.astype(np.int64) * tr.n_box + s) > 0)
+    offs = {tuple(tr.ij[a] - tr.ij[b]) for a, b in zip(t, s) if tr.level[a] == 4}
+    assert len(offs) == 40
+    leaves = tr.boxes_at(4)
+    pos = {int(b): k for k, b in enumerate(leaves)}
+    cover = np.zeros((len(leaves), len(leaves)), dtype=np.int64)
+    for a, b in zip(t, s):
+        sh = 4 - int(tr.level[a])
+        la = [k for k, c in enumerate(leaves) if np.all(tr.ij[c] >> sh == tr.ij[a])]
+        lb = [k for k, c in enumerate(leaves) if np.all(tr.ij[c] >> sh == tr.ij[b])]
+        cover[np.ix_(la, lb)] += 1
+    bx, ptr, nbr = W.quad_neighbours(tr, 4)
+    for k, b in enumerate(bx):
+        for n in nbr[ptr[k]:ptr[k + 1]]:
+            cover[pos[int(b)], pos[int(n)]] += 1
+    assert np.all(cover == 1)

@@ -515,6 +515,127 @@ def interaction_pairs(tree: Tree, levels=None) -> tuple[np.ndarray, np.ndarray]:
     return t[order], s[order]
 
 
+# --------------------------------------------------------------------------- quadtrees (2-D)
+
+def uniform_points2d(n: int, seed: int, low=0.0, high=1.0) -> np.ndarray:
+    """n points uniform in [low, high)^2."""
+    return rng(seed).uniform(low, high, size=(n, 2))
+
+
+def _spread2(v: np.ndarray) -> np.ndarray:
+    """Insert one zero bit between each of the low 20 bits of v (uint64)."""
+    v = v.astype(np.uint64) & np.uint64(0xFFFFF)
+    for shift, mask in ((16, 0x0000FFFF0000FFFF), (8, 0x00FF00FF00FF00FF), (4, 0x0F0F0F0F0F0F0F0F),
+                        (2, 0x3333333333333333), (1, 0x5555555555555555)):
+        v = (v | (v << np.uint64(shift))) & np.uint64(mask)
+    return v
+
+
+def morton2(ij: np.ndarray) -> np.ndarray:
+    """Interleaved key (x bit higher within each pair) for integer coords [n, 2]."""
+    ij = np.asarray(ij)
+    return (_spread2(ij[:, 0]) << np.uint64(1)) | _spread2(ij[:, 1])
+
+
+@dataclass
+class QuadTree:
+    """Uniform quadtree over [0,1)^2: every box of every level <= depth, level-major, Morton
+    order within a level (box id = level_start[l] + Morton key); points sorted by key."""
+    points: np.ndarray
+    perm: np.ndarray
+    level: np.ndarray
+    ij: np.ndarray
+    center: np.ndarray
+    pt_range: np.ndarray
+    level_start: np.ndarray
+    depth: int
+
+    @property
+    def n_box(self) -> int:
+        return int(self.level.shape[0])
+
+    @property
+    def n_levels(self) -> int:
+        return self.depth + 1
+
+    def boxes_at(self, lev: int) -> np.ndarray:
+        return np.arange(self.level_start[lev], self.level_start[lev + 1])
+
+    def box_size(self, lev: int) -> float:
+        return 2.0 ** (-lev)
+
+
+def uniform_quadtree(points: np.ndarray, depth: int) -> QuadTree:
+    scale = float(1 << MAX_DEPTH)
+    ij = np.clip(np.floor(points * scale).astype(np.int64), 0, (1 << MAX_DEPTH) - 1)
+    keys = morton2(ij)
+    perm = np.argsort(keys, kind="stable")
+    ks = keys[perm]
+    levels, ijs, centers, ranges, level_start = [], [], [], [], [0]
+    for lev in range(depth + 1):
+        lk = np.arange(4 ** lev, dtype=np.uint64)
+        shift = np.uint64(2 * (MAX_DEPTH - lev))
+        lo = np.searchsorted(ks, lk << shift)
+        hi = np.searchsorted(ks, (lk + np.uint64(1)) << shift) if lev > 0 else np.array([ks.shape[0]])
+        # decode: even bits are y, odd bits x
+        bij = np.zeros((lk.shape[0], 2), dtype=np.int64)
+        for b in range(lev):
+            bij[:, 0] |= ((lk >> np.uint64(2 * b + 1)) & np.uint64(1)).astype(np.int64) << b
+            bij[:, 1] |= ((lk >> np.uint64(2 * b)) & np.uint64(1)).astype(np.int64) << b
+        levels.append(np.full(lk.shape[0], lev, dtype=np.int32))
+        ijs.append(bij.astype(np.int32))
+        centers.append((bij + 0.5) * 2.0 ** (-lev))
+        ranges.append(np.stack([lo, hi], axis=1).astype(np.int64))
+        level_start.append(level_start[-1] + lk.shape[0])
+    return QuadTree(points=points[perm], perm=perm, level=np.concatenate(levels), ij=np.concatenate(ijs),
+                    center=np.concatenate(centers), pt_range=np.concatenate(ranges),
+                    level_start=np.asarray(level_start, dtype=np.int64), depth=depth)
+
+
+def quad_list2(tree: QuadTree, levels=None) -> tuple[np.ndarray, np.ndarray]:
+    """List-2 pairs (target, source) of a uniform quadtree: the children of the parent's
+    neighbours (parent included) that are not adjacent to the target; at most 27 per box,
+    40 distinct offsets per level (7^2 - 3^2).  Sorted by (target, source)."""
+    if levels is None:
+        levels = range(2, tree.n_levels)
+    tg, sr = [], []
+    for lev in levels:
+        ids = tree.boxes_at(lev)
+        ij = tree.ij[ids].astype(np.int64)
+        side = 1 << lev
+        base = 2 * (ij >> 1)
+        d = np.arange(-2, 4)
+        cand = base[:, None, None, :] + np.stack(np.meshgrid(d, d, indexing="ij"), axis=-1)[None]
+        cand = cand.reshape(len(ids), 36, 2)
+        far = np.max(np.abs(cand - ij[:, None, :]), axis=2) >= 2
+        inside = np.all((cand >= 0) & (cand < side), axis=2)
+        keep = far & inside
+        ti = np.broadcast_to(ids[:, None], keep.shape)[keep]
+        si = tree.level_start[lev] + morton2(cand[keep]).astype(np.int64)
+        tg.append(ti)
+        sr.append(si)
+    if not tg:
+        return np.zeros(0, np.int32), np.zeros(0, np.int32)
+    t, s = np.concatenate(tg).astype(np.int32), np.concatenate(sr).astype(np.int32)
+    order = np.lexsort((s, t))
+    return t[order], s[order]
+
+
+def quad_neighbours(tree: QuadTree, lev: int) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Boxes of level lev and their adjacent boxes (themselves included), CSR (box, ptr, nbr)."""
+    ids = tree.boxes_at(lev)
+    ij = tree.ij[ids].astype(np.int64)
+    side = 1 << lev
+    ptr, nbr = [0], []
+    for b, (i, j) in zip(ids, ij):
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                if 0 <= i + di < side and 0 <= j + dj < side:
+                    nbr.append(int(tree.level_start[lev] + morton2(np.array([[i + di, j + dj]]))[0]))
+        ptr.append(len(nbr))
+    return ids.astype(np.int32), np.asarray(ptr, np.int32), np.asarray(nbr, np.int32)
+
+
 # --------------------------------------------------------------------------- configs
 
 def small_two_box(seed: int = 0):
