@@ -68,7 +68,14 @@ typedef enum {
   FMM_ESTATE = -5        /* object in the wrong state (e.g. destroyed plan) */
 } fmm_status;
 
-typedef enum { FMM_LAPLACE = 0, FMM_HELMHOLTZ = 1, FMM_YUKAWA = 2, FMM_BIHARMONIC = 3 } fmm_kernel;
+typedef enum {
+  FMM_LAPLACE = 0,
+  FMM_HELMHOLTZ = 1,
+  FMM_YUKAWA = 2,
+  FMM_BIHARMONIC = 3,
+  FMM_LAPLACE2D = 4,   /* 2-D log r; only the fmm2d_* calls take it */
+  FMM_BIHARMONIC2D = 5 /* 2-D r^2 log r; only the fmm2d_* calls take it */
+} fmm_kernel;
 typedef enum { FMM_F64 = 0, FMM_F32 = 1, FMM_C128 = 2, FMM_C64 = 3 } fmm_dtype;
 
 typedef struct {
@@ -386,6 +393,67 @@ int fmm_p2m_adjoint(fmm_plan plan, int64_t n_box, const double* box_center, cons
  *   potential [n_tgt] dtype, OVERWRITTEN. */
 int fmm_direct(const fmm_desc* desc, int64_t n_src, const void* src_xyz, const void* weight,
                int64_t n_tgt, const void* tgt_xyz, void* potential, void* stream);
+
+/* ---- Two dimensions (Sec. 4.4, Laplace 2D and Biharmonic 2D): G = log r (FMM_LAPLACE2D,
+ * Delta G = 0 away from 0, c = 2) and G = r^2 log r (FMM_BIHARMONIC2D, Delta^2 G = 0, c = 4),
+ * FMM_F64 only, orders 0..FMM_MAX_ORDER.  desc->param is ignored.
+ *
+ * Expansions as in 3-D with d = 2: M(p) = {(a, b) : a + b <= p}, kept set J = {(a, b) : b < c}
+ * (y is the compressed axis), |J| = 2p + 1 for c = 2 and 4p - 2 for c = 4 (p >= 3).  Stored
+ * coefficient order: by b, then a (a fastest).  Multipoles and locals are stored scaled by
+ * their box size h: beta~_q = beta_q / h^|q|, theta~_i = theta_i h^|i|.  Points are [n][2]
+ * float64, box centres [n_box][2] float64, box sizes box_h [n_box] float64 > 0. ---- */
+
+/* N(p) = (p+1)(p+2)/2 and |J|.  Host only. */
+int fmm2d_sizes(const fmm_desc* desc, int32_t* n_full, int32_t* n_compressed);
+
+/* J in storage order: mxy [host][Nc][2] (a, b).  Host only. */
+int fmm2d_index_table(const fmm_desc* desc, int32_t* mxy);
+
+/* Scaled derivative tables G^(a,b)(h o) h^(a+b) for a + b <= 2p, b <= 2(c-1): every derivative
+ * the 2-D M2L reads.  From the paper's recurrences in x (eqs. deriv_laplace_2d,
+ * deriv_biharmonic_2d, with the y terms -2 m y G(n, m-1) - m(m-1) G(n, m-2) of their general
+ * form) started from closed-form low-order values, evaluated at o and scaled exactly in h.
+ *   offset [n][2] f64: translation vector in units of h, nonzero;  h [n] f64 > 0
+ *   out [n][2c-1][2p+1] f64, index (b, a); entries a + b > 2p zero.  OVERWRITTEN. */
+int fmm2d_deriv_tables(const fmm_desc* desc, int64_t n, const double* offset, const double* h, double* out,
+                       void* stream);
+
+/* 2-D P2M: mpole[k] = M^T alpha~ for the sources of pt_range[k] about box_center[k], alpha~_q =
+ * sum_y w ((c - y)/h)^q / q! (eqs. mpole, define_beta_multipole).  mpole [n_box][Nc]
+ * OVERWRITTEN; ranges clamped to [0, n_src]. */
+int fmm2d_p2m(const fmm_desc* desc, int64_t n_box, const double* box_center, const double* box_h,
+              const int64_t* pt_range, int64_t n_src, const double* src_xy, const double* weight, double* mpole,
+              void* stream);
+
+/* 2-D M2L (eq. m2l_toeplitz for d = 2): for k < n_tbox and every pair e in
+ * [pair_ptr[k], pair_ptr[k+1]): local[tbox[k]] += T~(tables[pair_tab[e]]) mpole[pair_src[e]],
+ * theta~_i += sum_{q in J} T~_(i+q) beta~_q.  Tables come from fmm2d_deriv_tables at the pair's
+ * offset (c_t - c_s)/h and h.  Target boxes of one call must be distinct; pair ranges are
+ * clamped to [0, n_pair] and pairs with ids outside [0, n_box) or [0, n_tab) skipped.
+ * Allocates nothing; capturable. */
+int fmm2d_m2l(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* pair_ptr, int64_t n_pair,
+              const int32_t* pair_src, const int32_t* pair_tab, int64_t n_tab, const double* tables, int64_t n_box,
+              const double* mpole, double* local, void* stream);
+
+/* 2-D L2P: potential[x] += sum_{m in M(p)} (M theta~[k])_m ((x - c)/h)^m / m! for the targets of
+ * pt_range[k] (eq. compressed-local-form).  Ranges of one call must be disjoint. */
+int fmm2d_l2p(const fmm_desc* desc, int64_t n_box, const double* box_center, const double* box_h,
+              const int64_t* pt_range, int64_t n_tgt, const double* tgt_xy, const double* local, double* potential,
+              void* stream);
+
+/* 2-D direct sum (eq. (1)): potential[x] = sum_y G(x - y) w_y, x == y skipped.  OVERWRITTEN. */
+int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, const double* weight, int64_t n_tgt,
+                 const double* tgt_xy, double* potential, void* stream);
+
+/* 2-D near field: potential[targets of tbox[k]] += direct sum over the sources of the boxes
+ * nbr[nbr_ptr[k] : nbr_ptr[k+1]] (x == y skipped).  Target boxes of one call must be distinct.
+ * max_tgt_per_box sets the launch width (ceil(max / 256) workgroups per box); every target is
+ * computed whatever its value. */
+int fmm2d_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* nbr_ptr, int64_t n_nbr,
+              const int32_t* nbr, int64_t n_box, const int64_t* tgt_range, const int64_t* src_range, int64_t n_src,
+              const double* src_xy, const double* weight, int64_t n_tgt, const double* tgt_xy, double* potential,
+              int32_t max_tgt_per_box, void* stream);
 
 /* ---- Octree and interaction lists on the device (the box hierarchy of Sec. 1 over which
  * the operators above run; the adaptive lists of the classical adaptive FMM).  Integer work:

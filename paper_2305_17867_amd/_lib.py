@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libfmm.so")
 FMM_OK, FMM_EINVAL, FMM_EUNSUPPORTED, FMM_EHIP, FMM_ENOMEM, FMM_ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "FMM_OK", -1: "FMM_EINVAL", -2: "FMM_EUNSUPPORTED", -3: "FMM_EHIP",
                 -4: "FMM_ENOMEM", -5: "FMM_ESTATE"}
-KERNELS = {"laplace": 0, "helmholtz": 1, "yukawa": 2, "biharmonic": 3}
+KERNELS = {"laplace": 0, "helmholtz": 1, "yukawa": 2, "biharmonic": 3, "laplace2d": 4, "biharmonic2d": 5}
 DTYPES = {"f64": 0, "f32": 1, "c128": 2, "c64": 3}
 MAX_ORDER = 16
 
@@ -77,6 +77,15 @@ SIGNATURES = {
     "fmm_m2l_multi_prepare": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),
     "fmm_m2l_multi_launch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), P]),
     "fmm_m2l_multi_destroy": (None, [P]),
+    "fmm2d_sizes": (C.c_int, [C.POINTER(FmmDesc), I32P, I32P]),
+    "fmm2d_index_table": (C.c_int, [C.POINTER(FmmDesc), I32P]),
+    "fmm2d_deriv_tables": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, P]),
+    "fmm2d_p2m": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
+    "fmm2d_m2l": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, P]),
+    "fmm2d_l2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
+    "fmm2d_direct": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P]),
+    "fmm2d_p2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, C.c_int64, P, P,
+                            C.c_int64, P, P, C.c_int32, P]),
     "fmm_tree_build": (C.c_int, [C.c_int64, P, C.c_int32, C.c_int32, C.POINTER(P), P]),
     "fmm_tree_size": (C.c_int, [P, I64P, I32P, I64P]),
     "fmm_tree_export": (C.c_int, [P, P, P, P, P, P, P, P, I64P, P]),

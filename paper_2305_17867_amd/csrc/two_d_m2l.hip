@@ -1,0 +1,102 @@
+// Batched compressed M2L in two dimensions (eq. m2l_toeplitz for d = 2):
+//   theta~_i[t] += sum over the pairs (t, s) of sum_{q in J} T~_(i + q) beta~_q[s],  i in J,
+// with T~ the scaled derivative table of the pair's translation vector.
+//
+// J holds at most 4p - 2 coefficients, so one pair is a small dense product that does not
+// fill a matrix-core tile; it runs on the vector units (FP64 vector and matrix peaks are the
+// same on this chip).  One lane owns one target box and one layer m_y = IY of its outputs
+// (the launch's y dimension picks the layer, so a wavefront never diverges on it): it holds the
+// layer's accumulators and the source's coefficients in registers, and reads each table entry
+// it needs once per pair.  Every index is a compile-time constant (p, c and the layer are
+// template parameters and the loops are unrolled).
+#include "two_d.hpp"
+
+namespace fmm2d {
+namespace {
+
+template <int P, int C, int IY>
+__device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k) {
+  constexpr int NC = n_kept(P, C);
+  constexpr int SX = 2 * P + 1;
+  constexpr int NR = P - IY + 1;  // outputs of the layer: (ix, IY), ix = 0 .. P - IY
+  const int32_t t = a.tbox[k];
+  if (t < 0 || t >= a.n_box) return;
+  int64_t e0 = a.pair_ptr[k], e1 = a.pair_ptr[k + 1];
+  e0 = e0 < 0 ? 0 : (e0 > a.n_pair ? a.n_pair : e0);
+  e1 = e1 < e0 ? e0 : (e1 > a.n_pair ? a.n_pair : e1);
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int32_t s = a.pair_src[e];
+    const int32_t tb = a.pair_tab[e];
+    if (s < 0 || s >= a.n_box || tb < 0 || tb >= a.n_tab) continue;
+    const double* __restrict__ B = a.mpole + (int64_t)s * NC;
+    const double* __restrict__ T = a.tables + (int64_t)tb * (2 * C - 1) * SX + IY * SX;
+    double b[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) b[q] = B[q];
+#pragma unroll
+    for (int qy = 0; qy < C && qy <= P; ++qy) {
+#pragma unroll
+      for (int j = 0; j <= 2 * P - IY - qy; ++j) {
+        // table entry (m_x = j, m_y = IY + qy) feeds every (ix, qx) with ix + qx = j
+        const double tv = T[qy * SX + j];
+#pragma unroll
+        for (int ix = 0; ix < NR; ++ix) {
+          const int qx = j - ix;
+          if (qx >= 0 && qx <= P - qy) acc[ix] = fma(tv, b[kept_pos(P, qx, qy)], acc[ix]);
+        }
+      }
+    }
+  }
+  double* out = a.local + (int64_t)t * NC;
+#pragma unroll
+  for (int ix = 0; ix < NR; ++ix) out[kept_pos(P, ix, IY)] += acc[ix];
+}
+
+template <int P, int C>
+__global__ __launch_bounds__(256) void m2l2d_kernel(M2LArgs2D a) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n_tbox) return;
+  switch (blockIdx.y) {
+    case 0:
+      m2l_layer<P, C, 0>(a, k);
+      break;
+    case 1:
+      if constexpr (P >= 1) m2l_layer<P, C, 1>(a, k);
+      break;
+    case 2:
+      if constexpr (C > 2 && P >= 2) m2l_layer<P, C, 2>(a, k);
+      break;
+    case 3:
+      if constexpr (C > 3 && P >= 3) m2l_layer<P, C, 3>(a, k);
+      break;
+    default:
+      break;
+  }
+}
+
+template <int C, int P>
+bool launch_p(const M2LArgs2D& a, int p, hipStream_t s) {
+  if constexpr (P > 16) {
+    return false;
+  } else {
+    if (p != P) return launch_p<C, P + 1>(a, p, s);
+    const int layers = C < P + 1 ? C : P + 1;
+    const dim3 grid((unsigned)((a.n_tbox + 255) / 256), (unsigned)layers);
+    m2l2d_kernel<P, C><<<grid, 256, 0, s>>>(a);
+    return true;
+  }
+}
+
+}  // namespace
+
+bool launch_m2l2d(const M2LArgs2D& a, int p, int c, hipStream_t s) {
+  if (a.n_tbox == 0) return true;
+  if (c == 2) return launch_p<2, 0>(a, p, s);
+  if (c == 4) return launch_p<4, 0>(a, p, s);
+  return false;
+}
+
+}  // namespace fmm2d

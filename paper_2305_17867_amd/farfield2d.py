@@ -1,0 +1,65 @@
+"""Far field of a uniform quadtree in two dimensions (kernels log r and r^2 log r, Sec. 4.4) from
+the 2-D operators: P2M of every box of the M2L levels, one M2L launch over the List-2 pairs of
+every level, L2P of every level's locals at its boxes' points.
+
+Set-up (host): the pairs are grouped by target box (CSR), and one scaled derivative table is
+made on the device per distinct (level, offset); at most 40 offsets occur per level (7^2 - 3^2).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import workloads as W
+
+from . import fmm
+
+
+class FarField2D:
+    def __init__(self, kernel: str, order: int, tree: "W.QuadTree", levels=None, device="cuda"):
+        self.desc = fmm.Desc(kernel, order, "f64")
+        self.levels = list(range(2, tree.n_levels)) if levels is None else list(levels)
+        dev = torch.device(device)
+        t, s = W.quad_list2(tree, self.levels)
+        self.n_pair = len(t)
+        lev = tree.level[t].astype(np.int64)
+        off = (tree.ij[t] - tree.ij[s]).astype(np.int64)
+        keys, pair_tab = np.unique(np.stack([lev, off[:, 0], off[:, 1]], axis=1), axis=0, return_inverse=True)
+        h = 2.0 ** (-keys[:, 0].astype(np.float64))
+        self.tables = fmm.deriv_tables2d(self.desc, torch.as_tensor(keys[:, 1:].astype(np.float64), device=dev),
+                                         torch.as_tensor(h, device=dev))
+        tb, first = np.unique(t, return_index=True)
+        ptr = np.concatenate([first, [len(t)]]).astype(np.int32)
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int32, device=dev)
+        self.tbox, self.pair_ptr, self.pair_src, self.pair_tab = i32(tb), i32(ptr), i32(s), i32(pair_tab.ravel())
+        self.n_box = tree.n_box
+        self.center = torch.as_tensor(tree.center, dtype=torch.float64, device=dev)
+        self.box_h = torch.as_tensor(2.0 ** (-tree.level.astype(np.float64)), device=dev)
+        self.rng = torch.as_tensor(tree.pt_range, dtype=torch.int64, device=dev)
+        self.level_boxes = {l: (int(tree.level_start[l]), int(tree.level_start[l + 1])) for l in self.levels}
+        self.box_lo = self.level_boxes[self.levels[0]][0]
+
+    def p2m(self, w, src):
+        nc = self.desc.nc
+        mpole = torch.zeros((self.n_box, nc), dtype=torch.float64, device=w.device)
+        a = self.box_lo
+        fmm.p2m2d(self.desc, self.center[a:], self.box_h[a:], self.rng[a:], src, w, out=mpole[a:])
+        return mpole
+
+    def m2l(self, mpole, local=None):
+        if local is None:
+            local = torch.zeros_like(mpole)
+        fmm.m2l2d(self.desc, self.tbox, self.pair_ptr, self.pair_src, self.pair_tab, self.tables, mpole, local)
+        return local
+
+    def l2p(self, local, tgt, pot):
+        for l in self.levels:  # the boxes of one level hold disjoint point ranges
+            a, b = self.level_boxes[l]
+            fmm.l2p2d(self.desc, self.center[a:b], self.box_h[a:b], self.rng[a:b], tgt, local[a:b], pot)
+        return pot
+
+    def forward(self, w, src, tgt):
+        mpole = self.p2m(w, src)
+        local = self.m2l(mpole)
+        pot = torch.zeros(tgt.shape[0], dtype=torch.float64, device=w.device)
+        return self.l2p(local, tgt, pot), mpole, local

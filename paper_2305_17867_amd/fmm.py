@@ -67,9 +67,14 @@ class Desc:
         self.kernel, self.order, self.dtype, self.param = kernel, int(order), dtype, float(param)
         self.c = make_desc(kernel, order, dtype, param)
 
+    @property
+    def two_d(self) -> bool:
+        return self.kernel.endswith("2d")
+
     def sizes(self) -> tuple[int, int]:
         nf, nc = C.c_int32(), C.c_int32()
-        check(_lib.load().fmm_sizes(C.byref(self.c), C.byref(nf), C.byref(nc)), "fmm_sizes")
+        name = "fmm2d_sizes" if self.two_d else "fmm_sizes"
+        check(getattr(_lib.load(), name)(C.byref(self.c), C.byref(nf), C.byref(nc)), name)
         return nf.value, nc.value
 
     @property
@@ -562,3 +567,98 @@ class Tree:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------- two dimensions
+
+def index_table2d(desc: Desc) -> np.ndarray:
+    """J of a 2-D descriptor in storage order, [Nc, 2] (a, b)."""
+    out = np.zeros((desc.nc, 2), dtype=np.int32)
+    check(_lib.load().fmm2d_index_table(C.byref(desc.c), out.ctypes.data_as(_lib.I32P)), "fmm2d_index_table")
+    return out
+
+
+def deriv_tables2d(desc: Desc, offsets: torch.Tensor, h: torch.Tensor) -> torch.Tensor:
+    """Scaled 2-D tables [n, 2c - 1, 2p + 1] at offsets [n, 2] (units of h) and sizes h [n]."""
+    n = offsets.shape[0]
+    _dev(offsets, torch.float64, "offset", (n, 2))
+    _dev(h, torch.float64, "h", (n,))
+    c = 4 if desc.kernel == "biharmonic2d" else 2
+    out = torch.empty((n, 2 * c - 1, 2 * desc.order + 1), dtype=torch.float64, device=offsets.device)
+    check(_lib.load().fmm2d_deriv_tables(C.byref(desc.c), n, _ptr(offsets), _ptr(h), _ptr(out), _stream()),
+          "fmm2d_deriv_tables")
+    return out
+
+
+def p2m2d(desc: Desc, center, box_h, rng, src, w, out=None) -> torch.Tensor:
+    nb, ns = center.shape[0], src.shape[0]
+    _dev(center, torch.float64, "box_center", (nb, 2))
+    _dev(box_h, torch.float64, "box_h", (nb,))
+    _dev(rng, torch.int64, "pt_range", (nb, 2))
+    _dev(src, torch.float64, "src_xy", (ns, 2))
+    _dev(w, torch.float64, "weight", (ns,))
+    if out is None:
+        out = torch.empty((nb, desc.nc), dtype=torch.float64, device=center.device)
+    _dev(out, torch.float64, "mpole", (nb, desc.nc))
+    check(_lib.load().fmm2d_p2m(C.byref(desc.c), nb, _ptr(center), _ptr(box_h), _ptr(rng), ns, _ptr(src), _ptr(w),
+                                _ptr(out), _stream()), "fmm2d_p2m")
+    return out
+
+
+def m2l2d(desc: Desc, tbox, pair_ptr, pair_src, pair_tab, tables, mpole, local) -> torch.Tensor:
+    nt, npair, ntab, nb = tbox.shape[0], pair_src.shape[0], tables.shape[0], mpole.shape[0]
+    _dev(tbox, torch.int32, "tbox", (nt,))
+    _dev(pair_ptr, torch.int32, "pair_ptr", (nt + 1,))
+    _dev(pair_src, torch.int32, "pair_src", (npair,))
+    _dev(pair_tab, torch.int32, "pair_tab", (npair,))
+    _dev(tables, torch.float64, "tables")
+    _dev(mpole, torch.float64, "mpole", (nb, desc.nc))
+    _dev(local, torch.float64, "local", (nb, desc.nc))
+    check(_lib.load().fmm2d_m2l(C.byref(desc.c), nt, _ptr(tbox), _ptr(pair_ptr), npair, _ptr(pair_src),
+                                _ptr(pair_tab), ntab, _ptr(tables), nb, _ptr(mpole), _ptr(local), _stream()),
+          "fmm2d_m2l")
+    return local
+
+
+def l2p2d(desc: Desc, center, box_h, rng, tgt, local, pot) -> torch.Tensor:
+    nb, nt = center.shape[0], tgt.shape[0]
+    _dev(center, torch.float64, "box_center", (nb, 2))
+    _dev(box_h, torch.float64, "box_h", (nb,))
+    _dev(rng, torch.int64, "pt_range", (nb, 2))
+    _dev(tgt, torch.float64, "tgt_xy", (nt, 2))
+    _dev(local, torch.float64, "local", (nb, desc.nc))
+    _dev(pot, torch.float64, "potential", (nt,))
+    check(_lib.load().fmm2d_l2p(C.byref(desc.c), nb, _ptr(center), _ptr(box_h), _ptr(rng), nt, _ptr(tgt),
+                                _ptr(local), _ptr(pot), _stream()), "fmm2d_l2p")
+    return pot
+
+
+def direct2d(desc: Desc, src, w, tgt, out=None) -> torch.Tensor:
+    ns, nt = src.shape[0], tgt.shape[0]
+    _dev(src, torch.float64, "src_xy", (ns, 2))
+    _dev(w, torch.float64, "weight", (ns,))
+    _dev(tgt, torch.float64, "tgt_xy", (nt, 2))
+    if out is None:
+        out = torch.empty(nt, dtype=torch.float64, device=tgt.device)
+    _dev(out, torch.float64, "potential", (nt,))
+    check(_lib.load().fmm2d_direct(C.byref(desc.c), ns, _ptr(src), _ptr(w), nt, _ptr(tgt), _ptr(out), _stream()),
+          "fmm2d_direct")
+    return out
+
+
+def p2p2d(desc: Desc, tbox, nbr_ptr, nbr, tgt_range, src_range, src, w, tgt, pot, max_tgt_per_box: int):
+    nt_box, nb = tbox.shape[0], tgt_range.shape[0]
+    ns, nt = src.shape[0], tgt.shape[0]
+    _dev(tbox, torch.int32, "tbox", (nt_box,))
+    _dev(nbr_ptr, torch.int32, "nbr_ptr", (nt_box + 1,))
+    _dev(nbr, torch.int32, "nbr", (nbr.shape[0],))
+    _dev(tgt_range, torch.int64, "tgt_range", (nb, 2))
+    _dev(src_range, torch.int64, "src_range", (nb, 2))
+    _dev(src, torch.float64, "src_xy", (ns, 2))
+    _dev(w, torch.float64, "weight", (ns,))
+    _dev(tgt, torch.float64, "tgt_xy", (nt, 2))
+    _dev(pot, torch.float64, "potential", (nt,))
+    check(_lib.load().fmm2d_p2p(C.byref(desc.c), nt_box, _ptr(tbox), _ptr(nbr_ptr), nbr.shape[0], _ptr(nbr), nb,
+                                _ptr(tgt_range), _ptr(src_range), ns, _ptr(src), _ptr(w), nt, _ptr(tgt), _ptr(pot),
+                                max(1, int(max_tgt_per_box)), _stream()), "fmm2d_p2p")
+    return pot

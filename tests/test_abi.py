@@ -75,6 +75,26 @@ def test_descriptor_validation(lib, bad, status):
     assert lib.load().fmm_last_error()
 
 
+@pytest.mark.parametrize("kernel,c", [("laplace2d", 2), ("biharmonic2d", 4)])
+@pytest.mark.parametrize("p", [0, 1, 3, 8, 16])
+def test_two_d_sizes_and_index_table_match_oracle(lib, kernel, c, p):
+    from oracle import two_d as T2
+    L = lib.load()
+    d = lib.make_desc(kernel, p, "f64")
+    nf, nc = C.c_int32(), C.c_int32()
+    assert L.fmm2d_sizes(C.byref(d), C.byref(nf), C.byref(nc)) == 0
+    J = T2.kept_set(p, c)
+    assert (nf.value, nc.value) == (T2.n_full(p), len(J))
+    out = (C.c_int32 * (2 * nc.value))()
+    assert L.fmm2d_index_table(C.byref(d), out) == 0
+    assert [(out[2 * k], out[2 * k + 1]) for k in range(nc.value)] == J
+    # 2-D kernels are refused by the 3-D calls and 3-D kernels by the 2-D calls; FP64 only
+    assert L.fmm_sizes(C.byref(d), C.byref(nf), C.byref(nc)) == -1
+    assert L.fmm2d_sizes(C.byref(lib.make_desc("laplace", p, "f64")), C.byref(nf), C.byref(nc)) == -1
+    assert L.fmm2d_sizes(C.byref(lib.make_desc(kernel, p, "f32")), C.byref(nf), C.byref(nc)) == -2
+    assert L.fmm2d_sizes(C.byref(lib.make_desc(kernel, 17, "f64")), C.byref(nf), C.byref(nc)) == -2
+
+
 def test_null_arguments_are_rejected_before_any_launch(lib):
     L = lib.load()
     assert L.fmm_sizes(None, None, None) == -1
@@ -113,6 +133,14 @@ def test_null_arguments_are_rejected_before_any_launch(lib):
     assert L.fmm_tree_list2(None, 2, 3, C.byref(n64), None, None, None) == -1
     assert L.fmm_tree_lists(None, 0, 0, C.byref(n64), C.byref(n64), None, None, None, None) == -1
     L.fmm_tree_destroy(None)
+    d2 = lib.make_desc("laplace2d", 4, "f64")
+    assert L.fmm2d_p2m(C.byref(d2), 1, None, None, None, 0, None, None, None, None) == -1
+    assert L.fmm2d_m2l(C.byref(d2), 1, None, None, 0, None, None, 0, None, 0, None, None, None) == -1
+    assert L.fmm2d_l2p(C.byref(d2), 1, None, None, None, 0, None, None, None, None) == -1
+    assert L.fmm2d_direct(C.byref(d2), 0, None, None, 1, None, None, None) == -1
+    assert L.fmm2d_p2p(C.byref(d2), 1, None, None, 0, None, 0, None, None, 0, None, None, 0, None, None, 1, None) == -1
+    assert L.fmm2d_deriv_tables(C.byref(d2), 1, None, None, None, None) == -1
+    assert L.fmm2d_m2l(C.byref(d2), 0, None, None, 0, None, None, 0, None, 0, None, None, None) == 0
     # zero-size work is a no-op that needs no GPU
     assert L.fmm_direct(C.byref(d), 0, None, None, 0, None, None, None) == 0
     assert L.fmm_deriv_tables(C.byref(d), 0, None, None, None, None) == 0
