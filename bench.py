@@ -785,6 +785,117 @@ def plummer_helmholtz(torch, fmm, dt, checks, reps=5):
     return out
 
 
+def two_d(torch, fmm, checks, reps=10, sample=256):
+    """The 2-D kernels (Sec. 4.4) on 2^20 uniform points in the unit square, uniform quadtree of
+    depth 8 (16 points per leaf on average), FP64: log r at p = 8 and 16, r^2 log r at p = 8 and
+    12.  Per case: P2M of every box of levels 2-8 (one launch per level), M2L over the List-2 pairs of
+    every level (one launch; 2 Nc^2 FP64 FLOP per pair against the FP64 peak), L2P level by
+    level, the near field of the leaves, and the error of the complete potential against the GPU
+    direct sum at sampled targets; the M2L result of one box and the complete potential at a few
+    targets are also compared with the oracle (FP64)."""
+    import workloads as W
+    from paper_2305_17867_amd.farfield2d import FarField2D
+    n, depth = 1 << 20, 8
+    tr = W.uniform_quadtree(W.uniform_points2d(n, SEED + 30), depth)
+    w = W.normal_weights(n, SEED + 31)
+    dev = "cuda"
+    P = torch.as_tensor(tr.points, dtype=torch.float64, device=dev)
+    wd = torch.as_tensor(w, dtype=torch.float64, device=dev)
+    rng = torch.as_tensor(tr.pt_range, dtype=torch.int64, device=dev)
+    boxes, ptr, nbr = W.quad_neighbours(tr, depth)
+    near_lists = [torch.as_tensor(a, dtype=torch.int32, device=dev) for a in (boxes, ptr, nbr)]
+    counts = tr.pt_range[:, 1] - tr.pt_range[:, 0]
+    max_leaf = int(counts[tr.level == depth].max())
+    g = np.random.Generator(np.random.PCG64(SEED + 32))
+    idx = np.sort(g.choice(n, sample, replace=False))
+    idx_d = torch.as_tensor(idx, device=dev)
+    few = idx[:16]
+    out = []
+    for kernel, p in (("laplace2d", 8), ("laplace2d", 16), ("biharmonic2d", 8), ("biharmonic2d", 12)):
+        log(f"2-D {kernel} p={p}")
+        ff = FarField2D(kernel, p, tr)
+        d = ff.desc
+        nc = d.nc
+        a = ff.box_lo
+        mpole = torch.zeros((tr.n_box, nc), dtype=torch.float64, device=dev)
+        local = torch.zeros_like(mpole)
+        pot = torch.zeros(n, dtype=torch.float64, device=dev)
+
+        def p2m():
+            mpole.zero_()
+            ff.p2m_into(wd, P, mpole)
+
+        def m2l():
+            fmm.m2l2d(d, ff.tbox, ff.pair_ptr, ff.pair_src, ff.pair_tab, ff.tables, mpole, local)
+
+        def l2p():
+            ff.l2p(local, P, pot)
+
+        def near():
+            fmm.p2p2d(d, *near_lists, rng, rng, P, wd, P, pot, max_tgt_per_box=max_leaf)
+
+        t_p2m, t_m2l, t_l2p, t_near = (time_kernel(torch, f, reps) for f in (p2m, m2l, l2p, near))
+        # the complete potential, once
+        p2m()
+        local.zero_()
+        m2l()
+        pot.zero_()
+        l2p()
+        near()
+        ref = fmm.direct2d(d, P, wd, P[idx_d].contiguous())
+        got = pot[idx_d]
+        err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+        flops = 2.0 * nc * nc * ff.n_pair
+        res = {"kernel": kernel, "order": p, "nc": nc, "m2l_pairs": ff.n_pair, "p2m_ms": t_p2m * 1e3,
+               "m2l_ms": t_m2l * 1e3, "l2p_ms": t_l2p * 1e3, "near_ms": t_near * 1e3,
+               "far_ms": (t_p2m + t_m2l + t_l2p) * 1e3, "m2l_pairs_per_s": ff.n_pair / t_m2l,
+               "p2m_includes": "zeroing the multipoles (the P2M accumulates)",
+               "m2l_roofline": {"bound": "alu", "achieved": flops / t_m2l / 1e12, "peak": PEAK["f64"] / 1e12,
+                                "unit": "TFLOP/s", "frac": flops / t_m2l / PEAK["f64"],
+                                "algorithmic": f"2*Nc^2 FLOP per pair, Nc={nc}, {ff.n_pair} pairs per launch"},
+               "rel_error_vs_gpu_direct": err, "error_sample": sample}
+        # oracle checks: one target box's M2L result, and the complete potential at 16 targets
+        tb = int(tr.level_start[depth] + W.morton2(np.array([[100, 150]]))[0])  # an interior leaf
+        k = int(np.flatnonzero(host_np(ff.tbox) == tb)[0])
+        e0, e1 = host_np(ff.pair_ptr)[k:k + 2]
+        srcs = host_np(ff.pair_src)[e0:e1]
+        mp_src = host_np(mpole)[srcs]
+        loc_t = host_np(local)[tb]
+        J = fmm.index_table2d(d)
+        checks.add(res, "m2l_error_vs_oracle", loc_t, ("2d-m2l", kernel, p),
+                   lambda kernel=kernel, p=p, srcs=srcs, mp_src=mp_src, tb=tb: ref_m2l_2d(kernel, p, tr, tb, srcs, mp_src),
+                   f"compressed local of box {tb} from its {len(srcs)} List-2 sources", orders=J.sum(axis=1))
+        checks.add(res, "error_vs_oracle_direct_sum", host_np(pot)[few], ("2d-direct", kernel),
+                   lambda kernel=kernel: ref_direct_2d(kernel, tr, w, few),
+                   "complete potential at 16 sampled points against the oracle's direct sum over all 2^20 sources")
+        log(json.dumps({k_: v for k_, v in res.items() if not isinstance(v, dict)}))
+        out.append(res)
+        del mpole, local, pot, ff
+        torch.cuda.empty_cache()
+    return {"workload": f"2-D uniform quadtree, 2^20 points, depth {depth}, FP64", "cases": out}
+
+
+def host_np(t):
+    return t.detach().cpu().numpy()
+
+
+def ref_m2l_2d(kernel, p, tr, tb, srcs, mp_src):
+    """Oracle (FP64): the compressed local of box tb from the multipoles of its List-2 sources,
+    tables from exact derivatives at 50 digits (eq. m2l_toeplitz for d = 2)."""
+    from oracle import two_d as T2
+    lev = int(tr.level[tb])
+    h = 2.0 ** -lev
+    theta = 0.0
+    for s, beta in zip(srcs, mp_src):
+        theta = theta + T2.m2l(kernel, p, (tr.ij[tb] - tr.ij[s]).astype(np.float64) * h, beta, h)
+    return theta
+
+
+def ref_direct_2d(kernel, tr, w, idx):
+    from oracle import two_d as T2
+    return T2.direct_sum(kernel, tr.points, w, tr.points[idx])
+
+
 def plummer_helmholtz_fmm(torch, fmm, reps=3, sample=256):
     """The complete Helmholtz potential (complex128, p = 12) of 2^21 Plummer points on their
     adaptive octree (<= 64 per leaf, k = 1 / largest leaf side): far field as a tree pass plus
@@ -918,6 +1029,7 @@ def main():
                     help="also time the mixed Yukawa + biharmonic workload when --only or --no-extras is given")
     ap.add_argument("--plummer", action="store_true",
                     help="also time the Plummer Helmholtz launch and FMM when --only or --no-extras is given")
+    ap.add_argument("--two-d", action="store_true", help="run the 2-D kernels section (with --only)")
     ap.add_argument("--gradient", action="store_true",
                     help="also time the far-field gradient pass when --only or --no-extras is given")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1011,6 +1123,10 @@ def main():
         out["plummer_helmholtz"] = [plummer_helmholtz(torch, fmm, dt, checks) for dt in ("c128", "c64")]
         log("Plummer Helmholtz, complete FMM (tree pass + near field)")
         out["plummer_helmholtz_fmm"] = plummer_helmholtz_fmm(torch, fmm)
+        torch.cuda.empty_cache()
+    if args.two_d or not (args.only or args.no_extras):
+        log("2-D kernels (log r, r^2 log r)")
+        out["two_d"] = two_d(torch, fmm, checks)
         torch.cuda.empty_cache()
     if args.gradient or not (args.only or args.no_extras):
         log("far-field gradient pass")

@@ -419,12 +419,15 @@ int fmm2d_index_table(const fmm_desc* desc, int32_t* mxy);
 int fmm2d_deriv_tables(const fmm_desc* desc, int64_t n, const double* offset, const double* h, double* out,
                        void* stream);
 
-/* 2-D P2M: mpole[k] = M^T alpha~ for the sources of pt_range[k] about box_center[k], alpha~_q =
+/* 2-D P2M: mpole[k] += M^T alpha~ for the sources of pt_range[k] about box_center[k], alpha~_q =
  * sum_y w ((c - y)/h)^q / q! (eqs. mpole, define_beta_multipole).  mpole [n_box][Nc]
- * OVERWRITTEN; ranges clamped to [0, n_src]. */
+ * ACCUMULATED (zero it first for the multipoles alone); ranges clamped to [0, n_src].  A box's
+ * points are taken in chunks of 256 by ceil(max_src_per_box / 256) workgroups, whose compressed
+ * sums are added atomically (in no fixed order when a box has more than 256 points); every
+ * point is summed whatever max_src_per_box says. */
 int fmm2d_p2m(const fmm_desc* desc, int64_t n_box, const double* box_center, const double* box_h,
               const int64_t* pt_range, int64_t n_src, const double* src_xy, const double* weight, double* mpole,
-              void* stream);
+              int32_t max_src_per_box, void* stream);
 
 /* 2-D M2L (eq. m2l_toeplitz for d = 2): for k < n_tbox and every pair e in
  * [pair_ptr[k], pair_ptr[k+1]): local[tbox[k]] += T~(tables[pair_tab[e]]) mpole[pair_src[e]],
@@ -437,10 +440,12 @@ int fmm2d_m2l(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const i
               const double* mpole, double* local, void* stream);
 
 /* 2-D L2P: potential[x] += sum_{m in M(p)} (M theta~[k])_m ((x - c)/h)^m / m! for the targets of
- * pt_range[k] (eq. compressed-local-form).  Ranges of one call must be disjoint. */
+ * pt_range[k] (eq. compressed-local-form).  Ranges of one call must be disjoint.  A box's targets
+ * are taken in chunks of 256 by ceil(max_tgt_per_box / 256) workgroups (every target is
+ * evaluated whatever max_tgt_per_box says). */
 int fmm2d_l2p(const fmm_desc* desc, int64_t n_box, const double* box_center, const double* box_h,
               const int64_t* pt_range, int64_t n_tgt, const double* tgt_xy, const double* local, double* potential,
-              void* stream);
+              int32_t max_tgt_per_box, void* stream);
 
 /* 2-D direct sum (eq. (1)): potential[x] = sum_y G(x - y) w_y, x == y skipped.  OVERWRITTEN. */
 int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, const double* weight, int64_t n_tgt,
@@ -448,7 +453,7 @@ int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, cons
 
 /* 2-D near field: potential[targets of tbox[k]] += direct sum over the sources of the boxes
  * nbr[nbr_ptr[k] : nbr_ptr[k+1]] (x == y skipped).  Target boxes of one call must be distinct.
- * max_tgt_per_box sets the launch width (ceil(max / 256) workgroups per box); every target is
+ * max_tgt_per_box sets the launch width (ceil(max / 64) wavefronts per box); every target is
  * computed whatever its value. */
 int fmm2d_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* nbr_ptr, int64_t n_nbr,
               const int32_t* nbr, int64_t n_box, const int64_t* tgt_range, const int64_t* src_range, int64_t n_src,

@@ -80,9 +80,9 @@ SIGNATURES = {
     "fmm2d_sizes": (C.c_int, [C.POINTER(FmmDesc), I32P, I32P]),
     "fmm2d_index_table": (C.c_int, [C.POINTER(FmmDesc), I32P]),
     "fmm2d_deriv_tables": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, P]),
-    "fmm2d_p2m": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
+    "fmm2d_p2m": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, C.c_int32, P]),
     "fmm2d_m2l": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, P]),
-    "fmm2d_l2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
+    "fmm2d_l2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, C.c_int32, P]),
     "fmm2d_direct": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P]),
     "fmm2d_p2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, C.c_int64, P, P,
                             C.c_int64, P, P, C.c_int32, P]),

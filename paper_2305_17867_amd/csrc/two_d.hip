@@ -148,9 +148,12 @@ __device__ void decompress_grid(double* g, int p, int c, int lane, int nl) {
 }
 
 constexpr int kRow = FMM_MAX_ORDER + 1;  // grid row length bound
-constexpr int kWg = 64;                  // one wavefront per box
+constexpr int kWg = 64;                  // one wavefront per (box, chunk)
+constexpr int kChunk = 256;              // points of a box per workgroup (P2M, L2P)
 
-// alpha~_(a, b) = sum_y w X^a Y^b / (a! b!), (X, Y) = (c - y) / h; beta~ = M^T alpha~.
+// alpha~_(a, b) = sum_y w X^a Y^b / (a! b!), (X, Y) = (c - y) / h; beta~ = M^T alpha~.  Workgroup
+// (box, y) takes the chunks y, y + gridDim.y, ... of kChunk points of the box and adds the
+// compressed sum of its points to the box's row atomically (compression is linear).
 __global__ __launch_bounds__(kWg) void p2m2d_kernel(int64_t n_box, const double* __restrict__ center,
                                                    const double* __restrict__ bh, const int64_t* __restrict__ range,
                                                    int64_t n_src, const double* __restrict__ xy,
@@ -167,14 +170,17 @@ __global__ __launch_bounds__(kWg) void p2m2d_kernel(int64_t n_box, const double*
   int64_t lo = range[2 * box], hi = range[2 * box + 1];
   lo = lo < 0 ? 0 : (lo > n_src ? n_src : lo);
   hi = hi < lo ? lo : (hi > n_src ? n_src : hi);
+  if (lo + (int64_t)blockIdx.y * kChunk >= hi) return;  // no points for this workgroup (uniform)
   constexpr int kSlots = (kRow * kRow + kWg - 1) / kWg;
   double acc[kSlots];
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) acc[k] = 0.0;
-  for (int64_t t0 = lo; t0 < hi; t0 += kWg) {
+  for (int64_t c0 = lo + (int64_t)blockIdx.y * kChunk; c0 < hi; c0 += (int64_t)gridDim.y * kChunk) {
+  const int64_t c1 = c0 + kChunk < hi ? c0 + kChunk : hi;
+  for (int64_t t0 = c0; t0 < c1; t0 += kWg) {
     const int64_t i = t0 + lane;
     double X = 0.0, Y = 0.0, wi = 0.0;
-    if (i < hi) {
+    if (i < c1) {
       X = (cx - xy[2 * i]) * ih;
       Y = (cy - xy[2 * i + 1]) * ih;
       wi = w[i];
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(kWg) void p2m2d_kernel(int64_t n_box, const double*
     }
     ws[lane] = wi;
     __syncthreads();
-    const int np = (int)(hi - t0 < kWg ? hi - t0 : kWg);
+    const int np = (int)(c1 - t0 < kWg ? c1 - t0 : kWg);
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) {
       const int e = lane + k * kWg;
@@ -199,6 +205,7 @@ __global__ __launch_bounds__(kWg) void p2m2d_kernel(int64_t n_box, const double*
       }
     }
     __syncthreads();
+  }
   }
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) {
@@ -214,11 +221,13 @@ __global__ __launch_bounds__(kWg) void p2m2d_kernel(int64_t n_box, const double*
       off += p - b + 1;
       ++b;
     }
-    mpole[box * nc + j] = grid[(j - off) + b * R];
+    atomicAdd(&mpole[box * nc + j], grid[(j - off) + b * R]);
   }
 }
 
-// phi(x) += sum_(a, b) L~_(a, b) X^a Y^b / (a! b!), (X, Y) = (x - c) / h, L~ = M theta~.
+// phi(x) += sum_(a, b) L~_(a, b) X^a Y^b / (a! b!), (X, Y) = (x - c) / h, L~ = M theta~.  Workgroup
+// (box, y) decompresses the box's local and evaluates it at the chunks y, y + gridDim.y, ... of
+// kChunk targets.
 __global__ __launch_bounds__(kWg) void l2p2d_kernel(int64_t n_box, const double* __restrict__ center,
                                                    const double* __restrict__ bh, const int64_t* __restrict__ range,
                                                    int64_t n_tgt, const double* __restrict__ xy,
@@ -228,6 +237,10 @@ __global__ __launch_bounds__(kWg) void l2p2d_kernel(int64_t n_box, const double*
   const int64_t box = blockIdx.x;
   const int lane = threadIdx.x;
   const int R = p + 1;
+  int64_t lo = range[2 * box], hi = range[2 * box + 1];
+  lo = lo < 0 ? 0 : (lo > n_tgt ? n_tgt : lo);
+  hi = hi < lo ? lo : (hi > n_tgt ? n_tgt : hi);
+  if (lo + (int64_t)blockIdx.y * kChunk >= hi) return;  // no targets for this workgroup (uniform)
   for (int e = lane; e < R * R; e += kWg) grid[e] = 0.0;
   __syncthreads();
   for (int j = lane; j < nc; j += kWg) {
@@ -241,10 +254,8 @@ __global__ __launch_bounds__(kWg) void l2p2d_kernel(int64_t n_box, const double*
   __syncthreads();
   decompress_grid(grid, p, c, lane, kWg);
   const double cx = center[2 * box], cy = center[2 * box + 1], ih = 1.0 / bh[box];
-  int64_t lo = range[2 * box], hi = range[2 * box + 1];
-  lo = lo < 0 ? 0 : (lo > n_tgt ? n_tgt : lo);
-  hi = hi < lo ? lo : (hi > n_tgt ? n_tgt : hi);
-  for (int64_t i = lo + lane; i < hi; i += kWg) {
+  for (int64_t c0 = lo + (int64_t)blockIdx.y * kChunk; c0 < hi; c0 += (int64_t)gridDim.y * kChunk)
+  for (int64_t i = c0 + lane; i < (c0 + kChunk < hi ? c0 + kChunk : hi); i += kWg) {
     const double X = (xy[2 * i] - cx) * ih, Y = (xy[2 * i + 1] - cy) * ih;
     double outer = 0.0;
     for (int b = p; b >= 0; --b) {
@@ -291,17 +302,21 @@ __global__ __launch_bounds__(kTpb) void direct2d_kernel(int kernel, int64_t n_sr
   if (active) pot[i] = acc;
 }
 
-// Near field: one workgroup per (target box of the list, chunk of 256 of its targets); the
-// sources of the listed boxes are staged through LDS.
-__global__ __launch_bounds__(kTpb) void p2p2d_kernel(int kernel, int64_t n_tbox, const int32_t* __restrict__ tbox,
-                                                    const int32_t* __restrict__ nbr_ptr, int64_t n_nbr,
-                                                    const int32_t* __restrict__ nbr, int64_t n_box,
-                                                    const int64_t* __restrict__ trange,
-                                                    const int64_t* __restrict__ srange, int64_t n_src,
-                                                    const double* __restrict__ src, const double* __restrict__ w,
-                                                    int64_t n_tgt, const double* __restrict__ tgt,
-                                                    double* __restrict__ pot) {
-  __shared__ double sx[kTile], sy[kTile], sw[kTile];
+// Near field: one wavefront per (target box of the list, chunk of 64 of its targets).  A chunk of
+// n targets gives each target `split` adjacent lanes (the largest power of two up to 16 with
+// n * split <= 64), each summing every split-th source of the listed boxes; a butterfly of lane
+// exchanges adds them up.  Sources are read straight from memory (lanes of one target read
+// consecutive sources, the targets of a chunk read the same ones).
+constexpr int kNearWg = 64;
+
+__global__ __launch_bounds__(kNearWg) void p2p2d_kernel(int kernel, int64_t n_tbox, const int32_t* __restrict__ tbox,
+                                                       const int32_t* __restrict__ nbr_ptr, int64_t n_nbr,
+                                                       const int32_t* __restrict__ nbr, int64_t n_box,
+                                                       const int64_t* __restrict__ trange,
+                                                       const int64_t* __restrict__ srange, int64_t n_src,
+                                                       const double* __restrict__ src, const double* __restrict__ w,
+                                                       int64_t n_tgt, const double* __restrict__ tgt,
+                                                       double* __restrict__ pot) {
   const int64_t k = blockIdx.x;
   const int32_t t = tbox[k];
   if (t < 0 || t >= n_box) return;
@@ -311,34 +326,30 @@ __global__ __launch_bounds__(kTpb) void p2p2d_kernel(int kernel, int64_t n_tbox,
   int64_t e0 = nbr_ptr[k], e1 = nbr_ptr[k + 1];
   e0 = e0 < 0 ? 0 : (e0 > n_nbr ? n_nbr : e0);
   e1 = e1 < e0 ? e0 : (e1 > n_nbr ? n_nbr : e1);
-  // chunks of kTile targets, blockIdx.y, blockIdx.y + gridDim.y, ...; the bound is uniform over
-  // the workgroup, so every thread meets every barrier
-  for (int64_t c0 = lo + (int64_t)blockIdx.y * kTile; c0 < hi; c0 += (int64_t)gridDim.y * kTile) {
-  const int64_t i = c0 + threadIdx.x;
-  const bool active = i < hi;
-  const double x = active ? tgt[2 * i] : 0.0, y = active ? tgt[2 * i + 1] : 0.0;
-  double acc = 0.0;
-  for (int64_t e = e0; e < e1; ++e) {
-    const int32_t s = nbr[e];
-    if (s < 0 || s >= n_box) continue;
-    int64_t s0 = srange[2 * (int64_t)s], s1 = srange[2 * (int64_t)s + 1];
-    s0 = s0 < 0 ? 0 : (s0 > n_src ? n_src : s0);
-    s1 = s1 < s0 ? s0 : (s1 > n_src ? n_src : s1);
-    for (int64_t t0 = s0; t0 < s1; t0 += kTile) {
-      const int64_t j = t0 + threadIdx.x;
-      sx[threadIdx.x] = j < s1 ? src[2 * j] : 0.0;
-      sy[threadIdx.x] = j < s1 ? src[2 * j + 1] : 0.0;
-      sw[threadIdx.x] = j < s1 ? w[j] : 0.0;
-      __syncthreads();
-      const int nt = (int)(s1 - t0 < kTile ? s1 - t0 : kTile);
-      for (int q = 0; q < nt; ++q) {
-        const double dx = x - sx[q], dy = y - sy[q];
-        acc = fma(green2d(kernel, dx * dx + dy * dy), sw[q], acc);
+  const int lane = threadIdx.x;
+  for (int64_t c0 = lo + (int64_t)blockIdx.y * kNearWg; c0 < hi; c0 += (int64_t)gridDim.y * kNearWg) {
+    const int n = (int)(hi - c0 < kNearWg ? hi - c0 : kNearWg);
+    int split = 1;
+    while (split < 16 && n * split * 2 <= kNearWg) split *= 2;
+    const int tl = lane / split, sp = lane % split;
+    const bool active = tl < n;
+    const int64_t i = c0 + tl;
+    const double x = active ? tgt[2 * i] : 0.0, y = active ? tgt[2 * i + 1] : 0.0;
+    double acc = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int32_t s = nbr[e];
+      if (s < 0 || s >= n_box) continue;
+      int64_t s0 = srange[2 * (int64_t)s], s1 = srange[2 * (int64_t)s + 1];
+      s0 = s0 < 0 ? 0 : (s0 > n_src ? n_src : s0);
+      s1 = s1 < s0 ? s0 : (s1 > n_src ? n_src : s1);
+      if (!active) continue;
+      for (int64_t j = s0 + sp; j < s1; j += split) {
+        const double dx = x - src[2 * j], dy = y - src[2 * j + 1];
+        acc = fma(green2d(kernel, dx * dx + dy * dy), w[j], acc);
       }
-      __syncthreads();
     }
-  }
-  if (active) pot[i] += acc;
+    for (int m = 1; m < split; m <<= 1) acc += __shfl_xor(acc, m, 64);  // every lane takes part
+    if (active && sp == 0) pot[i] += acc;
   }
 }
 
@@ -354,6 +365,12 @@ int check_desc2d(const fmm_desc* d) {
 }
 
 inline int pde_c(const fmm_desc* d) { return d->kernel == FMM_BIHARMONIC2D ? 4 : 2; }
+
+// workgroups per box along y for boxes of up to max_per_box points, `per` points each
+inline unsigned chunks(int32_t max_per_box, int per) {
+  const int64_t c = ((int64_t)(max_per_box < 1 ? 1 : max_per_box) + per - 1) / per;
+  return (unsigned)(c > 65535 ? 65535 : c);
+}
 
 int launched(const char* what) {
   const hipError_t e = hipGetLastError();
@@ -401,7 +418,7 @@ int fmm2d_deriv_tables(const fmm_desc* desc, int64_t n, const double* offset, co
 
 int fmm2d_p2m(const fmm_desc* desc, int64_t n_box, const double* box_center, const double* box_h,
               const int64_t* pt_range, int64_t n_src, const double* src_xy, const double* weight, double* mpole,
-              void* stream) {
+              int32_t max_src_per_box, void* stream) {
   int st = check_desc2d(desc);
   if (st) return st;
   FMM_REQUIRE(n_box >= 0 && n_src >= 0, FMM_EINVAL, "negative size");
@@ -410,7 +427,7 @@ int fmm2d_p2m(const fmm_desc* desc, int64_t n_box, const double* box_center, con
   FMM_REQUIRE(box_center && box_h && pt_range && mpole, FMM_EINVAL, "NULL pointer");
   FMM_REQUIRE(n_src == 0 || (src_xy && weight), FMM_EINVAL, "NULL source pointer");
   const int p = desc->order, c = pde_c(desc);
-  p2m2d_kernel<<<(unsigned)n_box, kWg, 0, (hipStream_t)stream>>>(n_box, box_center, box_h, pt_range, n_src, src_xy,
+  p2m2d_kernel<<<dim3((unsigned)n_box, chunks(max_src_per_box, kChunk)), kWg, 0, (hipStream_t)stream>>>(n_box, box_center, box_h, pt_range, n_src, src_xy,
                                                                   weight, mpole, p, c, fmm2d::n_kept(p, c));
   return launched("p2m2d_kernel");
 }
@@ -432,7 +449,7 @@ int fmm2d_m2l(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const i
 
 int fmm2d_l2p(const fmm_desc* desc, int64_t n_box, const double* box_center, const double* box_h,
               const int64_t* pt_range, int64_t n_tgt, const double* tgt_xy, const double* local, double* potential,
-              void* stream) {
+              int32_t max_tgt_per_box, void* stream) {
   int st = check_desc2d(desc);
   if (st) return st;
   FMM_REQUIRE(n_box >= 0 && n_tgt >= 0, FMM_EINVAL, "negative size");
@@ -441,7 +458,7 @@ int fmm2d_l2p(const fmm_desc* desc, int64_t n_box, const double* box_center, con
   FMM_REQUIRE(box_center && box_h && pt_range && local, FMM_EINVAL, "NULL pointer");
   FMM_REQUIRE(n_tgt == 0 || (tgt_xy && potential), FMM_EINVAL, "NULL target pointer");
   const int p = desc->order, c = pde_c(desc);
-  l2p2d_kernel<<<(unsigned)n_box, kWg, 0, (hipStream_t)stream>>>(n_box, box_center, box_h, pt_range, n_tgt, tgt_xy,
+  l2p2d_kernel<<<dim3((unsigned)n_box, chunks(max_tgt_per_box, kChunk)), kWg, 0, (hipStream_t)stream>>>(n_box, box_center, box_h, pt_range, n_tgt, tgt_xy,
                                                                   local, potential, p, c, fmm2d::n_kept(p, c));
   return launched("l2p2d_kernel");
 }
@@ -472,8 +489,8 @@ int fmm2d_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const i
   FMM_REQUIRE(tbox && nbr_ptr && tgt_range && src_range && tgt_xy && potential, FMM_EINVAL, "NULL pointer");
   FMM_REQUIRE(n_nbr == 0 || nbr, FMM_EINVAL, "NULL list");
   FMM_REQUIRE(n_src == 0 || (src_xy && weight), FMM_EINVAL, "NULL source pointer");
-  const dim3 grid((unsigned)n_tbox, (unsigned)((max_tgt_per_box + kTile - 1) / kTile));
-  p2p2d_kernel<<<grid, kTpb, 0, (hipStream_t)stream>>>(desc->kernel, n_tbox, tbox, nbr_ptr, n_nbr, nbr, n_box,
+  const dim3 grid((unsigned)n_tbox, chunks(max_tgt_per_box, kNearWg));
+  p2p2d_kernel<<<grid, kNearWg, 0, (hipStream_t)stream>>>(desc->kernel, n_tbox, tbox, nbr_ptr, n_nbr, nbr, n_box,
                                                        tgt_range, src_range, n_src, src_xy, weight, n_tgt, tgt_xy,
                                                        potential);
   return launched("p2p2d_kernel");

@@ -4,30 +4,40 @@
 //
 // J holds at most 4p - 2 coefficients, so one pair is a small dense product that does not
 // fill a matrix-core tile; it runs on the vector units (FP64 vector and matrix peaks are the
-// same on this chip).  One lane owns one target box and one layer m_y = IY of its outputs
-// (the launch's y dimension picks the layer, so a wavefront never diverges on it): it holds the
-// layer's accumulators and the source's coefficients in registers, and reads each table entry
-// it needs once per pair.  Every index is a compile-time constant (p, c and the layer are
-// template parameters and the loops are unrolled).
+// same on this chip).  kSplit adjacent lanes own one target box and one layer m_y = IY of its
+// outputs (the launch's y dimension picks the layer, so a wavefront never diverges on it); each
+// takes every kSplit-th pair of the target, holds the layer's accumulators and the source's
+// coefficients in registers and reads each table entry it needs once per pair; a butterfly of
+// lane exchanges adds the kSplit partial sums.  Splitting a target's pairs over lanes gives the
+// launch kSplit times the wavefronts, which the memory latency of the pair loop needs.  Every
+// index is a compile-time constant (p, c and the layer are template parameters and the loops
+// are unrolled).
 #include "two_d.hpp"
 
 namespace fmm2d {
 namespace {
 
+constexpr int kSplit = 4;
+
 template <int P, int C, int IY>
-__device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k) {
+__device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k, int part) {
   constexpr int NC = n_kept(P, C);
   constexpr int SX = 2 * P + 1;
   constexpr int NR = P - IY + 1;  // outputs of the layer: (ix, IY), ix = 0 .. P - IY
-  const int32_t t = a.tbox[k];
-  if (t < 0 || t >= a.n_box) return;
-  int64_t e0 = a.pair_ptr[k], e1 = a.pair_ptr[k + 1];
-  e0 = e0 < 0 ? 0 : (e0 > a.n_pair ? a.n_pair : e0);
-  e1 = e1 < e0 ? e0 : (e1 > a.n_pair ? a.n_pair : e1);
+  // every lane of the target's group runs to the exchanges below (no early exit)
+  const int32_t t = k < a.n_tbox ? a.tbox[k] : -1;
+  const bool valid = t >= 0 && t < a.n_box;
+  int64_t e0 = 0, e1 = 0;
+  if (valid) {
+    e0 = a.pair_ptr[k];
+    e1 = a.pair_ptr[k + 1];
+    e0 = e0 < 0 ? 0 : (e0 > a.n_pair ? a.n_pair : e0);
+    e1 = e1 < e0 ? e0 : (e1 > a.n_pair ? a.n_pair : e1);
+  }
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  for (int64_t e = e0; e < e1; ++e) {
+  for (int64_t e = e0 + part; e < e1; e += kSplit) {
     const int32_t s = a.pair_src[e];
     const int32_t tb = a.pair_tab[e];
     if (s < 0 || s >= a.n_box || tb < 0 || tb >= a.n_tab) continue;
@@ -50,6 +60,11 @@ __device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k) {
       }
     }
   }
+#pragma unroll
+  for (int ix = 0; ix < NR; ++ix)
+#pragma unroll
+    for (int m = 1; m < kSplit; m <<= 1) acc[ix] += __shfl_xor(acc[ix], m, 64);
+  if (!valid || part != 0) return;
   double* out = a.local + (int64_t)t * NC;
 #pragma unroll
   for (int ix = 0; ix < NR; ++ix) out[kept_pos(P, ix, IY)] += acc[ix];
@@ -57,20 +72,22 @@ __device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k) {
 
 template <int P, int C>
 __global__ __launch_bounds__(256) void m2l2d_kernel(M2LArgs2D a) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n_tbox) return;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = g / kSplit;  // target; its kSplit lanes are adjacent
+  const int part = (int)(g % kSplit);
+  if (k >= a.n_tbox) return;  // the same for all lanes of a group, so exchanges stay in step
   switch (blockIdx.y) {
     case 0:
-      m2l_layer<P, C, 0>(a, k);
+      m2l_layer<P, C, 0>(a, k, part);
       break;
     case 1:
-      if constexpr (P >= 1) m2l_layer<P, C, 1>(a, k);
+      if constexpr (P >= 1) m2l_layer<P, C, 1>(a, k, part);
       break;
     case 2:
-      if constexpr (C > 2 && P >= 2) m2l_layer<P, C, 2>(a, k);
+      if constexpr (C > 2 && P >= 2) m2l_layer<P, C, 2>(a, k, part);
       break;
     case 3:
-      if constexpr (C > 3 && P >= 3) m2l_layer<P, C, 3>(a, k);
+      if constexpr (C > 3 && P >= 3) m2l_layer<P, C, 3>(a, k, part);
       break;
     default:
       break;
@@ -84,7 +101,7 @@ bool launch_p(const M2LArgs2D& a, int p, hipStream_t s) {
   } else {
     if (p != P) return launch_p<C, P + 1>(a, p, s);
     const int layers = C < P + 1 ? C : P + 1;
-    const dim3 grid((unsigned)((a.n_tbox + 255) / 256), (unsigned)layers);
+    const dim3 grid((unsigned)((a.n_tbox * kSplit + 255) / 256), (unsigned)layers);
     m2l2d_kernel<P, C><<<grid, 256, 0, s>>>(a);
     return true;
   }

@@ -28,6 +28,8 @@ class FarField2D:
         h = 2.0 ** (-keys[:, 0].astype(np.float64))
         self.tables = fmm.deriv_tables2d(self.desc, torch.as_tensor(keys[:, 1:].astype(np.float64), device=dev),
                                          torch.as_tensor(h, device=dev))
+        # targets in box (Morton) order: neighbouring targets share most of their sources, whose
+        # multipoles the caches then serve to several lanes
         tb, first = np.unique(t, return_index=True)
         ptr = np.concatenate([first, [len(t)]]).astype(np.int32)
         i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int32, device=dev)
@@ -38,13 +40,23 @@ class FarField2D:
         self.rng = torch.as_tensor(tree.pt_range, dtype=torch.int64, device=dev)
         self.level_boxes = {l: (int(tree.level_start[l]), int(tree.level_start[l + 1])) for l in self.levels}
         self.box_lo = self.level_boxes[self.levels[0]][0]
+        counts = tree.pt_range[:, 1] - tree.pt_range[:, 0]
+        self.max_count = {l: max(1, int(counts[a:b].max())) for l, (a, b) in self.level_boxes.items()}
 
     def p2m(self, w, src):
+        """Multipoles of every box of the M2L levels (the boxes' chunks of points are added
+        atomically, so rows of boxes above 256 points may differ in the last bits between runs)."""
         nc = self.desc.nc
         mpole = torch.zeros((self.n_box, nc), dtype=torch.float64, device=w.device)
-        a = self.box_lo
-        fmm.p2m2d(self.desc, self.center[a:], self.box_h[a:], self.rng[a:], src, w, out=mpole[a:])
+        self.p2m_into(w, src, mpole)
         return mpole
+
+    def p2m_into(self, w, src, mpole):
+        """mpole += the multipoles, one launch per level (each sized for its level's largest box)."""
+        for l in self.levels:
+            a, b = self.level_boxes[l]
+            fmm.p2m2d(self.desc, self.center[a:b], self.box_h[a:b], self.rng[a:b], src, w, out=mpole[a:b],
+                      max_per_box=self.max_count[l])
 
     def m2l(self, mpole, local=None):
         if local is None:
@@ -55,7 +67,8 @@ class FarField2D:
     def l2p(self, local, tgt, pot):
         for l in self.levels:  # the boxes of one level hold disjoint point ranges
             a, b = self.level_boxes[l]
-            fmm.l2p2d(self.desc, self.center[a:b], self.box_h[a:b], self.rng[a:b], tgt, local[a:b], pot)
+            fmm.l2p2d(self.desc, self.center[a:b], self.box_h[a:b], self.rng[a:b], tgt, local[a:b], pot,
+                      max_per_box=self.max_count[l])
         return pot
 
     def forward(self, w, src, tgt):

@@ -590,7 +590,15 @@ def deriv_tables2d(desc: Desc, offsets: torch.Tensor, h: torch.Tensor) -> torch.
     return out
 
 
-def p2m2d(desc: Desc, center, box_h, rng, src, w, out=None) -> torch.Tensor:
+def _max_count(rng, given):
+    if given is not None:
+        return int(given)
+    return int((rng[:, 1] - rng[:, 0]).max().item()) if rng.shape[0] else 1
+
+
+def p2m2d(desc: Desc, center, box_h, rng, src, w, out=None, max_per_box=None) -> torch.Tensor:
+    """out += compressed scaled multipoles of the boxes (zeros when out is None).  max_per_box:
+    the largest point count of a box (sets the launch width; read from rng when None)."""
     nb, ns = center.shape[0], src.shape[0]
     _dev(center, torch.float64, "box_center", (nb, 2))
     _dev(box_h, torch.float64, "box_h", (nb,))
@@ -598,10 +606,10 @@ def p2m2d(desc: Desc, center, box_h, rng, src, w, out=None) -> torch.Tensor:
     _dev(src, torch.float64, "src_xy", (ns, 2))
     _dev(w, torch.float64, "weight", (ns,))
     if out is None:
-        out = torch.empty((nb, desc.nc), dtype=torch.float64, device=center.device)
+        out = torch.zeros((nb, desc.nc), dtype=torch.float64, device=center.device)
     _dev(out, torch.float64, "mpole", (nb, desc.nc))
     check(_lib.load().fmm2d_p2m(C.byref(desc.c), nb, _ptr(center), _ptr(box_h), _ptr(rng), ns, _ptr(src), _ptr(w),
-                                _ptr(out), _stream()), "fmm2d_p2m")
+                                _ptr(out), max(1, _max_count(rng, max_per_box)), _stream()), "fmm2d_p2m")
     return out
 
 
@@ -620,7 +628,7 @@ def m2l2d(desc: Desc, tbox, pair_ptr, pair_src, pair_tab, tables, mpole, local) 
     return local
 
 
-def l2p2d(desc: Desc, center, box_h, rng, tgt, local, pot) -> torch.Tensor:
+def l2p2d(desc: Desc, center, box_h, rng, tgt, local, pot, max_per_box=None) -> torch.Tensor:
     nb, nt = center.shape[0], tgt.shape[0]
     _dev(center, torch.float64, "box_center", (nb, 2))
     _dev(box_h, torch.float64, "box_h", (nb,))
@@ -629,7 +637,8 @@ def l2p2d(desc: Desc, center, box_h, rng, tgt, local, pot) -> torch.Tensor:
     _dev(local, torch.float64, "local", (nb, desc.nc))
     _dev(pot, torch.float64, "potential", (nt,))
     check(_lib.load().fmm2d_l2p(C.byref(desc.c), nb, _ptr(center), _ptr(box_h), _ptr(rng), nt, _ptr(tgt),
-                                _ptr(local), _ptr(pot), _stream()), "fmm2d_l2p")
+                                _ptr(local), _ptr(pot), max(1, _max_count(rng, max_per_box)), _stream()),
+          "fmm2d_l2p")
     return pot
 
 

@@ -134,9 +134,9 @@ def test_null_arguments_are_rejected_before_any_launch(lib):
     assert L.fmm_tree_lists(None, 0, 0, C.byref(n64), C.byref(n64), None, None, None, None) == -1
     L.fmm_tree_destroy(None)
     d2 = lib.make_desc("laplace2d", 4, "f64")
-    assert L.fmm2d_p2m(C.byref(d2), 1, None, None, None, 0, None, None, None, None) == -1
+    assert L.fmm2d_p2m(C.byref(d2), 1, None, None, None, 0, None, None, None, 1, None) == -1
     assert L.fmm2d_m2l(C.byref(d2), 1, None, None, 0, None, None, 0, None, 0, None, None, None) == -1
-    assert L.fmm2d_l2p(C.byref(d2), 1, None, None, None, 0, None, None, None, None) == -1
+    assert L.fmm2d_l2p(C.byref(d2), 1, None, None, None, 0, None, None, None, 1, None) == -1
     assert L.fmm2d_direct(C.byref(d2), 0, None, None, 1, None, None, None) == -1
     assert L.fmm2d_p2p(C.byref(d2), 1, None, None, 0, None, 0, None, None, 0, None, None, 0, None, None, 1, None) == -1
     assert L.fmm2d_deriv_tables(C.byref(d2), 1, None, None, None, None) == -1
