@@ -112,27 +112,33 @@ class Case:
         self.pot = torch.zeros(NPTS, dtype=vd, device=dev)
         self.n_pair = len(t)
         self.nc = nc
-        # launches with their arguments marshalled once (the step repeats them unchanged)
+        # launches with their arguments marshalled once (the step repeats them unchanged).  With a
+        # streaming-form batch the M2L stores every target's local and the L2P every point's
+        # potential (output mode FMM_OVERWRITE), so the step clears nothing; otherwise both
+        # accumulate into arrays the step zeroes first.
+        self.store = bool(self.batch.info()["stream_form"])
         self.run_p2m = self.plan.bind_p2m(self.center, self.level, self.rng, self.pts, self.w,
                                           self.mpole[self.leaf0:self.leaf0 + self.n_leaf])
-        self.run_m2l = self.batch.bind(self.mpole, self.local)
+        self.run_m2l = self.batch.bind(self.mpole, self.local, overwrite=self.store)
         self.run_l2p = self.plan.bind_l2p(self.center, self.level, self.rng, self.pts,
-                                          self.local[self.leaf0:self.leaf0 + self.n_leaf], self.pot)
+                                          self.local[self.leaf0:self.leaf0 + self.n_leaf], self.pot,
+                                          overwrite=self.store)
 
     def p2m(self):
         self.plan.p2m(self.center, self.level, self.rng, self.pts, self.w,
                       out=self.mpole[self.leaf0:self.leaf0 + self.n_leaf])
 
     def m2l(self):
-        self.batch(self.mpole, self.local)
+        self.batch(self.mpole, self.local, overwrite=self.store)
 
     def l2p(self):
         self.plan.l2p(self.center, self.level, self.rng, self.pts,
-                      self.local[self.leaf0:self.leaf0 + self.n_leaf], self.pot)
+                      self.local[self.leaf0:self.leaf0 + self.n_leaf], self.pot, overwrite=self.store)
 
     def step(self):
-        self.local.zero_()
-        self.pot.zero_()
+        if not self.store:
+            self.local.zero_()
+            self.pot.zero_()
         self.run_p2m()
         self.run_m2l()
         self.run_l2p()

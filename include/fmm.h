@@ -149,6 +149,18 @@ int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
             const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local,
             void* potential, void* stream);
 
+/* Output modes of the _ex calls: add to the output (as the plain calls do), or store into it
+ * (BLAS beta = 0: the old values are neither read nor needed, so the caller need not clear
+ * them). */
+enum { FMM_ACCUMULATE = 0, FMM_OVERWRITE = 1 };
+
+/* fmm_l2p with an output mode.  FMM_OVERWRITE: potential[x] = the local expansion's value for
+ * every target x of the call's boxes (ranges of one call must be disjoint); other entries are
+ * left unchanged. */
+int fmm_l2p_ex(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+               const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local, void* potential,
+               int32_t mode, void* stream);
+
 /* Compressed M2M (Sec. 4.3, eq. define_psi): for each k < n_parent, the scaled compressed
  * multipole of box parent[k] becomes psi~ = M^T T E beta~ summed over its children: each
  * child's kept coefficients are embedded with zeros elsewhere (E), translated to the parent
@@ -331,6 +343,12 @@ int fmm_batch_info(fmm_batch batch, int64_t* info, int32_t n_info);
  * mpole [n_box][Nc] dtype; local [n_box][Nc] dtype, ACCUMULATED.  Deterministic: every output
  * is summed in a fixed order. */
 int fmm_m2l_batched(fmm_batch batch, const void* mpole, void* local, void* stream);
+
+/* fmm_m2l_batched with an output mode (FMM_ACCUMULATE, FMM_OVERWRITE above).  FMM_OVERWRITE:
+ * local[t] = M2L(mpole) for every target box t of the batch, other rows unchanged; only for a
+ * streaming-form batch (FMM_EUNSUPPORTED for the tiled and FFT forms).  Same results bit for
+ * bit as accumulating into zeroed rows.  Allocates nothing; capturable. */
+int fmm_m2l_batched_ex(fmm_batch batch, const void* mpole, void* local, int32_t mode, void* stream);
 
 /* Several prepared batches launched one after another on `stream` (same dtype).  batches,
  * mpole, local: [host] arrays of n pointers.  For a single persistent launch see below. */

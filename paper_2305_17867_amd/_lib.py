@@ -77,6 +77,8 @@ SIGNATURES = {
     "fmm_m2l_multi_prepare": (C.c_int, [C.c_int32, C.POINTER(P), C.POINTER(P)]),
     "fmm_m2l_multi_launch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), P]),
     "fmm_m2l_multi_destroy": (None, [P]),
+    "fmm_l2p_ex": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, C.c_int32, P]),
+    "fmm_m2l_batched_ex": (C.c_int, [P, P, P, C.c_int32, P]),
     "fmm2d_sizes": (C.c_int, [C.POINTER(FmmDesc), I32P, I32P]),
     "fmm2d_index_table": (C.c_int, [C.POINTER(FmmDesc), I32P]),
     "fmm2d_deriv_tables": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, P]),

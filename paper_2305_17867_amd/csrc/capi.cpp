@@ -400,6 +400,14 @@ int fmm_l2l_adjoint(fmm_plan plan, int64_t n_parent, const int32_t* parent, cons
 int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
             const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local, void* potential,
             void* stream) {
+  return fmm_l2p_ex(plan, n_box, box_center, box_level, pt_range, n_tgt, tgt_xyz, local, potential, FMM_ACCUMULATE,
+                    stream);
+}
+
+int fmm_l2p_ex(fmm_plan plan, int64_t n_box, const double* box_center, const int32_t* box_level,
+               const int64_t* pt_range, int64_t n_tgt, const void* tgt_xyz, const void* local, void* potential,
+               int32_t mode, void* stream) {
+  FMM_REQUIRE(mode == FMM_ACCUMULATE || mode == FMM_OVERWRITE, FMM_EINVAL, "mode must be FMM_ACCUMULATE or FMM_OVERWRITE");
   int st = check_box_args(plan, n_box, box_center, box_level, pt_range, n_tgt, tgt_xyz, local,
                           n_tgt ? potential : local);
   if (st || n_box == 0) return st;
@@ -423,6 +431,7 @@ int fmm_l2p(fmm_plan plan, int64_t n_box, const double* box_center, const int32_
   a.xsign = 1.0;
   a.grad = nullptr;
   a.gscale = nullptr;
+  a.overwrite = mode == FMM_OVERWRITE ? 1 : 0;
   return launch_l2p(a, plan->p, plan->desc.dtype, (hipStream_t)stream);
 }
 
@@ -1331,6 +1340,20 @@ int fmm_m2l_batched(fmm_batch b, const void* mpole, void* local, void* stream) {
   FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
   FMM_REQUIRE(!b->adjoint, FMM_ESTATE, "batch was prepared for the adjoint; use fmm_m2l_batched_adjoint");
   return m2l_launch(b, mpole, local, stream);
+}
+
+int fmm_m2l_batched_ex(fmm_batch b, const void* mpole, void* local, int32_t mode, void* stream) {
+  FMM_REQUIRE(b, FMM_EINVAL, "batch is NULL");
+  FMM_REQUIRE(mode == FMM_ACCUMULATE || mode == FMM_OVERWRITE, FMM_EINVAL, "mode must be FMM_ACCUMULATE or FMM_OVERWRITE");
+  FMM_REQUIRE(!b->adjoint, FMM_ESTATE, "batch was prepared for the adjoint; use fmm_m2l_batched_adjoint");
+  if (mode == FMM_ACCUMULATE) return m2l_launch(b, mpole, local, stream);
+  FMM_REQUIRE(b->plan && b->plan->alive, FMM_ESTATE, "the batch's plan was destroyed");
+  FMM_REQUIRE(b->stream && !b->fft, FMM_EUNSUPPORTED, "FMM_OVERWRITE needs a streaming-form batch");
+  if (b->n_items == 0) return FMM_OK;
+  FMM_REQUIRE(mpole && local, FMM_EINVAL, "NULL coefficient array");
+  M2LStreamArgs a = m2l_stream_args(b, mpole, local);
+  a.overwrite = 1;
+  return launch_m2l_stream(a, b->p, b->c_pde, b->dtype, b->waves, (size_t)b->lds_bytes, (hipStream_t)stream);
 }
 
 int fmm_m2l_batched_adjoint(fmm_batch b, const void* local_grad, void* mpole_grad, void* stream) {

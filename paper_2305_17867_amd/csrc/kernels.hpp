@@ -73,6 +73,7 @@ struct L2PArgs {
   const void* xyz;          // [n_pts][3] real
   const void* local;        // [n_box][Nc] dtype
   void* pot;                // [n_pts] dtype, accumulated (may be null when grad is set)
+  int32_t overwrite;        // 1: the potentials are stored, not added to
   int32_t nc;
   int32_t c;
   RecArgs rec;
@@ -180,6 +181,7 @@ struct M2LStreamArgs {
   const int32_t* jbase;        // [Nc] base offset of each kept index into a table
   const void* mpole;           // [n_box][Nc]
   void* local;                 // [n_box][Nc]
+  int32_t overwrite;           // 1: the targets' rows are stored, not added to
   int32_t lds_slot;            // byte offset of the wavefronts' item-sum slots in LDS
   int32_t lds_sbq;             // byte offset of the q-base table (and two counters) in LDS
 };

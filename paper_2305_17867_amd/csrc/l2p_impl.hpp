@@ -224,7 +224,7 @@ __device__ inline int pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R*
       const int64_t s = t0 + (int64_t)j * kThreads;
       if (s < hi) {
 #pragma unroll
-        for (int u = 0; u < W; ++u) pot[s * W + u] += v[j][u];
+        for (int u = 0; u < W; ++u) pot[s * W + u] = a.overwrite ? v[j][u] : pot[s * W + u] + v[j][u];
       }
     }
   }

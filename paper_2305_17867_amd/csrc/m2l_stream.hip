@@ -390,7 +390,7 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
             const int i = TR * r + TL::row(kq, v);
             if (i < NC) {
 #pragma unroll
-              for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((double)out[i * CW + u] + acc[r][u][v]);
+              for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((a.overwrite ? 0.0 : (double)out[i * CW + u]) + acc[r][u][v]);
             }
           }
         if (kq == 0) {
@@ -399,7 +399,7 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
 #pragma unroll
             for (int u = 0; u < CW; ++u) {
               const int i = TR * RT + jr;
-              out[i * CW + u] = (R)((double)out[i * CW + u] + racc[jr][u]);
+              out[i * CW + u] = (R)((a.overwrite ? 0.0 : (double)out[i * CW + u]) + racc[jr][u]);
             }
         }
       }
@@ -540,7 +540,7 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
             const int i = TR * r + TL::row(kq, v);
             if (i < NC) {
 #pragma unroll
-              for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((double)out[i * CW + u] + tot[r][u][v]);
+              for (int u = 0; u < CW; ++u) out[i * CW + u] = (R)((a.overwrite ? 0.0 : (double)out[i * CW + u]) + tot[r][u][v]);
             }
           }
         if (kq == 0) {
@@ -549,7 +549,7 @@ __device__ __forceinline__ void m2ls_workgroup(const M2LStreamArgs& a) {
 #pragma unroll
             for (int u = 0; u < CW; ++u) {
               const int i = TR * RT + jr;
-              out[i * CW + u] = (R)((double)out[i * CW + u] + totr[jr][u]);
+              out[i * CW + u] = (R)((a.overwrite ? 0.0 : (double)out[i * CW + u]) + totr[jr][u]);
             }
         }
       }

@@ -162,25 +162,28 @@ class Plan:
                 _ptr(w), _ptr(out))
         return lambda: check(fn(*args, _stream()), "fmm_p2m")
 
-    def bind_l2p(self, center, level, rng, tgt, local, pot):
-        """Like bind_p2m, for L2P (the potentials keep accumulating on every call)."""
+    def bind_l2p(self, center, level, rng, tgt, local, pot, overwrite: bool = False):
+        """Like bind_p2m, for L2P (the potentials keep accumulating on every call; with
+        overwrite, the targets' potentials are stored instead)."""
         nb = self._boxes(center, level, rng)
         n = tgt.shape[0]
         _dev(tgt, self.desc.real_dtype, "tgt_xyz", (n, 3))
         _dev(local, self.desc.value_dtype, "local", (nb, self.nc))
         _dev(pot, self.desc.value_dtype, "potential", (n,))
-        fn = _lib.load().fmm_l2p
-        args = (self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(tgt), _ptr(local), _ptr(pot))
-        return lambda: check(fn(*args, _stream()), "fmm_l2p")
+        fn = _lib.load().fmm_l2p_ex
+        args = (self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(tgt), _ptr(local), _ptr(pot),
+                1 if overwrite else 0)
+        return lambda: check(fn(*args, _stream()), "fmm_l2p_ex")
 
-    def l2p(self, center, level, rng, tgt, local, pot) -> torch.Tensor:
+    def l2p(self, center, level, rng, tgt, local, pot, overwrite: bool = False) -> torch.Tensor:
+        """pot += the boxes' local expansions at their targets (overwrite: stored instead)."""
         nb = self._boxes(center, level, rng)
         n = tgt.shape[0]
         _dev(tgt, self.desc.real_dtype, "tgt_xyz", (n, 3))
         _dev(local, self.desc.value_dtype, "local", (nb, self.nc))
         _dev(pot, self.desc.value_dtype, "potential", (n,))
-        check(_lib.load().fmm_l2p(self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(tgt),
-                                  _ptr(local), _ptr(pot), _stream()), "fmm_l2p")
+        check(_lib.load().fmm_l2p_ex(self._h, nb, _ptr(center), _ptr(level), _ptr(rng), n, _ptr(tgt),
+                                     _ptr(local), _ptr(pot), 1 if overwrite else 0, _stream()), "fmm_l2p_ex")
         return pot
 
     def _lists(self, tbox, list_ptr, lst, center, level, rng, xyz):
@@ -359,28 +362,36 @@ class Batch:
               "fmm_batch_info")
         return dict(zip(self.INFO, v.tolist()))
 
-    def __call__(self, mpole: torch.Tensor, local: torch.Tensor) -> torch.Tensor:
-        """Forward batch: local += M2L(mpole).  Adjoint batch: mpole_grad (2nd) += M2L^T(local_grad)."""
+    def __call__(self, mpole: torch.Tensor, local: torch.Tensor, overwrite: bool = False) -> torch.Tensor:
+        """Forward batch: local += M2L(mpole) (overwrite: local = M2L(mpole) for the target rows,
+        streaming-form batches only).  Adjoint batch: mpole_grad (2nd) += M2L^T(local_grad)."""
         d = self.plan.desc
         _dev(mpole, d.value_dtype, "input", (self.n_box, self.plan.nc))
         _dev(local, d.value_dtype, "output", (self.n_box, self.plan.nc))
-        if self.adjoint:
+        if overwrite:
+            check(_lib.load().fmm_m2l_batched_ex(self._h, _ptr(mpole), _ptr(local), 1, _stream()),
+                  "fmm_m2l_batched_ex")
+        elif self.adjoint:
             check(_lib.load().fmm_m2l_batched_adjoint(self._h, _ptr(mpole), _ptr(local), _stream()),
                   "fmm_m2l_batched_adjoint")
         else:
             check(_lib.load().fmm_m2l_batched(self._h, _ptr(mpole), _ptr(local), _stream()), "fmm_m2l_batched")
         return local
 
-    def bind(self, mpole: torch.Tensor, local: torch.Tensor):
+    def bind(self, mpole: torch.Tensor, local: torch.Tensor, overwrite: bool = False):
         """A zero-argument callable that enqueues this batch on the current stream with the
-        given (checked once) tensors; see Plan.bind_p2m."""
+        given (checked once) tensors; see Plan.bind_p2m.  overwrite (forward streaming-form
+        batches): the targets' rows are stored instead of added to."""
         d = self.plan.desc
         _dev(mpole, d.value_dtype, "input", (self.n_box, self.plan.nc))
         _dev(local, d.value_dtype, "output", (self.n_box, self.plan.nc))
         lib = _lib.load()
+        h, a, b = self._h, _ptr(mpole), _ptr(local)
+        if overwrite:
+            fn = lib.fmm_m2l_batched_ex
+            return lambda: check(fn(h, a, b, 1, _stream()), "fmm_m2l_batched_ex")
         fn, name = ((lib.fmm_m2l_batched_adjoint, "fmm_m2l_batched_adjoint") if self.adjoint
                     else (lib.fmm_m2l_batched, "fmm_m2l_batched"))
-        h, a, b = self._h, _ptr(mpole), _ptr(local)
         return lambda: check(fn(h, a, b, _stream()), name)
 
     def close(self):
