@@ -8,6 +8,8 @@
 //   P2L  theta~_t[j] += sum_s sum_{y in s} w(y) G^(j)(c_t - y) h_t^|j|   (one workgroup per
 //        target box: the sums over all sources in a fixed order, one coefficient per lane)
 // Scaled form of Sec. 4.1.1 (t = 1/h of the expansion's own box).  Deterministic.
+// Real Laplace expansions up to order 8 take a faster path (one point per lane, derivatives in
+// registers by the recurrence of eq. deriv_laplace_3d), further below.
 #include "../../include/fmm.h"
 #include "common.hpp"
 #include "device_util.hpp"
@@ -160,9 +162,175 @@ __global__ __launch_bounds__(kPEThreads) void p2l_kernel(PointExpArgs a) {
   }
 }
 
+// ----------------------------------------------------------------------------- Laplace, p <= 8
+//
+// For the Laplace kernel the kept derivatives at one point are computed by one lane, in
+// registers, with the recurrence of eq. deriv_laplace_3d for g = 1/r at the scaled offset X:
+//   r^2 g(n,m,l) = -(2n-1) x g(n-1,m,l) - (n-1)^2 g(n-2,m,l) - 2m y g(n,m-1,l) - m(m-1) g(n,m-2,l)
+//                  - 2l z g(n,m,l-1) - l(l-1) g(n,m,l-2)                             (n >= 1),
+// with x and y exchanged for n = 0 (m >= 1) and the pure z recurrence for n = m = 0.  Every
+// term it reads lies in the kept slab l < 2 itself, so the slab is all the lane holds.  In the
+// scaled form G^(q)(h X) h^|q| = g^(q)(X) / (4 pi h).
+
+constexpr int kLapMaxP = 8;
+
+__host__ __device__ constexpr int lap_nkept(int P) { return (P + 1) * (P + 2) / 2 + P * (P + 1) / 2; }
+
+// position of (x, y, z), z < 2, in the kept order (m_z, then m_x, then m_y fastest)
+__host__ __device__ constexpr int lap_pos(int P, int x, int y, int z) {
+  const int Q = P - z;  // order bound of the slab
+  const int off = z == 0 ? 0 : (P + 1) * (P + 2) / 2;
+  return off + x * (Q + 1) - x * (x - 1) / 2 + y;
+}
+
+template <int P>
+__device__ __forceinline__ void lap_kept_derivs(double X, double Y, double Z, double (&g)[lap_nkept(P)]) {
+  const double r2 = X * X + Y * Y + Z * Z, ir2 = 1.0 / r2;
+#pragma unroll
+  for (int l = 0; l < 2 && l <= P; ++l)
+#pragma unroll
+    for (int n = 0; n <= P - l; ++n)
+#pragma unroll
+      for (int m = 0; m <= P - l - n; ++m) {
+        const int k = lap_pos(P, n, m, l);
+        if (n == 0 && m == 0 && l == 0) {
+          g[k] = sqrt(ir2);
+        } else if (n >= 1) {
+          double v = -(2.0 * n - 1.0) * X * g[lap_pos(P, n - 1, m, l)];
+          if (n >= 2) v -= (double)((n - 1) * (n - 1)) * g[lap_pos(P, n - 2, m, l)];
+          if (m >= 1) v -= 2.0 * m * Y * g[lap_pos(P, n, m - 1, l)];
+          if (m >= 2) v -= (double)(m * (m - 1)) * g[lap_pos(P, n, m - 2, l)];
+          if (l >= 1) v -= 2.0 * l * Z * g[lap_pos(P, n, m, l - 1)];
+          g[k] = v * ir2;
+        } else if (m >= 1) {
+          double v = -(2.0 * m - 1.0) * Y * g[lap_pos(P, 0, m - 1, l)];
+          if (m >= 2) v -= (double)((m - 1) * (m - 1)) * g[lap_pos(P, 0, m - 2, l)];
+          if (l >= 1) v -= 2.0 * l * Z * g[lap_pos(P, 0, m, l - 1)];
+          g[k] = v * ir2;
+        } else {  // n = m = 0, l = 1
+          g[k] = -Z * g[lap_pos(P, 0, 0, 0)] * ir2;
+        }
+      }
+}
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
+
+// M2P: workgroup (k, y) takes the chunks y, y + gridDim.y, ... of 64 targets of box tbox[k];
+// lane = target; the list box's multipole is the same for every lane.
+template <int P, typename R>
+__global__ __launch_bounds__(kPEThreads) void m2p_laplace_kernel(PointExpArgs a) {
+  constexpr int NC = lap_nkept(P);
+  const int64_t k = blockIdx.x;
+  const int t = a.tbox[k];
+  if (t < 0 || t >= a.n_box) return;  // uniform
+  int64_t lo, hi;
+  clamp_range(a, t, lo, hi);
+  int l0, l1;
+  list_bounds(a, k, l0, l1);
+  const R* xyz = reinterpret_cast<const R*>(a.xyz);
+  const R* mp = reinterpret_cast<const R*>(a.mpole);
+  for (int64_t c0 = lo + (int64_t)blockIdx.y * kPEThreads; c0 < hi; c0 += (int64_t)gridDim.y * kPEThreads) {
+    const int64_t i = c0 + threadIdx.x;
+    const bool ok = i < hi;
+    const double x = ok ? (double)xyz[3 * i] : 0.0, y = ok ? (double)xyz[3 * i + 1] : 0.0,
+                 z = ok ? (double)xyz[3 * i + 2] : 0.0;
+    double phi = 0.0;
+    for (int e = l0; e < l1; ++e) {
+      const int s = a.list[e];
+      if (s < 0 || s >= a.n_box) continue;  // uniform
+      const double ih = 1.0 / a.level_h[clamp_level(a, s)];
+      double g[NC];
+      lap_kept_derivs<P>((x - a.center[3 * s]) * ih, (y - a.center[3 * s + 1]) * ih, (z - a.center[3 * s + 2]) * ih, g);
+      const R* beta = mp + (int64_t)s * NC;
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) sum = fma((double)beta[q], g[q], sum);
+      phi = fma(sum, ih, phi);
+    }
+    if (ok) {
+      R* pot = reinterpret_cast<R*>(a.out);
+      pot[i] = (R)((double)pot[i] + phi * kInv4Pi);
+    }
+  }
+}
+
+// P2L: one wavefront per target box; lane = source point, 64 at a time; each chunk's weighted
+// derivatives go through an LDS transpose so that lane l sums coefficients l and l + 64 over
+// the chunk in lane order (deterministic).
+template <int P, typename R>
+__global__ __launch_bounds__(kPEThreads) void p2l_laplace_kernel(PointExpArgs a) {
+  constexpr int NC = lap_nkept(P);
+  constexpr int NJ = (NC + kPEThreads - 1) / kPEThreads;  // coefficients per lane
+  __shared__ double tr[NC][kPEThreads + 1];
+  const int64_t k = blockIdx.x;
+  const int t = a.tbox[k];
+  if (t < 0 || t >= a.n_box) return;  // uniform
+  int l0, l1;
+  list_bounds(a, k, l0, l1);
+  const double ih = 1.0 / a.level_h[clamp_level(a, t)];
+  const double c[3] = {a.center[3 * t], a.center[3 * t + 1], a.center[3 * t + 2]};
+  const R* xyz = reinterpret_cast<const R*>(a.xyz);
+  const R* wv = reinterpret_cast<const R*>(a.w);
+  const int lane = threadIdx.x;
+  double acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = 0.0;
+  for (int e = l0; e < l1; ++e) {
+    const int s = a.list[e];
+    if (s < 0 || s >= a.n_box) continue;  // uniform
+    int64_t lo, hi;
+    clamp_range(a, s, lo, hi);
+    for (int64_t c0 = lo; c0 < hi; c0 += kPEThreads) {  // uniform
+      const int64_t i = c0 + lane;
+      const bool ok = i < hi;
+      double g[NC];
+      lap_kept_derivs<P>(ok ? (c[0] - (double)xyz[3 * i]) * ih : 1.0, ok ? (c[1] - (double)xyz[3 * i + 1]) * ih : 0.0,
+                         ok ? (c[2] - (double)xyz[3 * i + 2]) * ih : 0.0, g);
+      const double wi = ok ? (double)wv[i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) tr[q][lane] = wi * g[q];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int q = lane + j * kPEThreads;
+        if (q < NC) {
+          double v = acc[j];
+          for (int u = 0; u < kPEThreads; ++u) v += tr[q][u];
+          acc[j] = v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  R* loc = reinterpret_cast<R*>(a.out) + (int64_t)t * NC;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int q = lane + j * kPEThreads;
+    if (q < NC) loc[q] = (R)((double)loc[q] + acc[j] * ih * kInv4Pi);
+  }
+}
+
+template <typename R, int P>
+int launch_laplace_p(const PointExpArgs& a, bool m2p, hipStream_t s) {
+  if constexpr (P > kLapMaxP) {
+    return fail(FMM_EUNSUPPORTED, "order");
+  } else {
+    if (a.p != P) return launch_laplace_p<R, P + 1>(a, m2p, s);
+    if (m2p)
+      hipLaunchKernelGGL((m2p_laplace_kernel<P, R>), dim3((unsigned)a.n_tbox, 2), dim3(kPEThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((p2l_laplace_kernel<P, R>), dim3((unsigned)a.n_tbox), dim3(kPEThreads), 0, s, a);
+    FMM_HIP_CHECK(hipGetLastError());
+    return FMM_OK;
+  }
+}
+
 template <typename R, bool CPLX>
 int launch_pe(const PointExpArgs& a, bool m2p, hipStream_t s) {
   if (a.n_tbox == 0) return FMM_OK;
+  if constexpr (!CPLX) {
+    if (a.kernel == FMM_LAPLACE && a.p <= kLapMaxP) return launch_laplace_p<R, 0>(a, m2p, s);
+  }
   if (m2p) {
     // parallel workgroups per target box: enough that a box of 64 points has one per point
     hipLaunchKernelGGL((m2p_kernel<R, CPLX>), dim3((unsigned)a.n_tbox, 64), dim3(kPEThreads), 0, s, a);

@@ -9,7 +9,8 @@ list boxes' sources.  References: the oracle's compressed P2L / M2P with mpmath 
 (the radial formula, no step shared with the GPU's recurrences) for p <= 8 in FP64 and
 complex128, the float64 recurrences (pinned to mpmath) otherwise.  Tolerances: FP64 /
 complex128 1e-12 normwise and per derivative order; FP32 / complex64 1e-5 (FP32 points and
-coefficients, FP64 derivatives and sums)."""
+coefficients, FP64 derivatives and sums).  Real Laplace up to p = 8 runs the one-point-per-lane
+path (derivatives in registers); the other cases the workgroup-per-point path."""
 import numpy as np
 import pytest
 import torch
@@ -23,7 +24,8 @@ pytestmark = pytest.mark.gpu
 
 CASES = [("laplace", 0.0, 8, "f64"), ("laplace", 0.0, 8, "f32"), ("yukawa", 2.0, 6, "f64"),
          ("biharmonic", 0.0, 8, "f64"), ("helmholtz", 1.0, 6, "c128"), ("helmholtz", 3.0, 6, "c64"),
-         ("laplace", 0.0, 12, "f64"), ("biharmonic", 0.0, 4, "f32")]
+         ("laplace", 0.0, 12, "f64"), ("biharmonic", 0.0, 4, "f32"), ("laplace", 0.0, 0, "f64"),
+         ("laplace", 0.0, 5, "f32")]
 
 
 def dev(x, dtype):
