@@ -200,3 +200,48 @@ def m2p(kernel: str, p: int, center, beta, tgt, h: float = 1.0) -> np.ndarray:
             out[k] = float(sum(beta[n] * deriv_mp(kernel, j[0], j[1], dx, dy) * hh ** (j[0] + j[1])
                                for n, j in enumerate(J)))
     return out
+
+
+def m2m(kernel: str, p: int, d, beta, h_child: float = 1.0, h_parent: float = 1.0) -> np.ndarray:
+    """Compressed M2M (Sec. 4.3, eq. define_psi, written out for d = 2): the child's scaled kept
+    coefficients beta~ are unscaled, embedded with zeros on M(p) \\ J (E), translated from the
+    child's centre c1 to the parent's c2, d = c2 - c1, by alpha'_r = sum_{q <= r} alpha_q
+    d^(r-q) / (r-q)! (eq. mpole_translated_full_coeffs) (T), compressed (M^T) and scaled by the
+    parent's size."""
+    c = pde_order(kernel)
+    J, F = kept_set(p, c), full_set(p)
+    M = decompression_matrix(kernel, p)
+    alpha = {q: 0.0 for q in F}
+    for k, q in enumerate(J):
+        alpha[q] = beta[k] * h_child ** (q[0] + q[1])
+    out = np.zeros(len(F))
+    for n, r in enumerate(F):
+        s = 0.0
+        for q in F:
+            if q[0] <= r[0] and q[1] <= r[1]:
+                a, b = r[0] - q[0], r[1] - q[1]
+                s += alpha[q] * d[0] ** a * d[1] ** b / (factorial(a) * factorial(b))
+        out[n] = s
+    psi = M.T @ out
+    return np.array([psi[k] / h_parent ** (q[0] + q[1]) for k, q in enumerate(J)])
+
+
+def l2l(kernel: str, p: int, d, theta, h_parent: float = 1.0, h_child: float = 1.0) -> np.ndarray:
+    """Compressed L2L (Sec. 4.2, eq. l2l-expr, for d = 2): the parent's scaled kept local is
+    unscaled and decompressed (L = M theta), the Taylor polynomial is re-expanded about the
+    child's centre, d = c_child - c_parent: L'_i = sum_k L_(i+k) d^k / k! over |i + k| <= p, and
+    the kept entries are scaled by the child's size."""
+    c = pde_order(kernel)
+    J, F = kept_set(p, c), full_set(p)
+    idx = {q: n for n, q in enumerate(F)}
+    L = decompression_matrix(kernel, p) @ np.array([theta[k] / h_parent ** (q[0] + q[1]) for k, q in enumerate(J)])
+    out = []
+    for i in J:
+        s = 0.0
+        for kx in range(p + 1):
+            for ky in range(p + 1 - kx):
+                m = (i[0] + kx, i[1] + ky)
+                if m[0] + m[1] <= p:
+                    s += L[idx[m]] * d[0] ** kx * d[1] ** ky / (factorial(kx) * factorial(ky))
+        out.append(s * h_child ** (i[0] + i[1]))
+    return np.array(out)

@@ -155,3 +155,38 @@ def test_kept_set_order_and_sizes():
     for p in range(0, 17):
         assert len(T2.kept_set(p, 2)) == 2 * p + 1
         assert len(T2.kept_set(p, 4)) == (T2.n_full(p) - T2.n_full(p - 4) if p >= 4 else T2.n_full(p))
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("p", [1, 5, 9])
+def test_m2m_equals_p2m_about_the_parent(kernel, p):
+    """Both PDEs are homogeneous, so the compressed M2M of a child's P2M is the parent's own
+    P2M of the same sources, to rounding (Sec. 4.3 for d = 2)."""
+    g = np.random.Generator(np.random.PCG64(21 + p))
+    hp, hc = 0.5, 0.25
+    cp = np.array([0.25, 0.75])
+    for o in ((1, 1), (-1, 1), (1, -1), (-1, -1)):
+        cc = cp + 0.5 * hc * np.array(o)
+        src = cc + hc * (g.random((25, 2)) - 0.5)
+        w = g.standard_normal(25)
+        psi = T2.m2m(kernel, p, cp - cc, T2.p2m(kernel, p, cc, src, w, hc), hc, hp)
+        want = T2.p2m(kernel, p, cp, src, w, hp)
+        assert np.abs(psi - want).max() <= 1e-13 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("p", [1, 5, 9])
+def test_l2l_preserves_the_local_expansion(kernel, p):
+    """Re-expanding a local's polynomial about a child centre changes nothing (Sec. 4.2 for
+    d = 2): the child's local evaluated at its targets equals the parent's."""
+    g = np.random.Generator(np.random.PCG64(31 + p))
+    J = T2.kept_set(p, T2.pde_order(kernel))
+    hp, hc = 0.5, 0.25
+    cp = np.array([0.25, 0.75])
+    theta = g.standard_normal(len(J)) * 0.6 ** np.array([a + b for a, b in J])
+    for o in ((1, 1), (-1, 1), (1, -1), (-1, -1)):
+        cc = cp + 0.5 * hc * np.array(o)
+        tgt = cc + hc * (g.random((9, 2)) - 0.5)
+        got = T2.l2p(kernel, p, cc, T2.l2l(kernel, p, cc - cp, theta, hp, hc), tgt, hc)
+        want = T2.l2p(kernel, p, cp, theta, tgt, hp)
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
