@@ -465,6 +465,22 @@ int fmm2d_l2p(const fmm_desc* desc, int64_t n_box, const double* box_center, con
               const int64_t* pt_range, int64_t n_tgt, const double* tgt_xy, const double* local, double* potential,
               int32_t max_tgt_per_box, void* stream);
 
+/* 2-D compressed M2M (Sec. 4.3, eq. define_psi for d = 2): mpole[parent[k]] = sum over the
+ * children child[k][0..3] (ids outside [0, n_box) mean "no child") of M^T T E beta~_child, the
+ * child's kept coefficients embedded in M(p), translated to the parent's centre by the binomial
+ * sums of eq. mpole_translated_full_coeffs and compressed; rescaled between the children's
+ * and the parent's box sizes.  OVERWRITTEN at the parents (zero without children).  Exact for
+ * both 2-D kernels (their PDEs are homogeneous).  A box must not be both a parent and a child
+ * in one call. */
+int fmm2d_m2m(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+              const double* box_center, const double* box_h, double* mpole, void* stream);
+
+/* 2-D compressed L2L (Sec. 4.2, eq. l2l-expr for d = 2): local[child[k][o]] += the kept part of
+ * the parent's decompressed local re-expanded about the child's centre.  ACCUMULATED at the
+ * children.  Children of one call must be distinct and must not be parents in the call. */
+int fmm2d_l2l(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+              const double* box_center, const double* box_h, double* local, void* stream);
+
 /* 2-D direct sum (eq. (1)): potential[x] = sum_y G(x - y) w_y, x == y skipped.  OVERWRITTEN. */
 int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, const double* weight, int64_t n_tgt,
                  const double* tgt_xy, double* potential, void* stream);

@@ -85,6 +85,8 @@ SIGNATURES = {
     "fmm2d_p2m": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, C.c_int32, P]),
     "fmm2d_m2l": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, P]),
     "fmm2d_l2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, P, C.c_int64, P, P, P, C.c_int32, P]),
+    "fmm2d_m2m": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P, P]),
+    "fmm2d_l2l": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P, P]),
     "fmm2d_direct": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, P, P]),
     "fmm2d_p2p": (C.c_int, [C.POINTER(FmmDesc), C.c_int64, P, P, C.c_int64, P, C.c_int64, P, P, C.c_int64, P, P,
                             C.c_int64, P, P, C.c_int32, P]),

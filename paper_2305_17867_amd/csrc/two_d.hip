@@ -268,6 +268,130 @@ __global__ __launch_bounds__(kWg) void l2p2d_kernel(int64_t n_box, const double*
   }
 }
 
+// ----------------------------------------------------------------------------- M2M, L2L
+
+// Powers d^k / k! (k <= p) of the two components of a translation vector, in LDS.
+__device__ void stage_powers(double* px, double* py, double dx, double dy, int p, int lane) {
+  if (lane == 0) {
+    double a = 1.0, b = 1.0;
+    px[0] = py[0] = 1.0;
+    for (int k = 1; k <= p; ++k) {
+      a *= dx / k;
+      b *= dy / k;
+      px[k] = a;
+      py[k] = b;
+    }
+  }
+}
+
+// Compressed M2M (Sec. 4.3, eq. define_psi for d = 2), in the parent's scaled variables: each
+// child's kept coefficients, rescaled to the parent's size ((h_c / h_p)^|q|), are embedded in
+// M(p), translated by the binomial sums alpha'_r = sum_{q <= r} b_q D^(r-q) / (r-q)! with
+// D = (c_p - c_c) / h_p (eq. mpole_translated_full_coeffs), summed over the children and
+// compressed in place.  One wavefront per parent; the parent's row is overwritten.
+__global__ __launch_bounds__(kWg) void m2m2d_kernel(int64_t n_parent, const int32_t* __restrict__ parent,
+                                                   const int32_t* __restrict__ child, int64_t n_box,
+                                                   const double* __restrict__ center, const double* __restrict__ bh,
+                                                   double* __restrict__ mpole, int p, int c, int nc) {
+  __shared__ double grid[kRow * kRow];   // alpha' of the parent (full)
+  __shared__ double emb[kRow * kRow];    // the current child's embedded coefficients
+  __shared__ double px[kRow], py[kRow];
+  const int64_t k = blockIdx.x;
+  const int par = parent[k];
+  if (par < 0 || par >= n_box) return;  // uniform
+  const int lane = threadIdx.x, R = p + 1;
+  for (int e = lane; e < R * R; e += kWg) grid[e] = 0.0;
+  const double hp = bh[par];
+  for (int o = 0; o < 4; ++o) {
+    const int ch = child[4 * k + o];
+    if (ch < 0 || ch >= n_box) continue;  // uniform
+    const double ratio = bh[ch] / hp;
+    for (int e = lane; e < R * R; e += kWg) emb[e] = 0.0;
+    __syncthreads();
+    for (int j = lane; j < nc; j += kWg) {
+      int b = 0, off = 0;
+      while (j >= off + (p - b + 1)) {
+        off += p - b + 1;
+        ++b;
+      }
+      const int a = j - off;
+      emb[a + b * R] = mpole[(int64_t)ch * nc + j] * pow(ratio, (double)(a + b));
+    }
+    stage_powers(px, py, (center[2 * par] - center[2 * ch]) / hp, (center[2 * par + 1] - center[2 * ch + 1]) / hp, p,
+                 lane);
+    __syncthreads();
+    for (int e = lane; e < R * R; e += kWg) {
+      const int ra = e % R, rb = e / R;
+      if (ra + rb > p) continue;
+      double acc = 0.0;
+      for (int qb = 0; qb <= rb && qb < c; ++qb)
+        for (int qa = 0; qa <= ra; ++qa) acc = fma(emb[qa + qb * R], px[ra - qa] * py[rb - qb], acc);
+      grid[e] += acc;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  compress_grid(grid, p, c, lane, kWg);
+  for (int j = lane; j < nc; j += kWg) {
+    int b = 0, off = 0;
+    while (j >= off + (p - b + 1)) {
+      off += p - b + 1;
+      ++b;
+    }
+    mpole[(int64_t)par * nc + j] = grid[(j - off) + b * R];
+  }
+}
+
+// Compressed L2L (Sec. 4.2, eq. l2l-expr for d = 2): the parent's kept local is decompressed in
+// place, its Taylor polynomial re-expanded about each child's centre (L'_i = sum_k L_(i+k)
+// D^k / k!, D = (c_c - c_p) / h_p, scaled variables) and the kept entries, rescaled to the
+// child's size, are added to the child's row.  One wavefront per parent.
+__global__ __launch_bounds__(kWg) void l2l2d_kernel(int64_t n_parent, const int32_t* __restrict__ parent,
+                                                   const int32_t* __restrict__ child, int64_t n_box,
+                                                   const double* __restrict__ center, const double* __restrict__ bh,
+                                                   double* __restrict__ local, int p, int c, int nc) {
+  __shared__ double grid[kRow * kRow];
+  __shared__ double px[kRow], py[kRow];
+  const int64_t k = blockIdx.x;
+  const int par = parent[k];
+  if (par < 0 || par >= n_box) return;  // uniform
+  const int lane = threadIdx.x, R = p + 1;
+  for (int e = lane; e < R * R; e += kWg) grid[e] = 0.0;
+  __syncthreads();
+  for (int j = lane; j < nc; j += kWg) {
+    int b = 0, off = 0;
+    while (j >= off + (p - b + 1)) {
+      off += p - b + 1;
+      ++b;
+    }
+    grid[(j - off) + b * R] = local[(int64_t)par * nc + j];
+  }
+  __syncthreads();
+  decompress_grid(grid, p, c, lane, kWg);
+  const double hp = bh[par];
+  for (int o = 0; o < 4; ++o) {
+    const int ch = child[4 * k + o];
+    if (ch < 0 || ch >= n_box) continue;  // uniform
+    stage_powers(px, py, (center[2 * ch] - center[2 * par]) / hp, (center[2 * ch + 1] - center[2 * par + 1]) / hp, p,
+                 lane);
+    __syncthreads();
+    const double ratio = bh[ch] / hp;
+    for (int j = lane; j < nc; j += kWg) {
+      int b = 0, off = 0;
+      while (j >= off + (p - b + 1)) {
+        off += p - b + 1;
+        ++b;
+      }
+      const int a = j - off;
+      double acc = 0.0;
+      for (int ky = 0; ky <= p - a - b; ++ky)
+        for (int kx = 0; kx <= p - a - b - ky; ++kx) acc = fma(grid[(a + kx) + (b + ky) * R], px[kx] * py[ky], acc);
+      local[(int64_t)ch * nc + j] += acc * pow(ratio, (double)(a + b));
+    }
+    __syncthreads();  // px, py are rewritten for the next child
+  }
+}
+
 // ----------------------------------------------------------------------------- direct, P2P
 
 __device__ __forceinline__ double green2d(int kernel, double r2) {
@@ -461,6 +585,34 @@ int fmm2d_l2p(const fmm_desc* desc, int64_t n_box, const double* box_center, con
   l2p2d_kernel<<<dim3((unsigned)n_box, chunks(max_tgt_per_box, kChunk)), kWg, 0, (hipStream_t)stream>>>(n_box, box_center, box_h, pt_range, n_tgt, tgt_xy,
                                                                   local, potential, p, c, fmm2d::n_kept(p, c));
   return launched("l2p2d_kernel");
+}
+
+int fmm2d_m2m(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+              const double* box_center, const double* box_h, double* mpole, void* stream) {
+  int st = check_desc2d(desc);
+  if (st) return st;
+  FMM_REQUIRE(n_parent >= 0 && n_box >= 0, FMM_EINVAL, "negative size");
+  if (n_parent == 0) return FMM_OK;
+  FMM_REQUIRE(n_parent <= 0x7fffffff, FMM_EINVAL, "too many parents");
+  FMM_REQUIRE(parent && child && box_center && box_h && mpole, FMM_EINVAL, "NULL pointer");
+  const int p = desc->order, c = pde_c(desc);
+  m2m2d_kernel<<<(unsigned)n_parent, kWg, 0, (hipStream_t)stream>>>(n_parent, parent, child, n_box, box_center, box_h,
+                                                                     mpole, p, c, fmm2d::n_kept(p, c));
+  return launched("m2m2d_kernel");
+}
+
+int fmm2d_l2l(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
+              const double* box_center, const double* box_h, double* local, void* stream) {
+  int st = check_desc2d(desc);
+  if (st) return st;
+  FMM_REQUIRE(n_parent >= 0 && n_box >= 0, FMM_EINVAL, "negative size");
+  if (n_parent == 0) return FMM_OK;
+  FMM_REQUIRE(n_parent <= 0x7fffffff, FMM_EINVAL, "too many parents");
+  FMM_REQUIRE(parent && child && box_center && box_h && local, FMM_EINVAL, "NULL pointer");
+  const int p = desc->order, c = pde_c(desc);
+  l2l2d_kernel<<<(unsigned)n_parent, kWg, 0, (hipStream_t)stream>>>(n_parent, parent, child, n_box, box_center, box_h,
+                                                                     local, p, c, fmm2d::n_kept(p, c));
+  return launched("l2l2d_kernel");
 }
 
 int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, const double* weight, int64_t n_tgt,

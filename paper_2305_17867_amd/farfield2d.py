@@ -1,6 +1,10 @@
 """Far field of a uniform quadtree in two dimensions (kernels log r and r^2 log r, Sec. 4.4) from
-the 2-D operators: P2M of every box of the M2L levels, one M2L launch over the List-2 pairs of
-every level, L2P of every level's locals at its boxes' points.
+the 2-D operators, in one of two forms:
+  - per level (default): P2M of every box of the M2L levels, one M2L launch over the List-2
+    pairs of every level, L2P of every level's locals at its boxes' points;
+  - tree pass (tree_pass=True): P2M at the leaves, compressed M2M up the levels (Sec. 4.3), the
+    same M2L, compressed L2L down the levels (Sec. 4.2) and L2P at the leaves.  Both kernels'
+    PDEs are homogeneous, so M2M and L2L are exact and the two forms agree to rounding.
 
 Set-up (host): the pairs are grouped by target box (CSR), and one scaled derivative table is
 made on the device per distinct (level, offset); at most 40 offsets occur per level (7^2 - 3^2).
@@ -16,8 +20,10 @@ from . import fmm
 
 
 class FarField2D:
-    def __init__(self, kernel: str, order: int, tree: "W.QuadTree", levels=None, device="cuda"):
+    def __init__(self, kernel: str, order: int, tree: "W.QuadTree", levels=None, device="cuda",
+                 tree_pass: bool = False):
         self.desc = fmm.Desc(kernel, order, "f64")
+        self.tree_pass = tree_pass
         self.levels = list(range(2, tree.n_levels)) if levels is None else list(levels)
         dev = torch.device(device)
         t, s = W.quad_list2(tree, self.levels)
@@ -42,6 +48,17 @@ class FarField2D:
         self.box_lo = self.level_boxes[self.levels[0]][0]
         counts = tree.pt_range[:, 1] - tree.pt_range[:, 0]
         self.max_count = {l: max(1, int(counts[a:b].max())) for l, (a, b) in self.level_boxes.items()}
+        self.leaf = tree.depth
+        self.family = {}
+        if tree_pass:
+            assert self.levels == list(range(self.levels[0], tree.n_levels)), \
+                "the tree pass needs every level from the first M2L level to the leaves"
+            # parents of level l and their four children (Morton key 4 key + octant) on level l + 1
+            for l in range(self.levels[0], self.leaf):
+                a, b = self.level_boxes[l]
+                par = np.arange(a, b, dtype=np.int64)
+                ch = tree.level_start[l + 1] + 4 * (par - a)[:, None] + np.arange(4)[None, :]
+                self.family[l] = (i32(par), i32(ch))
 
     def p2m(self, w, src):
         """Multipoles of every box of the M2L levels (the boxes' chunks of points are added
@@ -71,8 +88,32 @@ class FarField2D:
                       max_per_box=self.max_count[l])
         return pot
 
+    def upward(self, w, src, mpole):
+        """Tree pass: P2M at the leaves, then M2M level by level up to the first M2L level."""
+        a, b = self.level_boxes[self.leaf]
+        fmm.p2m2d(self.desc, self.center[a:b], self.box_h[a:b], self.rng[a:b], src, w, out=mpole[a:b],
+                  max_per_box=self.max_count[self.leaf])
+        for l in range(self.leaf - 1, self.levels[0] - 1, -1):
+            par, ch = self.family[l]
+            fmm.m2m2d(self.desc, par, ch, self.center, self.box_h, mpole)
+
+    def downward(self, local, tgt, pot):
+        """Tree pass: L2L level by level down to the leaves, then L2P at the leaves."""
+        for l in range(self.levels[0], self.leaf):
+            par, ch = self.family[l]
+            fmm.l2l2d(self.desc, par, ch, self.center, self.box_h, local)
+        a, b = self.level_boxes[self.leaf]
+        fmm.l2p2d(self.desc, self.center[a:b], self.box_h[a:b], self.rng[a:b], tgt, local[a:b], pot,
+                  max_per_box=self.max_count[self.leaf])
+
     def forward(self, w, src, tgt):
+        pot = torch.zeros(tgt.shape[0], dtype=torch.float64, device=w.device)
+        if self.tree_pass:
+            mpole = torch.zeros((self.n_box, self.desc.nc), dtype=torch.float64, device=w.device)
+            self.upward(w, src, mpole)
+            local = self.m2l(mpole)
+            self.downward(local, tgt, pot)
+            return pot, mpole, local
         mpole = self.p2m(w, src)
         local = self.m2l(mpole)
-        pot = torch.zeros(tgt.shape[0], dtype=torch.float64, device=w.device)
         return self.l2p(local, tgt, pot), mpole, local

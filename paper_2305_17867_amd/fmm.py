@@ -653,6 +653,28 @@ def l2p2d(desc: Desc, center, box_h, rng, tgt, local, pot, max_per_box=None) -> 
     return pot
 
 
+def _tree2d(desc: Desc, name, parent, child, center, box_h, coef):
+    npar, nb = parent.shape[0], center.shape[0]
+    _dev(parent, torch.int32, "parent", (npar,))
+    _dev(child, torch.int32, "child", (npar, 4))
+    _dev(center, torch.float64, "box_center", (nb, 2))
+    _dev(box_h, torch.float64, "box_h", (nb,))
+    _dev(coef, torch.float64, "coefficients", (nb, desc.nc))
+    check(getattr(_lib.load(), name)(C.byref(desc.c), npar, _ptr(parent), _ptr(child), nb, _ptr(center),
+                                     _ptr(box_h), _ptr(coef), _stream()), name)
+    return coef
+
+
+def m2m2d(desc: Desc, parent, child, center, box_h, mpole) -> torch.Tensor:
+    """mpole[parent] = compressed M2M of its (up to four) children (overwrites the parents' rows)."""
+    return _tree2d(desc, "fmm2d_m2m", parent, child, center, box_h, mpole)
+
+
+def l2l2d(desc: Desc, parent, child, center, box_h, local) -> torch.Tensor:
+    """local[children] += compressed L2L of their parent's local."""
+    return _tree2d(desc, "fmm2d_l2l", parent, child, center, box_h, local)
+
+
 def direct2d(desc: Desc, src, w, tgt, out=None) -> torch.Tensor:
     ns, nt = src.shape[0], tgt.shape[0]
     _dev(src, torch.float64, "src_xy", (ns, 2))

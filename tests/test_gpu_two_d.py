@@ -216,3 +216,59 @@ def test_complete_2d_fmm_matches_direct_sum(gpu_lib, kernel):
     # the oracle's own complete FMM on this workload: log r 3.1e-6 (p = 8), 7.6e-10 (p = 16);
     # r^2 log r 7.1e-7, 6.1e-11
     assert errs[1] < 2e-5 and errs[2] < 5e-9, errs
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("p", [0, 3, 8, 16])
+def test_m2m_and_l2l_match_oracle(gpu_lib, kernel, p):
+    """Parents on level 2 of a depth-3 quadtree with their four children (one child id replaced
+    by -1: no child); multipoles and locals decaying with the order; per-order check."""
+    tr = W.uniform_quadtree(W.uniform_points2d(500, 14), 3)
+    c = T2.pde_order(kernel)
+    J = np.array(T2.kept_set(p, c))
+    g = np.random.Generator(np.random.PCG64(15))
+    par = tr.boxes_at(2)
+    ch = tr.level_start[3] + 4 * (par - tr.level_start[2])[:, None] + np.arange(4)[None, :]
+    ch[3, 2] = -1
+    hbox = 2.0 ** -tr.level.astype(np.float64)
+    d = gpu_lib.Desc(kernel, p, "f64")
+    args = (dev(par, torch.int32), dev(ch, torch.int32), dev(tr.center), dev(hbox))
+    mp0 = g.standard_normal((tr.n_box, len(J))) * 0.5 ** J.sum(axis=1)
+    mp = dev(mp0)
+    gpu_lib.m2m2d(d, *args, mp)
+    got = host(mp)
+    want = np.zeros((len(par), len(J)))
+    for k, b in enumerate(par):
+        for cb in ch[k]:
+            if cb >= 0:
+                want[k] += T2.m2m(kernel, p, tr.center[b] - tr.center[cb], mp0[cb], hbox[cb], hbox[b])
+    assert per_order(got[par], want, J) < 1e-12
+    others = np.setdiff1d(np.arange(tr.n_box), par)
+    assert np.array_equal(got[others], mp0[others])
+    loc0 = g.standard_normal((tr.n_box, len(J))) * 0.7 ** J.sum(axis=1)
+    loc = dev(loc0)
+    gpu_lib.l2l2d(d, *args, loc)
+    got = host(loc)
+    want = loc0.copy()
+    for k, b in enumerate(par):
+        for cb in ch[k]:
+            if cb >= 0:
+                want[cb] += T2.l2l(kernel, p, tr.center[cb] - tr.center[b], loc0[b], hbox[b], hbox[cb])
+    kids = ch[ch >= 0]
+    assert per_order(got[kids] - loc0[kids], want[kids] - loc0[kids], J) < 1e-12
+    rest = np.setdiff1d(np.arange(tr.n_box), kids)
+    assert np.array_equal(got[rest], loc0[rest])
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_tree_pass_2d_fmm_equals_per_level_form(gpu_lib, kernel):
+    """Both 2-D PDEs are homogeneous, so M2M and L2L are exact: the tree pass (P2M and L2P at the
+    leaves only) gives the per-level far field to rounding."""
+    from paper_2305_17867_amd.farfield2d import FarField2D
+    tr = W.uniform_quadtree(W.uniform_points2d(6000, 16), 5)
+    w = W.normal_weights(6000, 17)
+    P, wd = dev(tr.points), dev(w)
+    for p in (4, 10):
+        a, _, _ = FarField2D(kernel, p, tr).forward(wd, P, P)
+        b, _, _ = FarField2D(kernel, p, tr, tree_pass=True).forward(wd, P, P)
+        assert rel(host(b), host(a)) < 1e-12, p
