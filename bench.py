@@ -798,7 +798,8 @@ def two_d(torch, fmm, checks, reps=10, sample=256):
     every level (one launch; 2 Nc^2 FP64 FLOP per pair against the FP64 peak), L2P level by
     level, the near field of the leaves, and the error of the complete potential against the GPU
     direct sum at sampled targets; the M2L result of one box and the complete potential at a few
-    targets are also compared with the oracle (FP64)."""
+    targets are also compared with the oracle (FP64).  Beside it the tree pass: P2M at the leaves
+    and M2M up, the same M2L, L2L down and L2P at the leaves."""
     import workloads as W
     from paper_2305_17867_amd.farfield2d import FarField2D
     n, depth = 1 << 20, 8
@@ -841,6 +842,19 @@ def two_d(torch, fmm, checks, reps=10, sample=256):
             fmm.p2p2d(d, *near_lists, rng, rng, P, wd, P, pot, max_tgt_per_box=max_leaf)
 
         t_p2m, t_m2l, t_l2p, t_near = (time_kernel(torch, f, reps) for f in (p2m, m2l, l2p, near))
+        # the tree pass: P2M at the leaves + M2M up, the same M2L, L2L down + L2P at the leaves
+        ft = FarField2D(kernel, p, tr, tree_pass=True)
+
+        def up():
+            mpole.zero_()
+            ft.upward(wd, P, mpole)
+
+        def down():
+            ft.downward(local, P, pot)
+
+        t_up, t_down = time_kernel(torch, up, reps), time_kernel(torch, down, reps)
+        pot_t, _, _ = ft.forward(wd, P, P)
+        fmm.p2p2d(d, *near_lists, rng, rng, P, wd, P, pot_t, max_tgt_per_box=max_leaf)
         # the complete potential, once
         p2m()
         local.zero_()
@@ -851,6 +865,7 @@ def two_d(torch, fmm, checks, reps=10, sample=256):
         ref = fmm.direct2d(d, P, wd, P[idx_d].contiguous())
         got = pot[idx_d]
         err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+        err_tree = float(torch.linalg.norm(pot_t[idx_d] - ref) / torch.linalg.norm(ref))
         flops = 2.0 * nc * nc * ff.n_pair
         res = {"kernel": kernel, "order": p, "nc": nc, "m2l_pairs": ff.n_pair, "p2m_ms": t_p2m * 1e3,
                "m2l_ms": t_m2l * 1e3, "l2p_ms": t_l2p * 1e3, "near_ms": t_near * 1e3,
@@ -859,7 +874,9 @@ def two_d(torch, fmm, checks, reps=10, sample=256):
                "m2l_roofline": {"bound": "alu", "achieved": flops / t_m2l / 1e12, "peak": PEAK["f64"] / 1e12,
                                 "unit": "TFLOP/s", "frac": flops / t_m2l / PEAK["f64"],
                                 "algorithmic": f"2*Nc^2 FLOP per pair, Nc={nc}, {ff.n_pair} pairs per launch"},
-               "rel_error_vs_gpu_direct": err, "error_sample": sample}
+               "rel_error_vs_gpu_direct": err, "error_sample": sample,
+               "tree_pass": {"p2m_m2m_ms": t_up * 1e3, "l2l_l2p_ms": t_down * 1e3,
+                             "far_ms": (t_up + t_m2l + t_down) * 1e3, "rel_error_vs_gpu_direct": err_tree}}
         # oracle checks: one target box's M2L result, and the complete potential at 16 targets
         tb = int(tr.level_start[depth] + W.morton2(np.array([[100, 150]]))[0])  # an interior leaf
         k = int(np.flatnonzero(host_np(ff.tbox) == tb)[0])
@@ -876,7 +893,7 @@ def two_d(torch, fmm, checks, reps=10, sample=256):
                    "complete potential at 16 sampled points against the oracle's direct sum over all 2^20 sources")
         log(json.dumps({k_: v for k_, v in res.items() if not isinstance(v, dict)}))
         out.append(res)
-        del mpole, local, pot, ff
+        del mpole, local, pot, ff, ft, pot_t
         torch.cuda.empty_cache()
     return {"workload": f"2-D uniform quadtree, 2^20 points, depth {depth}, FP64", "cases": out}
 
