@@ -11,16 +11,25 @@
 // lane exchanges adds the kSplit partial sums.  Splitting a target's pairs over lanes gives the
 // launch kSplit times the wavefronts, which the memory latency of the pair loop needs.  Every
 // index is a compile-time constant (p, c and the layer are template parameters and the loops
-// are unrolled).
+// are unrolled).  A workgroup reads its tables from LDS where they fit (one copy per workgroup).
 #include "two_d.hpp"
 
 namespace fmm2d {
 namespace {
 
 constexpr int kSplit = 4;
+constexpr int kStageTables = 40;             // tables a workgroup stages in LDS (one level's offsets)
+constexpr int kStageBytes = 64 * 1024;       // the largest static LDS array of a workgroup
 
-template <int P, int C, int IY>
-__device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k, int part) {
+template <int P, int C>
+constexpr int table_size() { return (2 * C - 1) * (2 * P + 1); }
+
+template <int P, int C>
+constexpr bool stages() { return kStageTables * table_size<P, C>() * 8 <= kStageBytes; }
+
+// TB: the tables, in LDS (staged: ids from t0 on) or in global memory (t0 = 0)
+template <int P, int C, int IY, typename TB>
+__device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k, int part, TB tables, int t0) {
   constexpr int NC = n_kept(P, C);
   constexpr int SX = 2 * P + 1;
   constexpr int NR = P - IY + 1;  // outputs of the layer: (ix, IY), ix = 0 .. P - IY
@@ -42,7 +51,7 @@ __device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k, int par
     const int32_t tb = a.pair_tab[e];
     if (s < 0 || s >= a.n_box || tb < 0 || tb >= a.n_tab) continue;
     const double* __restrict__ B = a.mpole + (int64_t)s * NC;
-    const double* __restrict__ T = a.tables + (int64_t)tb * (2 * C - 1) * SX + IY * SX;
+    const auto T = tables + (int64_t)(tb - t0) * (2 * C - 1) * SX + IY * SX;
     double b[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) b[q] = B[q];
@@ -70,27 +79,79 @@ __device__ __forceinline__ void m2l_layer(const M2LArgs2D& a, int64_t k, int par
   for (int ix = 0; ix < NR; ++ix) out[kept_pos(P, ix, IY)] += acc[ix];
 }
 
+template <int P, int C, typename TB>
+__device__ __forceinline__ void m2l_layers(const M2LArgs2D& a, int64_t k, int part, TB tables, int t0) {
+  switch (blockIdx.y) {
+    case 0:
+      m2l_layer<P, C, 0>(a, k, part, tables, t0);
+      break;
+    case 1:
+      if constexpr (P >= 1) m2l_layer<P, C, 1>(a, k, part, tables, t0);
+      break;
+    case 2:
+      if constexpr (C > 2 && P >= 2) m2l_layer<P, C, 2>(a, k, part, tables, t0);
+      break;
+    case 3:
+      if constexpr (C > 3 && P >= 3) m2l_layer<P, C, 3>(a, k, part, tables, t0);
+      break;
+    default:
+      break;
+  }
+}
+
+// The 64 targets of a workgroup are consecutive boxes, almost always of one level, whose pairs
+// use at most the 40 tables of that level's offsets: the workgroup finds the range of table ids
+// its pairs use and, when it is at most kStageTables long, copies those tables into LDS once.
 template <int P, int C>
 __global__ __launch_bounds__(256) void m2l2d_kernel(M2LArgs2D a) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = g / kSplit;  // target; its kSplit lanes are adjacent
   const int part = (int)(g % kSplit);
-  if (k >= a.n_tbox) return;  // the same for all lanes of a group, so exchanges stay in step
-  switch (blockIdx.y) {
-    case 0:
-      m2l_layer<P, C, 0>(a, k, part);
-      break;
-    case 1:
-      if constexpr (P >= 1) m2l_layer<P, C, 1>(a, k, part);
-      break;
-    case 2:
-      if constexpr (C > 2 && P >= 2) m2l_layer<P, C, 2>(a, k, part);
-      break;
-    case 3:
-      if constexpr (C > 3 && P >= 3) m2l_layer<P, C, 3>(a, k, part);
-      break;
-    default:
-      break;
+  if constexpr (stages<P, C>()) {
+    constexpr int TSZ = table_size<P, C>();
+    __shared__ double stab[kStageTables * TSZ];
+    __shared__ int rng[2];
+    if (threadIdx.x == 0) {
+      rng[0] = 0x7fffffff;
+      rng[1] = -1;
+    }
+    __syncthreads();
+    int lo = 0x7fffffff, hi = -1;
+    if (k < a.n_tbox) {
+      const int32_t t = a.tbox[k];
+      if (t >= 0 && t < a.n_box) {
+        int64_t e0 = a.pair_ptr[k], e1 = a.pair_ptr[k + 1];
+        e0 = e0 < 0 ? 0 : (e0 > a.n_pair ? a.n_pair : e0);
+        e1 = e1 < e0 ? e0 : (e1 > a.n_pair ? a.n_pair : e1);
+        for (int64_t e = e0 + part; e < e1; e += kSplit) {
+          const int32_t tb = a.pair_tab[e];
+          if (tb >= 0 && tb < a.n_tab) {
+            lo = tb < lo ? tb : lo;
+            hi = tb > hi ? tb : hi;
+          }
+        }
+      }
+    }
+    if (hi >= lo) {
+      atomicMin(&rng[0], lo);
+      atomicMax(&rng[1], hi);
+    }
+    __syncthreads();
+    const int t0 = rng[0], t1 = rng[1];
+    const bool staged = t1 >= t0 && t1 - t0 < kStageTables;  // uniform
+    if (staged) {
+      const double* src = a.tables + (int64_t)t0 * TSZ;
+      for (int i = threadIdx.x; i < (t1 - t0 + 1) * TSZ; i += blockDim.x) stab[i] = src[i];
+    }
+    __syncthreads();
+    if (k >= a.n_tbox) return;  // the same for all lanes of a group, so exchanges stay in step
+    if (staged)
+      m2l_layers<P, C>(a, k, part, static_cast<const double*>(stab), t0);
+    else
+      m2l_layers<P, C>(a, k, part, a.tables, 0);
+  } else {
+    if (k >= a.n_tbox) return;
+    m2l_layers<P, C>(a, k, part, a.tables, 0);
   }
 }
 
