@@ -680,8 +680,8 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
   const bool cplx = dtype_complex(dtype);
   const int CW = cplx ? 2 : 1;
 
-  // 1. validate pairs, group by (level, offset)
-  std::unordered_map<int64_t, int32_t> tab_of_key;
+  // 1. validate pairs, group by (level, offset); table ids in order of first appearance
+  std::vector<int32_t> tab_of_key((size_t)plan->n_levels * 17 * 289, -1);  // dense over the key range
   std::vector<int64_t> tab_keys;
   std::vector<int32_t> pair_tab(n_pair);
   for (int64_t k = 0; k < n_pair; ++k) {
@@ -700,12 +700,12 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
                 "pair " + std::to_string(k) + ": |offset| > 8");
     FMM_REQUIRE(ox || oy || oz, FMM_EINVAL, "pair " + std::to_string(k) + ": zero offset");
     const int64_t key = ((int64_t)lt * 17 + (ox + 8)) * 289 + (oy + 8) * 17 + (oz + 8);
-    auto it = tab_of_key.find(key);
-    if (it == tab_of_key.end()) {
-      it = tab_of_key.emplace(key, (int32_t)tab_keys.size()).first;
+    int32_t& id = tab_of_key[key];
+    if (id < 0) {
+      id = (int32_t)tab_keys.size();
       tab_keys.push_back(key);
     }
-    pair_tab[k] = it->second;
+    pair_tab[k] = id;
   }
 
   auto* b = new fmm_batch_s();
@@ -876,10 +876,15 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
 
   // 3. target tiles: same level and child parity, then the same set of offsets (signature) where
   //    possible, then Morton order of the parent; NT targets per tile
-  std::vector<int32_t> targets(tgt_box, tgt_box + n_pair);
+  // box id -> position among the targets (dense over the box ids)
+  std::vector<int32_t> tpos(n_box, -1);
+  std::vector<int32_t> targets;
+  for (int64_t k = 0; k < n_pair; ++k)
+    if (tpos[tgt_box[k]] < 0) {
+      tpos[tgt_box[k]] = 0;
+      targets.push_back(tgt_box[k]);
+    }
   std::sort(targets.begin(), targets.end());
-  targets.erase(std::unique(targets.begin(), targets.end()), targets.end());
-  std::unordered_map<int32_t, int32_t> tpos;
   for (size_t k = 0; k < targets.size(); ++k) tpos[targets[k]] = (int32_t)k;
   std::vector<std::vector<int32_t>> sig(targets.size());
   for (int64_t k = 0; k < n_pair; ++k) sig[tpos[tgt_box[k]]].push_back(pair_tab[k]);
@@ -906,7 +911,7 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     return tsig[tpos[a]] < tsig[tpos[c]];
   });
   std::vector<int32_t> tile_tgt;
-  std::unordered_map<int32_t, int32_t> slot_of;  // target -> tile * NT + col
+  std::vector<int32_t> slot_of(n_box, -1);  // target -> tile * NT + col
   {
     int col = NT;
     int64_t prev_group = -1;
@@ -936,9 +941,20 @@ static int prepare_impl(fmm_plan plan, int64_t n_pair, const int32_t* tgt_box, c
     const int32_t sl = slot_of[tgt_box[k]];
     pe[k] = {sl / NT, pair_tab[k], sl % NT, src_box[k]};
   }
-  std::sort(pe.begin(), pe.end(), [](const PE& a, const PE& c) {
-    return std::tie(a.tile, a.tab, a.col) < std::tie(c.tile, c.tab, c.col);
-  });
+  // order by (tile, tab, col): three stable counting passes, least significant key first
+  {
+    std::vector<PE> tmp(n_pair);
+    auto pass = [&](std::vector<PE>& in, std::vector<PE>& out, int64_t n_keys, auto key) {
+      std::vector<int64_t> pos(n_keys + 1, 0);
+      for (const PE& x : in) ++pos[key(x) + 1];
+      for (int64_t i = 0; i < n_keys; ++i) pos[i + 1] += pos[i];
+      for (const PE& x : in) out[pos[key(x)]++] = x;
+    };
+    pass(pe, tmp, NT, [](const PE& x) { return (int64_t)x.col; });
+    pass(tmp, pe, b->n_tab, [](const PE& x) { return (int64_t)x.tab; });
+    pass(pe, tmp, n_tiles, [](const PE& x) { return (int64_t)x.tile; });
+    pe.swap(tmp);
+  }
   std::vector<int32_t> entry_tab, entry_src, tile_e0(n_tiles + 1, 0);
   for (int64_t k = 0; k < n_pair; ++k) {
     if (k > 0 && pe[k].tile == pe[k - 1].tile && pe[k].tab == pe[k - 1].tab && pe[k].col == pe[k - 1].col)
