@@ -1,7 +1,8 @@
 // Two-dimensional kernels G = log r and G = r^2 log r (Sec. 4.4) with the compressed Cartesian
 // Taylor expansions of Secs. 2-3 for d = 2: derivative tables by the paper's recurrences
-// (eqs. deriv_laplace_2d and deriv_biharmonic_2d), P2M with the compression, L2P with the
-// decompression, the direct sum and the near field.  FP64.
+// (eqs. deriv_laplace_2d and deriv_biharmonic_2d), the direct sum, the near field and the
+// launchers of P2M, L2P (two_d_points.hip), M2L (two_d_m2l.hip), M2M and L2L (two_d_shift.hip).
+// FP64.
 //
 // Index sets: M(p) = {(a, b) : a + b <= p}, J = {(a, b) in M(p) : b < c} (c = 2 for the Laplace
 // equation, 4 for the biharmonic one; y is the compressed axis).  Compressing and decompressing
@@ -109,286 +110,6 @@ __global__ void tables2d_kernel(int64_t n, const double* __restrict__ offset, co
       at(2, 0) += h2 * lh * 2;
       at(0, 2) += h2 * lh * 2;
     }
-  }
-}
-
-// ----------------------------------------------------------------------------- P2M, L2P
-
-// Compression in place: alpha over the square grid (a, b), a + b <= p (row length p + 1); the
-// layers b >= c are pushed down by the PDE rule, highest first, so that afterwards the entries
-// with b < c hold beta = M^T alpha.
-__device__ void compress_grid(double* g, int p, int c, int lane, int nl) {
-  const int R = p + 1;
-  for (int b = p; b >= c; --b) {
-    for (int a = lane; a <= p - b; a += nl) {
-      const double v = g[a + b * R];
-      if (c == 2) {
-        g[(a + 2) + (b - 2) * R] -= v;
-      } else {
-        g[(a + 4) + (b - 4) * R] -= v;
-        g[(a + 2) + (b - 2) * R] -= 2.0 * v;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Decompression in place: entries with b < c hold theta; layers b >= c are filled lowest first.
-__device__ void decompress_grid(double* g, int p, int c, int lane, int nl) {
-  const int R = p + 1;
-  for (int b = c; b <= p; ++b) {
-    for (int a = lane; a <= p - b; a += nl) {
-      if (c == 2)
-        g[a + b * R] = -g[(a + 2) + (b - 2) * R];
-      else
-        g[a + b * R] = -g[(a + 4) + (b - 4) * R] - 2.0 * g[(a + 2) + (b - 2) * R];
-    }
-    __syncthreads();
-  }
-}
-
-constexpr int kRow = FMM_MAX_ORDER + 1;  // grid row length bound
-constexpr int kWg = 64;                  // one wavefront per (box, chunk)
-constexpr int kChunk = 256;              // points of a box per workgroup (P2M, L2P)
-
-// alpha~_(a, b) = sum_y w X^a Y^b / (a! b!), (X, Y) = (c - y) / h; beta~ = M^T alpha~.  Workgroup
-// (box, y) takes the chunks y, y + gridDim.y, ... of kChunk points of the box and adds the
-// compressed sum of its points to the box's row atomically (compression is linear).
-__global__ __launch_bounds__(kWg) void p2m2d_kernel(int64_t n_box, const double* __restrict__ center,
-                                                   const double* __restrict__ bh, const int64_t* __restrict__ range,
-                                                   int64_t n_src, const double* __restrict__ xy,
-                                                   const double* __restrict__ w, double* __restrict__ mpole, int p,
-                                                   int c, int nc) {
-  __shared__ double px[kWg][kRow];
-  __shared__ double py[kWg][kRow];
-  __shared__ double ws[kWg];
-  __shared__ double grid[kRow * kRow];
-  const int64_t box = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int R = p + 1;
-  const double cx = center[2 * box], cy = center[2 * box + 1], ih = 1.0 / bh[box];
-  int64_t lo = range[2 * box], hi = range[2 * box + 1];
-  lo = lo < 0 ? 0 : (lo > n_src ? n_src : lo);
-  hi = hi < lo ? lo : (hi > n_src ? n_src : hi);
-  if (lo + (int64_t)blockIdx.y * kChunk >= hi) return;  // no points for this workgroup (uniform)
-  constexpr int kSlots = (kRow * kRow + kWg - 1) / kWg;
-  double acc[kSlots];
-#pragma unroll
-  for (int k = 0; k < kSlots; ++k) acc[k] = 0.0;
-  for (int64_t c0 = lo + (int64_t)blockIdx.y * kChunk; c0 < hi; c0 += (int64_t)gridDim.y * kChunk) {
-  const int64_t c1 = c0 + kChunk < hi ? c0 + kChunk : hi;
-  for (int64_t t0 = c0; t0 < c1; t0 += kWg) {
-    const int64_t i = t0 + lane;
-    double X = 0.0, Y = 0.0, wi = 0.0;
-    if (i < c1) {
-      X = (cx - xy[2 * i]) * ih;
-      Y = (cy - xy[2 * i + 1]) * ih;
-      wi = w[i];
-    }
-    px[lane][0] = 1.0;
-    py[lane][0] = 1.0;
-    for (int a = 1; a <= p; ++a) {
-      px[lane][a] = px[lane][a - 1] * X / a;
-      py[lane][a] = py[lane][a - 1] * Y / a;
-    }
-    ws[lane] = wi;
-    __syncthreads();
-    const int np = (int)(c1 - t0 < kWg ? c1 - t0 : kWg);
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) {
-      const int e = lane + k * kWg;
-      const int a = e % R, b = e / R;
-      if (b <= p && a + b <= p) {
-        double s = acc[k];
-        for (int j = 0; j < np; ++j) s = fma(ws[j] * px[j][a], py[j][b], s);
-        acc[k] = s;
-      }
-    }
-    __syncthreads();
-  }
-  }
-#pragma unroll
-  for (int k = 0; k < kSlots; ++k) {
-    const int e = lane + k * kWg;
-    if (e < R * R) grid[e] = acc[k];
-  }
-  __syncthreads();
-  compress_grid(grid, p, c, lane, kWg);
-  for (int j = lane; j < nc; j += kWg) {
-    // position j of J -> (a, b)
-    int b = 0, off = 0;
-    while (j >= off + (p - b + 1)) {
-      off += p - b + 1;
-      ++b;
-    }
-    atomicAdd(&mpole[box * nc + j], grid[(j - off) + b * R]);
-  }
-}
-
-// phi(x) += sum_(a, b) L~_(a, b) X^a Y^b / (a! b!), (X, Y) = (x - c) / h, L~ = M theta~.  Workgroup
-// (box, y) decompresses the box's local and evaluates it at the chunks y, y + gridDim.y, ... of
-// kChunk targets.
-__global__ __launch_bounds__(kWg) void l2p2d_kernel(int64_t n_box, const double* __restrict__ center,
-                                                   const double* __restrict__ bh, const int64_t* __restrict__ range,
-                                                   int64_t n_tgt, const double* __restrict__ xy,
-                                                   const double* __restrict__ local, double* __restrict__ pot, int p,
-                                                   int c, int nc) {
-  __shared__ double grid[kRow * kRow];
-  const int64_t box = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int R = p + 1;
-  int64_t lo = range[2 * box], hi = range[2 * box + 1];
-  lo = lo < 0 ? 0 : (lo > n_tgt ? n_tgt : lo);
-  hi = hi < lo ? lo : (hi > n_tgt ? n_tgt : hi);
-  if (lo + (int64_t)blockIdx.y * kChunk >= hi) return;  // no targets for this workgroup (uniform)
-  for (int e = lane; e < R * R; e += kWg) grid[e] = 0.0;
-  __syncthreads();
-  for (int j = lane; j < nc; j += kWg) {
-    int b = 0, off = 0;
-    while (j >= off + (p - b + 1)) {
-      off += p - b + 1;
-      ++b;
-    }
-    grid[(j - off) + b * R] = local[box * nc + j];
-  }
-  __syncthreads();
-  decompress_grid(grid, p, c, lane, kWg);
-  const double cx = center[2 * box], cy = center[2 * box + 1], ih = 1.0 / bh[box];
-  for (int64_t c0 = lo + (int64_t)blockIdx.y * kChunk; c0 < hi; c0 += (int64_t)gridDim.y * kChunk)
-  for (int64_t i = c0 + lane; i < (c0 + kChunk < hi ? c0 + kChunk : hi); i += kWg) {
-    const double X = (xy[2 * i] - cx) * ih, Y = (xy[2 * i + 1] - cy) * ih;
-    double outer = 0.0;
-    for (int b = p; b >= 0; --b) {
-      // inner Horner over a with the 1/a! folded in: c_0 + X (c_1 + X/2 (c_2 + ...))
-      double s = grid[(p - b) + b * R];
-      for (int a = p - b - 1; a >= 0; --a) s = fma(s, X / (a + 1), grid[a + b * R]);
-      outer = b == p ? s : fma(outer, Y / (b + 1), s);
-    }
-    pot[i] += outer;
-  }
-}
-
-// ----------------------------------------------------------------------------- M2M, L2L
-
-// Powers d^k / k! (k <= p) of the two components of a translation vector, in LDS.
-__device__ void stage_powers(double* px, double* py, double dx, double dy, int p, int lane) {
-  if (lane == 0) {
-    double a = 1.0, b = 1.0;
-    px[0] = py[0] = 1.0;
-    for (int k = 1; k <= p; ++k) {
-      a *= dx / k;
-      b *= dy / k;
-      px[k] = a;
-      py[k] = b;
-    }
-  }
-}
-
-// Compressed M2M (Sec. 4.3, eq. define_psi for d = 2), in the parent's scaled variables: each
-// child's kept coefficients, rescaled to the parent's size ((h_c / h_p)^|q|), are embedded in
-// M(p), translated by the binomial sums alpha'_r = sum_{q <= r} b_q D^(r-q) / (r-q)! with
-// D = (c_p - c_c) / h_p (eq. mpole_translated_full_coeffs), summed over the children and
-// compressed in place.  One wavefront per parent; the parent's row is overwritten.
-__global__ __launch_bounds__(kWg) void m2m2d_kernel(int64_t n_parent, const int32_t* __restrict__ parent,
-                                                   const int32_t* __restrict__ child, int64_t n_box,
-                                                   const double* __restrict__ center, const double* __restrict__ bh,
-                                                   double* __restrict__ mpole, int p, int c, int nc) {
-  __shared__ double grid[kRow * kRow];   // alpha' of the parent (full)
-  __shared__ double emb[kRow * kRow];    // the current child's embedded coefficients
-  __shared__ double px[kRow], py[kRow];
-  const int64_t k = blockIdx.x;
-  const int par = parent[k];
-  if (par < 0 || par >= n_box) return;  // uniform
-  const int lane = threadIdx.x, R = p + 1;
-  for (int e = lane; e < R * R; e += kWg) grid[e] = 0.0;
-  const double hp = bh[par];
-  for (int o = 0; o < 4; ++o) {
-    const int ch = child[4 * k + o];
-    if (ch < 0 || ch >= n_box) continue;  // uniform
-    const double ratio = bh[ch] / hp;
-    for (int e = lane; e < R * R; e += kWg) emb[e] = 0.0;
-    __syncthreads();
-    for (int j = lane; j < nc; j += kWg) {
-      int b = 0, off = 0;
-      while (j >= off + (p - b + 1)) {
-        off += p - b + 1;
-        ++b;
-      }
-      const int a = j - off;
-      emb[a + b * R] = mpole[(int64_t)ch * nc + j] * pow(ratio, (double)(a + b));
-    }
-    stage_powers(px, py, (center[2 * par] - center[2 * ch]) / hp, (center[2 * par + 1] - center[2 * ch + 1]) / hp, p,
-                 lane);
-    __syncthreads();
-    for (int e = lane; e < R * R; e += kWg) {
-      const int ra = e % R, rb = e / R;
-      if (ra + rb > p) continue;
-      double acc = 0.0;
-      for (int qb = 0; qb <= rb && qb < c; ++qb)
-        for (int qa = 0; qa <= ra; ++qa) acc = fma(emb[qa + qb * R], px[ra - qa] * py[rb - qb], acc);
-      grid[e] += acc;
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  compress_grid(grid, p, c, lane, kWg);
-  for (int j = lane; j < nc; j += kWg) {
-    int b = 0, off = 0;
-    while (j >= off + (p - b + 1)) {
-      off += p - b + 1;
-      ++b;
-    }
-    mpole[(int64_t)par * nc + j] = grid[(j - off) + b * R];
-  }
-}
-
-// Compressed L2L (Sec. 4.2, eq. l2l-expr for d = 2): the parent's kept local is decompressed in
-// place, its Taylor polynomial re-expanded about each child's centre (L'_i = sum_k L_(i+k)
-// D^k / k!, D = (c_c - c_p) / h_p, scaled variables) and the kept entries, rescaled to the
-// child's size, are added to the child's row.  One wavefront per parent.
-__global__ __launch_bounds__(kWg) void l2l2d_kernel(int64_t n_parent, const int32_t* __restrict__ parent,
-                                                   const int32_t* __restrict__ child, int64_t n_box,
-                                                   const double* __restrict__ center, const double* __restrict__ bh,
-                                                   double* __restrict__ local, int p, int c, int nc) {
-  __shared__ double grid[kRow * kRow];
-  __shared__ double px[kRow], py[kRow];
-  const int64_t k = blockIdx.x;
-  const int par = parent[k];
-  if (par < 0 || par >= n_box) return;  // uniform
-  const int lane = threadIdx.x, R = p + 1;
-  for (int e = lane; e < R * R; e += kWg) grid[e] = 0.0;
-  __syncthreads();
-  for (int j = lane; j < nc; j += kWg) {
-    int b = 0, off = 0;
-    while (j >= off + (p - b + 1)) {
-      off += p - b + 1;
-      ++b;
-    }
-    grid[(j - off) + b * R] = local[(int64_t)par * nc + j];
-  }
-  __syncthreads();
-  decompress_grid(grid, p, c, lane, kWg);
-  const double hp = bh[par];
-  for (int o = 0; o < 4; ++o) {
-    const int ch = child[4 * k + o];
-    if (ch < 0 || ch >= n_box) continue;  // uniform
-    stage_powers(px, py, (center[2 * ch] - center[2 * par]) / hp, (center[2 * ch + 1] - center[2 * par + 1]) / hp, p,
-                 lane);
-    __syncthreads();
-    const double ratio = bh[ch] / hp;
-    for (int j = lane; j < nc; j += kWg) {
-      int b = 0, off = 0;
-      while (j >= off + (p - b + 1)) {
-        off += p - b + 1;
-        ++b;
-      }
-      const int a = j - off;
-      double acc = 0.0;
-      for (int ky = 0; ky <= p - a - b; ++ky)
-        for (int kx = 0; kx <= p - a - b - ky; ++kx) acc = fma(grid[(a + kx) + (b + ky) * R], px[kx] * py[ky], acc);
-      local[(int64_t)ch * nc + j] += acc * pow(ratio, (double)(a + b));
-    }
-    __syncthreads();  // px, py are rewritten for the next child
   }
 }
 
@@ -550,10 +271,12 @@ int fmm2d_p2m(const fmm_desc* desc, int64_t n_box, const double* box_center, con
   FMM_REQUIRE(n_box <= 0x7fffffff, FMM_EINVAL, "too many boxes");
   FMM_REQUIRE(box_center && box_h && pt_range && mpole, FMM_EINVAL, "NULL pointer");
   FMM_REQUIRE(n_src == 0 || (src_xy && weight), FMM_EINVAL, "NULL source pointer");
-  const int p = desc->order, c = pde_c(desc);
-  p2m2d_kernel<<<dim3((unsigned)n_box, chunks(max_src_per_box, kChunk)), kWg, 0, (hipStream_t)stream>>>(n_box, box_center, box_h, pt_range, n_src, src_xy,
-                                                                  weight, mpole, p, c, fmm2d::n_kept(p, c));
-  return launched("p2m2d_kernel");
+  PointArgs2D a{n_box, box_center, box_h, pt_range, n_src, src_xy, weight, nullptr, mpole, 0, 0};
+  unsigned columns = 1;
+  point_launch_shape(max_src_per_box, a.lg, a.per_lane, columns);
+  if (!launch_points2d(a, false, desc->order, pde_c(desc), columns, (hipStream_t)stream))
+    return fail(FMM_EUNSUPPORTED, "no 2-D P2M for this order");
+  return launched("p2m2d_points_kernel");
 }
 
 int fmm2d_m2l(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* pair_ptr, int64_t n_pair,
@@ -581,10 +304,13 @@ int fmm2d_l2p(const fmm_desc* desc, int64_t n_box, const double* box_center, con
   FMM_REQUIRE(n_box <= 0x7fffffff, FMM_EINVAL, "too many boxes");
   FMM_REQUIRE(box_center && box_h && pt_range && local, FMM_EINVAL, "NULL pointer");
   FMM_REQUIRE(n_tgt == 0 || (tgt_xy && potential), FMM_EINVAL, "NULL target pointer");
-  const int p = desc->order, c = pde_c(desc);
-  l2p2d_kernel<<<dim3((unsigned)n_box, chunks(max_tgt_per_box, kChunk)), kWg, 0, (hipStream_t)stream>>>(n_box, box_center, box_h, pt_range, n_tgt, tgt_xy,
-                                                                  local, potential, p, c, fmm2d::n_kept(p, c));
-  return launched("l2p2d_kernel");
+  PointArgs2D a{n_box, box_center, box_h, pt_range, n_tgt, tgt_xy, nullptr, potential,
+                const_cast<double*>(local), 0, 0};
+  unsigned columns = 1;
+  point_launch_shape(max_tgt_per_box, a.lg, a.per_lane, columns);
+  if (!launch_points2d(a, true, desc->order, pde_c(desc), columns, (hipStream_t)stream))
+    return fail(FMM_EUNSUPPORTED, "no 2-D L2P for this order");
+  return launched("l2p2d_points_kernel");
 }
 
 int fmm2d_m2m(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
@@ -595,10 +321,10 @@ int fmm2d_m2m(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, con
   if (n_parent == 0) return FMM_OK;
   FMM_REQUIRE(n_parent <= 0x7fffffff, FMM_EINVAL, "too many parents");
   FMM_REQUIRE(parent && child && box_center && box_h && mpole, FMM_EINVAL, "NULL pointer");
-  const int p = desc->order, c = pde_c(desc);
-  m2m2d_kernel<<<(unsigned)n_parent, kWg, 0, (hipStream_t)stream>>>(n_parent, parent, child, n_box, box_center, box_h,
-                                                                     mpole, p, c, fmm2d::n_kept(p, c));
-  return launched("m2m2d_kernel");
+  const ShiftArgs2D a{n_parent, parent, child, n_box, box_center, box_h, mpole};
+  if (!launch_shift2d(a, false, desc->order, pde_c(desc), (hipStream_t)stream))
+    return fail(FMM_EUNSUPPORTED, "no 2-D M2M for this order");
+  return launched("m2m2d_ring_kernel");
 }
 
 int fmm2d_l2l(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, const int32_t* child, int64_t n_box,
@@ -609,10 +335,10 @@ int fmm2d_l2l(const fmm_desc* desc, int64_t n_parent, const int32_t* parent, con
   if (n_parent == 0) return FMM_OK;
   FMM_REQUIRE(n_parent <= 0x7fffffff, FMM_EINVAL, "too many parents");
   FMM_REQUIRE(parent && child && box_center && box_h && local, FMM_EINVAL, "NULL pointer");
-  const int p = desc->order, c = pde_c(desc);
-  l2l2d_kernel<<<(unsigned)n_parent, kWg, 0, (hipStream_t)stream>>>(n_parent, parent, child, n_box, box_center, box_h,
-                                                                     local, p, c, fmm2d::n_kept(p, c));
-  return launched("l2l2d_kernel");
+  const ShiftArgs2D a{n_parent, parent, child, n_box, box_center, box_h, local};
+  if (!launch_shift2d(a, true, desc->order, pde_c(desc), (hipStream_t)stream))
+    return fail(FMM_EUNSUPPORTED, "no 2-D L2L for this order");
+  return launched("l2l2d_ring_kernel");
 }
 
 int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, const double* weight, int64_t n_tgt,

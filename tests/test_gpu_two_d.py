@@ -4,8 +4,10 @@
     complex-analytic derivatives at 50 digits, per derivative order, at every List-2 offset of
     a level and at box sizes 1 to 2^-12;
   - P2M, M2L and L2P against the oracle's definitions, per derivative order, with decaying
-    multipoles and locals so that every order is seen, over boxes with 0, 1, 64 and 150 points
-    (several point tiles and a ragged tail), ids outside the box range, empty pair lists;
+    multipoles and locals so that every order is seen, over boxes with 0, 1, 7, 64, 150 and 2600
+    points in every launch shape of P2M and L2P (lanes per box from 1 to 64, one or several
+    chunk columns, understated and overstated size hints), ids outside the box range, empty
+    pair lists;
   - the direct sum and the near field against the oracle's direct sum;
   - the complete 2-D FMM (far field over List 2 on every level + near field) against the direct
     sum: the error falls with the order.
@@ -84,18 +86,38 @@ def boxes_with_points(seed, counts, h=0.125):
     return np.array(centers), np.concatenate(pts), np.array(rng, dtype=np.int64)
 
 
+# Launch shapes of the 2-D P2M and L2P: the width comes from the largest box (max_per_box), but
+# every point is taken whatever it says.
+#   default: read from the ranges (150 points: 32 lanes per box, one chunk column);
+#   hint 1: one lane per box walks all its points;
+#   hint 5000: full wavefronts, five chunk columns of 1024 points (atomic adds, most empty);
+#   large box: a box of 2600 points over three chunk columns next to small ones.
+SHAPES = {"default": ([0, 1, 64, 150, 7], None), "hint1": ([0, 1, 64, 150, 7], 1),
+          "hint5000": ([0, 1, 64, 150, 7], 5000), "large_box": ([0, 1, 64, 2600, 7, 150], None)}
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("p", [0, 3, 8, 16])
-def test_p2m_matches_oracle(gpu_lib, kernel, p):
+@pytest.mark.parametrize("shape", list(SHAPES))
+def test_p2m_matches_oracle(gpu_lib, kernel, p, shape):
     h = 0.125
-    centers, pts, rng = boxes_with_points(3, [0, 1, 64, 150, 7])
+    counts, hint = SHAPES[shape]
+    centers, pts, rng = boxes_with_points(3, counts)
     w = np.random.Generator(np.random.PCG64(4)).standard_normal(len(pts))
     d = gpu_lib.Desc(kernel, p, "f64")
-    got = host(gpu_lib.p2m2d(d, dev(centers), dev(np.full(len(centers), h)), dev(rng, torch.int64), dev(pts), dev(w)))
+    got = host(gpu_lib.p2m2d(d, dev(centers), dev(np.full(len(centers), h)), dev(rng, torch.int64), dev(pts), dev(w),
+                             max_per_box=hint))
     want = np.array([T2.p2m(kernel, p, centers[k], pts[a:b], w[a:b], h) for k, (a, b) in enumerate(rng)])
     idx = np.array(T2.kept_set(p, T2.pde_order(kernel)))
     assert np.all(got[0] == 0)
     assert per_order(got, want, idx) < 1e-12
+    if hint is None and max(counts) <= 512:
+        # one chunk column: the rows are added plainly, so accumulating into a base gives the
+        # base plus the multipoles bit for bit
+        base = np.random.Generator(np.random.PCG64(5)).standard_normal(got.shape)
+        acc = host(gpu_lib.p2m2d(d, dev(centers), dev(np.full(len(centers), h)), dev(rng, torch.int64), dev(pts),
+                                 dev(w), out=dev(base)))
+        assert np.array_equal(acc, base + got)
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -146,9 +168,11 @@ def test_m2l_matches_oracle(gpu_lib, kernel, p):
 
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("p", [0, 3, 8, 16])
-def test_l2p_matches_oracle(gpu_lib, kernel, p):
+@pytest.mark.parametrize("shape", list(SHAPES))
+def test_l2p_matches_oracle(gpu_lib, kernel, p, shape):
     h = 0.125
-    centers, pts, rng = boxes_with_points(6, [0, 1, 64, 150, 9])
+    counts, hint = SHAPES[shape]
+    centers, pts, rng = boxes_with_points(6, counts)
     c = T2.pde_order(kernel)
     J = np.array(T2.kept_set(p, c))
     g = np.random.Generator(np.random.PCG64(7))
@@ -156,7 +180,8 @@ def test_l2p_matches_oracle(gpu_lib, kernel, p):
     pot0 = g.standard_normal(len(pts))
     d = gpu_lib.Desc(kernel, p, "f64")
     pot = dev(pot0)
-    gpu_lib.l2p2d(d, dev(centers), dev(np.full(len(centers), h)), dev(rng, torch.int64), dev(pts), dev(theta), pot)
+    gpu_lib.l2p2d(d, dev(centers), dev(np.full(len(centers), h)), dev(rng, torch.int64), dev(pts), dev(theta), pot,
+                  max_per_box=hint)
     want = pot0.copy()
     for k, (a, b) in enumerate(rng):
         want[a:b] += T2.l2p(kernel, p, centers[k], theta[k], pts[a:b], h)
