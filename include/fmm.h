@@ -486,9 +486,10 @@ int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, cons
                  const double* tgt_xy, double* potential, void* stream);
 
 /* 2-D near field: potential[targets of tbox[k]] += direct sum over the sources of the boxes
- * nbr[nbr_ptr[k] : nbr_ptr[k+1]] (x == y skipped).  Target boxes of one call must be distinct.
- * max_tgt_per_box sets the launch width (ceil(max / 64) wavefronts per box); every target is
- * computed whatever its value. */
+ * nbr[nbr_ptr[k] : nbr_ptr[k+1]] (x == y skipped).  Target boxes of one call must be distinct;
+ * list ranges are clamped to [0, n_nbr] and ids outside [0, n_box) skipped.  max_tgt_per_box
+ * sets the launch width (ceil(max / 64) wavefronts per box); every target is computed whatever
+ * its value. */
 int fmm2d_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const int32_t* nbr_ptr, int64_t n_nbr,
               const int32_t* nbr, int64_t n_box, const int64_t* tgt_range, const int64_t* src_range, int64_t n_src,
               const double* src_xy, const double* weight, int64_t n_tgt, const double* tgt_xy, double* potential,

@@ -147,54 +147,127 @@ __global__ __launch_bounds__(kTpb) void direct2d_kernel(int kernel, int64_t n_sr
   if (active) pot[i] = acc;
 }
 
+// Natural logarithm of a positive finite x, by the series log m = 2 atanh(s) = 2 (s + s^3/3 +
+// s^5/5 + ...), s = (m - 1) / (m + 1), after x = m 2^e with m in [sqrt(1/2), sqrt(2)) (frexp):
+// |s| <= 0.1716, so ten terms leave a truncation below 2^-55.  ln 2 is split into a high part
+// with eleven trailing zero bits (e ln2_hi is exact) and the rest.  Within 2 ulp of log x
+// (checked against 50-digit logarithms); about a third of the instructions of the library's
+// log, which the near field's interactions are bound by.
+__device__ __forceinline__ double log_series(double x) {
+  constexpr double kLn2Hi = 0x1.62e42fefa3800p-1, kLn2Lo = 0x1.ef35793c76730p-45;
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.70710678118654752440) {
+    m += m;
+    --e;
+  }
+  const double s = (m - 1.0) / (m + 1.0), s2 = s * s;
+  double poly = 1.0 / 19.0;
+  poly = fma(poly, s2, 1.0 / 17.0);
+  poly = fma(poly, s2, 1.0 / 15.0);
+  poly = fma(poly, s2, 1.0 / 13.0);
+  poly = fma(poly, s2, 1.0 / 11.0);
+  poly = fma(poly, s2, 1.0 / 9.0);
+  poly = fma(poly, s2, 1.0 / 7.0);
+  poly = fma(poly, s2, 1.0 / 5.0);
+  poly = fma(poly, s2, 1.0 / 3.0);
+  poly = fma(poly, s2, 1.0);
+  const double de = (double)e;
+  return fma(de, kLn2Hi, fma(de, kLn2Lo, 2.0 * s * poly));
+}
+
+template <int KERNEL>
+__device__ __forceinline__ double green2d_t(double r2) {
+  const double l = 0.5 * log_series(r2 == 0.0 ? 1.0 : r2);
+  const double g = KERNEL == FMM_BIHARMONIC2D ? r2 * l : l;
+  return r2 == 0.0 ? 0.0 : g;  // the x == y term is skipped
+}
+
+struct NearArgs2D {
+  int64_t n_tbox;
+  const int32_t* tbox;
+  const int32_t* nbr_ptr;
+  int64_t n_nbr;
+  const int32_t* nbr;
+  int64_t n_box;
+  const int64_t* trange;
+  const int64_t* srange;
+  int64_t n_src;
+  const double* src;
+  const double* w;
+  int64_t n_tgt;
+  const double* tgt;
+  double* pot;
+};
+
 // Near field: one wavefront per (target box of the list, chunk of 64 of its targets).  A chunk of
 // n targets gives each target `split` adjacent lanes (the largest power of two up to 16 with
-// n * split <= 64), each summing every split-th source of the listed boxes; a butterfly of lane
-// exchanges adds them up.  Sources are read straight from memory (lanes of one target read
-// consecutive sources, the targets of a chunk read the same ones).
-constexpr int kNearWg = 64;
-
-__global__ __launch_bounds__(kNearWg) void p2p2d_kernel(int kernel, int64_t n_tbox, const int32_t* __restrict__ tbox,
-                                                       const int32_t* __restrict__ nbr_ptr, int64_t n_nbr,
-                                                       const int32_t* __restrict__ nbr, int64_t n_box,
-                                                       const int64_t* __restrict__ trange,
-                                                       const int64_t* __restrict__ srange, int64_t n_src,
-                                                       const double* __restrict__ src, const double* __restrict__ w,
-                                                       int64_t n_tgt, const double* __restrict__ tgt,
-                                                       double* __restrict__ pot) {
+// n * split <= 64), each summing every split-th source of the listed boxes (unrolled by four); a
+// butterfly of lane exchanges adds them up.  The list is read 64 entries at a time, one entry per
+// lane (its id, then its source range), and each range is broadcast by a lane exchange, so no
+// chain of dependent loads stands before every listed box.
+template <int KERNEL>
+__global__ __launch_bounds__(64) void p2p2d_kernel(NearArgs2D a) {
   const int64_t k = blockIdx.x;
-  const int32_t t = tbox[k];
-  if (t < 0 || t >= n_box) return;
-  int64_t lo = trange[2 * (int64_t)t], hi = trange[2 * (int64_t)t + 1];
-  lo = lo < 0 ? 0 : (lo > n_tgt ? n_tgt : lo);
-  hi = hi < lo ? lo : (hi > n_tgt ? n_tgt : hi);
-  int64_t e0 = nbr_ptr[k], e1 = nbr_ptr[k + 1];
-  e0 = e0 < 0 ? 0 : (e0 > n_nbr ? n_nbr : e0);
-  e1 = e1 < e0 ? e0 : (e1 > n_nbr ? n_nbr : e1);
+  const int32_t t = a.tbox[k];
+  if (t < 0 || t >= a.n_box) return;  // uniform
+  int64_t lo = a.trange[2 * (int64_t)t], hi = a.trange[2 * (int64_t)t + 1];
+  lo = lo < 0 ? 0 : (lo > a.n_tgt ? a.n_tgt : lo);
+  hi = hi < lo ? lo : (hi > a.n_tgt ? a.n_tgt : hi);
+  int64_t e0 = a.nbr_ptr[k], e1 = a.nbr_ptr[k + 1];
+  e0 = e0 < 0 ? 0 : (e0 > a.n_nbr ? a.n_nbr : e0);
+  e1 = e1 < e0 ? e0 : (e1 > a.n_nbr ? a.n_nbr : e1);
   const int lane = threadIdx.x;
-  for (int64_t c0 = lo + (int64_t)blockIdx.y * kNearWg; c0 < hi; c0 += (int64_t)gridDim.y * kNearWg) {
-    const int n = (int)(hi - c0 < kNearWg ? hi - c0 : kNearWg);
+  for (int64_t c0 = lo + (int64_t)blockIdx.y * 64; c0 < hi; c0 += (int64_t)gridDim.y * 64) {
+    const int n = (int)(hi - c0 < 64 ? hi - c0 : 64);
     int split = 1;
-    while (split < 16 && n * split * 2 <= kNearWg) split *= 2;
+    while (split < 16 && n * split * 2 <= 64) split *= 2;
     const int tl = lane / split, sp = lane % split;
     const bool active = tl < n;
     const int64_t i = c0 + tl;
-    const double x = active ? tgt[2 * i] : 0.0, y = active ? tgt[2 * i + 1] : 0.0;
+    double x = 0.0, y = 0.0;
+    if (active) {
+      x = a.tgt[2 * i];
+      y = a.tgt[2 * i + 1];
+    }
     double acc = 0.0;
-    for (int64_t e = e0; e < e1; ++e) {
-      const int32_t s = nbr[e];
-      if (s < 0 || s >= n_box) continue;
-      int64_t s0 = srange[2 * (int64_t)s], s1 = srange[2 * (int64_t)s + 1];
-      s0 = s0 < 0 ? 0 : (s0 > n_src ? n_src : s0);
-      s1 = s1 < s0 ? s0 : (s1 > n_src ? n_src : s1);
-      if (!active) continue;
-      for (int64_t j = s0 + sp; j < s1; j += split) {
-        const double dx = x - src[2 * j], dy = y - src[2 * j + 1];
-        acc = fma(green2d(kernel, dx * dx + dy * dy), w[j], acc);
+    for (int64_t base = e0; base < e1; base += 64) {
+      int64_t s0 = 0, cnt = 0;
+      if (base + lane < e1) {
+        const int32_t s = a.nbr[base + lane];
+        if (s >= 0 && s < a.n_box) {
+          int64_t b0 = a.srange[2 * (int64_t)s], b1 = a.srange[2 * (int64_t)s + 1];
+          b0 = b0 < 0 ? 0 : (b0 > a.n_src ? a.n_src : b0);
+          b1 = b1 < b0 ? b0 : (b1 > a.n_src ? a.n_src : b1);
+          s0 = b0;
+          cnt = b1 - b0;
+        }
+      }
+      const int jn = (int)(e1 - base < 64 ? e1 - base : 64);
+      for (int j = 0; j < jn; ++j) {
+        const int64_t j0 = __shfl(s0, j, 64);
+        const int64_t j1 = j0 + __shfl(cnt, j, 64);
+        if (!active) continue;
+        int64_t m = j0 + sp;
+        for (; m + 3 * split < j1; m += 4 * split) {
+          double g[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t q = m + u * split;
+            const double dx = x - a.src[2 * q], dy = y - a.src[2 * q + 1];
+            g[u] = green2d_t<KERNEL>(fma(dx, dx, dy * dy));
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc = fma(g[u], a.w[m + u * split], acc);
+        }
+        for (; m < j1; m += split) {
+          const double dx = x - a.src[2 * m], dy = y - a.src[2 * m + 1];
+          acc = fma(green2d_t<KERNEL>(fma(dx, dx, dy * dy)), a.w[m], acc);
+        }
       }
     }
-    for (int m = 1; m < split; m <<= 1) acc += __shfl_xor(acc, m, 64);  // every lane takes part
-    if (active && sp == 0) pot[i] += acc;
+    for (int s = 1; s < split; s <<= 1) acc += __shfl_xor(acc, s, 64);  // every lane takes part
+    if (active && sp == 0) a.pot[i] += acc;
   }
 }
 
@@ -210,12 +283,6 @@ int check_desc2d(const fmm_desc* d) {
 }
 
 inline int pde_c(const fmm_desc* d) { return d->kernel == FMM_BIHARMONIC2D ? 4 : 2; }
-
-// workgroups per box along y for boxes of up to max_per_box points, `per` points each
-inline unsigned chunks(int32_t max_per_box, int per) {
-  const int64_t c = ((int64_t)(max_per_box < 1 ? 1 : max_per_box) + per - 1) / per;
-  return (unsigned)(c > 65535 ? 65535 : c);
-}
 
 int launched(const char* what) {
   const hipError_t e = hipGetLastError();
@@ -367,10 +434,15 @@ int fmm2d_p2p(const fmm_desc* desc, int64_t n_tbox, const int32_t* tbox, const i
   FMM_REQUIRE(tbox && nbr_ptr && tgt_range && src_range && tgt_xy && potential, FMM_EINVAL, "NULL pointer");
   FMM_REQUIRE(n_nbr == 0 || nbr, FMM_EINVAL, "NULL list");
   FMM_REQUIRE(n_src == 0 || (src_xy && weight), FMM_EINVAL, "NULL source pointer");
-  const dim3 grid((unsigned)n_tbox, chunks(max_tgt_per_box, kNearWg));
-  p2p2d_kernel<<<grid, kNearWg, 0, (hipStream_t)stream>>>(desc->kernel, n_tbox, tbox, nbr_ptr, n_nbr, nbr, n_box,
-                                                       tgt_range, src_range, n_src, src_xy, weight, n_tgt, tgt_xy,
-                                                       potential);
+  // workgroups per box along y: one per 64 targets of the largest box
+  const NearArgs2D a{n_tbox, tbox, nbr_ptr, n_nbr, nbr, n_box, tgt_range, src_range, n_src, src_xy, weight, n_tgt,
+                     tgt_xy, potential};
+  const int64_t chunks = ((int64_t)max_tgt_per_box + 63) / 64;
+  const dim3 grid((unsigned)n_tbox, (unsigned)(chunks > 65535 ? 65535 : chunks));
+  if (desc->kernel == FMM_BIHARMONIC2D)
+    p2p2d_kernel<FMM_BIHARMONIC2D><<<grid, 64, 0, (hipStream_t)stream>>>(a);
+  else
+    p2p2d_kernel<FMM_LAPLACE2D><<<grid, 64, 0, (hipStream_t)stream>>>(a);
   return launched("p2p2d_kernel");
 }
 

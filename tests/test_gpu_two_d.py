@@ -190,7 +190,12 @@ def test_l2p_matches_oracle(gpu_lib, kernel, p, shape):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_direct_and_near_field_match_oracle(gpu_lib, kernel):
+@pytest.mark.parametrize("hint", [8, 1, 64, 200])
+def test_direct_and_near_field_match_oracle(gpu_lib, kernel, hint):
+    """Near-field launch widths: hint 8 and 1 are below the largest box (several rounds of
+    targets per lane), 64 and 200 give one group per wavefront.  The lists are the leaves'
+    neighbours, plus one box whose list is every leaf (more entries than a group has lanes),
+    one empty list, an id out of range in a list and a target id out of range."""
     tr = W.uniform_quadtree(W.uniform_points2d(1500, 8), 3)
     pts = tr.points.copy()
     pts[10] = pts[11]  # coincident points: the x == y term is skipped
@@ -200,16 +205,31 @@ def test_direct_and_near_field_match_oracle(gpu_lib, kernel):
     got = host(gpu_lib.direct2d(d, P, wd, P))
     assert rel(got, T2.direct_sum(kernel, pts, w, pts)) < 1e-12
     boxes, ptr, nbr = W.quad_neighbours(tr, 3)
+    leaves = list(range(int(tr.level_start[3]), int(tr.level_start[4])))
+    lists = [list(nbr[ptr[k]:ptr[k + 1]]) for k in range(len(boxes))]
+    lists[0] = leaves                     # 64 entries
+    lists[1] = []                         # nothing to add
+    lists[2] = lists[2] + [-1, tr.n_box]  # skipped ids
+    boxes = list(boxes)
+    lists[3] = []
+    boxes[3] = tr.n_box                   # a target id out of range: skipped
+    ptr = np.concatenate([[0], np.cumsum([len(l) for l in lists])]).astype(np.int32)
+    flat = np.array([b for l in lists for b in l], dtype=np.int32)
     rng = dev(tr.pt_range, torch.int64)
     pot0 = np.random.Generator(np.random.PCG64(10)).standard_normal(len(pts))
     pot = dev(pot0)
     counts = tr.pt_range[:, 1] - tr.pt_range[:, 0]
-    gpu_lib.p2p2d(d, dev(boxes, torch.int32), dev(ptr, torch.int32), dev(nbr, torch.int32), rng, rng, P, wd, P, pot,
-                  max_tgt_per_box=8)  # narrower than the largest box: every target is still computed
+    gpu_lib.p2p2d(d, dev(np.array(boxes), torch.int32), dev(ptr, torch.int32), dev(flat, torch.int32), rng, rng, P,
+                  wd, P, pot, max_tgt_per_box=hint)  # every target is computed whatever the hint says
     want = pot0.copy()
     for k, b in enumerate(boxes):
+        if b >= tr.n_box:
+            continue
         a0, a1 = tr.pt_range[b]
-        src = np.concatenate([np.arange(*tr.pt_range[n]) for n in nbr[ptr[k]:ptr[k + 1]]])
+        ok = [n for n in lists[k] if 0 <= n < tr.n_box]
+        if not ok:
+            continue
+        src = np.concatenate([np.arange(*tr.pt_range[n]) for n in ok])
         want[a0:a1] += T2.direct_sum(kernel, pts[src], w[src], pts[a0:a1])
     assert counts.max() > 8
     assert rel(host(pot) - pot0, want - pot0) < 1e-12
