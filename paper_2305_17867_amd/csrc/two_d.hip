@@ -115,38 +115,6 @@ __global__ void tables2d_kernel(int64_t n, const double* __restrict__ offset, co
 
 // ----------------------------------------------------------------------------- direct, P2P
 
-__device__ __forceinline__ double green2d(int kernel, double r2) {
-  if (r2 == 0.0) return 0.0;
-  const double l = 0.5 * log(r2);
-  return kernel == FMM_BIHARMONIC2D ? r2 * l : l;
-}
-
-constexpr int kTile = 256;
-
-__global__ __launch_bounds__(kTpb) void direct2d_kernel(int kernel, int64_t n_src, const double* __restrict__ src,
-                                                       const double* __restrict__ w, int64_t n_tgt,
-                                                       const double* __restrict__ tgt, double* __restrict__ pot) {
-  __shared__ double sx[kTile], sy[kTile], sw[kTile];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = i < n_tgt;
-  const double x = active ? tgt[2 * i] : 0.0, y = active ? tgt[2 * i + 1] : 0.0;
-  double acc = 0.0;
-  for (int64_t t0 = 0; t0 < n_src; t0 += kTile) {
-    const int64_t j = t0 + threadIdx.x;
-    sx[threadIdx.x] = j < n_src ? src[2 * j] : 0.0;
-    sy[threadIdx.x] = j < n_src ? src[2 * j + 1] : 0.0;
-    sw[threadIdx.x] = j < n_src ? w[j] : 0.0;
-    __syncthreads();
-    const int nt = (int)(n_src - t0 < kTile ? n_src - t0 : kTile);
-    for (int k = 0; k < nt; ++k) {
-      const double dx = x - sx[k], dy = y - sy[k];
-      acc = fma(green2d(kernel, dx * dx + dy * dy), sw[k], acc);
-    }
-    __syncthreads();
-  }
-  if (active) pot[i] = acc;
-}
-
 // Natural logarithm of a positive finite x, by the series log m = 2 atanh(s) = 2 (s + s^3/3 +
 // s^5/5 + ...), s = (m - 1) / (m + 1), after x = m 2^e with m in [sqrt(1/2), sqrt(2)) (frexp):
 // |s| <= 0.1716, so ten terms leave a truncation below 2^-55.  ln 2 is split into a high part
@@ -181,6 +149,39 @@ __device__ __forceinline__ double green2d_t(double r2) {
   const double l = 0.5 * log_series(r2 == 0.0 ? 1.0 : r2);
   const double g = KERNEL == FMM_BIHARMONIC2D ? r2 * l : l;
   return r2 == 0.0 ? 0.0 : g;  // the x == y term is skipped
+}
+
+constexpr int kTile = 256;
+
+// Direct sum: sources staged through LDS in tiles of kTile; each target is taken by `split`
+// adjacent lanes (doubled until the launch has about 1,024 workgroups, at most a wavefront), each
+// on every split-th source of a tile; a butterfly of lane exchanges adds their sums.
+template <int KERNEL>
+__global__ __launch_bounds__(kTpb) void direct2d_kernel(int64_t n_src, const double* __restrict__ src,
+                                                       const double* __restrict__ w, int64_t n_tgt,
+                                                       const double* __restrict__ tgt, double* __restrict__ pot,
+                                                       int split) {
+  __shared__ double sx[kTile], sy[kTile], sw[kTile];
+  const int tl = threadIdx.x / split, sp = threadIdx.x % split;
+  const int64_t i = (int64_t)blockIdx.x * (kTpb / split) + tl;
+  const bool active = i < n_tgt;
+  const double x = active ? tgt[2 * i] : 0.0, y = active ? tgt[2 * i + 1] : 0.0;
+  double acc = 0.0;
+  for (int64_t t0 = 0; t0 < n_src; t0 += kTile) {
+    const int64_t j = t0 + threadIdx.x;
+    sx[threadIdx.x] = j < n_src ? src[2 * j] : 0.0;
+    sy[threadIdx.x] = j < n_src ? src[2 * j + 1] : 0.0;
+    sw[threadIdx.x] = j < n_src ? w[j] : 0.0;
+    __syncthreads();
+    const int nt = (int)(n_src - t0 < kTile ? n_src - t0 : kTile);
+    for (int k = sp; k < nt; k += split) {
+      const double dx = x - sx[k], dy = y - sy[k];
+      acc = fma(green2d_t<KERNEL>(fma(dx, dx, dy * dy)), sw[k], acc);
+    }
+    __syncthreads();
+  }
+  for (int m = 1; m < split; m <<= 1) acc += __shfl_xor(acc, m, 64);
+  if (active && sp == 0) pot[i] = acc;
 }
 
 struct NearArgs2D {
@@ -416,8 +417,15 @@ int fmm2d_direct(const fmm_desc* desc, int64_t n_src, const double* src_xy, cons
   if (n_tgt == 0) return FMM_OK;
   FMM_REQUIRE(tgt_xy && potential, FMM_EINVAL, "NULL target pointer");
   FMM_REQUIRE(n_src == 0 || (src_xy && weight), FMM_EINVAL, "NULL source pointer");
-  direct2d_kernel<<<blocks_for(n_tgt, kTpb), kTpb, 0, (hipStream_t)stream>>>(desc->kernel, n_src, src_xy, weight,
-                                                                            n_tgt, tgt_xy, potential);
+  int split = 1;
+  while (split < 64 && (n_tgt * split + kTpb - 1) / kTpb < 1024) split *= 2;
+  const unsigned grid = blocks_for(n_tgt, kTpb / split);
+  if (desc->kernel == FMM_BIHARMONIC2D)
+    direct2d_kernel<FMM_BIHARMONIC2D><<<grid, kTpb, 0, (hipStream_t)stream>>>(n_src, src_xy, weight, n_tgt, tgt_xy,
+                                                                              potential, split);
+  else
+    direct2d_kernel<FMM_LAPLACE2D><<<grid, kTpb, 0, (hipStream_t)stream>>>(n_src, src_xy, weight, n_tgt, tgt_xy,
+                                                                           potential, split);
   return launched("direct2d_kernel");
 }
 

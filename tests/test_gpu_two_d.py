@@ -190,6 +190,24 @@ def test_l2p_matches_oracle(gpu_lib, kernel, p, shape):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("n_tgt", [65_536 + 37, 262_144 + 101])
+def test_direct_sum_many_targets_sampled(gpu_lib, kernel, n_tgt):
+    """Launch widths of the 2-D direct sum with many targets (4 lanes and 1 lane per target),
+    ragged last workgroup, two source tiles with a ragged tail; one target coincides with a
+    source.  Compared with the oracle's direct sum at 1,500 sampled targets and the last one."""
+    g = np.random.Generator(np.random.PCG64(21))
+    src = g.random((300, 2))
+    w = g.standard_normal(300)
+    tgt = g.random((n_tgt, 2))
+    tgt[5] = src[7]
+    d = gpu_lib.Desc(kernel, 4, "f64")
+    got = host(gpu_lib.direct2d(d, dev(src), dev(w), dev(tgt)))
+    idx = np.unique(np.concatenate([g.choice(n_tgt, 1500, replace=False), [5, n_tgt - 1]]))
+    want = T2.direct_sum(kernel, src, w, tgt[idx])
+    assert rel(got[idx], want) < 1e-12
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("hint", [8, 1, 64, 200])
 def test_direct_and_near_field_match_oracle(gpu_lib, kernel, hint):
     """Near-field launch widths: hint 8 and 1 are below the largest box (several rounds of
