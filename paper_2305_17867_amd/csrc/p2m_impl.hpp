@@ -337,8 +337,230 @@ __global__ __launch_bounds__(kThreads) void p2m_kernel(P2MArgs a) {
   }
 }
 
+// ---- Several boxes per workgroup -------------------------------------------------------------
+// With one box per workgroup, a box of a few hundred points gives each lane only a handful of
+// points, the sums over 64 lanes cost as much as the accumulation, and the launch runs as
+// several rounds of resident workgroups, each paying a whole load -> reduce -> store chain.
+// Here a workgroup takes kQBoxes consecutive boxes: in every wavefront (which still owns a
+// quarter of M(p)), the kQLanes lanes of row r take the points of box r, so each lane
+// accumulates kQBoxes times more points and the sums run over kQLanes lanes only.
+
+constexpr int kQBoxes = 4;
+constexpr int kQLanes = 64 / kQBoxes;  // lanes per box in each wavefront (one DPP row)
+
+// points per box staged per pass (16 KB of real points per workgroup)
+template <typename R>
+constexpr int kQTile = sizeof(R) == 8 ? 128 : 256;
+
+template <typename R, bool CPLX>
+struct QStage {
+  R x[kQBoxes * kQTile<R>], y[kQBoxes * kQTile<R>], z[kQBoxes * kQTile<R>], wr[kQBoxes * kQTile<R>],
+      wi[CPLX ? kQBoxes * kQTile<R> : 1];
+};
+
+struct QBox {
+  double cx, cy, cz, inv_h;
+  int64_t lo;
+  int n, lev;
+};
+
+template <int P, typename R, bool CPLX>
+constexpr size_t quad_lds_bytes() {
+  return sizeof(double) * kQBoxes * nfull(P) * (CPLX ? 2 : 1) + sizeof(QStage<R, CPLX>) +
+         sizeof(R) * kWaves * 64 * kRedStride<R> + sizeof(QBox) * kQBoxes;
+}
+
+// the form is used where its LDS leaves room for three workgroups per CU
+template <int P, typename R, bool CPLX>
+constexpr bool quad_ok() {
+  return quad_lds_bytes<P, R, CPLX>() <= 52u * 1024u;
+}
+
+// Sum over the kQLanes lanes of each row of v[0 .. N-1] into dst_r[k * DS] * scale[k] (dst_r
+// the row's box), through the wavefront's LDS transpose buffer buf [64][kRedStride<R>],
+// kRedW<R> values per pass: each lane adds one value over a group of kRedW lanes of its row,
+// and for kRedW = 8 the two groups of a row are combined by a lane exchange within the row.
+template <int N, int DS, typename R>
+__device__ __forceinline__ void row_sum(const R (&v)[N > 0 ? N : 1], R* buf, int lane, double* dst_r,
+                                        const double* scale) {
+  constexpr int RW = kRedW<R>, RS = kRedStride<R>;
+  constexpr int G = kQLanes / RW;  // groups of lanes per row: 2 (FP64) or 1 (FP32)
+  static_assert(G == 1 || G == 2, "row groups");
+  const int r = lane / kQLanes, k = lane & (kQLanes - 1);
+  const int val = k & (RW - 1), grp = k / RW;
+  const int base = (r * kQLanes + grp * RW) * RS + val;
+#pragma unroll
+  for (int j = 0; j < (N + RW - 1) / RW; ++j) {
+#pragma unroll
+    for (int i = 0; i < RW; ++i) buf[lane * RS + i] = (RW * j + i < N) ? v[RW * j + i] : R(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // this wavefront's writes are in LDS
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < RW; ++i) s += (double)buf[base + i * RS];
+    if constexpr (G == 2) s += xchg<8>(s);
+    if (grp == 0 && RW * j + val < N) dst_r[(RW * j + val) * DS] = s * scale[RW * j + val];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // reads done before the next writes
+  }
+}
+
+// Stage points [t0, t0 + kQTile) of every box of the workgroup (X = s (c - y) h^-1 and w).
+template <typename R, bool CPLX>
+__device__ __forceinline__ void quad_stage(const P2MArgs& a, QStage<R, CPLX>& st, const QBox* bx, int t0) {
+  constexpr int T = kQTile<R>;
+  const R* xyz = reinterpret_cast<const R*>(a.xyz);
+  const R* w = reinterpret_cast<const R*>(a.w);
+#pragma unroll
+  for (int i = 0; i < kQBoxes * T / kThreads; ++i) {
+    const int slot = threadIdx.x + i * kThreads, r = slot / T, j = slot - r * T;
+    if (t0 + j < bx[r].n) {
+      const int64_t s = bx[r].lo + t0 + j;
+      const R ih = (R)bx[r].inv_h;
+      st.x[slot] = ((R)bx[r].cx - xyz[s * 3 + 0]) * ih;
+      st.y[slot] = ((R)bx[r].cy - xyz[s * 3 + 1]) * ih;
+      st.z[slot] = ((R)bx[r].cz - xyz[s * 3 + 2]) * ih;
+      if constexpr (CPLX) {
+        st.wr[slot] = w[2 * s];
+        st.wi[slot] = w[2 * s + 1];
+      } else {
+        st.wr[slot] = w[s];
+      }
+    }
+  }
+}
+
+template <int P, typename R, bool CPLX, int W_, int S_>
+__device__ __forceinline__ void quad_piece(const P2MArgs& a, QStage<R, CPLX>& st, R* buf, const QBox* bx, int nmax,
+                                           int lane, double* alpha) {
+  using PC = Pieces<P, CPLX>;
+  constexpr int A = PC::template q0<W_, S_>(), B = PC::template q1<W_, S_>(), N = B - A;
+  constexpr int T = kQTile<R>;
+  constexpr int WD = CPLX ? 2 : 1;
+  R ar[N > 0 ? N : 1], ai[N > 0 ? N : 1];
+#pragma unroll
+  for (int k = 0; k < (N > 0 ? N : 1); ++k) ar[k] = ai[k] = R(0);
+  const int r = lane / kQLanes, pl = lane & (kQLanes - 1);
+  const int n = bx[r].n;
+  const bool one_tile = nmax <= T;
+  for (int t0 = 0; t0 < nmax; t0 += T) {  // uniform over the workgroup
+    if (!one_tile) {  // the single tile of small boxes was staged once before the pieces
+      __syncthreads();
+      quad_stage<R, CPLX>(a, st, bx, t0);
+      __syncthreads();
+    }
+    const int cnt = n - t0 < T ? n - t0 : T;
+    for (int j = pl; j < cnt; j += kQLanes) {
+      const int sl = r * T + j;
+      accumulate_point<P, A, B, R, CPLX>(ar, ai, st.x[sl], st.y[sl], st.z[sl], st.wr[sl], CPLX ? st.wi[sl] : R(0));
+    }
+  }
+  const double* scale = kInvFact<P>.v + A;
+  double* dst = alpha + (size_t)r * nfull(P) * WD + (size_t)A * WD;
+  if constexpr (CPLX) {
+    row_sum<N, 2, R>(ar, buf, lane, dst, scale);
+    row_sum<N, 2, R>(ai, buf, lane, dst + 1, scale);
+  } else {
+    row_sum<N, 1, R>(ar, buf, lane, dst, scale);
+  }
+}
+
+template <int P, typename R, bool CPLX, int W_, int S_>
+__device__ __forceinline__ void quad_pieces(const P2MArgs& a, QStage<R, CPLX>& st, R* buf, const QBox* bx, int nmax,
+                                            int lane, double* alpha) {
+  if constexpr (S_ < Pieces<P, CPLX>::NS) {
+    quad_piece<P, R, CPLX, W_, S_>(a, st, buf, bx, nmax, lane, alpha);
+    quad_pieces<P, R, CPLX, W_, S_ + 1>(a, st, buf, bx, nmax, lane, alpha);
+  }
+}
+
+template <int P, typename R, bool CPLX>
+__global__ __launch_bounds__(kThreads) void p2m_quad_kernel(P2MArgs a) {
+  constexpr int NP = nfull(P);
+  constexpr int WD = CPLX ? 2 : 1;
+  __shared__ double alpha[kQBoxes * NP * WD];
+  __shared__ QStage<R, CPLX> st;
+  __shared__ R red[kWaves][64 * kRedStride<R>];
+  __shared__ QBox bx[kQBoxes];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t b0 = (int64_t)blockIdx.x * kQBoxes;
+  if (threadIdx.x < kQBoxes) {
+    const int64_t b = b0 + threadIdx.x;
+    QBox q{};
+    if (b < a.n_box) {
+      int lev = a.level[b];
+      lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
+      int64_t lo = a.range[2 * b], hi = a.range[2 * b + 1];
+      lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
+      hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
+      q.cx = a.center[3 * b];
+      q.cy = a.center[3 * b + 1];
+      q.cz = a.center[3 * b + 2];
+      q.inv_h = a.xsign / a.level_h[lev];
+      q.lo = lo;
+      q.n = (int)(hi - lo);
+      q.lev = lev;
+    }
+    bx[threadIdx.x] = q;
+  }
+  __syncthreads();
+  int nmax = 0;
+#pragma unroll
+  for (int r = 0; r < kQBoxes; ++r) nmax = bx[r].n > nmax ? bx[r].n : nmax;
+  if (nmax <= kQTile<R>) {
+    quad_stage<R, CPLX>(a, st, bx, 0);
+    __syncthreads();
+  }
+  R* buf = red[wave];
+  switch (wave) {
+    case 0: quad_pieces<P, R, CPLX, 0, 0>(a, st, buf, bx, nmax, lane, alpha); break;
+    case 1: quad_pieces<P, R, CPLX, 1, 0>(a, st, buf, bx, nmax, lane, alpha); break;
+    case 2: quad_pieces<P, R, CPLX, 2, 0>(a, st, buf, bx, nmax, lane, alpha); break;
+    default: quad_pieces<P, R, CPLX, 3, 0>(a, st, buf, bx, nmax, lane, alpha); break;
+  }
+  __syncthreads();
+  // compression beta~_j = sum_m M~[m][j] alpha~_m of every box of the workgroup (one sparse
+  // row of the box level's M~^T per coefficient)
+  const int nc = a.nc;
+  for (int idx = threadIdx.x; idx < kQBoxes * nc; idx += kThreads) {
+    const int r = idx / nc, j = idx - r * nc;
+    const int64_t b = b0 + r;
+    if (b >= a.n_box) break;  // boxes past the end come last
+    const int32_t* rp = a.cmp_ptr + (int64_t)bx[r].lev * (nc + 1);
+    const double* al = alpha + (size_t)r * NP * WD;
+    double sr = 0.0, si = 0.0;
+    for (int e = rp[j]; e < rp[j + 1]; ++e) {
+      const int m = a.cmp_col[e];
+      const double v = a.cmp_val[e];
+      sr += v * al[WD * m];
+      if constexpr (CPLX) si += v * al[WD * m + 1];
+    }
+    R* out = reinterpret_cast<R*>(a.out) + b * (int64_t)nc * WD;
+    out[WD * j] = (R)sr;
+    if constexpr (CPLX) out[WD * j + 1] = (R)si;
+  }
+}
+
 template <int P>
 int launch_p2m_p(const P2MArgs& a, int dtype, hipStream_t s) {
+  if (a.ny <= 1) {  // boxes not split into chunks: several boxes per workgroup where it fits
+    const dim3 gq((unsigned)((a.n_box + kQBoxes - 1) / kQBoxes)), tq(kThreads);
+    switch (dtype) {
+      case FMM_F64:
+        if constexpr (quad_ok<P, double, false>()) {
+          hipLaunchKernelGGL((p2m_quad_kernel<P, double, false>), gq, tq, 0, s, a);
+          FMM_HIP_CHECK(hipGetLastError());
+          return FMM_OK;
+        }
+        break;
+      case FMM_F32:
+        if constexpr (quad_ok<P, float, false>()) {
+          hipLaunchKernelGGL((p2m_quad_kernel<P, float, false>), gq, tq, 0, s, a);
+          FMM_HIP_CHECK(hipGetLastError());
+          return FMM_OK;
+        }
+        break;
+      default: break;
+    }
+  }
   dim3 g((unsigned)a.n_box, (unsigned)(a.ny > 1 ? a.ny : 1)), t(kThreads);
   switch (dtype) {
     case FMM_F64: hipLaunchKernelGGL((p2m_kernel<P, double, false>), g, t, 0, s, a); break;

@@ -396,6 +396,44 @@ def test_bound_launches_match_calls(gpu_lib, m2l_tree):
     assert torch.equal(p1, p2)
 
 
+@pytest.mark.parametrize("kernel", ["laplace", "biharmonic", "yukawa"])
+@pytest.mark.parametrize("single", [False, True])
+@pytest.mark.parametrize("p", [3, 8, 12])
+def test_p2m_several_boxes_per_workgroup(gpu_lib, kernel, single, p):
+    """Real P2M of boxes that are not split takes several boxes per workgroup: boxes of
+    different sizes (empty, one point, one tile, a tile and one more point, several tiles) and
+    levels share workgroups, and the number of boxes is not a multiple of the boxes per
+    workgroup.  Every box is checked on its own against the oracle, per derivative order."""
+    fmm = gpu_lib
+    tr, w = tree_inputs(1 << 15, 3, 21)
+    d = desc_for(fmm, kernel, p, single)
+    param = CASES[kernel]
+    lh = [tr.box_size(l) for l in range(tr.n_levels)]
+    plan = fmm.Plan(d, lh)
+    l2, l3 = tr.boxes_at(2), tr.boxes_at(3)
+    sizes = [300, 0, 1, 129, 256, 17, 5, 511, 128, 127, 255, 257, 64]
+    boxes = np.array([l2[i] if s > 64 or i % 2 else l3[i] for i, s in enumerate(sizes)])
+    rng = tr.pt_range[boxes].copy()
+    for k, s in enumerate(sizes):
+        rng[k, 1] = rng[k, 0] + min(s, rng[k, 1] - rng[k, 0])
+    got = host(plan.p2m(dev(tr.center[boxes], torch.float64), dev(tr.level[boxes], torch.int32),
+                        dev(rng, torch.int64), dev(tr.points, d.real_dtype), dev(w, d.value_dtype)))
+    perm = perm_to_lib(kernel, param, p, d.index_table())
+    orders = np.array([sum(m) for m in d.index_table()])
+    tol = (2e-6 if p <= 8 else 1e-5) if single else 1e-12
+    assert np.all(got[1] == 0)
+    for k, b in enumerate(boxes):
+        lo, hi = rng[k]
+        if hi == lo:
+            continue
+        beta = Z.p2m(kernel, param, p, tr.center[b], tr.points[lo:hi], w[lo:hi])
+        ref = Z.scale_multipole(kernel, param, p, beta, 1.0 / lh[tr.level[b]])[perm]
+        assert rel(got[k], ref) < tol, (k, hi - lo, rel(got[k], ref))
+        for n in range(p + 1):
+            sel = orders == n
+            assert rel(got[k][sel], ref[sel]) < 50 * tol, (k, n, rel(got[k][sel], ref[sel]))
+
+
 @pytest.mark.parametrize("kernel,single", [("laplace", False), ("helmholtz", False), ("yukawa", True)])
 def test_p2m_large_boxes_split_over_workgroups(gpu_lib, kernel, single):
     """Boxes with tens of thousands of points are spread over several workgroups whose results
