@@ -8,11 +8,12 @@
 // One wavefront per box (a workgroup of 64 lanes, so its barriers cost next to nothing).  The
 // decompressed coefficients live in LDS and are read as wave-wide broadcasts; every lane
 // evaluates KU targets at once with a nested Horner scheme, so that each coefficient read
-// feeds KU fused multiply-adds.  KU is chosen per pass from the points left (1, 2, 4 or 8),
-// so that a pass is not mostly empty: small leaves of adaptive trees take KU = 1, and boxes
-// of a few more than 256 points one pass of KU = 8 instead of two.  The index decode (full index -> (x, y, z)) comes from
-// compile-time tables, and the recursion terms are unrolled so that no per-lane array is
-// indexed dynamically.
+// feeds KU fused multiply-adds.  KU is chosen per pass from the points left (1, 2 or 4), so
+// that a pass is not mostly empty: small leaves of adaptive trees take KU = 1.  Memory reads
+// are issued in groups before their first use (the targets of a pass, the rows of the
+// decompression, the box's locals), never one per branch: a read inside a bounds check waits
+// for its own round trip.  The index decode (full index -> (x, y, z)) comes from compile-time
+// tables, so that no per-lane array is indexed dynamically.
 #pragma once
 
 #include "../../include/fmm.h"
@@ -27,10 +28,10 @@ namespace fmm {
 namespace detail_l2p {
 
 constexpr int kThreads = 64;  // one wavefront per box
-// most targets per lane and pass: 8 for real potentials, 4 where complex values or gradients
-// leave fewer registers
+// most targets per lane and pass (their reads are all issued before the evaluation, which
+// leaves registers for four)
 template <bool CPLX, bool GRAD>
-constexpr int kMaxU = (CPLX || GRAD) ? 4 : 8;
+constexpr int kMaxU = 4;
 constexpr int kChunk = kThreads * 8;  // points of a box per workgroup of the 2-D grid
 constexpr int kWavesPerEU = 4;  // register budget: at most 128 per lane
 
@@ -199,6 +200,94 @@ __device__ inline void horner_u(const R* C, const R (&X)[KU], const R (&Y)[KU], 
     for (int u = 0; u < W; ++u) out[j][u] = pz[j][u];
 }
 
+// The same sum for real values, with the whole nested scheme unrolled at compile time: every
+// row, slab and total starts from its first term (no products with zero), and no registers
+// are moved between loop iterations.  The coefficients are read from LDS in groups of kHG,
+// each group while the previous one is consumed; scheduling barriers between the groups keep
+// the compiler from moving every read to the top (which would hold them all in registers).
+constexpr int kHG = 8;
+
+template <int Q>
+struct HornerSteps {
+  // for position k of the Horner order: the row ends (fold into the slab sum) and the slab ends
+  // (fold into the total); the first row of a slab and the first slab start their sums
+  bool row_start[nfull(Q) > 0 ? nfull(Q) : 1], row_end[nfull(Q) > 0 ? nfull(Q) : 1];
+  bool first_row[nfull(Q) > 0 ? nfull(Q) : 1], slab_end[nfull(Q) > 0 ? nfull(Q) : 1];
+  bool first_slab[nfull(Q) > 0 ? nfull(Q) : 1];
+  constexpr HornerSteps() : row_start(), row_end(), first_row(), slab_end(), first_slab() {
+    int k = 0;
+    for (int z = Q; z >= 0; --z)
+      for (int x = Q - z; x >= 0; --x)
+        for (int y = Q - z - x; y >= 0; --y) {
+          row_start[k] = y == Q - z - x;
+          row_end[k] = y == 0;
+          first_row[k] = x == Q - z;
+          slab_end[k] = y == 0 && x == 0;
+          first_slab[k] = z == Q;
+          ++k;
+        }
+  }
+};
+
+template <int Q>
+__device__ constexpr HornerSteps<Q> kSteps{};
+
+template <int KU, int Q, typename R>
+__device__ inline void horner_unrolled(const R* C, const R (&X)[KU], const R (&Y)[KU], const R (&Z)[KU],
+                                       R (&out)[KU][1]) {
+  constexpr int NP = nfull(Q);
+  constexpr int G = kHG;
+  constexpr int NG = (NP + G - 1) / G;
+  constexpr HornerSteps<Q> S{};
+  R pz[KU], qx[KU], ry[KU];
+  R cb[2][G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) cb[0][i] = i < NP ? C[i] : R(0);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    if (g + 1 < NG) {
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+        if ((g + 1) * G + i < NP) cb[(g + 1) & 1][i] = C[(g + 1) * G + i];
+    }
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int k = g * G + i;
+      if (k < NP) {
+        const R c = cb[g & 1][i];
+#pragma unroll
+        for (int j = 0; j < KU; ++j) ry[j] = S.row_start[k] ? c : ry[j] * Y[j] + c;
+        if (S.row_end[k]) {
+#pragma unroll
+          for (int j = 0; j < KU; ++j) qx[j] = S.first_row[k] ? ry[j] : qx[j] * X[j] + ry[j];
+        }
+        if (S.slab_end[k]) {
+#pragma unroll
+          for (int j = 0; j < KU; ++j) pz[j] = S.first_slab[k] ? qx[j] : pz[j] * Z[j] + qx[j];
+        }
+      }
+    }
+    // the group's products happen here, before the next group's reads are issued (the
+    // compiler would otherwise place every product after the last read)
+#pragma unroll
+    for (int j = 0; j < KU; ++j) asm volatile("" : "+v"(ry[j]), "+v"(qx[j]), "+v"(pz[j]));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // the sums are used only under the callers' bounds checks; without this use here the
+  // compiler sinks every product chain into those branches, past the grouped reads
+#pragma unroll
+  for (int j = 0; j < KU; ++j) {
+    asm volatile("" : "+v"(pz[j]));
+    out[j][0] = pz[j];
+  }
+}
+
+// orders whose real potentials take the unrolled scheme: its code grows with N(p) times the
+// targets per lane, and at p = 12 (455 coefficients) it ran 2.5x slower than the loop form
+constexpr int kMaxUnrolledOrder = 9;
+
 // One pass over the next KU * 64 targets of the box from s0 (each lane takes KU of them, 64
 // apart): potentials and, for GRAD, gradients.  Returns the number of targets covered.
 template <int P, typename R, bool CPLX, bool GRAD, int KU, typename LG>
@@ -206,27 +295,41 @@ __device__ inline int pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R*
                            R cy, R cz, R ih) {
   constexpr int W = CPLX ? 2 : 1;
   const int64_t t0 = s0 + threadIdx.x;
+  // Every read of a group is issued before any of it is used: lanes past the end read point s0
+  // (in range: s0 < hi) and drop the value, so no read sits in a branch of its own that waits
+  // for it.  The values that are added to (accumulating potentials, gradients) are read after
+  // the evaluation, so they hold no registers during it.
+  const auto at = [&](int j) {
+    const int64_t s = t0 + (int64_t)j * kThreads;
+    return s < hi ? s : s0;
+  };
   R X[KU], Y[KU], Z[KU];
 #pragma unroll
   for (int j = 0; j < KU; ++j) {
-    const int64_t s = t0 + (int64_t)j * kThreads;
-    const bool ok = s < hi;
-    X[j] = ok ? (xyz[3 * s + 0] - cx) * ih : R(0);
-    Y[j] = ok ? (xyz[3 * s + 1] - cy) * ih : R(0);
-    Z[j] = ok ? (xyz[3 * s + 2] - cz) * ih : R(0);
+    const int64_t s = at(j);
+    const R x = xyz[3 * s + 0], y = xyz[3 * s + 1], z = xyz[3 * s + 2];
+    const bool ok = t0 + (int64_t)j * kThreads < hi;
+    X[j] = ok ? (x - cx) * ih : R(0);
+    Y[j] = ok ? (y - cy) * ih : R(0);
+    Z[j] = ok ? (z - cz) * ih : R(0);
   }
-  if (a.pot) {
+  R* pot = reinterpret_cast<R*>(a.pot);
+  if (pot) {
     R v[KU][W];
-    horner_u<KU, P, W, R>(Lc, X, Y, Z, v);
-    R* pot = reinterpret_cast<R*>(a.pot);
+    if constexpr (!CPLX && !GRAD && P <= kMaxUnrolledOrder) horner_unrolled<KU, P, R>(Lc, X, Y, Z, v);
+    else horner_u<KU, P, W, R>(Lc, X, Y, Z, v);
+    if (!a.overwrite) {
 #pragma unroll
-    for (int j = 0; j < KU; ++j) {
-      const int64_t s = t0 + (int64_t)j * kThreads;
-      if (s < hi) {
+      for (int j = 0; j < KU; ++j)
 #pragma unroll
-        for (int u = 0; u < W; ++u) pot[s * W + u] = a.overwrite ? v[j][u] : pot[s * W + u] + v[j][u];
-      }
+        for (int u = 0; u < W; ++u) v[j][u] += pot[at(j) * W + u];
     }
+#pragma unroll
+    for (int j = 0; j < KU; ++j)
+      if (t0 + (int64_t)j * kThreads < hi) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) pot[at(j) * W + u] = v[j][u];
+      }
   }
   if constexpr (GRAD && P > 0 && !CPLX) {
     R g[3][KU][1];
@@ -234,17 +337,72 @@ __device__ inline int pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R*
     horner_u<KU, P - 1, 1, R>(Lg[1], X, Y, Z, g[1]);
     horner_u<KU, P - 1, 1, R>(Lg[2], X, Y, Z, g[2]);
     R* gout = reinterpret_cast<R*>(a.grad);
+    const R* gs = reinterpret_cast<const R*>(a.gscale);
 #pragma unroll
     for (int j = 0; j < KU; ++j) {
-      const int64_t s = t0 + (int64_t)j * kThreads;
-      if (s < hi) {
-        const R sc = a.gscale ? reinterpret_cast<const R*>(a.gscale)[s] : R(1);
+      const R sc = gs ? gs[at(j)] : R(1);
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) gout[3 * s + ax] += sc * ih * g[ax][j][0];
-      }
+      for (int ax = 0; ax < 3; ++ax) g[ax][j][0] = gout[3 * at(j) + ax] + sc * ih * g[ax][j][0];
     }
+#pragma unroll
+    for (int j = 0; j < KU; ++j)
+      if (t0 + (int64_t)j * kThreads < hi) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) gout[3 * at(j) + ax] = g[ax][j][0];
+      }
   }
   return KU * kThreads;
+}
+
+// Rows k = lane + i * 64 (i < NK) of a level's sparse decompression: out[i] = theta~_k for kept
+// rows (k < nc), and sum_e val[e] src[col[e]] over the row's entries otherwise.  The row bounds
+// of all NK rows, then the first PRE entries of every row, are read before any of them is
+// used, so a lane waits for two memory round trips instead of one per entry (rows longer than
+// PRE finish in a loop).  About 24 entries per lane are read ahead.
+template <int NK>
+constexpr int kPre = 24 / NK > 8 ? 8 : (24 / NK < 2 ? 2 : 24 / NK);
+
+template <int NK, int W, int PRE = kPre<NK * W>>
+__device__ inline void sparse_rows(const int32_t* rp, const int32_t* col, const double* val, const double* src,
+                                   int nc, int np, double (&out)[NK][W]) {
+  int e0[NK], e1[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const int k = threadIdx.x + i * kThreads;
+    const bool dec = k >= nc && k < np;
+    const int kk = k < np ? k : 0;
+    const int lo = rp[kk], hi = rp[kk + 1];
+    e0[i] = dec ? lo : 0;
+    e1[i] = dec ? hi : 0;
+  }
+  int cj[NK][PRE];
+  double cv[NK][PRE];
+#pragma unroll
+  for (int i = 0; i < NK; ++i)
+#pragma unroll
+    for (int t = 0; t < PRE; ++t) {
+      const int e = e0[i] + t < e1[i] ? e0[i] + t : 0;  // the arrays hold at least one entry
+      cj[i][t] = col[e];
+      cv[i][t] = val[e];
+    }
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const int k = threadIdx.x + i * kThreads;
+#pragma unroll
+    for (int u = 0; u < W; ++u) out[i][u] = k < nc ? src[k * W + u] : 0.0;
+#pragma unroll
+    for (int t = 0; t < PRE; ++t)
+      if (e0[i] + t < e1[i]) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) out[i][u] += cv[i][t] * src[cj[i][t] * W + u];
+      }
+    for (int e = e0[i] + PRE; e < e1[i]; ++e) {
+      const int j = col[e];
+      const double v = val[e];
+#pragma unroll
+      for (int u = 0; u < W; ++u) out[i][u] += v * src[j * W + u];
+    }
+  }
 }
 
 template <int P, typename R, bool CPLX, bool GRAD>
@@ -268,7 +426,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const double h = a.level_h[lev];
   const int nc = a.nc;
   const R* loc = reinterpret_cast<const R*>(a.local) + b * (int64_t)nc * W;
-  for (int k = threadIdx.x; k < nc * W; k += kThreads) Ld[k] = (double)loc[k];
+  {  // all reads of the box's locals first (the last lanes re-read entry 0), then the LDS stores
+    constexpr int NL = (NP * W + kThreads - 1) / kThreads;
+    R lv[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int k = threadIdx.x + i * kThreads;
+      lv[i] = loc[k < nc * W ? k : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int k = threadIdx.x + i * kThreads;
+      if (k < nc * W) Ld[k] = (double)lv[i];
+    }
+  }
   if (threadIdx.x < 2 * W) {
     Lc[NP * W + threadIdx.x] = R(0);
 #pragma unroll
@@ -279,18 +450,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   // of the level's M~ per full index, read from the kept prefix only, so no level waits for
   // another
   const int32_t* rp = a.dec_ptr + (int64_t)lev * (NP + 1);
-  for (int k = threadIdx.x; k < NP; k += kThreads) {
-    double lv[W];
+  constexpr int NK = (NP + kThreads - 1) / kThreads;  // full indices per lane
+  double lvs[NK][W];
+  if constexpr (NK <= 4) {
+    sparse_rows<NK, W>(rp, a.dec_col, a.dec_val, Ld, nc, NP, lvs);
+  } else {  // high orders: too many rows per lane to read ahead
 #pragma unroll
-    for (int u = 0; u < W; ++u) lv[u] = k < nc ? Ld[k * W + u] : 0.0;
-    if (k >= nc) {
-      for (int e = rp[k]; e < rp[k + 1]; ++e) {
-        const int j = a.dec_col[e];
-        const double v = a.dec_val[e];
+    for (int i = 0; i < NK; ++i) {
+      const int k = threadIdx.x + i * kThreads;
 #pragma unroll
-        for (int u = 0; u < W; ++u) lv[u] += v * Ld[j * W + u];
+      for (int u = 0; u < W; ++u) lvs[i][u] = k < nc ? Ld[k * W + u] : 0.0;
+      if (k >= nc && k < NP) {
+        for (int e = rp[k]; e < rp[k + 1]; ++e) {
+          const int j = a.dec_col[e];
+          const double v = a.dec_val[e];
+#pragma unroll
+          for (int u = 0; u < W; ++u) lvs[i][u] += v * Ld[j * W + u];
+        }
       }
     }
+  }
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const int k = threadIdx.x + i * kThreads;
+    if (k >= NP) break;
+    double lv[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) lv[u] = lvs[i][u];
     const double f = kDecode<P>.inv_fact[k];
     const int hk = kHorner<P>.pos[k];
 #pragma unroll

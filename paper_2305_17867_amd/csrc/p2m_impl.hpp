@@ -404,26 +404,46 @@ __device__ __forceinline__ void row_sum(const R (&v)[N > 0 ? N : 1], R* buf, int
 }
 
 // Stage points [t0, t0 + kQTile) of every box of the workgroup (X = s (c - y) h^-1 and w).
+// Every read is issued before any is used: slots past a box's end read point 0 (the workgroup
+// holds at least one point, so the array is not empty) and store nothing.
 template <typename R, bool CPLX>
 __device__ __forceinline__ void quad_stage(const P2MArgs& a, QStage<R, CPLX>& st, const QBox* bx, int t0) {
   constexpr int T = kQTile<R>;
+  constexpr int NS = kQBoxes * T / kThreads;  // slots per thread
   const R* xyz = reinterpret_cast<const R*>(a.xyz);
   const R* w = reinterpret_cast<const R*>(a.w);
+  int64_t src[NS];
+  bool ok[NS];
 #pragma unroll
-  for (int i = 0; i < kQBoxes * T / kThreads; ++i) {
+  for (int i = 0; i < NS; ++i) {
     const int slot = threadIdx.x + i * kThreads, r = slot / T, j = slot - r * T;
-    if (t0 + j < bx[r].n) {
-      const int64_t s = bx[r].lo + t0 + j;
+    ok[i] = t0 + j < bx[r].n;
+    src[i] = ok[i] ? bx[r].lo + t0 + j : 0;
+  }
+  R px[NS], py[NS], pz[NS], wr[NS], wi[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    px[i] = xyz[src[i] * 3 + 0];
+    py[i] = xyz[src[i] * 3 + 1];
+    pz[i] = xyz[src[i] * 3 + 2];
+    if constexpr (CPLX) {
+      wr[i] = w[2 * src[i]];
+      wi[i] = w[2 * src[i] + 1];
+    } else {
+      wr[i] = w[src[i]];
+      wi[i] = R(0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int slot = threadIdx.x + i * kThreads, r = slot / T;
+    if (ok[i]) {
       const R ih = (R)bx[r].inv_h;
-      st.x[slot] = ((R)bx[r].cx - xyz[s * 3 + 0]) * ih;
-      st.y[slot] = ((R)bx[r].cy - xyz[s * 3 + 1]) * ih;
-      st.z[slot] = ((R)bx[r].cz - xyz[s * 3 + 2]) * ih;
-      if constexpr (CPLX) {
-        st.wr[slot] = w[2 * s];
-        st.wi[slot] = w[2 * s + 1];
-      } else {
-        st.wr[slot] = w[s];
-      }
+      st.x[slot] = ((R)bx[r].cx - px[i]) * ih;
+      st.y[slot] = ((R)bx[r].cy - py[i]) * ih;
+      st.z[slot] = ((R)bx[r].cz - pz[i]) * ih;
+      st.wr[slot] = wr[i];
+      if constexpr (CPLX) st.wi[slot] = wi[i];
     }
   }
 }
@@ -505,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void p2m_quad_kernel(P2MArgs a) {
   int nmax = 0;
 #pragma unroll
   for (int r = 0; r < kQBoxes; ++r) nmax = bx[r].n > nmax ? bx[r].n : nmax;
-  if (nmax <= kQTile<R>) {
+  if (nmax > 0 && nmax <= kQTile<R>) {
     quad_stage<R, CPLX>(a, st, bx, 0);
     __syncthreads();
   }
