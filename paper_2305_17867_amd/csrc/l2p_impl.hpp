@@ -28,10 +28,13 @@ namespace fmm {
 namespace detail_l2p {
 
 constexpr int kThreads = 64;  // one wavefront per box
-// most targets per lane and pass (their reads are all issued before the evaluation, which
-// leaves registers for four)
+// most targets per lane and pass: 8 for real potentials, 4 where complex values or gradients
+// leave fewer registers.  The unrolled evaluation (whose reads are all issued before it) takes
+// at most 4: a box of a few more than 256 points then runs a pass of 4 and a short one, which
+// measured faster than one pass of 6 (boxes of the uniform level hold 256 +- 16 points).
 template <bool CPLX, bool GRAD>
-constexpr int kMaxU = 4;
+constexpr int kMaxU = (CPLX || GRAD) ? 4 : 8;
+constexpr int kMaxUnrolledU = 4;
 constexpr int kChunk = kThreads * 8;  // points of a box per workgroup of the 2-D grid
 constexpr int kWavesPerEU = 4;  // register budget: at most 128 per lane
 
@@ -290,15 +293,64 @@ constexpr int kMaxUnrolledOrder = 9;
 
 // One pass over the next KU * 64 targets of the box from s0 (each lane takes KU of them, 64
 // apart): potentials and, for GRAD, gradients.  Returns the number of targets covered.
+// The pass for the loop form of the evaluation (orders above the unrolled ones, complex values,
+// gradients): each target's reads sit in its bounds check.  Grouping them ahead, as in pass()
+// below, gained nothing with the loop form at p = 8 and made p = 12 slower.
 template <int P, typename R, bool CPLX, bool GRAD, int KU, typename LG>
-__device__ inline int pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R* xyz, int64_t s0, int64_t hi, R cx,
-                           R cy, R cz, R ih) {
+__device__ inline int pass_loop(const L2PArgs& a, const R* Lc, const LG& Lg, const R* xyz, int64_t s0, int64_t hi,
+                                R cx, R cy, R cz, R ih) {
   constexpr int W = CPLX ? 2 : 1;
   const int64_t t0 = s0 + threadIdx.x;
-  // Every read of a group is issued before any of it is used: lanes past the end read point s0
-  // (in range: s0 < hi) and drop the value, so no read sits in a branch of its own that waits
-  // for it.  The values that are added to (accumulating potentials, gradients) are read after
-  // the evaluation, so they hold no registers during it.
+  R X[KU], Y[KU], Z[KU];
+#pragma unroll
+  for (int j = 0; j < KU; ++j) {
+    const int64_t s = t0 + (int64_t)j * kThreads;
+    const bool ok = s < hi;
+    X[j] = ok ? (xyz[3 * s + 0] - cx) * ih : R(0);
+    Y[j] = ok ? (xyz[3 * s + 1] - cy) * ih : R(0);
+    Z[j] = ok ? (xyz[3 * s + 2] - cz) * ih : R(0);
+  }
+  if (a.pot) {
+    R v[KU][W];
+    horner_u<KU, P, W, R>(Lc, X, Y, Z, v);
+    R* pot = reinterpret_cast<R*>(a.pot);
+#pragma unroll
+    for (int j = 0; j < KU; ++j) {
+      const int64_t s = t0 + (int64_t)j * kThreads;
+      if (s < hi) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) pot[s * W + u] = a.overwrite ? v[j][u] : pot[s * W + u] + v[j][u];
+      }
+    }
+  }
+  if constexpr (GRAD && P > 0 && !CPLX) {
+    R g[3][KU][1];
+    horner_u<KU, P - 1, 1, R>(Lg[0], X, Y, Z, g[0]);
+    horner_u<KU, P - 1, 1, R>(Lg[1], X, Y, Z, g[1]);
+    horner_u<KU, P - 1, 1, R>(Lg[2], X, Y, Z, g[2]);
+    R* gout = reinterpret_cast<R*>(a.grad);
+#pragma unroll
+    for (int j = 0; j < KU; ++j) {
+      const int64_t s = t0 + (int64_t)j * kThreads;
+      if (s < hi) {
+        const R sc = a.gscale ? reinterpret_cast<const R*>(a.gscale)[s] : R(1);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) gout[3 * s + ax] += sc * ih * g[ax][j][0];
+      }
+    }
+  }
+  return KU * kThreads;
+}
+
+// The pass for real potentials with the unrolled evaluation (orders up to kMaxUnrolledOrder).
+// Every read of a group is issued before any of it is used: lanes past the end read point s0
+// (in range: s0 < hi) and drop the value, so no read sits in a branch of its own that waits for
+// it.  The old potentials (when adding) are read after the evaluation, so they hold no
+// registers during it.
+template <int P, typename R, int KU>
+__device__ inline int pass(const L2PArgs& a, const R* Lc, const R* xyz, int64_t s0, int64_t hi, R cx, R cy, R cz,
+                           R ih) {
+  const int64_t t0 = s0 + threadIdx.x;
   const auto at = [&](int j) {
     const int64_t s = t0 + (int64_t)j * kThreads;
     return s < hi ? s : s0;
@@ -315,43 +367,27 @@ __device__ inline int pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R*
   }
   R* pot = reinterpret_cast<R*>(a.pot);
   if (pot) {
-    R v[KU][W];
-    if constexpr (!CPLX && !GRAD && P <= kMaxUnrolledOrder) horner_unrolled<KU, P, R>(Lc, X, Y, Z, v);
-    else horner_u<KU, P, W, R>(Lc, X, Y, Z, v);
+    R v[KU][1];
+    horner_unrolled<KU, P, R>(Lc, X, Y, Z, v);
     if (!a.overwrite) {
 #pragma unroll
-      for (int j = 0; j < KU; ++j)
-#pragma unroll
-        for (int u = 0; u < W; ++u) v[j][u] += pot[at(j) * W + u];
+      for (int j = 0; j < KU; ++j) v[j][0] += pot[at(j)];
     }
 #pragma unroll
     for (int j = 0; j < KU; ++j)
-      if (t0 + (int64_t)j * kThreads < hi) {
-#pragma unroll
-        for (int u = 0; u < W; ++u) pot[at(j) * W + u] = v[j][u];
-      }
-  }
-  if constexpr (GRAD && P > 0 && !CPLX) {
-    R g[3][KU][1];
-    horner_u<KU, P - 1, 1, R>(Lg[0], X, Y, Z, g[0]);
-    horner_u<KU, P - 1, 1, R>(Lg[1], X, Y, Z, g[1]);
-    horner_u<KU, P - 1, 1, R>(Lg[2], X, Y, Z, g[2]);
-    R* gout = reinterpret_cast<R*>(a.grad);
-    const R* gs = reinterpret_cast<const R*>(a.gscale);
-#pragma unroll
-    for (int j = 0; j < KU; ++j) {
-      const R sc = gs ? gs[at(j)] : R(1);
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) g[ax][j][0] = gout[3 * at(j) + ax] + sc * ih * g[ax][j][0];
-    }
-#pragma unroll
-    for (int j = 0; j < KU; ++j)
-      if (t0 + (int64_t)j * kThreads < hi) {
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) gout[3 * at(j) + ax] = g[ax][j][0];
-      }
+      if (t0 + (int64_t)j * kThreads < hi) pot[at(j)] = v[j][0];
   }
   return KU * kThreads;
+}
+
+// The unrolled evaluation with grouped reads where it applies (a pass of 8 targets per lane
+// becomes one of 4), else the loop form.
+template <int P, typename R, bool CPLX, bool GRAD, int KU, typename LG>
+__device__ inline int any_pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R* xyz, int64_t s0, int64_t hi, R cx,
+                               R cy, R cz, R ih) {
+  if constexpr (!CPLX && !GRAD && P <= kMaxUnrolledOrder)
+    return pass<P, R, (KU < kMaxUnrolledU ? KU : kMaxUnrolledU)>(a, Lc, xyz, s0, hi, cx, cy, cz, ih);
+  else return pass_loop<P, R, CPLX, GRAD, KU>(a, Lc, Lg, xyz, s0, hi, cx, cy, cz, ih);
 }
 
 // Rows k = lane + i * 64 (i < NK) of a level's sparse decompression: out[i] = theta~_k for kept
@@ -426,7 +462,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   const double h = a.level_h[lev];
   const int nc = a.nc;
   const R* loc = reinterpret_cast<const R*>(a.local) + b * (int64_t)nc * W;
-  {  // all reads of the box's locals first (the last lanes re-read entry 0), then the LDS stores
+  constexpr int NK = (NP + kThreads - 1) / kThreads;  // full indices per lane
+  if constexpr (NK > 4) {  // high orders: the plain loop (grouping the reads was slower at p = 12)
+    for (int k = threadIdx.x; k < nc * W; k += kThreads) Ld[k] = (double)loc[k];
+  } else {  // all reads of the box's locals first (the last lanes re-read entry 0), then the LDS stores
     constexpr int NL = (NP * W + kThreads - 1) / kThreads;
     R lv[NL];
 #pragma unroll
@@ -450,33 +489,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   // of the level's M~ per full index, read from the kept prefix only, so no level waits for
   // another
   const int32_t* rp = a.dec_ptr + (int64_t)lev * (NP + 1);
-  constexpr int NK = (NP + kThreads - 1) / kThreads;  // full indices per lane
-  double lvs[NK][W];
-  if constexpr (NK <= 4) {
-    sparse_rows<NK, W>(rp, a.dec_col, a.dec_val, Ld, nc, NP, lvs);
-  } else {  // high orders: too many rows per lane to read ahead
-#pragma unroll
-    for (int i = 0; i < NK; ++i) {
-      const int k = threadIdx.x + i * kThreads;
-#pragma unroll
-      for (int u = 0; u < W; ++u) lvs[i][u] = k < nc ? Ld[k * W + u] : 0.0;
-      if (k >= nc && k < NP) {
-        for (int e = rp[k]; e < rp[k + 1]; ++e) {
-          const int j = a.dec_col[e];
-          const double v = a.dec_val[e];
-#pragma unroll
-          for (int u = 0; u < W; ++u) lvs[i][u] += v * Ld[j * W + u];
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NK; ++i) {
-    const int k = threadIdx.x + i * kThreads;
-    if (k >= NP) break;
-    double lv[W];
-#pragma unroll
-    for (int u = 0; u < W; ++u) lv[u] = lvs[i][u];
+  // the coefficient of full index k (decompressed value lv) in Horner order, scaled by 1 / k!,
+  // and for GRAD the coefficients of its derivatives
+  const auto put = [&](int k, const double (&lv)[W]) {
     const double f = kDecode<P>.inv_fact[k];
     const int hk = kHorner<P>.pos[k];
 #pragma unroll
@@ -494,6 +509,31 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
         for (int u = 0; u < W; ++u) Lg[ax][g * W + u] = (R)(lv[u] * fg);
       }
     }
+  };
+  if constexpr (NK <= 4) {
+    double lvs[NK][W];
+    sparse_rows<NK, W>(rp, a.dec_col, a.dec_val, Ld, nc, NP, lvs);
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const int k = threadIdx.x + i * kThreads;
+      if (k >= NP) break;
+      put(k, lvs[i]);
+    }
+  } else {  // high orders: too many rows per lane to read ahead
+    for (int k = threadIdx.x; k < NP; k += kThreads) {
+      double lv[W];
+#pragma unroll
+      for (int u = 0; u < W; ++u) lv[u] = k < nc ? Ld[k * W + u] : 0.0;
+      if (k >= nc) {
+        for (int e = rp[k]; e < rp[k + 1]; ++e) {
+          const int j = a.dec_col[e];
+          const double v = a.dec_val[e];
+#pragma unroll
+          for (int u = 0; u < W; ++u) lv[u] += v * Ld[j * W + u];
+        }
+      }
+      put(k, lv);
+    }
   }
   __syncthreads();
   const double cen[3] = {a.center[3 * b], a.center[3 * b + 1], a.center[3 * b + 2]};
@@ -505,10 +545,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
     for (int64_t s0 = c0; s0 < c1;) {  // passes sized to the points left in the chunk
       const int64_t left = c1 - s0;
       int step;
-      if (left <= kThreads) step = pass<P, R, CPLX, GRAD, 1>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
-      else if (left <= 2 * kThreads) step = pass<P, R, CPLX, GRAD, 2>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
-      else if (KM == 4 || left <= 4 * kThreads) step = pass<P, R, CPLX, GRAD, 4>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
-      else step = pass<P, R, CPLX, GRAD, KM>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      if (left <= kThreads) step = any_pass<P, R, CPLX, GRAD, 1>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      else if (left <= 2 * kThreads) step = any_pass<P, R, CPLX, GRAD, 2>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      else if (KM == 4 || left <= 4 * kThreads) step = any_pass<P, R, CPLX, GRAD, 4>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
+      else step = any_pass<P, R, CPLX, GRAD, KM>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
       s0 += step;
     }
   }
