@@ -30,11 +30,12 @@ namespace detail_l2p {
 constexpr int kThreads = 64;  // one wavefront per box
 // most targets per lane and pass: 8 for real potentials, 4 where complex values or gradients
 // leave fewer registers.  The unrolled evaluation (whose reads are all issued before it) takes
-// at most 4: a box of a few more than 256 points then runs a pass of 4 and a short one, which
-// measured faster than one pass of 6 (boxes of the uniform level hold 256 +- 16 points).
+// at most 5: a box of a few more than 256 points (boxes of a uniform level of 2^20 points
+// hold 256 +- 16) runs one pass of 5 instead of a pass of 4 and a short second one (which
+// repeats the whole sweep over the coefficients); a pass of 6 measured slower than both.
 template <bool CPLX, bool GRAD>
 constexpr int kMaxU = (CPLX || GRAD) ? 4 : 8;
-constexpr int kMaxUnrolledU = 4;
+constexpr int kMaxUnrolledU = 5;
 constexpr int kChunk = kThreads * 8;  // points of a box per workgroup of the 2-D grid
 constexpr int kWavesPerEU = 4;  // register budget: at most 128 per lane
 
@@ -381,7 +382,7 @@ __device__ inline int pass(const L2PArgs& a, const R* Lc, const R* xyz, int64_t 
 }
 
 // The unrolled evaluation with grouped reads where it applies (a pass of 8 targets per lane
-// becomes one of 4), else the loop form.
+// becomes one of 5), else the loop form.
 template <int P, typename R, bool CPLX, bool GRAD, int KU, typename LG>
 __device__ inline int any_pass(const L2PArgs& a, const R* Lc, const LG& Lg, const R* xyz, int64_t s0, int64_t hi, R cx,
                                R cy, R cz, R ih) {
