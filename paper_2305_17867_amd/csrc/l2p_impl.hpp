@@ -348,9 +348,9 @@ __device__ inline int pass_loop(const L2PArgs& a, const R* Lc, const LG& Lg, con
 // (in range: s0 < hi) and drop the value, so no read sits in a branch of its own that waits for
 // it.  The old potentials (when adding) are read after the evaluation, so they hold no
 // registers during it.
-template <int P, typename R, int KU>
+template <int P, typename R, int KU, bool PRE = false>
 __device__ inline int pass(const L2PArgs& a, const R* Lc, const R* xyz, int64_t s0, int64_t hi, R cx, R cy, R cz,
-                           R ih) {
+                           R ih, const R (*pre)[kMaxUnrolledU] = nullptr) {
   const int64_t t0 = s0 + threadIdx.x;
   const auto at = [&](int j) {
     const int64_t s = t0 + (int64_t)j * kThreads;
@@ -359,8 +359,17 @@ __device__ inline int pass(const L2PArgs& a, const R* Lc, const R* xyz, int64_t 
   R X[KU], Y[KU], Z[KU];
 #pragma unroll
   for (int j = 0; j < KU; ++j) {
-    const int64_t s = at(j);
-    const R x = xyz[3 * s + 0], y = xyz[3 * s + 1], z = xyz[3 * s + 2];
+    R x, y, z;
+    if constexpr (PRE) {  // read at the start of the kernel
+      x = pre[0][j];
+      y = pre[1][j];
+      z = pre[2][j];
+    } else {
+      const int64_t s = at(j);
+      x = xyz[3 * s + 0];
+      y = xyz[3 * s + 1];
+      z = xyz[3 * s + 2];
+    }
     const bool ok = t0 + (int64_t)j * kThreads < hi;
     X[j] = ok ? (x - cx) * ih : R(0);
     Y[j] = ok ? (y - cy) * ih : R(0);
@@ -458,6 +467,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   lo = lo < 0 ? 0 : (lo > a.n_pts ? a.n_pts : lo);
   hi = hi < lo ? lo : (hi > a.n_pts ? a.n_pts : hi);
   if (lo + (int64_t)blockIdx.y * ch >= hi) return;  // uniform: no points for this workgroup
+  constexpr bool UNR = !CPLX && !GRAD && P <= kMaxUnrolledOrder;
+  const R* xyz = reinterpret_cast<const R*>(a.xyz);
+  // the unrolled form reads the coordinates of its first pass here, so that they arrive while
+  // the locals are read and decompressed (lanes past the chunk read its first point)
+  const int64_t f0 = lo + (int64_t)blockIdx.y * ch, f1 = f0 + ch < hi ? f0 + ch : hi;
+  R pre[3][kMaxUnrolledU];
+  const bool use_pre = UNR && f1 - f0 > 2 * kThreads;  // small leaves keep their narrow passes
+  if (use_pre) {
+#pragma unroll
+    for (int j = 0; j < kMaxUnrolledU; ++j) {
+      const int64_t s = f0 + threadIdx.x + (int64_t)j * kThreads;
+      const int64_t sc = s < f1 ? s : f0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) pre[ax][j] = xyz[3 * sc + ax];
+    }
+  }
   int lev = a.level[b];
   lev = lev < 0 ? 0 : (lev >= a.n_levels ? a.n_levels - 1 : lev);
   const double h = a.level_h[lev];
@@ -513,7 +538,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   };
   if constexpr (NK <= 4) {
     double lvs[NK][W];
-    sparse_rows<NK, W>(rp, a.dec_col, a.dec_val, Ld, nc, NP, lvs);
+    // (about 12 entries per lane read ahead where the first pass's coordinates are in flight)
+    constexpr int PRE = UNR ? (12 / NK > 8 ? 8 : (12 / NK < 2 ? 2 : 12 / NK)) : kPre<NK * W>;
+    sparse_rows<NK, W, PRE>(rp, a.dec_col, a.dec_val, Ld, nc, NP, lvs);
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       const int k = threadIdx.x + i * kThreads;
@@ -538,12 +565,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWaves
   }
   __syncthreads();
   const double cen[3] = {a.center[3 * b], a.center[3 * b + 1], a.center[3 * b + 2]};
-  const R* xyz = reinterpret_cast<const R*>(a.xyz);
   const R cx = (R)cen[0], cy = (R)cen[1], cz = (R)cen[2], ih = (R)(a.xsign / h);
   constexpr int KM = kMaxU<CPLX, GRAD>;
-  for (int64_t c0 = lo + (int64_t)blockIdx.y * ch; c0 < hi; c0 += (int64_t)gridDim.y * ch) {  // uniform
+  int64_t first_end = f0;  // the first pass, with the coordinates read at the start
+  if constexpr (UNR) {
+    if (use_pre) {
+      if (f1 - f0 <= 4 * kThreads) first_end += pass<P, R, 4, true>(a, Lc, xyz, f0, f1, cx, cy, cz, ih, pre);
+      else first_end += pass<P, R, kMaxUnrolledU, true>(a, Lc, xyz, f0, f1, cx, cy, cz, ih, pre);
+    }
+  }
+  for (int64_t c0 = f0; c0 < hi; c0 += (int64_t)gridDim.y * ch) {  // uniform
     const int64_t c1 = c0 + ch < hi ? c0 + ch : hi;
-    for (int64_t s0 = c0; s0 < c1;) {  // passes sized to the points left in the chunk
+    for (int64_t s0 = c0 == f0 ? first_end : c0; s0 < c1;) {  // passes sized to the points left in the chunk
       const int64_t left = c1 - s0;
       int step;
       if (left <= kThreads) step = any_pass<P, R, CPLX, GRAD, 1>(a, Lc, Lg, xyz, s0, c1, cx, cy, cz, ih);
